@@ -1,0 +1,220 @@
+"""Benchmark: Aggregate Risk Analysis on one MI355X.
+
+One step = one analysis request on resident tables: ara_run_layers (fold +
+trial pass over the whole 1M x Poisson(1000) Year Event Table, 16 ELTs) and
+ara_risk_metrics (mean, PML/TVaR at 99% and 99.6%).  Inputs are resident in
+HBM before the timed region.  Prints one JSON line.
+
+Also measured: the trial-pass kernel's own duration (HIP events on its launch
+stream) for the roofline, the gradient/forward time ratio (forward with S
+checkpoints + metrics vs ara_backward), and the CPU oracle on a bounded
+sample of the same workload.
+"""
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "trial_pass_config1_traffic.json")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1606_04473_amd", "csrc", "kernels_trial.hip")
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", default="config1")
+    ap.add_argument("--cpu-sample-trials", type=int, default=300_000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-backward", action="store_true")
+    ap.add_argument("--literal-steps", type=int, default=0,
+                    help="also time the literal per-ELT lookup kernel this many times")
+    return ap.parse_args()
+
+
+def measured_traffic():
+    """HBM bytes per trial-pass launch from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(TRAFFIC_FILE) as f:
+        rec = json.load(f)
+    src = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    if rec.get("kernel_source_sha256") != src:
+        return None
+    return rec.get("traffic_bytes_per_launch")
+
+
+def main() -> None:
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build measures one GPU; the analysis shards by trials "
+                                   "across GPUs (see DESIGN.md) but multi-GPU runs are not part of it",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+    from paper_1606_04473_amd import ara
+    from workloads import make_config
+
+    torch.cuda.set_device(0)
+    torch.cuda.init()
+    t0 = time.time()
+    w = make_config(args.config)
+    yet, pool, layer = w.yet, w.pool, w.layers[0]
+    J = layer.n_elts
+    N, n_ev, C = yet.n_trials, yet.n_events, yet.catalogue_size
+    log(f"generated {args.config}: N={N} events={n_ev} C={C} J={J} in {time.time() - t0:.1f}s")
+    t0 = time.time()
+    tables = ara.create_tables(yet.offsets, yet.ids, pool.losses)
+    log(f"tables resident ({tables.bytes() / 1e9:.2f} GB) in {time.time() - t0:.1f}s")
+    spec = ara.LayerSpec.from_layer(layer, pool, N)
+    probs = list(w.probs)
+    out = torch.empty(N, dtype=torch.float64, device="cuda")
+    res = torch.empty(1 + 2 * len(probs), dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def step(flags=0):
+        ara.run_layers(tables, [spec], out=out, flags=flags, stream=stream)
+        ara.risk_metrics(out, probs, outputs=res, stream=stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ara.kernel_stats(tables, ara.KERNEL_TRIAL_PASS, reset=True)
+    ara.kernel_stats(tables, ara.KERNEL_FOLD, reset=True)
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.time()
+    start.record(stream)
+    for _ in range(args.steps):
+        step(ara.ARA_PROFILE)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    wall = time.time() - wall0
+    ms_total = start.elapsed_time(stop)
+    ms_step = ms_total / args.steps
+    n_tp, ms_tp = ara.kernel_stats(tables, ara.KERNEL_TRIAL_PASS)
+    n_fold, ms_fold = ara.kernel_stats(tables, ara.KERNEL_FOLD)
+    tp_avg = ms_tp / max(n_tp, 1)
+    fold_avg = ms_fold / max(n_fold, 1)
+    log(f"step {ms_step:.4f} ms (wall {wall / args.steps * 1e3:.4f} ms); trial pass {tp_avg:.4f} ms; "
+        f"fold {fold_avg:.4f} ms")
+    h = res.cpu().numpy()
+    log(f"mean={h[0]:.6e} PML={h[1:1 + len(probs)]} TVaR={h[1 + len(probs):]}")
+
+    lookups = float(n_ev) * J
+    value = lookups / (ms_step / 1e3)
+    step_bytes = 4.0 * n_ev + 8.0 * (N + 1) + 8.0 * J * C + 8.0 * N
+    tp_bytes = 4.0 * n_ev + 8.0 * (N + 1) + 8.0 * N + 8.0 * C
+    achieved = tp_bytes / (tp_avg / 1e3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
+                "kernel": "trial_pass_kernel<64,false,false>",
+                "algorithmic_bytes_per_launch": tp_bytes, "avg_launch_ms": round(tp_avg, 5)}
+
+    extra = {"pct_hbm_step": round(step_bytes / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+             "step_algorithmic_bytes": step_bytes, "fold_ms": round(fold_avg, 5),
+             "trial_pass_ms": round(tp_avg, 5)}
+
+    if args.literal_steps > 0:
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(args.literal_steps):
+            ara.run_layers(tables, [spec], out=out, flags=ara.ARA_LITERAL, stream=stream)
+        b.record(stream)
+        torch.cuda.synchronize()
+        lit_ms = a.elapsed_time(b) / args.literal_steps
+        extra["literal_run_layers_ms"] = round(lit_ms, 4)
+        extra["literal_lookups_per_s"] = lookups / (lit_ms / 1e3)
+        log(f"literal run_layers {lit_ms:.3f} ms")
+
+    if not args.no_backward:
+        gm = torch.empty(2 * J + 4, dtype=torch.float64, device="cuda")
+        gt = torch.empty(2 * J + 4, dtype=torch.float64, device="cuda")
+        for _ in range(2):
+            step(ara.ARA_CHECKPOINT_S)
+            ara.backward(tables, spec, 0.99, grad_mean=gm, grad_tvar=gt, stream=stream)
+        torch.cuda.synchronize()
+        reps = max(3, args.steps // 2)
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        fwd = bwd = 0.0
+        for _ in range(reps):
+            e[0].record(stream)
+            step(ara.ARA_CHECKPOINT_S)
+            e[1].record(stream)
+            ara.backward(tables, spec, 0.99, grad_mean=gm, grad_tvar=gt, stream=stream)
+            e[2].record(stream)
+            torch.cuda.synchronize()
+            fwd += e[0].elapsed_time(e[1])
+            bwd += e[1].elapsed_time(e[2])
+        extra["fwd_checkpointed_ms"] = round(fwd / reps, 4)
+        extra["backward_ms"] = round(bwd / reps, 4)
+        extra["grad_fwd_ratio"] = round(bwd / fwd, 4)
+        extra["grad_fwd_ratio_vs_plain_step"] = round((bwd / reps) / ms_step, 4)
+        log(f"forward+ckpt {fwd / reps:.4f} ms, backward {bwd / reps:.4f} ms")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        from workloads import Layer
+        n_s = min(args.cpu_sample_trials, N)
+        sub = Layer(layer.elt_index, layer.occ_retention, layer.occ_limit, layer.agg_retention,
+                    layer.agg_limit, 0, n_s)
+        ev_s = int(yet.offsets[n_s])
+        t1 = time.time()
+        oracle.run_layer(yet, pool, sub)
+        dt = time.time() - t1
+        cpu = {"value": ev_s * J / dt, "unit": "event-ELT lookups/s", "cores": oracle.max_threads(),
+               "kind": "oracle",
+               "sample": f"first {n_s} trials ({ev_s} events x {J} ELTs) of the same workload, "
+                         f"{dt:.1f} s, exact-sum FP64 C oracle"}
+        log(f"cpu oracle: {cpu['value']:.3e} lookups/s on {cpu['cores']} threads ({dt:.1f}s)")
+
+    line = {
+        "metric": "event-ELT lookups/s + % HBM peak (1M×1000 YET); grad/fwd time; tenant p99",
+        "value": value,
+        "unit": "event-ELT lookups/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "plain ARA paper-scale one-GPU share: 1,000,000 trials x Poisson(1000) "
+                               "events over a 2,000,000-event catalogue, 1 layer over 16 dense ELTs "
+                               "(20,000 lognormal(10,2) losses each), PML/TVaR at 99% and 99.6%",
+                   "trials": N, "events": n_ev, "catalogue": C, "elts_per_layer": J},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    line.update(extra)
+    tables.close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,261 @@
+/*
+ * ara.h -- C ABI of the MI355X (gfx950) Aggregate Risk Analysis library.
+ *
+ * The analysis (Prades, Varghese, Reano, Silla, "Multi-Tenant Virtual GPUs
+ * for Optimising Performance of a Financial Risk Application", Section III)
+ * maps a Year Event Table (YET, Eq. 1) and a set of Event Loss Tables (ELT,
+ * Eq. 2) grouped into layers (Eq. 3) to a Year Loss Table (YLT): one loss per
+ * trial, from which PML and TVaR are derived (Section III-A, end).
+ *
+ * Per trial t, event occurrence d and layer ELT j (Algorithm 3):
+ *     x_j  = clamp(ELT_j[E_{t,d}]; R_j, Lim_j)          per-ELT terms
+ *     y_d  = sum_j x_j          (layer ELT order)        combine over ELTs
+ *     o_d  = clamp(y_d; OccR, OccL)                       occurrence terms
+ *     S_t  = sum_d o_d                                    annual total
+ *     YLT_t= clamp(S_t; AggR, AggL)                       aggregate terms
+ * with clamp(v; R, L) = min(max(v - R, 0), L).
+ *
+ * Conventions for every call:
+ *   - Return value: ara_status, ARA_OK (0) on success.  On failure nothing
+ *     observable has been written to outputs, and ara_last_error() returns a
+ *     thread-local message.  No exception or abort crosses this ABI.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *   - Pointers are host memory unless ARA_DEVICE_PTR is set in `flags`, in
+ *     which case the pointers named by that call's comment are device memory
+ *     on the device the tables live on.  ara_layer arrays are always host.
+ *   - Calls with host outputs return after the results are in host memory.
+ *     Calls with device outputs are asynchronous on `stream`.
+ *   - Tables are read-only after creation: several threads may run layers on
+ *     the same tables concurrently, on different streams.  Per-call scratch
+ *     comes from the device's stream-ordered memory pool.
+ */
+#ifndef ARA_H
+#define ARA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t ara_status;
+
+#define ARA_OK                   0
+#define ARA_ERR_INVALID_ARG      1  /* malformed argument: NULL, negative size, NaN term, p outside (0,1), bad CSR */
+#define ARA_ERR_OUT_OF_RANGE     2  /* an event ID >= catalogue size, or an ELT index outside the pool */
+#define ARA_ERR_BUFFER_TOO_SMALL 3  /* an output capacity is below what the call writes */
+#define ARA_ERR_NO_MEMORY        4  /* device allocation failed, or the footprint exceeds the set budget */
+#define ARA_ERR_DEVICE           5  /* a HIP runtime error; the HIP message is in ara_last_error() */
+#define ARA_ERR_NOT_READY        6  /* ara_backward without a matching checkpointed forward */
+#define ARA_ERR_UNSUPPORTED      7  /* a valid request this build does not handle (e.g. J > ARA_MAX_LAYER_ELTS) */
+
+/* flags */
+#define ARA_DEVICE_PTR   (1u << 0)  /* pointer arguments of the call are device memory */
+#define ARA_LITERAL      (1u << 1)  /* ara_run_layers: per-occurrence, per-ELT lookups exactly as
+                                       Algorithm 3 is written, instead of one lookup of the
+                                       per-event occurrence loss computed for the whole catalogue */
+#define ARA_CHECKPOINT_S (1u << 2)  /* ara_run_layers: keep S_t, YLT_t and the stride-64 prefix
+                                       checkpoints of S inside the tables for ara_backward */
+#define ARA_PER_LAYER    (1u << 3)  /* ara_run_layers with several layers: one launch sequence per
+                                       layer instead of the single persistent batched launch */
+#define ARA_GRAPH        (1u << 4)  /* ara_run_layers: replay a HIP graph captured for this layer
+                                       shape (captured on first use, re-captured on shape change) */
+#define ARA_PROFILE      (1u << 5)  /* ara_run_layers: bracket each kernel with HIP events on the
+                                       call's stream; read the totals with ara_kernel_stats */
+
+/* kernel classes reported by ara_kernel_stats */
+#define ARA_KERNEL_FOLD       0     /* per-catalogue occurrence losses */
+#define ARA_KERNEL_TRIAL_PASS 1     /* YET stream, lookups, annual totals, aggregate terms */
+#define ARA_KERNEL_BATCHED    2     /* persistent multi-layer trial pass */
+
+#define ARA_MAX_LAYER_ELTS 64       /* most ELTs one layer may cover (the paper's layers cover 3-30) */
+#define ARA_CHECKPOINT_STRIDE 64    /* events between stored prefix sums of S */
+
+typedef struct ara_tables ara_tables;
+
+/*
+ * A layer (Eq. 3): the ELTs it covers and its terms.  The per-ELT terms
+ * (the tuple attached to each ELT in Eq. 2) are read as a retention and a
+ * limit.  The layer terms are (OccR, OccL, AggR, AggL).  All arrays are host
+ * memory, n_elts entries, in the layer's ELT order (the order in which x_j
+ * are summed).  Retentions >= 0, limits >= 0 (+inf allowed), no NaN.
+ * The layer covers trials [trial_begin, trial_begin + trial_count).
+ */
+typedef struct ara_layer {
+    int32_t n_elts;
+    const int32_t* elt_index;       /* rows of the ELT pool */
+    const double* elt_retention;
+    const double* elt_limit;
+    double occ_retention, occ_limit;
+    double agg_retention, agg_limit;
+    int64_t trial_begin, trial_count;
+} ara_layer;
+
+/*
+ * Launch-shape knobs picked by the autotuner; zero fields mean "default".
+ */
+typedef struct ara_tuning {
+    int32_t block_threads;          /* threads per workgroup of the trial pass (multiple of 64) */
+    int32_t waves_per_trial_log2;   /* unused (0) = one wave per trial */
+    int32_t lanes_per_trial;        /* 64 (one wave per trial), 32, 16 or 8 lanes per trial */
+    int32_t blocks_per_cu;          /* resident workgroups per CU the grid is sized for */
+    int32_t fold_events_per_thread; /* catalogue events per thread in the fold kernel: 1, 2, 4 */
+    int32_t reserved[3];
+} ara_tuning;
+
+/*
+ * ara_create_tables -- Algorithm 2 (TransferDataToDevice): make the YET and
+ * the ELT pool resident on the current device.
+ *
+ *   trial_offsets  int64[n_trials + 1], CSR offsets: trial t's events are
+ *                  event_ids[trial_offsets[t] .. trial_offsets[t+1]), in
+ *                  ascending time-stamp order (Eq. 1).  offsets[0] == 0,
+ *                  non-decreasing, offsets[n_trials] == n_events.
+ *   event_ids      uint32[n_events], catalogue indices < catalogue_size.
+ *   elt_losses     float64[n_elts][catalogue_size], row-major dense
+ *                  direct-access tables (Section III-B); 0.0 = no loss.
+ *                  Finite and >= 0.
+ *   flags          ARA_DEVICE_PTR: the three arrays are device memory.
+ *   out            receives the handle; freed by ara_destroy_tables.
+ *
+ * The arrays are caller-owned and only read during the call: the library
+ * copies them into device memory it owns.  Validation runs on the device
+ * after the copy: ARA_ERR_OUT_OF_RANGE for an ID >= catalogue_size,
+ * ARA_ERR_INVALID_ARG for bad offsets or a negative/NaN/inf loss,
+ * ARA_ERR_NO_MEMORY if the device cannot hold the tables.  Synchronous.
+ */
+ara_status ara_create_tables(const int64_t* trial_offsets, int64_t n_trials,
+                             const uint32_t* event_ids, int64_t n_events,
+                             const double* elt_losses, int32_t n_elts,
+                             int64_t catalogue_size, uint32_t flags, void* stream,
+                             ara_tables** out);
+
+/* Release the device memory of the tables.  NULL is accepted. */
+void ara_destroy_tables(ara_tables* tables);
+
+/*
+ * ara_run_layers -- Algorithm 1's layer loop around Algorithm 3: the year
+ * loss of every trial of every layer.
+ *
+ *   layers/n_layers  host array of layer descriptions (see ara_layer).
+ *   ylt              float64 output, the layers' year losses back to back
+ *                    (layer 0's trial_count values first); host memory, or
+ *                    device memory with ARA_DEVICE_PTR.
+ *   ylt_capacity     number of doubles `ylt` can hold; ARA_ERR_BUFFER_TOO_SMALL
+ *                    if below the sum of trial_count.
+ *   flags            ARA_DEVICE_PTR, ARA_LITERAL, ARA_CHECKPOINT_S (one layer
+ *                    only), ARA_PER_LAYER, ARA_GRAPH.
+ *
+ * Year losses do not depend on the flags beyond floating-point rounding of
+ * S (the sum over occurrences is accumulated in double-double and rounded
+ * once, so it equals the correctly rounded sum except within ~1e-29 relative
+ * of a rounding tie).  Errors: ARA_ERR_INVALID_ARG (negative/NaN term, bad
+ * trial range), ARA_ERR_OUT_OF_RANGE (ELT index outside the pool),
+ * ARA_ERR_UNSUPPORTED (n_elts > ARA_MAX_LAYER_ELTS).
+ */
+ara_status ara_run_layers(ara_tables* tables, const ara_layer* layers, int32_t n_layers,
+                          double* ylt, int64_t ylt_capacity, uint32_t flags, void* stream);
+
+/*
+ * ara_risk_metrics -- the portfolio risk metrics named in Section III-A
+ * (PML, TVaR), plus the mean annual loss, from one layer's YLT.
+ *
+ *   ylt        float64[n_trials], values >= 0 (as produced by ara_run_layers);
+ *              host memory or device memory with ARA_DEVICE_PTR.
+ *   probs      host float64[n_probs], each in (0, 1); n_probs <= 4
+ *              (ARA_ERR_UNSUPPORTED above).
+ *   mean_out   1 double; pml_out, tvar_out n_probs doubles each; host
+ *              memory, or device memory with ARA_DEVICE_PTR.
+ *
+ * With m = ceil(n_trials * (1 - p)) -- p read as the short decimal it
+ * approximates, so a product within 1e-9 relative of an integer is that
+ * integer -- clamped to [1, n_trials]: PML_p is the m-th largest year loss
+ * and TVaR_p the mean of the m largest.  Sums are accumulated in
+ * double-double and rounded once.  Errors: ARA_ERR_INVALID_ARG for
+ * n_trials < 1 or p outside (0, 1).
+ */
+ara_status ara_risk_metrics(const double* ylt, int64_t n_trials, const double* probs,
+                            int32_t n_probs, double* mean_out, double* pml_out,
+                            double* tvar_out, uint32_t flags, void* stream);
+
+/*
+ * ara_backward -- gradients of the mean annual loss and of TVaR_p with
+ * respect to theta = [R_1..R_J, Lim_1..Lim_J, OccR, OccL, AggR, AggL] of one
+ * layer (2J + 4 values each, in that order).  The paper defines no
+ * gradient; the year loss is piecewise linear in theta and the convention at
+ * a kink is the strict one: a clamp with reduced value t = v - R passes the
+ * slope only for 0 < t < L, d/dR = -1 there, d/dL = 1 for t > L, 0 at equality.
+ * Every partial is then an integer count; the mean divides by n, TVaR by m
+ * (trials tied at the m-th largest value share the remaining slots equally).
+ *
+ * Requires a preceding ara_run_layers(tables, layer, 1, ..., ARA_CHECKPOINT_S)
+ * with identical layer terms, else ARA_ERR_NOT_READY.  grad_mean/grad_tvar
+ * are host memory (2J + 4 doubles each), or device memory with
+ * ARA_DEVICE_PTR.  Either may be NULL to skip it.
+ */
+ara_status ara_backward(ara_tables* tables, const ara_layer* layer, double tvar_p,
+                        double* grad_mean, double* grad_tvar, uint32_t flags, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* auxiliary calls                                                          */
+/* ------------------------------------------------------------------------ */
+
+/* Thread-local message describing the last failure on this thread. */
+const char* ara_last_error(void);
+
+/* Static name of a status code. */
+const char* ara_status_string(ara_status status);
+
+/* Device bytes held by the tables (YET, offsets, ELT pool). */
+ara_status ara_table_bytes(const ara_tables* tables, int64_t* bytes);
+
+/* Peak device scratch bytes ara_run_layers(tables, layers, n_layers, ..,
+   flags) allocates beyond the tables and the output; for admission control. */
+ara_status ara_footprint(const ara_tables* tables, const ara_layer* layers, int32_t n_layers,
+                         uint32_t flags, int64_t* bytes);
+
+/*
+ * ara_debug_lookups -- the raw lookups of Algorithm 3 for one trial, as the
+ * device performs them: ids_out[k] = k-th event ID of the trial and
+ * losses_out[k * n_elts + j] = ELT_{elt_index[j]}[ids_out[k]].  Host outputs;
+ * `capacity` is the number of events the buffers hold (losses_out holds
+ * capacity * n_elts doubles); *n_out receives the trial's event count.
+ * ARA_ERR_BUFFER_TOO_SMALL if the trial has more events than `capacity`.
+ */
+ara_status ara_debug_lookups(ara_tables* tables, const ara_layer* layer, int64_t trial,
+                             uint32_t* ids_out, double* losses_out, int64_t capacity,
+                             int64_t* n_out, void* stream);
+
+/*
+ * ara_read_checkpoints -- copy the state kept by ARA_CHECKPOINT_S to host.
+ * what = 0: S_t for the layer's trials (trial_count doubles);
+ * what = 1: stride-64 prefix checkpoints: slot b holds, for the trial that
+ *           owns global event 64b+63, the sum of o over that trial's events
+ *           up to and including event 64b+63 (n_events/64 doubles; slots
+ *           whose event lies outside the layer's trials hold NaN).
+ * *n_out receives the number of values.
+ */
+ara_status ara_read_checkpoints(ara_tables* tables, int32_t what, double* out,
+                                int64_t capacity, int64_t* n_out);
+
+/*
+ * ara_kernel_stats -- launches and summed device time (ms, from HIP events)
+ * of one kernel class over the ara_run_layers calls made with ARA_PROFILE
+ * since the last reset.  Waits for the recorded events.  reset != 0 clears
+ * the totals after reading them.
+ */
+ara_status ara_kernel_stats(ara_tables* tables, int32_t kernel, int64_t* launches, double* total_ms,
+                            int32_t reset);
+
+/* Launch-shape knobs used by later calls on these tables (NULL resets). */
+ara_status ara_set_tuning(ara_tables* tables, const ara_tuning* tuning);
+ara_status ara_get_tuning(const ara_tables* tables, ara_tuning* tuning);
+
+/* Number of compute units and the device index of the tables' device. */
+ara_status ara_device_info(int32_t* n_cu, int32_t* device);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ARA_H */

@@ -1,0 +1,427 @@
+"""ctypes binding of libara (include/ara.h): argument marshalling only.
+
+Every computation happens in the HIP library.  Inputs may be NumPy arrays
+(host memory) or torch CUDA tensors (device memory); the binding passes the
+pointer, the matching ARA_DEVICE_PTR flag and torch's current stream.  If the
+library is missing the first call raises -- there is no CPU fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libara.so")
+
+ARA_OK = 0
+ARA_ERR_INVALID_ARG = 1
+ARA_ERR_OUT_OF_RANGE = 2
+ARA_ERR_BUFFER_TOO_SMALL = 3
+ARA_ERR_NO_MEMORY = 4
+ARA_ERR_DEVICE = 5
+ARA_ERR_NOT_READY = 6
+ARA_ERR_UNSUPPORTED = 7
+
+ARA_DEVICE_PTR = 1 << 0
+ARA_LITERAL = 1 << 1
+ARA_CHECKPOINT_S = 1 << 2
+ARA_PER_LAYER = 1 << 3
+ARA_GRAPH = 1 << 4
+ARA_PROFILE = 1 << 5
+
+KERNEL_FOLD = 0
+KERNEL_TRIAL_PASS = 1
+KERNEL_BATCHED = 2
+
+MAX_LAYER_ELTS = 64
+CHECKPOINT_STRIDE = 64
+
+EXPORTED = (
+    "ara_create_tables", "ara_destroy_tables", "ara_run_layers", "ara_risk_metrics", "ara_backward",
+    "ara_last_error", "ara_status_string", "ara_table_bytes", "ara_footprint", "ara_debug_lookups",
+    "ara_read_checkpoints", "ara_set_tuning", "ara_get_tuning", "ara_device_info",
+    "ara_kernel_stats",
+)
+
+
+class AraError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{_STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+_STATUS_NAMES = {
+    1: "ARA_ERR_INVALID_ARG", 2: "ARA_ERR_OUT_OF_RANGE", 3: "ARA_ERR_BUFFER_TOO_SMALL",
+    4: "ARA_ERR_NO_MEMORY", 5: "ARA_ERR_DEVICE", 6: "ARA_ERR_NOT_READY", 7: "ARA_ERR_UNSUPPORTED",
+}
+
+
+class CLayer(ctypes.Structure):
+    _fields_ = [
+        ("n_elts", ctypes.c_int32),
+        ("elt_index", ctypes.c_void_p),
+        ("elt_retention", ctypes.c_void_p),
+        ("elt_limit", ctypes.c_void_p),
+        ("occ_retention", ctypes.c_double),
+        ("occ_limit", ctypes.c_double),
+        ("agg_retention", ctypes.c_double),
+        ("agg_limit", ctypes.c_double),
+        ("trial_begin", ctypes.c_int64),
+        ("trial_count", ctypes.c_int64),
+    ]
+
+
+class CTuning(ctypes.Structure):
+    _fields_ = [
+        ("block_threads", ctypes.c_int32),
+        ("waves_per_trial_log2", ctypes.c_int32),
+        ("lanes_per_trial", ctypes.c_int32),
+        ("blocks_per_cu", ctypes.c_int32),
+        ("fold_events_per_thread", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 3),
+    ]
+
+
+_LIB = None
+
+
+def lib():
+    """Load libara.so; raise if it has not been built."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                           "or python paper_1606_04473_amd/build.py")
+    L = ctypes.CDLL(LIB_PATH)
+    P, i32, i64, u32, f64 = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32,
+                             ctypes.c_double)
+    L.ara_create_tables.argtypes = [P, i64, P, i64, P, i32, i64, u32, P, ctypes.POINTER(P)]
+    L.ara_create_tables.restype = i32
+    L.ara_destroy_tables.argtypes = [P]
+    L.ara_destroy_tables.restype = None
+    L.ara_run_layers.argtypes = [P, ctypes.POINTER(CLayer), i32, P, i64, u32, P]
+    L.ara_run_layers.restype = i32
+    L.ara_risk_metrics.argtypes = [P, i64, P, i32, P, P, P, u32, P]
+    L.ara_risk_metrics.restype = i32
+    L.ara_backward.argtypes = [P, ctypes.POINTER(CLayer), f64, P, P, u32, P]
+    L.ara_backward.restype = i32
+    L.ara_last_error.argtypes = []
+    L.ara_last_error.restype = ctypes.c_char_p
+    L.ara_status_string.argtypes = [i32]
+    L.ara_status_string.restype = ctypes.c_char_p
+    L.ara_table_bytes.argtypes = [P, ctypes.POINTER(i64)]
+    L.ara_table_bytes.restype = i32
+    L.ara_footprint.argtypes = [P, ctypes.POINTER(CLayer), i32, u32, ctypes.POINTER(i64)]
+    L.ara_footprint.restype = i32
+    L.ara_debug_lookups.argtypes = [P, ctypes.POINTER(CLayer), i64, P, P, i64, ctypes.POINTER(i64), P]
+    L.ara_debug_lookups.restype = i32
+    L.ara_read_checkpoints.argtypes = [P, i32, P, i64, ctypes.POINTER(i64)]
+    L.ara_read_checkpoints.restype = i32
+    L.ara_set_tuning.argtypes = [P, ctypes.POINTER(CTuning)]
+    L.ara_set_tuning.restype = i32
+    L.ara_get_tuning.argtypes = [P, ctypes.POINTER(CTuning)]
+    L.ara_get_tuning.restype = i32
+    L.ara_kernel_stats.argtypes = [P, i32, ctypes.POINTER(i64), ctypes.POINTER(f64), i32]
+    L.ara_kernel_stats.restype = i32
+    L.ara_device_info.argtypes = [ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    L.ara_device_info.restype = i32
+    _LIB = L
+    return L
+
+
+def _check(status: int) -> None:
+    if status != ARA_OK:
+        msg = lib().ara_last_error().decode(errors="replace")
+        raise AraError(status, msg)
+
+
+# ---------------------------------------------------------------------------
+# array marshalling
+# ---------------------------------------------------------------------------
+
+def _is_device(x) -> bool:
+    return hasattr(x, "is_cuda") and bool(x.is_cuda)
+
+
+def _ptr(x, dtype=None):
+    """(pointer, keepalive, on_device) for a NumPy array or torch tensor."""
+    if x is None:
+        return None, None, False
+    if hasattr(x, "data_ptr"):
+        if dtype is not None:
+            import torch
+            want = {np.float64: torch.float64, np.int64: torch.int64, np.uint32: None,
+                    np.int32: torch.int32}[dtype]
+            if want is not None and x.dtype != want:
+                raise TypeError(f"expected {want}, got {x.dtype}")
+        if not x.is_contiguous():
+            raise ValueError("tensor must be contiguous")
+        return ctypes.c_void_p(x.data_ptr()), x, _is_device(x)
+    a = np.ascontiguousarray(x, dtype=dtype) if dtype is not None else np.ascontiguousarray(x)
+    return a.ctypes.data_as(ctypes.c_void_p), a, False
+
+
+def _stream(stream) -> ctypes.c_void_p:
+    if stream is None:
+        try:
+            import torch
+            if torch.cuda.is_available() and torch.cuda.is_initialized():
+                return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+        except Exception:
+            pass
+        return ctypes.c_void_p(0)
+    if hasattr(stream, "cuda_stream"):
+        return ctypes.c_void_p(stream.cuda_stream)
+    return ctypes.c_void_p(int(stream))
+
+
+@dataclass
+class LayerSpec:
+    """A layer as the library sees it: pool rows, per-ELT terms, layer terms
+    and the trial range."""
+
+    elt_index: np.ndarray
+    elt_retention: np.ndarray
+    elt_limit: np.ndarray
+    occ_retention: float
+    occ_limit: float
+    agg_retention: float
+    agg_limit: float
+    trial_begin: int
+    trial_count: int
+
+    @property
+    def n_elts(self) -> int:
+        return int(len(self.elt_index))
+
+    @staticmethod
+    def from_layer(layer, pool, n_trials: int) -> "LayerSpec":
+        idx = np.ascontiguousarray(layer.elt_index, dtype=np.int32)
+        count = layer.trial_count if layer.trial_count >= 0 else n_trials - layer.trial_begin
+        return LayerSpec(idx, np.ascontiguousarray(pool.retention[idx], dtype=np.float64),
+                         np.ascontiguousarray(pool.limit[idx], dtype=np.float64),
+                         float(layer.occ_retention), float(layer.occ_limit),
+                         float(layer.agg_retention), float(layer.agg_limit),
+                         int(layer.trial_begin), int(count))
+
+    def theta(self) -> np.ndarray:
+        return np.concatenate([self.elt_retention, self.elt_limit,
+                               [self.occ_retention, self.occ_limit, self.agg_retention,
+                                self.agg_limit]]).astype(np.float64)
+
+    def with_theta(self, theta: Sequence[float]) -> "LayerSpec":
+        J = self.n_elts
+        t = np.asarray(theta, dtype=np.float64)
+        return LayerSpec(self.elt_index, t[:J].copy(), t[J:2 * J].copy(), float(t[2 * J]),
+                         float(t[2 * J + 1]), float(t[2 * J + 2]), float(t[2 * J + 3]),
+                         self.trial_begin, self.trial_count)
+
+
+def _c_layers(specs: Sequence[LayerSpec]):
+    arr = (CLayer * len(specs))()
+    keep = []
+    for i, s in enumerate(specs):
+        idx = np.ascontiguousarray(s.elt_index, dtype=np.int32)
+        R = np.ascontiguousarray(s.elt_retention, dtype=np.float64)
+        Lim = np.ascontiguousarray(s.elt_limit, dtype=np.float64)
+        keep += [idx, R, Lim]
+        arr[i] = CLayer(idx.shape[0], idx.ctypes.data_as(ctypes.c_void_p),
+                        R.ctypes.data_as(ctypes.c_void_p), Lim.ctypes.data_as(ctypes.c_void_p),
+                        s.occ_retention, s.occ_limit, s.agg_retention, s.agg_limit,
+                        int(s.trial_begin), int(s.trial_count))
+    return arr, keep
+
+
+# ---------------------------------------------------------------------------
+# API
+# ---------------------------------------------------------------------------
+
+class Tables:
+    """Resident YET + ELT pool (ara_create_tables / ara_destroy_tables)."""
+
+    def __init__(self, handle, n_trials: int, n_events: int, catalogue_size: int, n_pool: int):
+        self._h = handle
+        self.n_trials = n_trials
+        self.n_events = n_events
+        self.catalogue_size = catalogue_size
+        self.n_pool = n_pool
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise RuntimeError("tables destroyed")
+        return self._h
+
+    def close(self) -> None:
+        if self._h is not None:
+            lib().ara_destroy_tables(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def bytes(self) -> int:
+        v = ctypes.c_int64()
+        _check(lib().ara_table_bytes(self.handle, ctypes.byref(v)))
+        return int(v.value)
+
+
+def create_tables(offsets, ids, elt_losses, catalogue_size: Optional[int] = None,
+                  stream=None) -> Tables:
+    """ara_create_tables.  NumPy inputs are host memory; CUDA tensors device memory."""
+    po, ko, do = _ptr(offsets, np.int64)
+    pi, ki, di = _ptr(ids, np.uint32)
+    pe, ke, de = _ptr(elt_losses, np.float64)
+    if not (do == di == de):
+        raise ValueError("inputs must all be host arrays or all device tensors")
+    n_trials = int(ko.shape[0]) - 1
+    n_events = int(ki.shape[0])
+    shape = tuple(ke.shape)
+    n_pool = int(shape[0])
+    C = int(shape[1]) if catalogue_size is None else int(catalogue_size)
+    h = ctypes.c_void_p()
+    _check(lib().ara_create_tables(po, n_trials, pi, n_events, pe, n_pool, C,
+                                   ARA_DEVICE_PTR if do else 0, _stream(stream), ctypes.byref(h)))
+    return Tables(h, n_trials, n_events, C, n_pool)
+
+
+def run_layers(tables: Tables, layers: Sequence[LayerSpec], out=None, flags: int = 0,
+               stream=None):
+    """ara_run_layers.  Returns the YLT (back to back per layer): a NumPy array
+    when `out` is None, else `out` (NumPy or a CUDA float64 tensor)."""
+    arr, keep = _c_layers(layers)
+    total = int(sum(l.trial_count for l in layers))
+    if out is None:
+        out = np.empty(total, dtype=np.float64)
+    po, ko, dev = _ptr(out, np.float64)
+    f = flags | (ARA_DEVICE_PTR if dev else 0)
+    _check(lib().ara_run_layers(tables.handle, arr, len(layers), po, int(ko.numel() if dev else ko.size),
+                                f, _stream(stream)))
+    return out
+
+
+def risk_metrics(ylt, probs: Sequence[float], stream=None, outputs=None):
+    """ara_risk_metrics.  Host input -> (mean, [pml], [tvar]) floats.  Device
+    input -> the same computed on the device; if `outputs` is a float64 CUDA
+    tensor of size 1 + 2 n_probs it receives [mean, pml..., tvar...] and the
+    call stays asynchronous."""
+    py, ky, dev = _ptr(ylt, np.float64)
+    n = int(ky.numel() if dev else ky.size)
+    p = np.ascontiguousarray(probs, dtype=np.float64)
+    k = p.shape[0]
+    if dev:
+        import torch
+        res = outputs if outputs is not None else torch.empty(1 + 2 * k, dtype=torch.float64,
+                                                              device=ky.device)
+        base = res.data_ptr()
+        _check(lib().ara_risk_metrics(py, n, p.ctypes.data_as(ctypes.c_void_p), k,
+                                      ctypes.c_void_p(base), ctypes.c_void_p(base + 8),
+                                      ctypes.c_void_p(base + 8 * (1 + k)), ARA_DEVICE_PTR,
+                                      _stream(stream)))
+        if outputs is not None:
+            return outputs
+        h = res.cpu().numpy()
+        return float(h[0]), h[1:1 + k].tolist(), h[1 + k:].tolist()
+    mean = ctypes.c_double()
+    pml = np.empty(max(k, 1), dtype=np.float64)
+    tvar = np.empty(max(k, 1), dtype=np.float64)
+    _check(lib().ara_risk_metrics(py, n, p.ctypes.data_as(ctypes.c_void_p), k, ctypes.byref(mean),
+                                  pml.ctypes.data_as(ctypes.c_void_p),
+                                  tvar.ctypes.data_as(ctypes.c_void_p), 0, _stream(stream)))
+    return float(mean.value), pml[:k].tolist(), tvar[:k].tolist()
+
+
+def backward(tables: Tables, layer: LayerSpec, tvar_p: float, grad_mean=None, grad_tvar=None,
+             stream=None):
+    """ara_backward.  Returns (grad_mean, grad_tvar) as NumPy arrays of 2J+4
+    unless CUDA tensors are passed to receive them."""
+    arr, keep = _c_layers([layer])
+    P = 2 * layer.n_elts + 4
+    if grad_mean is None and grad_tvar is None:
+        gm = np.empty(P, dtype=np.float64)
+        gt = np.empty(P, dtype=np.float64)
+        _check(lib().ara_backward(tables.handle, arr, float(tvar_p),
+                                  gm.ctypes.data_as(ctypes.c_void_p),
+                                  gt.ctypes.data_as(ctypes.c_void_p), 0, _stream(stream)))
+        return gm, gt
+    pm, km, dm = _ptr(grad_mean, np.float64)
+    pt, kt, dt = _ptr(grad_tvar, np.float64)
+    dev = dm or dt
+    _check(lib().ara_backward(tables.handle, arr, float(tvar_p), pm, pt,
+                              ARA_DEVICE_PTR if dev else 0, _stream(stream)))
+    return grad_mean, grad_tvar
+
+
+def debug_lookups(tables: Tables, layer: LayerSpec, trial: int, capacity: int = 4096, stream=None):
+    """ara_debug_lookups: (ids[K], losses[K][J]) as the device looks them up."""
+    arr, keep = _c_layers([layer])
+    J = layer.n_elts
+    ids = np.empty(capacity, dtype=np.uint32)
+    losses = np.empty(capacity * max(J, 1), dtype=np.float64)
+    n = ctypes.c_int64()
+    _check(lib().ara_debug_lookups(tables.handle, arr, int(trial), ids.ctypes.data_as(ctypes.c_void_p),
+                                   losses.ctypes.data_as(ctypes.c_void_p), capacity, ctypes.byref(n),
+                                   _stream(stream)))
+    K = int(n.value)
+    return ids[:K].copy(), losses[:K * J].reshape(K, J).copy()
+
+
+def read_checkpoints(tables: Tables, what: int):
+    n = ctypes.c_int64()
+    st = lib().ara_read_checkpoints(tables.handle, what, None, 0, ctypes.byref(n))
+    if st not in (ARA_OK, ARA_ERR_BUFFER_TOO_SMALL):
+        _check(st)
+    out = np.empty(max(int(n.value), 1), dtype=np.float64)
+    _check(lib().ara_read_checkpoints(tables.handle, what, out.ctypes.data_as(ctypes.c_void_p),
+                                      out.shape[0], ctypes.byref(n)))
+    return out[:int(n.value)]
+
+
+def footprint(tables: Tables, layers: Sequence[LayerSpec], flags: int = 0) -> int:
+    arr, keep = _c_layers(layers)
+    v = ctypes.c_int64()
+    _check(lib().ara_footprint(tables.handle, arr, len(layers), flags, ctypes.byref(v)))
+    return int(v.value)
+
+
+def set_tuning(tables: Tables, lanes_per_trial: int = 0, blocks_per_cu: int = 0,
+               block_threads: int = 0, fold_events_per_thread: int = 0) -> None:
+    t = CTuning(block_threads, 0, lanes_per_trial, blocks_per_cu, fold_events_per_thread)
+    _check(lib().ara_set_tuning(tables.handle, ctypes.byref(t)))
+
+
+def get_tuning(tables: Tables) -> dict:
+    t = CTuning()
+    _check(lib().ara_get_tuning(tables.handle, ctypes.byref(t)))
+    return dict(block_threads=t.block_threads, lanes_per_trial=t.lanes_per_trial,
+                blocks_per_cu=t.blocks_per_cu, fold_events_per_thread=t.fold_events_per_thread)
+
+
+def kernel_stats(tables: Tables, kernel: int, reset: bool = False):
+    """(launches, total_ms) of one kernel class over ARA_PROFILE runs."""
+    n = ctypes.c_int64()
+    ms = ctypes.c_double()
+    _check(lib().ara_kernel_stats(tables.handle, kernel, ctypes.byref(n), ctypes.byref(ms),
+                                  1 if reset else 0))
+    return int(n.value), float(ms.value)
+
+
+def device_info():
+    n = ctypes.c_int32()
+    d = ctypes.c_int32()
+    _check(lib().ara_device_info(ctypes.byref(n), ctypes.byref(d)))
+    return int(n.value), int(d.value)
+
+
+def status_string(status: int) -> str:
+    return lib().ara_status_string(status).decode()

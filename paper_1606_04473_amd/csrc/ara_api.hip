@@ -1,0 +1,595 @@
+// C ABI of libara: argument checks, table residency, per-call scratch from
+// the stream-ordered pool, kernel dispatch.  No exception crosses the ABI.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "ara_internal.hpp"
+
+namespace {
+
+thread_local std::string g_error;
+
+ara_status fail(ara_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_error = buf;
+    return st;
+}
+
+ara_status hip_fail(hipError_t e, const char* what) {
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
+        return fail(ARA_ERR_NO_MEMORY, "%s: %s", what, hipGetErrorString(e));
+    return fail(ARA_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, what)                       \
+    do {                                          \
+        hipError_t e_ = (expr);                   \
+        if (e_ != hipSuccess) return hip_fail(e_, what); \
+    } while (0)
+
+// Make the tables' device current for the scope of a call.
+struct DeviceScope {
+    int prev = -1;
+    bool ok = true;
+    explicit DeviceScope(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) ok = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceScope() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+// Stream-ordered scratch that is returned to the pool when the scope ends.
+struct PoolBuffer {
+    void* p = nullptr;
+    hipStream_t s = nullptr;
+    ~PoolBuffer() {
+        if (p) (void)hipFreeAsync(p, s);
+    }
+    hipError_t alloc(size_t bytes, hipStream_t stream) {
+        s = stream;
+        if (bytes == 0) bytes = 256;
+        return hipMallocAsync(&p, bytes, stream);
+    }
+};
+
+void keep_pool_memory(int device) {
+    static std::mutex mu;
+    static std::vector<int> done;
+    std::lock_guard<std::mutex> g(mu);
+    for (int d : done)
+        if (d == device) return;
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, device) == hipSuccess) {
+        uint64_t thr = UINT64_MAX;
+        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+    }
+    done.push_back(device);
+}
+
+bool bad_term(double v) { return std::isnan(v) || v < 0.0; }
+
+ara_status build_layer_args(const ara_tables* t, const ara_layer& in, ara::LayerArgs& L) {
+    std::memset(&L, 0, sizeof(L));
+    if (in.n_elts < 0) return fail(ARA_ERR_INVALID_ARG, "layer n_elts < 0");
+    if (in.n_elts > ara::kMaxJ)
+        return fail(ARA_ERR_UNSUPPORTED, "layer covers %d ELTs; at most %d supported", in.n_elts, ara::kMaxJ);
+    if (in.n_elts > 0 && (!in.elt_index || !in.elt_retention || !in.elt_limit))
+        return fail(ARA_ERR_INVALID_ARG, "layer ELT arrays are NULL");
+    L.J = in.n_elts;
+    for (int j = 0; j < in.n_elts; ++j) {
+        if (in.elt_index[j] < 0 || in.elt_index[j] >= t->n_pool)
+            return fail(ARA_ERR_OUT_OF_RANGE, "ELT index %d outside the pool of %d", in.elt_index[j], t->n_pool);
+        if (bad_term(in.elt_retention[j]) || bad_term(in.elt_limit[j]) || std::isinf(in.elt_retention[j]))
+            return fail(ARA_ERR_INVALID_ARG, "ELT %d terms must be >= 0, finite retention, not NaN", j);
+        L.idx[j] = in.elt_index[j];
+        L.R[j] = in.elt_retention[j];
+        L.Lim[j] = in.elt_limit[j];
+    }
+    if (bad_term(in.occ_retention) || bad_term(in.occ_limit) || bad_term(in.agg_retention) ||
+        bad_term(in.agg_limit) || std::isinf(in.occ_retention) || std::isinf(in.agg_retention))
+        return fail(ARA_ERR_INVALID_ARG, "layer terms must be >= 0, finite retentions, not NaN");
+    L.occR = in.occ_retention;
+    L.occL = in.occ_limit;
+    L.aggR = in.agg_retention;
+    L.aggL = in.agg_limit;
+    if (in.trial_begin < 0 || in.trial_count < 0 || in.trial_begin > t->n_trials ||
+        in.trial_count > t->n_trials - in.trial_begin)
+        return fail(ARA_ERR_INVALID_ARG, "trial range [%lld, +%lld) outside [0, %lld)",
+                    (long long)in.trial_begin, (long long)in.trial_count, (long long)t->n_trials);
+    L.trial_begin = in.trial_begin;
+    L.trial_count = in.trial_count;
+    return ARA_OK;
+}
+
+bool same_layer(const ara::LayerArgs& a, const ara::LayerArgs& b) {
+    if (a.J != b.J || a.trial_begin != b.trial_begin || a.trial_count != b.trial_count) return false;
+    if (a.occR != b.occR || a.occL != b.occL || a.aggR != b.aggR || a.aggL != b.aggL) return false;
+    for (int j = 0; j < a.J; ++j)
+        if (a.idx[j] != b.idx[j] || a.R[j] != b.R[j] || a.Lim[j] != b.Lim[j]) return false;
+    return true;
+}
+
+// m = ceil(n (1 - p)), p read as the short decimal it approximates: a
+// product within 1e-9 relative of an integer is taken as that integer.
+int64_t tail_count(int64_t n, double p) {
+    const double q = (1.0 - p) * static_cast<double>(n);
+    const double r = std::nearbyint(q);
+    int64_t m;
+    if (std::fabs(q - r) <= 1e-9 * std::fmax(1.0, q)) m = static_cast<int64_t>(r);
+    else m = static_cast<int64_t>(std::ceil(q));
+    if (m < 1) m = 1;
+    if (m > n) m = n;
+    return m;
+}
+
+void free_checkpoints(ara::CheckpointState& ck) {
+    if (ck.S) (void)hipFree(ck.S);
+    if (ck.ylt) (void)hipFree(ck.ylt);
+    if (ck.stride) (void)hipFree(ck.stride);
+    ck = ara::CheckpointState{};
+}
+
+hipError_t take_event(ara::ProfileState& ps, hipEvent_t* ev) {
+    if (!ps.free_events.empty()) {
+        *ev = ps.free_events.back();
+        ps.free_events.pop_back();
+        return hipSuccess;
+    }
+    return hipEventCreate(ev);
+}
+
+// Records an event pair around a launch when profiling is on.
+struct KernelTimer {
+    ara_tables* t;
+    hipStream_t s;
+    bool on;
+    int kind;
+    hipEvent_t a = nullptr, b = nullptr;
+    KernelTimer(ara_tables* t_, hipStream_t s_, bool on_, int kind_) : t(t_), s(s_), on(on_), kind(kind_) {
+        if (!on) return;
+        std::lock_guard<std::mutex> g(t->prof_mu);
+        if (take_event(t->prof, &a) != hipSuccess || take_event(t->prof, &b) != hipSuccess) {
+            on = false;
+            return;
+        }
+        if (hipEventRecord(a, s) != hipSuccess) on = false;
+    }
+    void done() {
+        if (!on) return;
+        if (hipEventRecord(b, s) != hipSuccess) return;
+        std::lock_guard<std::mutex> g(t->prof_mu);
+        t->prof.pending.push_back({a, b, kind});
+        on = false;
+    }
+};
+
+int query_cu_count(int device) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess || prop.multiProcessorCount <= 0) return 256;
+    return prop.multiProcessorCount;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ara_last_error(void) { return g_error.c_str(); }
+
+const char* ara_status_string(ara_status s) {
+    switch (s) {
+        case ARA_OK: return "ARA_OK";
+        case ARA_ERR_INVALID_ARG: return "ARA_ERR_INVALID_ARG";
+        case ARA_ERR_OUT_OF_RANGE: return "ARA_ERR_OUT_OF_RANGE";
+        case ARA_ERR_BUFFER_TOO_SMALL: return "ARA_ERR_BUFFER_TOO_SMALL";
+        case ARA_ERR_NO_MEMORY: return "ARA_ERR_NO_MEMORY";
+        case ARA_ERR_DEVICE: return "ARA_ERR_DEVICE";
+        case ARA_ERR_NOT_READY: return "ARA_ERR_NOT_READY";
+        case ARA_ERR_UNSUPPORTED: return "ARA_ERR_UNSUPPORTED";
+        default: return "ARA_ERR_UNKNOWN";
+    }
+}
+
+ara_status ara_device_info(int32_t* n_cu, int32_t* device) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+    if (n_cu) *n_cu = query_cu_count(dev);
+    if (device) *device = dev;
+    return ARA_OK;
+}
+
+ara_status ara_create_tables(const int64_t* trial_offsets, int64_t n_trials, const uint32_t* event_ids,
+                             int64_t n_events, const double* elt_losses, int32_t n_elts,
+                             int64_t catalogue_size, uint32_t flags, void* stream, ara_tables** out) {
+    if (!out) return fail(ARA_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (n_trials < 0 || n_events < 0 || n_elts < 0 || catalogue_size < 1)
+        return fail(ARA_ERR_INVALID_ARG, "negative size or empty catalogue");
+    if (catalogue_size > (int64_t(1) << 32))
+        return fail(ARA_ERR_INVALID_ARG, "catalogue larger than 2^32 events (IDs are uint32)");
+    if (!trial_offsets || (n_events > 0 && !event_ids) || (n_elts > 0 && !elt_losses))
+        return fail(ARA_ERR_INVALID_ARG, "NULL input array");
+    const bool dev_in = (flags & ARA_DEVICE_PTR) != 0;
+    if (!dev_in) {
+        if (trial_offsets[0] != 0 || trial_offsets[n_trials] != n_events)
+            return fail(ARA_ERR_INVALID_ARG, "offsets must start at 0 and end at n_events");
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int device = 0;
+    HIP_TRY(hipGetDevice(&device), "hipGetDevice");
+    keep_pool_memory(device);
+    ara_tables* t = new (std::nothrow) ara_tables();
+    if (!t) return fail(ARA_ERR_NO_MEMORY, "host allocation failed");
+    t->device = device;
+    t->n_cu = query_cu_count(device);
+    t->n_trials = n_trials;
+    t->n_events = n_events;
+    t->C = catalogue_size;
+    t->n_pool = n_elts;
+    auto cleanup = [&](ara_status st) {
+        ara_destroy_tables(t);
+        return st;
+    };
+    const size_t off_bytes = sizeof(int64_t) * (n_trials + 1);
+    const size_t id_bytes = sizeof(uint32_t) * (n_events + ara::kIdPad);
+    const size_t elt_bytes = sizeof(double) * static_cast<size_t>(n_elts) * catalogue_size;
+    hipError_t e;
+    if ((e = hipMalloc(&t->offsets, off_bytes)) != hipSuccess) return cleanup(hip_fail(e, "hipMalloc offsets"));
+    if ((e = hipMalloc(&t->ids, id_bytes)) != hipSuccess) return cleanup(hip_fail(e, "hipMalloc event ids"));
+    if (elt_bytes && (e = hipMalloc(&t->elts, elt_bytes)) != hipSuccess)
+        return cleanup(hip_fail(e, "hipMalloc ELT pool"));
+    t->bytes = static_cast<int64_t>(off_bytes + id_bytes + elt_bytes);
+    const hipMemcpyKind kind = dev_in ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    if ((e = hipMemcpyAsync(t->offsets, trial_offsets, off_bytes, kind, s)) != hipSuccess)
+        return cleanup(hip_fail(e, "copy offsets"));
+    if (n_events && (e = hipMemcpyAsync(t->ids, event_ids, sizeof(uint32_t) * n_events, kind, s)) != hipSuccess)
+        return cleanup(hip_fail(e, "copy event ids"));
+    if ((e = hipMemsetAsync(t->ids + n_events, 0, sizeof(uint32_t) * ara::kIdPad, s)) != hipSuccess)
+        return cleanup(hip_fail(e, "clear id padding"));
+    if (elt_bytes && (e = hipMemcpyAsync(t->elts, elt_losses, elt_bytes, kind, s)) != hipSuccess)
+        return cleanup(hip_fail(e, "copy ELT pool"));
+    // validation on the device, one flag word read back
+    PoolBuffer flag;
+    if ((e = flag.alloc(sizeof(uint32_t), s)) != hipSuccess) return cleanup(hip_fail(e, "scratch"));
+    if ((e = hipMemsetAsync(flag.p, 0, sizeof(uint32_t), s)) != hipSuccess) return cleanup(hip_fail(e, "memset"));
+    if ((e = ara::launch_validate(t->offsets, n_trials, t->ids, n_events, t->elts,
+                                  static_cast<int64_t>(n_elts) * catalogue_size, catalogue_size,
+                                  static_cast<uint32_t*>(flag.p), t->n_cu, s)) != hipSuccess)
+        return cleanup(hip_fail(e, "validate kernel"));
+    uint32_t host_flag = 0;
+    int64_t ends[2] = {0, 0};
+    if ((e = hipMemcpyAsync(&host_flag, flag.p, sizeof(uint32_t), hipMemcpyDeviceToHost, s)) != hipSuccess)
+        return cleanup(hip_fail(e, "read validation flag"));
+    if ((e = hipMemcpyAsync(&ends[0], t->offsets, sizeof(int64_t), hipMemcpyDeviceToHost, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(&ends[1], t->offsets + n_trials, sizeof(int64_t), hipMemcpyDeviceToHost, s)) !=
+            hipSuccess)
+        return cleanup(hip_fail(e, "read offsets"));
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return cleanup(hip_fail(e, "synchronize"));
+    if (host_flag & 1u) return cleanup(fail(ARA_ERR_OUT_OF_RANGE, "an event ID is >= catalogue size %lld",
+                                            (long long)catalogue_size));
+    if ((host_flag & 2u) || ends[0] != 0 || ends[1] != n_events)
+        return cleanup(fail(ARA_ERR_INVALID_ARG, "trial offsets must start at 0, not decrease, end at n_events"));
+    if (host_flag & 4u) return cleanup(fail(ARA_ERR_INVALID_ARG, "ELT losses must be finite and >= 0"));
+    *out = t;
+    return ARA_OK;
+}
+
+void ara_destroy_tables(ara_tables* t) {
+    if (!t) return;
+    DeviceScope ds(t->device);
+    if (t->offsets) (void)hipFree(t->offsets);
+    if (t->ids) (void)hipFree(t->ids);
+    if (t->elts) (void)hipFree(t->elts);
+    free_checkpoints(t->ck);
+    for (auto& p : t->prof.pending) {
+        (void)hipEventDestroy(p.start);
+        (void)hipEventDestroy(p.stop);
+    }
+    for (auto e : t->prof.free_events) (void)hipEventDestroy(e);
+    delete t;
+}
+
+ara_status ara_table_bytes(const ara_tables* t, int64_t* bytes) {
+    if (!t || !bytes) return fail(ARA_ERR_INVALID_ARG, "NULL argument");
+    *bytes = t->bytes;
+    return ARA_OK;
+}
+
+ara_status ara_kernel_stats(ara_tables* t, int32_t kernel, int64_t* launches, double* total_ms, int32_t reset) {
+    if (!t || kernel < 0 || kernel > 2) return fail(ARA_ERR_INVALID_ARG, "bad argument");
+    DeviceScope ds(t->device);
+    std::lock_guard<std::mutex> g(t->prof_mu);
+    auto& ps = t->prof;
+    for (auto& p : ps.pending) {
+        HIP_TRY(hipEventSynchronize(p.stop), "event synchronize");
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, p.start, p.stop), "event elapsed");
+        ps.launches[p.kind] += 1;
+        ps.total_ms[p.kind] += ms;
+        ps.free_events.push_back(p.start);
+        ps.free_events.push_back(p.stop);
+    }
+    ps.pending.clear();
+    if (launches) *launches = ps.launches[kernel];
+    if (total_ms) *total_ms = ps.total_ms[kernel];
+    if (reset) {
+        ps.launches[kernel] = 0;
+        ps.total_ms[kernel] = 0.0;
+    }
+    return ARA_OK;
+}
+
+ara_status ara_set_tuning(ara_tables* t, const ara_tuning* tu) {
+    if (!t) return fail(ARA_ERR_INVALID_ARG, "NULL tables");
+    ara_tuning v{};
+    if (tu) v = *tu;
+    if (v.lanes_per_trial != 0 && v.lanes_per_trial != 8 && v.lanes_per_trial != 16 &&
+        v.lanes_per_trial != 32 && v.lanes_per_trial != 64)
+        return fail(ARA_ERR_INVALID_ARG, "lanes_per_trial must be 8, 16, 32 or 64");
+    if (v.blocks_per_cu < 0 || v.blocks_per_cu > 64) return fail(ARA_ERR_INVALID_ARG, "blocks_per_cu in [0, 64]");
+    std::lock_guard<std::mutex> g(t->mu);
+    t->tuning = v;
+    return ARA_OK;
+}
+
+ara_status ara_get_tuning(const ara_tables* t, ara_tuning* tu) {
+    if (!t || !tu) return fail(ARA_ERR_INVALID_ARG, "NULL argument");
+    std::lock_guard<std::mutex> g(const_cast<ara_tables*>(t)->mu);
+    *tu = t->tuning;
+    return ARA_OK;
+}
+
+ara_status ara_footprint(const ara_tables* t, const ara_layer* layers, int32_t n_layers, uint32_t flags,
+                         int64_t* bytes) {
+    if (!t || !bytes || (n_layers > 0 && !layers) || n_layers < 0)
+        return fail(ARA_ERR_INVALID_ARG, "NULL argument or negative layer count");
+    int64_t total = 0;
+    for (int i = 0; i < n_layers; ++i) total += layers[i].trial_count;
+    int64_t b = 0;
+    if (!(flags & ARA_LITERAL)) b += sizeof(double) * t->C;            // occurrence losses
+    if (!(flags & ARA_DEVICE_PTR)) b += sizeof(double) * total;       // staged output
+    if (flags & ARA_CHECKPOINT_S)
+        b += 2 * sizeof(double) * total + sizeof(double) * (t->n_events / ara::kStride + 1);
+    *bytes = b;
+    return ARA_OK;
+}
+
+ara_status ara_run_layers(ara_tables* t, const ara_layer* layers, int32_t n_layers, double* ylt,
+                          int64_t ylt_capacity, uint32_t flags, void* stream) {
+    if (!t || !layers || n_layers < 1) return fail(ARA_ERR_INVALID_ARG, "NULL argument or no layer");
+    const bool ckpt = (flags & ARA_CHECKPOINT_S) != 0;
+    if (ckpt && n_layers != 1) return fail(ARA_ERR_UNSUPPORTED, "ARA_CHECKPOINT_S takes exactly one layer");
+    std::vector<ara::LayerArgs> L(n_layers);
+    int64_t total = 0;
+    for (int i = 0; i < n_layers; ++i) {
+        ara_status st = build_layer_args(t, layers[i], L[i]);
+        if (st != ARA_OK) return st;
+        L[i].out_offset = total;
+        total += L[i].trial_count;
+    }
+    if (total == 0) return ARA_OK;
+    if (!ylt) return fail(ARA_ERR_INVALID_ARG, "ylt is NULL");
+    if (ylt_capacity < total)
+        return fail(ARA_ERR_BUFFER_TOO_SMALL, "ylt holds %lld values, %lld needed", (long long)ylt_capacity,
+                    (long long)total);
+    DeviceScope ds(t->device);
+    if (!ds.ok) return fail(ARA_ERR_DEVICE, "cannot select the tables' device");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const bool dev_out = (flags & ARA_DEVICE_PTR) != 0;
+    const bool literal = (flags & ARA_LITERAL) != 0;
+    ara_tuning tu;
+    {
+        std::lock_guard<std::mutex> g(t->mu);
+        tu = t->tuning;
+    }
+    PoolBuffer staged, obuf;
+    double* out = ylt;
+    if (!dev_out) {
+        HIP_TRY(staged.alloc(sizeof(double) * (total > 0 ? total : 1), s), "scratch for YLT");
+        out = static_cast<double*>(staged.p);
+    }
+    if (!literal) HIP_TRY(obuf.alloc(sizeof(double) * t->C, s), "scratch for occurrence losses");
+    double* S_buf = nullptr;
+    double* stride_buf = nullptr;
+    std::unique_lock<std::mutex> ck_lock(t->mu, std::defer_lock);
+    if (ckpt) {
+        ck_lock.lock();
+        auto& ck = t->ck;
+        ck.valid = false;
+        if (ck.count < L[0].trial_count || !ck.S) {
+            if (ck.S) (void)hipFree(ck.S);
+            if (ck.ylt) (void)hipFree(ck.ylt);
+            ck.S = ck.ylt = nullptr;
+            const size_t nb = sizeof(double) * (L[0].trial_count > 0 ? L[0].trial_count : 1);
+            HIP_TRY(hipMalloc(&ck.S, nb), "checkpoint S");
+            HIP_TRY(hipMalloc(&ck.ylt, nb), "checkpoint YLT");
+            ck.count = L[0].trial_count;
+        }
+        if (!ck.stride) HIP_TRY(hipMalloc(&ck.stride, sizeof(double) * (t->n_events / ara::kStride + 1)),
+                                "stride checkpoints");
+        HIP_TRY(ara::launch_fill(ck.stride, t->n_events / ara::kStride + 1, std::nan(""), s), "fill");
+        S_buf = ck.S;
+        stride_buf = ck.stride;
+    }
+    for (int i = 0; i < n_layers; ++i) {
+        ara::TrialPassArgs a{};
+        a.offsets = t->offsets;
+        a.ids = t->ids;
+        a.elts = t->elts;
+        a.C = t->C;
+        a.o = static_cast<const double*>(obuf.p);
+        a.ylt = out + L[i].out_offset;
+        a.S = S_buf;
+        a.stride = stride_buf;
+        const bool prof = (flags & ARA_PROFILE) != 0;
+        if (!literal) {
+            KernelTimer kt(t, s, prof, ARA_KERNEL_FOLD);
+            HIP_TRY(ara::launch_fold(t->elts, t->C, L[i], static_cast<double*>(obuf.p), tu, s), "fold");
+            kt.done();
+        }
+        KernelTimer kt(t, s, prof, ARA_KERNEL_TRIAL_PASS);
+        HIP_TRY(ara::launch_trial_pass(a, L[i], literal, tu, t->n_cu, s), "trial pass");
+        kt.done();
+    }
+    if (ckpt) {
+        HIP_TRY(hipMemcpyAsync(t->ck.ylt, out, sizeof(double) * L[0].trial_count, hipMemcpyDeviceToDevice, s),
+                "keep YLT");
+        t->ck.key = L[0];
+        t->ck.valid = true;
+    }
+    if (!dev_out) {
+        HIP_TRY(hipMemcpyAsync(ylt, out, sizeof(double) * total, hipMemcpyDeviceToHost, s), "copy YLT");
+        HIP_TRY(hipStreamSynchronize(s), "synchronize");
+    }
+    return ARA_OK;
+}
+
+ara_status ara_risk_metrics(const double* ylt, int64_t n_trials, const double* probs, int32_t n_probs,
+                            double* mean_out, double* pml_out, double* tvar_out, uint32_t flags, void* stream) {
+    if (!ylt || !mean_out || n_probs < 0 || (n_probs > 0 && (!probs || !pml_out || !tvar_out)))
+        return fail(ARA_ERR_INVALID_ARG, "NULL argument");
+    if (n_trials < 1) return fail(ARA_ERR_INVALID_ARG, "need at least one trial");
+    if (n_probs > 4) return fail(ARA_ERR_UNSUPPORTED, "at most 4 probabilities per call");
+    std::vector<int64_t> m(n_probs);
+    for (int q = 0; q < n_probs; ++q) {
+        if (!(probs[q] > 0.0 && probs[q] < 1.0)) return fail(ARA_ERR_INVALID_ARG, "p must lie in (0, 1)");
+        m[q] = tail_count(n_trials, probs[q]);
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int device = 0;
+    HIP_TRY(hipGetDevice(&device), "hipGetDevice");
+    keep_pool_memory(device);
+    const int n_cu = query_cu_count(device);
+    const bool dev = (flags & ARA_DEVICE_PTR) != 0;
+    PoolBuffer scratch, staged_in, results;
+    HIP_TRY(scratch.alloc(ara::metrics_scratch_bytes(n_probs), s), "metrics scratch");
+    HIP_TRY(results.alloc(sizeof(double) * (1 + 2 * n_probs), s), "metrics results");
+    const double* x = ylt;
+    if (!dev) {
+        HIP_TRY(staged_in.alloc(sizeof(double) * n_trials, s), "metrics input");
+        HIP_TRY(hipMemcpyAsync(staged_in.p, ylt, sizeof(double) * n_trials, hipMemcpyHostToDevice, s), "copy YLT");
+        x = static_cast<const double*>(staged_in.p);
+    }
+    double* r = static_cast<double*>(results.p);
+    HIP_TRY(ara::launch_metrics(x, n_trials, m.data(), n_probs, scratch.p, r, n_cu, s), "metrics kernels");
+    if (dev) {
+        HIP_TRY(hipMemcpyAsync(mean_out, r, sizeof(double), hipMemcpyDeviceToDevice, s), "copy mean");
+        for (int q = 0; q < n_probs; ++q) {
+            HIP_TRY(hipMemcpyAsync(pml_out + q, r + 1 + 2 * q, sizeof(double), hipMemcpyDeviceToDevice, s), "copy");
+            HIP_TRY(hipMemcpyAsync(tvar_out + q, r + 2 + 2 * q, sizeof(double), hipMemcpyDeviceToDevice, s), "copy");
+        }
+        return ARA_OK;
+    }
+    std::vector<double> h(1 + 2 * n_probs);
+    HIP_TRY(hipMemcpyAsync(h.data(), r, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s), "copy metrics");
+    HIP_TRY(hipStreamSynchronize(s), "synchronize");
+    if (std::isnan(h[0])) return fail(ARA_ERR_INVALID_ARG, "year losses must be >= 0 and not NaN");
+    *mean_out = h[0];
+    for (int q = 0; q < n_probs; ++q) {
+        pml_out[q] = h[1 + 2 * q];
+        tvar_out[q] = h[2 + 2 * q];
+    }
+    return ARA_OK;
+}
+
+ara_status ara_backward(ara_tables* t, const ara_layer* layer, double tvar_p, double* grad_mean,
+                        double* grad_tvar, uint32_t flags, void* stream) {
+    if (!t || !layer) return fail(ARA_ERR_INVALID_ARG, "NULL argument");
+    if (!(tvar_p > 0.0 && tvar_p < 1.0)) return fail(ARA_ERR_INVALID_ARG, "tvar_p must lie in (0, 1)");
+    ara::LayerArgs L;
+    ara_status st = build_layer_args(t, *layer, L);
+    if (st != ARA_OK) return st;
+    if (L.trial_count < 1) return fail(ARA_ERR_INVALID_ARG, "layer has no trials");
+    std::lock_guard<std::mutex> g(t->mu);
+    if (!t->ck.valid || !same_layer(t->ck.key, L))
+        return fail(ARA_ERR_NOT_READY, "no checkpointed forward for this layer (run with ARA_CHECKPOINT_S)");
+    DeviceScope ds(t->device);
+    if (!ds.ok) return fail(ARA_ERR_DEVICE, "cannot select the tables' device");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int P = 2 * L.J + 4;
+    const bool dev = (flags & ARA_DEVICE_PTR) != 0;
+    PoolBuffer scratch, staged;
+    HIP_TRY(scratch.alloc(ara::adjoint_scratch_bytes(t->C, L.J), s), "adjoint scratch");
+    double* gm = grad_mean;
+    double* gt = grad_tvar;
+    if (!dev) {
+        HIP_TRY(staged.alloc(sizeof(double) * 2 * P, s), "adjoint output");
+        gm = grad_mean ? static_cast<double*>(staged.p) : nullptr;
+        gt = grad_tvar ? static_cast<double*>(staged.p) + P : nullptr;
+    }
+    const int64_t m = tail_count(L.trial_count, tvar_p);
+    HIP_TRY(ara::launch_adjoint(t->offsets, t->ids, t->elts, t->C, L, t->ck.S, t->ck.ylt, m, scratch.p, gm, gt,
+                                t->n_cu, s),
+            "adjoint kernels");
+    if (!dev) {
+        std::vector<double> h(2 * P);
+        HIP_TRY(hipMemcpyAsync(h.data(), staged.p, sizeof(double) * 2 * P, hipMemcpyDeviceToHost, s), "copy");
+        HIP_TRY(hipStreamSynchronize(s), "synchronize");
+        if (grad_mean) std::memcpy(grad_mean, h.data(), sizeof(double) * P);
+        if (grad_tvar) std::memcpy(grad_tvar, h.data() + P, sizeof(double) * P);
+    }
+    return ARA_OK;
+}
+
+ara_status ara_debug_lookups(ara_tables* t, const ara_layer* layer, int64_t trial, uint32_t* ids_out,
+                             double* losses_out, int64_t capacity, int64_t* n_out, void* stream) {
+    if (!t || !layer || !n_out || capacity < 0) return fail(ARA_ERR_INVALID_ARG, "NULL argument");
+    if (trial < 0 || trial >= t->n_trials) return fail(ARA_ERR_INVALID_ARG, "trial outside the YET");
+    ara_layer probe = *layer;
+    probe.trial_begin = 0;
+    probe.trial_count = 0;
+    ara::LayerArgs L;
+    ara_status st = build_layer_args(t, probe, L);
+    if (st != ARA_OK) return st;
+    DeviceScope ds(t->device);
+    if (!ds.ok) return fail(ARA_ERR_DEVICE, "cannot select the tables' device");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int64_t be[2];
+    HIP_TRY(hipMemcpyAsync(be, t->offsets + trial, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, s), "offsets");
+    HIP_TRY(hipStreamSynchronize(s), "synchronize");
+    const int64_t K = be[1] - be[0];
+    *n_out = K;
+    if (K > capacity) return fail(ARA_ERR_BUFFER_TOO_SMALL, "trial has %lld events, capacity %lld",
+                                  (long long)K, (long long)capacity);
+    if (K == 0) return ARA_OK;
+    if (!ids_out || (L.J > 0 && !losses_out)) return fail(ARA_ERR_INVALID_ARG, "NULL output");
+    PoolBuffer dids, dloss;
+    HIP_TRY(dids.alloc(sizeof(uint32_t) * K, s), "scratch");
+    HIP_TRY(dloss.alloc(sizeof(double) * K * (L.J > 0 ? L.J : 1), s), "scratch");
+    HIP_TRY(ara::launch_debug_lookups(t->offsets, t->ids, t->elts, t->C, L, trial, static_cast<uint32_t*>(dids.p),
+                                      static_cast<double*>(dloss.p), s),
+            "lookup kernel");
+    HIP_TRY(hipMemcpyAsync(ids_out, dids.p, sizeof(uint32_t) * K, hipMemcpyDeviceToHost, s), "copy ids");
+    if (L.J > 0)
+        HIP_TRY(hipMemcpyAsync(losses_out, dloss.p, sizeof(double) * K * L.J, hipMemcpyDeviceToHost, s), "copy");
+    HIP_TRY(hipStreamSynchronize(s), "synchronize");
+    return ARA_OK;
+}
+
+ara_status ara_read_checkpoints(ara_tables* t, int32_t what, double* out, int64_t capacity, int64_t* n_out) {
+    if (!t || !n_out || (what != 0 && what != 1)) return fail(ARA_ERR_INVALID_ARG, "bad argument");
+    std::lock_guard<std::mutex> g(t->mu);
+    if (!t->ck.valid) return fail(ARA_ERR_NOT_READY, "no checkpointed forward");
+    DeviceScope ds(t->device);
+    const int64_t n = what == 0 ? t->ck.key.trial_count : t->n_events / ara::kStride;
+    *n_out = n;
+    if (capacity < n) return fail(ARA_ERR_BUFFER_TOO_SMALL, "need %lld values", (long long)n);
+    if (n == 0) return ARA_OK;
+    if (!out) return fail(ARA_ERR_INVALID_ARG, "NULL output");
+    HIP_TRY(hipDeviceSynchronize(), "synchronize");
+    HIP_TRY(hipMemcpy(out, what == 0 ? t->ck.S : t->ck.stride, sizeof(double) * n, hipMemcpyDeviceToHost), "copy");
+    return ARA_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,197 @@
+// Internal declarations shared by the HIP translation units of libara.
+// Device code is written for gfx950 (CDNA4): 64-lane wavefronts, 160 KB LDS
+// per CU, 256 CUs in 8 XCDs.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "ara.h"
+
+namespace ara {
+
+constexpr int kWave = 64;
+constexpr int kMaxJ = ARA_MAX_LAYER_ELTS;
+constexpr int kStride = ARA_CHECKPOINT_STRIDE;
+// The event-ID array is padded with zero IDs so that aligned 16-byte loads
+// covering a trial's last events never leave the allocation.
+constexpr int64_t kIdPad = 1024;
+
+// Layer description passed by value: it lands in the kernel-argument
+// segment and is read with scalar loads (the paper kept financial terms in
+// constant memory for the same reason: every lane reads the same value).
+struct LayerArgs {
+    int32_t J;
+    int32_t pad_;
+    double occR, occL, aggR, aggL;
+    int64_t trial_begin, trial_count;
+    int64_t out_offset;
+    int32_t idx[kMaxJ];
+    double R[kMaxJ];
+    double Lim[kMaxJ];
+};
+
+// ---------------------------------------------------------------------------
+// device helpers
+// ---------------------------------------------------------------------------
+
+// clamp(v; r, lim) = min(max(v - r, 0), lim): retention r, then limit lim.
+__device__ __forceinline__ double apply_terms(double v, double r, double lim) {
+    double t = v - r;
+    t = (t > 0.0) ? t : 0.0;
+    t = (t > lim) ? lim : t;
+    return t;
+}
+
+// Error-free sum (Knuth): s + e == a + b exactly.
+__device__ __forceinline__ void two_sum(double a, double b, double& s, double& e) {
+    s = a + b;
+    double bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
+}
+
+// Double-double accumulate: (hi, lo) += x.
+__device__ __forceinline__ void dd_add(double& hi, double& lo, double x) {
+    double s, e;
+    two_sum(hi, x, s, e);
+    hi = s;
+    lo += e;
+}
+
+// (hi, lo) += (hi2, lo2).  Symmetric in its operands, so butterfly partners
+// end with identical values.
+__device__ __forceinline__ void dd_merge(double& hi, double& lo, double hi2, double lo2) {
+    double s, e;
+    two_sum(hi, hi2, s, e);
+    hi = s;
+    lo = (lo + lo2) + e;
+}
+
+__device__ __forceinline__ double shfl_xor_f64(double v, int mask) {
+    return __shfl_xor(v, mask, kWave);
+}
+
+__device__ __forceinline__ double shfl_f64(double v, int src) {
+    return __shfl(v, src, kWave);
+}
+
+// Butterfly reduction over `width` lanes (power of two <= 64); every lane of
+// each group of `width` lanes ends with the group's total.
+__device__ __forceinline__ void group_reduce_dd(double& hi, double& lo, int width) {
+    for (int off = width >> 1; off >= 1; off >>= 1) {
+        double h2 = shfl_xor_f64(hi, off);
+        double l2 = shfl_xor_f64(lo, off);
+        dd_merge(hi, lo, h2, l2);
+    }
+}
+
+__device__ __forceinline__ int64_t uniform_i64(int64_t v) {
+    uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(v));
+    uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(static_cast<uint64_t>(v) >> 32));
+    return static_cast<int64_t>((static_cast<uint64_t>(hi) << 32) | lo);
+}
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------------------
+// host-side state
+// ---------------------------------------------------------------------------
+
+struct CheckpointState {
+    bool valid = false;
+    LayerArgs key{};
+    double* S = nullptr;        // [trial_count]
+    double* ylt = nullptr;      // [trial_count]
+    double* stride = nullptr;   // [n_events / 64 + 1]
+    int64_t count = 0;
+};
+
+struct ProfileState {
+    struct Pending {
+        hipEvent_t start, stop;
+        int kind;
+    };
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> free_events;
+    int64_t launches[3] = {0, 0, 0};
+    double total_ms[3] = {0.0, 0.0, 0.0};
+};
+
+}  // namespace ara
+
+struct ara_tables {
+    int device = 0;
+    int n_cu = 256;
+    int64_t n_trials = 0;
+    int64_t n_events = 0;
+    int64_t C = 0;
+    int32_t n_pool = 0;
+    int64_t* offsets = nullptr;   // [n_trials + 1]
+    uint32_t* ids = nullptr;      // [n_events + kIdPad]
+    double* elts = nullptr;       // [n_pool][C]
+    int64_t bytes = 0;
+    ara_tuning tuning{};
+    std::mutex mu;                // guards ck and tuning
+    ara::CheckpointState ck;
+    std::mutex prof_mu;           // guards prof
+    ara::ProfileState prof;
+};
+
+namespace ara {
+
+// ---------------------------------------------------------------------------
+// launchers (each defined in the translation unit holding its kernels)
+// ---------------------------------------------------------------------------
+
+struct TrialPassArgs {
+    const int64_t* offsets;
+    const uint32_t* ids;
+    const double* elts;   // literal mode
+    int64_t C;
+    const double* o;      // folded mode: occurrence-net loss per catalogue event
+    double* ylt;          // [trial_count]
+    double* S;            // [trial_count] or null
+    double* stride;       // checkpoints or null
+};
+
+hipError_t launch_validate(const int64_t* offsets, int64_t n_trials, const uint32_t* ids,
+                           int64_t n_events, const double* elts, int64_t n_elt_values,
+                           int64_t C, uint32_t* d_flags, int n_cu, hipStream_t s);
+hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t s);
+
+hipError_t launch_fold(const double* elts, int64_t C, const LayerArgs& L, double* o,
+                       const ara_tuning& tu, hipStream_t s);
+hipError_t launch_trial_pass(const TrialPassArgs& a, const LayerArgs& L, bool literal,
+                             const ara_tuning& tu, int n_cu, hipStream_t s);
+hipError_t launch_debug_lookups(const int64_t* offsets, const uint32_t* ids, const double* elts,
+                                int64_t C, const LayerArgs& L, int64_t trial, uint32_t* ids_out,
+                                double* losses_out, hipStream_t s);
+
+// metrics: results[0] = mean, results[1 + 2q] = PML_q, results[2 + 2q] = TVaR_q
+int64_t metrics_scratch_bytes(int n_probs);
+hipError_t launch_metrics(const double* ylt, int64_t n, const int64_t* m_host, int n_probs,
+                          void* scratch, double* d_results, int n_cu, hipStream_t s);
+
+// order statistics of a YLT for one tail count m
+struct TailStats {
+    uint64_t v_bits;   // bit pattern of the m-th largest year loss
+    int64_t c_gt;      // year losses strictly above it
+    int64_t c_eq;      // year losses equal to it
+    int64_t m;
+};
+int64_t tail_stats_scratch_bytes();
+hipError_t launch_tail_stats(const double* ylt, int64_t n, int64_t m, void* scratch, TailStats* out,
+                             int n_cu, hipStream_t s);
+
+// adjoint
+int64_t adjoint_scratch_bytes(int64_t C, int J);
+hipError_t launch_adjoint(const int64_t* offsets, const uint32_t* ids, const double* elts,
+                          int64_t C, const LayerArgs& L, const double* S, const double* ylt,
+                          int64_t m, void* scratch, double* d_grad_mean, double* d_grad_tvar,
+                          int n_cu, hipStream_t s);
+
+}  // namespace ara

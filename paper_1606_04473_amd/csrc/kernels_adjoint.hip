@@ -1,0 +1,216 @@
+// Adjoint of the year loss with respect to a layer's terms.
+//
+// With the strict convention at kinks every partial of YLT_t is an integer:
+//   d YLT_t / d theta_k = a_t * sum over the trial's occurrences of g_k(E)
+// for the per-ELT and occurrence terms, where a_t = [0 < S_t - AggR < AggL]
+// and g_k(E) in {-1, 0, 1} depends on the event only; dYLT_t/dAggR = -a_t and
+// dYLT_t/dAggL = [S_t - AggR > AggL].  Summing over trials with weights w_t
+// (1 for the mean; for TVaR c_eq above the m-th largest value v and m - c_gt
+// at v) regroups by event:
+//   sum_t w_t a_t sum_d g_k(E_td) = sum_E g_k(E) * W(E),
+//   W(E) = sum over active trials of w_t * (multiplicity of E in trial t).
+// So the backward is one pass over the events of active trials that builds
+// the integer histogram W (only for events whose occurrence loss can move:
+// y(E) - OccR > 0), then one pass over the catalogue that evaluates g(E)
+// with the forward's FP64 operations and accumulates g_k(E) W(E) in int64.
+// Integer atomics make the result independent of scheduling.
+#include "ara_internal.hpp"
+
+namespace ara {
+
+namespace {
+
+constexpr int kMaxP = 2 * kMaxJ + 4;
+
+// signed 64-bit add through the unsigned atomic (two's complement wraps)
+__device__ __forceinline__ void add_i64(long long* p, long long v) {
+    atomicAdd(reinterpret_cast<unsigned long long*>(p), static_cast<unsigned long long>(v));
+}
+
+struct AdjScratch {
+    uint8_t* mark;         // [C]
+    uint64_t* w_mean;      // [C]
+    uint64_t* w_tvar;      // [C]
+    long long* acc;        // [2][kMaxP] integer numerators
+    TailStats* tail;
+    void* tail_scratch;
+};
+
+__global__ __launch_bounds__(256) void mark_kernel(const double* __restrict__ elts, int64_t C, LayerArgs L,
+                                                   uint8_t* __restrict__ mark, uint64_t* __restrict__ w_mean,
+                                                   uint64_t* __restrict__ w_tvar) {
+    const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= C) return;
+    double y = 0.0;
+    for (int j = 0; j < L.J; ++j)
+        y = y + apply_terms(elts[static_cast<int64_t>(L.idx[j]) * C + e], L.R[j], L.Lim[j]);
+    mark[e] = (y - L.occR > 0.0) ? 1 : 0;
+    w_mean[e] = 0;
+    w_tvar[e] = 0;
+}
+
+__global__ void clear_acc_kernel(long long* acc) {
+    for (int i = threadIdx.x; i < 2 * kMaxP; i += blockDim.x) acc[i] = 0;
+}
+
+// one wavefront per trial; only trials inside the aggregate band read events
+__global__ __launch_bounds__(256) void active_trials_kernel(const int64_t* __restrict__ offsets,
+                                                            const uint32_t* __restrict__ ids, LayerArgs L,
+                                                            const double* __restrict__ S,
+                                                            const double* __restrict__ ylt,
+                                                            const TailStats* __restrict__ tail,
+                                                            const uint8_t* __restrict__ mark,
+                                                            uint64_t* __restrict__ w_mean,
+                                                            uint64_t* __restrict__ w_tvar,
+                                                            long long* __restrict__ acc) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = uniform_i64((static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6);
+    const int64_t n_waves = (static_cast<int64_t>(gridDim.x) * blockDim.x) >> 6;
+    const TailStats ts = *tail;
+    const int P = 2 * L.J + 4;
+    long long agg_r_mean = 0, agg_l_mean = 0, agg_r_tvar = 0, agg_l_tvar = 0;
+    for (int64_t k = wave; k < L.trial_count; k += n_waves) {
+        const double ta = S[k] - L.aggR;
+        const bool in_band = (ta > 0.0) && (ta < L.aggL);
+        const bool above = ta > L.aggL;
+        const uint64_t key = __double_as_longlong(ylt[k] + 0.0);
+        const long long wt = key > ts.v_bits ? ts.c_eq : (key == ts.v_bits ? ts.m - ts.c_gt : 0);
+        if (in_band) {
+            agg_r_mean -= 1;
+            agg_r_tvar -= wt;
+        }
+        if (above) {
+            agg_l_mean += 1;
+            agg_l_tvar += wt;
+        }
+        if (!in_band) continue;
+        const int64_t t = L.trial_begin + k;
+        const int64_t b = offsets[t];
+        const int64_t e = offsets[t + 1];
+        for (int64_t i = b + lane; i < e; i += kWave) {
+            const uint32_t id = ids[i];
+            if (mark[id]) {
+                atomicAdd(reinterpret_cast<unsigned long long*>(&w_mean[id]), 1ull);
+                if (wt) atomicAdd(reinterpret_cast<unsigned long long*>(&w_tvar[id]),
+                                  static_cast<unsigned long long>(wt));
+            }
+        }
+    }
+    if (lane == 0) {
+        if (agg_r_mean) add_i64(&acc[P - 2], agg_r_mean);
+        if (agg_l_mean) add_i64(&acc[P - 1], agg_l_mean);
+        if (agg_r_tvar) add_i64(&acc[kMaxP + P - 2], agg_r_tvar);
+        if (agg_l_tvar) add_i64(&acc[kMaxP + P - 1], agg_l_tvar);
+    }
+}
+
+// g(E) W(E) over the catalogue; per-workgroup int64 accumulators in LDS
+__global__ __launch_bounds__(256) void catalogue_kernel(const double* __restrict__ elts, int64_t C, LayerArgs L,
+                                                        const uint64_t* __restrict__ w_mean,
+                                                        const uint64_t* __restrict__ w_tvar,
+                                                        long long* __restrict__ acc) {
+    __shared__ long long lacc[2 * kMaxP];
+    const int P = 2 * L.J + 4;
+    for (int i = threadIdx.x; i < 2 * kMaxP; i += blockDim.x) lacc[i] = 0;
+    __syncthreads();
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+    for (int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < C; e += stride) {
+        const long long wm = static_cast<long long>(w_mean[e]);
+        const long long wv = static_cast<long long>(w_tvar[e]);
+        if (wm == 0 && wv == 0) continue;
+        double y = 0.0;
+        for (int j = 0; j < L.J; ++j)
+            y = y + apply_terms(elts[static_cast<int64_t>(L.idx[j]) * C + e], L.R[j], L.Lim[j]);
+        const double to = y - L.occR;
+        const bool in_occ = (to > 0.0) && (to < L.occL);
+        const bool above_occ = to > L.occL;
+        if (above_occ) {
+            add_i64(&lacc[2 * L.J + 1], wm);
+            if (wv) add_i64(&lacc[kMaxP + 2 * L.J + 1], wv);
+        }
+        if (!in_occ) continue;
+        add_i64(&lacc[2 * L.J], -wm);
+        if (wv) add_i64(&lacc[kMaxP + 2 * L.J], -wv);
+        for (int j = 0; j < L.J; ++j) {
+            const double tj = elts[static_cast<int64_t>(L.idx[j]) * C + e] - L.R[j];
+            if (tj > 0.0 && tj < L.Lim[j]) {
+                add_i64(&lacc[j], -wm);
+                if (wv) add_i64(&lacc[kMaxP + j], -wv);
+            }
+            if (tj > L.Lim[j]) {
+                add_i64(&lacc[L.J + j], wm);
+                if (wv) add_i64(&lacc[kMaxP + L.J + j], wv);
+            }
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < 2 * kMaxP; i += blockDim.x) {
+        const int q = i % kMaxP;
+        if (q < P - 2 && lacc[i] != 0) add_i64(&acc[i], lacc[i]);
+    }
+}
+
+__global__ void finalize_kernel(const long long* acc, const TailStats* tail, int P, int64_t n,
+                                double* grad_mean, double* grad_tvar) {
+    const int i = threadIdx.x;
+    if (i >= P) return;
+    const TailStats ts = *tail;
+    if (grad_mean) grad_mean[i] = static_cast<double>(acc[i]) / static_cast<double>(n);
+    if (grad_tvar) grad_tvar[i] = static_cast<double>(acc[kMaxP + i]) / static_cast<double>(ts.m * ts.c_eq);
+}
+
+AdjScratch carve(void* base, int64_t C) {
+    char* p = static_cast<char*>(base);
+    AdjScratch s;
+    const int64_t Ca = (C + 255) & ~int64_t(255);
+    s.w_mean = reinterpret_cast<uint64_t*>(p);
+    p += Ca * sizeof(uint64_t);
+    s.w_tvar = reinterpret_cast<uint64_t*>(p);
+    p += Ca * sizeof(uint64_t);
+    s.acc = reinterpret_cast<long long*>(p);
+    p += 2 * kMaxP * sizeof(long long);
+    s.tail = reinterpret_cast<TailStats*>(p);
+    p += 256;
+    s.mark = reinterpret_cast<uint8_t*>(p);
+    p += Ca;
+    s.tail_scratch = p;
+    return s;
+}
+
+}  // namespace
+
+int64_t adjoint_scratch_bytes(int64_t C, int J) {
+    (void)J;
+    const int64_t Ca = (C + 255) & ~int64_t(255);
+    return Ca * (2 * sizeof(uint64_t) + 1) + 2 * kMaxP * sizeof(long long) + 256 + tail_stats_scratch_bytes();
+}
+
+hipError_t launch_adjoint(const int64_t* offsets, const uint32_t* ids, const double* elts, int64_t C,
+                          const LayerArgs& L, const double* S, const double* ylt, int64_t m, void* scratch,
+                          double* d_grad_mean, double* d_grad_tvar, int n_cu, hipStream_t s) {
+    AdjScratch a = carve(scratch, C);
+    hipError_t err;
+    const int64_t n = L.trial_count;
+    if ((err = launch_tail_stats(ylt, n, m, a.tail_scratch, a.tail, n_cu, s)) != hipSuccess) return err;
+    hipLaunchKernelGGL(clear_acc_kernel, dim3(1), dim3(256), 0, s, a.acc);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+    const uint32_t cblocks = static_cast<uint32_t>((C + 255) / 256);
+    hipLaunchKernelGGL(mark_kernel, dim3(cblocks), dim3(256), 0, s, elts, C, L, a.mark, a.w_mean, a.w_tvar);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+    int64_t tblocks = (n + 3) / 4;
+    if (tblocks > int64_t(n_cu) * 8) tblocks = int64_t(n_cu) * 8;
+    if (tblocks < 1) tblocks = 1;
+    hipLaunchKernelGGL(active_trials_kernel, dim3(static_cast<uint32_t>(tblocks)), dim3(256), 0, s, offsets,
+                       ids, L, S, ylt, a.tail, a.mark, a.w_mean, a.w_tvar, a.acc);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+    int64_t gblocks = (C + 255) / 256;
+    if (gblocks > int64_t(n_cu) * 4) gblocks = int64_t(n_cu) * 4;
+    hipLaunchKernelGGL(catalogue_kernel, dim3(static_cast<uint32_t>(gblocks)), dim3(256), 0, s, elts, C, L,
+                       a.w_mean, a.w_tvar, a.acc);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(256), 0, s, a.acc, a.tail, 2 * L.J + 4, n, d_grad_mean,
+                       d_grad_tvar);
+    return hipGetLastError();
+}
+
+}  // namespace ara

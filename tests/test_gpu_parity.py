@@ -1,0 +1,419 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle.
+
+Bars: lookups and event indexing bit-exact; year losses, S and metrics within
+1e-12 relative (the library sums S in double-double and rounds once, the
+oracle sums exactly and rounds once, so almost every value is bit-exact and
+the tests also count those); gradients are ratios of integers and must match
+exactly.
+"""
+
+import json
+import math
+import os
+import threading
+
+import numpy as np
+import pytest
+
+import oracle
+from workloads import ELTPool, Layer, make_config, make_tiny_yet, make_yet, make_elt_pool
+
+pytestmark = pytest.mark.gpu
+
+REL = 1e-12
+INF = math.inf
+
+
+@pytest.fixture(scope="module")
+def ara():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    from paper_1606_04473_amd import ara as mod
+    mod.lib()
+    return mod
+
+
+def _close(a, b, rel=REL):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    err = np.abs(a - b)
+    return bool(np.all(err <= rel * np.abs(b))), float(np.max(err / np.maximum(np.abs(b), 1e-300),
+                                                              initial=0.0))
+
+
+def _spec(ara, layer, pool, yet):
+    return ara.LayerSpec.from_layer(layer, pool, yet.n_trials)
+
+
+# ---------------------------------------------------------------------------
+# closed forms through the C ABI
+# ---------------------------------------------------------------------------
+
+def test_closed_form_cases(ara, golden_dir):
+    g = json.load(open(os.path.join(golden_dir, "closed_form_cases.json")))
+    losses = np.array(g["elts"], dtype=np.float64)
+    pool = ELTPool(losses, np.array(g["elt_retention"]), np.array(g["elt_limit"]))
+    for case in g["cases"]:
+        yet = make_tiny_yet(case["trials"], g["catalogue_size"])
+        t = case["terms"]
+        f = lambda v: INF if v == "inf" else float(v)  # noqa: E731
+        layer = Layer(np.array(case["elt_index"], dtype=np.int32), f(t["occ_retention"]),
+                      f(t["occ_limit"]), f(t["agg_retention"]), f(t["agg_limit"]), 0, yet.n_trials)
+        tables = ara.create_tables(yet.offsets, yet.ids, pool.losses)
+        for flags in (0, ara.ARA_LITERAL, ara.ARA_CHECKPOINT_S):
+            for lpt in (64, 16):
+                ara.set_tuning(tables, lanes_per_trial=lpt)
+                ylt = ara.run_layers(tables, [_spec(ara, layer, pool, yet)], flags=flags)
+                assert ylt.tolist() == case["year_loss"], (case["name"], flags, lpt)
+        tables.close()
+    m = g["metrics_case_C_first4"]
+    mean, pml, tvar = ara.risk_metrics(np.array(m["year_loss"]), [r["p"] for r in m["by_p"]])
+    assert mean == m["mean"]
+    for r, a, b in zip(m["by_p"], pml, tvar):
+        assert a == r["pml"]
+        assert b == (r["tvar"] if "tvar" in r else r["tvar_num"] / r["tvar_den"])
+
+
+def test_closed_form_gradients(ara, golden_dir):
+    g = json.load(open(os.path.join(golden_dir, "closed_form_cases.json")))
+    pool = ELTPool(np.array(g["elts"]), np.array(g["elt_retention"]), np.array(g["elt_limit"]))
+    caseC = g["cases"][2]
+    gr = g["gradients_case_C_first4"]
+    yet = make_tiny_yet(caseC["trials"][:4], g["catalogue_size"])
+    layer = Layer(np.array([0, 1], dtype=np.int32), 100.0, 500.0, 150.0, 400.0, 0, 4)
+    tables = ara.create_tables(yet.offsets, yet.ids, pool.losses)
+    spec = _spec(ara, layer, pool, yet)
+    ara.run_layers(tables, [spec], flags=ara.ARA_CHECKPOINT_S)
+    gm, gt = ara.backward(tables, spec, gr["tvar_p"])
+    assert gm.tolist() == gr["grad_mean"]
+    assert gt.tolist() == gr["grad_tvar"]
+    tables.close()
+
+
+# ---------------------------------------------------------------------------
+# config 0 (small) -- full parity
+# ---------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def cfg0(ara):
+    w = make_config("config0")
+    yet, pool, layer = w.yet, w.pool, w.layers[0]
+    tables = ara.create_tables(yet.offsets, yet.ids, pool.losses)
+    ref, S = oracle.run_layer(yet, pool, layer)
+    yield w, tables, ref, S
+    tables.close()
+
+
+def test_config0_year_losses_all_modes(ara, cfg0):
+    w, tables, ref, S = cfg0
+    spec = _spec(ara, w.layers[0], w.pool, w.yet)
+    base = None
+    for flags in (0, ara.ARA_LITERAL, ara.ARA_CHECKPOINT_S, ara.ARA_LITERAL | ara.ARA_CHECKPOINT_S):
+        for lpt in (64, 32, 16, 8):
+            ara.set_tuning(tables, lanes_per_trial=lpt)
+            ylt = ara.run_layers(tables, [spec], flags=flags)
+            ok, worst = _close(ylt, ref)
+            assert ok, (flags, lpt, worst)
+            exact = float(np.mean(ylt == ref))
+            assert exact > 0.999, (flags, lpt, exact)
+            if base is None:
+                base = ylt
+    ara.set_tuning(tables)
+    assert np.count_nonzero(ref) > 100 and np.count_nonzero(ref == w.layers[0].agg_limit) > 0
+
+
+def test_config0_lookups_bit_exact(ara, cfg0):
+    w, tables, _, _ = cfg0
+    spec = _spec(ara, w.layers[0], w.pool, w.yet)
+    for t in (0, 1, 17, 4999, w.yet.n_trials - 1):
+        ids, losses = ara.debug_lookups(tables, spec, t)
+        rids, rl = oracle.lookups(w.yet, w.pool, w.layers[0], t)
+        assert np.array_equal(ids, rids)
+        assert np.array_equal(losses.view(np.uint64), rl.view(np.uint64))
+
+
+def test_config0_metrics(ara, cfg0):
+    w, tables, ref, _ = cfg0
+    spec = _spec(ara, w.layers[0], w.pool, w.yet)
+    ylt = ara.run_layers(tables, [spec])
+    probs = [0.99, 0.996, 0.9, 0.5]
+    mean, pml, tvar = ara.risk_metrics(ylt, probs)
+    rmean, rpml, rtvar = oracle.risk_metrics(ref, probs)
+    assert abs(mean - rmean) <= REL * abs(rmean)
+    for a, b in zip(pml, rpml):
+        assert abs(a - b) <= REL * abs(b)
+    for a, b in zip(tvar, rtvar):
+        assert abs(a - b) <= REL * abs(b)
+    import torch
+    d = torch.from_numpy(ylt).cuda()
+    dmean, dpml, dtvar = ara.risk_metrics(d, probs)
+    assert (dmean, dpml, dtvar) == (mean, pml, tvar)
+
+
+def test_config0_checkpoints(ara, cfg0):
+    w, tables, ref, S = cfg0
+    yet, pool, layer = w.yet, w.pool, w.layers[0]
+    spec = _spec(ara, layer, pool, yet)
+    ara.run_layers(tables, [spec], flags=ara.ARA_CHECKPOINT_S)
+    S_gpu = ara.read_checkpoints(tables, 0)
+    ok, worst = _close(S_gpu, S)
+    assert ok, worst
+    slots = ara.read_checkpoints(tables, 1)
+    _, o = oracle.occurrence_catalogue(pool, layer)
+    trial_of = np.repeat(np.arange(yet.n_trials), np.diff(yet.offsets))
+    checked = 0
+    for b in range(slots.shape[0]):
+        last = 64 * b + 63
+        t = trial_of[last]
+        start = yet.offsets[t]
+        pref = math.fsum(o[yet.ids[start:last + 1]].tolist())
+        assert abs(slots[b] - pref) <= REL * pref, b
+        checked += 1
+    assert checked == yet.n_events // 64
+
+
+def test_config0_gradients_match_oracle_exactly(ara, cfg0):
+    w, tables, ref, S = cfg0
+    yet, pool, layer = w.yet, w.pool, w.layers[0]
+    spec = _spec(ara, layer, pool, yet)
+    ara.run_layers(tables, [spec], flags=ara.ARA_CHECKPOINT_S)
+    for p in (0.99, 0.9):
+        gm, gt = ara.backward(tables, spec, p)
+        g = oracle.gradients(yet, pool, layer, p, ylt=ref, S=S)
+        assert np.array_equal(gm, g["grad_mean"]), (gm, g["grad_mean"])
+        assert np.array_equal(gt, g["grad_tvar"]), (gt, g["grad_tvar"])
+    assert np.count_nonzero(gm) == gm.shape[0]
+
+
+def test_backward_requires_checkpointed_forward(ara, cfg0):
+    w, tables, _, _ = cfg0
+    spec = _spec(ara, w.layers[0], w.pool, w.yet)
+    ara.run_layers(tables, [spec], flags=ara.ARA_CHECKPOINT_S)
+    other = spec.with_theta(spec.theta() * 1.01)
+    with pytest.raises(ara.AraError) as e:
+        ara.backward(tables, other, 0.99)
+    assert e.value.status == ara.ARA_ERR_NOT_READY
+
+
+def test_config0_deterministic_and_split_invariant(ara, cfg0):
+    w, tables, ref, _ = cfg0
+    yet, pool, layer = w.yet, w.pool, w.layers[0]
+    spec = _spec(ara, layer, pool, yet)
+    a = ara.run_layers(tables, [spec])
+    b = ara.run_layers(tables, [spec])
+    assert np.array_equal(a, b)
+    parts = []
+    for begin, count in ((0, 3333), (3333, 1), (3334, yet.n_trials - 3334)):
+        s2 = ara.LayerSpec(spec.elt_index, spec.elt_retention, spec.elt_limit, spec.occ_retention,
+                           spec.occ_limit, spec.agg_retention, spec.agg_limit, begin, count)
+        parts.append(ara.run_layers(tables, [s2]))
+    assert np.array_equal(np.concatenate(parts), a)
+    # several layers back to back in one call
+    both = ara.run_layers(tables, [spec, spec])
+    assert np.array_equal(both[:yet.n_trials], a) and np.array_equal(both[yet.n_trials:], a)
+
+
+def test_concurrent_streams_same_results(ara, cfg0):
+    import torch
+    w, tables, ref, _ = cfg0
+    spec = _spec(ara, w.layers[0], w.pool, w.yet)
+    base = ara.run_layers(tables, [spec])
+    outs = [torch.empty(w.yet.n_trials, dtype=torch.float64, device="cuda") for _ in range(4)]
+    streams = [torch.cuda.Stream() for _ in range(4)]
+    errors = []
+
+    def work(i):
+        try:
+            with torch.cuda.stream(streams[i]):
+                for _ in range(3):
+                    ara.run_layers(tables, [spec], out=outs[i], stream=streams[i])
+        except Exception as exc:  # pragma: no cover - reported below
+            errors.append(exc)
+
+    th = [threading.Thread(target=work, args=(i,)) for i in range(4)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    torch.cuda.synchronize()
+    assert not errors, errors
+    for o in outs:
+        assert np.array_equal(o.cpu().numpy(), base)
+
+
+# ---------------------------------------------------------------------------
+# ragged, empty and degenerate inputs
+# ---------------------------------------------------------------------------
+
+def test_ragged_and_edge_cases(ara):
+    rng = np.random.default_rng(21)
+    C = 5000
+    pool = make_elt_pool(70, C, 900, seed=22)
+    lengths = rng.choice([0, 1, 2, 3, 5, 63, 64, 65, 255, 256, 257, 1500, 3000], size=300)
+    trials = [rng.integers(0, C, size=k).tolist() for k in lengths]
+    yet = make_tiny_yet(trials, C)
+    tables = ara.create_tables(yet.offsets, yet.ids, pool.losses)
+    layers = [
+        Layer(np.arange(64, dtype=np.int32), 1000.0, 4.0e5, 5.0e4, 2.0e6, 0, yet.n_trials),   # max J
+        Layer(np.array([3], dtype=np.int32), 0.0, INF, 0.0, INF, 0, yet.n_trials),            # no terms
+        Layer(np.zeros(0, dtype=np.int32), 0.0, INF, 0.0, INF, 0, yet.n_trials),              # J = 0
+        Layer(np.array([5, 9], dtype=np.int32), 0.0, 0.0, 0.0, INF, 0, yet.n_trials),         # OccL = 0
+        Layer(np.array([5, 9], dtype=np.int32), 10.0, INF, 1e300, INF, 7, 200),               # AggR huge
+        Layer(np.array([2, 1], dtype=np.int32), 10.0, INF, 0.0, INF, 299, 1),                 # last trial
+        Layer(np.array([2, 1], dtype=np.int32), 10.0, INF, 0.0, INF, 300, 0),                 # empty range
+    ]
+    for layer in layers:
+        spec = _spec(ara, layer, pool, yet)
+        ref, _ = oracle.run_layer(yet, pool, layer)
+        for flags in (0, ara.ARA_LITERAL, ara.ARA_CHECKPOINT_S):
+            for lpt in (64, 8):
+                ara.set_tuning(tables, lanes_per_trial=lpt)
+                ylt = ara.run_layers(tables, [spec], flags=flags)
+                ok, worst = _close(ylt, ref)
+                assert ok, (layer.n_elts, flags, lpt, worst)
+    tables.close()
+
+
+def test_error_paths(ara):
+    C = 100
+    pool = make_elt_pool(2, C, 10, seed=3)
+    yet = make_tiny_yet([[1, 2], [3]], C)
+    bad_ids = yet.ids.copy()
+    bad_ids[1] = C
+    with pytest.raises(ara.AraError) as e:
+        ara.create_tables(yet.offsets, bad_ids, pool.losses)
+    assert e.value.status == ara.ARA_ERR_OUT_OF_RANGE
+    neg = pool.losses.copy()
+    neg[1, 5] = -1.0
+    with pytest.raises(ara.AraError) as e:
+        ara.create_tables(yet.offsets, yet.ids, neg)
+    assert e.value.status == ara.ARA_ERR_INVALID_ARG
+    nan = pool.losses.copy()
+    nan[0, 0] = math.nan
+    with pytest.raises(ara.AraError) as e:
+        ara.create_tables(yet.offsets, yet.ids, nan)
+    assert e.value.status == ara.ARA_ERR_INVALID_ARG
+    tables = ara.create_tables(yet.offsets, yet.ids, pool.losses)
+    good = Layer(np.array([0, 1], dtype=np.int32), 0.0, INF, 0.0, INF, 0, 2)
+    spec = _spec(ara, good, pool, yet)
+    for bad in (spec.with_theta(np.r_[-1.0, spec.theta()[1:]]),
+                spec.with_theta(np.r_[spec.theta()[:-1], math.nan])):
+        with pytest.raises(ara.AraError) as e:
+            ara.run_layers(tables, [bad])
+        assert e.value.status == ara.ARA_ERR_INVALID_ARG
+    out_of_pool = ara.LayerSpec(np.array([2], np.int32), np.zeros(1), np.ones(1), 0.0, 1.0, 0.0, 1.0, 0, 2)
+    with pytest.raises(ara.AraError) as e:
+        ara.run_layers(tables, [out_of_pool])
+    assert e.value.status == ara.ARA_ERR_OUT_OF_RANGE
+    with pytest.raises(ara.AraError) as e:
+        ara.run_layers(tables, [spec], out=np.empty(1))
+    assert e.value.status == ara.ARA_ERR_BUFFER_TOO_SMALL
+    too_many = ara.LayerSpec(np.zeros(65, np.int32), np.zeros(65), np.ones(65), 0.0, 1.0, 0.0, 1.0, 0, 2)
+    with pytest.raises(ara.AraError) as e:
+        ara.run_layers(tables, [too_many])
+    assert e.value.status == ara.ARA_ERR_UNSUPPORTED
+    with pytest.raises(ara.AraError) as e:
+        ara.risk_metrics(np.array([1.0, -2.0]), [0.5])
+    assert e.value.status == ara.ARA_ERR_INVALID_ARG
+    tables.close()
+
+
+# ---------------------------------------------------------------------------
+# paper-scale share (1M trials x Poisson(1000), 16 ELTs): sampled parity
+# ---------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def cfg1(ara):
+    w = make_config("config1")
+    tables = ara.create_tables(w.yet.offsets, w.yet.ids, w.pool.losses)
+    yield w, tables
+    tables.close()
+
+
+def _sample_yet(yet, trials):
+    return make_tiny_yet([yet.trial(int(t)).tolist() for t in trials], yet.catalogue_size)
+
+
+def test_config1_full_size_sampled(ara, cfg1):
+    import torch
+    w, tables = cfg1
+    yet, pool, layer = w.yet, w.pool, w.layers[0]
+    spec = _spec(ara, layer, pool, yet)
+    out = torch.empty(yet.n_trials, dtype=torch.float64, device="cuda")
+    ara.run_layers(tables, [spec], out=out)            # the launch configuration the bench times
+    torch.cuda.synchronize()
+    ylt = out.cpu().numpy()
+    rng = np.random.default_rng(5)
+    sample = np.unique(np.concatenate([rng.integers(0, yet.n_trials, 600), [0, yet.n_trials - 1]]))
+    sub = _sample_yet(yet, sample)
+    ref, _ = oracle.run_layer(sub, pool, Layer(layer.elt_index, layer.occ_retention, layer.occ_limit,
+                                               layer.agg_retention, layer.agg_limit, 0, sub.n_trials))
+    ok, worst = _close(ylt[sample], ref)
+    assert ok, worst
+    assert np.all(ylt >= 0.0) and np.all(ylt <= layer.agg_limit)
+    # lookups for sampled trials, bit-exact
+    for t in sample[:8]:
+        ids, losses = ara.debug_lookups(tables, spec, int(t))
+        rids, rl = oracle.lookups(yet, pool, layer, int(t))
+        assert np.array_equal(ids, rids) and np.array_equal(losses.view(np.uint64), rl.view(np.uint64))
+    # metrics: properties that pin PML/TVaR at any size
+    probs = list(w.probs)
+    res = ara.risk_metrics(out, probs, outputs=torch.empty(1 + 2 * len(probs), dtype=torch.float64,
+                                                           device="cuda"))
+    h = res.cpu().numpy()
+    desc = np.sort(ylt)[::-1]
+    assert abs(h[0] - math.fsum(ylt.tolist()) / ylt.shape[0]) <= REL * h[0]
+    for q, p in enumerate(probs):
+        m = oracle.tail_count(ylt.shape[0], p)
+        pml, tvar = h[1 + q], h[1 + len(probs) + q]
+        assert np.sum(ylt > pml) < m <= np.sum(ylt >= pml)
+        assert abs(tvar - math.fsum(desc[:m].tolist()) / m) <= REL * tvar
+
+
+def test_config1_prefix_full_parity_and_gradients(ara, cfg1):
+    w, tables = cfg1
+    yet, pool = w.yet, w.pool
+    n = 20_000
+    layer = Layer(w.layers[0].elt_index, w.layers[0].occ_retention, w.layers[0].occ_limit,
+                  w.layers[0].agg_retention, w.layers[0].agg_limit, 0, n)
+    spec = _spec(ara, layer, pool, yet)
+    ylt = ara.run_layers(tables, [spec], flags=ara.ARA_CHECKPOINT_S)
+    ref, S = oracle.run_layer(yet, pool, layer)
+    ok, worst = _close(ylt, ref)
+    assert ok, worst
+    gm, gt = ara.backward(tables, spec, 0.99)
+    g = oracle.gradients(yet, pool, layer, 0.99, ylt=ref, S=S)
+    assert np.array_equal(gm, g["grad_mean"])
+    assert np.array_equal(gt, g["grad_tvar"])
+
+
+def test_config1_gradient_vs_finite_differences(ara, cfg1):
+    """Central differences of the GPU forward at step 1e-4 relative agree with
+    the adjoint; kinks crossed inside +-h bound the disagreement."""
+    import torch
+    w, tables = cfg1
+    yet, pool, layer = w.yet, w.pool, w.layers[0]
+    spec = _spec(ara, layer, pool, yet)
+    out = torch.empty(yet.n_trials, dtype=torch.float64, device="cuda")
+    ara.run_layers(tables, [spec], out=out, flags=ara.ARA_CHECKPOINT_S)
+    gm, gt = ara.backward(tables, spec, 0.99)
+    theta = spec.theta()
+
+    def f(th):
+        ara.run_layers(tables, [spec.with_theta(th)], out=out)
+        mean, _, tvar = ara.risk_metrics(out, [0.99])
+        return mean, tvar[0]
+
+    worst = 0.0
+    for k in range(theta.shape[0]):
+        h = 1e-4 * abs(theta[k])
+        tp, tm = theta.copy(), theta.copy()
+        tp[k] += h
+        tm[k] -= h
+        (mp, vp), (mm, vm) = f(tp), f(tm)
+        for fd, g in (((mp - mm) / (2 * h), gm[k]), ((vp - vm) / (2 * h), gt[k])):
+            err = abs(fd - g) / max(abs(g), 1e-3)
+            worst = max(worst, err)
+            assert err < 2e-2, (k, fd, g)
