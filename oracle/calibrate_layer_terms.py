@@ -11,8 +11,8 @@ loss themselves).  Recipe, per layer:
   the layer's first trials (with the occurrence terms above and no aggregate
   terms); AggL = midpoint at the 99.9th percentile minus AggR.
 
-Midpoints keep the terms off data points, so finite differences do not sit on
-a kink.  Usage:  python -m oracle.calibrate_layer_terms [--only config0]
+Midpoints between distinct neighbouring values keep the terms off data
+points, so no occurrence or trial sits exactly on a kink.  Usage:  python -m oracle.calibrate_layer_terms [--only config0]
 """
 
 from __future__ import annotations
@@ -38,13 +38,22 @@ SAMPLE_LIBRARY = 4_000
 
 
 def quantile_midpoint(values: np.ndarray, q_permille: int) -> float:
+    """Midpoint between the order statistic k = ceil(q n) and the next larger
+    distinct value.  Losses capped by one ELT's limit all share the same value,
+    so plain neighbours can be equal; skipping ties keeps the term strictly
+    between data values (no occurrence sits exactly on its kink)."""
     v = np.sort(np.asarray(values, dtype=np.float64))
     n = v.shape[0]
     if n < 2:
         raise ValueError("need at least two values")
     k = (q_permille * n + 999) // 1000
     k = min(max(k, 1), n - 1)
-    return float((v[k - 1] + v[k]) * 0.5)
+    lo = v[k - 1]
+    above = v[k - 1:][v[k - 1:] > lo]
+    if above.shape[0] == 0:
+        below = v[v < lo]
+        return float((below[-1] + lo) * 0.5) if below.shape[0] else float(lo)
+    return float((lo + above[0]) * 0.5)
 
 
 def calibrate(yet, pool, layer: gen.Layer, n_sample: int) -> dict:
