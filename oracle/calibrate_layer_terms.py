@@ -5,8 +5,10 @@ workloads/layer_terms.json, which the generators read (they never compute a
 loss themselves).  Recipe, per layer:
 
 * OccR = midpoint of the order statistics around the 10th percentile of the
-  nonzero ELT-combined losses y(E) over the catalogue; OccL = the same
-  midpoint at the 99th percentile minus OccR;
+  nonzero ELT-combined losses y(E) over the catalogue; OccR + OccL = the
+  midpoint of the widest relative gap between distinct y values between the
+  98.5th and 99.5th percentiles (the cap sits among the atoms of
+  ELT-capped losses and must keep clear of them);
 * AggR = midpoint around the median of the annual totals S over a sample of
   the layer's first trials (with the occurrence terms above and no aggregate
   terms); AggL = midpoint at the 99.9th percentile minus AggR.
@@ -56,13 +58,30 @@ def quantile_midpoint(values: np.ndarray, q_permille: int) -> float:
     return float((lo + above[0]) * 0.5)
 
 
+def widest_gap_midpoint(values: np.ndarray, lo_permille: int, hi_permille: int) -> float:
+    """Midpoint of the widest relative gap between consecutive distinct values
+    whose order statistics lie between the two quantiles.  Used for the
+    occurrence cap, which sits among the atoms of ELT-capped losses: a
+    central difference with step 1e-4 relative must not straddle an atom."""
+    v = np.sort(np.asarray(values, dtype=np.float64))
+    n = v.shape[0]
+    a = min(max((lo_permille * n + 999) // 1000, 1), n) - 1
+    b = min(max((hi_permille * n + 999) // 1000, 1), n)
+    d = np.unique(v[a:b + 1])
+    if d.shape[0] < 2:
+        return quantile_midpoint(v, (lo_permille + hi_permille) // 2)
+    rel = (d[1:] - d[:-1]) / d[1:]
+    i = int(np.argmax(rel))
+    return float((d[i] + d[i + 1]) * 0.5)
+
+
 def calibrate(yet, pool, layer: gen.Layer, n_sample: int) -> dict:
     free = gen.Layer(layer.elt_index, 0.0, math.inf, 0.0, math.inf, layer.trial_begin,
                      layer.trial_count)
     y, _ = ref.occurrence_catalogue(pool, free)
     nz = y[y > 0.0]
     occ_r = quantile_midpoint(nz, 100)
-    occ_l = quantile_midpoint(nz, 990) - occ_r
+    occ_l = widest_gap_midpoint(nz, 985, 995) - occ_r
     count = layer.resolved_count(yet.n_trials)
     sample = gen.Layer(layer.elt_index, occ_r, occ_l, 0.0, math.inf, layer.trial_begin,
                        min(n_sample, count))
@@ -80,7 +99,8 @@ def main(argv=None) -> None:
     path = gen._TERMS_FILE
     out = gen.load_layer_terms()
     out["recipe"] = (
-        "OccR = q10 midpoint of nonzero y(E); OccL = q99 midpoint - OccR; "
+        "OccR = q10 midpoint of nonzero y(E); OccR + OccL = midpoint of the widest gap "
+        "between distinct y values in [q98.5, q99.5]; "
         "AggR = q50 midpoint of S over the first sample_trials trials; "
         "AggL = q99.9 midpoint - AggR; written by oracle/calibrate_layer_terms.py")
     for name in ("config0", "config1"):

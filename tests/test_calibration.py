@@ -14,6 +14,12 @@ from workloads import generators as gen
 from workloads import make_config
 
 
+def test_widest_gap_midpoint():
+    v = np.array([1.0, 2.0, 2.0, 2.1, 3.0, 3.05, 9.0, 10.0])
+    # between the order statistics k=2..8 the widest relative gap is 3.05 -> 9.0
+    assert cal.widest_gap_midpoint(v, 200, 1000) == 6.025
+
+
 def test_quantile_midpoint_skips_ties():
     v = np.array([1.0, 2.0, 2.0, 2.0, 2.0, 5.0])
     # k = ceil(0.5 * 6) = 3 -> v_3 = 2.0; next distinct value 5.0
@@ -37,6 +43,9 @@ def test_terms_off_data_atoms(name, n_prefix):
     nz = y[y > 0.0]
     for edge in (layer.occ_retention, layer.occ_retention + layer.occ_limit):
         assert np.min(np.abs(nz - edge)) > 1e-9 * edge
+    # the cap keeps a central difference at step 1e-4 clear of every atom
+    cap = layer.occ_retention + layer.occ_limit
+    assert np.min(np.abs(nz - cap)) > 2e-4 * cap
     _, S = oracle.run_layer(w.yet, w.pool, layer)
     for edge in (layer.agg_retention, layer.agg_retention + layer.agg_limit):
         assert np.min(np.abs(S - edge)) > 1e-9 * edge
