@@ -54,8 +54,8 @@ typedef int32_t ara_status;
 #define ARA_LITERAL      (1u << 1)  /* ara_run_layers: per-occurrence, per-ELT lookups exactly as
                                        Algorithm 3 is written, instead of one lookup of the
                                        per-event occurrence loss computed for the whole catalogue */
-#define ARA_CHECKPOINT_S (1u << 2)  /* ara_run_layers: keep S_t, YLT_t and the stride-64 prefix
-                                       checkpoints of S inside the tables for ara_backward */
+#define ARA_CHECKPOINT_S (1u << 2)  /* ara_run_layers: keep each trial's annual total S_t and
+                                       YLT_t inside the tables for ara_backward */
 #define ARA_PER_LAYER    (1u << 3)  /* ara_run_layers with several layers: one launch sequence per
                                        layer instead of the single persistent batched launch */
 #define ARA_GRAPH        (1u << 4)  /* ara_run_layers: replay a HIP graph captured for this layer
@@ -63,13 +63,20 @@ typedef int32_t ara_status;
 #define ARA_PROFILE      (1u << 5)  /* ara_run_layers: bracket each kernel with HIP events on the
                                        call's stream; read the totals with ara_kernel_stats */
 
+#define ARA_CHECKPOINT_STRIDE (1u << 7) /* ara_run_layers: ARA_CHECKPOINT_S plus the prefix sums
+                                       of S every 64 events in time order (read them with
+                                       ara_read_checkpoints); uses the time-ordered pass */
+#define ARA_PLAIN_LAYOUT (1u << 6)  /* ara_create_tables: keep only the time-ordered YET (no
+                                       catalogue-partitioned copy; saves ~4 B per event of device
+                                       memory, slower ara_run_layers) */
+
 /* kernel classes reported by ara_kernel_stats */
 #define ARA_KERNEL_FOLD       0     /* per-catalogue occurrence losses */
 #define ARA_KERNEL_TRIAL_PASS 1     /* YET stream, lookups, annual totals, aggregate terms */
 #define ARA_KERNEL_BATCHED    2     /* persistent multi-layer trial pass */
 
 #define ARA_MAX_LAYER_ELTS 64       /* most ELTs one layer may cover (the paper's layers cover 3-30) */
-#define ARA_CHECKPOINT_STRIDE 64    /* events between stored prefix sums of S */
+#define ARA_CHECKPOINT_EVERY 64     /* events between stored prefix sums of S */
 
 typedef struct ara_tables ara_tables;
 
@@ -116,6 +123,13 @@ typedef struct ara_tuning {
  *                  direct-access tables (Section III-B); 0.0 = no loss.
  *                  Finite and >= 0.
  *   flags          ARA_DEVICE_PTR: the three arrays are device memory.
+ *                  ARA_PLAIN_LAYOUT: skip the catalogue-partitioned copy.
+ *
+ * Besides the time-ordered CSR the library keeps, by default, a second copy
+ * of the event IDs laid out for its trial pass: tiles of 256 consecutive
+ * trials, inside a tile the catalogue's parts of 2^19 events one after the
+ * other, inside a part each trial's events of that part in time order.  It
+ * depends on the YET alone, so every layer run on the tables uses it.
  *   out            receives the handle; freed by ara_destroy_tables.
  *
  * The arrays are caller-owned and only read during the call: the library
@@ -143,8 +157,9 @@ void ara_destroy_tables(ara_tables* tables);
  *                    device memory with ARA_DEVICE_PTR.
  *   ylt_capacity     number of doubles `ylt` can hold; ARA_ERR_BUFFER_TOO_SMALL
  *                    if below the sum of trial_count.
- *   flags            ARA_DEVICE_PTR, ARA_LITERAL, ARA_CHECKPOINT_S (one layer
- *                    only), ARA_PER_LAYER, ARA_GRAPH.
+ *   flags            ARA_DEVICE_PTR, ARA_LITERAL, ARA_CHECKPOINT_S or
+ *                    ARA_CHECKPOINT_STRIDE (one layer only), ARA_PER_LAYER,
+ *                    ARA_GRAPH, ARA_PROFILE.
  *
  * Year losses do not depend on the flags beyond floating-point rounding of
  * S (the sum over occurrences is accumulated in double-double and rounded
@@ -227,7 +242,8 @@ ara_status ara_debug_lookups(ara_tables* tables, const ara_layer* layer, int64_t
                              int64_t* n_out, void* stream);
 
 /*
- * ara_read_checkpoints -- copy the state kept by ARA_CHECKPOINT_S to host.
+ * ara_read_checkpoints -- copy the state kept by ARA_CHECKPOINT_S (what = 0)
+ * or ARA_CHECKPOINT_STRIDE (what = 1) to host.
  * what = 0: S_t for the layer's trials (trial_count doubles);
  * what = 1: stride-64 prefix checkpoints: slot b holds, for the trial that
  *           owns global event 64b+63, the sum of o over that trial's events

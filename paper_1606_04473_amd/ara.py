@@ -34,13 +34,15 @@ ARA_CHECKPOINT_S = 1 << 2
 ARA_PER_LAYER = 1 << 3
 ARA_GRAPH = 1 << 4
 ARA_PROFILE = 1 << 5
+ARA_PLAIN_LAYOUT = 1 << 6
+ARA_CHECKPOINT_STRIDE = 1 << 7
 
 KERNEL_FOLD = 0
 KERNEL_TRIAL_PASS = 1
 KERNEL_BATCHED = 2
 
 MAX_LAYER_ELTS = 64
-CHECKPOINT_STRIDE = 64
+CHECKPOINT_EVERY = 64
 
 EXPORTED = (
     "ara_create_tables", "ara_destroy_tables", "ara_run_layers", "ara_risk_metrics", "ara_backward",
@@ -277,7 +279,7 @@ class Tables:
 
 
 def create_tables(offsets, ids, elt_losses, catalogue_size: Optional[int] = None,
-                  stream=None) -> Tables:
+                  stream=None, flags: int = 0) -> Tables:
     """ara_create_tables.  NumPy inputs are host memory; CUDA tensors device memory."""
     po, ko, do = _ptr(offsets, np.int64)
     pi, ki, di = _ptr(ids, np.uint32)
@@ -291,7 +293,8 @@ def create_tables(offsets, ids, elt_losses, catalogue_size: Optional[int] = None
     C = int(shape[1]) if catalogue_size is None else int(catalogue_size)
     h = ctypes.c_void_p()
     _check(lib().ara_create_tables(po, n_trials, pi, n_events, pe, n_pool, C,
-                                   ARA_DEVICE_PTR if do else 0, _stream(stream), ctypes.byref(h)))
+                                   flags | (ARA_DEVICE_PTR if do else 0), _stream(stream),
+                                   ctypes.byref(h)))
     return Tables(h, n_trials, n_events, C, n_pool)
 
 

@@ -216,8 +216,8 @@ ara_status ara_create_tables(const int64_t* trial_offsets, int64_t n_trials, con
     *out = nullptr;
     if (n_trials < 0 || n_events < 0 || n_elts < 0 || catalogue_size < 1)
         return fail(ARA_ERR_INVALID_ARG, "negative size or empty catalogue");
-    if (catalogue_size > (int64_t(1) << 32))
-        return fail(ARA_ERR_INVALID_ARG, "catalogue larger than 2^32 events (IDs are uint32)");
+    if (catalogue_size >= (int64_t(1) << 32))
+        return fail(ARA_ERR_INVALID_ARG, "catalogue of 2^32 events or more (IDs are uint32, 0xFFFFFFFF is reserved)");
     if (!trial_offsets || (n_events > 0 && !event_ids) || (n_elts > 0 && !elt_losses))
         return fail(ARA_ERR_INVALID_ARG, "NULL input array");
     const bool dev_in = (flags & ARA_DEVICE_PTR) != 0;
@@ -281,6 +281,16 @@ ara_status ara_create_tables(const int64_t* trial_offsets, int64_t n_trials, con
     if ((host_flag & 2u) || ends[0] != 0 || ends[1] != n_events)
         return cleanup(fail(ARA_ERR_INVALID_ARG, "trial offsets must start at 0, not decrease, end at n_events"));
     if (host_flag & 4u) return cleanup(fail(ARA_ERR_INVALID_ARG, "ELT losses must be finite and >= 0"));
+    if (!(flags & ARA_PLAIN_LAYOUT) && n_trials > 0) {
+        e = ara::build_part_layout(t->offsets, t->ids, n_trials, n_events, catalogue_size, t->n_cu, s, &t->parts);
+        if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) {
+            (void)hipGetLastError();
+            t->parts = ara::PartLayout{};      // not enough memory for the copy: plain layout only
+        } else if (e != hipSuccess) {
+            return cleanup(hip_fail(e, "partitioned layout"));
+        }
+        t->bytes += t->parts.bytes;
+    }
     *out = t;
     return ARA_OK;
 }
@@ -292,6 +302,7 @@ void ara_destroy_tables(ara_tables* t) {
     if (t->ids) (void)hipFree(t->ids);
     if (t->elts) (void)hipFree(t->elts);
     free_checkpoints(t->ck);
+    ara::free_part_layout(&t->parts);
     for (auto& p : t->prof.pending) {
         (void)hipEventDestroy(p.start);
         (void)hipEventDestroy(p.stop);
@@ -358,9 +369,10 @@ ara_status ara_footprint(const ara_tables* t, const ara_layer* layers, int32_t n
     for (int i = 0; i < n_layers; ++i) total += layers[i].trial_count;
     int64_t b = 0;
     if (!(flags & ARA_LITERAL)) b += sizeof(double) * t->C;            // occurrence losses
+    if (!(flags & ARA_LITERAL) && t->parts.P > 0) b += ara::part_scratch_bytes(t->C, t->parts.P);
     if (!(flags & ARA_DEVICE_PTR)) b += sizeof(double) * total;       // staged output
-    if (flags & ARA_CHECKPOINT_S)
-        b += 2 * sizeof(double) * total + sizeof(double) * (t->n_events / ara::kStride + 1);
+    if (flags & (ARA_CHECKPOINT_S | ARA_CHECKPOINT_STRIDE)) b += 2 * sizeof(double) * total;
+    if (flags & ARA_CHECKPOINT_STRIDE) b += sizeof(double) * (t->n_events / ara::kStride + 1);
     *bytes = b;
     return ARA_OK;
 }
@@ -368,6 +380,7 @@ ara_status ara_footprint(const ara_tables* t, const ara_layer* layers, int32_t n
 ara_status ara_run_layers(ara_tables* t, const ara_layer* layers, int32_t n_layers, double* ylt,
                           int64_t ylt_capacity, uint32_t flags, void* stream) {
     if (!t || !layers || n_layers < 1) return fail(ARA_ERR_INVALID_ARG, "NULL argument or no layer");
+    if (flags & ARA_CHECKPOINT_STRIDE) flags |= ARA_CHECKPOINT_S;
     const bool ckpt = (flags & ARA_CHECKPOINT_S) != 0;
     if (ckpt && n_layers != 1) return fail(ARA_ERR_UNSUPPORTED, "ARA_CHECKPOINT_S takes exactly one layer");
     std::vector<ara::LayerArgs> L(n_layers);
@@ -400,6 +413,10 @@ ara_status ara_run_layers(ara_tables* t, const ara_layer* layers, int32_t n_laye
         out = static_cast<double*>(staged.p);
     }
     if (!literal) HIP_TRY(obuf.alloc(sizeof(double) * t->C, s), "scratch for occurrence losses");
+    // the partitioned pass serves plain runs; stride checkpoints need time order
+    const bool use_parts = !literal && t->parts.P > 0 && !(flags & ARA_CHECKPOINT_STRIDE);
+    PoolBuffer pbuf;
+    if (use_parts) HIP_TRY(pbuf.alloc(ara::part_scratch_bytes(t->C, t->parts.P), s), "scratch for part images");
     double* S_buf = nullptr;
     double* stride_buf = nullptr;
     std::unique_lock<std::mutex> ck_lock(t->mu, std::defer_lock);
@@ -416,11 +433,15 @@ ara_status ara_run_layers(ara_tables* t, const ara_layer* layers, int32_t n_laye
             HIP_TRY(hipMalloc(&ck.ylt, nb), "checkpoint YLT");
             ck.count = L[0].trial_count;
         }
-        if (!ck.stride) HIP_TRY(hipMalloc(&ck.stride, sizeof(double) * (t->n_events / ara::kStride + 1)),
-                                "stride checkpoints");
-        HIP_TRY(ara::launch_fill(ck.stride, t->n_events / ara::kStride + 1, std::nan(""), s), "fill");
+        ck.has_stride = false;
+        if (flags & ARA_CHECKPOINT_STRIDE) {
+            if (!ck.stride) HIP_TRY(hipMalloc(&ck.stride, sizeof(double) * (t->n_events / ara::kStride + 1)),
+                                    "stride checkpoints");
+            HIP_TRY(ara::launch_fill(ck.stride, t->n_events / ara::kStride + 1, std::nan(""), s), "fill");
+            stride_buf = ck.stride;
+            ck.has_stride = true;
+        }
         S_buf = ck.S;
-        stride_buf = ck.stride;
     }
     for (int i = 0; i < n_layers; ++i) {
         ara::TrialPassArgs a{};
@@ -436,10 +457,17 @@ ara_status ara_run_layers(ara_tables* t, const ara_layer* layers, int32_t n_laye
         if (!literal) {
             KernelTimer kt(t, s, prof, ARA_KERNEL_FOLD);
             HIP_TRY(ara::launch_fold(t->elts, t->C, L[i], static_cast<double*>(obuf.p), tu, s), "fold");
+            if (use_parts)
+                HIP_TRY(ara::launch_part_fold(static_cast<const double*>(obuf.p), t->C, t->parts.P, pbuf.p, s),
+                        "part images");
             kt.done();
         }
         KernelTimer kt(t, s, prof, ARA_KERNEL_TRIAL_PASS);
-        HIP_TRY(ara::launch_trial_pass(a, L[i], literal, tu, t->n_cu, s), "trial pass");
+        if (use_parts)
+            HIP_TRY(ara::launch_part_pass(t->parts, t->n_trials, L[i], pbuf.p, a.ylt, a.S, t->n_cu, s),
+                    "partitioned trial pass");
+        else
+            HIP_TRY(ara::launch_trial_pass(a, L[i], literal, tu, t->n_cu, s), "trial pass");
         kt.done();
     }
     if (ckpt) {
@@ -529,8 +557,19 @@ ara_status ara_backward(ara_tables* t, const ara_layer* layer, double tvar_p, do
         gt = grad_tvar ? static_cast<double*>(staged.p) + P : nullptr;
     }
     const int64_t m = tail_count(L.trial_count, tvar_p);
+    // with the partitioned layout the histogram pass reads the nonzero bitmap
+    // of the part images, rebuilt here from a fold of the layer
+    PoolBuffer obuf, pbuf;
+    const bool use_parts = t->parts.P > 0;
+    if (use_parts) {
+        const ara_tuning tu = t->tuning;   // t->mu is held
+        HIP_TRY(obuf.alloc(sizeof(double) * t->C, s), "scratch for occurrence losses");
+        HIP_TRY(pbuf.alloc(ara::part_scratch_bytes(t->C, t->parts.P), s), "scratch for part images");
+        HIP_TRY(ara::launch_fold(t->elts, t->C, L, static_cast<double*>(obuf.p), tu, s), "fold");
+        HIP_TRY(ara::launch_part_fold(static_cast<const double*>(obuf.p), t->C, t->parts.P, pbuf.p, s), "images");
+    }
     HIP_TRY(ara::launch_adjoint(t->offsets, t->ids, t->elts, t->C, L, t->ck.S, t->ck.ylt, m, scratch.p, gm, gt,
-                                t->n_cu, s),
+                                t->n_cu, s, use_parts ? &t->parts : nullptr, pbuf.p, t->n_trials),
             "adjoint kernels");
     if (!dev) {
         std::vector<double> h(2 * P);
@@ -581,6 +620,8 @@ ara_status ara_read_checkpoints(ara_tables* t, int32_t what, double* out, int64_
     if (!t || !n_out || (what != 0 && what != 1)) return fail(ARA_ERR_INVALID_ARG, "bad argument");
     std::lock_guard<std::mutex> g(t->mu);
     if (!t->ck.valid) return fail(ARA_ERR_NOT_READY, "no checkpointed forward");
+    if (what == 1 && !t->ck.has_stride)
+        return fail(ARA_ERR_NOT_READY, "no stride checkpoints (run with ARA_CHECKPOINT_STRIDE)");
     DeviceScope ds(t->device);
     const int64_t n = what == 0 ? t->ck.key.trial_count : t->n_events / ara::kStride;
     *n_out = n;

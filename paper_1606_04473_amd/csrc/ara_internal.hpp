@@ -16,7 +16,7 @@ namespace ara {
 
 constexpr int kWave = 64;
 constexpr int kMaxJ = ARA_MAX_LAYER_ELTS;
-constexpr int kStride = ARA_CHECKPOINT_STRIDE;
+constexpr int kStride = ARA_CHECKPOINT_EVERY;
 // The event-ID array is padded with zero IDs so that aligned 16-byte loads
 // covering a trial's last events never leave the allocation.
 constexpr int64_t kIdPad = 1024;
@@ -107,7 +107,59 @@ struct CheckpointState {
     double* S = nullptr;        // [trial_count]
     double* ylt = nullptr;      // [trial_count]
     double* stride = nullptr;   // [n_events / 64 + 1]
+    bool has_stride = false;
     int64_t count = 0;
+};
+
+// Part-major copy of the YET (see kernels_parts.hip): tiles of T trials,
+// inside a tile part by part, inside a part trial by trial.
+constexpr int kMaxParts = 64;
+struct PartLayout {
+    int P = 0;                      // catalogue parts; 0 = layout absent
+    int T = 0;                      // trials per tile
+    int64_t n_tiles = 0;
+    int64_t length = 0;             // IDs in pids (with padding)
+    int64_t bytes = 0;
+    uint32_t* pids = nullptr;       // [length + kIdPad]
+    uint32_t* seg_rel = nullptr;    // [n_tiles][T*P + 1] segment starts relative to the tile
+    int64_t* tile_start = nullptr;  // [n_tiles + 1]
+};
+
+struct PartPassArgs {
+    const uint32_t* pids;
+    const uint32_t* seg_rel;
+    const int64_t* tile_start;
+    const uint8_t* img;
+    const double* compact;
+    int64_t N;
+    int P;
+    int T;
+    int64_t t_lo, t_hi;
+    int64_t first_tile, last_tile;
+    double aggR, aggL;
+    double* ylt;
+    double* S;
+    uint32_t* tile_counter;
+};
+
+struct TailStats;
+struct PartAdjArgs {
+    const uint32_t* pids;
+    const uint32_t* seg_rel;
+    const int64_t* tile_start;
+    const uint8_t* img;
+    int64_t N;
+    int P;
+    int T;
+    int64_t t_lo, t_hi;
+    int64_t first_tile, last_tile;
+    double aggR, aggL;
+    const double* S;
+    const double* ylt;
+    const TailStats* tail;
+    uint64_t* w_mean;
+    uint64_t* w_tvar;
+    uint32_t* tile_counter;
 };
 
 struct ProfileState {
@@ -137,6 +189,7 @@ struct ara_tables {
     ara_tuning tuning{};
     std::mutex mu;                // guards ck and tuning
     ara::CheckpointState ck;
+    ara::PartLayout parts;
     std::mutex prof_mu;           // guards prof
     ara::ProfileState prof;
 };
@@ -171,6 +224,15 @@ hipError_t launch_debug_lookups(const int64_t* offsets, const uint32_t* ids, con
                                 int64_t C, const LayerArgs& L, int64_t trial, uint32_t* ids_out,
                                 double* losses_out, hipStream_t s);
 
+// catalogue-partitioned path
+hipError_t build_part_layout(const int64_t* offsets, const uint32_t* ids, int64_t N, int64_t n_events, int64_t C,
+                             int n_cu, hipStream_t s, PartLayout* out);
+void free_part_layout(PartLayout* L);
+int64_t part_scratch_bytes(int64_t C, int P);
+hipError_t launch_part_fold(const double* o, int64_t C, int P, void* scratch, hipStream_t s);
+hipError_t launch_part_pass(const PartLayout& lay, int64_t N, const LayerArgs& L, void* scratch, double* ylt,
+                            double* S, int n_cu, hipStream_t s);
+
 // metrics: results[0] = mean, results[1 + 2q] = PML_q, results[2 + 2q] = TVaR_q
 int64_t metrics_scratch_bytes(int n_probs);
 hipError_t launch_metrics(const double* ylt, int64_t n, const int64_t* m_host, int n_probs,
@@ -187,11 +249,17 @@ int64_t tail_stats_scratch_bytes();
 hipError_t launch_tail_stats(const double* ylt, int64_t n, int64_t m, void* scratch, TailStats* out,
                              int n_cu, hipStream_t s);
 
-// adjoint
+hipError_t launch_part_adjoint(const PartLayout& lay, int64_t N, const LayerArgs& L, void* part_scratch,
+                               const double* S, const double* ylt, const TailStats* tail, uint64_t* w_mean,
+                               uint64_t* w_tvar, int n_cu, hipStream_t s);
+
+// adjoint; with `parts` (and `part_scratch` holding the forward's part images)
+// the histogram pass runs over the partitioned layout
 int64_t adjoint_scratch_bytes(int64_t C, int J);
 hipError_t launch_adjoint(const int64_t* offsets, const uint32_t* ids, const double* elts,
                           int64_t C, const LayerArgs& L, const double* S, const double* ylt,
                           int64_t m, void* scratch, double* d_grad_mean, double* d_grad_tvar,
-                          int n_cu, hipStream_t s);
+                          int n_cu, hipStream_t s, const PartLayout* parts, void* part_scratch,
+                          int64_t n_trials_total);
 
 }  // namespace ara

@@ -38,15 +38,16 @@ struct AdjScratch {
 
 __global__ __launch_bounds__(256) void mark_kernel(const double* __restrict__ elts, int64_t C, LayerArgs L,
                                                    uint8_t* __restrict__ mark, uint64_t* __restrict__ w_mean,
-                                                   uint64_t* __restrict__ w_tvar) {
+                                                   uint64_t* __restrict__ w_tvar, int with_mark) {
     const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (e >= C) return;
+    w_mean[e] = 0;
+    w_tvar[e] = 0;
+    if (!with_mark) return;
     double y = 0.0;
     for (int j = 0; j < L.J; ++j)
         y = y + apply_terms(elts[static_cast<int64_t>(L.idx[j]) * C + e], L.R[j], L.Lim[j]);
     mark[e] = (y - L.occR > 0.0) ? 1 : 0;
-    w_mean[e] = 0;
-    w_tvar[e] = 0;
 }
 
 __global__ void clear_acc_kernel(long long* acc) {
@@ -101,6 +102,42 @@ __global__ __launch_bounds__(256) void active_trials_kernel(const int64_t* __res
         if (agg_l_mean) add_i64(&acc[P - 1], agg_l_mean);
         if (agg_r_tvar) add_i64(&acc[kMaxP + P - 2], agg_r_tvar);
         if (agg_l_tvar) add_i64(&acc[kMaxP + P - 1], agg_l_tvar);
+    }
+}
+
+// aggregate-term partials alone (the partitioned histogram pass leaves them out)
+__global__ __launch_bounds__(256) void agg_counts_kernel(LayerArgs L, const double* __restrict__ S,
+                                                         const double* __restrict__ ylt,
+                                                         const TailStats* __restrict__ tail,
+                                                         long long* __restrict__ acc) {
+    const TailStats ts = *tail;
+    const int P = 2 * L.J + 4;
+    long long r_mean = 0, l_mean = 0, r_tvar = 0, l_tvar = 0;
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+    for (int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; k < L.trial_count; k += stride) {
+        const double ta = S[k] - L.aggR;
+        const uint64_t key = __double_as_longlong(ylt[k] + 0.0);
+        const long long wt = key > ts.v_bits ? ts.c_eq : (key == ts.v_bits ? ts.m - ts.c_gt : 0);
+        if ((ta > 0.0) && (ta < L.aggL)) {
+            r_mean -= 1;
+            r_tvar -= wt;
+        }
+        if (ta > L.aggL) {
+            l_mean += 1;
+            l_tvar += wt;
+        }
+    }
+    for (int off = 32; off >= 1; off >>= 1) {
+        r_mean += __shfl_xor(r_mean, off, kWave);
+        l_mean += __shfl_xor(l_mean, off, kWave);
+        r_tvar += __shfl_xor(r_tvar, off, kWave);
+        l_tvar += __shfl_xor(l_tvar, off, kWave);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        if (r_mean) add_i64(&acc[P - 2], r_mean);
+        if (l_mean) add_i64(&acc[P - 1], l_mean);
+        if (r_tvar) add_i64(&acc[kMaxP + P - 2], r_tvar);
+        if (l_tvar) add_i64(&acc[kMaxP + P - 1], l_tvar);
     }
 }
 
@@ -187,7 +224,8 @@ int64_t adjoint_scratch_bytes(int64_t C, int J) {
 
 hipError_t launch_adjoint(const int64_t* offsets, const uint32_t* ids, const double* elts, int64_t C,
                           const LayerArgs& L, const double* S, const double* ylt, int64_t m, void* scratch,
-                          double* d_grad_mean, double* d_grad_tvar, int n_cu, hipStream_t s) {
+                          double* d_grad_mean, double* d_grad_tvar, int n_cu, hipStream_t s,
+                          const PartLayout* parts, void* part_scratch, int64_t n_trials_total) {
     AdjScratch a = carve(scratch, C);
     hipError_t err;
     const int64_t n = L.trial_count;
@@ -195,14 +233,28 @@ hipError_t launch_adjoint(const int64_t* offsets, const uint32_t* ids, const dou
     hipLaunchKernelGGL(clear_acc_kernel, dim3(1), dim3(256), 0, s, a.acc);
     if ((err = hipGetLastError()) != hipSuccess) return err;
     const uint32_t cblocks = static_cast<uint32_t>((C + 255) / 256);
-    hipLaunchKernelGGL(mark_kernel, dim3(cblocks), dim3(256), 0, s, elts, C, L, a.mark, a.w_mean, a.w_tvar);
+    const int with_mark = (parts && parts->P > 0 && part_scratch) ? 0 : 1;
+    hipLaunchKernelGGL(mark_kernel, dim3(cblocks), dim3(256), 0, s, elts, C, L, a.mark, a.w_mean, a.w_tvar,
+                       with_mark);
     if ((err = hipGetLastError()) != hipSuccess) return err;
-    int64_t tblocks = (n + 3) / 4;
-    if (tblocks > int64_t(n_cu) * 8) tblocks = int64_t(n_cu) * 8;
-    if (tblocks < 1) tblocks = 1;
-    hipLaunchKernelGGL(active_trials_kernel, dim3(static_cast<uint32_t>(tblocks)), dim3(256), 0, s, offsets,
-                       ids, L, S, ylt, a.tail, a.mark, a.w_mean, a.w_tvar, a.acc);
-    if ((err = hipGetLastError()) != hipSuccess) return err;
+    if (parts && parts->P > 0 && part_scratch) {
+        int64_t ab = (n + 255) / 256;
+        if (ab > int64_t(n_cu) * 4) ab = int64_t(n_cu) * 4;
+        if (ab < 1) ab = 1;
+        hipLaunchKernelGGL(agg_counts_kernel, dim3(static_cast<uint32_t>(ab)), dim3(256), 0, s, L, S, ylt, a.tail,
+                           a.acc);
+        if ((err = hipGetLastError()) != hipSuccess) return err;
+        if ((err = launch_part_adjoint(*parts, n_trials_total, L, part_scratch, S, ylt, a.tail, a.w_mean,
+                                       a.w_tvar, n_cu, s)) != hipSuccess)
+            return err;
+    } else {
+        int64_t tblocks = (n + 3) / 4;
+        if (tblocks > int64_t(n_cu) * 8) tblocks = int64_t(n_cu) * 8;
+        if (tblocks < 1) tblocks = 1;
+        hipLaunchKernelGGL(active_trials_kernel, dim3(static_cast<uint32_t>(tblocks)), dim3(256), 0, s, offsets,
+                           ids, L, S, ylt, a.tail, a.mark, a.w_mean, a.w_tvar, a.acc);
+        if ((err = hipGetLastError()) != hipSuccess) return err;
+    }
     int64_t gblocks = (C + 255) / 256;
     if (gblocks > int64_t(n_cu) * 4) gblocks = int64_t(n_cu) * 4;
     hipLaunchKernelGGL(catalogue_kernel, dim3(static_cast<uint32_t>(gblocks)), dim3(256), 0, s, elts, C, L,

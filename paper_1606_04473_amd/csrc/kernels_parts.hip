@@ -1,0 +1,589 @@
+// Catalogue-partitioned trial pass.
+//
+// Random 8-byte gathers from a table larger than L2 run an order of magnitude
+// below the HBM stream rate on gfx950, and most occurrences of a layer carry
+// zero loss (an event absent from every ELT of the layer, or below the
+// occurrence retention).  So the per-event question "is o(E) nonzero, and
+// where is its value" is answered from LDS:
+//
+//  * the catalogue is cut into parts of 2^19 events; for each part the fold
+//    builds a 74,240-byte image: a 64 KB bitmap of nonzero o(E), a 16-bit rank
+//    per 128 events relative to its 4096-event superblock, and the global rank
+//    of each superblock; the nonzero values themselves go, in catalogue order,
+//    to a compact array small enough to stay in L2;
+//  * at table creation the YET is laid out part-major inside tiles of
+//    consecutive trials (tile -> part -> trial -> that trial's events of that
+//    part in time order, each segment padded to 16 bytes with an ID no event
+//    has), so a workgroup can hold one part image in LDS and stream exactly
+//    the events that need it;
+//  * a workgroup takes a tile, walks the parts in order, and for each trial
+//    adds the part's partial sum (double-double) into the trial's LDS
+//    accumulator; the trial's owner and the part order are fixed, so the
+//    result does not depend on scheduling.
+#include <vector>
+
+#include "ara_internal.hpp"
+
+namespace ara {
+
+namespace {
+
+constexpr int kPartShift = 19;
+constexpr int64_t kPartSize = int64_t(1) << kPartShift;       // catalogue events per part
+constexpr int kWords = kPartSize / 64;                        // 8192 u64 bitmap words
+constexpr int kRank16 = kPartSize / 128;                      // 4096 u16
+constexpr int kSuperShift = 12;
+constexpr int kSuper = 1 << kSuperShift;                      // 4096 events per superblock
+constexpr int kBase32 = kPartSize / kSuper;                   // 128 u32
+constexpr int64_t kImgBytes = int64_t(kWords) * 8 + int64_t(kRank16) * 2 + int64_t(kBase32) * 4;
+static_assert(kImgBytes == 74240, "part image layout");
+static_assert(kImgBytes % 16 == 0, "16-byte copies");
+constexpr int kTileMax = 256;                                 // trials per tile (LDS accumulators)
+constexpr uint32_t kSentinel = 0xFFFFFFFFu;
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+    const int lane = threadIdx.x & 63;
+    return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+// ---------------------------------------------------------------------------
+// create-time layout
+// ---------------------------------------------------------------------------
+
+// events per (trial, part), one wavefront per trial
+__global__ __launch_bounds__(256) void part_count_kernel(const int64_t* __restrict__ offsets,
+                                                         const uint32_t* __restrict__ ids, int64_t N, int P,
+                                                         int32_t* __restrict__ cnt) {
+    __shared__ int32_t c[4][kMaxParts];
+    const int w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int64_t n_waves = (static_cast<int64_t>(gridDim.x) * blockDim.x) >> 6;
+    for (int64_t t = uniform_i64((static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6); t < N;
+         t += n_waves) {
+        for (int p = lane; p < P; p += 64) c[w][p] = 0;
+        __builtin_amdgcn_wave_barrier();
+        for (int64_t i = offsets[t] + lane; i < offsets[t + 1]; i += 64) atomicAdd(&c[w][ids[i] >> kPartShift], 1);
+        __builtin_amdgcn_wave_barrier();
+        for (int p = lane; p < P; p += 64) cnt[t * P + p] = c[w][p];
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+// per tile: layout-order exclusive scan of the padded segment sizes
+__global__ __launch_bounds__(256) void tile_scan_kernel(const int32_t* __restrict__ cnt, int64_t N, int P, int T,
+                                                        uint32_t* __restrict__ seg_rel, int64_t* __restrict__ tile_size) {
+    __shared__ int64_t part_sum[256];
+    const int64_t tile = blockIdx.x;
+    const int64_t t0 = tile * T;
+    const int Tk = static_cast<int>(N - t0 < T ? N - t0 : T);
+    const int n = P * Tk;
+    const int64_t base = tile * (static_cast<int64_t>(T) * P + 1);
+    const int per = (n + 255) / 256;
+    const int j0 = threadIdx.x * per;
+    int64_t local = 0;
+    for (int j = j0; j < j0 + per && j < n; ++j) {
+        const int p = j / Tk, i = j % Tk;
+        local += (cnt[(t0 + i) * P + p] + 3) & ~3;
+    }
+    part_sum[threadIdx.x] = local;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        int64_t add = threadIdx.x >= off ? part_sum[threadIdx.x - off] : 0;
+        __syncthreads();
+        part_sum[threadIdx.x] += add;
+        __syncthreads();
+    }
+    int64_t run = part_sum[threadIdx.x] - local;
+    for (int j = j0; j < j0 + per && j < n; ++j) {
+        const int p = j / Tk, i = j % Tk;
+        seg_rel[base + j] = static_cast<uint32_t>(run);
+        run += (cnt[(t0 + i) * P + p] + 3) & ~3;
+    }
+    if (threadIdx.x == 255) {
+        seg_rel[base + n] = static_cast<uint32_t>(part_sum[255]);
+        tile_size[tile] = part_sum[255];
+    }
+}
+
+__global__ void fill_u32_kernel(uint32_t* p, int64_t n, uint32_t v) {
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
+}
+
+// stable scatter of each trial's events into its part segments, one wave per trial
+__global__ __launch_bounds__(256) void part_scatter_kernel(const int64_t* __restrict__ offsets,
+                                                           const uint32_t* __restrict__ ids, int64_t N, int P, int T,
+                                                           const uint32_t* __restrict__ seg_rel,
+                                                           const int64_t* __restrict__ tile_start,
+                                                           uint32_t* __restrict__ pids) {
+    __shared__ int64_t cur[4][kMaxParts];
+    const int w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int64_t n_waves = (static_cast<int64_t>(gridDim.x) * blockDim.x) >> 6;
+    for (int64_t t = uniform_i64((static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6); t < N;
+         t += n_waves) {
+        const int64_t tile = t / T;
+        const int i = static_cast<int>(t - tile * T);
+        const int64_t t0 = tile * T;
+        const int Tk = static_cast<int>(N - t0 < T ? N - t0 : T);
+        const int64_t base = tile * (static_cast<int64_t>(T) * P + 1);
+        for (int p = lane; p < P; p += 64) cur[w][p] = tile_start[tile] + seg_rel[base + static_cast<int64_t>(p) * Tk + i];
+        __builtin_amdgcn_wave_barrier();
+        const int64_t b = offsets[t], e = offsets[t + 1];
+        for (int64_t c = b; c < e; c += 64) {
+            const bool valid = c + lane < e;
+            const uint32_t id = valid ? ids[c + lane] : 0u;
+            const int pid = static_cast<int>(id >> kPartShift);
+            for (int q = 0; q < P; ++q) {
+                const uint64_t m = __ballot(valid && pid == q);
+                if (m == 0) continue;
+                const int64_t at = cur[w][q];
+                if (valid && pid == q) pids[at + __popcll(m & lanemask_lt())] = id;
+                __builtin_amdgcn_wave_barrier();
+                if (lane == 0) cur[w][q] = at + __popcll(m);
+                __builtin_amdgcn_wave_barrier();
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// per-request part images
+// ---------------------------------------------------------------------------
+
+// one workgroup (256 threads) per superblock of 4096 catalogue events:
+// bitmap words, per-128 ranks inside the superblock, superblock count
+__global__ __launch_bounds__(256) void part_image_kernel(const double* __restrict__ o, int64_t C,
+                                                         uint8_t* __restrict__ img, uint32_t* __restrict__ sb_count) {
+    __shared__ uint32_t wc[64];
+    const int64_t sb = blockIdx.x;
+    const int64_t e0 = sb * kSuper;
+    const int64_t part = e0 >> kPartShift;
+    const int ls = static_cast<int>((e0 & (kPartSize - 1)) >> kSuperShift);
+    uint64_t* bm = reinterpret_cast<uint64_t*>(img + part * kImgBytes);
+    uint16_t* r16 = reinterpret_cast<uint16_t*>(img + part * kImgBytes + int64_t(kWords) * 8);
+    const int w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    for (int k = 0; k < 16; ++k) {
+        const int word = w * 16 + k;                       // 0..63 inside the superblock
+        const int64_t E = e0 + word * 64 + lane;
+        const bool nz = E < C && o[E] != 0.0;
+        const uint64_t bits = __ballot(nz);
+        if (lane == 0) {
+            bm[ls * 64 + word] = bits;
+            wc[word] = __popcll(bits);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 32) {
+        uint32_t before = 0;
+        for (int b = 0; b < static_cast<int>(threadIdx.x); ++b) before += wc[2 * b] + wc[2 * b + 1];
+        r16[ls * 32 + threadIdx.x] = static_cast<uint16_t>(before);
+    }
+    if (threadIdx.x == 0) {
+        uint32_t total = 0;
+        for (int k = 0; k < 64; ++k) total += wc[k];
+        sb_count[sb] = total;
+    }
+}
+
+// exclusive scan of the superblock counts (one workgroup) into each part's
+// base32 table
+__global__ __launch_bounds__(1024) void superblock_scan_kernel(const uint32_t* __restrict__ sb_count, int64_t n_sb,
+                                                               uint8_t* __restrict__ img) {
+    __shared__ uint64_t s[1024];
+    uint64_t carry = 0;
+    for (int64_t c0 = 0; c0 < n_sb; c0 += 1024) {
+        const int64_t i = c0 + threadIdx.x;
+        const uint64_t v = i < n_sb ? sb_count[i] : 0;
+        s[threadIdx.x] = v;
+        __syncthreads();
+        for (int off = 1; off < 1024; off <<= 1) {
+            uint64_t add = threadIdx.x >= off ? s[threadIdx.x - off] : 0;
+            __syncthreads();
+            s[threadIdx.x] += add;
+            __syncthreads();
+        }
+        if (i < n_sb) {
+            const int64_t part = i / kBase32;
+            const int ls = static_cast<int>(i % kBase32);
+            uint32_t* b32 = reinterpret_cast<uint32_t*>(img + part * kImgBytes + int64_t(kWords) * 8 +
+                                                        int64_t(kRank16) * 2);
+            b32[ls] = static_cast<uint32_t>(carry + s[threadIdx.x] - v);
+        }
+        const uint64_t total = s[1023];
+        __syncthreads();
+        carry += total;
+    }
+}
+
+// nonzero o(E) to compact[rank(E)], one workgroup per superblock
+__global__ __launch_bounds__(256) void compact_kernel(const double* __restrict__ o, int64_t C,
+                                                      const uint8_t* __restrict__ img, double* __restrict__ compact) {
+    __shared__ uint32_t pre[64];
+    const int64_t sb = blockIdx.x;
+    const int64_t e0 = sb * kSuper;
+    const int64_t part = e0 >> kPartShift;
+    const int ls = static_cast<int>((e0 & (kPartSize - 1)) >> kSuperShift);
+    const uint64_t* bm = reinterpret_cast<const uint64_t*>(img + part * kImgBytes);
+    const uint32_t* b32 = reinterpret_cast<const uint32_t*>(img + part * kImgBytes + int64_t(kWords) * 8 +
+                                                            int64_t(kRank16) * 2);
+    if (threadIdx.x == 0) {
+        uint32_t run = b32[ls];
+        for (int k = 0; k < 64; ++k) {
+            pre[k] = run;
+            run += __popcll(bm[ls * 64 + k]);
+        }
+    }
+    __syncthreads();
+    const int w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    for (int k = 0; k < 16; ++k) {
+        const int word = w * 16 + k;
+        const int64_t E = e0 + word * 64 + lane;
+        const uint64_t bits = bm[ls * 64 + word];
+        if ((bits >> lane) & 1ull) compact[pre[word] + __popcll(bits & lanemask_lt())] = o[E];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// the partitioned trial pass
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(512) void part_pass_kernel(PartPassArgs a) {
+    __shared__ __attribute__((aligned(16))) uint64_t bm[kWords];
+    __shared__ __attribute__((aligned(16))) uint16_t r16[kRank16];
+    __shared__ __attribute__((aligned(16))) uint32_t b32[kBase32];
+    __shared__ double acc_hi[kTileMax];
+    __shared__ double acc_lo[kTileMax];
+    __shared__ int64_t s_tile;
+    const int lane = threadIdx.x & 63;
+    const int lig = lane & 15;                      // lane in its 16-lane group
+    const int slot = (threadIdx.x >> 6) * 4 + (lane >> 4);   // 32 groups per workgroup
+    const int P = a.P;
+    for (;;) {
+        if (threadIdx.x == 0) s_tile = a.first_tile + atomicAdd(a.tile_counter, 1u);
+        __syncthreads();
+        const int64_t tile = s_tile;
+        if (tile >= a.last_tile) break;
+        const int64_t t0 = tile * a.T;
+        const int Tk = static_cast<int>(a.N - t0 < a.T ? a.N - t0 : a.T);
+        const int64_t sbase = tile * (static_cast<int64_t>(a.T) * P + 1);
+        const uint32_t* tids = a.pids + a.tile_start[tile];
+        for (int i = threadIdx.x; i < Tk; i += blockDim.x) {
+            acc_hi[i] = 0.0;
+            acc_lo[i] = 0.0;
+        }
+        for (int p = 0; p < P; ++p) {
+            __syncthreads();
+            {
+                const u32x4* src = reinterpret_cast<const u32x4*>(a.img + p * kImgBytes);
+                u32x4* dst_bm = reinterpret_cast<u32x4*>(bm);
+                for (int k = threadIdx.x; k < kWords / 2; k += blockDim.x) dst_bm[k] = src[k];
+                const u32x4* src_r = src + kWords / 2;
+                u32x4* dst_r = reinterpret_cast<u32x4*>(r16);
+                for (int k = threadIdx.x; k < kRank16 / 8; k += blockDim.x) dst_r[k] = src_r[k];
+                const u32x4* src_b = src_r + kRank16 / 8;
+                u32x4* dst_b = reinterpret_cast<u32x4*>(b32);
+                for (int k = threadIdx.x; k < kBase32 / 4; k += blockDim.x) dst_b[k] = src_b[k];
+            }
+            __syncthreads();
+            const uint32_t pbase = static_cast<uint32_t>(static_cast<int64_t>(p) << kPartShift);
+            for (int i = slot; i < Tk; i += 32) {
+                const int64_t t = t0 + i;
+                if (t < a.t_lo || t >= a.t_hi) continue;
+                const uint32_t s = a.seg_rel[sbase + static_cast<int64_t>(p) * Tk + i];
+                const uint32_t e = a.seg_rel[sbase + static_cast<int64_t>(p) * Tk + i + 1];
+                double hi = 0.0, lo = 0.0;
+                for (uint32_t c = s + lig * 4; c < e; c += 64) {
+                    const u32x4 v = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(tids + c));
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const uint32_t el = v[q] - pbase;           // sentinel and foreign IDs fail the test
+                        if (el < static_cast<uint32_t>(kPartSize)) {
+                            const uint64_t word = bm[el >> 6];
+                            if ((word >> (el & 63)) & 1ull) {
+                                uint32_t r = b32[el >> kSuperShift] + r16[el >> 7];
+                                if ((el >> 6) & 1) r += __popcll(bm[(el >> 6) - 1]);
+                                r += __popcll(word & ((1ull << (el & 63)) - 1ull));
+                                dd_add(hi, lo, a.compact[r]);
+                            }
+                        }
+                    }
+                }
+                group_reduce_dd(hi, lo, 16);
+                if (lig == 0) {
+                    double h = acc_hi[i], l = acc_lo[i];
+                    dd_merge(h, l, hi, lo);
+                    acc_hi[i] = h;
+                    acc_lo[i] = l;
+                }
+            }
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < Tk; i += blockDim.x) {
+            const int64_t t = t0 + i;
+            if (t < a.t_lo || t >= a.t_hi) continue;
+            const double S = acc_hi[i] + acc_lo[i];
+            a.ylt[t - a.t_lo] = apply_terms(S, a.aggR, a.aggL);
+            if (a.S) a.S[t - a.t_lo] = S;
+        }
+        __syncthreads();
+    }
+}
+
+// Backward histogram over the partitioned layout: for every trial inside the
+// aggregate band, every occurrence whose event has a movable occurrence loss
+// (bit set in the part bitmap) adds 1 to W_mean[E] and the trial's TVaR weight
+// to W_tvar[E].  Integer atomics: the histogram does not depend on order.
+__global__ __launch_bounds__(512) void part_adjoint_kernel(PartAdjArgs a) {
+    __shared__ __attribute__((aligned(16))) uint64_t bm[kWords];
+    __shared__ int64_t s_tile;
+    const int lane = threadIdx.x & 63;
+    const int lig = lane & 15;
+    const int slot = (threadIdx.x >> 6) * 4 + (lane >> 4);
+    const int P = a.P;
+    const TailStats ts = *a.tail;
+    for (;;) {
+        if (threadIdx.x == 0) s_tile = a.first_tile + atomicAdd(a.tile_counter, 1u);
+        __syncthreads();
+        const int64_t tile = s_tile;
+        if (tile >= a.last_tile) break;
+        const int64_t t0 = tile * a.T;
+        const int Tk = static_cast<int>(a.N - t0 < a.T ? a.N - t0 : a.T);
+        const int64_t sbase = tile * (static_cast<int64_t>(a.T) * P + 1);
+        const uint32_t* tids = a.pids + a.tile_start[tile];
+        for (int p = 0; p < P; ++p) {
+            __syncthreads();
+            {
+                const u32x4* src = reinterpret_cast<const u32x4*>(a.img + p * kImgBytes);
+                u32x4* dst = reinterpret_cast<u32x4*>(bm);
+                for (int k = threadIdx.x; k < kWords / 2; k += blockDim.x) dst[k] = src[k];
+            }
+            __syncthreads();
+            const uint32_t pbase = static_cast<uint32_t>(static_cast<int64_t>(p) << kPartShift);
+            for (int i = slot; i < Tk; i += 32) {
+                const int64_t t = t0 + i;
+                if (t < a.t_lo || t >= a.t_hi) continue;
+                const int64_t k = t - a.t_lo;
+                const double ta = a.S[k] - a.aggR;
+                if (!((ta > 0.0) && (ta < a.aggL))) continue;
+                const uint64_t key = __double_as_longlong(a.ylt[k] + 0.0);
+                const unsigned long long wt =
+                    key > ts.v_bits ? ts.c_eq : (key == ts.v_bits ? ts.m - ts.c_gt : 0);
+                const uint32_t s = a.seg_rel[sbase + static_cast<int64_t>(p) * Tk + i];
+                const uint32_t e = a.seg_rel[sbase + static_cast<int64_t>(p) * Tk + i + 1];
+                for (uint32_t c = s + lig * 4; c < e; c += 64) {
+                    const u32x4 v = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(tids + c));
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const uint32_t el = v[q] - pbase;
+                        if (el < static_cast<uint32_t>(kPartSize) && ((bm[el >> 6] >> (el & 63)) & 1ull)) {
+                            atomicAdd(reinterpret_cast<unsigned long long*>(&a.w_mean[v[q]]), 1ull);
+                            if (wt) atomicAdd(reinterpret_cast<unsigned long long*>(&a.w_tvar[v[q]]), wt);
+                        }
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+}  // namespace
+
+int64_t part_image_bytes(int P) { return static_cast<int64_t>(P) * kImgBytes; }
+int64_t part_size() { return kPartSize; }
+int part_tile_trials() { return kTileMax; }
+
+hipError_t build_part_layout(const int64_t* offsets, const uint32_t* ids, int64_t N, int64_t n_events, int64_t C,
+                             int n_cu, hipStream_t s, PartLayout* out) {
+    *out = PartLayout{};
+    const int P = static_cast<int>((C + kPartSize - 1) / kPartSize);
+    if (P < 1 || P > kMaxParts || N < 1) return hipSuccess;            // layout not used
+    const int T = kTileMax;
+    const int64_t n_tiles = (N + T - 1) / T;
+    hipError_t e;
+    int32_t* cnt = nullptr;
+    int64_t* tsize = nullptr;
+    if ((e = hipMalloc(&cnt, sizeof(int32_t) * N * P)) != hipSuccess) return e;
+    if ((e = hipMalloc(&out->seg_rel, sizeof(uint32_t) * (n_tiles * (static_cast<int64_t>(T) * P + 1)))) != hipSuccess)
+        goto fail;
+    if ((e = hipMalloc(&tsize, sizeof(int64_t) * n_tiles)) != hipSuccess) goto fail;
+    if ((e = hipMalloc(&out->tile_start, sizeof(int64_t) * (n_tiles + 1))) != hipSuccess) goto fail;
+    {
+        int64_t blocks = (N + 3) / 4;
+        if (blocks > int64_t(n_cu) * 16) blocks = int64_t(n_cu) * 16;
+        hipLaunchKernelGGL(part_count_kernel, dim3(static_cast<uint32_t>(blocks)), dim3(256), 0, s, offsets, ids, N,
+                           P, cnt);
+        if ((e = hipGetLastError()) != hipSuccess) goto fail;
+        hipLaunchKernelGGL(tile_scan_kernel, dim3(static_cast<uint32_t>(n_tiles)), dim3(256), 0, s, cnt, N, P, T,
+                           out->seg_rel, tsize);
+        if ((e = hipGetLastError()) != hipSuccess) goto fail;
+        std::vector<int64_t> h(n_tiles), st(n_tiles + 1);
+        if ((e = hipMemcpyAsync(h.data(), tsize, sizeof(int64_t) * n_tiles, hipMemcpyDeviceToHost, s)) != hipSuccess)
+            goto fail;
+        if ((e = hipStreamSynchronize(s)) != hipSuccess) goto fail;
+        st[0] = 0;
+        for (int64_t k = 0; k < n_tiles; ++k) {
+            if (h[k] >= (int64_t(1) << 32)) {   // a tile too large for 32-bit offsets: keep the plain layout
+                (void)hipFree(cnt);
+                (void)hipFree(tsize);
+                (void)hipFree(out->seg_rel);
+                (void)hipFree(out->tile_start);
+                *out = PartLayout{};
+                return hipSuccess;
+            }
+            st[k + 1] = st[k] + h[k];
+        }
+        const int64_t total = st[n_tiles];
+        if ((e = hipMemcpyAsync(out->tile_start, st.data(), sizeof(int64_t) * (n_tiles + 1), hipMemcpyHostToDevice,
+                                s)) != hipSuccess)
+            goto fail;
+        if ((e = hipMalloc(&out->pids, sizeof(uint32_t) * (total + kIdPad))) != hipSuccess) goto fail;
+        int64_t fb = (total + kIdPad + 255) / 256;
+        if (fb > 8192) fb = 8192;
+        hipLaunchKernelGGL(fill_u32_kernel, dim3(static_cast<uint32_t>(fb)), dim3(256), 0, s, out->pids, total + kIdPad,
+                           kSentinel);
+        if ((e = hipGetLastError()) != hipSuccess) goto fail;
+        hipLaunchKernelGGL(part_scatter_kernel, dim3(static_cast<uint32_t>(blocks)), dim3(256), 0, s, offsets, ids, N,
+                           P, T, out->seg_rel, out->tile_start, out->pids);
+        if ((e = hipGetLastError()) != hipSuccess) goto fail;
+        if ((e = hipStreamSynchronize(s)) != hipSuccess) goto fail;
+        (void)n_events;
+        out->P = P;
+        out->T = T;
+        out->n_tiles = n_tiles;
+        out->length = total;
+        out->bytes = sizeof(uint32_t) * (total + kIdPad) + sizeof(uint32_t) * (n_tiles * (int64_t(T) * P + 1)) +
+                     sizeof(int64_t) * (n_tiles + 1);
+    }
+    (void)hipFree(cnt);
+    (void)hipFree(tsize);
+    return hipSuccess;
+fail:
+    if (cnt) (void)hipFree(cnt);
+    if (tsize) (void)hipFree(tsize);
+    free_part_layout(out);
+    return e;
+}
+
+void free_part_layout(PartLayout* L) {
+    if (L->pids) (void)hipFree(L->pids);
+    if (L->seg_rel) (void)hipFree(L->seg_rel);
+    if (L->tile_start) (void)hipFree(L->tile_start);
+    *L = PartLayout{};
+}
+
+int64_t part_scratch_bytes(int64_t C, int P) {
+    const int64_t n_sb = static_cast<int64_t>(P) * kBase32;
+    return part_image_bytes(P) + sizeof(uint32_t) * n_sb + sizeof(double) * C + 256;
+}
+
+namespace {
+struct PartScratch {
+    uint8_t* img;
+    uint32_t* sb_count;
+    uint32_t* counter;
+    double* compact;
+};
+PartScratch carve_parts(void* scratch, int P) {
+    char* p = static_cast<char*>(scratch);
+    PartScratch r;
+    r.img = reinterpret_cast<uint8_t*>(p);
+    p += part_image_bytes(P);
+    const int64_t n_sb = static_cast<int64_t>(P) * kBase32;
+    r.sb_count = reinterpret_cast<uint32_t*>(p);
+    p += sizeof(uint32_t) * n_sb;
+    r.counter = reinterpret_cast<uint32_t*>(p);
+    p += 256;
+    r.compact = reinterpret_cast<double*>(p);
+    return r;
+}
+}  // namespace
+
+hipError_t launch_part_fold(const double* o, int64_t C, int P, void* scratch, hipStream_t s) {
+    PartScratch ps = carve_parts(scratch, P);
+    const int64_t n_sb = static_cast<int64_t>(P) * kBase32;
+    hipError_t e;
+    hipLaunchKernelGGL(part_image_kernel, dim3(static_cast<uint32_t>(n_sb)), dim3(256), 0, s, o, C, ps.img,
+                       ps.sb_count);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(superblock_scan_kernel, dim3(1), dim3(1024), 0, s, ps.sb_count, n_sb, ps.img);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(compact_kernel, dim3(static_cast<uint32_t>(n_sb)), dim3(256), 0, s, o, C, ps.img, ps.compact);
+    return hipGetLastError();
+}
+
+hipError_t launch_part_pass(const PartLayout& lay, int64_t N, const LayerArgs& L, void* scratch, double* ylt,
+                            double* S, int n_cu, hipStream_t s) {
+    if (L.trial_count <= 0) return hipSuccess;
+    const int P = lay.P;
+    PartScratch ps = carve_parts(scratch, P);
+    hipError_t e;
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(64), 0, s, ps.counter, int64_t(1), 0u);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    PartPassArgs a{};
+    a.pids = lay.pids;
+    a.seg_rel = lay.seg_rel;
+    a.tile_start = lay.tile_start;
+    a.img = ps.img;
+    a.compact = ps.compact;
+    a.N = N;
+    a.P = P;
+    a.T = lay.T;
+    a.t_lo = L.trial_begin;
+    a.t_hi = L.trial_begin + L.trial_count;
+    a.first_tile = L.trial_begin / lay.T;
+    a.last_tile = (a.t_hi + lay.T - 1) / lay.T;
+    a.aggR = L.aggR;
+    a.aggL = L.aggL;
+    a.ylt = ylt;
+    a.S = S;
+    a.tile_counter = ps.counter;
+    int64_t grid = a.last_tile - a.first_tile;
+    if (grid > int64_t(n_cu) * 2) grid = int64_t(n_cu) * 2;
+    hipLaunchKernelGGL(part_pass_kernel, dim3(static_cast<uint32_t>(grid)), dim3(512), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace ara
+
+namespace ara {
+
+hipError_t launch_part_adjoint(const PartLayout& lay, int64_t N, const LayerArgs& L, void* part_scratch,
+                               const double* S, const double* ylt, const TailStats* tail, uint64_t* w_mean,
+                               uint64_t* w_tvar, int n_cu, hipStream_t s) {
+    if (L.trial_count <= 0) return hipSuccess;
+    PartScratch ps = carve_parts(part_scratch, lay.P);
+    hipError_t e;
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(64), 0, s, ps.counter, int64_t(1), 0u);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    PartAdjArgs a{};
+    a.pids = lay.pids;
+    a.seg_rel = lay.seg_rel;
+    a.tile_start = lay.tile_start;
+    a.img = ps.img;
+    a.N = N;
+    a.P = lay.P;
+    a.T = lay.T;
+    a.t_lo = L.trial_begin;
+    a.t_hi = L.trial_begin + L.trial_count;
+    a.first_tile = L.trial_begin / lay.T;
+    a.last_tile = (a.t_hi + lay.T - 1) / lay.T;
+    a.aggR = L.aggR;
+    a.aggL = L.aggL;
+    a.S = S;
+    a.ylt = ylt;
+    a.tail = tail;
+    a.w_mean = w_mean;
+    a.w_tvar = w_tvar;
+    a.tile_counter = ps.counter;
+    int64_t grid = a.last_tile - a.first_tile;
+    if (grid > int64_t(n_cu) * 2) grid = int64_t(n_cu) * 2;
+    hipLaunchKernelGGL(part_adjoint_kernel, dim3(static_cast<uint32_t>(grid)), dim3(512), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace ara

@@ -110,7 +110,8 @@ def test_config0_year_losses_all_modes(ara, cfg0):
     w, tables, ref, S = cfg0
     spec = _spec(ara, w.layers[0], w.pool, w.yet)
     base = None
-    for flags in (0, ara.ARA_LITERAL, ara.ARA_CHECKPOINT_S, ara.ARA_LITERAL | ara.ARA_CHECKPOINT_S):
+    for flags in (0, ara.ARA_LITERAL, ara.ARA_CHECKPOINT_S, ara.ARA_CHECKPOINT_STRIDE,
+                  ara.ARA_LITERAL | ara.ARA_CHECKPOINT_S):
         for lpt in (64, 32, 16, 8):
             ara.set_tuning(tables, lanes_per_trial=lpt)
             ylt = ara.run_layers(tables, [spec], flags=flags)
@@ -157,6 +158,11 @@ def test_config0_checkpoints(ara, cfg0):
     yet, pool, layer = w.yet, w.pool, w.layers[0]
     spec = _spec(ara, layer, pool, yet)
     ara.run_layers(tables, [spec], flags=ara.ARA_CHECKPOINT_S)
+    with pytest.raises(ara.AraError):
+        ara.read_checkpoints(tables, 1)                   # no stride checkpoints were asked for
+    ok, worst = _close(ara.read_checkpoints(tables, 0), S)
+    assert ok, worst
+    ara.run_layers(tables, [spec], flags=ara.ARA_CHECKPOINT_STRIDE)
     S_gpu = ara.read_checkpoints(tables, 0)
     ok, worst = _close(S_gpu, S)
     assert ok, worst
@@ -267,7 +273,7 @@ def test_ragged_and_edge_cases(ara):
     for layer in layers:
         spec = _spec(ara, layer, pool, yet)
         ref, _ = oracle.run_layer(yet, pool, layer)
-        for flags in (0, ara.ARA_LITERAL, ara.ARA_CHECKPOINT_S):
+        for flags in (0, ara.ARA_LITERAL, ara.ARA_CHECKPOINT_STRIDE):
             for lpt in (64, 8):
                 ara.set_tuning(tables, lanes_per_trial=lpt)
                 ylt = ara.run_layers(tables, [spec], flags=flags)
@@ -318,6 +324,35 @@ def test_error_paths(ara):
         ara.risk_metrics(np.array([1.0, -2.0]), [0.5])
     assert e.value.status == ara.ARA_ERR_INVALID_ARG
     tables.close()
+
+
+def test_multi_part_catalogue_and_layouts(ara):
+    """A catalogue of several 2^19-event parts, ragged trials, sub-ranges that
+    cut tiles: the partitioned pass, the time-ordered pass (plain layout) and
+    the literal pass all match the oracle."""
+    C = 1_300_000
+    yet = make_yet(1500, 150.0, C, seed=41)
+    rng = np.random.default_rng(42)
+    lengths = np.diff(yet.offsets)
+    assert lengths.max() > 150 and lengths.min() >= 0
+    pool = make_elt_pool(5, C, 60_000, seed=43)
+    part = ara.create_tables(yet.offsets, yet.ids, pool.losses)
+    plain = ara.create_tables(yet.offsets, yet.ids, pool.losses, flags=ara.ARA_PLAIN_LAYOUT)
+    assert part.bytes() > plain.bytes()
+    for begin, count in ((0, yet.n_trials), (255, 2), (100, 1000), (1499, 1), (256, 256)):
+        layer = Layer(np.array([4, 0, 2], dtype=np.int32), 2000.0, 3.0e5, 1.0e5, 4.0e5, begin, count)
+        spec = _spec(ara, layer, pool, yet)
+        ref, S = oracle.run_layer(yet, pool, layer)
+        for tables, flags in ((part, 0), (plain, 0), (part, ara.ARA_LITERAL), (part, ara.ARA_CHECKPOINT_S)):
+            ylt = ara.run_layers(tables, [spec], flags=flags)
+            ok, worst = _close(ylt, ref)
+            assert ok, (begin, count, flags, worst)
+        got_S = ara.read_checkpoints(part, 0)
+        ok, worst = _close(got_S, S)
+        assert ok, worst
+    assert rng is not None
+    part.close()
+    plain.close()
 
 
 # ---------------------------------------------------------------------------
