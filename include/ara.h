@@ -144,6 +144,17 @@ ara_status ara_create_tables(const int64_t* trial_offsets, int64_t n_trials,
                              int64_t catalogue_size, uint32_t flags, void* stream,
                              ara_tables** out);
 
+/*
+ * ara_create_yet -- Algorithm 2 for one YET slice when the ELTs are already
+ * resident: new tables that own the given YET (copied like ara_create_tables
+ * does, validated against base's catalogue, with the partitioned copy unless
+ * ARA_PLAIN_LAYOUT) and share base's ELT pool without copying it.  `base`
+ * must outlive the new tables.  Errors as ara_create_tables.
+ */
+ara_status ara_create_yet(const ara_tables* base, const int64_t* trial_offsets, int64_t n_trials,
+                          const uint32_t* event_ids, int64_t n_events, uint32_t flags, void* stream,
+                          ara_tables** out);
+
 /* Release the device memory of the tables.  NULL is accepted. */
 void ara_destroy_tables(ara_tables* tables);
 

@@ -48,7 +48,7 @@ EXPORTED = (
     "ara_create_tables", "ara_destroy_tables", "ara_run_layers", "ara_risk_metrics", "ara_backward",
     "ara_last_error", "ara_status_string", "ara_table_bytes", "ara_footprint", "ara_debug_lookups",
     "ara_read_checkpoints", "ara_set_tuning", "ara_get_tuning", "ara_device_info",
-    "ara_kernel_stats",
+    "ara_kernel_stats", "ara_create_yet",
 )
 
 
@@ -106,6 +106,8 @@ def lib():
                              ctypes.c_double)
     L.ara_create_tables.argtypes = [P, i64, P, i64, P, i32, i64, u32, P, ctypes.POINTER(P)]
     L.ara_create_tables.restype = i32
+    L.ara_create_yet.argtypes = [P, P, i64, P, i64, u32, P, ctypes.POINTER(P)]
+    L.ara_create_yet.restype = i32
     L.ara_destroy_tables.argtypes = [P]
     L.ara_destroy_tables.restype = None
     L.ara_run_layers.argtypes = [P, ctypes.POINTER(CLayer), i32, P, i64, u32, P]
@@ -296,6 +298,23 @@ def create_tables(offsets, ids, elt_losses, catalogue_size: Optional[int] = None
                                    flags | (ARA_DEVICE_PTR if do else 0), _stream(stream),
                                    ctypes.byref(h)))
     return Tables(h, n_trials, n_events, C, n_pool)
+
+
+def create_yet(base: Tables, offsets, ids, stream=None, flags: int = 0) -> Tables:
+    """ara_create_yet: tables owning this YET and sharing base's ELT pool.
+    The returned object keeps `base` alive."""
+    po, ko, do = _ptr(offsets, np.int64)
+    pi, ki, di = _ptr(ids, np.uint32)
+    if do != di:
+        raise ValueError("offsets and ids must both be host arrays or both device tensors")
+    n_trials = int(ko.shape[0]) - 1
+    n_events = int(ki.shape[0])
+    h = ctypes.c_void_p()
+    _check(lib().ara_create_yet(base.handle, po, n_trials, pi, n_events,
+                                flags | (ARA_DEVICE_PTR if do else 0), _stream(stream), ctypes.byref(h)))
+    t = Tables(h, n_trials, n_events, base.catalogue_size, base.n_pool)
+    t._base = base
+    return t
 
 
 def run_layers(tables: Tables, layers: Sequence[LayerSpec], out=None, flags: int = 0,

@@ -209,9 +209,28 @@ ara_status ara_device_info(int32_t* n_cu, int32_t* device) {
     return ARA_OK;
 }
 
+static ara_status create_impl(const int64_t* trial_offsets, int64_t n_trials, const uint32_t* event_ids,
+                              int64_t n_events, const double* elt_losses, int32_t n_elts, int64_t catalogue_size,
+                              uint32_t flags, void* stream, const ara_tables* base, ara_tables** out);
+
 ara_status ara_create_tables(const int64_t* trial_offsets, int64_t n_trials, const uint32_t* event_ids,
                              int64_t n_events, const double* elt_losses, int32_t n_elts,
                              int64_t catalogue_size, uint32_t flags, void* stream, ara_tables** out) {
+    return create_impl(trial_offsets, n_trials, event_ids, n_events, elt_losses, n_elts, catalogue_size, flags,
+                       stream, nullptr, out);
+}
+
+ara_status ara_create_yet(const ara_tables* base, const int64_t* trial_offsets, int64_t n_trials,
+                          const uint32_t* event_ids, int64_t n_events, uint32_t flags, void* stream,
+                          ara_tables** out) {
+    if (!base) return fail(ARA_ERR_INVALID_ARG, "base tables are NULL");
+    return create_impl(trial_offsets, n_trials, event_ids, n_events, base->elts, base->n_pool, base->C, flags,
+                       stream, base, out);
+}
+
+static ara_status create_impl(const int64_t* trial_offsets, int64_t n_trials, const uint32_t* event_ids,
+                              int64_t n_events, const double* elt_losses, int32_t n_elts, int64_t catalogue_size,
+                              uint32_t flags, void* stream, const ara_tables* base, ara_tables** out) {
     if (!out) return fail(ARA_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
     if (n_trials < 0 || n_events < 0 || n_elts < 0 || catalogue_size < 1)
@@ -227,7 +246,12 @@ ara_status ara_create_tables(const int64_t* trial_offsets, int64_t n_trials, con
     }
     hipStream_t s = static_cast<hipStream_t>(stream);
     int device = 0;
-    HIP_TRY(hipGetDevice(&device), "hipGetDevice");
+    if (base) {
+        device = base->device;
+        if (hipSetDevice(device) != hipSuccess) return fail(ARA_ERR_DEVICE, "cannot select the base tables' device");
+    } else {
+        HIP_TRY(hipGetDevice(&device), "hipGetDevice");
+    }
     keep_pool_memory(device);
     ara_tables* t = new (std::nothrow) ara_tables();
     if (!t) return fail(ARA_ERR_NO_MEMORY, "host allocation failed");
@@ -243,7 +267,13 @@ ara_status ara_create_tables(const int64_t* trial_offsets, int64_t n_trials, con
     };
     const size_t off_bytes = sizeof(int64_t) * (n_trials + 1);
     const size_t id_bytes = sizeof(uint32_t) * (n_events + ara::kIdPad);
-    const size_t elt_bytes = sizeof(double) * static_cast<size_t>(n_elts) * catalogue_size;
+    const size_t elt_bytes = base ? 0 : sizeof(double) * static_cast<size_t>(n_elts) * catalogue_size;
+    if (base) {
+        t->elts = const_cast<double*>(elt_losses);
+        t->owns_elts = false;
+        std::lock_guard<std::mutex> g(const_cast<ara_tables*>(base)->mu);
+        t->tuning = base->tuning;
+    }
     hipError_t e;
     if ((e = hipMalloc(&t->offsets, off_bytes)) != hipSuccess) return cleanup(hip_fail(e, "hipMalloc offsets"));
     if ((e = hipMalloc(&t->ids, id_bytes)) != hipSuccess) return cleanup(hip_fail(e, "hipMalloc event ids"));
@@ -264,7 +294,7 @@ ara_status ara_create_tables(const int64_t* trial_offsets, int64_t n_trials, con
     if ((e = flag.alloc(sizeof(uint32_t), s)) != hipSuccess) return cleanup(hip_fail(e, "scratch"));
     if ((e = hipMemsetAsync(flag.p, 0, sizeof(uint32_t), s)) != hipSuccess) return cleanup(hip_fail(e, "memset"));
     if ((e = ara::launch_validate(t->offsets, n_trials, t->ids, n_events, t->elts,
-                                  static_cast<int64_t>(n_elts) * catalogue_size, catalogue_size,
+                                  base ? 0 : static_cast<int64_t>(n_elts) * catalogue_size, catalogue_size,
                                   static_cast<uint32_t*>(flag.p), t->n_cu, s)) != hipSuccess)
         return cleanup(hip_fail(e, "validate kernel"));
     uint32_t host_flag = 0;
@@ -300,7 +330,7 @@ void ara_destroy_tables(ara_tables* t) {
     DeviceScope ds(t->device);
     if (t->offsets) (void)hipFree(t->offsets);
     if (t->ids) (void)hipFree(t->ids);
-    if (t->elts) (void)hipFree(t->elts);
+    if (t->elts && t->owns_elts) (void)hipFree(t->elts);
     free_checkpoints(t->ck);
     ara::free_part_layout(&t->parts);
     for (auto& p : t->prof.pending) {

@@ -185,6 +185,7 @@ struct ara_tables {
     int64_t* offsets = nullptr;   // [n_trials + 1]
     uint32_t* ids = nullptr;      // [n_events + kIdPad]
     double* elts = nullptr;       // [n_pool][C]
+    bool owns_elts = true;        // false: the pool belongs to another tables object
     int64_t bytes = 0;
     ara_tuning tuning{};
     std::mutex mu;                // guards ck and tuning

@@ -1,0 +1,295 @@
+"""Multi-tenant request loop on one GPU.
+
+The paper runs several clients ("tenants") on virtual GPUs mapped onto one
+physical GPU, so that one tenant's host-to-device transfer overlaps another's
+kernel, and compares two transfer modes (Section V-D): *concurrent* (every
+device receives its data at once, sharing the link) and *sequential* (one
+transfer at a time at full link bandwidth while others compute).  Here a
+tenant is a worker thread with its own HIP stream; tenants share one GPU, the
+resident ELT pool and, in "resident" mode, the resident YET.
+
+Each request is an analysis: a slice of trials of the YET and 1-16 layers.
+Shipped modes copy the slice to the device (Algorithm 2) -- concurrently or
+under a FIFO transfer token -- and build tables for it that share the
+resident ELT pool (ara_create_yet); resident mode runs the layers on trial
+ranges of the resident YET.  Admission is by device memory: a request waits
+(FIFO) until its footprint fits the budget, then runs as soon as its tenant is
+free, overlapping with the other tenants' work (continuous batching: requests
+are admitted as slots and memory free up, not in fixed batches).  Results
+carry arrival, admission, start and finish times; latency is finish minus
+arrival.
+"""
+
+from __future__ import annotations
+
+import math
+import threading
+import time
+from collections import deque
+from dataclasses import dataclass, field
+from typing import Dict, List, Optional, Sequence
+
+import numpy as np
+
+MODES = ("concurrent", "sequential", "resident")
+
+
+# ---------------------------------------------------------------------------
+# admission by device memory (no GPU needed)
+# ---------------------------------------------------------------------------
+
+class AdmissionController:
+    """FIFO admission against a byte budget.
+
+    acquire(n) blocks until every earlier waiter has been admitted and
+    used + n <= budget; a request larger than the whole budget is refused
+    (returns False) instead of waiting forever.
+    """
+
+    def __init__(self, budget_bytes: int):
+        self.budget = int(budget_bytes)
+        self.used = 0
+        self.peak = 0
+        self._cv = threading.Condition()
+        self._queue: deque = deque()
+        self.waits: List[float] = []
+
+    def acquire(self, nbytes: int, timeout: Optional[float] = None) -> bool:
+        nbytes = int(nbytes)
+        if nbytes > self.budget:
+            return False
+        t0 = time.perf_counter()
+        me = object()
+        with self._cv:
+            self._queue.append(me)
+            deadline = None if timeout is None else t0 + timeout
+            while not (self._queue[0] is me and self.used + nbytes <= self.budget):
+                remaining = None if deadline is None else deadline - time.perf_counter()
+                if remaining is not None and remaining <= 0:
+                    self._queue.remove(me)
+                    self._cv.notify_all()
+                    return False
+                self._cv.wait(remaining)
+            self._queue.popleft()
+            self.used += nbytes
+            self.peak = max(self.peak, self.used)
+            self.waits.append(time.perf_counter() - t0)
+            self._cv.notify_all()
+        return True
+
+    def release(self, nbytes: int) -> None:
+        with self._cv:
+            self.used -= int(nbytes)
+            assert self.used >= 0
+            self._cv.notify_all()
+
+
+# ---------------------------------------------------------------------------
+# requests
+# ---------------------------------------------------------------------------
+
+@dataclass
+class Request:
+    rid: int
+    tenant: int
+    arrival: float              # seconds after the start of the run
+    trial_begin: int
+    n_trials: int
+    layer_ids: List[int]
+
+
+@dataclass
+class Result:
+    rid: int
+    tenant: int
+    arrival: float
+    admitted: float = math.nan
+    started: float = math.nan
+    finished: float = math.nan
+    footprint: int = 0
+    metrics: List[List[float]] = field(default_factory=list)   # per layer [mean, pml.., tvar..]
+    error: Optional[str] = None
+
+    @property
+    def latency(self) -> float:
+        return self.finished - self.arrival
+
+
+def make_requests(n_tenants: int, per_tenant: int, rate_per_tenant: float, n_yet_trials: int,
+                  n_library: int, seed: int, n_min: int = 10_000, n_max: int = 1_000_000,
+                  layers_max: int = 16) -> List[Request]:
+    """Poisson arrivals per tenant (seed + 1000 * tenant), n ~ log-uniform
+    [n_min, n_max] trials at a uniform offset, 1..layers_max layers drawn
+    without replacement from the layer library."""
+    reqs: List[Request] = []
+    n_max = min(n_max, n_yet_trials)
+    n_min = min(n_min, n_max)
+    rid = 0
+    for k in range(n_tenants):
+        rng = np.random.Generator(np.random.PCG64(seed + 1000 * k))
+        t = 0.0
+        for _ in range(per_tenant):
+            t += float(rng.exponential(1.0 / rate_per_tenant)) if rate_per_tenant > 0 else 0.0
+            n = int(round(math.exp(rng.uniform(math.log(n_min), math.log(n_max)))))
+            n = min(max(n, 1), n_yet_trials)
+            begin = int(rng.integers(0, n_yet_trials - n + 1))
+            nl = int(rng.integers(1, layers_max + 1))
+            lids = rng.choice(n_library, size=min(nl, n_library), replace=False).tolist()
+            reqs.append(Request(rid, k, t, begin, n, lids))
+            rid += 1
+    reqs.sort(key=lambda r: (r.arrival, r.rid))
+    return reqs
+
+
+def percentile(x: Sequence[float], q: float) -> float:
+    a = np.sort(np.asarray(x, dtype=np.float64))
+    if a.shape[0] == 0:
+        return math.nan
+    k = max(0, min(a.shape[0] - 1, int(math.ceil(q / 100.0 * a.shape[0])) - 1))
+    return float(a[k])
+
+
+def summarize(results: Sequence[Result], wall: float) -> Dict[str, float]:
+    ok = [r for r in results if r.error is None]
+    lat = [r.latency for r in ok]
+    return {
+        "requests": len(results),
+        "completed": len(ok),
+        "rejected": len(results) - len(ok),
+        "wall_s": wall,
+        "throughput_req_s": len(ok) / wall if wall > 0 else math.nan,
+        "p50_ms": percentile(lat, 50) * 1e3,
+        "p99_ms": percentile(lat, 99) * 1e3,
+        "mean_ms": float(np.mean(lat)) * 1e3 if lat else math.nan,
+    }
+
+
+# ---------------------------------------------------------------------------
+# the GPU server
+# ---------------------------------------------------------------------------
+
+class Server:
+    """Runs requests for n_tenants tenants on one GPU.
+
+    base:     resident tables (ELT pool and, for resident mode, the YET);
+    offsets, ids: the host YET the requests slice (ids pinned by the server);
+    library:  LayerSpec list (trial ranges are replaced per request);
+    probs:    risk-metric probabilities reported per layer.
+    """
+
+    def __init__(self, base, offsets: np.ndarray, ids: np.ndarray, library, n_tenants: int,
+                 mode: str, budget_bytes: int, probs=(0.99,)):
+        import torch
+        from . import ara
+        if mode not in MODES:
+            raise ValueError(mode)
+        self.torch = torch
+        self.ara = ara
+        self.base = base
+        self.offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+        self.library = list(library)
+        self.n_tenants = n_tenants
+        self.mode = mode
+        self.probs = list(probs)
+        self.admission = AdmissionController(budget_bytes)
+        self.transfer_token = threading.Lock()
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        self.streams = [torch.cuda.Stream() for _ in range(n_tenants)]
+        self.host_ids = None
+        if mode != "resident":
+            self.host_ids = torch.from_numpy(np.ascontiguousarray(ids, dtype=np.uint32).view(np.int32)).pin_memory()
+
+    def footprint(self, req: Request) -> int:
+        n_ev = int(self.offsets[req.trial_begin + req.n_trials] - self.offsets[req.trial_begin])
+        out = 8 * req.n_trials * len(req.layer_ids) + 8 * (1 + 2 * len(self.probs)) * len(req.layer_ids)
+        scratch = 8 * self.base.catalogue_size * 2 + 8 * 1024 * 1024   # occurrence losses, images, compact
+        if self.mode == "resident":
+            return out + scratch
+        yet = 4 * n_ev + 8 * (req.n_trials + 1)
+        # staging copy + owned copy + partitioned copy (~ the IDs again, padded)
+        return 2 * yet + 5 * n_ev + 16 * req.n_trials + out + scratch
+
+    def _layers_for(self, req: Request, begin: int):
+        specs = []
+        for lid in req.layer_ids:
+            s = self.library[lid]
+            specs.append(self.ara.LayerSpec(s.elt_index, s.elt_retention, s.elt_limit, s.occ_retention,
+                                            s.occ_limit, s.agg_retention, s.agg_limit, begin, req.n_trials))
+        return specs
+
+    def _serve_one(self, req: Request, res: Result, t0: float) -> None:
+        torch, ara = self.torch, self.ara
+        stream = self.streams[req.tenant]
+        nb = self.footprint(req)
+        res.footprint = nb
+        if not self.admission.acquire(nb):
+            res.error = "footprint exceeds the device-memory budget"
+            res.finished = time.perf_counter() - t0
+            return
+        res.admitted = time.perf_counter() - t0
+        tables = None
+        try:
+            with torch.cuda.stream(stream):
+                res.started = time.perf_counter() - t0
+                if self.mode == "resident":
+                    tables, begin = self.base, req.trial_begin
+                else:
+                    lo = int(self.offsets[req.trial_begin])
+                    hi = int(self.offsets[req.trial_begin + req.n_trials])
+                    off = torch.from_numpy(self.offsets[req.trial_begin:req.trial_begin + req.n_trials + 1] - lo)
+                    off = off.pin_memory()
+                    d_ids = torch.empty(hi - lo, dtype=torch.int32, device=self.device)
+                    d_off = torch.empty(req.n_trials + 1, dtype=torch.int64, device=self.device)
+                    if self.mode == "sequential":
+                        with self.transfer_token:
+                            d_ids.copy_(self.host_ids[lo:hi], non_blocking=True)
+                            d_off.copy_(off, non_blocking=True)
+                            stream.synchronize()
+                    else:
+                        d_ids.copy_(self.host_ids[lo:hi], non_blocking=True)
+                        d_off.copy_(off, non_blocking=True)
+                    tables = ara.create_yet(self.base, d_off, d_ids, stream=stream)
+                    del d_ids, d_off
+                    begin = 0
+                specs = self._layers_for(req, begin)
+                k = len(self.probs)
+                ylt = torch.empty(req.n_trials, dtype=torch.float64, device=self.device)
+                out = torch.empty((len(specs), 1 + 2 * k), dtype=torch.float64, device=self.device)
+                for i, s in enumerate(specs):
+                    ara.run_layers(tables, [s], out=ylt, stream=stream)
+                    ara.risk_metrics(ylt, self.probs, outputs=out[i], stream=stream)
+                host = out.cpu()              # waits for this tenant's stream only
+                res.metrics = host.numpy().tolist()
+        except Exception as exc:              # a poisoned request fails alone
+            res.error = f"{type(exc).__name__}: {exc}"
+        finally:
+            if tables is not None and tables is not self.base:
+                tables.close()
+            res.finished = time.perf_counter() - t0
+            self.admission.release(nb)
+
+    def run(self, requests: Sequence[Request], time_scale: float = 1.0) -> List[Result]:
+        """Serve `requests` (arrival times scaled by time_scale).  One worker
+        per tenant takes that tenant's requests in arrival order."""
+        per_tenant: Dict[int, List[Request]] = {k: [] for k in range(self.n_tenants)}
+        for r in requests:
+            per_tenant[r.tenant % self.n_tenants].append(r)
+        results = {r.rid: Result(r.rid, r.tenant, r.arrival * time_scale) for r in requests}
+        t0 = time.perf_counter()
+
+        def worker(k: int) -> None:
+            for r in per_tenant[k]:
+                wait = r.arrival * time_scale - (time.perf_counter() - t0)
+                if wait > 0:
+                    time.sleep(wait)
+                rr = Request(r.rid, k, r.arrival, r.trial_begin, r.n_trials, r.layer_ids)
+                self._serve_one(rr, results[r.rid], t0)
+
+        threads = [threading.Thread(target=worker, args=(k,)) for k in range(self.n_tenants)]
+        for th in threads:
+            th.start()
+        for th in threads:
+            th.join()
+        self.torch.cuda.synchronize()
+        self.wall = time.perf_counter() - t0
+        return [results[r.rid] for r in requests]

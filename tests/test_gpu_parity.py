@@ -456,3 +456,19 @@ def test_config1_gradient_vs_finite_differences(ara, cfg1):
                 bad.append((name, k, float(fd), float(g)))
     print(f"worst relative FD disagreement {worst:.3e}")
     assert not bad, bad
+
+
+def test_autograd_function_matches_oracle(ara, cfg0):
+    import torch
+    from paper_1606_04473_amd.autograd import mean_and_tvar, theta_of
+    w, tables, ref, S = cfg0
+    yet, pool, layer = w.yet, w.pool, w.layers[0]
+    spec = _spec(ara, layer, pool, yet)
+    theta = theta_of(spec).requires_grad_(True)
+    mean, tvar, ylt = mean_and_tvar(theta, tables, spec, 0.99)
+    (2.0 * mean + 0.5 * tvar).backward()
+    g = oracle.gradients(yet, pool, layer, 0.99, ylt=ref, S=S)
+    expect = 2.0 * g["grad_mean"] + 0.5 * g["grad_tvar"]
+    assert np.array_equal(theta.grad.numpy(), expect)
+    rmean, _, rtvar = oracle.risk_metrics(ref, [0.99])
+    assert abs(mean.item() - rmean) <= REL * rmean and abs(tvar.item() - rtvar[0]) <= REL * rtvar[0]
