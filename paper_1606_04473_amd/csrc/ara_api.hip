@@ -4,6 +4,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <new>
 #include <string>
 #include <vector>
@@ -175,6 +176,115 @@ struct KernelTimer {
     }
 };
 
+// Make the staging buffer at least `bytes` and wait for earlier copies out of it.
+hipError_t stage_acquire(ara::HostStage& st, size_t bytes) {
+    hipError_t e;
+    if (!st.done && (e = hipEventCreateWithFlags(&st.done, hipEventDisableTiming)) != hipSuccess) return e;
+    if ((e = hipEventSynchronize(st.done)) != hipSuccess) return e;
+    if (st.cap < bytes) {
+        if (st.p) (void)hipHostFree(st.p);
+        st.p = nullptr;
+        st.cap = 0;
+        size_t want = bytes < (1u << 20) ? (1u << 20) : bytes;
+        if ((e = hipHostMalloc(&st.p, want, hipHostMallocDefault)) != hipSuccess) return e;
+        st.cap = want;
+    }
+    return hipSuccess;
+}
+
+void stage_free(ara::HostStage& st) {
+    if (st.done) {
+        (void)hipEventSynchronize(st.done);
+        (void)hipEventDestroy(st.done);
+    }
+    if (st.p) (void)hipHostFree(st.p);
+    st = ara::HostStage{};
+}
+
+void free_graph(ara::GraphEntry* g) {
+    if (!g) return;
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    stage_free(g->stage);
+    if (g->scratch) (void)hipFree(g->scratch);
+    delete g;
+}
+
+// Host-side description of a batched run.
+struct BatchPlan {
+    std::vector<ara::BatchLayerDesc> layers;
+    std::vector<ara::BatchFoldDesc> fold;
+    std::vector<int32_t> idx;
+    std::vector<double> R, Lim;
+    std::vector<int2> items;
+    std::vector<int64_t> key;
+};
+
+BatchPlan make_plan(const ara_tables* t, const std::vector<ara::LayerArgs>& L, const double* ylt_ptr) {
+    BatchPlan b;
+    const int T = t->parts.T;
+    struct Cost {
+        int64_t c;
+        int l;
+        int64_t tile;
+    };
+    std::vector<Cost> costs;
+    b.key.push_back(static_cast<int64_t>(L.size()));
+    b.key.push_back(reinterpret_cast<int64_t>(ylt_ptr));
+    for (size_t l = 0; l < L.size(); ++l) {
+        const auto& a = L[l];
+        b.layers.push_back({a.trial_begin, a.trial_begin + a.trial_count, a.aggR, a.aggL, a.out_offset});
+        b.fold.push_back({a.J, static_cast<int32_t>(b.idx.size()), a.occR, a.occL});
+        for (int j = 0; j < a.J; ++j) {
+            b.idx.push_back(a.idx[j]);
+            b.R.push_back(a.R[j]);
+            b.Lim.push_back(a.Lim[j]);
+        }
+        b.key.push_back(a.J);
+        b.key.push_back(a.trial_begin);
+        b.key.push_back(a.trial_count);
+        if (a.trial_count <= 0) continue;
+        const int64_t lo = a.trial_begin, hi = a.trial_begin + a.trial_count;
+        for (int64_t tile = lo / T; tile * T < hi; ++tile) {
+            const int64_t a0 = std::max(lo, tile * T), a1 = std::min(hi, (tile + 1) * T);
+            costs.push_back({a1 - a0, static_cast<int>(l), tile});
+        }
+    }
+    std::stable_sort(costs.begin(), costs.end(), [](const Cost& x, const Cost& y) { return x.c > y.c; });
+    b.items.reserve(costs.size());
+    for (const auto& c : costs) b.items.push_back(make_int2(c.l, static_cast<int>(c.tile)));
+    return b;
+}
+
+// Copy the plan's descriptors (and, with_items, the work list) into the
+// device scratch through pinned staging, on stream s.
+hipError_t upload_plan(ara::HostStage& st, const BatchPlan& b, const ara::BatchedScratch& bs, bool with_items,
+                       hipStream_t s) {
+    const size_t n1 = sizeof(ara::BatchLayerDesc) * b.layers.size();
+    const size_t n2 = sizeof(ara::BatchFoldDesc) * b.fold.size();
+    const size_t n3 = sizeof(double) * b.R.size();
+    const size_t n4 = sizeof(int32_t) * b.idx.size();
+    const size_t n5 = with_items ? sizeof(int2) * b.items.size() : 0;
+    hipError_t e;
+    if ((e = stage_acquire(st, n1 + n2 + 2 * n3 + n4 + n5 + 64)) != hipSuccess) return e;
+    char* h = static_cast<char*>(st.p);
+    size_t off = 0;
+    auto put = [&](void* dst, const void* src, size_t n) -> hipError_t {
+        if (n == 0) return hipSuccess;
+        std::memcpy(h + off, src, n);
+        hipError_t r = hipMemcpyAsync(dst, h + off, n, hipMemcpyHostToDevice, s);
+        off += (n + 15) & ~size_t(15);
+        return r;
+    };
+    if ((e = put(bs.layers, b.layers.data(), n1)) != hipSuccess) return e;
+    if ((e = put(bs.fold, b.fold.data(), n2)) != hipSuccess) return e;
+    if ((e = put(bs.R, b.R.data(), n3)) != hipSuccess) return e;
+    if ((e = put(bs.Lim, b.Lim.data(), n3)) != hipSuccess) return e;
+    if ((e = put(bs.idx, b.idx.data(), n4)) != hipSuccess) return e;
+    if ((e = put(bs.items, b.items.data(), n5)) != hipSuccess) return e;
+    return hipEventRecord(st.done, s);
+}
+
 int query_cu_count(int device) {
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) != hipSuccess || prop.multiProcessorCount <= 0) return 256;
@@ -333,6 +443,9 @@ void ara_destroy_tables(ara_tables* t) {
     if (t->elts && t->owns_elts) (void)hipFree(t->elts);
     free_checkpoints(t->ck);
     ara::free_part_layout(&t->parts);
+    for (auto* g : t->graphs) free_graph(g);
+    t->graphs.clear();
+    stage_free(t->stage);
     for (auto& p : t->prof.pending) {
         (void)hipEventDestroy(p.start);
         (void)hipEventDestroy(p.stop);
@@ -473,7 +586,72 @@ ara_status ara_run_layers(ara_tables* t, const ara_layer* layers, int32_t n_laye
         }
         S_buf = ck.S;
     }
-    for (int i = 0; i < n_layers; ++i) {
+    const bool batched = n_layers > 1 && !(flags & ARA_PER_LAYER) && !literal && !ckpt && t->parts.P > 0;
+    if ((flags & ARA_GRAPH) && batched && (!dev_out || s == nullptr))
+        return fail(ARA_ERR_INVALID_ARG, "ARA_GRAPH needs a device output and a non-null stream");
+    if (batched) {
+        BatchPlan plan = make_plan(t, L, out);
+        const int64_t n_items = static_cast<int64_t>(plan.items.size());
+        const int64_t n_elts_total = static_cast<int64_t>(plan.idx.size());
+        const int64_t sbytes = ara::batched_scratch_bytes(t->C, t->parts.P, n_layers, n_items, n_elts_total);
+        const bool prof = (flags & ARA_PROFILE) != 0;
+        if (flags & ARA_GRAPH) {
+            std::lock_guard<std::mutex> g(t->stage_mu);
+            ara::GraphEntry* ge = nullptr;
+            for (auto* c : t->graphs)
+                if (c->key == plan.key) ge = c;
+            if (!ge) {
+                ge = new ara::GraphEntry();
+                ge->key = plan.key;
+                hipError_t e = hipMalloc(&ge->scratch, sbytes);
+                if (e != hipSuccess) {
+                    free_graph(ge);
+                    return hip_fail(e, "graph scratch");
+                }
+                ara::BatchedScratch bs =
+                    ara::carve_batched(ge->scratch, t->C, t->parts.P, n_layers, n_items, n_elts_total);
+                if ((e = upload_plan(ge->stage, plan, bs, true, s)) != hipSuccess ||
+                    (e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal)) != hipSuccess) {
+                    free_graph(ge);
+                    return hip_fail(e, "graph capture");
+                }
+                hipError_t le = ara::launch_batched(t->parts, t->n_trials, t->C, t->elts, n_layers, bs, n_items, out,
+                                                    t->n_cu, s, nullptr, nullptr);
+                e = hipStreamEndCapture(s, &ge->graph);
+                if (le != hipSuccess || e != hipSuccess ||
+                    (e = hipGraphInstantiate(&ge->exec, ge->graph, nullptr, nullptr, 0)) != hipSuccess) {
+                    free_graph(ge);
+                    return hip_fail(le != hipSuccess ? le : e, "graph instantiate");
+                }
+                if (t->graphs.size() >= 8) {
+                    free_graph(t->graphs.front());
+                    t->graphs.erase(t->graphs.begin());
+                }
+                t->graphs.push_back(ge);
+            } else {
+                ara::BatchedScratch bs =
+                    ara::carve_batched(ge->scratch, t->C, t->parts.P, n_layers, n_items, n_elts_total);
+                HIP_TRY(upload_plan(ge->stage, plan, bs, false, s), "upload layer terms");
+            }
+            KernelTimer kt(t, s, prof, ARA_KERNEL_BATCHED);
+            HIP_TRY(hipGraphLaunch(ge->exec, s), "graph launch");
+            kt.done();
+        } else {
+            PoolBuffer bbuf;
+            HIP_TRY(bbuf.alloc(sbytes, s), "batched scratch");
+            ara::BatchedScratch bs = ara::carve_batched(bbuf.p, t->C, t->parts.P, n_layers, n_items, n_elts_total);
+            {
+                std::lock_guard<std::mutex> g(t->stage_mu);
+                HIP_TRY(upload_plan(t->stage, plan, bs, true, s), "upload work list");
+            }
+            KernelTimer kt(t, s, prof, ARA_KERNEL_BATCHED);
+            HIP_TRY(ara::launch_batched(t->parts, t->n_trials, t->C, t->elts, n_layers, bs, n_items, out, t->n_cu, s,
+                                        nullptr, nullptr),
+                    "batched pass");
+            kt.done();
+        }
+    }
+    for (int i = 0; i < n_layers && !batched; ++i) {
         ara::TrialPassArgs a{};
         a.offsets = t->offsets;
         a.ids = t->ids;

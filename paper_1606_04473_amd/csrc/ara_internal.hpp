@@ -142,6 +142,47 @@ struct PartPassArgs {
     uint32_t* tile_counter;
 };
 
+// batched multi-layer pass
+struct BatchLayerDesc {
+    int64_t t_lo, t_hi;
+    double aggR, aggL;
+    int64_t out_off;
+};
+struct BatchFoldDesc {
+    int32_t J, off;
+    double occR, occL;
+};
+struct BatchedPassArgs {
+    const uint32_t* pids;
+    const uint32_t* seg_rel;
+    const int64_t* tile_start;
+    const uint8_t* img;
+    int64_t img_stride;
+    const double* compact;
+    int64_t C;
+    int64_t N;
+    int P;
+    int T;
+    const int2* items;             // (layer, tile), decreasing cost
+    int32_t n_items;
+    const BatchLayerDesc* layers;
+    double* ylt;
+    uint32_t* item_counter;
+};
+struct BatchedScratch {
+    double* o;
+    double* compact;
+    uint8_t* img;
+    uint32_t* sb_count;
+    uint32_t* counter;
+    int2* items;
+    BatchLayerDesc* layers;
+    BatchFoldDesc* fold;
+    double* R;
+    double* Lim;
+    int32_t* idx;
+};
+
 struct TailStats;
 struct PartAdjArgs {
     const uint32_t* pids;
@@ -173,6 +214,24 @@ struct ProfileState {
     double total_ms[3] = {0.0, 0.0, 0.0};
 };
 
+// Pinned host staging for small per-call uploads; the event marks when the
+// last copy out of it has completed.
+struct HostStage {
+    void* p = nullptr;
+    size_t cap = 0;
+    hipEvent_t done = nullptr;
+};
+
+// A captured batched run: persistent scratch, a graph, and the shape it was
+// captured for.
+struct GraphEntry {
+    std::vector<int64_t> key;
+    void* scratch = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+    HostStage stage;
+};
+
 }  // namespace ara
 
 struct ara_tables {
@@ -191,6 +250,9 @@ struct ara_tables {
     std::mutex mu;                // guards ck and tuning
     ara::CheckpointState ck;
     ara::PartLayout parts;
+    std::mutex stage_mu;          // guards stage and graphs
+    ara::HostStage stage;
+    std::vector<ara::GraphEntry*> graphs;
     std::mutex prof_mu;           // guards prof
     ara::ProfileState prof;
 };
@@ -233,6 +295,12 @@ int64_t part_scratch_bytes(int64_t C, int P);
 hipError_t launch_part_fold(const double* o, int64_t C, int P, void* scratch, hipStream_t s);
 hipError_t launch_part_pass(const PartLayout& lay, int64_t N, const LayerArgs& L, void* scratch, double* ylt,
                             double* S, int n_cu, hipStream_t s);
+
+int64_t batched_scratch_bytes(int64_t C, int P, int n_layers, int64_t n_items, int64_t n_elts_total);
+BatchedScratch carve_batched(void* scratch, int64_t C, int P, int n_layers, int64_t n_items, int64_t n_elts_total);
+hipError_t launch_batched(const PartLayout& lay, int64_t N, int64_t C, const double* elts, int n_layers,
+                          const BatchedScratch& b, int64_t n_items, double* ylt, int n_cu, hipStream_t s,
+                          hipEvent_t pass_start, hipEvent_t pass_stop);
 
 // metrics: results[0] = mean, results[1 + 2q] = PML_q, results[2 + 2q] = TVaR_q
 int64_t metrics_scratch_bytes(int n_probs);

@@ -155,8 +155,12 @@ __global__ __launch_bounds__(256) void part_scatter_kernel(const int64_t* __rest
 // one workgroup (256 threads) per superblock of 4096 catalogue events:
 // bitmap words, per-128 ranks inside the superblock, superblock count
 __global__ __launch_bounds__(256) void part_image_kernel(const double* __restrict__ o, int64_t C,
-                                                         uint8_t* __restrict__ img, uint32_t* __restrict__ sb_count) {
+                                                         uint8_t* __restrict__ img, uint32_t* __restrict__ sb_count,
+                                                         int64_t o_stride, int64_t img_stride, int64_t sb_stride) {
     __shared__ uint32_t wc[64];
+    o += blockIdx.y * o_stride;
+    img += blockIdx.y * img_stride;
+    sb_count += blockIdx.y * sb_stride;
     const int64_t sb = blockIdx.x;
     const int64_t e0 = sb * kSuper;
     const int64_t part = e0 >> kPartShift;
@@ -191,8 +195,10 @@ __global__ __launch_bounds__(256) void part_image_kernel(const double* __restric
 // exclusive scan of the superblock counts (one workgroup) into each part's
 // base32 table
 __global__ __launch_bounds__(1024) void superblock_scan_kernel(const uint32_t* __restrict__ sb_count, int64_t n_sb,
-                                                               uint8_t* __restrict__ img) {
+                                                               uint8_t* __restrict__ img, int64_t img_stride) {
     __shared__ uint64_t s[1024];
+    sb_count += blockIdx.y * n_sb;
+    img += blockIdx.y * img_stride;
     uint64_t carry = 0;
     for (int64_t c0 = 0; c0 < n_sb; c0 += 1024) {
         const int64_t i = c0 + threadIdx.x;
@@ -220,8 +226,12 @@ __global__ __launch_bounds__(1024) void superblock_scan_kernel(const uint32_t* _
 
 // nonzero o(E) to compact[rank(E)], one workgroup per superblock
 __global__ __launch_bounds__(256) void compact_kernel(const double* __restrict__ o, int64_t C,
-                                                      const uint8_t* __restrict__ img, double* __restrict__ compact) {
+                                                      const uint8_t* __restrict__ img, double* __restrict__ compact,
+                                                      int64_t o_stride, int64_t img_stride) {
     __shared__ uint32_t pre[64];
+    o += blockIdx.y * o_stride;
+    img += blockIdx.y * img_stride;
+    compact += blockIdx.y * o_stride;
     const int64_t sb = blockIdx.x;
     const int64_t e0 = sb * kSuper;
     const int64_t part = e0 >> kPartShift;
@@ -251,86 +261,138 @@ __global__ __launch_bounds__(256) void compact_kernel(const double* __restrict__
 // the partitioned trial pass
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(512) void part_pass_kernel(PartPassArgs a) {
-    __shared__ __attribute__((aligned(16))) uint64_t bm[kWords];
-    __shared__ __attribute__((aligned(16))) uint16_t r16[kRank16];
-    __shared__ __attribute__((aligned(16))) uint32_t b32[kBase32];
-    __shared__ double acc_hi[kTileMax];
-    __shared__ double acc_lo[kTileMax];
-    __shared__ int64_t s_tile;
+// LDS state of one workgroup of the partitioned pass
+struct PassLds {
+    uint64_t bm[kWords];
+    uint16_t r16[kRank16];
+    uint32_t b32[kBase32];
+    double acc_hi[kTileMax];
+    double acc_lo[kTileMax];
+    int64_t tile;
+    int32_t item;
+};
+
+// One (layer, tile): every part image in turn, every trial of the tile inside
+// [t_lo, t_hi); writes YLT (and S) for those trials.  All threads of the
+// workgroup call it; it starts and ends with a barrier.
+__device__ __forceinline__ void pass_tile(PassLds& sh, const uint32_t* __restrict__ pids,
+                                          const uint32_t* __restrict__ seg_rel,
+                                          const int64_t* __restrict__ tile_start, const uint8_t* __restrict__ img,
+                                          const double* __restrict__ compact, int64_t N, int P, int T, int64_t tile,
+                                          int64_t t_lo, int64_t t_hi, double aggR, double aggL,
+                                          double* __restrict__ ylt, double* __restrict__ S_out) {
     const int lane = threadIdx.x & 63;
-    const int lig = lane & 15;                      // lane in its 16-lane group
-    const int slot = (threadIdx.x >> 6) * 4 + (lane >> 4);   // 32 groups per workgroup
-    const int P = a.P;
-    for (;;) {
-        if (threadIdx.x == 0) s_tile = a.first_tile + atomicAdd(a.tile_counter, 1u);
+    const int lig = lane & 15;                                 // lane in its 16-lane group
+    const int slot = (threadIdx.x >> 6) * 4 + (lane >> 4);    // 32 groups per workgroup
+    const int64_t t0 = tile * T;
+    const int Tk = static_cast<int>(N - t0 < T ? N - t0 : T);
+    const int64_t sbase = tile * (static_cast<int64_t>(T) * P + 1);
+    const uint32_t* tids = pids + tile_start[tile];
+    for (int i = threadIdx.x; i < Tk; i += blockDim.x) {
+        sh.acc_hi[i] = 0.0;
+        sh.acc_lo[i] = 0.0;
+    }
+    for (int p = 0; p < P; ++p) {
         __syncthreads();
-        const int64_t tile = s_tile;
-        if (tile >= a.last_tile) break;
-        const int64_t t0 = tile * a.T;
-        const int Tk = static_cast<int>(a.N - t0 < a.T ? a.N - t0 : a.T);
-        const int64_t sbase = tile * (static_cast<int64_t>(a.T) * P + 1);
-        const uint32_t* tids = a.pids + a.tile_start[tile];
-        for (int i = threadIdx.x; i < Tk; i += blockDim.x) {
-            acc_hi[i] = 0.0;
-            acc_lo[i] = 0.0;
+        {
+            const u32x4* src = reinterpret_cast<const u32x4*>(img + p * kImgBytes);
+            u32x4* dst_bm = reinterpret_cast<u32x4*>(sh.bm);
+            for (int k = threadIdx.x; k < kWords / 2; k += blockDim.x) dst_bm[k] = src[k];
+            const u32x4* src_r = src + kWords / 2;
+            u32x4* dst_r = reinterpret_cast<u32x4*>(sh.r16);
+            for (int k = threadIdx.x; k < kRank16 / 8; k += blockDim.x) dst_r[k] = src_r[k];
+            const u32x4* src_b = src_r + kRank16 / 8;
+            u32x4* dst_b = reinterpret_cast<u32x4*>(sh.b32);
+            for (int k = threadIdx.x; k < kBase32 / 4; k += blockDim.x) dst_b[k] = src_b[k];
         }
-        for (int p = 0; p < P; ++p) {
-            __syncthreads();
-            {
-                const u32x4* src = reinterpret_cast<const u32x4*>(a.img + p * kImgBytes);
-                u32x4* dst_bm = reinterpret_cast<u32x4*>(bm);
-                for (int k = threadIdx.x; k < kWords / 2; k += blockDim.x) dst_bm[k] = src[k];
-                const u32x4* src_r = src + kWords / 2;
-                u32x4* dst_r = reinterpret_cast<u32x4*>(r16);
-                for (int k = threadIdx.x; k < kRank16 / 8; k += blockDim.x) dst_r[k] = src_r[k];
-                const u32x4* src_b = src_r + kRank16 / 8;
-                u32x4* dst_b = reinterpret_cast<u32x4*>(b32);
-                for (int k = threadIdx.x; k < kBase32 / 4; k += blockDim.x) dst_b[k] = src_b[k];
-            }
-            __syncthreads();
-            const uint32_t pbase = static_cast<uint32_t>(static_cast<int64_t>(p) << kPartShift);
-            for (int i = slot; i < Tk; i += 32) {
-                const int64_t t = t0 + i;
-                if (t < a.t_lo || t >= a.t_hi) continue;
-                const uint32_t s = a.seg_rel[sbase + static_cast<int64_t>(p) * Tk + i];
-                const uint32_t e = a.seg_rel[sbase + static_cast<int64_t>(p) * Tk + i + 1];
-                double hi = 0.0, lo = 0.0;
-                for (uint32_t c = s + lig * 4; c < e; c += 64) {
-                    const u32x4 v = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(tids + c));
+        __syncthreads();
+        const uint32_t pbase = static_cast<uint32_t>(static_cast<int64_t>(p) << kPartShift);
+        for (int i = slot; i < Tk; i += 32) {
+            const int64_t t = t0 + i;
+            if (t < t_lo || t >= t_hi) continue;
+            const uint32_t s = seg_rel[sbase + static_cast<int64_t>(p) * Tk + i];
+            const uint32_t e = seg_rel[sbase + static_cast<int64_t>(p) * Tk + i + 1];
+            double hi = 0.0, lo = 0.0;
+            for (uint32_t c = s + lig * 4; c < e; c += 64) {
+                const u32x4 v = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(tids + c));
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const uint32_t el = v[q] - pbase;           // sentinel and foreign IDs fail the test
-                        if (el < static_cast<uint32_t>(kPartSize)) {
-                            const uint64_t word = bm[el >> 6];
-                            if ((word >> (el & 63)) & 1ull) {
-                                uint32_t r = b32[el >> kSuperShift] + r16[el >> 7];
-                                if ((el >> 6) & 1) r += __popcll(bm[(el >> 6) - 1]);
-                                r += __popcll(word & ((1ull << (el & 63)) - 1ull));
-                                dd_add(hi, lo, a.compact[r]);
-                            }
+                for (int q = 0; q < 4; ++q) {
+                    const uint32_t el = v[q] - pbase;           // sentinel and foreign IDs fail the test
+                    if (el < static_cast<uint32_t>(kPartSize)) {
+                        const uint64_t word = sh.bm[el >> 6];
+                        if ((word >> (el & 63)) & 1ull) {
+                            uint32_t r = sh.b32[el >> kSuperShift] + sh.r16[el >> 7];
+                            if ((el >> 6) & 1) r += __popcll(sh.bm[(el >> 6) - 1]);
+                            r += __popcll(word & ((1ull << (el & 63)) - 1ull));
+                            dd_add(hi, lo, compact[r]);
                         }
                     }
                 }
-                group_reduce_dd(hi, lo, 16);
-                if (lig == 0) {
-                    double h = acc_hi[i], l = acc_lo[i];
-                    dd_merge(h, l, hi, lo);
-                    acc_hi[i] = h;
-                    acc_lo[i] = l;
-                }
+            }
+            group_reduce_dd(hi, lo, 16);
+            if (lig == 0) {
+                double h = sh.acc_hi[i], l = sh.acc_lo[i];
+                dd_merge(h, l, hi, lo);
+                sh.acc_hi[i] = h;
+                sh.acc_lo[i] = l;
             }
         }
-        __syncthreads();
-        for (int i = threadIdx.x; i < Tk; i += blockDim.x) {
-            const int64_t t = t0 + i;
-            if (t < a.t_lo || t >= a.t_hi) continue;
-            const double S = acc_hi[i] + acc_lo[i];
-            a.ylt[t - a.t_lo] = apply_terms(S, a.aggR, a.aggL);
-            if (a.S) a.S[t - a.t_lo] = S;
-        }
-        __syncthreads();
     }
+    __syncthreads();
+    for (int i = threadIdx.x; i < Tk; i += blockDim.x) {
+        const int64_t t = t0 + i;
+        if (t < t_lo || t >= t_hi) continue;
+        const double S = sh.acc_hi[i] + sh.acc_lo[i];
+        ylt[t - t_lo] = apply_terms(S, aggR, aggL);
+        if (S_out) S_out[t - t_lo] = S;
+    }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(512) void part_pass_kernel(PartPassArgs a) {
+    __shared__ __attribute__((aligned(16))) PassLds sh;
+    for (;;) {
+        if (threadIdx.x == 0) sh.tile = a.first_tile + atomicAdd(a.tile_counter, 1u);
+        __syncthreads();
+        const int64_t tile = sh.tile;
+        if (tile >= a.last_tile) break;
+        pass_tile(sh, a.pids, a.seg_rel, a.tile_start, a.img, a.compact, a.N, a.P, a.T, tile, a.t_lo, a.t_hi,
+                  a.aggR, a.aggL, a.ylt, a.S);
+    }
+}
+
+// The persistent multi-layer pass: one grid drains a work list of
+// (layer, tile) items, ordered by decreasing cost, through an atomic counter.
+__global__ __launch_bounds__(512) void batched_pass_kernel(BatchedPassArgs a) {
+    __shared__ __attribute__((aligned(16))) PassLds sh;
+    for (;;) {
+        if (threadIdx.x == 0) sh.item = static_cast<int32_t>(atomicAdd(a.item_counter, 1u));
+        __syncthreads();
+        const int32_t it = sh.item;
+        if (it >= a.n_items) break;
+        const int2 w = a.items[it];
+        const BatchLayerDesc d = a.layers[w.x];
+        pass_tile(sh, a.pids, a.seg_rel, a.tile_start, a.img + w.x * a.img_stride, a.compact + w.x * a.C, a.N,
+                  a.P, a.T, w.y, d.t_lo, d.t_hi, d.aggR, d.aggL, a.ylt + d.out_off, nullptr);
+    }
+}
+
+// per-layer fold for a batch: o[l][E], ELT terms from device tables
+__global__ __launch_bounds__(256) void batched_fold_kernel(const double* __restrict__ elts, int64_t C,
+                                                           const BatchFoldDesc* __restrict__ fd,
+                                                           const int32_t* __restrict__ idx,
+                                                           const double* __restrict__ R,
+                                                           const double* __restrict__ Lim, double* __restrict__ o) {
+    const int l = blockIdx.y;
+    const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= C) return;
+    const BatchFoldDesc d = fd[l];
+    double y = 0.0;
+    for (int j = 0; j < d.J; ++j) {
+        const int k = d.off + j;
+        y = y + apply_terms(elts[static_cast<int64_t>(idx[k]) * C + e], R[k], Lim[k]);
+    }
+    o[static_cast<int64_t>(l) * C + e] = apply_terms(y, d.occR, d.occL);
 }
 
 // Backward histogram over the partitioned layout: for every trial inside the
@@ -508,11 +570,12 @@ hipError_t launch_part_fold(const double* o, int64_t C, int P, void* scratch, hi
     const int64_t n_sb = static_cast<int64_t>(P) * kBase32;
     hipError_t e;
     hipLaunchKernelGGL(part_image_kernel, dim3(static_cast<uint32_t>(n_sb)), dim3(256), 0, s, o, C, ps.img,
-                       ps.sb_count);
+                       ps.sb_count, int64_t(0), int64_t(0), int64_t(0));
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(superblock_scan_kernel, dim3(1), dim3(1024), 0, s, ps.sb_count, n_sb, ps.img);
+    hipLaunchKernelGGL(superblock_scan_kernel, dim3(1), dim3(1024), 0, s, ps.sb_count, n_sb, ps.img, int64_t(0));
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(compact_kernel, dim3(static_cast<uint32_t>(n_sb)), dim3(256), 0, s, o, C, ps.img, ps.compact);
+    hipLaunchKernelGGL(compact_kernel, dim3(static_cast<uint32_t>(n_sb)), dim3(256), 0, s, o, C, ps.img, ps.compact,
+                       int64_t(0), int64_t(0));
     return hipGetLastError();
 }
 
@@ -584,6 +647,98 @@ hipError_t launch_part_adjoint(const PartLayout& lay, int64_t N, const LayerArgs
     if (grid > int64_t(n_cu) * 2) grid = int64_t(n_cu) * 2;
     hipLaunchKernelGGL(part_adjoint_kernel, dim3(static_cast<uint32_t>(grid)), dim3(512), 0, s, a);
     return hipGetLastError();
+}
+
+}  // namespace ara
+
+namespace ara {
+
+int64_t batched_scratch_bytes(int64_t C, int P, int n_layers, int64_t n_items, int64_t n_elts_total) {
+    const int64_t n_sb = static_cast<int64_t>(P) * kBase32;
+    int64_t b = 0;
+    b += sizeof(double) * C * n_layers;                  // o
+    b += sizeof(double) * C * n_layers;                  // compact
+    b += part_image_bytes(P) * n_layers;                 // images
+    b += sizeof(uint32_t) * n_sb * n_layers;             // superblock counts
+    b += 256;                                            // counter
+    b += sizeof(int2) * n_items + 256;
+    b += sizeof(BatchLayerDesc) * n_layers + sizeof(BatchFoldDesc) * n_layers + 512;
+    b += (sizeof(int32_t) + 2 * sizeof(double)) * n_elts_total + 512;
+    return b;
+}
+
+BatchedScratch carve_batched(void* scratch, int64_t C, int P, int n_layers, int64_t n_items, int64_t n_elts_total) {
+    char* p = static_cast<char*>(scratch);
+    const int64_t n_sb = static_cast<int64_t>(P) * kBase32;
+    BatchedScratch r;
+    r.o = reinterpret_cast<double*>(p);
+    p += sizeof(double) * C * n_layers;
+    r.compact = reinterpret_cast<double*>(p);
+    p += sizeof(double) * C * n_layers;
+    r.img = reinterpret_cast<uint8_t*>(p);
+    p += part_image_bytes(P) * n_layers;
+    r.sb_count = reinterpret_cast<uint32_t*>(p);
+    p += sizeof(uint32_t) * n_sb * n_layers;
+    r.counter = reinterpret_cast<uint32_t*>(p);
+    p += 256;
+    r.items = reinterpret_cast<int2*>(p);
+    p += sizeof(int2) * n_items + 256;
+    r.layers = reinterpret_cast<BatchLayerDesc*>(p);
+    p += sizeof(BatchLayerDesc) * n_layers;
+    r.fold = reinterpret_cast<BatchFoldDesc*>(p);
+    p += sizeof(BatchFoldDesc) * n_layers + 512;
+    r.R = reinterpret_cast<double*>(p);
+    p += sizeof(double) * n_elts_total;
+    r.Lim = reinterpret_cast<double*>(p);
+    p += sizeof(double) * n_elts_total;
+    r.idx = reinterpret_cast<int32_t*>(p);
+    return r;
+}
+
+hipError_t launch_batched(const PartLayout& lay, int64_t N, int64_t C, const double* elts, int n_layers,
+                          const BatchedScratch& b, int64_t n_items, double* ylt, int n_cu, hipStream_t s,
+                          hipEvent_t pass_start, hipEvent_t pass_stop) {
+    hipError_t e;
+    const int P = lay.P;
+    const int64_t n_sb = static_cast<int64_t>(P) * kBase32;
+    const int64_t img_stride = part_image_bytes(P);
+    hipLaunchKernelGGL(batched_fold_kernel, dim3(static_cast<uint32_t>((C + 255) / 256), n_layers), dim3(256), 0, s,
+                       elts, C, b.fold, b.idx, b.R, b.Lim, b.o);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(part_image_kernel, dim3(static_cast<uint32_t>(n_sb), n_layers), dim3(256), 0, s, b.o, C, b.img,
+                       b.sb_count, C, img_stride, n_sb);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(superblock_scan_kernel, dim3(1, n_layers), dim3(1024), 0, s, b.sb_count, n_sb, b.img,
+                       img_stride);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(compact_kernel, dim3(static_cast<uint32_t>(n_sb), n_layers), dim3(256), 0, s, b.o, C, b.img,
+                       b.compact, C, img_stride);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(64), 0, s, b.counter, int64_t(1), 0u);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    BatchedPassArgs a{};
+    a.pids = lay.pids;
+    a.seg_rel = lay.seg_rel;
+    a.tile_start = lay.tile_start;
+    a.img = b.img;
+    a.img_stride = img_stride;
+    a.compact = b.compact;
+    a.C = C;
+    a.N = N;
+    a.P = P;
+    a.T = lay.T;
+    a.items = b.items;
+    a.n_items = static_cast<int32_t>(n_items);
+    a.layers = b.layers;
+    a.ylt = ylt;
+    a.item_counter = b.counter;
+    int64_t grid = n_items < int64_t(n_cu) * 2 ? n_items : int64_t(n_cu) * 2;
+    if (grid < 1) grid = 1;
+    if (pass_start && (e = hipEventRecord(pass_start, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(batched_pass_kernel, dim3(static_cast<uint32_t>(grid)), dim3(512), 0, s, a);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (pass_stop && (e = hipEventRecord(pass_stop, s)) != hipSuccess) return e;
+    return hipSuccess;
 }
 
 }  // namespace ara

@@ -472,3 +472,45 @@ def test_autograd_function_matches_oracle(ara, cfg0):
     assert np.array_equal(theta.grad.numpy(), expect)
     rmean, _, rtvar = oracle.risk_metrics(ref, [0.99])
     assert abs(mean.item() - rmean) <= REL * rmean and abs(tvar.item() - rtvar[0]) <= REL * rtvar[0]
+
+
+def test_batched_layers_persistent_and_graph(ara):
+    """Layers with uneven ELT counts and trial ranges in one persistent launch
+    (and as a replayed HIP graph) equal the per-layer runs and the oracle."""
+    import torch
+    C = 1_100_000
+    yet = make_yet(3000, 120.0, C, seed=51)
+    pool = make_elt_pool(40, C, 30_000, seed=52)
+    rng = np.random.default_rng(53)
+    layers = []
+    for k in range(7):
+        J = int(rng.integers(1, 33))
+        idx = rng.choice(40, size=J, replace=False).astype(np.int32)
+        n = int(rng.integers(1, yet.n_trials + 1))
+        b = int(rng.integers(0, yet.n_trials - n + 1))
+        layers.append(Layer(idx, 1500.0 + 100 * k, 5.0e5, 2.0e4 * (k + 1), 6.0e5, b, n))
+    specs = [_spec(ara, l, pool, yet) for l in layers]
+    tables = ara.create_tables(yet.offsets, yet.ids, pool.losses)
+    refs = [oracle.run_layer(yet, pool, l)[0] for l in layers]
+    ref = np.concatenate(refs)
+    eager = ara.run_layers(tables, specs)
+    per = ara.run_layers(tables, specs, flags=ara.ARA_PER_LAYER)
+    ok, worst = _close(eager, ref)
+    assert ok, worst
+    assert np.array_equal(eager, per)
+    out = torch.empty(ref.shape[0], dtype=torch.float64, device="cuda")
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        for rep in range(4):
+            # change terms between replays: same shape, same graph
+            scaled = [s.with_theta(s.theta() * (1.0 + 0.01 * rep)) for s in specs]
+            expect = ara.run_layers(tables, scaled)                    # eager, host output
+            out.fill_(-1.0)
+            ara.run_layers(tables, scaled, out=out, flags=ara.ARA_GRAPH, stream=stream)
+            stream.synchronize()
+            got = out.cpu().numpy()
+            assert np.array_equal(got, expect), rep
+            _ = torch.ones(1000, device="cuda").sum().item()          # unrelated eager work between replays
+    with pytest.raises(ara.AraError):
+        ara.run_layers(tables, specs, flags=ara.ARA_GRAPH)            # host output refused
+    tables.close()
