@@ -106,12 +106,13 @@ typedef struct ara_layer {
  * Launch-shape knobs picked by the autotuner; zero fields mean "default".
  */
 typedef struct ara_tuning {
-    int32_t block_threads;          /* threads per workgroup of the trial pass (multiple of 64) */
-    int32_t waves_per_trial_log2;   /* unused (0) = one wave per trial */
-    int32_t lanes_per_trial;        /* 64 (one wave per trial), 32, 16 or 8 lanes per trial */
-    int32_t blocks_per_cu;          /* resident workgroups per CU the grid is sized for */
-    int32_t fold_events_per_thread; /* catalogue events per thread in the fold kernel: 1, 2, 4 */
-    int32_t reserved[3];
+    int32_t block_threads;          /* reserved (0); workgroup sizes are fixed per kernel */
+    int32_t part_lanes_per_trial;   /* partitioned pass: lanes per trial group, 8/16/32/64 (0 = 16) */
+    int32_t lanes_per_trial;        /* time-ordered pass: 64 (one wave per trial), 32, 16 or 8 */
+    int32_t blocks_per_cu;          /* time-ordered pass: resident workgroups per CU (0 = 8) */
+    int32_t fold_events_per_thread; /* reserved (0) */
+    int32_t schedule;               /* batched pass work order: 0 = decreasing cost, 1 = layer-major */
+    int32_t reserved[2];
 } ara_tuning;
 
 /*

@@ -82,11 +82,12 @@ class CLayer(ctypes.Structure):
 class CTuning(ctypes.Structure):
     _fields_ = [
         ("block_threads", ctypes.c_int32),
-        ("waves_per_trial_log2", ctypes.c_int32),
+        ("part_lanes_per_trial", ctypes.c_int32),
         ("lanes_per_trial", ctypes.c_int32),
         ("blocks_per_cu", ctypes.c_int32),
         ("fold_events_per_thread", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 3),
+        ("schedule", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 2),
     ]
 
 
@@ -416,17 +417,20 @@ def footprint(tables: Tables, layers: Sequence[LayerSpec], flags: int = 0) -> in
     return int(v.value)
 
 
+TUNING_FIELDS = ("part_lanes_per_trial", "lanes_per_trial", "blocks_per_cu", "schedule")
+
+
 def set_tuning(tables: Tables, lanes_per_trial: int = 0, blocks_per_cu: int = 0,
-               block_threads: int = 0, fold_events_per_thread: int = 0) -> None:
-    t = CTuning(block_threads, 0, lanes_per_trial, blocks_per_cu, fold_events_per_thread)
+               part_lanes_per_trial: int = 0, schedule: int = 0) -> None:
+    """Launch-shape knobs for later calls on `tables` (0 = default)."""
+    t = CTuning(0, part_lanes_per_trial, lanes_per_trial, blocks_per_cu, 0, schedule)
     _check(lib().ara_set_tuning(tables.handle, ctypes.byref(t)))
 
 
 def get_tuning(tables: Tables) -> dict:
     t = CTuning()
     _check(lib().ara_get_tuning(tables.handle, ctypes.byref(t)))
-    return dict(block_threads=t.block_threads, lanes_per_trial=t.lanes_per_trial,
-                blocks_per_cu=t.blocks_per_cu, fold_events_per_thread=t.fold_events_per_thread)
+    return {k: int(getattr(t, k)) for k in TUNING_FIELDS}
 
 
 def kernel_stats(tables: Tables, kernel: int, reset: bool = False):

@@ -220,7 +220,8 @@ struct BatchPlan {
     std::vector<int64_t> key;
 };
 
-BatchPlan make_plan(const ara_tables* t, const std::vector<ara::LayerArgs>& L, const double* ylt_ptr) {
+BatchPlan make_plan(const ara_tables* t, const std::vector<ara::LayerArgs>& L, const double* ylt_ptr,
+                    int schedule) {
     BatchPlan b;
     const int T = t->parts.T;
     struct Cost {
@@ -250,7 +251,10 @@ BatchPlan make_plan(const ara_tables* t, const std::vector<ara::LayerArgs>& L, c
             costs.push_back({a1 - a0, static_cast<int>(l), tile});
         }
     }
-    std::stable_sort(costs.begin(), costs.end(), [](const Cost& x, const Cost& y) { return x.c > y.c; });
+    // schedule 0: decreasing cost (longest items first); 1: layer-major order
+    if (schedule == 0)
+        std::stable_sort(costs.begin(), costs.end(), [](const Cost& x, const Cost& y) { return x.c > y.c; });
+    b.key.push_back(schedule);
     b.items.reserve(costs.size());
     for (const auto& c : costs) b.items.push_back(make_int2(c.l, static_cast<int>(c.tile)));
     return b;
@@ -492,6 +496,10 @@ ara_status ara_set_tuning(ara_tables* t, const ara_tuning* tu) {
         v.lanes_per_trial != 32 && v.lanes_per_trial != 64)
         return fail(ARA_ERR_INVALID_ARG, "lanes_per_trial must be 8, 16, 32 or 64");
     if (v.blocks_per_cu < 0 || v.blocks_per_cu > 64) return fail(ARA_ERR_INVALID_ARG, "blocks_per_cu in [0, 64]");
+    if (v.part_lanes_per_trial != 0 && v.part_lanes_per_trial != 8 && v.part_lanes_per_trial != 16 &&
+        v.part_lanes_per_trial != 32 && v.part_lanes_per_trial != 64)
+        return fail(ARA_ERR_INVALID_ARG, "part_lanes_per_trial must be 8, 16, 32 or 64");
+    if (v.schedule < 0 || v.schedule > 1) return fail(ARA_ERR_INVALID_ARG, "schedule must be 0 or 1");
     std::lock_guard<std::mutex> g(t->mu);
     t->tuning = v;
     return ARA_OK;
@@ -590,7 +598,7 @@ ara_status ara_run_layers(ara_tables* t, const ara_layer* layers, int32_t n_laye
     if ((flags & ARA_GRAPH) && batched && (!dev_out || s == nullptr))
         return fail(ARA_ERR_INVALID_ARG, "ARA_GRAPH needs a device output and a non-null stream");
     if (batched) {
-        BatchPlan plan = make_plan(t, L, out);
+        BatchPlan plan = make_plan(t, L, out, tu.schedule);
         const int64_t n_items = static_cast<int64_t>(plan.items.size());
         const int64_t n_elts_total = static_cast<int64_t>(plan.idx.size());
         const int64_t sbytes = ara::batched_scratch_bytes(t->C, t->parts.P, n_layers, n_items, n_elts_total);
@@ -616,7 +624,7 @@ ara_status ara_run_layers(ara_tables* t, const ara_layer* layers, int32_t n_laye
                     return hip_fail(e, "graph capture");
                 }
                 hipError_t le = ara::launch_batched(t->parts, t->n_trials, t->C, t->elts, n_layers, bs, n_items, out,
-                                                    t->n_cu, s, nullptr, nullptr);
+                                                    t->n_cu, s, nullptr, nullptr, tu.part_lanes_per_trial);
                 e = hipStreamEndCapture(s, &ge->graph);
                 if (le != hipSuccess || e != hipSuccess ||
                     (e = hipGraphInstantiate(&ge->exec, ge->graph, nullptr, nullptr, 0)) != hipSuccess) {
@@ -646,7 +654,7 @@ ara_status ara_run_layers(ara_tables* t, const ara_layer* layers, int32_t n_laye
             }
             KernelTimer kt(t, s, prof, ARA_KERNEL_BATCHED);
             HIP_TRY(ara::launch_batched(t->parts, t->n_trials, t->C, t->elts, n_layers, bs, n_items, out, t->n_cu, s,
-                                        nullptr, nullptr),
+                                        nullptr, nullptr, tu.part_lanes_per_trial),
                     "batched pass");
             kt.done();
         }
@@ -672,7 +680,8 @@ ara_status ara_run_layers(ara_tables* t, const ara_layer* layers, int32_t n_laye
         }
         KernelTimer kt(t, s, prof, ARA_KERNEL_TRIAL_PASS);
         if (use_parts)
-            HIP_TRY(ara::launch_part_pass(t->parts, t->n_trials, L[i], pbuf.p, a.ylt, a.S, t->n_cu, s),
+            HIP_TRY(ara::launch_part_pass(t->parts, t->n_trials, L[i], pbuf.p, a.ylt, a.S, t->n_cu, s,
+                                          tu.part_lanes_per_trial),
                     "partitioned trial pass");
         else
             HIP_TRY(ara::launch_trial_pass(a, L[i], literal, tu, t->n_cu, s), "trial pass");

@@ -294,13 +294,13 @@ void free_part_layout(PartLayout* L);
 int64_t part_scratch_bytes(int64_t C, int P);
 hipError_t launch_part_fold(const double* o, int64_t C, int P, void* scratch, hipStream_t s);
 hipError_t launch_part_pass(const PartLayout& lay, int64_t N, const LayerArgs& L, void* scratch, double* ylt,
-                            double* S, int n_cu, hipStream_t s);
+                            double* S, int n_cu, hipStream_t s, int lpt);
 
 int64_t batched_scratch_bytes(int64_t C, int P, int n_layers, int64_t n_items, int64_t n_elts_total);
 BatchedScratch carve_batched(void* scratch, int64_t C, int P, int n_layers, int64_t n_items, int64_t n_elts_total);
 hipError_t launch_batched(const PartLayout& lay, int64_t N, int64_t C, const double* elts, int n_layers,
                           const BatchedScratch& b, int64_t n_items, double* ylt, int n_cu, hipStream_t s,
-                          hipEvent_t pass_start, hipEvent_t pass_stop);
+                          hipEvent_t pass_start, hipEvent_t pass_stop, int lpt);
 
 // metrics: results[0] = mean, results[1 + 2q] = PML_q, results[2 + 2q] = TVaR_q
 int64_t metrics_scratch_bytes(int n_probs);

@@ -275,15 +275,17 @@ struct PassLds {
 // One (layer, tile): every part image in turn, every trial of the tile inside
 // [t_lo, t_hi); writes YLT (and S) for those trials.  All threads of the
 // workgroup call it; it starts and ends with a barrier.
+template <int LPT>
 __device__ __forceinline__ void pass_tile(PassLds& sh, const uint32_t* __restrict__ pids,
                                           const uint32_t* __restrict__ seg_rel,
                                           const int64_t* __restrict__ tile_start, const uint8_t* __restrict__ img,
                                           const double* __restrict__ compact, int64_t N, int P, int T, int64_t tile,
                                           int64_t t_lo, int64_t t_hi, double aggR, double aggL,
                                           double* __restrict__ ylt, double* __restrict__ S_out) {
-    const int lane = threadIdx.x & 63;
-    const int lig = lane & 15;                                 // lane in its 16-lane group
-    const int slot = (threadIdx.x >> 6) * 4 + (lane >> 4);    // 32 groups per workgroup
+    static_assert(LPT == 8 || LPT == 16 || LPT == 32 || LPT == 64, "lanes per trial");
+    const int lig = threadIdx.x & (LPT - 1);                   // lane in its group
+    const int slot = threadIdx.x / LPT;                        // group index in the workgroup
+    const int n_slots = blockDim.x / LPT;
     const int64_t t0 = tile * T;
     const int Tk = static_cast<int>(N - t0 < T ? N - t0 : T);
     const int64_t sbase = tile * (static_cast<int64_t>(T) * P + 1);
@@ -307,13 +309,13 @@ __device__ __forceinline__ void pass_tile(PassLds& sh, const uint32_t* __restric
         }
         __syncthreads();
         const uint32_t pbase = static_cast<uint32_t>(static_cast<int64_t>(p) << kPartShift);
-        for (int i = slot; i < Tk; i += 32) {
+        for (int i = slot; i < Tk; i += n_slots) {
             const int64_t t = t0 + i;
             if (t < t_lo || t >= t_hi) continue;
             const uint32_t s = seg_rel[sbase + static_cast<int64_t>(p) * Tk + i];
             const uint32_t e = seg_rel[sbase + static_cast<int64_t>(p) * Tk + i + 1];
             double hi = 0.0, lo = 0.0;
-            for (uint32_t c = s + lig * 4; c < e; c += 64) {
+            for (uint32_t c = s + lig * 4; c < e; c += LPT * 4) {
                 const u32x4 v = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(tids + c));
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
@@ -329,7 +331,7 @@ __device__ __forceinline__ void pass_tile(PassLds& sh, const uint32_t* __restric
                     }
                 }
             }
-            group_reduce_dd(hi, lo, 16);
+            group_reduce_dd(hi, lo, LPT);
             if (lig == 0) {
                 double h = sh.acc_hi[i], l = sh.acc_lo[i];
                 dd_merge(h, l, hi, lo);
@@ -349,6 +351,7 @@ __device__ __forceinline__ void pass_tile(PassLds& sh, const uint32_t* __restric
     __syncthreads();
 }
 
+template <int LPT>
 __global__ __launch_bounds__(512) void part_pass_kernel(PartPassArgs a) {
     __shared__ __attribute__((aligned(16))) PassLds sh;
     for (;;) {
@@ -356,13 +359,14 @@ __global__ __launch_bounds__(512) void part_pass_kernel(PartPassArgs a) {
         __syncthreads();
         const int64_t tile = sh.tile;
         if (tile >= a.last_tile) break;
-        pass_tile(sh, a.pids, a.seg_rel, a.tile_start, a.img, a.compact, a.N, a.P, a.T, tile, a.t_lo, a.t_hi,
-                  a.aggR, a.aggL, a.ylt, a.S);
+        pass_tile<LPT>(sh, a.pids, a.seg_rel, a.tile_start, a.img, a.compact, a.N, a.P, a.T, tile, a.t_lo,
+                       a.t_hi, a.aggR, a.aggL, a.ylt, a.S);
     }
 }
 
 // The persistent multi-layer pass: one grid drains a work list of
 // (layer, tile) items, ordered by decreasing cost, through an atomic counter.
+template <int LPT>
 __global__ __launch_bounds__(512) void batched_pass_kernel(BatchedPassArgs a) {
     __shared__ __attribute__((aligned(16))) PassLds sh;
     for (;;) {
@@ -372,8 +376,8 @@ __global__ __launch_bounds__(512) void batched_pass_kernel(BatchedPassArgs a) {
         if (it >= a.n_items) break;
         const int2 w = a.items[it];
         const BatchLayerDesc d = a.layers[w.x];
-        pass_tile(sh, a.pids, a.seg_rel, a.tile_start, a.img + w.x * a.img_stride, a.compact + w.x * a.C, a.N,
-                  a.P, a.T, w.y, d.t_lo, d.t_hi, d.aggR, d.aggL, a.ylt + d.out_off, nullptr);
+        pass_tile<LPT>(sh, a.pids, a.seg_rel, a.tile_start, a.img + w.x * a.img_stride, a.compact + w.x * a.C,
+                       a.N, a.P, a.T, w.y, d.t_lo, d.t_hi, d.aggR, d.aggL, a.ylt + d.out_off, nullptr);
     }
 }
 
@@ -451,6 +455,26 @@ __global__ __launch_bounds__(512) void part_adjoint_kernel(PartAdjArgs a) {
         }
         __syncthreads();
     }
+}
+
+hipError_t launch_part_pass_lpt(int lpt, int grid, const PartPassArgs& a, hipStream_t s) {
+    switch (lpt) {
+        case 8: hipLaunchKernelGGL(part_pass_kernel<8>, dim3(grid), dim3(512), 0, s, a); break;
+        case 32: hipLaunchKernelGGL(part_pass_kernel<32>, dim3(grid), dim3(512), 0, s, a); break;
+        case 64: hipLaunchKernelGGL(part_pass_kernel<64>, dim3(grid), dim3(512), 0, s, a); break;
+        default: hipLaunchKernelGGL(part_pass_kernel<16>, dim3(grid), dim3(512), 0, s, a); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_batched_pass_lpt(int lpt, int grid, const BatchedPassArgs& a, hipStream_t s) {
+    switch (lpt) {
+        case 8: hipLaunchKernelGGL(batched_pass_kernel<8>, dim3(grid), dim3(512), 0, s, a); break;
+        case 32: hipLaunchKernelGGL(batched_pass_kernel<32>, dim3(grid), dim3(512), 0, s, a); break;
+        case 64: hipLaunchKernelGGL(batched_pass_kernel<64>, dim3(grid), dim3(512), 0, s, a); break;
+        default: hipLaunchKernelGGL(batched_pass_kernel<16>, dim3(grid), dim3(512), 0, s, a); break;
+    }
+    return hipGetLastError();
 }
 
 }  // namespace
@@ -580,7 +604,7 @@ hipError_t launch_part_fold(const double* o, int64_t C, int P, void* scratch, hi
 }
 
 hipError_t launch_part_pass(const PartLayout& lay, int64_t N, const LayerArgs& L, void* scratch, double* ylt,
-                            double* S, int n_cu, hipStream_t s) {
+                            double* S, int n_cu, hipStream_t s, int lpt) {
     if (L.trial_count <= 0) return hipSuccess;
     const int P = lay.P;
     PartScratch ps = carve_parts(scratch, P);
@@ -607,8 +631,7 @@ hipError_t launch_part_pass(const PartLayout& lay, int64_t N, const LayerArgs& L
     a.tile_counter = ps.counter;
     int64_t grid = a.last_tile - a.first_tile;
     if (grid > int64_t(n_cu) * 2) grid = int64_t(n_cu) * 2;
-    hipLaunchKernelGGL(part_pass_kernel, dim3(static_cast<uint32_t>(grid)), dim3(512), 0, s, a);
-    return hipGetLastError();
+    return launch_part_pass_lpt(lpt, static_cast<int>(grid), a, s);
 }
 
 }  // namespace ara
@@ -697,7 +720,7 @@ BatchedScratch carve_batched(void* scratch, int64_t C, int P, int n_layers, int6
 
 hipError_t launch_batched(const PartLayout& lay, int64_t N, int64_t C, const double* elts, int n_layers,
                           const BatchedScratch& b, int64_t n_items, double* ylt, int n_cu, hipStream_t s,
-                          hipEvent_t pass_start, hipEvent_t pass_stop) {
+                          hipEvent_t pass_start, hipEvent_t pass_stop, int lpt) {
     hipError_t e;
     const int P = lay.P;
     const int64_t n_sb = static_cast<int64_t>(P) * kBase32;
@@ -735,8 +758,7 @@ hipError_t launch_batched(const PartLayout& lay, int64_t N, int64_t C, const dou
     int64_t grid = n_items < int64_t(n_cu) * 2 ? n_items : int64_t(n_cu) * 2;
     if (grid < 1) grid = 1;
     if (pass_start && (e = hipEventRecord(pass_start, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(batched_pass_kernel, dim3(static_cast<uint32_t>(grid)), dim3(512), 0, s, a);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = launch_batched_pass_lpt(lpt, static_cast<int>(grid), a, s)) != hipSuccess) return e;
     if (pass_stop && (e = hipEventRecord(pass_stop, s)) != hipSuccess) return e;
     return hipSuccess;
 }

@@ -514,3 +514,24 @@ def test_batched_layers_persistent_and_graph(ara):
     with pytest.raises(ara.AraError):
         ara.run_layers(tables, specs, flags=ara.ARA_GRAPH)            # host output refused
     tables.close()
+
+
+def test_autotuner_choices_keep_parity(ara, tmp_path):
+    import torch
+    from paper_1606_04473_amd import autotune
+    w = make_config("config0")
+    yet, pool, layer = w.yet, w.pool, w.layers[0]
+    tables = ara.create_tables(yet.offsets, yet.ids, pool.losses)
+    spec = _spec(ara, layer, pool, yet)
+    ref, _ = oracle.run_layer(yet, pool, layer)
+    out = torch.empty(yet.n_trials, dtype=torch.float64, device="cuda")
+    res = autotune.tune(tables, [spec], out, repeats=2)
+    assert len(res["timings"]) == 4 and res["best_ms"] > 0
+    for ms, knobs in res["timings"]:
+        ara.set_tuning(tables, **knobs)
+        ylt = ara.run_layers(tables, [spec])
+        ok, worst = _close(ylt, ref)
+        assert ok, (knobs, worst)
+    best = autotune.tuned(tables, [spec], out, path=str(tmp_path / "c.json"), repeats=1)
+    assert ara.get_tuning(tables)["part_lanes_per_trial"] == best["part_lanes_per_trial"]
+    tables.close()

@@ -108,3 +108,23 @@ def test_alone_equals_mix_all_modes():
                 if r.error is None:
                     assert r.metrics == ref[r.rid], (mode, r.rid)
     base.close()
+
+
+def test_autotune_cache_and_shape_class(tmp_path):
+    from paper_1606_04473_amd import autotune
+
+    class T:
+        n_events, n_trials, catalogue_size = 1_000_000_000, 1_000_000, 2_000_000
+
+    class L:
+        def __init__(self, J, n):
+            self.n_elts, self.trial_count = J, n
+
+    one = autotune.shape_class(T, [L(16, 1_000_000)])
+    many = autotune.shape_class(T, [L(16, 500_000)] * 64)
+    assert one.startswith("P4-ev10-") and one.endswith("-one-J4") and "-many-" in many
+    assert len(autotune.candidates(1)) == 4 and len(autotune.candidates(64)) == 6
+    path = str(tmp_path / "cache.json")
+    assert autotune.load_cache(path) == {}
+    autotune.save_cache({"k": {"part_lanes_per_trial": 32}}, path)
+    assert autotune.load_cache(path) == {"k": {"part_lanes_per_trial": 32}}
