@@ -45,7 +45,22 @@ def parse():
     ap.add_argument("--no-backward", action="store_true")
     ap.add_argument("--literal-steps", type=int, default=0,
                     help="also time the literal per-ELT lookup kernel this many times")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy (reference for counter scaling)")
     return ap.parse_args()
+
+
+def copy_probe() -> None:
+    """A plain copy of known size: 1 GiB read + 1 GiB written per launch.
+    Hardware counters of this launch scale those of the trial pass."""
+    import torch
+    n = (1 << 30) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": n * 8, "launches": 3}), flush=True)
 
 
 def measured_traffic():
@@ -63,6 +78,9 @@ def measured_traffic():
 
 def main() -> None:
     args = parse()
+    if args.copy_probe:
+        copy_probe()
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(json.dumps({"error": "this build measures one GPU; the analysis shards by trials "
@@ -128,7 +146,7 @@ def main() -> None:
     achieved = tp_bytes / (tp_avg / 1e3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
-                "kernel": "trial_pass_kernel<64,false,false>",
+                "kernel": "part_pass_kernel",
                 "algorithmic_bytes_per_launch": tp_bytes, "avg_launch_ms": round(tp_avg, 5)}
 
     extra = {"pct_hbm_step": round(step_bytes / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
