@@ -27,7 +27,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "trial_pass_config1_traffic.json")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_1606_04473_amd", "csrc", "kernels_trial.hip")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1606_04473_amd", "csrc", "kernels_parts.hip")
 
 
 def log(msg: str) -> None:
