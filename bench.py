@@ -45,6 +45,9 @@ def parse():
     ap.add_argument("--no-backward", action="store_true")
     ap.add_argument("--literal-steps", type=int, default=0,
                     help="also time the literal per-ELT lookup kernel this many times")
+    ap.add_argument("--no-serving", action="store_true",
+                    help="skip the multi-tenant serving study (config 4)")
+    ap.add_argument("--serving-per-tenant", type=int, default=6)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (reference for counter scaling)")
     return ap.parse_args()
@@ -209,6 +212,22 @@ def main() -> None:
                          f"{dt:.1f} s, exact-sum FP64 C oracle"}
         log(f"cpu oracle: {cpu['value']:.3e} lookups/s on {cpu['cores']} threads ({dt:.1f}s)")
 
+    tables.close()
+    del out, res
+    serving = None
+    if not args.no_serving:
+        from paper_1606_04473_amd import serving as srv
+        t1 = time.time()
+        w4 = make_config("config4")
+        base = ara.create_tables(w4.yet.offsets, w4.yet.ids, w4.pool.losses)
+        library = [ara.LayerSpec.from_layer(l, w4.pool, w4.yet.n_trials) for l in w4.layers]
+        log(f"config4 tables resident ({base.bytes() / 1e9:.2f} GB) in {time.time() - t1:.1f}s")
+        serving = srv.run_tenant_study(base, w4.yet.offsets, w4.yet.ids, library, n_tenants=8,
+                                       per_tenant=args.serving_per_tenant, log=log)
+        base.close()
+        extra["tenant_p99_ms"] = serving["concurrent_8t"]["p99_ms"]
+        extra["tenant_p99_ms_single_tenant"] = serving["concurrent_1t"]["p99_ms"]
+
     line = {
         "metric": "event-ELT lookups/s + % HBM peak (1M×1000 YET); grad/fwd time; tenant p99",
         "value": value,
@@ -230,7 +249,8 @@ def main() -> None:
         "cpu_baseline": cpu,
     }
     line.update(extra)
-    tables.close()
+    if serving is not None:
+        line["serving"] = serving
     print(json.dumps(line), flush=True)
 
 

@@ -168,6 +168,13 @@ def summarize(results: Sequence[Result], wall: float) -> Dict[str, float]:
 # the GPU server
 # ---------------------------------------------------------------------------
 
+def pin_ids(ids: np.ndarray):
+    """Event IDs in pinned host memory (as int32 bit patterns), the source of
+    every shipped request slice."""
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(ids, dtype=np.uint32).view(np.int32)).pin_memory()
+
+
 class Server:
     """Runs requests for n_tenants tenants on one GPU.
 
@@ -178,7 +185,7 @@ class Server:
     """
 
     def __init__(self, base, offsets: np.ndarray, ids: np.ndarray, library, n_tenants: int,
-                 mode: str, budget_bytes: int, probs=(0.99,)):
+                 mode: str, budget_bytes: int, probs=(0.99,), pinned_ids=None):
         import torch
         from . import ara
         if mode not in MODES:
@@ -195,9 +202,9 @@ class Server:
         self.transfer_token = threading.Lock()
         self.device = torch.device("cuda", torch.cuda.current_device())
         self.streams = [torch.cuda.Stream() for _ in range(n_tenants)]
-        self.host_ids = None
-        if mode != "resident":
-            self.host_ids = torch.from_numpy(np.ascontiguousarray(ids, dtype=np.uint32).view(np.int32)).pin_memory()
+        self.host_ids = pinned_ids
+        if mode != "resident" and self.host_ids is None:
+            self.host_ids = pin_ids(ids)
 
     def footprint(self, req: Request) -> int:
         n_ev = int(self.offsets[req.trial_begin + req.n_trials] - self.offsets[req.trial_begin])
@@ -293,3 +300,37 @@ class Server:
         self.torch.cuda.synchronize()
         self.wall = time.perf_counter() - t0
         return [results[r.rid] for r in requests]
+
+
+def run_tenant_study(base, offsets, ids, library, n_tenants: int = 8, per_tenant: int = 6,
+                     seed: int = 160604478, budget_bytes: int = 160 << 30, probs=(0.99,),
+                     load: float = 0.7, modes: Sequence[str] = ("concurrent", "sequential", "resident"),
+                     log=None) -> Dict[str, object]:
+    """Config-4 study: requests with Poisson arrivals at `load` times the
+    single-tenant capacity, served by n_tenants tenants in each transfer mode
+    and by one tenant; p50/p99 latency and throughput for each."""
+    n_yet = int(offsets.shape[0] - 1)
+    pinned = pin_ids(ids)
+    # capacity: one tenant, requests back to back, shipped concurrently
+    probe = make_requests(1, 6, 0.0, n_yet, len(library), seed=seed + 77)
+    for r in probe:
+        r.arrival = 0.0
+    srv = Server(base, offsets, ids, library, 1, "concurrent", budget_bytes, probs, pinned)
+    srv.run(probe[:1], 0.0)                                   # warm-up
+    res = srv.run(probe, 0.0)
+    service = srv.wall / max(len(res), 1)
+    rate_total = load / service
+    reqs = make_requests(n_tenants, per_tenant, rate_total / n_tenants, n_yet, len(library), seed=seed)
+    out: Dict[str, object] = {"service_ms_one_tenant": service * 1e3, "arrival_rate_req_s": rate_total,
+                              "load": load, "tenants": n_tenants, "requests": len(reqs)}
+    for mode in modes:
+        for k in (1, n_tenants):
+            s = Server(base, offsets, ids, library, k, mode, budget_bytes, probs, pinned)
+            r = s.run(reqs, 1.0)
+            summ = summarize(r, s.wall)
+            summ["admission_peak_bytes"] = s.admission.peak
+            out[f"{mode}_{k}t"] = summ
+            if log:
+                log(f"serving {mode} tenants={k}: p50 {summ['p50_ms']:.1f} ms p99 {summ['p99_ms']:.1f} ms "
+                    f"{summ['throughput_req_s']:.2f} req/s")
+    return out

@@ -90,10 +90,14 @@ def test_alone_equals_mix_all_modes():
     reqs = make_requests(4, 4, 200.0, yet.n_trials, len(library) - 1, seed=74, n_min=500, n_max=8000,
                          layers_max=4)
     reqs[5].layer_ids = reqs[5].layer_ids + [len(library) - 1]       # poisoned request
+    from paper_1606_04473_amd.serving import pin_ids
+    pinned = pin_ids(yet.ids)
     ref = None
     for mode in ("resident", "concurrent", "sequential"):
-        alone = Server(base, yet.offsets, yet.ids, library, 1, mode, budget_bytes=8 << 30).run(reqs, 0.0)
-        mix = Server(base, yet.offsets, yet.ids, library, 4, mode, budget_bytes=8 << 30).run(reqs, 1.0)
+        alone = Server(base, yet.offsets, yet.ids, library, 1, mode, budget_bytes=8 << 30,
+                       pinned_ids=pinned).run(reqs, 0.0)
+        mix = Server(base, yet.offsets, yet.ids, library, 4, mode, budget_bytes=8 << 30,
+                     pinned_ids=pinned).run(reqs, 1.0)
         for a, m in zip(alone, mix):
             assert (a.error is None) == (m.error is None), (mode, a.rid, a.error, m.error)
             if a.rid == reqs[5].rid:
