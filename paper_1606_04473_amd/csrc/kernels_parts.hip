@@ -315,21 +315,37 @@ __device__ __forceinline__ void pass_tile(PassLds& sh, const uint32_t* __restric
             const uint32_t s = seg_rel[sbase + static_cast<int64_t>(p) * Tk + i];
             const uint32_t e = seg_rel[sbase + static_cast<int64_t>(p) * Tk + i + 1];
             double hi = 0.0, lo = 0.0;
-            for (uint32_t c = s + lig * 4; c < e; c += LPT * 4) {
-                const u32x4 v = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(tids + c));
+            // kU loads per lane in flight, then the LDS tests, then the ranks
+            // of the hits, then every gather at once (a miss reads compact[0],
+            // one shared line per wave), then the sums
+            constexpr int kU = 4;
+            for (uint32_t c = s + lig * 4; c < e; c += LPT * 4 * kU) {
+                u32x4 v[kU];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const uint32_t el = v[q] - pbase;           // sentinel and foreign IDs fail the test
+                for (int u = 0; u < kU; ++u) {
+                    const uint32_t cu = c + u * LPT * 4;
+                    v[u] = cu < e ? __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(tids + cu))
+                                  : u32x4{kSentinel, kSentinel, kSentinel, kSentinel};
+                }
+                uint32_t r[kU * 4];
+#pragma unroll
+                for (int k = 0; k < kU * 4; ++k) {
+                    const uint32_t el = v[k >> 2][k & 3] - pbase;    // sentinel and foreign IDs fail the test
+                    r[k] = 0xFFFFFFFFu;
                     if (el < static_cast<uint32_t>(kPartSize)) {
                         const uint64_t word = sh.bm[el >> 6];
                         if ((word >> (el & 63)) & 1ull) {
-                            uint32_t r = sh.b32[el >> kSuperShift] + sh.r16[el >> 7];
-                            if ((el >> 6) & 1) r += __popcll(sh.bm[(el >> 6) - 1]);
-                            r += __popcll(word & ((1ull << (el & 63)) - 1ull));
-                            dd_add(hi, lo, compact[r]);
+                            uint32_t rk = sh.b32[el >> kSuperShift] + sh.r16[el >> 7];
+                            if ((el >> 6) & 1) rk += __popcll(sh.bm[(el >> 6) - 1]);
+                            r[k] = rk + __popcll(word & ((1ull << (el & 63)) - 1ull));
                         }
                     }
                 }
+                double val[kU * 4];
+#pragma unroll
+                for (int k = 0; k < kU * 4; ++k) val[k] = compact[r[k] == 0xFFFFFFFFu ? 0u : r[k]];
+#pragma unroll
+                for (int k = 0; k < kU * 4; ++k) dd_add(hi, lo, r[k] == 0xFFFFFFFFu ? 0.0 : val[k]);
             }
             group_reduce_dd(hi, lo, LPT);
             if (lig == 0) {
@@ -440,14 +456,22 @@ __global__ __launch_bounds__(512) void part_adjoint_kernel(PartAdjArgs a) {
                     key > ts.v_bits ? ts.c_eq : (key == ts.v_bits ? ts.m - ts.c_gt : 0);
                 const uint32_t s = a.seg_rel[sbase + static_cast<int64_t>(p) * Tk + i];
                 const uint32_t e = a.seg_rel[sbase + static_cast<int64_t>(p) * Tk + i + 1];
-                for (uint32_t c = s + lig * 4; c < e; c += 64) {
-                    const u32x4 v = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(tids + c));
+                constexpr int kU = 4;
+                for (uint32_t c = s + lig * 4; c < e; c += 64 * kU) {
+                    u32x4 v[kU];
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const uint32_t el = v[q] - pbase;
+                    for (int u = 0; u < kU; ++u) {
+                        const uint32_t cu = c + u * 64;
+                        v[u] = cu < e ? __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(tids + cu))
+                                      : u32x4{kSentinel, kSentinel, kSentinel, kSentinel};
+                    }
+#pragma unroll
+                    for (int k = 0; k < kU * 4; ++k) {
+                        const uint32_t id = v[k >> 2][k & 3];
+                        const uint32_t el = id - pbase;
                         if (el < static_cast<uint32_t>(kPartSize) && ((bm[el >> 6] >> (el & 63)) & 1ull)) {
-                            atomicAdd(reinterpret_cast<unsigned long long*>(&a.w_mean[v[q]]), 1ull);
-                            if (wt) atomicAdd(reinterpret_cast<unsigned long long*>(&a.w_tvar[v[q]]), wt);
+                            atomicAdd(reinterpret_cast<unsigned long long*>(&a.w_mean[id]), 1ull);
+                            if (wt) atomicAdd(reinterpret_cast<unsigned long long*>(&a.w_tvar[id]), wt);
                         }
                     }
                 }

@@ -87,7 +87,30 @@ __global__ __launch_bounds__(256) void trial_pass_kernel(TrialPassArgs a, LayerA
         const int64_t e = a.offsets[t + 1];
         double hi = 0.0, lo = 0.0;
         const int64_t start = CKPT ? (b & ~int64_t(255)) : (b & ~int64_t(3));
-        for (int64_t c = start; c < e; c += kChunk) {
+        if constexpr (!CKPT) {
+            // kU chunks per lane in flight before any lookup
+            constexpr int kU = 4;
+            for (int64_t c = start; c < e; c += kChunk * kU) {
+                u32x4 v[kU];
+#pragma unroll
+                for (int u = 0; u < kU; ++u) {
+                    const int64_t base = c + u * kChunk + lig * 4;
+                    v[u] = base < e ? load_ids_nt(a.ids + base) : u32x4{0u, 0u, 0u, 0u};
+                }
+#pragma unroll
+                for (int u = 0; u < kU; ++u) {
+                    const int64_t base = c + u * kChunk + lig * 4;
+                    bool valid[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) valid[q] = (base + q >= b) && (base + q < e);
+                    double oq[4];
+                    occurrence_losses<LITERAL>(a, L, v[u], valid, oq);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) dd_add(hi, lo, oq[q]);
+                }
+            }
+        }
+        for (int64_t c = start; CKPT && c < e; c += kChunk) {
             const int64_t base = c + lig * 4;
             u32x4 v = {0u, 0u, 0u, 0u};
             if (base < e) v = load_ids_nt(a.ids + base);
