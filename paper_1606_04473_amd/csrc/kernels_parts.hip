@@ -309,51 +309,85 @@ __device__ __forceinline__ void pass_tile(PassLds& sh, const uint32_t* __restric
         }
         __syncthreads();
         const uint32_t pbase = static_cast<uint32_t>(static_cast<int64_t>(p) << kPartShift);
-        for (int i = slot; i < Tk; i += n_slots) {
+        // A group walks its trials' segments of this part in batches of
+        // LPT*4*kU IDs; the loads of the next batch are issued before the
+        // current batch is looked up, so HBM latency overlaps the LDS tests,
+        // the gathers and the sums.  Trials outside [t_lo, t_hi) have empty
+        // segments.
+        constexpr int kU = 4;
+        constexpr uint32_t kBatch = LPT * 4 * kU;
+        auto seg = [&](int i, uint32_t& sb, uint32_t& se) {
             const int64_t t = t0 + i;
-            if (t < t_lo || t >= t_hi) continue;
-            const uint32_t s = seg_rel[sbase + static_cast<int64_t>(p) * Tk + i];
-            const uint32_t e = seg_rel[sbase + static_cast<int64_t>(p) * Tk + i + 1];
-            double hi = 0.0, lo = 0.0;
-            // kU loads per lane in flight, then the LDS tests, then the ranks
-            // of the hits, then every gather at once (a miss reads compact[0],
-            // one shared line per wave), then the sums
-            constexpr int kU = 4;
-            for (uint32_t c = s + lig * 4; c < e; c += LPT * 4 * kU) {
-                u32x4 v[kU];
+            sb = seg_rel[sbase + static_cast<int64_t>(p) * Tk + i];
+            se = (t < t_lo || t >= t_hi) ? sb : seg_rel[sbase + static_cast<int64_t>(p) * Tk + i + 1];
+        };
+        auto load_batch = [&](uint32_t c, uint32_t e, u32x4* v) {
 #pragma unroll
-                for (int u = 0; u < kU; ++u) {
-                    const uint32_t cu = c + u * LPT * 4;
-                    v[u] = cu < e ? __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(tids + cu))
-                                  : u32x4{kSentinel, kSentinel, kSentinel, kSentinel};
+            for (int u = 0; u < kU; ++u) {
+                const uint32_t cu = c + lig * 4 + u * LPT * 4;
+                v[u] = cu < e ? __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(tids + cu))
+                              : u32x4{kSentinel, kSentinel, kSentinel, kSentinel};
+            }
+        };
+        int i = slot;
+        uint32_t cs = 0, ce = 0, c = 0;
+        u32x4 cur[kU], nxt[kU];
+        if (i < Tk) {
+            seg(i, cs, ce);
+            c = cs;
+            load_batch(c, ce, cur);
+        }
+        double hi = 0.0, lo = 0.0;
+        while (i < Tk) {
+            // coordinates of the next batch: the rest of this segment, or the
+            // group's next trial
+            int ni = i;
+            uint32_t ns = cs, ne = ce, nc = c + kBatch;
+            if (nc >= ce) {
+                ni = i + n_slots;
+                if (ni < Tk) {
+                    seg(ni, ns, ne);
+                    nc = ns;
                 }
-                uint32_t r[kU * 4];
+            }
+            if (ni < Tk) load_batch(nc, ne, nxt);
+            uint32_t r[kU * 4];
 #pragma unroll
-                for (int k = 0; k < kU * 4; ++k) {
-                    const uint32_t el = v[k >> 2][k & 3] - pbase;    // sentinel and foreign IDs fail the test
-                    r[k] = 0xFFFFFFFFu;
-                    if (el < static_cast<uint32_t>(kPartSize)) {
-                        const uint64_t word = sh.bm[el >> 6];
-                        if ((word >> (el & 63)) & 1ull) {
-                            uint32_t rk = sh.b32[el >> kSuperShift] + sh.r16[el >> 7];
-                            if ((el >> 6) & 1) rk += __popcll(sh.bm[(el >> 6) - 1]);
-                            r[k] = rk + __popcll(word & ((1ull << (el & 63)) - 1ull));
-                        }
+            for (int k = 0; k < kU * 4; ++k) {
+                const uint32_t el = cur[k >> 2][k & 3] - pbase;   // sentinel and foreign IDs fail the test
+                r[k] = 0xFFFFFFFFu;
+                if (el < static_cast<uint32_t>(kPartSize)) {
+                    const uint64_t word = sh.bm[el >> 6];
+                    if ((word >> (el & 63)) & 1ull) {
+                        uint32_t rk = sh.b32[el >> kSuperShift] + sh.r16[el >> 7];
+                        if ((el >> 6) & 1) rk += __popcll(sh.bm[(el >> 6) - 1]);
+                        r[k] = rk + __popcll(word & ((1ull << (el & 63)) - 1ull));
                     }
                 }
-                double val[kU * 4];
-#pragma unroll
-                for (int k = 0; k < kU * 4; ++k) val[k] = compact[r[k] == 0xFFFFFFFFu ? 0u : r[k]];
-#pragma unroll
-                for (int k = 0; k < kU * 4; ++k) dd_add(hi, lo, r[k] == 0xFFFFFFFFu ? 0.0 : val[k]);
             }
-            group_reduce_dd(hi, lo, LPT);
-            if (lig == 0) {
-                double h = sh.acc_hi[i], l = sh.acc_lo[i];
-                dd_merge(h, l, hi, lo);
-                sh.acc_hi[i] = h;
-                sh.acc_lo[i] = l;
+            double val[kU * 4];
+#pragma unroll
+            for (int k = 0; k < kU * 4; ++k) val[k] = compact[r[k] == 0xFFFFFFFFu ? 0u : r[k]];
+#pragma unroll
+            for (int k = 0; k < kU * 4; ++k) dd_add(hi, lo, r[k] == 0xFFFFFFFFu ? 0.0 : val[k]);
+            if (ni != i) {
+                // the trial's segment is done: group total into its accumulator
+                group_reduce_dd(hi, lo, LPT);
+                if (lig == 0) {
+                    double h = sh.acc_hi[i], l = sh.acc_lo[i];
+                    dd_merge(h, l, hi, lo);
+                    sh.acc_hi[i] = h;
+                    sh.acc_lo[i] = l;
+                }
+                hi = 0.0;
+                lo = 0.0;
             }
+            i = ni;
+            cs = ns;
+            ce = ne;
+            c = nc;
+#pragma unroll
+            for (int u = 0; u < kU; ++u) cur[u] = nxt[u];
         }
     }
     __syncthreads();
