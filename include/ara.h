@@ -112,7 +112,9 @@ typedef struct ara_tuning {
     int32_t blocks_per_cu;          /* time-ordered pass: resident workgroups per CU (0 = 8) */
     int32_t fold_events_per_thread; /* reserved (0) */
     int32_t schedule;               /* batched pass work order: 0 = decreasing cost, 1 = layer-major */
-    int32_t reserved[2];
+    int32_t pass_variant;           /* single-layer pass: 0 = XCD-affine dense gathers (each XCD
+                                       serves its own catalogue parts), 1 = LDS ranks + compact values */
+    int32_t reserved;
 } ara_tuning;
 
 /*
@@ -132,7 +134,7 @@ typedef struct ara_tuning {
  *
  * Besides the time-ordered CSR the library keeps, by default, a second copy
  * of the event IDs laid out for its trial pass: tiles of 256 consecutive
- * trials, inside a tile the catalogue's parts of 2^19 events one after the
+ * trials, inside a tile the catalogue's parts of 2^18 events one after the
  * other, inside a part each trial's events of that part in time order.  It
  * depends on the YET alone, so every layer run on the tables uses it.
  *   out            receives the handle; freed by ara_destroy_tables.

@@ -87,7 +87,8 @@ class CTuning(ctypes.Structure):
         ("blocks_per_cu", ctypes.c_int32),
         ("fold_events_per_thread", ctypes.c_int32),
         ("schedule", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 2),
+        ("pass_variant", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 
@@ -417,13 +418,13 @@ def footprint(tables: Tables, layers: Sequence[LayerSpec], flags: int = 0) -> in
     return int(v.value)
 
 
-TUNING_FIELDS = ("part_lanes_per_trial", "lanes_per_trial", "blocks_per_cu", "schedule")
+TUNING_FIELDS = ("part_lanes_per_trial", "lanes_per_trial", "blocks_per_cu", "schedule", "pass_variant")
 
 
 def set_tuning(tables: Tables, lanes_per_trial: int = 0, blocks_per_cu: int = 0,
-               part_lanes_per_trial: int = 0, schedule: int = 0) -> None:
+               part_lanes_per_trial: int = 0, schedule: int = 0, pass_variant: int = 0) -> None:
     """Launch-shape knobs for later calls on `tables` (0 = default)."""
-    t = CTuning(0, part_lanes_per_trial, lanes_per_trial, blocks_per_cu, 0, schedule)
+    t = CTuning(0, part_lanes_per_trial, lanes_per_trial, blocks_per_cu, 0, schedule, pass_variant)
     _check(lib().ara_set_tuning(tables.handle, ctypes.byref(t)))
 
 

@@ -30,16 +30,19 @@ def shape_class(tables: "ara.Tables", layers: Sequence["ara.LayerSpec"]) -> str:
     trials = sum(l.trial_count for l in layers) / max(n_layers, 1)
     mean_events = tables.n_events / max(tables.n_trials, 1)
     mean_j = sum(l.n_elts for l in layers) / max(n_layers, 1)
-    parts = (tables.catalogue_size + (1 << 19) - 1) >> 19
+    parts = (tables.catalogue_size + (1 << 18) - 1) >> 18
     b = lambda v: int(round(math.log2(max(v, 1.0))))  # noqa: E731
     layer_class = "one" if n_layers == 1 else ("few" if n_layers <= 8 else "many")
     return f"P{parts}-ev{b(mean_events)}-n{b(trials)}-{layer_class}-J{b(mean_j)}"
 
 
 def candidates(n_layers: int) -> List[Dict[str, int]]:
-    out = [dict(part_lanes_per_trial=lpt) for lpt in (8, 16, 32, 64)]
     if n_layers > 1:
+        out = [dict(part_lanes_per_trial=lpt) for lpt in (8, 16, 32, 64)]
         out += [dict(part_lanes_per_trial=lpt, schedule=1) for lpt in (16, 32)]
+        return out
+    out = [dict(part_lanes_per_trial=lpt) for lpt in (8, 16, 32)]
+    out += [dict(part_lanes_per_trial=16, pass_variant=1)]
     return out
 
 

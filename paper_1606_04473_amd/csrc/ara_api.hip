@@ -500,6 +500,7 @@ ara_status ara_set_tuning(ara_tables* t, const ara_tuning* tu) {
         v.part_lanes_per_trial != 32 && v.part_lanes_per_trial != 64)
         return fail(ARA_ERR_INVALID_ARG, "part_lanes_per_trial must be 8, 16, 32 or 64");
     if (v.schedule < 0 || v.schedule > 1) return fail(ARA_ERR_INVALID_ARG, "schedule must be 0 or 1");
+    if (v.pass_variant < 0 || v.pass_variant > 1) return fail(ARA_ERR_INVALID_ARG, "pass_variant must be 0 or 1");
     std::lock_guard<std::mutex> g(t->mu);
     t->tuning = v;
     return ARA_OK;
@@ -520,7 +521,11 @@ ara_status ara_footprint(const ara_tables* t, const ara_layer* layers, int32_t n
     for (int i = 0; i < n_layers; ++i) total += layers[i].trial_count;
     int64_t b = 0;
     if (!(flags & ARA_LITERAL)) b += sizeof(double) * t->C;            // occurrence losses
-    if (!(flags & ARA_LITERAL) && t->parts.P > 0) b += ara::part_scratch_bytes(t->C, t->parts.P);
+    if (!(flags & ARA_LITERAL) && t->parts.P > 0) {
+        int64_t most = 0;
+        for (int i = 0; i < n_layers; ++i) most = std::max(most, layers[i].trial_count);
+        b += ara::part_scratch_bytes(t->C, t->parts.P) + 16 * int64_t(t->parts.P) * most;
+    }
     if (!(flags & ARA_DEVICE_PTR)) b += sizeof(double) * total;       // staged output
     if (flags & (ARA_CHECKPOINT_S | ARA_CHECKPOINT_STRIDE)) b += 2 * sizeof(double) * total;
     if (flags & ARA_CHECKPOINT_STRIDE) b += sizeof(double) * (t->n_events / ara::kStride + 1);
@@ -566,8 +571,16 @@ ara_status ara_run_layers(ara_tables* t, const ara_layer* layers, int32_t n_laye
     if (!literal) HIP_TRY(obuf.alloc(sizeof(double) * t->C, s), "scratch for occurrence losses");
     // the partitioned pass serves plain runs; stride checkpoints need time order
     const bool use_parts = !literal && t->parts.P > 0 && !(flags & ARA_CHECKPOINT_STRIDE);
-    PoolBuffer pbuf;
+    PoolBuffer pbuf, xbuf;
     if (use_parts) HIP_TRY(pbuf.alloc(ara::part_scratch_bytes(t->C, t->parts.P), s), "scratch for part images");
+    // the XCD-affine pass (default) writes per-part partial sums; pass_variant 1
+    // selects the rank-based pass with the compact value array
+    const bool use_xcd = use_parts && tu.pass_variant == 0;
+    if (use_xcd) {
+        int64_t most = 0;
+        for (int i = 0; i < n_layers; ++i) most = std::max(most, L[i].trial_count);
+        HIP_TRY(xbuf.alloc(sizeof(double) * 2 * t->parts.P * (most > 0 ? most : 1), s), "scratch for partials");
+    }
     double* S_buf = nullptr;
     double* stride_buf = nullptr;
     std::unique_lock<std::mutex> ck_lock(t->mu, std::defer_lock);
@@ -674,12 +687,18 @@ ara_status ara_run_layers(ara_tables* t, const ara_layer* layers, int32_t n_laye
             KernelTimer kt(t, s, prof, ARA_KERNEL_FOLD);
             HIP_TRY(ara::launch_fold(t->elts, t->C, L[i], static_cast<double*>(obuf.p), tu, s), "fold");
             if (use_parts)
-                HIP_TRY(ara::launch_part_fold(static_cast<const double*>(obuf.p), t->C, t->parts.P, pbuf.p, s),
+                HIP_TRY(ara::launch_part_fold(static_cast<const double*>(obuf.p), t->C, t->parts.P, pbuf.p, s,
+                                              !use_xcd),
                         "part images");
             kt.done();
         }
         KernelTimer kt(t, s, prof, ARA_KERNEL_TRIAL_PASS);
-        if (use_parts)
+        if (use_xcd)
+            HIP_TRY(ara::launch_xcd_pass(t->parts, t->n_trials, L[i], pbuf.p, static_cast<const double*>(obuf.p),
+                                         static_cast<double*>(xbuf.p), a.ylt, a.S, t->n_cu, s,
+                                         tu.part_lanes_per_trial ? tu.part_lanes_per_trial : 8, nullptr),
+                    "XCD-affine trial pass");
+        else if (use_parts)
             HIP_TRY(ara::launch_part_pass(t->parts, t->n_trials, L[i], pbuf.p, a.ylt, a.S, t->n_cu, s,
                                           tu.part_lanes_per_trial),
                     "partitioned trial pass");
@@ -783,7 +802,8 @@ ara_status ara_backward(ara_tables* t, const ara_layer* layer, double tvar_p, do
         HIP_TRY(obuf.alloc(sizeof(double) * t->C, s), "scratch for occurrence losses");
         HIP_TRY(pbuf.alloc(ara::part_scratch_bytes(t->C, t->parts.P), s), "scratch for part images");
         HIP_TRY(ara::launch_fold(t->elts, t->C, L, static_cast<double*>(obuf.p), tu, s), "fold");
-        HIP_TRY(ara::launch_part_fold(static_cast<const double*>(obuf.p), t->C, t->parts.P, pbuf.p, s), "images");
+        HIP_TRY(ara::launch_part_fold(static_cast<const double*>(obuf.p), t->C, t->parts.P, pbuf.p, s, false),
+                "images");
     }
     HIP_TRY(ara::launch_adjoint(t->offsets, t->ids, t->elts, t->C, L, t->ck.S, t->ck.ylt, m, scratch.p, gm, gt,
                                 t->n_cu, s, use_parts ? &t->parts : nullptr, pbuf.p, t->n_trials),

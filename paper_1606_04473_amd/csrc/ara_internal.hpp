@@ -125,6 +125,25 @@ struct PartLayout {
     int64_t* tile_start = nullptr;  // [n_tiles + 1]
 };
 
+constexpr int kXcds = 8;           // gfx950 (MI355X): 8 XCDs, workgroups dispatched round-robin
+
+struct XcdPassArgs {
+    const uint32_t* pids;
+    const uint32_t* seg_rel;
+    const int64_t* tile_start;
+    const uint8_t* img;             // part images; the bitmap opens each
+    const double* o;                // dense occurrence losses [C]
+    int64_t N;
+    int P;
+    int T;
+    int64_t t_lo, t_hi;
+    int64_t first_tile, last_tile;
+    double* part_hi;                // [P][count]
+    double* part_lo;
+    uint32_t* counters;             // [P]
+    int n_xcd;
+};
+
 struct PartPassArgs {
     const uint32_t* pids;
     const uint32_t* seg_rel;
@@ -292,7 +311,10 @@ hipError_t build_part_layout(const int64_t* offsets, const uint32_t* ids, int64_
                              int n_cu, hipStream_t s, PartLayout* out);
 void free_part_layout(PartLayout* L);
 int64_t part_scratch_bytes(int64_t C, int P);
-hipError_t launch_part_fold(const double* o, int64_t C, int P, void* scratch, hipStream_t s);
+hipError_t launch_part_fold(const double* o, int64_t C, int P, void* scratch, hipStream_t s, bool with_ranks);
+hipError_t launch_xcd_pass(const PartLayout& lay, int64_t N, const LayerArgs& L, void* part_scratch,
+                           const double* o, double* partials, double* ylt, double* S, int n_cu, hipStream_t s,
+                           int lpt, hipEvent_t mid);
 hipError_t launch_part_pass(const PartLayout& lay, int64_t N, const LayerArgs& L, void* scratch, double* ylt,
                             double* S, int n_cu, hipStream_t s, int lpt);
 

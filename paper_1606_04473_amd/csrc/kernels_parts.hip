@@ -6,8 +6,8 @@
 // occurrence retention).  So the per-event question "is o(E) nonzero, and
 // where is its value" is answered from LDS:
 //
-//  * the catalogue is cut into parts of 2^19 events; for each part the fold
-//    builds a 74,240-byte image: a 64 KB bitmap of nonzero o(E), a 16-bit rank
+//  * the catalogue is cut into parts of 2^18 events; for each part the fold
+//    builds a 37,120-byte image: a 32 KB bitmap of nonzero o(E), a 16-bit rank
 //    per 128 events relative to its 4096-event superblock, and the global rank
 //    of each superblock; the nonzero values themselves go, in catalogue order,
 //    to a compact array small enough to stay in L2;
@@ -28,7 +28,7 @@ namespace ara {
 
 namespace {
 
-constexpr int kPartShift = 19;
+constexpr int kPartShift = 18;
 constexpr int64_t kPartSize = int64_t(1) << kPartShift;       // catalogue events per part
 constexpr int kWords = kPartSize / 64;                        // 8192 u64 bitmap words
 constexpr int kRank16 = kPartSize / 128;                      // 4096 u16
@@ -36,7 +36,7 @@ constexpr int kSuperShift = 12;
 constexpr int kSuper = 1 << kSuperShift;                      // 4096 events per superblock
 constexpr int kBase32 = kPartSize / kSuper;                   // 128 u32
 constexpr int64_t kImgBytes = int64_t(kWords) * 8 + int64_t(kRank16) * 2 + int64_t(kBase32) * 4;
-static_assert(kImgBytes == 74240, "part image layout");
+static_assert(kImgBytes == 37120, "part image layout");
 static_assert(kImgBytes % 16 == 0, "16-byte copies");
 constexpr int kTileMax = 256;                                 // trials per tile (LDS accumulators)
 constexpr uint32_t kSentinel = 0xFFFFFFFFu;
@@ -515,6 +515,136 @@ __global__ __launch_bounds__(512) void part_adjoint_kernel(PartAdjArgs a) {
     }
 }
 
+// XCD-affine pass.  Workgroups are dispatched to the 8 XCDs round-robin, so
+// workgroup b runs on XCD b % 8; each XCD serves its own catalogue parts
+// (part p on XCD p % 8).  A part's dense occurrence losses are 2 MB, so they
+// stay in that XCD's 4 MB L2 and a hit gathers o[E] directly, with no rank
+// arithmetic; the part's 32 KB bitmap is loaded into LDS once per part.  Each
+// (part, trial) double-double partial goes to HBM; xcd_combine_kernel adds
+// the parts of a trial in part order.
+template <int LPT>
+__global__ __launch_bounds__(512) void xcd_pass_kernel(XcdPassArgs a) {
+    __shared__ __attribute__((aligned(16))) uint64_t bm[kWords];
+    __shared__ int64_t s_tile;
+    static_assert(LPT == 8 || LPT == 16 || LPT == 32 || LPT == 64, "lanes per trial");
+    const int lig = threadIdx.x & (LPT - 1);
+    const int slot = threadIdx.x / LPT;
+    const int n_slots = blockDim.x / LPT;
+    const int x = static_cast<int>(blockIdx.x % a.n_xcd);
+    const int P = a.P;
+    const int p0 = P >= a.n_xcd ? x : x % P;
+    const int pstep = P >= a.n_xcd ? a.n_xcd : P;
+    const int64_t count = a.t_hi - a.t_lo;
+    constexpr int kU = 4;
+    constexpr uint32_t kBatch = LPT * 4 * kU;
+    for (int p = p0; p < P; p += pstep) {
+        __syncthreads();
+        {
+            const u32x4* src = reinterpret_cast<const u32x4*>(a.img + static_cast<int64_t>(p) * kImgBytes);
+            u32x4* dst = reinterpret_cast<u32x4*>(bm);
+            for (int k = threadIdx.x; k < kWords / 2; k += blockDim.x) dst[k] = src[k];
+        }
+        const uint32_t pbase = static_cast<uint32_t>(static_cast<int64_t>(p) << kPartShift);
+        const double* op = a.o + static_cast<int64_t>(p) * kPartSize;
+        for (;;) {
+            if (threadIdx.x == 0) s_tile = a.first_tile + atomicAdd(&a.counters[p], 1u);
+            __syncthreads();
+            const int64_t tile = s_tile;
+            if (tile >= a.last_tile) break;
+            const int64_t t0 = tile * a.T;
+            const int Tk = static_cast<int>(a.N - t0 < a.T ? a.N - t0 : a.T);
+            const int64_t sbase = tile * (static_cast<int64_t>(a.T) * P + 1);
+            const uint32_t* tids = a.pids + a.tile_start[tile];
+            auto seg = [&](int i, uint32_t& sb, uint32_t& se) {
+                const int64_t t = t0 + i;
+                sb = a.seg_rel[sbase + static_cast<int64_t>(p) * Tk + i];
+                se = (t < a.t_lo || t >= a.t_hi) ? sb : a.seg_rel[sbase + static_cast<int64_t>(p) * Tk + i + 1];
+            };
+            auto load_batch = [&](uint32_t c, uint32_t e, u32x4* v) {
+#pragma unroll
+                for (int u = 0; u < kU; ++u) {
+                    const uint32_t cu = c + lig * 4 + u * LPT * 4;
+                    v[u] = cu < e ? __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(tids + cu))
+                                  : u32x4{kSentinel, kSentinel, kSentinel, kSentinel};
+                }
+            };
+            int i = slot;
+            uint32_t cs = 0, ce = 0, c = 0;
+            u32x4 cur[kU], nxt[kU];
+            if (i < Tk) {
+                seg(i, cs, ce);
+                c = cs;
+                load_batch(c, ce, cur);
+            }
+            double hi = 0.0, lo = 0.0;
+            while (i < Tk) {
+                int ni = i;
+                uint32_t ns = cs, ne = ce, nc = c + kBatch;
+                if (nc >= ce) {
+                    ni = i + n_slots;
+                    if (ni < Tk) {
+                        seg(ni, ns, ne);
+                        nc = ns;
+                    }
+                }
+                if (ni < Tk) load_batch(nc, ne, nxt);
+                double val[kU * 4];
+                bool hit[kU * 4];
+#pragma unroll
+                for (int k = 0; k < kU * 4; ++k) {
+                    const uint32_t el = cur[k >> 2][k & 3] - pbase;   // sentinel and foreign IDs fail the test
+                    const bool in = el < static_cast<uint32_t>(kPartSize);
+                    const uint32_t ec = in ? el : 0u;
+                    hit[k] = in && ((bm[ec >> 6] >> (ec & 63)) & 1ull);
+                    val[k] = op[hit[k] ? ec : 0u];
+                }
+#pragma unroll
+                for (int k = 0; k < kU * 4; ++k) dd_add(hi, lo, hit[k] ? val[k] : 0.0);
+                if (ni != i) {
+                    group_reduce_dd(hi, lo, LPT);
+                    const int64_t t = t0 + i;
+                    if (lig == 0 && t >= a.t_lo && t < a.t_hi) {
+                        a.part_hi[static_cast<int64_t>(p) * count + (t - a.t_lo)] = hi;
+                        a.part_lo[static_cast<int64_t>(p) * count + (t - a.t_lo)] = lo;
+                    }
+                    hi = 0.0;
+                    lo = 0.0;
+                }
+                i = ni;
+                cs = ns;
+                ce = ne;
+                c = nc;
+#pragma unroll
+                for (int u = 0; u < kU; ++u) cur[u] = nxt[u];
+            }
+            __syncthreads();
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void xcd_combine_kernel(const double* __restrict__ part_hi,
+                                                          const double* __restrict__ part_lo, int P, int64_t count,
+                                                          double aggR, double aggL, double* __restrict__ ylt,
+                                                          double* __restrict__ S_out) {
+    const int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k >= count) return;
+    double hi = 0.0, lo = 0.0;
+    for (int p = 0; p < P; ++p) dd_merge(hi, lo, part_hi[p * count + k], part_lo[p * count + k]);
+    const double S = hi + lo;
+    ylt[k] = apply_terms(S, aggR, aggL);
+    if (S_out) S_out[k] = S;
+}
+
+hipError_t launch_xcd_pass_lpt(int lpt, int grid, const XcdPassArgs& a, hipStream_t s) {
+    switch (lpt) {
+        case 16: hipLaunchKernelGGL(xcd_pass_kernel<16>, dim3(grid), dim3(512), 0, s, a); break;
+        case 32: hipLaunchKernelGGL(xcd_pass_kernel<32>, dim3(grid), dim3(512), 0, s, a); break;
+        case 64: hipLaunchKernelGGL(xcd_pass_kernel<64>, dim3(grid), dim3(512), 0, s, a); break;
+        default: hipLaunchKernelGGL(xcd_pass_kernel<8>, dim3(grid), dim3(512), 0, s, a); break;
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_part_pass_lpt(int lpt, int grid, const PartPassArgs& a, hipStream_t s) {
     switch (lpt) {
         case 8: hipLaunchKernelGGL(part_pass_kernel<8>, dim3(grid), dim3(512), 0, s, a); break;
@@ -647,13 +777,14 @@ PartScratch carve_parts(void* scratch, int P) {
 }
 }  // namespace
 
-hipError_t launch_part_fold(const double* o, int64_t C, int P, void* scratch, hipStream_t s) {
+hipError_t launch_part_fold(const double* o, int64_t C, int P, void* scratch, hipStream_t s, bool with_ranks) {
     PartScratch ps = carve_parts(scratch, P);
     const int64_t n_sb = static_cast<int64_t>(P) * kBase32;
     hipError_t e;
     hipLaunchKernelGGL(part_image_kernel, dim3(static_cast<uint32_t>(n_sb)), dim3(256), 0, s, o, C, ps.img,
                        ps.sb_count, int64_t(0), int64_t(0), int64_t(0));
     if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (!with_ranks) return hipSuccess;
     hipLaunchKernelGGL(superblock_scan_kernel, dim3(1), dim3(1024), 0, s, ps.sb_count, n_sb, ps.img, int64_t(0));
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(compact_kernel, dim3(static_cast<uint32_t>(n_sb)), dim3(256), 0, s, o, C, ps.img, ps.compact,
@@ -819,6 +950,48 @@ hipError_t launch_batched(const PartLayout& lay, int64_t N, int64_t C, const dou
     if ((e = launch_batched_pass_lpt(lpt, static_cast<int>(grid), a, s)) != hipSuccess) return e;
     if (pass_stop && (e = hipEventRecord(pass_stop, s)) != hipSuccess) return e;
     return hipSuccess;
+}
+
+}  // namespace ara
+
+namespace ara {
+
+hipError_t launch_xcd_pass(const PartLayout& lay, int64_t N, const LayerArgs& L, void* part_scratch,
+                           const double* o, double* partials, double* ylt, double* S, int n_cu, hipStream_t s,
+                           int lpt, hipEvent_t mid) {
+    if (L.trial_count <= 0) return hipSuccess;
+    const int P = lay.P;
+    PartScratch ps = carve_parts(part_scratch, P);
+    hipError_t e;
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(64), 0, s, ps.counter, int64_t(P), 0u);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    XcdPassArgs a{};
+    a.pids = lay.pids;
+    a.seg_rel = lay.seg_rel;
+    a.tile_start = lay.tile_start;
+    a.img = ps.img;
+    a.o = o;
+    a.N = N;
+    a.P = P;
+    a.T = lay.T;
+    a.t_lo = L.trial_begin;
+    a.t_hi = L.trial_begin + L.trial_count;
+    a.first_tile = L.trial_begin / lay.T;
+    a.last_tile = (a.t_hi + lay.T - 1) / lay.T;
+    a.part_hi = partials;
+    a.part_lo = partials + static_cast<int64_t>(P) * L.trial_count;
+    a.counters = ps.counter;
+    a.n_xcd = kXcds;
+    // two workgroups per CU, a multiple of the XCD count so every XCD gets the same share
+    int64_t grid = int64_t(n_cu) * 2;
+    grid -= grid % kXcds;
+    if (grid < kXcds) grid = kXcds;
+    if ((e = launch_xcd_pass_lpt(lpt, static_cast<int>(grid), a, s)) != hipSuccess) return e;
+    if (mid && (e = hipEventRecord(mid, s)) != hipSuccess) return e;
+    const int64_t blocks = (L.trial_count + 255) / 256;
+    hipLaunchKernelGGL(xcd_combine_kernel, dim3(static_cast<uint32_t>(blocks)), dim3(256), 0, s, a.part_hi, a.part_lo,
+                       P, L.trial_count, L.aggR, L.aggL, ylt, S);
+    return hipGetLastError();
 }
 
 }  // namespace ara
