@@ -524,7 +524,10 @@ __global__ __launch_bounds__(512) void part_adjoint_kernel(PartAdjArgs a) {
 // the parts of a trial in part order.
 template <int LPT>
 __global__ __launch_bounds__(512) void xcd_pass_kernel(XcdPassArgs a) {
+    constexpr int kU = 4;
+    constexpr int kQueue = LPT * 4 * kU;            // one batch of a group, all hits at most
     __shared__ __attribute__((aligned(16))) uint64_t bm[kWords];
+    __shared__ uint32_t queue[512 / LPT][kQueue];   // per-group hit queues
     __shared__ int64_t s_tile;
     static_assert(LPT == 8 || LPT == 16 || LPT == 32 || LPT == 64, "lanes per trial");
     const int lig = threadIdx.x & (LPT - 1);
@@ -535,8 +538,8 @@ __global__ __launch_bounds__(512) void xcd_pass_kernel(XcdPassArgs a) {
     const int p0 = P >= a.n_xcd ? x : x % P;
     const int pstep = P >= a.n_xcd ? a.n_xcd : P;
     const int64_t count = a.t_hi - a.t_lo;
-    constexpr int kU = 4;
     constexpr uint32_t kBatch = LPT * 4 * kU;
+    uint32_t* q = queue[slot];
     for (int p = p0; p < P; p += pstep) {
         __syncthreads();
         {
@@ -588,18 +591,38 @@ __global__ __launch_bounds__(512) void xcd_pass_kernel(XcdPassArgs a) {
                     }
                 }
                 if (ni < Tk) load_batch(nc, ne, nxt);
-                double val[kU * 4];
+                // LDS test of every ID; hits go to the group's queue (lane
+                // order, then position), then the group gathers them with
+                // every lane busy
+                uint32_t ec[kU * 4];
                 bool hit[kU * 4];
+                int nh = 0;
 #pragma unroll
                 for (int k = 0; k < kU * 4; ++k) {
                     const uint32_t el = cur[k >> 2][k & 3] - pbase;   // sentinel and foreign IDs fail the test
                     const bool in = el < static_cast<uint32_t>(kPartSize);
-                    const uint32_t ec = in ? el : 0u;
-                    hit[k] = in && ((bm[ec >> 6] >> (ec & 63)) & 1ull);
-                    val[k] = op[hit[k] ? ec : 0u];
+                    ec[k] = in ? el : 0u;
+                    hit[k] = in && ((bm[ec[k] >> 6] >> (ec[k] & 63)) & 1ull);
+                    nh += hit[k] ? 1 : 0;
                 }
+                int incl = nh;
 #pragma unroll
-                for (int k = 0; k < kU * 4; ++k) dd_add(hi, lo, hit[k] ? val[k] : 0.0);
+                for (int off = 1; off < LPT; off <<= 1) {
+                    const int v = __shfl_up(incl, off, LPT);
+                    if (lig >= off) incl += v;
+                }
+                const int total = __shfl(incl, LPT - 1, LPT);
+                int pos = incl - nh;
+#pragma unroll
+                for (int k = 0; k < kU * 4; ++k) {
+                    if (hit[k]) q[pos] = ec[k];
+                    pos += hit[k] ? 1 : 0;
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                for (int j = lig; j < total; j += LPT) dd_add(hi, lo, op[q[j]]);
+                __builtin_amdgcn_wave_barrier();
                 if (ni != i) {
                     group_reduce_dd(hi, lo, LPT);
                     const int64_t t = t0 + i;
