@@ -36,7 +36,6 @@ struct Scratch {
     uint32_t* hist;       // [n_probs][kBins]
     SelState* st;         // [n_probs]
     uint32_t* flag;
-    uint32_t* done;       // workgroups finished in the current launch
 };
 
 Scratch carve(void* base, int n_probs) {
@@ -54,7 +53,6 @@ Scratch carve(void* base, int n_probs) {
     s.st = reinterpret_cast<SelState*>(p);
     p += static_cast<int64_t>(kMaxProbs) * sizeof(SelState);
     s.flag = reinterpret_cast<uint32_t*>(p);
-    s.done = s.flag + 4;
     return s;
 }
 
@@ -166,15 +164,12 @@ __global__ void select_init_kernel(Scratch s, MArgs ma, int n_probs) {
         s.st[tid].k = ma.m[tid];
         s.st[tid].m = ma.m[tid];
     }
-    if (tid == 0) {
-        *s.flag = 0;
-        *s.done = 0;
-    }
+    if (tid == 0) *s.flag = 0;
     for (int i = tid; i < n_probs * kBins; i += gridDim.x * blockDim.x) s.hist[i] = 0;
 }
 
 __global__ __launch_bounds__(256) void histogram_kernel(const double* __restrict__ x, int64_t n, Scratch s,
-                                                        int n_probs, int pass) {
+                                                        int n_probs, int pass, int with_mean) {
     extern __shared__ uint32_t lds_hist[];   // [n_probs][kBins]
     for (int i = threadIdx.x; i < n_probs * kBins; i += blockDim.x) lds_hist[i] = 0;
     __syncthreads();
@@ -187,15 +182,26 @@ __global__ __launch_bounds__(256) void histogram_kernel(const double* __restrict
     }
     const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
     uint32_t bad = 0;
+    double mhi = 0.0, mlo = 0.0;
     for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) {
         const double v = x[i];
         if (pass == 0 && !(v >= 0.0)) bad = 1;
+        if (with_mean) dd_add(mhi, mlo, v);
         const uint64_t key = key_of(v);
         const uint32_t d = static_cast<uint32_t>((key >> shift) & dmask);
         for (int q = 0; q < n_probs; ++q)
             if ((key & msk[q]) == pre[q]) atomicAdd(&lds_hist[q * kBins + d], 1u);
     }
     if (bad) atomicOr(s.flag, 1u);
+    if (with_mean) {
+        int64_t zero = 0;
+        block_reduce_dd(mhi, mlo, zero);
+        if (threadIdx.x == 0) {
+            s.part_hi[blockIdx.x] = mhi;
+            s.part_lo[blockIdx.x] = mlo;
+            s.part_cnt[blockIdx.x] = 0;
+        }
+    }
     __syncthreads();
     for (int i = threadIdx.x; i < n_probs * kBins; i += blockDim.x) {
         const uint32_t c = lds_hist[i];
@@ -277,171 +283,6 @@ __global__ __launch_bounds__(256) void tail_count_kernel(const double* __restric
     }
 }
 
-// Is this workgroup the last of the launch to finish?  Each workgroup
-// publishes its results, fences, then takes a ticket; the last one sees all.
-__device__ __forceinline__ bool last_block(uint32_t* done) {
-    __shared__ bool is_last;
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) is_last = atomicAdd(done, 1u) == gridDim.x - 1;
-    __syncthreads();
-    if (is_last) __threadfence();
-    return is_last;
-}
-
-// digit choice for probability q by one workgroup of 256 threads
-__device__ void choose_digit(Scratch& s, int q, int pass) {
-    uint32_t* h = s.hist + static_cast<int64_t>(q) * kBins;
-    const int nb = 1 << kBits[pass];
-    const int per = (nb + 255) / 256;
-    const int hiBin = nb - per * threadIdx.x;
-    const int loBin = hiBin - per;
-    uint64_t local = 0;
-    for (int b = hiBin - 1; b >= loBin && b >= 0; --b) local += __atomic_load_n(&h[b], __ATOMIC_RELAXED);
-    __shared__ uint64_t scan[256];
-    scan[threadIdx.x] = local;
-    __syncthreads();
-    for (int off = 1; off < 256; off <<= 1) {
-        uint64_t add = threadIdx.x >= off ? scan[threadIdx.x - off] : 0;
-        __syncthreads();
-        scan[threadIdx.x] += add;
-        __syncthreads();
-    }
-    const uint64_t incl = scan[threadIdx.x];
-    const uint64_t excl = incl - local;
-    const SelState st = s.st[q];
-    const uint64_t k = static_cast<uint64_t>(st.k);
-    __syncthreads();
-    if (excl < k && k <= incl) {
-        uint64_t cum = excl;
-        for (int b = hiBin - 1; b >= loBin && b >= 0; --b) {
-            const uint64_t c = __atomic_load_n(&h[b], __ATOMIC_RELAXED);
-            if (cum + c >= k) {
-                const int shift = kShift[pass];
-                const uint64_t dmask = (uint64_t(1) << kBits[pass]) - 1;
-                s.st[q].k = static_cast<int64_t>(k - cum);
-                s.st[q].prefix = st.prefix | (static_cast<uint64_t>(b) << shift);
-                s.st[q].mask = st.mask | (dmask << shift);
-                break;
-            }
-            cum += c;
-        }
-    }
-    __syncthreads();
-    for (int b = threadIdx.x; b < kBins; b += 256) h[b] = 0;
-    __syncthreads();
-}
-
-// One radix pass for every probability: privatised histograms, flushed with
-// atomics; the last workgroup chooses the digits.  Pass 0 also sums every
-// value (mean) and checks validity; its last workgroup writes the mean.
-__global__ __launch_bounds__(256) void radix_pass_kernel(const double* __restrict__ x, int64_t n, Scratch s,
-                                                         int n_probs, int pass, double* out) {
-    extern __shared__ uint32_t lds_hist[];
-    for (int i = threadIdx.x; i < n_probs * kBins; i += blockDim.x) lds_hist[i] = 0;
-    __syncthreads();
-    const int shift = kShift[pass];
-    const uint64_t dmask = (uint64_t(1) << kBits[pass]) - 1;
-    uint64_t pre[kMaxProbs], msk[kMaxProbs];
-    for (int q = 0; q < kMaxProbs; ++q) {
-        pre[q] = q < n_probs ? s.st[q].prefix : 0;
-        msk[q] = q < n_probs ? s.st[q].mask : 0;
-    }
-    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
-    uint32_t bad = 0;
-    double hi = 0.0, lo = 0.0;
-    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) {
-        const double v = x[i];
-        if (pass == 0) {
-            if (!(v >= 0.0)) bad = 1;
-            dd_add(hi, lo, v);
-        }
-        const uint64_t key = key_of(v);
-        const uint32_t d = static_cast<uint32_t>((key >> shift) & dmask);
-#pragma unroll
-        for (int q = 0; q < kMaxProbs; ++q)
-            if (q < n_probs && (key & msk[q]) == pre[q]) atomicAdd(&lds_hist[q * kBins + d], 1u);
-    }
-    if (bad) atomicOr(s.flag, 1u);
-    if (pass == 0) {
-        int64_t zero = 0;
-        block_reduce_dd(hi, lo, zero);
-        if (threadIdx.x == 0) {
-            s.part_hi[blockIdx.x] = hi;
-            s.part_lo[blockIdx.x] = lo;
-        }
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < n_probs * kBins; i += blockDim.x) {
-        const uint32_t c = lds_hist[i];
-        if (c) atomicAdd(&s.hist[i], c);
-    }
-    if (!last_block(s.done)) return;
-    for (int q = 0; q < n_probs; ++q) choose_digit(s, q, pass);
-    if (pass == 0 && out) {
-        double h = 0.0, l = 0.0;
-        for (int i = threadIdx.x; i < static_cast<int>(gridDim.x); i += blockDim.x) dd_merge(h, l, s.part_hi[i], s.part_lo[i]);
-        int64_t zero = 0;
-        block_reduce_dd(h, l, zero);
-        if (threadIdx.x == 0) {
-            const bool badv = __atomic_load_n(s.flag, __ATOMIC_RELAXED) != 0;
-            out[0] = badv ? __longlong_as_double(0x7ff8000000000000LL) : (h + l) / static_cast<double>(n);
-        }
-    }
-    if (threadIdx.x == 0) *s.done = 0;
-}
-
-// Sum and count of the values above each probability's threshold; the last
-// workgroup finishes PML and TVaR.
-__global__ __launch_bounds__(256) void tail_sums_kernel(const double* __restrict__ x, int64_t n, Scratch s,
-                                                        int n_probs, double* out) {
-    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
-    const int64_t tid = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    for (int q = 0; q < n_probs; ++q) {
-        double hi = 0.0, lo = 0.0;
-        int64_t cnt = 0;
-        const uint64_t thr = s.st[q].prefix;
-        for (int64_t i = tid; i < n; i += stride) {
-            const double v = x[i];
-            if (key_of(v) > thr) {
-                dd_add(hi, lo, v);
-                cnt += 1;
-            }
-        }
-        block_reduce_dd(hi, lo, cnt);
-        if (threadIdx.x == 0) {
-            s.part_hi[(1 + q) * kSumBlocks + blockIdx.x] = hi;
-            s.part_lo[(1 + q) * kSumBlocks + blockIdx.x] = lo;
-            s.part_cnt[(1 + q) * kSumBlocks + blockIdx.x] = cnt;
-        }
-        __syncthreads();
-    }
-    if (!last_block(s.done)) return;
-    const bool bad = __atomic_load_n(s.flag, __ATOMIC_RELAXED) != 0;
-    for (int q = 0; q < n_probs; ++q) {
-        double hi = 0.0, lo = 0.0;
-        int64_t cnt = 0;
-        for (int i = threadIdx.x; i < static_cast<int>(gridDim.x); i += blockDim.x) {
-            dd_merge(hi, lo, s.part_hi[(1 + q) * kSumBlocks + i], s.part_lo[(1 + q) * kSumBlocks + i]);
-            cnt += s.part_cnt[(1 + q) * kSumBlocks + i];
-        }
-        block_reduce_dd(hi, lo, cnt);
-        if (threadIdx.x == 0) {
-            const double nan = __longlong_as_double(0x7ff8000000000000LL);
-            const SelState st = s.st[q];
-            const double v = __longlong_as_double(static_cast<long long>(st.prefix));
-            const double r = static_cast<double>(st.m - cnt);   // copies of v in the top m
-            const double p = r * v;
-            const double pe = fma(r, v, -p);                   // exact product p + pe
-            dd_merge(hi, lo, p, pe);
-            out[1 + 2 * q] = bad ? nan : v;
-            out[2 + 2 * q] = bad ? nan : (hi + lo) / static_cast<double>(st.m);
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) *s.done = 0;
-}
-
 }  // namespace
 
 int64_t metrics_scratch_bytes(int n_probs) {
@@ -460,19 +301,31 @@ hipError_t launch_metrics(const double* ylt, int64_t n, const int64_t* m_host, i
     hipError_t err;
     hipLaunchKernelGGL(select_init_kernel, dim3(16), dim3(256), 0, st, s, ma, n_probs);
     if ((err = hipGetLastError()) != hipSuccess) return err;
-    int blocks = static_cast<int>((n + 1023) / 1024);
-    if (blocks > kSumBlocks) blocks = kSumBlocks;
-    if (blocks > 2 * n_cu) blocks = 2 * n_cu;
-    if (blocks < 1) blocks = 1;
+    // few workgroups for the histogram passes: each flushes n_probs x 4096
+    // bins with global atomics, which costs more than the 8 bytes per value
+    int hblocks = static_cast<int>((n + 4095) / 4096);
+    if (hblocks > n_cu / 4) hblocks = n_cu / 4;
+    if (hblocks < 1) hblocks = 1;
     const size_t lds = sizeof(uint32_t) * kBins * (n_probs > 0 ? n_probs : 1);
     const int passes = n_probs > 0 ? kPasses : 1;
     for (int pass = 0; pass < passes; ++pass) {
-        hipLaunchKernelGGL(radix_pass_kernel, dim3(blocks), dim3(256), lds, st, ylt, n, s, n_probs, pass,
-                           pass == 0 ? d_results : nullptr);
+        hipLaunchKernelGGL(histogram_kernel, dim3(hblocks), dim3(256), lds, st, ylt, n, s, n_probs, pass,
+                           pass == 0 ? 1 : 0);
         if ((err = hipGetLastError()) != hipSuccess) return err;
+        if (n_probs > 0) {
+            hipLaunchKernelGGL(select_digit_kernel, dim3(n_probs), dim3(256), 0, st, s, pass);
+            if ((err = hipGetLastError()) != hipSuccess) return err;
+        }
     }
+    hipLaunchKernelGGL((final_sums_kernel<0>), dim3(1), dim3(64), 0, st, s, n_probs, hblocks, n, d_results);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
     if (n_probs > 0) {
-        hipLaunchKernelGGL(tail_sums_kernel, dim3(blocks), dim3(256), 0, st, ylt, n, s, n_probs, d_results);
+        int blocks = static_cast<int>((n + 1023) / 1024);
+        if (blocks > kSumBlocks) blocks = kSumBlocks;
+        if (blocks < 1) blocks = 1;
+        hipLaunchKernelGGL((partial_sums_kernel<1>), dim3(blocks), dim3(256), 0, st, ylt, n, s, n_probs);
+        if ((err = hipGetLastError()) != hipSuccess) return err;
+        hipLaunchKernelGGL((final_sums_kernel<1>), dim3(1), dim3(64), 0, st, s, n_probs, blocks, n, d_results);
         if ((err = hipGetLastError()) != hipSuccess) return err;
     }
     return hipSuccess;
@@ -497,7 +350,7 @@ hipError_t launch_tail_stats(const double* ylt, int64_t n, int64_t m, void* scra
     if (hblocks < 1) hblocks = 1;
     for (int pass = 0; pass < kPasses; ++pass) {
         hipLaunchKernelGGL(histogram_kernel, dim3(hblocks), dim3(256), sizeof(uint32_t) * kBins, st, ylt, n, s,
-                           1, pass);
+                           1, pass, 0);
         if ((err = hipGetLastError()) != hipSuccess) return err;
         hipLaunchKernelGGL(select_digit_kernel, dim3(1), dim3(256), 0, st, s, pass);
         if ((err = hipGetLastError()) != hipSuccess) return err;
