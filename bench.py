@@ -149,7 +149,7 @@ def main() -> None:
     achieved = tp_bytes / (tp_avg / 1e3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
-                "kernel": "part_pass_kernel",
+                "kernel": "xcd_pass_kernel + xcd_combine_kernel",
                 "algorithmic_bytes_per_launch": tp_bytes, "avg_launch_ms": round(tp_avg, 5)}
 
     extra = {"pct_hbm_step": round(step_bytes / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4),

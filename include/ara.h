@@ -107,7 +107,8 @@ typedef struct ara_layer {
  */
 typedef struct ara_tuning {
     int32_t block_threads;          /* reserved (0); workgroup sizes are fixed per kernel */
-    int32_t part_lanes_per_trial;   /* partitioned pass: lanes per trial group, 8/16/32/64 (0 = 16) */
+    int32_t part_lanes_per_trial;   /* partitioned passes: lanes per trial group, 8/16/32/64
+                                       (0 = 16; the XCD-affine pass takes 8/16/32, 0 or 64 = 8) */
     int32_t lanes_per_trial;        /* time-ordered pass: 64 (one wave per trial), 32, 16 or 8 */
     int32_t blocks_per_cu;          /* time-ordered pass: resident workgroups per CU (0 = 8) */
     int32_t fold_events_per_thread; /* reserved (0) */

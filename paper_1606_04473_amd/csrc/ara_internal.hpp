@@ -140,7 +140,7 @@ struct XcdPassArgs {
     int64_t first_tile, last_tile;
     double* part_hi;                // [P][count]
     double* part_lo;
-    uint32_t* counters;             // [P]
+    const uint32_t* pad;            // 16 readable bytes of sentinels (the padding after the IDs)
     int n_xcd;
 };
 

@@ -39,6 +39,7 @@ constexpr int64_t kImgBytes = int64_t(kWords) * 8 + int64_t(kRank16) * 2 + int64
 static_assert(kImgBytes == 37120, "part image layout");
 static_assert(kImgBytes % 16 == 0, "16-byte copies");
 constexpr int kTileMax = 256;                                 // trials per tile (LDS accumulators)
+constexpr int kTileAlign = 32;                                // tiles start on 128-byte boundaries
 constexpr uint32_t kSentinel = 0xFFFFFFFFu;
 
 __device__ __forceinline__ uint64_t lanemask_lt() {
@@ -522,24 +523,75 @@ __global__ __launch_bounds__(512) void part_adjoint_kernel(PartAdjArgs a) {
 // arithmetic; the part's 32 KB bitmap is loaded into LDS once per part.  Each
 // (part, trial) double-double partial goes to HBM; xcd_combine_kernel adds
 // the parts of a trial in part order.
-template <int LPT>
+// Inclusive prefix sum over the 64 lanes of a wave with DPP lane moves: four
+// shifts build each 16-lane row's scan, two row broadcasts carry row totals.
+__device__ __forceinline__ uint32_t wave_scan_u32(uint32_t x) {
+    x += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(x), 0x111, 0xF, 0xF, false));
+    x += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(x), 0x112, 0xF, 0xF, false));
+    x += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(x), 0x114, 0xF, 0xF, false));
+    x += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(x), 0x118, 0xF, 0xF, false));
+    x += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(x), 0x142, 0xA, 0xF, false));
+    x += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(x), 0x143, 0xC, 0xF, false));
+    return x;
+}
+
+// the value held by the partner lane (lane ^ 1)
+__device__ __forceinline__ double swap_pair_f64(double v) {
+    const uint64_t b = __double_as_longlong(v);
+    const uint32_t lo = static_cast<uint32_t>(__builtin_amdgcn_mov_dpp(static_cast<int>(static_cast<uint32_t>(b)), 0xB1,
+                                                                        0xF, 0xF, false));
+    const uint32_t hi = static_cast<uint32_t>(__builtin_amdgcn_mov_dpp(static_cast<int>(static_cast<uint32_t>(b >> 32)),
+                                                                        0xB1, 0xF, 0xF, false));
+    return __longlong_as_double(static_cast<int64_t>((static_cast<uint64_t>(hi) << 32) | lo));
+}
+
+// XCD-affine trial pass.  Workgroups on XCD x serve the catalogue parts
+// p = x (mod 8), whose 2 MB of occurrence losses stay in that XCD's L2.  Each
+// wave owns 32 consecutive trials of a tile and streams their IDs of part p
+// as one contiguous range, 1024 IDs per batch: every ID is tested against the
+// part's bitmap in LDS and the hits are appended, in position order, to the
+// wave's LDS queue.  The queue is drained at the end of the tile (or when it
+// may overflow): two lanes per trial gather the losses of that trial's hits
+// and sum them in double-double, in queue order, so the result does not
+// depend on timing.  Tiles are assigned to workgroups statically, so the
+// next tile's boundaries are read a tile ahead and its first batch is loaded
+// while the current tile's last one is tested.
 __global__ __launch_bounds__(512) void xcd_pass_kernel(XcdPassArgs a) {
-    constexpr int kU = 4;
-    constexpr int kQueue = LPT * 4 * kU;            // one batch of a group, all hits at most
-    __shared__ __attribute__((aligned(16))) uint64_t bm[kWords];
-    __shared__ uint32_t queue[512 / LPT][kQueue];   // per-group hit queues
-    __shared__ int64_t s_tile;
-    static_assert(LPT == 8 || LPT == 16 || LPT == 32 || LPT == 64, "lanes per trial");
-    const int lig = threadIdx.x & (LPT - 1);
-    const int slot = threadIdx.x / LPT;
-    const int n_slots = blockDim.x / LPT;
-    const int x = static_cast<int>(blockIdx.x % a.n_xcd);
+    constexpr int kU = 4;                           // 16-byte loads per lane per batch
+    constexpr int kTrialsPW = kTileMax / 8;         // 32 trials per wave
+    constexpr uint32_t kBatch = 64 * 4 * kU;        // IDs per batch
+    constexpr int kQ = 1280;                        // queue entries per wave
+    constexpr int kInf = 0x3FFFFFFF;
+    static_assert(kQ >= static_cast<int>(kBatch), "a batch must fit the queue");
+    __shared__ __attribute__((aligned(16))) uint32_t bm[kWords * 2];
+    __shared__ uint32_t queue[8][kQ];               // per-wave hit queues: event index within the part
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+    uint32_t* q = queue[wv];
+    // parts served by this workgroup (its XCD's), and its rank among the servers of each
+    const int n_xcd = a.n_xcd;
+    const int x = static_cast<int>(blockIdx.x % n_xcd);
+    const int r = static_cast<int>(blockIdx.x / n_xcd);
+    const int nr = static_cast<int>(gridDim.x / n_xcd);
     const int P = a.P;
-    const int p0 = P >= a.n_xcd ? x : x % P;
-    const int pstep = P >= a.n_xcd ? a.n_xcd : P;
+    int p0, pstep, srank, nserv;
+    if (P >= n_xcd) {
+        p0 = x;
+        pstep = n_xcd;
+        srank = r;
+        nserv = nr;
+    } else {
+        p0 = x % P;
+        pstep = P;
+        srank = (x / P) * nr + r;
+        nserv = ((n_xcd - 1 - p0) / P + 1) * nr;
+    }
+    const int64_t n_tiles = a.last_tile - a.first_tile;
     const int64_t count = a.t_hi - a.t_lo;
-    constexpr uint32_t kBatch = LPT * 4 * kU;
-    uint32_t* q = queue[slot];
+    const int j0w = wv * kTrialsPW;                 // the wave's first trial in a tile
+    const int pt = lane >> 1;                       // the trial this lane sums (with its partner)
+    const int half = lane & 1;
+
     for (int p = p0; p < P; p += pstep) {
         __syncthreads();
         {
@@ -547,100 +599,213 @@ __global__ __launch_bounds__(512) void xcd_pass_kernel(XcdPassArgs a) {
             u32x4* dst = reinterpret_cast<u32x4*>(bm);
             for (int k = threadIdx.x; k < kWords / 2; k += blockDim.x) dst[k] = src[k];
         }
+        __syncthreads();
+        if (srank >= n_tiles) continue;
         const uint32_t pbase = static_cast<uint32_t>(static_cast<int64_t>(p) << kPartShift);
         const double* op = a.o + static_cast<int64_t>(p) * kPartSize;
-        for (;;) {
-            if (threadIdx.x == 0) s_tile = a.first_tile + atomicAdd(&a.counters[p], 1u);
-            __syncthreads();
-            const int64_t tile = s_tile;
-            if (tile >= a.last_tile) break;
+
+        // this server's m-th tile, clamped to a real tile past the end (never used there)
+        auto tile_of = [&](int64_t m) -> int64_t {
+            const int64_t tile = a.first_tile + srank + m * nserv;
+            return tile < a.last_tile ? tile : a.last_tile - 1;
+        };
+        auto trials_in = [&](int64_t tile) -> int {
             const int64_t t0 = tile * a.T;
-            const int Tk = static_cast<int>(a.N - t0 < a.T ? a.N - t0 : a.T);
-            const int64_t sbase = tile * (static_cast<int64_t>(a.T) * P + 1);
-            const uint32_t* tids = a.pids + a.tile_start[tile];
-            auto seg = [&](int i, uint32_t& sb, uint32_t& se) {
-                const int64_t t = t0 + i;
-                sb = a.seg_rel[sbase + static_cast<int64_t>(p) * Tk + i];
-                se = (t < a.t_lo || t >= a.t_hi) ? sb : a.seg_rel[sbase + static_cast<int64_t>(p) * Tk + i + 1];
-            };
-            auto load_batch = [&](uint32_t c, uint32_t e, u32x4* v) {
+            return static_cast<int>(a.N - t0 < a.T ? a.N - t0 : a.T);
+        };
+        // the wave's 33 segment boundaries in a tile, lane i holding boundary i
+        // (lanes past 32 repeat the last), clamped to the tile's trial count
+        auto load_bounds = [&](int64_t tile) -> uint32_t {
+            const int Tk = trials_in(tile);
+            const int64_t sb = tile * (static_cast<int64_t>(a.T) * P + 1) + static_cast<int64_t>(p) * Tk;
+            const int i = j0w + (lane < kTrialsPW ? lane : kTrialsPW);
+            return a.seg_rel[sb + (i < Tk ? i : Tk)];
+        };
+        // the wave's trials [jlo, jhi) of a tile (relative to j0w), clipped to
+        // the tile and to the layer's trials
+        auto clip = [&](int64_t tile, int& jlo, int& jhi) {
+            const int64_t t0 = tile * a.T + j0w;
+            const int Tk = trials_in(tile) - j0w;
+            jlo = 0;
+            jhi = kTrialsPW < Tk ? kTrialsPW : (Tk > 0 ? Tk : 0);
+            if (t0 + jlo < a.t_lo) jlo = static_cast<int>(a.t_lo - t0 < jhi ? a.t_lo - t0 : jhi);
+            if (t0 + jhi > a.t_hi) jhi = static_cast<int>(a.t_hi - t0 > jlo ? a.t_hi - t0 : jlo);
+            if (jhi < jlo) jhi = jlo;
+        };
+
+        // current tile
+        int64_t m = 0;
+        int64_t tile = tile_of(0);
+        uint32_t B = load_bounds(tile);
+        int jlo, jhi;
+        uint32_t rs, re;
+        const uint32_t* tids;
+        // next tile: its range and ID base (its first batch is loaded during
+        // this tile's last); boundaries of the next two tiles are read ahead
+        uint32_t B1 = load_bounds(tile_of(1));
+        uint32_t B2 = load_bounds(tile_of(2));
+        uint32_t n_rs, n_re;
+        const uint32_t* n_tids;
+        bool has_next = srank + nserv < n_tiles;
+        int qs;                                     // lane i: queue index of trial i's first hit
+        int qn = 0;                                 // entries in the queue
+        double acc_hi = 0.0, acc_lo = 0.0;
+
+        auto enter = [&]() {                        // make `tile` (boundaries B) current
+            clip(tile, jlo, jhi);
+            rs = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(B), jlo));
+            re = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(B), jhi));
+            tids = a.pids + a.tile_start[tile];
+            qs = B <= rs ? 0 : kInf;
+        };
+        auto aim = [&](int64_t ntile) {             // the range of `ntile` (boundaries B1)
+            int nlo, nhi;
+            clip(ntile, nlo, nhi);
+            n_rs = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(B1), nlo));
+            n_re = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(B1), nhi));
+            n_tids = a.pids + a.tile_start[ntile];
+        };
+        enter();
+        aim(tile_of(1));
+        // batches start on 128-byte lines (tiles are aligned); positions before
+        // rs are masked off
+        uint32_t c = rs & ~uint32_t(kTileAlign - 1);
+
+        // one batch of 16-byte ID chunks; chunks outside [cb, end) read the padding
+        auto load_batch = [&](const uint32_t* ids, uint32_t cb, uint32_t end, u32x4* v) {
 #pragma unroll
-                for (int u = 0; u < kU; ++u) {
-                    const uint32_t cu = c + lig * 4 + u * LPT * 4;
-                    v[u] = cu < e ? __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(tids + cu))
-                                  : u32x4{kSentinel, kSentinel, kSentinel, kSentinel};
-                }
-            };
-            int i = slot;
-            uint32_t cs = 0, ce = 0, c = 0;
-            u32x4 cur[kU], nxt[kU];
-            if (i < Tk) {
-                seg(i, cs, ce);
-                c = cs;
-                load_batch(c, ce, cur);
+            for (int u = 0; u < kU; ++u) {
+                const uint32_t cu = cb + u * 256 + lane * 4;
+                const uint32_t* src = cu < end ? ids + cu : a.pad;
+                v[u] = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(src));
             }
-            double hi = 0.0, lo = 0.0;
-            while (i < Tk) {
-                int ni = i;
-                uint32_t ns = cs, ne = ce, nc = c + kBatch;
-                if (nc >= ce) {
-                    ni = i + n_slots;
-                    if (ni < Tk) {
-                        seg(ni, ns, ne);
-                        nc = ns;
-                    }
-                }
-                if (ni < Tk) load_batch(nc, ne, nxt);
-                // LDS test of every ID; hits go to the group's queue (lane
-                // order, then position), then the group gathers them with
-                // every lane busy
-                uint32_t ec[kU * 4];
-                bool hit[kU * 4];
-                int nh = 0;
+        };
+        // the batch after the one at c: the rest of this tile, else the next tile's first
+        auto load_next = [&](u32x4* v) {
+            if (c + kBatch < re)
+                load_batch(tids, c + kBatch, re, v);
+            else
+                load_batch(n_tids, n_rs & ~uint32_t(kTileAlign - 1), has_next ? n_re : 0u, v);
+        };
+        // test a batch against the bitmap and append its hits to the queue in
+        // position order (chunk u, lane, word); note where each trial's hits start
+        auto process = [&](const u32x4* ids) {
+            uint32_t hits = 0;                      // bit 4u+w: word w of chunk u is a hit
 #pragma unroll
-                for (int k = 0; k < kU * 4; ++k) {
-                    const uint32_t el = cur[k >> 2][k & 3] - pbase;   // sentinel and foreign IDs fail the test
-                    const bool in = el < static_cast<uint32_t>(kPartSize);
-                    ec[k] = in ? el : 0u;
-                    hit[k] = in && ((bm[ec[k] >> 6] >> (ec[k] & 63)) & 1ull);
-                    nh += hit[k] ? 1 : 0;
-                }
-                int incl = nh;
+            for (int u = 0; u < kU; ++u) {
+                const uint32_t pos = c + u * 256 + lane * 4;
+                const uint32_t ok = pos >= rs && pos < re ? 1u : 0u;
 #pragma unroll
-                for (int off = 1; off < LPT; off <<= 1) {
-                    const int v = __shfl_up(incl, off, LPT);
-                    if (lig >= off) incl += v;
+                for (int w = 0; w < 4; ++w) {
+                    const uint32_t el = ids[u][w] - pbase;   // sentinel and foreign IDs fall outside
+                    const uint32_t in = el < static_cast<uint32_t>(kPartSize) ? ok : 0u;
+                    const uint32_t ec = el & static_cast<uint32_t>(kPartSize - 1);
+                    hits |= (in & __builtin_amdgcn_ubfe(bm[ec >> 5], ec & 31u, 1u)) << (u * 4 + w);
                 }
-                const int total = __shfl(incl, LPT - 1, LPT);
-                int pos = incl - nh;
-#pragma unroll
-                for (int k = 0; k < kU * 4; ++k) {
-                    if (hit[k]) q[pos] = ec[k];
-                    pos += hit[k] ? 1 : 0;
-                }
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                for (int j = lig; j < total; j += LPT) dd_add(hi, lo, op[q[j]]);
-                __builtin_amdgcn_wave_barrier();
-                if (ni != i) {
-                    group_reduce_dd(hi, lo, LPT);
-                    const int64_t t = t0 + i;
-                    if (lig == 0 && t >= a.t_lo && t < a.t_hi) {
-                        a.part_hi[static_cast<int64_t>(p) * count + (t - a.t_lo)] = hi;
-                        a.part_lo[static_cast<int64_t>(p) * count + (t - a.t_lo)] = lo;
-                    }
-                    hi = 0.0;
-                    lo = 0.0;
-                }
-                i = ni;
-                cs = ns;
-                ce = ne;
-                c = nc;
-#pragma unroll
-                for (int u = 0; u < kU; ++u) cur[u] = nxt[u];
             }
-            __syncthreads();
+            const uint32_t h0 = __builtin_popcount(hits & 0xFu), h1 = __builtin_popcount((hits >> 4) & 0xFu);
+            const uint32_t h2 = __builtin_popcount((hits >> 8) & 0xFu), h3 = __builtin_popcount(hits >> 12);
+            const uint32_t s01 = wave_scan_u32(h0 | (h1 << 16));
+            const uint32_t s23 = wave_scan_u32(h2 | (h3 << 16));
+            const uint32_t t01 = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(s01), 63));
+            const uint32_t t23 = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(s23), 63));
+            const int b1 = qn + static_cast<int>(t01 & 0xFFFFu);
+            const int b2 = b1 + static_cast<int>(t01 >> 16);
+            const int b3 = b2 + static_cast<int>(t23 & 0xFFFFu);
+            int pre[kU];
+            pre[0] = qn + static_cast<int>((s01 & 0xFFFFu) - h0);
+            pre[1] = b1 + static_cast<int>((s01 >> 16) - h1);
+            pre[2] = b2 + static_cast<int>((s23 & 0xFFFFu) - h2);
+            pre[3] = b3 + static_cast<int>((s23 >> 16) - h3);
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                int at = pre[u];
+#pragma unroll
+                for (int w = 0; w < 4; ++w) {
+                    const uint32_t hb = (hits >> (u * 4 + w)) & 1u;
+                    if (hb) q[at] = (ids[u][w] - pbase) & static_cast<uint32_t>(kPartSize - 1);
+                    at += static_cast<int>(hb);
+                }
+            }
+            // trial boundaries inside this batch: the first hit at or after the
+            // boundary's chunk is where that trial's hits start
+            const uint32_t k = (B - c) >> 2;        // chunk of this lane's boundary (if in the batch)
+            const int src = static_cast<int>(k & 63u);
+            const int v0 = __shfl(pre[0], src), v1 = __shfl(pre[1], src);
+            const int v2 = __shfl(pre[2], src), v3 = __shfl(pre[3], src);
+            if (B > rs && B < re && B >= c && B - c < kBatch) {
+                const uint32_t uu = k >> 6;
+                qs = uu == 0 ? v0 : (uu == 1 ? v1 : (uu == 2 ? v2 : v3));
+            }
+            qn = b3 + static_cast<int>(t23 >> 16);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        };
+        // gather and sum the queued hits: lanes 2t and 2t+1 take trial t's
+        // entries alternately, four gathers in flight per lane
+        auto drain = [&]() {
+            int lo = __shfl(qs, pt), hi = __shfl(qs, pt + 1);
+            lo = lo < 0 ? 0 : (lo > qn ? qn : lo);
+            hi = hi < 0 ? 0 : (hi > qn ? qn : hi);
+            for (int j = lo + half; j < hi; j += 8) {
+                double v[4];
+#pragma unroll
+                for (int r2 = 0; r2 < 4; ++r2) {
+                    const int jj = j + 2 * r2;
+                    v[r2] = 0.0;
+                    if (jj < hi) v[r2] = op[q[jj]];
+                }
+#pragma unroll
+                for (int r2 = 0; r2 < 4; ++r2)
+                    if (j + 2 * r2 < hi) dd_add(acc_hi, acc_lo, v[r2]);
+            }
+            qs = qs == kInf ? kInf : qs - qn;
+            qn = 0;
+            __builtin_amdgcn_wave_barrier();
+        };
+        // after a batch: advance; at the end of the wave's range drain the queue,
+        // write the trial sums and move to the next tile (its first batch is in
+        // flight).  Returns false when the server's tiles are done.
+        auto step = [&]() -> bool {
+            c += kBatch;
+            if (c < re) {
+                if (qn + static_cast<int>(kBatch) > kQ) drain();
+                return true;
+            }
+            drain();
+            dd_merge(acc_hi, acc_lo, swap_pair_f64(acc_hi), swap_pair_f64(acc_lo));
+            if (half == 0 && pt >= jlo && pt < jhi) {
+                const int64_t t = tile * a.T + j0w + pt;
+                a.part_hi[static_cast<int64_t>(p) * count + (t - a.t_lo)] = acc_hi;
+                a.part_lo[static_cast<int64_t>(p) * count + (t - a.t_lo)] = acc_lo;
+            }
+            acc_hi = 0.0;
+            acc_lo = 0.0;
+            if (!has_next) return false;
+            ++m;
+            tile = tile_of(m);
+            B = B1;
+            enter();
+            c = rs & ~uint32_t(kTileAlign - 1);
+            has_next = srank + (m + 1) * nserv < n_tiles;
+            B1 = B2;
+            aim(tile_of(m + 1));
+            B2 = load_bounds(tile_of(m + 2));
+            return true;
+        };
+
+        // two register buffers in turn, so the loads of the next batch stay in
+        // flight while this one is tested, with no copy that waits for them
+        u32x4 bufA[kU], bufB[kU];
+        load_batch(tids, c, re, bufA);
+        for (;;) {
+            load_next(bufB);
+            process(bufA);
+            if (!step()) break;
+            load_next(bufA);
+            process(bufB);
+            if (!step()) break;
         }
     }
 }
@@ -658,15 +823,6 @@ __global__ __launch_bounds__(256) void xcd_combine_kernel(const double* __restri
     if (S_out) S_out[k] = S;
 }
 
-hipError_t launch_xcd_pass_lpt(int lpt, int grid, const XcdPassArgs& a, hipStream_t s) {
-    switch (lpt) {
-        case 16: hipLaunchKernelGGL(xcd_pass_kernel<16>, dim3(grid), dim3(512), 0, s, a); break;
-        case 32: hipLaunchKernelGGL(xcd_pass_kernel<32>, dim3(grid), dim3(512), 0, s, a); break;
-        case 64: hipLaunchKernelGGL(xcd_pass_kernel<64>, dim3(grid), dim3(512), 0, s, a); break;
-        default: hipLaunchKernelGGL(xcd_pass_kernel<8>, dim3(grid), dim3(512), 0, s, a); break;
-    }
-    return hipGetLastError();
-}
 
 hipError_t launch_part_pass_lpt(int lpt, int grid, const PartPassArgs& a, hipStream_t s) {
     switch (lpt) {
@@ -724,7 +880,7 @@ hipError_t build_part_layout(const int64_t* offsets, const uint32_t* ids, int64_
         if ((e = hipStreamSynchronize(s)) != hipSuccess) goto fail;
         st[0] = 0;
         for (int64_t k = 0; k < n_tiles; ++k) {
-            if (h[k] >= (int64_t(1) << 32)) {   // a tile too large for 32-bit offsets: keep the plain layout
+            if (h[k] >= (int64_t(1) << 31)) {   // too large for 32-bit positions: keep the plain layout
                 (void)hipFree(cnt);
                 (void)hipFree(tsize);
                 (void)hipFree(out->seg_rel);
@@ -732,7 +888,7 @@ hipError_t build_part_layout(const int64_t* offsets, const uint32_t* ids, int64_
                 *out = PartLayout{};
                 return hipSuccess;
             }
-            st[k + 1] = st[k] + h[k];
+            st[k + 1] = st[k] + ((h[k] + kTileAlign - 1) & ~int64_t(kTileAlign - 1));   // padded with sentinels
         }
         const int64_t total = st[n_tiles];
         if ((e = hipMemcpyAsync(out->tile_start, st.data(), sizeof(int64_t) * (n_tiles + 1), hipMemcpyHostToDevice,
@@ -986,8 +1142,6 @@ hipError_t launch_xcd_pass(const PartLayout& lay, int64_t N, const LayerArgs& L,
     const int P = lay.P;
     PartScratch ps = carve_parts(part_scratch, P);
     hipError_t e;
-    hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(64), 0, s, ps.counter, int64_t(P), 0u);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
     XcdPassArgs a{};
     a.pids = lay.pids;
     a.seg_rel = lay.seg_rel;
@@ -1003,13 +1157,15 @@ hipError_t launch_xcd_pass(const PartLayout& lay, int64_t N, const LayerArgs& L,
     a.last_tile = (a.t_hi + lay.T - 1) / lay.T;
     a.part_hi = partials;
     a.part_lo = partials + static_cast<int64_t>(P) * L.trial_count;
-    a.counters = ps.counter;
+    a.pad = lay.pids + lay.length;
     a.n_xcd = kXcds;
     // two workgroups per CU, a multiple of the XCD count so every XCD gets the same share
     int64_t grid = int64_t(n_cu) * 2;
     grid -= grid % kXcds;
     if (grid < kXcds) grid = kXcds;
-    if ((e = launch_xcd_pass_lpt(lpt, static_cast<int>(grid), a, s)) != hipSuccess) return e;
+    (void)lpt;
+    hipLaunchKernelGGL(xcd_pass_kernel, dim3(static_cast<uint32_t>(grid)), dim3(512), 0, s, a);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
     if (mid && (e = hipEventRecord(mid, s)) != hipSuccess) return e;
     const int64_t blocks = (L.trial_count + 255) / 256;
     hipLaunchKernelGGL(xcd_combine_kernel, dim3(static_cast<uint32_t>(blocks)), dim3(256), 0, s, a.part_hi, a.part_lo,
