@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <cstring>
 #include <algorithm>
+#include <list>
 #include <new>
 #include <string>
 #include <vector>
@@ -63,6 +64,74 @@ struct PoolBuffer {
         if (bytes == 0) bytes = 256;
         return hipMallocAsync(&p, bytes, stream);
     }
+};
+
+// Take a kept scratch buffer of at least `bytes` for work on stream s (see
+// ScratchBuffer); give it back with scratch_release after enqueueing.
+hipError_t scratch_acquire(std::mutex& mu, std::vector<ara::ScratchBuffer*>& sets, size_t bytes, hipStream_t s,
+                           ara::ScratchBuffer** out) {
+    *out = nullptr;
+    ara::ScratchBuffer* pick = nullptr;
+    {
+        std::lock_guard<std::mutex> g(mu);
+        for (auto* b : sets) {
+            if (b->busy) continue;
+            if (b->stream != s && b->done && hipEventQuery(b->done) != hipSuccess) continue;
+            if (!pick || (b->cap >= bytes && (pick->cap < bytes || b->stream == s))) pick = b;
+        }
+        if (!pick) {
+            pick = new (std::nothrow) ara::ScratchBuffer();
+            if (!pick) return hipErrorOutOfMemory;
+            sets.push_back(pick);
+        }
+        pick->busy = true;
+    }
+    hipError_t e = hipSuccess;
+    if (!pick->done) e = hipEventCreateWithFlags(&pick->done, hipEventDisableTiming);
+    if (e == hipSuccess && pick->cap < bytes) {
+        // growing: the old memory may still be read by work on its stream
+        if (pick->p) {
+            if (pick->stream) e = hipStreamSynchronize(pick->stream);
+            if (e == hipSuccess) e = hipFree(pick->p);
+        }
+        pick->p = nullptr;
+        pick->cap = 0;
+        if (e == hipSuccess) e = hipMalloc(&pick->p, bytes);
+        if (e == hipSuccess) pick->cap = bytes;
+    }
+    if (e != hipSuccess) {
+        std::lock_guard<std::mutex> g(mu);
+        pick->busy = false;
+        return e;
+    }
+    *out = pick;
+    return hipSuccess;
+}
+
+void scratch_release(std::mutex& mu, ara::ScratchBuffer* b, hipStream_t s) {
+    if (!b) return;
+    (void)hipEventRecord(b->done, s);
+    std::lock_guard<std::mutex> g(mu);
+    b->stream = s;
+    b->busy = false;
+}
+
+void scratch_free_all(std::vector<ara::ScratchBuffer*>& sets) {
+    for (auto* b : sets) {
+        if (b->p) (void)hipFree(b->p);
+        if (b->done) (void)hipEventDestroy(b->done);
+        delete b;
+    }
+    sets.clear();
+}
+
+// releases on scope exit, so early error returns give the buffer back
+struct ScratchLease {
+    std::mutex& mu;
+    ara::ScratchBuffer* b = nullptr;
+    hipStream_t s = nullptr;
+    ScratchLease(std::mutex& m) : mu(m) {}
+    ~ScratchLease() { scratch_release(mu, b, s); }
 };
 
 void keep_pool_memory(int device) {
@@ -446,6 +515,7 @@ void ara_destroy_tables(ara_tables* t) {
     if (t->ids) (void)hipFree(t->ids);
     if (t->elts && t->owns_elts) (void)hipFree(t->elts);
     free_checkpoints(t->ck);
+    scratch_free_all(t->scratch);
     ara::free_part_layout(&t->parts);
     for (auto* g : t->graphs) free_graph(g);
     t->graphs.clear();
@@ -562,25 +632,40 @@ ara_status ara_run_layers(ara_tables* t, const ara_layer* layers, int32_t n_laye
         std::lock_guard<std::mutex> g(t->mu);
         tu = t->tuning;
     }
-    PoolBuffer staged, obuf;
+    PoolBuffer staged;
     double* out = ylt;
     if (!dev_out) {
         HIP_TRY(staged.alloc(sizeof(double) * (total > 0 ? total : 1), s), "scratch for YLT");
         out = static_cast<double*>(staged.p);
     }
-    if (!literal) HIP_TRY(obuf.alloc(sizeof(double) * t->C, s), "scratch for occurrence losses");
     // the partitioned pass serves plain runs; stride checkpoints need time order
     const bool use_parts = !literal && t->parts.P > 0 && !(flags & ARA_CHECKPOINT_STRIDE);
-    PoolBuffer pbuf, xbuf;
-    if (use_parts) HIP_TRY(pbuf.alloc(ara::part_scratch_bytes(t->C, t->parts.P), s), "scratch for part images");
     // the XCD-affine pass (default) writes per-part partial sums; pass_variant 1
     // selects the rank-based pass with the compact value array
     const bool use_xcd = use_parts && tu.pass_variant == 0;
+    const bool batched = n_layers > 1 && !(flags & ARA_PER_LAYER) && !literal && !ckpt && t->parts.P > 0;
+    // one kept scratch buffer for the per-layer path: occurrence losses, part
+    // images, partial sums (the batched path keeps its own)
+    auto up = [](size_t n) { return (n + 255) & ~size_t(255); };
+    const size_t o_bytes = literal ? 0 : up(sizeof(double) * t->C);
+    const size_t p_bytes = use_parts ? up(static_cast<size_t>(ara::part_scratch_bytes(t->C, t->parts.P))) : 0;
+    size_t x_bytes = 0;
     if (use_xcd) {
         int64_t most = 0;
         for (int i = 0; i < n_layers; ++i) most = std::max(most, L[i].trial_count);
-        HIP_TRY(xbuf.alloc(sizeof(double) * 2 * t->parts.P * (most > 0 ? most : 1), s), "scratch for partials");
+        x_bytes = up(sizeof(double) * 2 * t->parts.P * (most > 0 ? most : 1));
     }
+    ScratchLease lease(t->scratch_mu);
+    lease.s = s;
+    char* base = nullptr;
+    if (!batched) {
+        HIP_TRY(scratch_acquire(t->scratch_mu, t->scratch, o_bytes + p_bytes + x_bytes + 256, s, &lease.b),
+                "scratch for occurrence losses, part images and partial sums");
+        base = static_cast<char*>(lease.b->p);
+    }
+    struct {
+        void* p;
+    } obuf{base}, pbuf{base ? base + o_bytes : nullptr}, xbuf{base ? base + o_bytes + p_bytes : nullptr};
     double* S_buf = nullptr;
     double* stride_buf = nullptr;
     std::unique_lock<std::mutex> ck_lock(t->mu, std::defer_lock);
@@ -607,7 +692,6 @@ ara_status ara_run_layers(ara_tables* t, const ara_layer* layers, int32_t n_laye
         }
         S_buf = ck.S;
     }
-    const bool batched = n_layers > 1 && !(flags & ARA_PER_LAYER) && !literal && !ckpt && t->parts.P > 0;
     if ((flags & ARA_GRAPH) && batched && (!dev_out || s == nullptr))
         return fail(ARA_ERR_INVALID_ARG, "ARA_GRAPH needs a device output and a non-null stream");
     if (batched) {
@@ -736,9 +820,26 @@ ara_status ara_risk_metrics(const double* ylt, int64_t n_trials, const double* p
     keep_pool_memory(device);
     const int n_cu = query_cu_count(device);
     const bool dev = (flags & ARA_DEVICE_PTR) != 0;
-    PoolBuffer scratch, staged_in, results;
-    HIP_TRY(scratch.alloc(ara::metrics_scratch_bytes(n_probs), s), "metrics scratch");
-    HIP_TRY(results.alloc(sizeof(double) * (1 + 2 * n_probs), s), "metrics results");
+    PoolBuffer staged_in, results;
+    // kept per device, like the tables' scratch (see ScratchBuffer)
+    static std::mutex metrics_mu;
+    static std::list<std::pair<int, std::vector<ara::ScratchBuffer*>>> metrics_sets;   // stable addresses
+    std::vector<ara::ScratchBuffer*>* sets = nullptr;
+    {
+        std::lock_guard<std::mutex> g(metrics_mu);
+        for (auto& d : metrics_sets)
+            if (d.first == device) sets = &d.second;
+        if (!sets) {
+            metrics_sets.emplace_back(device, std::vector<ara::ScratchBuffer*>());
+            sets = &metrics_sets.back().second;
+        }
+    }
+    ScratchLease scratch(metrics_mu);
+    scratch.s = s;
+    HIP_TRY(scratch_acquire(metrics_mu, *sets, static_cast<size_t>(ara::metrics_scratch_bytes(n_probs)), s,
+                            &scratch.b),
+            "metrics scratch");
+    if (!dev) HIP_TRY(results.alloc(sizeof(double) * (1 + 2 * n_probs), s), "metrics results");
     const double* x = ylt;
     if (!dev) {
         HIP_TRY(staged_in.alloc(sizeof(double) * n_trials, s), "metrics input");
@@ -746,15 +847,12 @@ ara_status ara_risk_metrics(const double* ylt, int64_t n_trials, const double* p
         x = static_cast<const double*>(staged_in.p);
     }
     double* r = static_cast<double*>(results.p);
-    HIP_TRY(ara::launch_metrics(x, n_trials, m.data(), n_probs, scratch.p, r, n_cu, s), "metrics kernels");
-    if (dev) {
-        HIP_TRY(hipMemcpyAsync(mean_out, r, sizeof(double), hipMemcpyDeviceToDevice, s), "copy mean");
-        for (int q = 0; q < n_probs; ++q) {
-            HIP_TRY(hipMemcpyAsync(pml_out + q, r + 1 + 2 * q, sizeof(double), hipMemcpyDeviceToDevice, s), "copy");
-            HIP_TRY(hipMemcpyAsync(tvar_out + q, r + 2 + 2 * q, sizeof(double), hipMemcpyDeviceToDevice, s), "copy");
-        }
-        return ARA_OK;
-    }
+    // device outputs are written by the kernels themselves; host outputs go
+    // through the results buffer [mean, PML_0, TVaR_0, PML_1, ...]
+    const ara::MetricsOut out = dev ? ara::MetricsOut{mean_out, pml_out, tvar_out, 1}
+                                    : ara::MetricsOut{r, r + 1, r + 2, 2};
+    HIP_TRY(ara::launch_metrics(x, n_trials, m.data(), n_probs, scratch.b->p, out, n_cu, s), "metrics kernels");
+    if (dev) return ARA_OK;
     std::vector<double> h(1 + 2 * n_probs);
     HIP_TRY(hipMemcpyAsync(h.data(), r, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s), "copy metrics");
     HIP_TRY(hipStreamSynchronize(s), "synchronize");

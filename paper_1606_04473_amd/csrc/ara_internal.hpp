@@ -241,6 +241,20 @@ struct HostStage {
     hipEvent_t done = nullptr;
 };
 
+// Device scratch kept between calls.  Stream-ordered allocation makes the
+// host wait for the previous call's work before it hands the memory out
+// again; a kept buffer is handed to the next call on the same stream at once
+// (stream order protects it), or to a call on another stream once the event
+// recorded after its last use has completed.  Calls that find no free buffer
+// get a new one, so concurrent callers never share.
+struct ScratchBuffer {
+    void* p = nullptr;
+    size_t cap = 0;
+    hipEvent_t done = nullptr;      // recorded on `stream` after the last use
+    hipStream_t stream = nullptr;
+    bool busy = false;
+};
+
 // A captured batched run: persistent scratch, a graph, and the shape it was
 // captured for.
 struct GraphEntry {
@@ -274,6 +288,8 @@ struct ara_tables {
     std::vector<ara::GraphEntry*> graphs;
     std::mutex prof_mu;           // guards prof
     ara::ProfileState prof;
+    std::mutex scratch_mu;        // guards scratch
+    std::vector<ara::ScratchBuffer*> scratch;
 };
 
 namespace ara {
@@ -324,10 +340,16 @@ hipError_t launch_batched(const PartLayout& lay, int64_t N, int64_t C, const dou
                           const BatchedScratch& b, int64_t n_items, double* ylt, int n_cu, hipStream_t s,
                           hipEvent_t pass_start, hipEvent_t pass_stop, int lpt);
 
-// metrics: results[0] = mean, results[1 + 2q] = PML_q, results[2 + 2q] = TVaR_q
+// metrics: *mean, pml[q * stride] = PML_q, tvar[q * stride] = TVaR_q (device pointers)
+struct MetricsOut {
+    double* mean;
+    double* pml;
+    double* tvar;
+    int stride;
+};
 int64_t metrics_scratch_bytes(int n_probs);
 hipError_t launch_metrics(const double* ylt, int64_t n, const int64_t* m_host, int n_probs,
-                          void* scratch, double* d_results, int n_cu, hipStream_t s);
+                          void* scratch, MetricsOut out, int n_cu, hipStream_t s);
 
 // order statistics of a YLT for one tail count m
 struct TailStats {

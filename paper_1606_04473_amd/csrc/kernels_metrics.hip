@@ -120,7 +120,7 @@ __global__ __launch_bounds__(256) void partial_sums_kernel(const double* __restr
 
 template <int MODE>
 __global__ __launch_bounds__(64) void final_sums_kernel(Scratch s, int n_probs, int n_part, int64_t n,
-                                                        double* out) {
+                                                        MetricsOut out) {
     const int nq = MODE == 0 ? 1 : n_probs;
     const bool bad = *s.flag != 0;
     for (int q = 0; q < nq; ++q) {
@@ -136,7 +136,7 @@ __global__ __launch_bounds__(64) void final_sums_kernel(Scratch s, int n_probs, 
         if (threadIdx.x == 0) {
             const double nan = __longlong_as_double(0x7ff8000000000000LL);
             if (MODE == 0) {
-                out[0] = bad ? nan : (hi + lo) / static_cast<double>(n);
+                *out.mean = bad ? nan : (hi + lo) / static_cast<double>(n);
             } else {
                 const SelState st = s.st[q];
                 const double v = __longlong_as_double(static_cast<long long>(st.prefix));
@@ -144,8 +144,8 @@ __global__ __launch_bounds__(64) void final_sums_kernel(Scratch s, int n_probs, 
                 const double p = r * v;
                 const double pe = fma(r, v, -p);                   // exact product p + pe
                 dd_merge(hi, lo, p, pe);
-                out[1 + 2 * q] = bad ? nan : v;
-                out[2 + 2 * q] = bad ? nan : (hi + lo) / static_cast<double>(st.m);
+                out.pml[q * out.stride] = bad ? nan : v;
+                out.tvar[q * out.stride] = bad ? nan : (hi + lo) / static_cast<double>(st.m);
             }
         }
     }
@@ -183,15 +183,24 @@ __global__ __launch_bounds__(256) void histogram_kernel(const double* __restrict
     const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
     uint32_t bad = 0;
     double mhi = 0.0, mlo = 0.0;
-    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) {
-        const double v = x[i];
+    auto take = [&](double v) {
         if (pass == 0 && !(v >= 0.0)) bad = 1;
         if (with_mean) dd_add(mhi, mlo, v);
         const uint64_t key = key_of(v);
         const uint32_t d = static_cast<uint32_t>((key >> shift) & dmask);
         for (int q = 0; q < n_probs; ++q)
             if ((key & msk[q]) == pre[q]) atomicAdd(&lds_hist[q * kBins + d], 1u);
+    };
+    // four loads in flight per thread, then the tail
+    int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    for (; i + 3 * stride < n; i += 4 * stride) {
+        const double v0 = x[i], v1 = x[i + stride], v2 = x[i + 2 * stride], v3 = x[i + 3 * stride];
+        take(v0);
+        take(v1);
+        take(v2);
+        take(v3);
     }
+    for (; i < n; i += stride) take(x[i]);
     if (bad) atomicOr(s.flag, 1u);
     if (with_mean) {
         int64_t zero = 0;
@@ -293,7 +302,7 @@ int64_t metrics_scratch_bytes(int n_probs) {
 }
 
 hipError_t launch_metrics(const double* ylt, int64_t n, const int64_t* m_host, int n_probs,
-                          void* scratch, double* d_results, int n_cu, hipStream_t st) {
+                          void* scratch, MetricsOut out, int n_cu, hipStream_t st) {
     if (n_probs > kMaxProbs) return hipErrorInvalidValue;
     Scratch s = carve(scratch, n_probs);
     MArgs ma{};
@@ -301,11 +310,12 @@ hipError_t launch_metrics(const double* ylt, int64_t n, const int64_t* m_host, i
     hipError_t err;
     hipLaunchKernelGGL(select_init_kernel, dim3(16), dim3(256), 0, st, s, ma, n_probs);
     if ((err = hipGetLastError()) != hipSuccess) return err;
-    // few workgroups for the histogram passes: each flushes n_probs x 4096
-    // bins with global atomics, which costs more than the 8 bytes per value
-    int hblocks = static_cast<int>((n + 4095) / 4096);
-    if (hblocks > n_cu / 4) hblocks = n_cu / 4;
+    // enough workgroups to keep many loads in flight; each adds only its
+    // non-zero bins to the global histogram (values crowd into few bins)
+    int hblocks = static_cast<int>((n + 2047) / 2048);
+    if (hblocks > kSumBlocks) hblocks = kSumBlocks;
     if (hblocks < 1) hblocks = 1;
+    (void)n_cu;
     const size_t lds = sizeof(uint32_t) * kBins * (n_probs > 0 ? n_probs : 1);
     const int passes = n_probs > 0 ? kPasses : 1;
     for (int pass = 0; pass < passes; ++pass) {
@@ -317,7 +327,7 @@ hipError_t launch_metrics(const double* ylt, int64_t n, const int64_t* m_host, i
             if ((err = hipGetLastError()) != hipSuccess) return err;
         }
     }
-    hipLaunchKernelGGL((final_sums_kernel<0>), dim3(1), dim3(64), 0, st, s, n_probs, hblocks, n, d_results);
+    hipLaunchKernelGGL((final_sums_kernel<0>), dim3(1), dim3(64), 0, st, s, n_probs, hblocks, n, out);
     if ((err = hipGetLastError()) != hipSuccess) return err;
     if (n_probs > 0) {
         int blocks = static_cast<int>((n + 1023) / 1024);
@@ -325,7 +335,7 @@ hipError_t launch_metrics(const double* ylt, int64_t n, const int64_t* m_host, i
         if (blocks < 1) blocks = 1;
         hipLaunchKernelGGL((partial_sums_kernel<1>), dim3(blocks), dim3(256), 0, st, ylt, n, s, n_probs);
         if ((err = hipGetLastError()) != hipSuccess) return err;
-        hipLaunchKernelGGL((final_sums_kernel<1>), dim3(1), dim3(64), 0, st, s, n_probs, blocks, n, d_results);
+        hipLaunchKernelGGL((final_sums_kernel<1>), dim3(1), dim3(64), 0, st, s, n_probs, blocks, n, out);
         if ((err = hipGetLastError()) != hipSuccess) return err;
     }
     return hipSuccess;

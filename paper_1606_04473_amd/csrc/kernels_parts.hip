@@ -563,7 +563,8 @@ __global__ __launch_bounds__(512) void xcd_pass_kernel(XcdPassArgs a) {
     constexpr int kQ = 1280;                        // queue entries per wave
     constexpr int kInf = 0x3FFFFFFF;
     static_assert(kQ >= static_cast<int>(kBatch), "a batch must fit the queue");
-    __shared__ __attribute__((aligned(16))) uint32_t bm[kWords * 2];
+    constexpr uint32_t kZeroWord = kWords * 2 * 4;  // byte offset of the zero word after the bitmap
+    __shared__ __attribute__((aligned(16))) uint32_t bm[kWords * 2 + 4];
     __shared__ uint32_t queue[8][kQ];               // per-wave hit queues: event index within the part
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
@@ -598,10 +599,12 @@ __global__ __launch_bounds__(512) void xcd_pass_kernel(XcdPassArgs a) {
             const u32x4* src = reinterpret_cast<const u32x4*>(a.img + static_cast<int64_t>(p) * kImgBytes);
             u32x4* dst = reinterpret_cast<u32x4*>(bm);
             for (int k = threadIdx.x; k < kWords / 2; k += blockDim.x) dst[k] = src[k];
+            if (threadIdx.x == 0) dst[kWords / 2] = u32x4{0u, 0u, 0u, 0u};
         }
         __syncthreads();
         if (srank >= n_tiles) continue;
         const uint32_t pbase = static_cast<uint32_t>(static_cast<int64_t>(p) << kPartShift);
+        const uint32_t pw4 = pbase >> 3;            // byte offset of part p's first bitmap word, were it global
         const double* op = a.o + static_cast<int64_t>(p) * kPartSize;
 
         // this server's m-th tile, clamped to a real tile past the end (never used there)
@@ -690,19 +693,26 @@ __global__ __launch_bounds__(512) void xcd_pass_kernel(XcdPassArgs a) {
         // test a batch against the bitmap and append its hits to the queue in
         // position order (chunk u, lane, word); note where each trial's hits start
         auto process = [&](const u32x4* ids) {
+            // every ID in [rs, re) belongs to part p, so the only other values
+            // are the sentinel padding: its word index runs past the bitmap and
+            // is clamped to the zero word after it.  The bit offset only uses the
+            // low 5 bits, which an event shares with its part-relative index.
             uint32_t hits = 0;                      // bit 4u+w: word w of chunk u is a hit
+            uint32_t okmask = 0;
 #pragma unroll
             for (int u = 0; u < kU; ++u) {
                 const uint32_t pos = c + u * 256 + lane * 4;
-                const uint32_t ok = pos >= rs && pos < re ? 1u : 0u;
+                okmask |= (pos >= rs && pos < re ? 0xFu : 0u) << (u * 4);
 #pragma unroll
                 for (int w = 0; w < 4; ++w) {
-                    const uint32_t el = ids[u][w] - pbase;   // sentinel and foreign IDs fall outside
-                    const uint32_t in = el < static_cast<uint32_t>(kPartSize) ? ok : 0u;
-                    const uint32_t ec = el & static_cast<uint32_t>(kPartSize - 1);
-                    hits |= (in & __builtin_amdgcn_ubfe(bm[ec >> 5], ec & 31u, 1u)) << (u * 4 + w);
+                    const uint32_t id = ids[u][w];
+                    uint32_t wa = ((id >> 5) << 2) - pw4;          // byte address of the bitmap word
+                    wa = wa < kZeroWord ? wa : kZeroWord;
+                    const uint32_t word = *reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(bm) + wa);
+                    hits |= __builtin_amdgcn_ubfe(word, id, 1u) << (u * 4 + w);
                 }
             }
+            hits &= okmask;
             const uint32_t h0 = __builtin_popcount(hits & 0xFu), h1 = __builtin_popcount((hits >> 4) & 0xFu);
             const uint32_t h2 = __builtin_popcount((hits >> 8) & 0xFu), h3 = __builtin_popcount(hits >> 12);
             const uint32_t s01 = wave_scan_u32(h0 | (h1 << 16));
@@ -723,7 +733,7 @@ __global__ __launch_bounds__(512) void xcd_pass_kernel(XcdPassArgs a) {
 #pragma unroll
                 for (int w = 0; w < 4; ++w) {
                     const uint32_t hb = (hits >> (u * 4 + w)) & 1u;
-                    if (hb) q[at] = (ids[u][w] - pbase) & static_cast<uint32_t>(kPartSize - 1);
+                    if (hb) q[at] = ids[u][w] - pbase;
                     at += static_cast<int>(hb);
                 }
             }
