@@ -78,6 +78,8 @@ typedef int32_t ara_status;
 #define ARA_KERNEL_FOLD       0     /* per-catalogue occurrence losses */
 #define ARA_KERNEL_TRIAL_PASS 1     /* YET stream, lookups, annual totals, aggregate terms */
 #define ARA_KERNEL_BATCHED    2     /* persistent multi-layer trial pass */
+#define ARA_KERNEL_COMBINE    3     /* merge of the per-part partial sums into annual totals and
+                                       aggregate terms (after the catalogue-partitioned pass) */
 
 #define ARA_MAX_LAYER_ELTS 64       /* most ELTs one layer may cover (the paper's layers cover 3-30) */
 #define ARA_CHECKPOINT_EVERY 64     /* events between stored prefix sums of S */
@@ -275,9 +277,11 @@ ara_status ara_read_checkpoints(ara_tables* tables, int32_t what, double* out,
 
 /*
  * ara_kernel_stats -- launches and summed device time (ms, from HIP events)
- * of one kernel class over the ara_run_layers calls made with ARA_PROFILE
- * since the last reset.  Waits for the recorded events.  reset != 0 clears
- * the totals after reading them.
+ * of one kernel class (ARA_KERNEL_*, 0..3; ARA_ERR_INVALID_ARG otherwise)
+ * over the ara_run_layers calls made with ARA_PROFILE since the last reset.
+ * With the catalogue-partitioned pass, ARA_KERNEL_TRIAL_PASS times the pass
+ * kernel alone and ARA_KERNEL_COMBINE the merge after it.  Waits for the
+ * recorded events.  reset != 0 clears the totals after reading them.
  */
 ara_status ara_kernel_stats(ara_tables* tables, int32_t kernel, int64_t* launches, double* total_ms,
                             int32_t reset);

@@ -40,6 +40,7 @@ ARA_CHECKPOINT_STRIDE = 1 << 7
 KERNEL_FOLD = 0
 KERNEL_TRIAL_PASS = 1
 KERNEL_BATCHED = 2
+KERNEL_COMBINE = 3
 
 MAX_LAYER_ELTS = 64
 CHECKPOINT_EVERY = 64

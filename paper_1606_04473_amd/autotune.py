@@ -1,8 +1,9 @@
 """Autotuner for the trial-pass launch shape and the batched schedule.
 
-Candidates are the ara_tuning knobs: lanes per trial group in the
-partitioned pass (8/16/32/64), lanes per trial in the time-ordered pass, and
-the order of the batched (layer, tile) work list.  Each candidate runs the
+Candidates are the ara_tuning knobs: the single-layer pass variant (the
+XCD-affine pass, or the rank-based pass with 16 or 32 lanes per trial group),
+lanes per trial group in the batched pass (8/16/32/64), and the order of the
+batched (layer, tile) work list.  Each candidate runs the
 caller's layers a few times with ARA_PROFILE; the kernel time the library
 measures with HIP events decides.  Results are cached per (device, shape
 class) in a JSON file, so a shape is tuned once.
@@ -41,8 +42,8 @@ def candidates(n_layers: int) -> List[Dict[str, int]]:
         out = [dict(part_lanes_per_trial=lpt) for lpt in (8, 16, 32, 64)]
         out += [dict(part_lanes_per_trial=lpt, schedule=1) for lpt in (16, 32)]
         return out
-    out = [dict(part_lanes_per_trial=lpt) for lpt in (8, 16, 32)]
-    out += [dict(part_lanes_per_trial=16, pass_variant=1)]
+    out = [dict(pass_variant=0)]
+    out += [dict(part_lanes_per_trial=lpt, pass_variant=1) for lpt in (16, 32)]
     return out
 
 
@@ -72,15 +73,21 @@ def measure(tables: "ara.Tables", layers: Sequence["ara.LayerSpec"], knobs: Dict
     """Average device time (ms) of the pass kernel(s) for one candidate."""
     import torch
     ara.set_tuning(tables, **knobs)
-    kernel = ara.KERNEL_BATCHED if (len(layers) > 1 and not flags & ara.ARA_PER_LAYER) else ara.KERNEL_TRIAL_PASS
+    batched = len(layers) > 1 and not flags & ara.ARA_PER_LAYER
+    # the partitioned pass times its merge separately: count both
+    kernels = [ara.KERNEL_BATCHED] if batched else [ara.KERNEL_TRIAL_PASS, ara.KERNEL_COMBINE]
     for _ in range(warmup):
         ara.run_layers(tables, layers, out=out, flags=flags)
     torch.cuda.synchronize()
-    ara.kernel_stats(tables, kernel, reset=True)
+    for k in kernels:
+        ara.kernel_stats(tables, k, reset=True)
     for _ in range(repeats):
         ara.run_layers(tables, layers, out=out, flags=flags | ara.ARA_PROFILE)
-    n, ms = ara.kernel_stats(tables, kernel, reset=True)
-    return ms / max(n, 1)
+    total = 0.0
+    for k in kernels:
+        n, ms = ara.kernel_stats(tables, k, reset=True)
+        total += ms / max(n, 1) if n else 0.0
+    return total
 
 
 def tune(tables: "ara.Tables", layers: Sequence["ara.LayerSpec"], out, flags: int = 0, repeats: int = 5,

@@ -535,7 +535,7 @@ ara_status ara_table_bytes(const ara_tables* t, int64_t* bytes) {
 }
 
 ara_status ara_kernel_stats(ara_tables* t, int32_t kernel, int64_t* launches, double* total_ms, int32_t reset) {
-    if (!t || kernel < 0 || kernel > 2) return fail(ARA_ERR_INVALID_ARG, "bad argument");
+    if (!t || kernel < 0 || kernel > 3) return fail(ARA_ERR_INVALID_ARG, "bad argument");
     DeviceScope ds(t->device);
     std::lock_guard<std::mutex> g(t->prof_mu);
     auto& ps = t->prof;
@@ -776,13 +776,20 @@ ara_status ara_run_layers(ara_tables* t, const ara_layer* layers, int32_t n_laye
                         "part images");
             kt.done();
         }
-        KernelTimer kt(t, s, prof, ARA_KERNEL_TRIAL_PASS);
-        if (use_xcd)
+        if (use_xcd) {
+            KernelTimer kp(t, s, prof, ARA_KERNEL_TRIAL_PASS);
             HIP_TRY(ara::launch_xcd_pass(t->parts, t->n_trials, L[i], pbuf.p, static_cast<const double*>(obuf.p),
-                                         static_cast<double*>(xbuf.p), a.ylt, a.S, t->n_cu, s,
-                                         tu.part_lanes_per_trial ? tu.part_lanes_per_trial : 8, nullptr),
+                                         static_cast<double*>(xbuf.p), t->n_cu, s),
                     "XCD-affine trial pass");
-        else if (use_parts)
+            kp.done();
+            KernelTimer kc(t, s, prof, ARA_KERNEL_COMBINE);
+            HIP_TRY(ara::launch_xcd_combine(t->parts, L[i], static_cast<const double*>(xbuf.p), a.ylt, a.S, s),
+                    "partial sums merge");
+            kc.done();
+            continue;
+        }
+        KernelTimer kt(t, s, prof, ARA_KERNEL_TRIAL_PASS);
+        if (use_parts)
             HIP_TRY(ara::launch_part_pass(t->parts, t->n_trials, L[i], pbuf.p, a.ylt, a.S, t->n_cu, s,
                                           tu.part_lanes_per_trial),
                     "partitioned trial pass");

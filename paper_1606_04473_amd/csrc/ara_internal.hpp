@@ -229,8 +229,8 @@ struct ProfileState {
     };
     std::vector<Pending> pending;
     std::vector<hipEvent_t> free_events;
-    int64_t launches[3] = {0, 0, 0};
-    double total_ms[3] = {0.0, 0.0, 0.0};
+    int64_t launches[4] = {0, 0, 0, 0};
+    double total_ms[4] = {0.0, 0.0, 0.0, 0.0};
 };
 
 // Pinned host staging for small per-call uploads; the event marks when the
@@ -328,9 +328,11 @@ hipError_t build_part_layout(const int64_t* offsets, const uint32_t* ids, int64_
 void free_part_layout(PartLayout* L);
 int64_t part_scratch_bytes(int64_t C, int P);
 hipError_t launch_part_fold(const double* o, int64_t C, int P, void* scratch, hipStream_t s, bool with_ranks);
+// the XCD-affine pass writes per-part partial sums; the combine merges them
 hipError_t launch_xcd_pass(const PartLayout& lay, int64_t N, const LayerArgs& L, void* part_scratch,
-                           const double* o, double* partials, double* ylt, double* S, int n_cu, hipStream_t s,
-                           int lpt, hipEvent_t mid);
+                           const double* o, double* partials, int n_cu, hipStream_t s);
+hipError_t launch_xcd_combine(const PartLayout& lay, const LayerArgs& L, const double* partials, double* ylt,
+                              double* S, hipStream_t s);
 hipError_t launch_part_pass(const PartLayout& lay, int64_t N, const LayerArgs& L, void* scratch, double* ylt,
                             double* S, int n_cu, hipStream_t s, int lpt);
 

@@ -1146,12 +1146,10 @@ hipError_t launch_batched(const PartLayout& lay, int64_t N, int64_t C, const dou
 namespace ara {
 
 hipError_t launch_xcd_pass(const PartLayout& lay, int64_t N, const LayerArgs& L, void* part_scratch,
-                           const double* o, double* partials, double* ylt, double* S, int n_cu, hipStream_t s,
-                           int lpt, hipEvent_t mid) {
+                           const double* o, double* partials, int n_cu, hipStream_t s) {
     if (L.trial_count <= 0) return hipSuccess;
     const int P = lay.P;
     PartScratch ps = carve_parts(part_scratch, P);
-    hipError_t e;
     XcdPassArgs a{};
     a.pids = lay.pids;
     a.seg_rel = lay.seg_rel;
@@ -1173,13 +1171,17 @@ hipError_t launch_xcd_pass(const PartLayout& lay, int64_t N, const LayerArgs& L,
     int64_t grid = int64_t(n_cu) * 2;
     grid -= grid % kXcds;
     if (grid < kXcds) grid = kXcds;
-    (void)lpt;
     hipLaunchKernelGGL(xcd_pass_kernel, dim3(static_cast<uint32_t>(grid)), dim3(512), 0, s, a);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    if (mid && (e = hipEventRecord(mid, s)) != hipSuccess) return e;
+    return hipGetLastError();
+}
+
+hipError_t launch_xcd_combine(const PartLayout& lay, const LayerArgs& L, const double* partials, double* ylt,
+                              double* S, hipStream_t s) {
+    if (L.trial_count <= 0) return hipSuccess;
+    const int P = lay.P;
     const int64_t blocks = (L.trial_count + 255) / 256;
-    hipLaunchKernelGGL(xcd_combine_kernel, dim3(static_cast<uint32_t>(blocks)), dim3(256), 0, s, a.part_hi, a.part_lo,
-                       P, L.trial_count, L.aggR, L.aggL, ylt, S);
+    hipLaunchKernelGGL(xcd_combine_kernel, dim3(static_cast<uint32_t>(blocks)), dim3(256), 0, s, partials,
+                       partials + static_cast<int64_t>(P) * L.trial_count, P, L.trial_count, L.aggR, L.aggL, ylt, S);
     return hipGetLastError();
 }
 

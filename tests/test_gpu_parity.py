@@ -526,12 +526,13 @@ def test_autotuner_choices_keep_parity(ara, tmp_path):
     ref, _ = oracle.run_layer(yet, pool, layer)
     out = torch.empty(yet.n_trials, dtype=torch.float64, device="cuda")
     res = autotune.tune(tables, [spec], out, repeats=2)
-    assert len(res["timings"]) == 4 and res["best_ms"] > 0
+    assert len(res["timings"]) == len(autotune.candidates(1)) and res["best_ms"] > 0
     for ms, knobs in res["timings"]:
         ara.set_tuning(tables, **knobs)
         ylt = ara.run_layers(tables, [spec])
         ok, worst = _close(ylt, ref)
         assert ok, (knobs, worst)
     best = autotune.tuned(tables, [spec], out, path=str(tmp_path / "c.json"), repeats=1)
-    assert ara.get_tuning(tables)["part_lanes_per_trial"] == best["part_lanes_per_trial"]
+    got = ara.get_tuning(tables)
+    assert all(got[k] == v for k, v in best.items()), (got, best)
     tables.close()

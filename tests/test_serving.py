@@ -127,7 +127,7 @@ def test_autotune_cache_and_shape_class(tmp_path):
     one = autotune.shape_class(T, [L(16, 1_000_000)])
     many = autotune.shape_class(T, [L(16, 500_000)] * 64)
     assert one.startswith("P8-ev10-") and one.endswith("-one-J4") and "-many-" in many
-    assert len(autotune.candidates(1)) == 4 and len(autotune.candidates(64)) == 6
+    assert len(autotune.candidates(1)) == 3 and len(autotune.candidates(64)) == 6
     path = str(tmp_path / "cache.json")
     assert autotune.load_cache(path) == {}
     autotune.save_cache({"k": {"part_lanes_per_trial": 32}}, path)
