@@ -556,11 +556,11 @@ __device__ __forceinline__ double swap_pair_f64(double v) {
 // depend on timing.  Tiles are assigned to workgroups statically, so the
 // next tile's boundaries are read a tile ahead and its first batch is loaded
 // while the current tile's last one is tested.
-__global__ __launch_bounds__(512) void xcd_pass_kernel(XcdPassArgs a) {
-    constexpr int kU = 4;                           // 16-byte loads per lane per batch
+__global__ __launch_bounds__(512, 6) void xcd_pass_kernel(XcdPassArgs a) {
+    constexpr int kU = 2;                           // 16-byte loads per lane per batch
     constexpr int kTrialsPW = kTileMax / 8;         // 32 trials per wave
     constexpr uint32_t kBatch = 64 * 4 * kU;        // IDs per batch
-    constexpr int kQ = 1280;                        // queue entries per wave
+    constexpr int kQ = 640;                         // queue entries per wave (3 workgroups per CU)
     constexpr int kInf = 0x3FFFFFFF;
     static_assert(kQ >= static_cast<int>(kBatch), "a batch must fit the queue");
     constexpr uint32_t kZeroWord = kWords * 2 * 4;  // byte offset of the zero word after the bitmap
@@ -690,6 +690,28 @@ __global__ __launch_bounds__(512) void xcd_pass_kernel(XcdPassArgs a) {
             else
                 load_batch(n_tids, n_rs & ~uint32_t(kTileAlign - 1), has_next ? n_re : 0u, v);
         };
+        // gather and sum the queued hits: lanes 2t and 2t+1 take trial t's
+        // entries alternately, four gathers in flight per lane
+        auto drain = [&]() {
+            int lo = __shfl(qs, pt), hi = __shfl(qs, pt + 1);
+            lo = lo < 0 ? 0 : (lo > qn ? qn : lo);
+            hi = hi < 0 ? 0 : (hi > qn ? qn : hi);
+            for (int j = lo + half; j < hi; j += 8) {
+                double v[4];
+#pragma unroll
+                for (int r2 = 0; r2 < 4; ++r2) {
+                    const int jj = j + 2 * r2;
+                    v[r2] = 0.0;
+                    if (jj < hi) v[r2] = op[q[jj]];
+                }
+#pragma unroll
+                for (int r2 = 0; r2 < 4; ++r2)
+                    if (j + 2 * r2 < hi) dd_add(acc_hi, acc_lo, v[r2]);
+            }
+            qs = qs == kInf ? kInf : qs - qn;
+            qn = 0;
+            __builtin_amdgcn_wave_barrier();
+        };
         // test a batch against the bitmap and append its hits to the queue in
         // position order (chunk u, lane, word); note where each trial's hits start
         auto process = [&](const u32x4* ids) {
@@ -713,20 +735,33 @@ __global__ __launch_bounds__(512) void xcd_pass_kernel(XcdPassArgs a) {
                 }
             }
             hits &= okmask;
-            const uint32_t h0 = __builtin_popcount(hits & 0xFu), h1 = __builtin_popcount((hits >> 4) & 0xFu);
-            const uint32_t h2 = __builtin_popcount((hits >> 8) & 0xFu), h3 = __builtin_popcount(hits >> 12);
-            const uint32_t s01 = wave_scan_u32(h0 | (h1 << 16));
-            const uint32_t s23 = wave_scan_u32(h2 | (h3 << 16));
-            const uint32_t t01 = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(s01), 63));
-            const uint32_t t23 = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(s23), 63));
-            const int b1 = qn + static_cast<int>(t01 & 0xFFFFu);
-            const int b2 = b1 + static_cast<int>(t01 >> 16);
-            const int b3 = b2 + static_cast<int>(t23 & 0xFFFFu);
+            // per-chunk hit counts, prefix-summed over the wave two chunks at a time
+            // (16-bit halves: at most 4 x 64 hits per chunk)
+            uint32_t ex[kU], tot[kU];
+#pragma unroll
+            for (int u = 0; u < kU; u += 2) {
+                const uint32_t ha = __builtin_popcount((hits >> (4 * u)) & 0xFu);
+                const uint32_t hb = __builtin_popcount((hits >> (4 * u + 4)) & 0xFu);
+                const uint32_t sc = wave_scan_u32(ha | (hb << 16));
+                const uint32_t tt = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(sc), 63));
+                ex[u] = (sc & 0xFFFFu) - ha;
+                ex[u + 1] = (sc >> 16) - hb;
+                tot[u] = tt & 0xFFFFu;
+                tot[u + 1] = tt >> 16;
+            }
+            int total = 0;
+#pragma unroll
+            for (int u = 0; u < kU; ++u) total += static_cast<int>(tot[u]);
+            if (qn + total > kQ) drain();            // exact: the batch always fits an empty queue
             int pre[kU];
-            pre[0] = qn + static_cast<int>((s01 & 0xFFFFu) - h0);
-            pre[1] = b1 + static_cast<int>((s01 >> 16) - h1);
-            pre[2] = b2 + static_cast<int>((s23 & 0xFFFFu) - h2);
-            pre[3] = b3 + static_cast<int>((s23 >> 16) - h3);
+            {
+                int base = qn;
+#pragma unroll
+                for (int u = 0; u < kU; ++u) {
+                    pre[u] = base + static_cast<int>(ex[u]);
+                    base += static_cast<int>(tot[u]);
+                }
+            }
 #pragma unroll
             for (int u = 0; u < kU; ++u) {
                 int at = pre[u];
@@ -741,48 +776,24 @@ __global__ __launch_bounds__(512) void xcd_pass_kernel(XcdPassArgs a) {
             // boundary's chunk is where that trial's hits start
             const uint32_t k = (B - c) >> 2;        // chunk of this lane's boundary (if in the batch)
             const int src = static_cast<int>(k & 63u);
-            const int v0 = __shfl(pre[0], src), v1 = __shfl(pre[1], src);
-            const int v2 = __shfl(pre[2], src), v3 = __shfl(pre[3], src);
-            if (B > rs && B < re && B >= c && B - c < kBatch) {
-                const uint32_t uu = k >> 6;
-                qs = uu == 0 ? v0 : (uu == 1 ? v1 : (uu == 2 ? v2 : v3));
+            int vq = 0;
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const int v = __shfl(pre[u], src);
+                vq = (k >> 6) == static_cast<uint32_t>(u) ? v : vq;
             }
-            qn = b3 + static_cast<int>(t23 >> 16);
+            if (B > rs && B < re && B >= c && B - c < kBatch) qs = vq;
+            qn += total;
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        };
-        // gather and sum the queued hits: lanes 2t and 2t+1 take trial t's
-        // entries alternately, four gathers in flight per lane
-        auto drain = [&]() {
-            int lo = __shfl(qs, pt), hi = __shfl(qs, pt + 1);
-            lo = lo < 0 ? 0 : (lo > qn ? qn : lo);
-            hi = hi < 0 ? 0 : (hi > qn ? qn : hi);
-            for (int j = lo + half; j < hi; j += 8) {
-                double v[4];
-#pragma unroll
-                for (int r2 = 0; r2 < 4; ++r2) {
-                    const int jj = j + 2 * r2;
-                    v[r2] = 0.0;
-                    if (jj < hi) v[r2] = op[q[jj]];
-                }
-#pragma unroll
-                for (int r2 = 0; r2 < 4; ++r2)
-                    if (j + 2 * r2 < hi) dd_add(acc_hi, acc_lo, v[r2]);
-            }
-            qs = qs == kInf ? kInf : qs - qn;
-            qn = 0;
-            __builtin_amdgcn_wave_barrier();
         };
         // after a batch: advance; at the end of the wave's range drain the queue,
         // write the trial sums and move to the next tile (its first batch is in
         // flight).  Returns false when the server's tiles are done.
         auto step = [&]() -> bool {
             c += kBatch;
-            if (c < re) {
-                if (qn + static_cast<int>(kBatch) > kQ) drain();
-                return true;
-            }
+            if (c < re) return true;
             drain();
             dd_merge(acc_hi, acc_lo, swap_pair_f64(acc_hi), swap_pair_f64(acc_lo));
             if (half == 0 && pt >= jlo && pt < jhi) {
@@ -1167,8 +1178,9 @@ hipError_t launch_xcd_pass(const PartLayout& lay, int64_t N, const LayerArgs& L,
     a.part_lo = partials + static_cast<int64_t>(P) * L.trial_count;
     a.pad = lay.pids + lay.length;
     a.n_xcd = kXcds;
-    // two workgroups per CU, a multiple of the XCD count so every XCD gets the same share
-    int64_t grid = int64_t(n_cu) * 2;
+    // three workgroups per CU (the LDS and register budgets are sized for it),
+    // a multiple of the XCD count so every XCD gets the same share
+    int64_t grid = int64_t(n_cu) * 3;
     grid -= grid % kXcds;
     if (grid < kXcds) grid = kXcds;
     hipLaunchKernelGGL(xcd_pass_kernel, dim3(static_cast<uint32_t>(grid)), dim3(512), 0, s, a);
