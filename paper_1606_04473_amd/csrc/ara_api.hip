@@ -772,14 +772,14 @@ ara_status ara_run_layers(ara_tables* t, const ara_layer* layers, int32_t n_laye
             HIP_TRY(ara::launch_fold(t->elts, t->C, L[i], static_cast<double*>(obuf.p), tu, s), "fold");
             if (use_parts)
                 HIP_TRY(ara::launch_part_fold(static_cast<const double*>(obuf.p), t->C, t->parts.P, pbuf.p, s,
-                                              !use_xcd),
+                                              true),
                         "part images");
             kt.done();
         }
         if (use_xcd) {
             KernelTimer kp(t, s, prof, ARA_KERNEL_TRIAL_PASS);
-            HIP_TRY(ara::launch_xcd_pass(t->parts, t->n_trials, L[i], pbuf.p, static_cast<const double*>(obuf.p),
-                                         static_cast<double*>(xbuf.p), t->n_cu, s),
+            HIP_TRY(ara::launch_xcd_pass(t->parts, t->n_trials, t->C, L[i], pbuf.p, static_cast<double*>(xbuf.p),
+                                         t->n_cu, s),
                     "XCD-affine trial pass");
             kp.done();
             KernelTimer kc(t, s, prof, ARA_KERNEL_COMBINE);

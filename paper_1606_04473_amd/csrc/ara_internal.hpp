@@ -131,8 +131,9 @@ struct XcdPassArgs {
     const uint32_t* pids;
     const uint32_t* seg_rel;
     const int64_t* tile_start;
-    const uint8_t* img;             // part images; the bitmap opens each
-    const double* o;                // dense occurrence losses [C]
+    const uint8_t* img;             // part images: bitmap, 128-event ranks, superblock bases
+    const double* compact;          // nonzero occurrence losses in rank order
+    int64_t C;                      // catalogue size (bounds compact)
     int64_t N;
     int P;
     int T;
@@ -329,8 +330,8 @@ void free_part_layout(PartLayout* L);
 int64_t part_scratch_bytes(int64_t C, int P);
 hipError_t launch_part_fold(const double* o, int64_t C, int P, void* scratch, hipStream_t s, bool with_ranks);
 // the XCD-affine pass writes per-part partial sums; the combine merges them
-hipError_t launch_xcd_pass(const PartLayout& lay, int64_t N, const LayerArgs& L, void* part_scratch,
-                           const double* o, double* partials, int n_cu, hipStream_t s);
+hipError_t launch_xcd_pass(const PartLayout& lay, int64_t N, int64_t C, const LayerArgs& L, void* part_scratch,
+                           double* partials, int n_cu, hipStream_t s);
 hipError_t launch_xcd_combine(const PartLayout& lay, const LayerArgs& L, const double* partials, double* ylt,
                               double* S, hipStream_t s);
 hipError_t launch_part_pass(const PartLayout& lay, int64_t N, const LayerArgs& L, void* scratch, double* ylt,

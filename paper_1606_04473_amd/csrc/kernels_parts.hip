@@ -556,20 +556,30 @@ __device__ __forceinline__ double swap_pair_f64(double v) {
 // depend on timing.  Tiles are assigned to workgroups statically, so the
 // next tile's boundaries are read a tile ahead and its first batch is loaded
 // while the current tile's last one is tested.
-__global__ __launch_bounds__(512, 6) void xcd_pass_kernel(XcdPassArgs a) {
+__global__ __launch_bounds__(1024) void xcd_pass_kernel(XcdPassArgs a) {
     constexpr int kU = 2;                           // 16-byte loads per lane per batch
     constexpr int kTrialsPW = kTileMax / 8;         // 32 trials per wave
     constexpr uint32_t kBatch = 64 * 4 * kU;        // IDs per batch
-    constexpr int kQ = 640;                         // queue entries per wave (3 workgroups per CU)
+    constexpr int kQ = 640;                         // queue entries per wave
+    constexpr int kCache = 10240;                   // nonzero losses of the part kept in LDS
     constexpr int kInf = 0x3FFFFFFF;
     static_assert(kQ >= static_cast<int>(kBatch), "a batch must fit the queue");
-    constexpr uint32_t kZeroWord = kWords * 2 * 4;  // byte offset of the zero word after the bitmap
-    __shared__ __attribute__((aligned(16))) uint32_t bm[kWords * 2 + 4];
-    __shared__ uint32_t queue[8][kQ];               // per-wave hit queues: event index within the part
+    // LDS: the part image (bitmap, 128-event ranks, superblock bases) and a
+    // zero word after it, the hit queues, and the first kCache nonzero losses
+    constexpr uint32_t kBmBytes = kWords * 8;       // 32 KB bitmap
+    constexpr uint32_t kZeroWord = static_cast<uint32_t>(kImgBytes);   // byte offset of the zero word
+    __shared__ __attribute__((aligned(16))) uint32_t img[kImgBytes / 4 + 4];
+    __shared__ uint32_t queue[16][kQ];              // per-wave hit queues: event index within the part
+    __shared__ double cache[kCache];
+    const uint32_t* bm = img;
+    const uint16_t* r16 = reinterpret_cast<const uint16_t*>(reinterpret_cast<const char*>(img) + kBmBytes);
+    const uint32_t* b32 = reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(img) + kBmBytes +
+                                                            kRank16 * 2);
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
     uint32_t* q = queue[wv];
-    // parts served by this workgroup (its XCD's), and its rank among the servers of each
+    // parts served by this workgroup (its XCD's), and its rank among the servers
+    // of each; the two halves of the workgroup (8 waves each) serve separately
     const int n_xcd = a.n_xcd;
     const int x = static_cast<int>(blockIdx.x % n_xcd);
     const int r = static_cast<int>(blockIdx.x / n_xcd);
@@ -587,9 +597,11 @@ __global__ __launch_bounds__(512, 6) void xcd_pass_kernel(XcdPassArgs a) {
         srank = (x / P) * nr + r;
         nserv = ((n_xcd - 1 - p0) / P + 1) * nr;
     }
+    srank = 2 * srank + (wv >> 3);
+    nserv = 2 * nserv;
     const int64_t n_tiles = a.last_tile - a.first_tile;
     const int64_t count = a.t_hi - a.t_lo;
-    const int j0w = wv * kTrialsPW;                 // the wave's first trial in a tile
+    const int j0w = (wv & 7) * kTrialsPW;           // the wave's first trial in a tile
     const int pt = lane >> 1;                       // the trial this lane sums (with its partner)
     const int half = lane & 1;
 
@@ -597,15 +609,21 @@ __global__ __launch_bounds__(512, 6) void xcd_pass_kernel(XcdPassArgs a) {
         __syncthreads();
         {
             const u32x4* src = reinterpret_cast<const u32x4*>(a.img + static_cast<int64_t>(p) * kImgBytes);
-            u32x4* dst = reinterpret_cast<u32x4*>(bm);
-            for (int k = threadIdx.x; k < kWords / 2; k += blockDim.x) dst[k] = src[k];
-            if (threadIdx.x == 0) dst[kWords / 2] = u32x4{0u, 0u, 0u, 0u};
+            u32x4* dst = reinterpret_cast<u32x4*>(img);
+            for (int k = threadIdx.x; k < static_cast<int>(kImgBytes / 16); k += blockDim.x) dst[k] = src[k];
+            if (threadIdx.x == 0) dst[kImgBytes / 16] = u32x4{0u, 0u, 0u, 0u};
+        }
+        __syncthreads();
+        // the part's first nonzero losses, in rank order (global ranks from b32)
+        const uint32_t rank0 = b32[0];
+        for (int k = threadIdx.x; k < kCache; k += blockDim.x) {
+            const int64_t g = static_cast<int64_t>(rank0) + k;
+            cache[k] = g < a.C ? a.compact[g] : 0.0;
         }
         __syncthreads();
         if (srank >= n_tiles) continue;
         const uint32_t pbase = static_cast<uint32_t>(static_cast<int64_t>(p) << kPartShift);
         const uint32_t pw4 = pbase >> 3;            // byte offset of part p's first bitmap word, were it global
-        const double* op = a.o + static_cast<int64_t>(p) * kPartSize;
 
         // this server's m-th tile, clamped to a real tile past the end (never used there)
         auto tile_of = [&](int64_t m) -> int64_t {
@@ -702,7 +720,21 @@ __global__ __launch_bounds__(512, 6) void xcd_pass_kernel(XcdPassArgs a) {
                 for (int r2 = 0; r2 < 4; ++r2) {
                     const int jj = j + 2 * r2;
                     v[r2] = 0.0;
-                    if (jj < hi) v[r2] = op[q[jj]];
+                    if (jj < hi) {
+                        // rank of the event among the nonzero ones: superblock base,
+                        // 128-event offset, and the set bits below it in its 128 bits
+                        const uint32_t e = q[jj];
+                        const u32x4 w4 = *reinterpret_cast<const u32x4*>(bm + ((e >> 7) << 2));
+                        const uint32_t b = e & 127u, wi = b >> 5;
+                        const uint32_t below = (b & 31u) ? (~0u >> (32u - (b & 31u))) : 0u;
+                        uint32_t cnt = __builtin_popcount(wi == 0 ? (w4.x & below) : w4.x);
+                        cnt += wi >= 1 ? __builtin_popcount(wi == 1 ? (w4.y & below) : w4.y) : 0u;
+                        cnt += wi >= 2 ? __builtin_popcount(wi == 2 ? (w4.z & below) : w4.z) : 0u;
+                        cnt += wi == 3 ? __builtin_popcount(w4.w & below) : 0u;
+                        const uint32_t rk = b32[e >> 12] + r16[e >> 7] + cnt;
+                        const uint32_t lr = rk - rank0;
+                        v[r2] = lr < static_cast<uint32_t>(kCache) ? cache[lr] : a.compact[rk];
+                    }
                 }
 #pragma unroll
                 for (int r2 = 0; r2 < 4; ++r2)
@@ -729,7 +761,7 @@ __global__ __launch_bounds__(512, 6) void xcd_pass_kernel(XcdPassArgs a) {
                 for (int w = 0; w < 4; ++w) {
                     const uint32_t id = ids[u][w];
                     uint32_t wa = ((id >> 5) << 2) - pw4;          // byte address of the bitmap word
-                    wa = wa < kZeroWord ? wa : kZeroWord;
+                    wa = wa < kBmBytes ? wa : kZeroWord;
                     const uint32_t word = *reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(bm) + wa);
                     hits |= __builtin_amdgcn_ubfe(word, id, 1u) << (u * 4 + w);
                 }
@@ -1156,8 +1188,8 @@ hipError_t launch_batched(const PartLayout& lay, int64_t N, int64_t C, const dou
 
 namespace ara {
 
-hipError_t launch_xcd_pass(const PartLayout& lay, int64_t N, const LayerArgs& L, void* part_scratch,
-                           const double* o, double* partials, int n_cu, hipStream_t s) {
+hipError_t launch_xcd_pass(const PartLayout& lay, int64_t N, int64_t C, const LayerArgs& L, void* part_scratch,
+                           double* partials, int n_cu, hipStream_t s) {
     if (L.trial_count <= 0) return hipSuccess;
     const int P = lay.P;
     PartScratch ps = carve_parts(part_scratch, P);
@@ -1166,7 +1198,8 @@ hipError_t launch_xcd_pass(const PartLayout& lay, int64_t N, const LayerArgs& L,
     a.seg_rel = lay.seg_rel;
     a.tile_start = lay.tile_start;
     a.img = ps.img;
-    a.o = o;
+    a.compact = ps.compact;
+    a.C = C;
     a.N = N;
     a.P = P;
     a.T = lay.T;
@@ -1178,12 +1211,12 @@ hipError_t launch_xcd_pass(const PartLayout& lay, int64_t N, const LayerArgs& L,
     a.part_lo = partials + static_cast<int64_t>(P) * L.trial_count;
     a.pad = lay.pids + lay.length;
     a.n_xcd = kXcds;
-    // three workgroups per CU (the LDS and register budgets are sized for it),
-    // a multiple of the XCD count so every XCD gets the same share
-    int64_t grid = int64_t(n_cu) * 3;
+    // one 1024-thread workgroup per CU (its LDS holds the part image and the
+    // loss cache), a multiple of the XCD count so every XCD gets the same share
+    int64_t grid = int64_t(n_cu);
     grid -= grid % kXcds;
     if (grid < kXcds) grid = kXcds;
-    hipLaunchKernelGGL(xcd_pass_kernel, dim3(static_cast<uint32_t>(grid)), dim3(512), 0, s, a);
+    hipLaunchKernelGGL(xcd_pass_kernel, dim3(static_cast<uint32_t>(grid)), dim3(1024), 0, s, a);
     return hipGetLastError();
 }
 
