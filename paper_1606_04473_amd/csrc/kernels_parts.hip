@@ -773,13 +773,15 @@ __global__ __launch_bounds__(1024) void xcd_pass_kernel(XcdPassArgs a) {
 #pragma unroll
             for (int u = 0; u < kU; u += 2) {
                 const uint32_t ha = __builtin_popcount((hits >> (4 * u)) & 0xFu);
-                const uint32_t hb = __builtin_popcount((hits >> (4 * u + 4)) & 0xFu);
+                const uint32_t hb = u + 1 < kU ? __builtin_popcount((hits >> (4 * u + 4)) & 0xFu) : 0u;
                 const uint32_t sc = wave_scan_u32(ha | (hb << 16));
                 const uint32_t tt = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(sc), 63));
                 ex[u] = (sc & 0xFFFFu) - ha;
-                ex[u + 1] = (sc >> 16) - hb;
                 tot[u] = tt & 0xFFFFu;
-                tot[u + 1] = tt >> 16;
+                if (u + 1 < kU) {
+                    ex[u + 1] = (sc >> 16) - hb;
+                    tot[u + 1] = tt >> 16;
+                }
             }
             int total = 0;
 #pragma unroll
