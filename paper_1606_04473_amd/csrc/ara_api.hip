@@ -769,11 +769,12 @@ ara_status ara_run_layers(ara_tables* t, const ara_layer* layers, int32_t n_laye
         const bool prof = (flags & ARA_PROFILE) != 0;
         if (!literal) {
             KernelTimer kt(t, s, prof, ARA_KERNEL_FOLD);
-            HIP_TRY(ara::launch_fold(t->elts, t->C, L[i], static_cast<double*>(obuf.p), tu, s), "fold");
             if (use_parts)
-                HIP_TRY(ara::launch_part_fold(static_cast<const double*>(obuf.p), t->C, t->parts.P, pbuf.p, s,
-                                              true),
-                        "part images");
+                HIP_TRY(ara::launch_fold_parts(t->elts, t->C, L[i], static_cast<double*>(obuf.p), t->parts.P, pbuf.p,
+                                               s),
+                        "fold and part images");
+            else
+                HIP_TRY(ara::launch_fold(t->elts, t->C, L[i], static_cast<double*>(obuf.p), tu, s), "fold");
             kt.done();
         }
         if (use_xcd) {

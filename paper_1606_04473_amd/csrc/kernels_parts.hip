@@ -193,6 +193,65 @@ __global__ __launch_bounds__(256) void part_image_kernel(const double* __restric
     }
 }
 
+// The fold and the part images in one pass: one workgroup (256 threads) per
+// superblock of 4096 catalogue events.  Each lane folds 16 events (one per
+// 64-event word, so every ELT row is read in coalesced 512-byte rows with 16
+// loads in flight), summing the ELTs of each event in layer order exactly as
+// the fold does, then writes o, the bitmap words, the per-128 ranks and the
+// superblock count.
+__global__ __launch_bounds__(256) void fold_image_kernel(const double* __restrict__ elts, int64_t C, LayerArgs L,
+                                                         double* __restrict__ o, uint8_t* __restrict__ img,
+                                                         uint32_t* __restrict__ sb_count) {
+    __shared__ uint32_t wc[64];
+    const int64_t sb = blockIdx.x;
+    const int64_t e0 = sb * kSuper;
+    const int64_t part = e0 >> kPartShift;
+    const int ls = static_cast<int>((e0 & (kPartSize - 1)) >> kSuperShift);
+    uint64_t* bm = reinterpret_cast<uint64_t*>(img + part * kImgBytes);
+    uint16_t* r16 = reinterpret_cast<uint16_t*>(img + part * kImgBytes + int64_t(kWords) * 8);
+    const int w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int64_t eb = e0 + static_cast<int64_t>(w) * 16 * 64 + lane;   // event of word 0 of this wave
+    double y[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) y[k] = 0.0;
+    for (int j = 0; j < L.J; ++j) {
+        const double* row = elts + static_cast<int64_t>(L.idx[j]) * C;
+        const double R = L.R[j], Lim = L.Lim[j];
+        double l[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const int64_t E = eb + k * 64;
+            l[k] = E < C ? __builtin_nontemporal_load(row + E) : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < 16; ++k) y[k] = y[k] + apply_terms(l[k], R, Lim);
+    }
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        const int word = w * 16 + k;
+        const int64_t E = eb + k * 64;
+        const double v = apply_terms(y[k], L.occR, L.occL);
+        if (E < C) o[E] = v;
+        const uint64_t bits = __ballot(E < C && v != 0.0);
+        if (lane == 0) {
+            bm[ls * 64 + word] = bits;
+            wc[word] = __popcll(bits);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 32) {
+        uint32_t before = 0;
+        for (int b = 0; b < static_cast<int>(threadIdx.x); ++b) before += wc[2 * b] + wc[2 * b + 1];
+        r16[ls * 32 + threadIdx.x] = static_cast<uint16_t>(before);
+    }
+    if (threadIdx.x == 0) {
+        uint32_t total = 0;
+        for (int k = 0; k < 64; ++k) total += wc[k];
+        sb_count[sb] = total;
+    }
+}
+
 // exclusive scan of the superblock counts (one workgroup) into each part's
 // base32 table
 __global__ __launch_bounds__(1024) void superblock_scan_kernel(const uint32_t* __restrict__ sb_count, int64_t n_sb,
@@ -1019,6 +1078,21 @@ hipError_t launch_part_fold(const double* o, int64_t C, int P, void* scratch, hi
                        ps.sb_count, int64_t(0), int64_t(0), int64_t(0));
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (!with_ranks) return hipSuccess;
+    hipLaunchKernelGGL(superblock_scan_kernel, dim3(1), dim3(1024), 0, s, ps.sb_count, n_sb, ps.img, int64_t(0));
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(compact_kernel, dim3(static_cast<uint32_t>(n_sb)), dim3(256), 0, s, o, C, ps.img, ps.compact,
+                       int64_t(0), int64_t(0));
+    return hipGetLastError();
+}
+
+hipError_t launch_fold_parts(const double* elts, int64_t C, const LayerArgs& L, double* o, int P, void* scratch,
+                             hipStream_t s) {
+    PartScratch ps = carve_parts(scratch, P);
+    const int64_t n_sb = static_cast<int64_t>(P) * kBase32;
+    hipError_t e;
+    hipLaunchKernelGGL(fold_image_kernel, dim3(static_cast<uint32_t>(n_sb)), dim3(256), 0, s, elts, C, L, o, ps.img,
+                       ps.sb_count);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(superblock_scan_kernel, dim3(1), dim3(1024), 0, s, ps.sb_count, n_sb, ps.img, int64_t(0));
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(compact_kernel, dim3(static_cast<uint32_t>(n_sb)), dim3(256), 0, s, o, C, ps.img, ps.compact,
