@@ -3,12 +3,15 @@
 // Year losses are >= 0, so their IEEE-754 bit patterns order like their
 // values when read as uint64.  PML_p (the m-th largest) is found by a radix
 // select over those patterns: six passes with 12/12/12/12/12/4-bit digits,
-// each pass a privatised LDS histogram of the values that match the prefix
-// chosen so far, followed by a one-workgroup digit choice.  All requested
-// probabilities advance together in each pass.  TVaR_p = (sum of the values
-// above v + (m - c_gt) v) / m, with v = PML_p and c_gt the count above it.
-// Sums are double-double, reduced in a fixed order (deterministic), and the
-// product (m - c_gt) v is added exactly via fma.
+// each a privatised LDS histogram of the values that match the prefix chosen
+// so far.  The digit of a pass is chosen at the start of the next pass by
+// every workgroup from the previous histogram (the same data, so the same
+// choice), which saves a launch per pass; three histograms rotate so that the
+// one being cleared is never read or written in the same pass.  All requested
+// probabilities advance together.  TVaR_p = (sum of the values above v +
+// (m - c_gt) v) / m, with v = PML_p and c_gt the count above it.  Sums are
+// double-double, reduced in a fixed order (deterministic), and the product
+// (m - c_gt) v is added exactly via fma.
 #include "ara_internal.hpp"
 
 namespace ara {
@@ -33,12 +36,15 @@ struct Scratch {
     double* part_hi;      // [kMaxProbs + 1][kSumBlocks]
     double* part_lo;
     int64_t* part_cnt;
-    uint32_t* hist;       // [n_probs][kBins]
-    SelState* st;         // [n_probs]
+    uint32_t* hist;       // [3][kMaxProbs][kBins]: pass k fills hist[k % 3]
+    SelState* st;         // [2][kMaxProbs]: the state pass k uses is st[k & 1] (pass 0: st[0])
     uint32_t* flag;
 };
 
+constexpr int64_t kHistStride = int64_t(kMaxProbs) * kBins;   // one rotating histogram
+
 Scratch carve(void* base, int n_probs) {
+    (void)n_probs;
     char* p = static_cast<char*>(base);
     Scratch s;
     const int64_t np = static_cast<int64_t>(kMaxProbs + 1) * kSumBlocks;
@@ -49,9 +55,9 @@ Scratch carve(void* base, int n_probs) {
     s.part_cnt = reinterpret_cast<int64_t*>(p);
     p += np * sizeof(int64_t);
     s.hist = reinterpret_cast<uint32_t*>(p);
-    p += static_cast<int64_t>(n_probs) * kBins * sizeof(uint32_t);
+    p += 3 * kHistStride * sizeof(uint32_t);
     s.st = reinterpret_cast<SelState*>(p);
-    p += static_cast<int64_t>(kMaxProbs) * sizeof(SelState);
+    p += 2 * kMaxProbs * sizeof(SelState);
     s.flag = reinterpret_cast<uint32_t*>(p);
     return s;
 }
@@ -86,76 +92,77 @@ __device__ __forceinline__ void block_reduce_dd(double& hi, double& lo, int64_t&
     }
 }
 
-// mode 0: sum of all values (slot 0); mode 1: for each prob q, sum and
-// count of the values strictly above its selected threshold (slot 1 + q)
-template <int MODE>
-__global__ __launch_bounds__(256) void partial_sums_kernel(const double* __restrict__ x, int64_t n,
-                                                           Scratch s, int n_probs) {
-    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
-    const int64_t tid = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    const int nq = MODE == 0 ? 1 : n_probs;
-    for (int q = 0; q < nq; ++q) {
-        double hi = 0.0, lo = 0.0;
-        int64_t cnt = 0;
-        const uint64_t thr = MODE == 0 ? 0 : s.st[q].prefix;
-        for (int64_t i = tid; i < n; i += stride) {
-            const double v = x[i];
-            if (MODE == 0) {
-                dd_add(hi, lo, v);
-            } else if (key_of(v) > thr) {
-                dd_add(hi, lo, v);
-                cnt += 1;
-            }
-        }
-        block_reduce_dd(hi, lo, cnt);
-        if (threadIdx.x == 0) {
-            const int slot = MODE == 0 ? 0 : 1 + q;
-            s.part_hi[slot * kSumBlocks + blockIdx.x] = hi;
-            s.part_lo[slot * kSumBlocks + blockIdx.x] = lo;
-            s.part_cnt[slot * kSumBlocks + blockIdx.x] = cnt;
-        }
-        __syncthreads();
-    }
-}
-
-template <int MODE>
-__global__ __launch_bounds__(64) void final_sums_kernel(Scratch s, int n_probs, int n_part, int64_t n,
-                                                        MetricsOut out) {
-    const int nq = MODE == 0 ? 1 : n_probs;
-    const bool bad = *s.flag != 0;
-    for (int q = 0; q < nq; ++q) {
-        const int slot = MODE == 0 ? 0 : 1 + q;
-        double hi = 0.0, lo = 0.0;
-        int64_t cnt = 0;
-        for (int i = threadIdx.x; i < n_part; i += kWave) {
-            dd_merge(hi, lo, s.part_hi[slot * kSumBlocks + i], s.part_lo[slot * kSumBlocks + i]);
-            cnt += s.part_cnt[slot * kSumBlocks + i];
-        }
-        group_reduce_dd(hi, lo, kWave);
-        for (int off = 32; off >= 1; off >>= 1) cnt += __shfl_xor(cnt, off, kWave);
-        if (threadIdx.x == 0) {
-            const double nan = __longlong_as_double(0x7ff8000000000000LL);
-            if (MODE == 0) {
-                *out.mean = bad ? nan : (hi + lo) / static_cast<double>(n);
-            } else {
-                const SelState st = s.st[q];
-                const double v = __longlong_as_double(static_cast<long long>(st.prefix));
-                const double r = static_cast<double>(st.m - cnt);   // copies of v in the top m
-                const double p = r * v;
-                const double pe = fma(r, v, -p);                   // exact product p + pe
-                dd_merge(hi, lo, p, pe);
-                out.pml[q * out.stride] = bad ? nan : v;
-                out.tvar[q * out.stride] = bad ? nan : (hi + lo) / static_cast<double>(st.m);
-            }
-        }
-    }
-}
-
 struct MArgs {
     int64_t m[kMaxProbs];
 };
 
-// resets the selection state and clears the histograms with plain stores
+// Choose the digit of `pass` for one probability from that pass's histogram
+// h, starting from the state st the pass used: the digit (from the top)
+// whose bin holds the k-th largest remaining value.  Every thread of the
+// 256-thread workgroup calls it and gets the new state.
+__device__ SelState choose_digit(const uint32_t* __restrict__ h, SelState st, int pass) {
+    __shared__ uint64_t scan[256];
+    __shared__ SelState out;
+    const int nb = 1 << kBits[pass];
+    const int per = (nb + 255) / 256;                    // 16 (12-bit digits) or 1 (the last, 4-bit)
+    // thread i owns bins [nb - per (i+1), nb - per i): thread 0 the largest digits
+    const int hiBin = nb - per * threadIdx.x;
+    const int loBin = hiBin - per;
+    uint32_t cnt[16];
+    if (per == 16) {                                      // 16 aligned bins: four 16-byte loads
+        const u32x4* v = reinterpret_cast<const u32x4*>(h + loBin);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const u32x4 t = v[k];
+            cnt[4 * k] = t.x;
+            cnt[4 * k + 1] = t.y;
+            cnt[4 * k + 2] = t.z;
+            cnt[4 * k + 3] = t.w;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < 16; ++k) cnt[k] = (k < per && loBin + k >= 0) ? h[loBin + k] : 0u;
+    }
+    uint64_t local = 0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) local += cnt[k];
+    if (threadIdx.x == 0) out = st;       // unchanged unless a bin is chosen (k beyond the count)
+    scan[threadIdx.x] = local;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        uint64_t add = threadIdx.x >= off ? scan[threadIdx.x - off] : 0;
+        __syncthreads();
+        scan[threadIdx.x] += add;
+        __syncthreads();
+    }
+    const uint64_t incl = scan[threadIdx.x];
+    const uint64_t excl = incl - local;
+    const uint64_t k = static_cast<uint64_t>(st.k);
+    if (excl < k && k <= incl) {
+        uint64_t cum = excl;
+        for (int i = per - 1; i >= 0; --i) {              // from this thread's largest digit down
+            const uint64_t c = cnt[i];
+            if (cum + c >= k) {
+                const int b = loBin + i;
+                const int shift = kShift[pass];
+                const uint64_t dmask = (uint64_t(1) << kBits[pass]) - 1;
+                SelState r = st;
+                r.k = static_cast<int64_t>(k - cum);
+                r.prefix = st.prefix | (static_cast<uint64_t>(b) << shift);
+                r.mask = st.mask | (dmask << shift);
+                out = r;
+                break;
+            }
+            cum += c;
+        }
+    }
+    __syncthreads();
+    const SelState r = out;
+    __syncthreads();
+    return r;
+}
+
+// resets the selection state and clears the first histogram with plain stores
 __global__ void select_init_kernel(Scratch s, MArgs ma, int n_probs) {
     const int tid = blockIdx.x * blockDim.x + threadIdx.x;
     if (tid < n_probs) {
@@ -168,17 +175,36 @@ __global__ void select_init_kernel(Scratch s, MArgs ma, int n_probs) {
     for (int i = tid; i < n_probs * kBins; i += gridDim.x * blockDim.x) s.hist[i] = 0;
 }
 
+// Pass `pass` of the radix select (and, in pass 0, the sum for the mean):
+// finish the previous pass's digit choice, clear the histogram the next pass
+// fills, and count this pass's digits of the values matching the prefix.
 __global__ __launch_bounds__(256) void histogram_kernel(const double* __restrict__ x, int64_t n, Scratch s,
                                                         int n_probs, int pass, int with_mean) {
     extern __shared__ uint32_t lds_hist[];   // [n_probs][kBins]
+    __shared__ SelState cur[kMaxProbs];
     for (int i = threadIdx.x; i < n_probs * kBins; i += blockDim.x) lds_hist[i] = 0;
+    for (int q = 0; q < n_probs; ++q) {
+        SelState st = s.st[q];                          // pass 0: the initial state
+        if (pass > 0) {
+            st = s.st[((pass - 1) & 1) * kMaxProbs + q];
+            st = choose_digit(s.hist + ((pass - 1) % 3) * kHistStride + int64_t(q) * kBins, st, pass - 1);
+            if (blockIdx.x == 0 && threadIdx.x == 0) s.st[(pass & 1) * kMaxProbs + q] = st;
+        }
+        if (threadIdx.x == 0) cur[q] = st;
+    }
+    {   // the histogram pass + 1 fills: last used two passes ago, so nobody touches it now
+        uint32_t* nxt = s.hist + ((pass + 1) % 3) * kHistStride;
+        const int64_t per = (int64_t(n_probs) * kBins + gridDim.x - 1) / gridDim.x;
+        const int64_t b0 = per * blockIdx.x;
+        for (int64_t i = b0 + threadIdx.x; i < b0 + per && i < int64_t(n_probs) * kBins; i += blockDim.x) nxt[i] = 0;
+    }
     __syncthreads();
     const int shift = kShift[pass];
     const uint64_t dmask = (uint64_t(1) << kBits[pass]) - 1;
     uint64_t pre[kMaxProbs], msk[kMaxProbs];
     for (int q = 0; q < n_probs; ++q) {
-        pre[q] = s.st[q].prefix;
-        msk[q] = s.st[q].mask;
+        pre[q] = cur[q].prefix;
+        msk[q] = cur[q].mask;
     }
     const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
     uint32_t bad = 0;
@@ -212,61 +238,102 @@ __global__ __launch_bounds__(256) void histogram_kernel(const double* __restrict
         }
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < n_probs * kBins; i += blockDim.x) {
-        const uint32_t c = lds_hist[i];
-        if (c) atomicAdd(&s.hist[i], c);
+    uint32_t* h = s.hist + (pass % 3) * kHistStride;
+    for (int k = threadIdx.x; k < n_probs * kBins; k += blockDim.x) {
+        const uint32_t c = lds_hist[k];
+        if (c) atomicAdd(&h[k], c);
     }
 }
 
-// one workgroup of 256 threads per probability: choose the digit holding the
-// k-th largest remaining value, then clear the histogram for the next pass
-__global__ __launch_bounds__(256) void select_digit_kernel(Scratch s, int pass) {
-    const int q = blockIdx.x;
-    uint32_t* h = s.hist + static_cast<int64_t>(q) * kBins;
-    const int nb = 1 << kBits[pass];
-    const int per = (nb + 255) / 256;
-    // thread i owns bins [nb - per (i+1), nb - per i): thread 0 the largest digits
-    const int hiBin = nb - per * threadIdx.x;
-    const int loBin = hiBin - per;
-    uint64_t local = 0;
-    for (int b = hiBin - 1; b >= loBin && b >= 0; --b) local += h[b];
-    __shared__ uint64_t scan[256];
-    scan[threadIdx.x] = local;
-    __syncthreads();
-    for (int off = 1; off < 256; off <<= 1) {
-        uint64_t add = threadIdx.x >= off ? scan[threadIdx.x - off] : 0;
-        __syncthreads();
-        scan[threadIdx.x] += add;
-        __syncthreads();
-    }
-    const uint64_t incl = scan[threadIdx.x];
-    const uint64_t excl = incl - local;
-    const SelState st = s.st[q];
-    const uint64_t k = static_cast<uint64_t>(st.k);
-    __syncthreads();
-    if (excl < k && k <= incl) {
-        uint64_t cum = excl;
-        for (int b = hiBin - 1; b >= loBin && b >= 0; --b) {
-            const uint64_t c = h[b];
-            if (cum + c >= k) {
-                const int shift = kShift[pass];
-                const uint64_t dmask = (uint64_t(1) << kBits[pass]) - 1;
-                s.st[q].k = static_cast<int64_t>(k - cum);
-                s.st[q].prefix = st.prefix | (static_cast<uint64_t>(b) << shift);
-                s.st[q].mask = st.mask | (dmask << shift);
-                break;
-            }
-            cum += c;
+// After the last pass: every workgroup chooses the last digit (block 0 keeps
+// the final state in st[0]), then sums and counts, for each probability, the
+// values strictly above its threshold (slot 1 + q).
+__global__ __launch_bounds__(256) void tail_sums_kernel(const double* __restrict__ x, int64_t n, Scratch s,
+                                                        int n_probs) {
+    __shared__ uint64_t thr_s[kMaxProbs];
+    constexpr int last = kPasses - 1;
+    for (int q = 0; q < n_probs; ++q) {
+        SelState st = s.st[(last & 1) * kMaxProbs + q];
+        st = choose_digit(s.hist + (last % 3) * kHistStride + int64_t(q) * kBins, st, last);
+        if (threadIdx.x == 0) {
+            thr_s[q] = st.prefix;
+            if (blockIdx.x == 0) s.st[((last + 1) & 1) * kMaxProbs + q] = st;
         }
     }
     __syncthreads();
-    for (int b = threadIdx.x; b < kBins; b += 256) h[b] = 0;
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+    const int64_t tid = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    for (int q = 0; q < n_probs; ++q) {
+        double hi = 0.0, lo = 0.0;
+        int64_t cnt = 0;
+        const uint64_t thr = thr_s[q];
+        auto take = [&](double v) {
+            if (key_of(v) > thr) {
+                dd_add(hi, lo, v);
+                cnt += 1;
+            }
+        };
+        int64_t i = tid;
+        for (; i + 3 * stride < n; i += 4 * stride) {
+            const double v0 = x[i], v1 = x[i + stride], v2 = x[i + 2 * stride], v3 = x[i + 3 * stride];
+            take(v0);
+            take(v1);
+            take(v2);
+            take(v3);
+        }
+        for (; i < n; i += stride) take(x[i]);
+        block_reduce_dd(hi, lo, cnt);
+        if (threadIdx.x == 0) {
+            s.part_hi[(1 + q) * kSumBlocks + blockIdx.x] = hi;
+            s.part_lo[(1 + q) * kSumBlocks + blockIdx.x] = lo;
+            s.part_cnt[(1 + q) * kSumBlocks + blockIdx.x] = cnt;
+        }
+        __syncthreads();
+    }
 }
 
-__global__ void tail_finish_kernel(Scratch s, TailStats* out) {
+// one workgroup: the mean from the pass-0 partials, then PML and TVaR per
+// probability from the tail partials (fixed reduction order)
+__global__ __launch_bounds__(256) void final_kernel(Scratch s, int n_probs, int n_mean_part, int n_tail_part,
+                                                    int64_t n, MetricsOut out) {
+    const bool bad = *s.flag != 0;
+    const double nan = __longlong_as_double(0x7ff8000000000000LL);
+    for (int slot = 0; slot <= n_probs; ++slot) {
+        const int np = slot == 0 ? n_mean_part : n_tail_part;
+        double hi = 0.0, lo = 0.0;
+        int64_t cnt = 0;
+        for (int i = threadIdx.x; i < np; i += blockDim.x) {
+            dd_merge(hi, lo, s.part_hi[slot * kSumBlocks + i], s.part_lo[slot * kSumBlocks + i]);
+            cnt += s.part_cnt[slot * kSumBlocks + i];
+        }
+        block_reduce_dd(hi, lo, cnt);
+        if (threadIdx.x == 0) {
+            if (slot == 0) {
+                *out.mean = bad ? nan : (hi + lo) / static_cast<double>(n);
+            } else {
+                const int q = slot - 1;
+                const SelState st = s.st[((kPasses) & 1) * kMaxProbs + q];
+                const double v = __longlong_as_double(static_cast<long long>(st.prefix));
+                const double r = static_cast<double>(st.m - cnt);   // copies of v in the top m
+                const double p = r * v;
+                const double pe = fma(r, v, -p);                   // exact product p + pe
+                dd_merge(hi, lo, p, pe);
+                out.pml[q * out.stride] = bad ? nan : v;
+                out.tvar[q * out.stride] = bad ? nan : (hi + lo) / static_cast<double>(st.m);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// one workgroup: the final digit for the single tail count, into `out`
+__global__ __launch_bounds__(256) void tail_finish_kernel(Scratch s, TailStats* out) {
+    constexpr int last = kPasses - 1;
+    SelState st = s.st[(last & 1) * kMaxProbs];
+    st = choose_digit(s.hist + (last % 3) * kHistStride, st, last);
     if (threadIdx.x == 0) {
-        out->v_bits = s.st[0].prefix;
-        out->m = s.st[0].m;
+        out->v_bits = st.prefix;
+        out->m = st.m;
         out->c_gt = 0;
         out->c_eq = 0;
     }
@@ -295,15 +362,16 @@ __global__ __launch_bounds__(256) void tail_count_kernel(const double* __restric
 }  // namespace
 
 int64_t metrics_scratch_bytes(int n_probs) {
+    (void)n_probs;
     const int64_t np = static_cast<int64_t>(kMaxProbs + 1) * kSumBlocks;
-    return np * (2 * sizeof(double) + sizeof(int64_t)) +
-           static_cast<int64_t>(n_probs) * kBins * sizeof(uint32_t) + kMaxProbs * sizeof(SelState) +
-           64;
+    return np * (2 * sizeof(double) + sizeof(int64_t)) + 3 * kHistStride * sizeof(uint32_t) +
+           2 * kMaxProbs * sizeof(SelState) + 64;
 }
 
 hipError_t launch_metrics(const double* ylt, int64_t n, const int64_t* m_host, int n_probs,
                           void* scratch, MetricsOut out, int n_cu, hipStream_t st) {
     if (n_probs > kMaxProbs) return hipErrorInvalidValue;
+    (void)n_cu;
     Scratch s = carve(scratch, n_probs);
     MArgs ma{};
     for (int q = 0; q < n_probs; ++q) ma.m[q] = m_host[q];
@@ -315,30 +383,23 @@ hipError_t launch_metrics(const double* ylt, int64_t n, const int64_t* m_host, i
     int hblocks = static_cast<int>((n + 2047) / 2048);
     if (hblocks > kSumBlocks) hblocks = kSumBlocks;
     if (hblocks < 1) hblocks = 1;
-    (void)n_cu;
     const size_t lds = sizeof(uint32_t) * kBins * (n_probs > 0 ? n_probs : 1);
     const int passes = n_probs > 0 ? kPasses : 1;
     for (int pass = 0; pass < passes; ++pass) {
         hipLaunchKernelGGL(histogram_kernel, dim3(hblocks), dim3(256), lds, st, ylt, n, s, n_probs, pass,
                            pass == 0 ? 1 : 0);
         if ((err = hipGetLastError()) != hipSuccess) return err;
-        if (n_probs > 0) {
-            hipLaunchKernelGGL(select_digit_kernel, dim3(n_probs), dim3(256), 0, st, s, pass);
-            if ((err = hipGetLastError()) != hipSuccess) return err;
-        }
     }
-    hipLaunchKernelGGL((final_sums_kernel<0>), dim3(1), dim3(64), 0, st, s, n_probs, hblocks, n, out);
-    if ((err = hipGetLastError()) != hipSuccess) return err;
+    int tblocks = 1;
     if (n_probs > 0) {
-        int blocks = static_cast<int>((n + 1023) / 1024);
-        if (blocks > kSumBlocks) blocks = kSumBlocks;
-        if (blocks < 1) blocks = 1;
-        hipLaunchKernelGGL((partial_sums_kernel<1>), dim3(blocks), dim3(256), 0, st, ylt, n, s, n_probs);
-        if ((err = hipGetLastError()) != hipSuccess) return err;
-        hipLaunchKernelGGL((final_sums_kernel<1>), dim3(1), dim3(64), 0, st, s, n_probs, blocks, n, out);
+        tblocks = static_cast<int>((n + 1023) / 1024);
+        if (tblocks > kSumBlocks) tblocks = kSumBlocks;
+        if (tblocks < 1) tblocks = 1;
+        hipLaunchKernelGGL(tail_sums_kernel, dim3(tblocks), dim3(256), 0, st, ylt, n, s, n_probs);
         if ((err = hipGetLastError()) != hipSuccess) return err;
     }
-    return hipSuccess;
+    hipLaunchKernelGGL(final_kernel, dim3(1), dim3(256), 0, st, s, n_probs, hblocks, tblocks, n, out);
+    return hipGetLastError();
 }
 
 }  // namespace ara
@@ -355,19 +416,20 @@ hipError_t launch_tail_stats(const double* ylt, int64_t n, int64_t m, void* scra
     hipError_t err;
     hipLaunchKernelGGL(select_init_kernel, dim3(16), dim3(256), 0, st, s, ma, 1);
     if ((err = hipGetLastError()) != hipSuccess) return err;
-    int hblocks = static_cast<int>((n + 1023) / 1024);
-    if (hblocks > 2 * n_cu) hblocks = 2 * n_cu;
+    int hblocks = static_cast<int>((n + 2047) / 2048);
+    if (hblocks > kSumBlocks) hblocks = kSumBlocks;
     if (hblocks < 1) hblocks = 1;
     for (int pass = 0; pass < kPasses; ++pass) {
         hipLaunchKernelGGL(histogram_kernel, dim3(hblocks), dim3(256), sizeof(uint32_t) * kBins, st, ylt, n, s,
                            1, pass, 0);
         if ((err = hipGetLastError()) != hipSuccess) return err;
-        hipLaunchKernelGGL(select_digit_kernel, dim3(1), dim3(256), 0, st, s, pass);
-        if ((err = hipGetLastError()) != hipSuccess) return err;
     }
-    hipLaunchKernelGGL(tail_finish_kernel, dim3(1), dim3(64), 0, st, s, out);
+    hipLaunchKernelGGL(tail_finish_kernel, dim3(1), dim3(256), 0, st, s, out);
     if ((err = hipGetLastError()) != hipSuccess) return err;
-    hipLaunchKernelGGL(tail_count_kernel, dim3(hblocks), dim3(256), 0, st, ylt, n, out);
+    int cblocks = static_cast<int>((n + 1023) / 1024);
+    if (cblocks > 2 * n_cu) cblocks = 2 * n_cu;
+    if (cblocks < 1) cblocks = 1;
+    hipLaunchKernelGGL(tail_count_kernel, dim3(cblocks), dim3(256), 0, st, ylt, n, out);
     return hipGetLastError();
 }
 
