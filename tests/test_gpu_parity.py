@@ -355,6 +355,28 @@ def test_multi_part_catalogue_and_layouts(ara):
     plain.close()
 
 
+def test_more_parts_than_xcds(ara):
+    """A catalogue of 11 parts of 2^18 events: workgroups of the XCD-affine
+    pass serve two parts in turn (reloading the part image and the LDS loss
+    cache), part sizes are ragged at the end, and each part holds more nonzero
+    losses than the LDS cache, so both the cached and the L2 values are read.
+    The rank-based pass variant is checked on the same inputs."""
+    C = 2_700_000
+    yet = make_yet(700, 120.0, C, seed=51)
+    pool = make_elt_pool(4, C, 120_000, seed=52)
+    tables = ara.create_tables(yet.offsets, yet.ids, pool.losses)
+    for begin, count in ((0, yet.n_trials), (300, 257), (511, 2)):
+        layer = Layer(np.array([3, 1, 0], dtype=np.int32), 1500.0, 4.0e5, 5.0e4, 6.0e5, begin, count)
+        spec = _spec(ara, layer, pool, yet)
+        ref, _ = oracle.run_layer(yet, pool, layer)
+        for knobs in (dict(pass_variant=0), dict(pass_variant=1, part_lanes_per_trial=16)):
+            ara.set_tuning(tables, **knobs)
+            ylt = ara.run_layers(tables, [spec])
+            ok, worst = _close(ylt, ref)
+            assert ok, (begin, count, knobs, worst)
+    tables.close()
+
+
 # ---------------------------------------------------------------------------
 # paper-scale share (1M trials x Poisson(1000), 16 ELTs): sampled parity
 # ---------------------------------------------------------------------------
