@@ -48,6 +48,9 @@ def parse():
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the multi-tenant serving study (config 4)")
     ap.add_argument("--serving-per-tenant", type=int, default=6)
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the 64-layer batched run (config 2)")
+    ap.add_argument("--batched-steps", type=int, default=5)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (reference for counter scaling)")
     return ap.parse_args()
@@ -77,6 +80,43 @@ def measured_traffic():
     if rec.get("kernel_source_sha256") != src:
         return None
     return rec.get("traffic_bytes_per_launch")
+
+
+def batched_study(ara, tables, w, library, steps, stream):
+    """All 64 layers of the shared-YET library in one call: the batched
+    persistent pass replayed from a HIP graph, and one launch sequence per
+    layer, each timed with HIP events over `steps` runs."""
+    import torch
+    off = w.yet.offsets
+    lookups = sum(float(off[l.trial_begin + l.trial_count] - off[l.trial_begin]) * l.n_elts for l in library)
+    events = sum(float(off[l.trial_begin + l.trial_count] - off[l.trial_begin]) for l in library)
+    total = sum(l.trial_count for l in library)
+    C = w.yet.catalogue_size
+    out = torch.empty(total, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.Stream()            # graph capture needs a stream of its own
+    res = {"layers": len(library), "lookups": lookups, "ylt_values": total}
+    # Alg. 1 order (a YET pass per layer) and a fused single pass, as algorithmic bytes
+    res["alg1_bytes"] = 4.0 * events + sum(8.0 * l.n_elts * C + 16.0 * l.trial_count for l in library)
+    res["fused_bytes"] = 4.0 * w.yet.n_events + 8.0 * len({int(j) for l in library for j in l.elt_index}) * C \
+        + 8.0 * total
+    for name, flags in (("graph", ara.ARA_GRAPH), ("per_layer", ara.ARA_PER_LAYER)):
+        torch.cuda.synchronize()
+        for _ in range(2):
+            ara.run_layers(tables, library, out=out, flags=flags, stream=stream)
+        stream.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(steps):
+            ara.run_layers(tables, library, out=out, flags=flags, stream=stream)
+        b.record(stream)
+        stream.synchronize()
+        ms = a.elapsed_time(b) / steps
+        res[name] = {"ms": round(ms, 3), "lookups_per_s": lookups / (ms / 1e3),
+                     "pct_hbm_fused_bytes": round(res["fused_bytes"] / (ms / 1e3) / (HBM_PEAK_GBS * 1e9), 4)}
+        log(f"batched 64 layers ({name}): {ms:.3f} ms, {lookups / (ms / 1e3):.3e} lookups/s")
+    del out
+    return res
 
 
 def main() -> None:
@@ -219,18 +259,22 @@ def main() -> None:
     tables.close()
     del out, res
     serving = None
-    if not args.no_serving:
-        from paper_1606_04473_amd import serving as srv
+    batched = None
+    if not (args.no_serving and args.no_batched):
         t1 = time.time()
         w4 = make_config("config4")
         base = ara.create_tables(w4.yet.offsets, w4.yet.ids, w4.pool.losses)
         library = [ara.LayerSpec.from_layer(l, w4.pool, w4.yet.n_trials) for l in w4.layers]
-        log(f"config4 tables resident ({base.bytes() / 1e9:.2f} GB) in {time.time() - t1:.1f}s")
-        serving = srv.run_tenant_study(base, w4.yet.offsets, w4.yet.ids, library, n_tenants=8,
-                                       per_tenant=args.serving_per_tenant, log=log)
+        log(f"config2/4 tables resident ({base.bytes() / 1e9:.2f} GB) in {time.time() - t1:.1f}s")
+        if not args.no_batched:
+            batched = batched_study(ara, base, w4, library, args.batched_steps, stream)
+        if not args.no_serving:
+            from paper_1606_04473_amd import serving as srv
+            serving = srv.run_tenant_study(base, w4.yet.offsets, w4.yet.ids, library, n_tenants=8,
+                                           per_tenant=args.serving_per_tenant, log=log)
+            extra["tenant_p99_ms"] = serving["concurrent_8t"]["p99_ms"]
+            extra["tenant_p99_ms_single_tenant"] = serving["concurrent_1t"]["p99_ms"]
         base.close()
-        extra["tenant_p99_ms"] = serving["concurrent_8t"]["p99_ms"]
-        extra["tenant_p99_ms_single_tenant"] = serving["concurrent_1t"]["p99_ms"]
 
     line = {
         "metric": "event-ELT lookups/s + % HBM peak (1M×1000 YET); grad/fwd time; tenant p99",
@@ -253,6 +297,8 @@ def main() -> None:
         "cpu_baseline": cpu,
     }
     line.update(extra)
+    if batched is not None:
+        line["batched_config2"] = batched
     if serving is not None:
         line["serving"] = serving
     print(json.dumps(line), flush=True)

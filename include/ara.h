@@ -56,14 +56,18 @@ typedef int32_t ara_status;
                                        per-event occurrence loss computed for the whole catalogue */
 #define ARA_CHECKPOINT_S (1u << 2)  /* ara_run_layers: keep each trial's annual total S_t and
                                        YLT_t inside the tables for ara_backward */
-#define ARA_PER_LAYER    (1u << 3)  /* ara_run_layers with several layers: one launch sequence per
-                                       layer instead of the batched launch (a fold per layer, then
-                                       one persistent pass over a (layer, tile) work list sorted by
-                                       decreasing cost) */
-#define ARA_GRAPH        (1u << 4)  /* ara_run_layers with several layers: replay a HIP graph of the
-                                       batched launch, captured on first use for this shape (layer
-                                       count, ELT counts, trial ranges, output pointer); terms may
-                                       change between replays.  Requires a device output. */
+#define ARA_PER_LAYER    (1u << 3)  /* ara_run_layers with several layers and pass_variant 1: one
+                                       launch sequence per layer instead of the batched launch (a
+                                       fold per layer, then one persistent pass over a (layer, tile)
+                                       work list sorted by decreasing cost).  With pass_variant 0
+                                       (the default) layers always run one sequence each. */
+#define ARA_GRAPH        (1u << 4)  /* ara_run_layers: replay a HIP graph of the whole call, captured
+                                       on first use for this shape (layer count, trial ranges,
+                                       output pointer; with pass_variant 1 also the ELT counts) --
+                                       the per-layer sequences, or with pass_variant 1 and several
+                                       layers the batched launch.  Terms and ELT choices may change
+                                       between replays.  Requires a device output and a non-null
+                                       stream (ARA_ERR_INVALID_ARG otherwise). */
 #define ARA_PROFILE      (1u << 5)  /* ara_run_layers: bracket each kernel with HIP events on the
                                        call's stream; read the totals with ara_kernel_stats */
 

@@ -643,9 +643,14 @@ ara_status ara_run_layers(ara_tables* t, const ara_layer* layers, int32_t n_laye
     // the XCD-affine pass (default) writes per-part partial sums; pass_variant 1
     // selects the rank-based pass with the compact value array
     const bool use_xcd = use_parts && tu.pass_variant == 0;
-    const bool batched = n_layers > 1 && !(flags & ARA_PER_LAYER) && !literal && !ckpt && t->parts.P > 0;
+    // several layers run as one persistent rank-based launch with pass_variant
+    // 1; with the XCD-affine pass (the default) they run one launch sequence
+    // per layer, which ARA_GRAPH captures and replays as a whole
+    const bool batched = n_layers > 1 && !(flags & ARA_PER_LAYER) && !literal && !ckpt && t->parts.P > 0 &&
+                         tu.pass_variant == 1;
+    const bool xgraph = (flags & ARA_GRAPH) && use_xcd && !ckpt;
     // one kept scratch buffer for the per-layer path: occurrence losses, part
-    // images, partial sums (the batched path keeps its own)
+    // images, partial sums (the batched path and graphs keep their own)
     auto up = [](size_t n) { return (n + 255) & ~size_t(255); };
     const size_t o_bytes = literal ? 0 : up(sizeof(double) * t->C);
     const size_t p_bytes = use_parts ? up(static_cast<size_t>(ara::part_scratch_bytes(t->C, t->parts.P))) : 0;
@@ -658,7 +663,7 @@ ara_status ara_run_layers(ara_tables* t, const ara_layer* layers, int32_t n_laye
     ScratchLease lease(t->scratch_mu);
     lease.s = s;
     char* base = nullptr;
-    if (!batched) {
+    if (!batched && !xgraph) {
         HIP_TRY(scratch_acquire(t->scratch_mu, t->scratch, o_bytes + p_bytes + x_bytes + 256, s, &lease.b),
                 "scratch for occurrence losses, part images and partial sums");
         base = static_cast<char*>(lease.b->p);
@@ -692,8 +697,77 @@ ara_status ara_run_layers(ara_tables* t, const ara_layer* layers, int32_t n_laye
         }
         S_buf = ck.S;
     }
-    if ((flags & ARA_GRAPH) && batched && (!dev_out || s == nullptr))
+    if ((flags & ARA_GRAPH) && (batched || xgraph) && (!dev_out || s == nullptr))
         return fail(ARA_ERR_INVALID_ARG, "ARA_GRAPH needs a device output and a non-null stream");
+    if (xgraph) {
+        // key: layer count, output, trial ranges (terms and ELT choices may change)
+        std::vector<int64_t> key{-1, static_cast<int64_t>(n_layers), reinterpret_cast<int64_t>(out)};   // -1: not a batched plan
+        int64_t most = 0;
+        for (int i = 0; i < n_layers; ++i) {
+            key.push_back(L[i].trial_begin);
+            key.push_back(L[i].trial_count);
+            most = std::max(most, L[i].trial_count);
+        }
+        const size_t la_bytes = up(sizeof(ara::LayerArgs) * n_layers);
+        const size_t xg_bytes = up(sizeof(double) * 2 * t->parts.P * (most > 0 ? most : 1));
+        const bool prof = (flags & ARA_PROFILE) != 0;
+        std::lock_guard<std::mutex> g(t->stage_mu);
+        ara::GraphEntry* ge = nullptr;
+        for (auto* c : t->graphs)
+            if (c->key == key) ge = c;
+        auto upload = [&](ara::GraphEntry* e) -> hipError_t {
+            hipError_t r = stage_acquire(e->stage, sizeof(ara::LayerArgs) * n_layers);
+            if (r != hipSuccess) return r;
+            std::memcpy(e->stage.p, L.data(), sizeof(ara::LayerArgs) * n_layers);
+            if ((r = hipMemcpyAsync(e->scratch, e->stage.p, sizeof(ara::LayerArgs) * n_layers, hipMemcpyHostToDevice,
+                                    s)) != hipSuccess)
+                return r;
+            return hipEventRecord(e->stage.done, s);
+        };
+        if (!ge) {
+            ge = new ara::GraphEntry();
+            ge->key = key;
+            hipError_t e = hipMalloc(&ge->scratch, la_bytes + o_bytes + p_bytes + xg_bytes);
+            if (e != hipSuccess) {
+                free_graph(ge);
+                return hip_fail(e, "graph scratch");
+            }
+            char* gb = static_cast<char*>(ge->scratch);
+            const ara::LayerArgs* dL = reinterpret_cast<const ara::LayerArgs*>(gb);
+            double* go = reinterpret_cast<double*>(gb + la_bytes);
+            void* gp = gb + la_bytes + o_bytes;
+            double* gx = reinterpret_cast<double*>(gb + la_bytes + o_bytes + p_bytes);
+            if ((e = upload(ge)) != hipSuccess || (e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal)) !=
+                                                      hipSuccess) {
+                free_graph(ge);
+                return hip_fail(e, "graph capture");
+            }
+            hipError_t le = hipSuccess;
+            for (int i = 0; i < n_layers && le == hipSuccess; ++i) {
+                le = ara::launch_fold_parts(t->elts, t->C, L[i], dL + i, go, t->parts.P, gp, s);
+                if (le == hipSuccess) le = ara::launch_xcd_pass(t->parts, t->n_trials, t->C, L[i], gp, gx, t->n_cu, s);
+                if (le == hipSuccess)
+                    le = ara::launch_xcd_combine(t->parts, L[i], dL + i, gx, out + L[i].out_offset, nullptr, s);
+            }
+            e = hipStreamEndCapture(s, &ge->graph);
+            if (le != hipSuccess || e != hipSuccess ||
+                (e = hipGraphInstantiate(&ge->exec, ge->graph, nullptr, nullptr, 0)) != hipSuccess) {
+                free_graph(ge);
+                return hip_fail(le != hipSuccess ? le : e, "graph instantiate");
+            }
+            if (t->graphs.size() >= 8) {
+                free_graph(t->graphs.front());
+                t->graphs.erase(t->graphs.begin());
+            }
+            t->graphs.push_back(ge);
+        } else {
+            HIP_TRY(upload(ge), "upload layer terms");
+        }
+        KernelTimer kt(t, s, prof, ARA_KERNEL_BATCHED);
+        HIP_TRY(hipGraphLaunch(ge->exec, s), "graph launch");
+        kt.done();
+        return ARA_OK;
+    }
     if (batched) {
         BatchPlan plan = make_plan(t, L, out, tu.schedule);
         const int64_t n_items = static_cast<int64_t>(plan.items.size());
@@ -770,8 +844,8 @@ ara_status ara_run_layers(ara_tables* t, const ara_layer* layers, int32_t n_laye
         if (!literal) {
             KernelTimer kt(t, s, prof, ARA_KERNEL_FOLD);
             if (use_parts)
-                HIP_TRY(ara::launch_fold_parts(t->elts, t->C, L[i], static_cast<double*>(obuf.p), t->parts.P, pbuf.p,
-                                               s),
+                HIP_TRY(ara::launch_fold_parts(t->elts, t->C, L[i], nullptr, static_cast<double*>(obuf.p), t->parts.P,
+                                               pbuf.p, s),
                         "fold and part images");
             else
                 HIP_TRY(ara::launch_fold(t->elts, t->C, L[i], static_cast<double*>(obuf.p), tu, s), "fold");
@@ -784,7 +858,7 @@ ara_status ara_run_layers(ara_tables* t, const ara_layer* layers, int32_t n_laye
                     "XCD-affine trial pass");
             kp.done();
             KernelTimer kc(t, s, prof, ARA_KERNEL_COMBINE);
-            HIP_TRY(ara::launch_xcd_combine(t->parts, L[i], static_cast<const double*>(xbuf.p), a.ylt, a.S, s),
+            HIP_TRY(ara::launch_xcd_combine(t->parts, L[i], nullptr, static_cast<const double*>(xbuf.p), a.ylt, a.S, s),
                     "partial sums merge");
             kc.done();
             continue;

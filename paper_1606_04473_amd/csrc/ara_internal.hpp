@@ -329,14 +329,15 @@ hipError_t build_part_layout(const int64_t* offsets, const uint32_t* ids, int64_
 void free_part_layout(PartLayout* L);
 int64_t part_scratch_bytes(int64_t C, int P);
 hipError_t launch_part_fold(const double* o, int64_t C, int P, void* scratch, hipStream_t s, bool with_ranks);
-// the fold fused with the part images, then ranks and the compact array
-hipError_t launch_fold_parts(const double* elts, int64_t C, const LayerArgs& L, double* o, int P, void* scratch,
-                             hipStream_t s);
+// the fold fused with the part images, then ranks and the compact array; with
+// L_dev the terms are read from device memory (for graph replays), else from L
+hipError_t launch_fold_parts(const double* elts, int64_t C, const LayerArgs& L, const LayerArgs* L_dev, double* o,
+                             int P, void* scratch, hipStream_t s);
 // the XCD-affine pass writes per-part partial sums; the combine merges them
 hipError_t launch_xcd_pass(const PartLayout& lay, int64_t N, int64_t C, const LayerArgs& L, void* part_scratch,
                            double* partials, int n_cu, hipStream_t s);
-hipError_t launch_xcd_combine(const PartLayout& lay, const LayerArgs& L, const double* partials, double* ylt,
-                              double* S, hipStream_t s);
+hipError_t launch_xcd_combine(const PartLayout& lay, const LayerArgs& L, const LayerArgs* L_dev,
+                              const double* partials, double* ylt, double* S, hipStream_t s);
 hipError_t launch_part_pass(const PartLayout& lay, int64_t N, const LayerArgs& L, void* scratch, double* ylt,
                             double* S, int n_cu, hipStream_t s, int lpt);
 

@@ -199,9 +199,9 @@ __global__ __launch_bounds__(256) void part_image_kernel(const double* __restric
 // loads in flight), summing the ELTs of each event in layer order exactly as
 // the fold does, then writes o, the bitmap words, the per-128 ranks and the
 // superblock count.
-__global__ __launch_bounds__(256) void fold_image_kernel(const double* __restrict__ elts, int64_t C, LayerArgs L,
-                                                         double* __restrict__ o, uint8_t* __restrict__ img,
-                                                         uint32_t* __restrict__ sb_count) {
+__device__ __forceinline__ void fold_image_body(const double* __restrict__ elts, int64_t C, const LayerArgs& L,
+                                                double* __restrict__ o, uint8_t* __restrict__ img,
+                                                uint32_t* __restrict__ sb_count) {
     __shared__ uint32_t wc[64];
     const int64_t sb = blockIdx.x;
     const int64_t e0 = sb * kSuper;
@@ -250,6 +250,20 @@ __global__ __launch_bounds__(256) void fold_image_kernel(const double* __restric
         for (int k = 0; k < 64; ++k) total += wc[k];
         sb_count[sb] = total;
     }
+}
+
+// terms as kernel arguments (eager runs) or read from device memory (graph
+// replays, whose terms may change between replays)
+__global__ __launch_bounds__(256) void fold_image_kernel(const double* __restrict__ elts, int64_t C, LayerArgs L,
+                                                         double* __restrict__ o, uint8_t* __restrict__ img,
+                                                         uint32_t* __restrict__ sb_count) {
+    fold_image_body(elts, C, L, o, img, sb_count);
+}
+__global__ __launch_bounds__(256) void fold_image_dev_kernel(const double* __restrict__ elts, int64_t C,
+                                                             const LayerArgs* __restrict__ L, double* __restrict__ o,
+                                                             uint8_t* __restrict__ img,
+                                                             uint32_t* __restrict__ sb_count) {
+    fold_image_body(elts, C, *L, o, img, sb_count);
 }
 
 // exclusive scan of the superblock counts (one workgroup) into each part's
@@ -926,10 +940,14 @@ __global__ __launch_bounds__(1024) void xcd_pass_kernel(XcdPassArgs a) {
 
 __global__ __launch_bounds__(256) void xcd_combine_kernel(const double* __restrict__ part_hi,
                                                           const double* __restrict__ part_lo, int P, int64_t count,
-                                                          double aggR, double aggL, double* __restrict__ ylt,
-                                                          double* __restrict__ S_out) {
+                                                          double aggR, double aggL, const LayerArgs* __restrict__ L_dev,
+                                                          double* __restrict__ ylt, double* __restrict__ S_out) {
     const int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (k >= count) return;
+    if (L_dev) {                                    // terms from device memory (graph replays)
+        aggR = L_dev->aggR;
+        aggL = L_dev->aggL;
+    }
     double hi = 0.0, lo = 0.0;
     for (int p = 0; p < P; ++p) dd_merge(hi, lo, part_hi[p * count + k], part_lo[p * count + k]);
     const double S = hi + lo;
@@ -1085,13 +1103,17 @@ hipError_t launch_part_fold(const double* o, int64_t C, int P, void* scratch, hi
     return hipGetLastError();
 }
 
-hipError_t launch_fold_parts(const double* elts, int64_t C, const LayerArgs& L, double* o, int P, void* scratch,
-                             hipStream_t s) {
+hipError_t launch_fold_parts(const double* elts, int64_t C, const LayerArgs& L, const LayerArgs* L_dev, double* o,
+                             int P, void* scratch, hipStream_t s) {
     PartScratch ps = carve_parts(scratch, P);
     const int64_t n_sb = static_cast<int64_t>(P) * kBase32;
     hipError_t e;
-    hipLaunchKernelGGL(fold_image_kernel, dim3(static_cast<uint32_t>(n_sb)), dim3(256), 0, s, elts, C, L, o, ps.img,
-                       ps.sb_count);
+    if (L_dev)
+        hipLaunchKernelGGL(fold_image_dev_kernel, dim3(static_cast<uint32_t>(n_sb)), dim3(256), 0, s, elts, C, L_dev,
+                           o, ps.img, ps.sb_count);
+    else
+        hipLaunchKernelGGL(fold_image_kernel, dim3(static_cast<uint32_t>(n_sb)), dim3(256), 0, s, elts, C, L, o,
+                           ps.img, ps.sb_count);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(superblock_scan_kernel, dim3(1), dim3(1024), 0, s, ps.sb_count, n_sb, ps.img, int64_t(0));
     if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -1296,13 +1318,14 @@ hipError_t launch_xcd_pass(const PartLayout& lay, int64_t N, int64_t C, const La
     return hipGetLastError();
 }
 
-hipError_t launch_xcd_combine(const PartLayout& lay, const LayerArgs& L, const double* partials, double* ylt,
-                              double* S, hipStream_t s) {
+hipError_t launch_xcd_combine(const PartLayout& lay, const LayerArgs& L, const LayerArgs* L_dev,
+                              const double* partials, double* ylt, double* S, hipStream_t s) {
     if (L.trial_count <= 0) return hipSuccess;
     const int P = lay.P;
     const int64_t blocks = (L.trial_count + 255) / 256;
     hipLaunchKernelGGL(xcd_combine_kernel, dim3(static_cast<uint32_t>(blocks)), dim3(256), 0, s, partials,
-                       partials + static_cast<int64_t>(P) * L.trial_count, P, L.trial_count, L.aggR, L.aggL, ylt, S);
+                       partials + static_cast<int64_t>(P) * L.trial_count, P, L.trial_count, L.aggR, L.aggL, L_dev, ylt,
+                       S);
     return hipGetLastError();
 }
 

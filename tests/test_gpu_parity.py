@@ -497,8 +497,10 @@ def test_autograd_function_matches_oracle(ara, cfg0):
 
 
 def test_batched_layers_persistent_and_graph(ara):
-    """Layers with uneven ELT counts and trial ranges in one persistent launch
-    (and as a replayed HIP graph) equal the per-layer runs and the oracle."""
+    """Layers with uneven ELT counts and trial ranges in one call: per-layer
+    XCD-affine sequences (default) and the persistent rank-based launch
+    (pass_variant 1) equal the oracle, and their replayed HIP graphs equal the
+    eager runs bit for bit while the terms change between replays."""
     import torch
     C = 1_100_000
     yet = make_yet(3000, 120.0, C, seed=51)
@@ -515,26 +517,28 @@ def test_batched_layers_persistent_and_graph(ara):
     tables = ara.create_tables(yet.offsets, yet.ids, pool.losses)
     refs = [oracle.run_layer(yet, pool, l)[0] for l in layers]
     ref = np.concatenate(refs)
-    eager = ara.run_layers(tables, specs)
-    per = ara.run_layers(tables, specs, flags=ara.ARA_PER_LAYER)
-    ok, worst = _close(eager, ref)
-    assert ok, worst
-    assert np.array_equal(eager, per)
     out = torch.empty(ref.shape[0], dtype=torch.float64, device="cuda")
     stream = torch.cuda.Stream()
-    with torch.cuda.stream(stream):
-        for rep in range(4):
-            # change terms between replays: same shape, same graph
-            scaled = [s.with_theta(s.theta() * (1.0 + 0.01 * rep)) for s in specs]
-            expect = ara.run_layers(tables, scaled)                    # eager, host output
-            out.fill_(-1.0)
-            ara.run_layers(tables, scaled, out=out, flags=ara.ARA_GRAPH, stream=stream)
-            stream.synchronize()
-            got = out.cpu().numpy()
-            assert np.array_equal(got, expect), rep
-            _ = torch.ones(1000, device="cuda").sum().item()          # unrelated eager work between replays
-    with pytest.raises(ara.AraError):
-        ara.run_layers(tables, specs, flags=ara.ARA_GRAPH)            # host output refused
+    for variant in (0, 1):
+        ara.set_tuning(tables, pass_variant=variant, part_lanes_per_trial=16)
+        eager = ara.run_layers(tables, specs)
+        per = ara.run_layers(tables, specs, flags=ara.ARA_PER_LAYER)
+        ok, worst = _close(eager, ref)
+        assert ok, (variant, worst)
+        assert np.array_equal(eager, per), variant
+        with torch.cuda.stream(stream):
+            for rep in range(4):
+                # change terms between replays: same shape, same graph
+                scaled = [s.with_theta(s.theta() * (1.0 + 0.01 * rep)) for s in specs]
+                expect = ara.run_layers(tables, scaled)                    # eager, host output
+                out.fill_(-1.0)
+                ara.run_layers(tables, scaled, out=out, flags=ara.ARA_GRAPH, stream=stream)
+                stream.synchronize()
+                got = out.cpu().numpy()
+                assert np.array_equal(got, expect), (variant, rep)
+                _ = torch.ones(1000, device="cuda").sum().item()          # unrelated eager work between replays
+        with pytest.raises(ara.AraError):
+            ara.run_layers(tables, specs, flags=ara.ARA_GRAPH)            # host output refused
     tables.close()
 
 
