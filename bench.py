@@ -274,6 +274,10 @@ def main() -> None:
                                            per_tenant=args.serving_per_tenant, log=log)
             extra["tenant_p99_ms"] = serving["concurrent_8t"]["p99_ms"]
             extra["tenant_p99_ms_single_tenant"] = serving["concurrent_1t"]["p99_ms"]
+            # one analysis (the whole YET, 4 layers) split over 1-8 tenants: time,
+            # energy and the deployment model fitted on one tenant
+            serving["split"] = srv.split_study(base, w4.yet.offsets, srv.pin_ids(w4.yet.ids), library,
+                                               layer_ids=[0, 1, 2, 3], log=log)
         base.close()
 
     line = {

@@ -334,3 +334,262 @@ def run_tenant_study(base, offsets, ids, library, n_tenants: int = 8, per_tenant
                 log(f"serving {mode} tenants={k}: p50 {summ['p50_ms']:.1f} ms p99 {summ['p99_ms']:.1f} ms "
                     f"{summ['throughput_req_s']:.2f} req/s")
     return out
+
+
+# ---------------------------------------------------------------------------
+# one analysis split over v tenants: measured time and energy beside the
+# deployment model of Section V-E (Eqs. 4-10), fitted on one tenant
+# ---------------------------------------------------------------------------
+
+class PowerSampler:
+    """Samples the GPU's socket power (W) and graphics activity (%) every
+    `period` seconds through amdsmi (read-only queries), in a thread.  If
+    amdsmi is unavailable the sampler records nothing and reports None."""
+
+    def __init__(self, device_index: int = 0, period: float = 0.05):
+        self.period = period
+        self.samples: List[tuple] = []
+        self._stop = threading.Event()
+        self._thread = None
+        self._h = None
+        try:
+            import amdsmi
+            amdsmi.amdsmi_init()
+            self._smi = amdsmi
+            self._h = amdsmi.amdsmi_get_processor_handles()[device_index]
+            self.read()
+        except Exception:            # no library, no permission, or no such query on this driver
+            self._h = None
+
+    @property
+    def available(self) -> bool:
+        return self._h is not None
+
+    def read(self):
+        p = self._smi.amdsmi_get_power_info(self._h)
+        w = p.get("current_socket_power", p.get("average_socket_power"))
+        try:
+            act = self._smi.amdsmi_get_gpu_activity(self._h).get("gfx_activity")
+        except Exception:
+            act = None
+        return float(w), (float(act) if isinstance(act, (int, float)) else None)
+
+    def _run(self) -> None:
+        while not self._stop.is_set():
+            try:
+                w, a = self.read()
+                self.samples.append((time.perf_counter(), w, a))
+            except Exception:
+                pass
+            self._stop.wait(self.period)
+
+    def __enter__(self):
+        self.samples = []
+        if self.available:
+            self._stop.clear()
+            self._thread = threading.Thread(target=self._run, daemon=True)
+            self._thread.start()
+        return self
+
+    def __exit__(self, *exc):
+        if self._thread is not None:
+            self._stop.set()
+            self._thread.join()
+            self._thread = None
+        return False
+
+    def summary(self) -> Optional[Dict[str, float]]:
+        """Energy (J, trapezoid over the samples), mean power (W) and mean
+        graphics activity (%) of the last sampled interval."""
+        s = self.samples
+        if len(s) < 2:
+            return None
+        e = sum(0.5 * (s[i][1] + s[i + 1][1]) * (s[i + 1][0] - s[i][0]) for i in range(len(s) - 1))
+        dt = s[-1][0] - s[0][0]
+        acts = [a for _, _, a in s if a is not None]
+        return {"energy_j": e, "mean_power_w": e / dt if dt > 0 else float("nan"),
+                "mean_gfx_activity_pct": (sum(acts) / len(acts)) if acts else None, "samples": len(s)}
+
+
+def split_ranges(n: int, v: int) -> List[tuple]:
+    """v contiguous trial ranges covering [0, n), sizes differing by at most one."""
+    q, r = divmod(n, v)
+    out, b = [], 0
+    for k in range(v):
+        c = q + (1 if k < r else 0)
+        out.append((b, c))
+        b += c
+    return out
+
+
+def fit_split_model(transfer_s: float, compute_s: float, fixed_s: float, w_idle: float, w_busy: float):
+    """Eqs. 4-10 on one physical GPU with v tenants: T_transfer(v) = v
+    fixed_s + transfer_s (the YET is split, the per-tenant costs are not),
+    T_comp(v) = compute_s / v, time = max(Eq. 7, Eq. 8), energy by Eq. 10 with
+    the measured idle and busy power."""
+    from .perf_model import Platform
+    return Platform(compute_s, fixed_s, 0.0, 0.0, 0.0, transfer_s, w_idle=w_idle, w_compute=w_busy)
+
+
+def split_study(base, offsets, pinned_ids, library, layer_ids: Sequence[int], tenants=(1, 2, 4, 8),
+                modes=("concurrent", "sequential"), probs=(0.99,), repeats: int = 2, log=None) -> Dict[str, object]:
+    """The whole YET analysed with `layer_ids`, split over v tenants on one
+    GPU (each ships its slice, builds its tables, runs the layers and the
+    metrics), for each transfer mode; wall time, energy and activity per
+    (mode, v), and the model's prediction from single-tenant components."""
+    import torch
+    from . import ara
+    from .perf_model import Platform   # noqa: F401  (documents the dependency)
+    offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+    n = int(offsets.shape[0] - 1)
+    dev = torch.device("cuda", torch.cuda.current_device())
+    sampler = PowerSampler(torch.cuda.current_device())
+
+    def specs_for(begin: int, count: int):
+        out = []
+        for lid in layer_ids:
+            s = library[lid]
+            out.append(ara.LayerSpec(s.elt_index, s.elt_retention, s.elt_limit, s.occ_retention, s.occ_limit,
+                                     s.agg_retention, s.agg_limit, begin, count))
+        return out
+
+    def ship(lo_t: int, cnt: int, stream):
+        lo, hi = int(offsets[lo_t]), int(offsets[lo_t + cnt])
+        off = torch.from_numpy(offsets[lo_t:lo_t + cnt + 1] - lo).pin_memory()
+        d_ids = torch.empty(hi - lo, dtype=torch.int32, device=dev)
+        d_off = torch.empty(cnt + 1, dtype=torch.int64, device=dev)
+        d_ids.copy_(pinned_ids[lo:hi], non_blocking=True)
+        d_off.copy_(off, non_blocking=True)
+        return d_off, d_ids
+
+    def compute(tables, begin: int, cnt: int, stream) -> None:
+        ylt = torch.empty(cnt, dtype=torch.float64, device=dev)
+        res = torch.empty(1 + 2 * len(probs), dtype=torch.float64, device=dev)
+        for s in specs_for(begin, cnt):
+            ara.run_layers(tables, [s], out=ylt, stream=stream)
+            ara.risk_metrics(ylt, list(probs), outputs=res, stream=stream)
+
+    # single-tenant components for the fit
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        for _ in range(2):
+            t0 = time.perf_counter()
+            d_off, d_ids = ship(0, n, st)
+            st.synchronize()
+            t_ship = time.perf_counter() - t0
+            t0 = time.perf_counter()
+            tab = ara.create_yet(base, d_off, d_ids, stream=st)
+            st.synchronize()
+            t_build = time.perf_counter() - t0
+            del d_off, d_ids
+            t0 = time.perf_counter()
+            compute(tab, 0, n, st)
+            st.synchronize()
+            t_comp = time.perf_counter() - t0
+            tab.close()
+        # per-tenant fixed cost: a one-trial slice shipped and built
+        t0 = time.perf_counter()
+        d_off, d_ids = ship(0, 1, st)
+        tab = ara.create_yet(base, d_off, d_ids, stream=st)
+        st.synchronize()
+        t_fixed = time.perf_counter() - t0
+        tab.close()
+        del d_off, d_ids
+    torch.cuda.synchronize()
+    w_idle = w_busy = None
+    if sampler.available:
+        # the power reading is an average over about a second: sample 2 s windows
+        time.sleep(1.0)
+        with sampler:
+            time.sleep(2.0)
+        idle = sampler.summary()
+        with sampler:
+            t0 = time.perf_counter()
+            while time.perf_counter() - t0 < 2.0:
+                compute(base, 0, n, None)
+                torch.cuda.synchronize()
+        busy = sampler.summary()
+        w_idle = idle["mean_power_w"] if idle else None
+        w_busy = busy["mean_power_w"] if busy else None
+    # the build runs on the GPU and splits with the trials: count it as compute
+    model = fit_split_model(t_ship, t_comp + t_build, t_fixed, w_idle or 0.0, w_busy or 0.0)
+    out: Dict[str, object] = {"trials": n, "layers": list(layer_ids), "fit": {
+        "transfer_s": t_ship, "compute_s": t_comp, "build_s": t_build, "fixed_per_tenant_s": t_fixed,
+        "power_idle_w": w_idle, "power_busy_w": w_busy}, "runs": {}}
+
+    for mode in modes:
+        for v in tenants:
+            streams = [torch.cuda.Stream() for _ in range(v)]
+            token = threading.Lock()
+            errors: List[str] = []
+
+            built: List[object] = []
+
+            def tenant(k: int, b: int, c: int) -> None:
+                try:
+                    s = streams[k]
+                    with torch.cuda.stream(s):
+                        if mode == "sequential":
+                            with token:
+                                d_off, d_ids = ship(b, c, s)
+                                s.synchronize()
+                        else:
+                            d_off, d_ids = ship(b, c, s)
+                        tab = ara.create_yet(base, d_off, d_ids, stream=s)
+                        del d_off, d_ids
+                        compute(tab, 0, c, s)
+                        s.synchronize()
+                        built.append(tab)     # freed after the run: a free waits for the whole device
+                except Exception as exc:  # reported, not raised inside the thread
+                    errors.append(f"{type(exc).__name__}: {exc}")
+
+            def once() -> float:
+                torch.cuda.synchronize()
+                ths = [threading.Thread(target=tenant, args=(k, b, c))
+                       for k, (b, c) in enumerate(split_ranges(n, v))]
+                t0 = time.perf_counter()
+                for th in ths:
+                    th.start()
+                for th in ths:
+                    th.join()
+                torch.cuda.synchronize()
+                wall = time.perf_counter() - t0
+                for tab in built:
+                    tab.close()
+                built.clear()
+                return wall
+
+            best = once()
+            # energy: the analysis back to back for >= 2 s inside one sampling
+            # window (the power readings are too coarse for a single run); the
+            # tables' frees between runs fall inside the window too
+            k_runs = max(repeats, int(math.ceil(2.0 / max(best, 1e-3))))
+            energy = None
+            with sampler:
+                for _ in range(k_runs):
+                    best = min(best, once())
+            summ = sampler.summary()
+            if summ:
+                # the window also holds the frees and thread starts between runs:
+                # energy per analysis = the window's mean power x the analysis time
+                energy = {"mean_power_w": summ["mean_power_w"],
+                          "mean_gfx_activity_pct": summ["mean_gfx_activity_pct"],
+                          "energy_j": summ["mean_power_w"] * best, "window_energy_j": summ["energy_j"],
+                          "runs_in_window": k_runs, "samples": summ["samples"]}
+            rec = {"time_s": best, "model_time_s": model.exec_time(1, v),
+                   "model_fully_overlapped_s": model.time_fully_overlapped(1, v),
+                   "model_not_overlapped_s": model.time_not_overlapped(1, v)}
+            if energy:
+                rec.update(energy)
+                rec["model_energy_j"] = model.energy(1, v)
+            if errors:
+                rec["errors"] = errors[:3]
+            out["runs"][f"{mode}_{v}"] = rec
+            if log:
+                en = f", {energy['energy_j']:.1f} J" if energy else ""
+                log(f"split {mode} v={v}: {best * 1e3:.1f} ms (model {rec['model_time_s'] * 1e3:.1f} ms){en}")
+    best_key = min(out["runs"], key=lambda k: out["runs"][k]["time_s"])
+    model_v = min(tenants, key=lambda v: model.exec_time(1, v))
+    out["best_measured"] = best_key
+    out["best_model_tenants"] = model_v
+    return out

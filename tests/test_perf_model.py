@@ -59,3 +59,25 @@ def test_model_closed_forms():
     fit = pm.fit_one_gpu(1.0, 3.0, 0.01)
     assert fit.exec_time(1, 1) == pytest.approx(4.01)
     assert len(pm.tenants_on_one_gpu(fit, 8)) == 8
+
+
+def test_split_ranges_cover_trials():
+    from paper_1606_04473_amd.serving import split_ranges
+    for n, v in ((10, 3), (1_000_000, 8), (7, 7), (5, 1)):
+        r = split_ranges(n, v)
+        assert len(r) == v and r[0][0] == 0
+        assert all(b + c == r[i + 1][0] for i, (b, c) in enumerate(r[:-1]))
+        assert r[-1][0] + r[-1][1] == n
+        assert max(c for _, c in r) - min(c for _, c in r) <= 1
+
+
+def test_split_model_is_eqs_7_to_10_on_one_gpu():
+    from paper_1606_04473_amd.serving import fit_split_model
+    m = fit_split_model(transfer_s=0.08, compute_s=0.02, fixed_s=0.001, w_idle=150.0, w_busy=700.0)
+    for v in (1, 2, 4, 8):
+        tt = v * 0.001 + 0.08                      # Eq. 6: per-tenant costs grow, the split YET does not
+        full = tt / v + v * (0.02 / v)             # Eq. 7 with p = 1
+        part = tt + 0.02 / v                       # Eq. 8
+        assert m.exec_time(1, v) == pytest.approx(max(full, part))   # Eq. 9
+        t = max(full, part)
+        assert m.energy(1, v) == pytest.approx(0.02 * 700.0 + (t - 0.02) * 150.0)   # Eq. 10
