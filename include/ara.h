@@ -267,6 +267,25 @@ ara_status ara_debug_lookups(ara_tables* tables, const ara_layer* layer, int64_t
                              int64_t* n_out, void* stream);
 
 /*
+ * ara_event_nets -- per-event net losses of one layer, the cumulative form of
+ * the aggregate terms (Section III-B: the aggregate terms act on the
+ * cumulative loss of the trial).  For each trial t of the layer and its
+ * events d = 1..K_t in storage (time) order, with S_d the running total of
+ * the occurrence losses o and A_d = clamp(S_d; AggR, AggL), A_0 =
+ * clamp(0; AggR, AggL):  nets[i] = A_d - A_{d-1}, where i is the event's
+ * position counted from the first event of the layer's first trial.  Each
+ * S_d is rounded once from an extended-precision running sum.  The nets of a
+ * trial add up to its year loss minus A_0.
+ *
+ *   nets      float64[capacity]; host memory, or device memory with
+ *             ARA_DEVICE_PTR (then written on `stream` without waiting).
+ *   *n_out    receives the number of events in the layer's trials.
+ * ARA_ERR_BUFFER_TOO_SMALL if capacity < *n_out (nothing written).
+ */
+ara_status ara_event_nets(ara_tables* tables, const ara_layer* layer, double* nets, int64_t capacity,
+                          int64_t* n_out, uint32_t flags, void* stream);
+
+/*
  * ara_read_checkpoints -- copy the state kept by ARA_CHECKPOINT_S (what = 0)
  * or ARA_CHECKPOINT_STRIDE (what = 1) to host.
  * what = 0: S_t for the layer's trials (trial_count doubles);

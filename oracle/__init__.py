@@ -15,6 +15,8 @@ from .reference import (  # noqa: F401
     run_layer_python,
     run_layer_numpy,
     occurrence_catalogue,
+    event_nets,
+    event_nets_python,
     lookups,
     tail_count,
     risk_metrics,

@@ -202,6 +202,54 @@ int ara_oracle_run_layer(const int64_t* offsets, int64_t n_trials,
     return bad ? ORACLE_ERR_RANGE : ORACLE_OK;
 }
 
+/*
+ * Per-event net losses: the aggregate terms act on the trial's cumulative
+ * loss (Section III-B), so after the d-th event of a trial (time order) the
+ * recovered amount is A_d = clamp(S_d; AggR, AggL) with S_d the sum of the
+ * first d occurrence losses, and the d-th event adds A_d - A_{d-1}, with
+ * A_0 = clamp(0; AggR, AggL).  Each S_d is the exact running sum rounded once.
+ * nets_out[i] belongs to global event offsets[trial_begin] + i.
+ */
+int ara_oracle_event_nets(const int64_t* offsets, int64_t n_trials,
+                          const uint32_t* ids, int64_t n_events,
+                          const double* elts, int32_t n_pool, int64_t C,
+                          int32_t J, const int32_t* elt_index,
+                          const double* R, const double* Lim,
+                          double occR, double occL, double aggR, double aggL,
+                          int64_t trial_begin, int64_t trial_count,
+                          double* nets_out, int32_t n_threads)
+{
+    layer_view L = {elts, C, J, elt_index, R, Lim, occR, occL};
+    if (check_layer(&L, n_pool) != ORACLE_OK) return ORACLE_ERR_RANGE;
+    if (trial_begin < 0 || trial_count < 0 || trial_begin + trial_count > n_trials)
+        return ORACLE_ERR_ARG;
+    if (offsets[n_trials] != n_events) return ORACLE_ERR_ARG;
+    const int64_t first = offsets[trial_begin];
+    const double A0 = apply_terms(0.0, aggR, aggL);
+    int bad = 0;
+#ifdef _OPENMP
+    if (n_threads > 0) omp_set_num_threads(n_threads);
+#else
+    (void)n_threads;
+#endif
+#pragma omp parallel for schedule(dynamic, 64) reduction(| : bad)
+    for (int64_t k = 0; k < trial_count; ++k) {
+        int64_t t = trial_begin + k;
+        exact_sum acc;
+        exact_init(&acc);
+        double A_prev = A0;
+        for (int64_t i = offsets[t]; i < offsets[t + 1]; ++i) {
+            uint32_t e = ids[i];
+            if ((int64_t)e >= C) { bad |= 1; nets_out[i - first] = 0.0; continue; }
+            exact_add(&acc, occurrence_loss(&L, e, NULL));
+            double A = apply_terms(exact_result(&acc), aggR, aggL);
+            nets_out[i - first] = A - A_prev;
+            A_prev = A;
+        }
+    }
+    return bad ? ORACLE_ERR_RANGE : ORACLE_OK;
+}
+
 /* y(E) and o(E) for every catalogue event: used to calibrate layer terms from
    quantiles and to cross-check the per-occurrence arithmetic. */
 int ara_oracle_occurrence_catalogue(const double* elts, int32_t n_pool, int64_t C,

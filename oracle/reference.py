@@ -51,6 +51,9 @@ def _lib():
         lib.ara_oracle_grad_counts.argtypes = [P, i64, P, i64, P, i32, i64, i32, P, P, P,
                                                f64, f64, f64, f64, i64, i64, P, P, i32]
         lib.ara_oracle_grad_counts.restype = i32
+        lib.ara_oracle_event_nets.argtypes = [P, i64, P, i64, P, i32, i64, i32, P, P, P,
+                                              f64, f64, f64, f64, i64, i64, P, i32]
+        lib.ara_oracle_event_nets.restype = i32
         lib.ara_oracle_exact_sum.argtypes = [P, i64]
         lib.ara_oracle_exact_sum.restype = f64
         lib.ara_oracle_max_threads.argtypes = []
@@ -118,6 +121,56 @@ def run_layer(yet, pool, layer, sum_mode: str = "exact", threads: int = 0):
     if rc != 0:
         raise ValueError(f"oracle rejected the input (code {rc})")
     return ylt, S
+
+
+def event_nets(yet, pool, layer, threads: int = 0) -> np.ndarray:
+    """Per-event net losses of ``layer`` (Section III-B: the aggregate terms act
+    on the trial's cumulative loss), via the C oracle.
+
+    For the d-th event of a trial, A_d = clamp(S_d; AggR, AggL) with S_d the
+    exact running total of the occurrence losses rounded once, and the event's
+    net is A_d - A_{d-1} (A_0 = clamp(0; AggR, AggL)).  Entry i belongs to
+    event offsets[trial_begin] + i.  Pinned by: the hand-worked nets of
+    tests/golden/closed_form_cases.json, event_nets_python on every tiny
+    trial, and the invariants (nets >= 0, each net at most its occurrence
+    loss, the nets of a trial telescoping to its year loss minus A_0).
+    """
+    lib = _lib()
+    offsets = np.ascontiguousarray(yet.offsets, dtype=np.int64)
+    ids = np.ascontiguousarray(yet.ids, dtype=np.uint32)
+    elts = np.ascontiguousarray(pool.losses, dtype=np.float64)
+    idx, R, Lim = _layer_arrays(pool, layer)
+    begin, count = _range(yet, layer)
+    nets = np.empty(int(offsets[begin + count] - offsets[begin]), dtype=np.float64)
+    rc = lib.ara_oracle_event_nets(_ptr(offsets), yet.n_trials, _ptr(ids), ids.shape[0],
+                                   _ptr(elts), elts.shape[0], elts.shape[1],
+                                   idx.shape[0], _ptr(idx), _ptr(R), _ptr(Lim),
+                                   layer.occ_retention, layer.occ_limit,
+                                   layer.agg_retention, layer.agg_limit,
+                                   begin, count, _ptr(nets), threads)
+    if rc != 0:
+        raise ValueError(f"oracle rejected the input (code {rc})")
+    return nets
+
+
+def event_nets_python(trials: Sequence[Sequence[int]], losses, elt_index, R, Lim,
+                      occ_r, occ_l, agg_r, agg_l) -> List[float]:
+    """Per-event nets in plain Python: every prefix total recomputed from
+    scratch with math.fsum, for tiny cases."""
+    out = []
+    a0 = _terms(0.0, agg_r, agg_l)
+    for trial in trials:
+        occ = []
+        a_prev = a0
+        for e in trial:
+            y = 0.0
+            for j, row in enumerate(elt_index):
+                y = y + _terms(float(losses[row][e]), float(R[j]), float(Lim[j]))
+            occ.append(_terms(y, occ_r, occ_l))
+            a = _terms(math.fsum(occ), agg_r, agg_l)
+            out.append(a - a_prev)
+            a_prev = a
+    return out
 
 
 def _terms(v: float, r: float, lim: float) -> float:

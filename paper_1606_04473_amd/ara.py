@@ -48,6 +48,7 @@ CHECKPOINT_EVERY = 64
 EXPORTED = (
     "ara_create_tables", "ara_destroy_tables", "ara_run_layers", "ara_risk_metrics", "ara_backward",
     "ara_last_error", "ara_status_string", "ara_table_bytes", "ara_footprint", "ara_debug_lookups",
+    "ara_event_nets",
     "ara_read_checkpoints", "ara_set_tuning", "ara_get_tuning", "ara_device_info",
     "ara_kernel_stats", "ara_create_yet",
 )
@@ -129,6 +130,8 @@ def lib():
     L.ara_footprint.restype = i32
     L.ara_debug_lookups.argtypes = [P, ctypes.POINTER(CLayer), i64, P, P, i64, ctypes.POINTER(i64), P]
     L.ara_debug_lookups.restype = i32
+    L.ara_event_nets.argtypes = [P, ctypes.POINTER(CLayer), P, i64, ctypes.POINTER(i64), u32, P]
+    L.ara_event_nets.restype = i32
     L.ara_read_checkpoints.argtypes = [P, i32, P, i64, ctypes.POINTER(i64)]
     L.ara_read_checkpoints.restype = i32
     L.ara_set_tuning.argtypes = [P, ctypes.POINTER(CTuning)]
@@ -399,6 +402,27 @@ def debug_lookups(tables: Tables, layer: LayerSpec, trial: int, capacity: int = 
                                    _stream(stream)))
     K = int(n.value)
     return ids[:K].copy(), losses[:K * J].reshape(K, J).copy()
+
+
+def event_nets(tables: Tables, layer: LayerSpec, out=None, stream=None):
+    """ara_event_nets: per-event net losses of the layer's trials in time
+    order.  Returns a NumPy array, or fills `out` (NumPy or a CUDA float64
+    tensor) and returns it."""
+    arr, keep = _c_layers([layer])
+    n = ctypes.c_int64()
+    if out is None:
+        st = lib().ara_event_nets(tables.handle, arr, None, 0, ctypes.byref(n), 0, _stream(stream))
+        if st not in (ARA_OK, ARA_ERR_BUFFER_TOO_SMALL):
+            _check(st)
+        out = np.empty(max(int(n.value), 1), dtype=np.float64)
+        _check(lib().ara_event_nets(tables.handle, arr, out.ctypes.data_as(ctypes.c_void_p), out.shape[0],
+                                    ctypes.byref(n), 0, _stream(stream)))
+        return out[:int(n.value)]
+    po, ko, dev = _ptr(out, np.float64)
+    cap = int(ko.numel() if dev else ko.size)
+    _check(lib().ara_event_nets(tables.handle, arr, po, cap, ctypes.byref(n), ARA_DEVICE_PTR if dev else 0,
+                                _stream(stream)))
+    return out
 
 
 def read_checkpoints(tables: Tables, what: int):

@@ -1033,6 +1033,50 @@ ara_status ara_debug_lookups(ara_tables* t, const ara_layer* layer, int64_t tria
     return ARA_OK;
 }
 
+ara_status ara_event_nets(ara_tables* t, const ara_layer* layer, double* nets, int64_t capacity, int64_t* n_out,
+                          uint32_t flags, void* stream) {
+    if (!t || !layer || !n_out || capacity < 0) return fail(ARA_ERR_INVALID_ARG, "NULL argument");
+    ara::LayerArgs L;
+    ara_status st = build_layer_args(t, *layer, L);
+    if (st != ARA_OK) return st;
+    DeviceScope ds(t->device);
+    if (!ds.ok) return fail(ARA_ERR_DEVICE, "cannot select the tables' device");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int64_t be[2] = {0, 0};
+    HIP_TRY(hipMemcpyAsync(&be[0], t->offsets + L.trial_begin, sizeof(int64_t), hipMemcpyDeviceToHost, s), "offsets");
+    HIP_TRY(hipMemcpyAsync(&be[1], t->offsets + L.trial_begin + L.trial_count, sizeof(int64_t), hipMemcpyDeviceToHost,
+                           s),
+            "offsets");
+    HIP_TRY(hipStreamSynchronize(s), "synchronize");
+    const int64_t n = be[1] - be[0];
+    *n_out = n;
+    if (n > capacity) return fail(ARA_ERR_BUFFER_TOO_SMALL, "the layer's trials hold %lld events, capacity %lld",
+                                  (long long)n, (long long)capacity);
+    if (n == 0) return ARA_OK;
+    if (!nets) return fail(ARA_ERR_INVALID_ARG, "NULL output");
+    const bool dev = (flags & ARA_DEVICE_PTR) != 0;
+    PoolBuffer obuf, staged;
+    HIP_TRY(obuf.alloc(sizeof(double) * t->C, s), "scratch for occurrence losses");
+    double* out = nets;
+    if (!dev) {
+        HIP_TRY(staged.alloc(sizeof(double) * n, s), "scratch for net losses");
+        out = static_cast<double*>(staged.p);
+    }
+    ara_tuning tu;
+    {
+        std::lock_guard<std::mutex> g(t->mu);
+        tu = t->tuning;
+    }
+    HIP_TRY(ara::launch_fold(t->elts, t->C, L, static_cast<double*>(obuf.p), tu, s), "fold");
+    HIP_TRY(ara::launch_event_nets(t->offsets, t->ids, static_cast<const double*>(obuf.p), L, out, t->n_cu, s),
+            "net-loss kernel");
+    if (!dev) {
+        HIP_TRY(hipMemcpyAsync(nets, out, sizeof(double) * n, hipMemcpyDeviceToHost, s), "copy nets");
+        HIP_TRY(hipStreamSynchronize(s), "synchronize");
+    }
+    return ARA_OK;
+}
+
 ara_status ara_read_checkpoints(ara_tables* t, int32_t what, double* out, int64_t capacity, int64_t* n_out) {
     if (!t || !n_out || (what != 0 && what != 1)) return fail(ARA_ERR_INVALID_ARG, "bad argument");
     std::lock_guard<std::mutex> g(t->mu);

@@ -319,6 +319,9 @@ hipError_t launch_fold(const double* elts, int64_t C, const LayerArgs& L, double
                        const ara_tuning& tu, hipStream_t s);
 hipError_t launch_trial_pass(const TrialPassArgs& a, const LayerArgs& L, bool literal,
                              const ara_tuning& tu, int n_cu, hipStream_t s);
+// per-event net losses of a layer's trials, in time order, from the folded o
+hipError_t launch_event_nets(const int64_t* offsets, const uint32_t* ids, const double* o, const LayerArgs& L,
+                             double* nets, int n_cu, hipStream_t s);
 hipError_t launch_debug_lookups(const int64_t* offsets, const uint32_t* ids, const double* elts,
                                 int64_t C, const LayerArgs& L, int64_t trial, uint32_t* ids_out,
                                 double* losses_out, hipStream_t s);

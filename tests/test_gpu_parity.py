@@ -282,6 +282,84 @@ def test_ragged_and_edge_cases(ara):
     tables.close()
 
 
+def _nets_close(got, ref, yet, layer, ylt_ref):
+    """|got - ref| within 1e-12 of the year loss of the event's trial (each net
+    is a difference of two clamped running totals, each within an ulp)."""
+    begin = layer.trial_begin
+    count = layer.resolved_count(yet.n_trials)
+    lens = np.diff(yet.offsets[begin:begin + count + 1])
+    scale = np.repeat(np.maximum(ylt_ref, 1.0), lens)
+    err = np.abs(np.asarray(got) - ref)
+    return bool(np.all(err <= REL * scale)), float(np.mean(np.asarray(got) == ref)) if len(ref) else 1.0
+
+
+def test_event_nets_closed_form(ara, golden_dir):
+    g = json.load(open(os.path.join(golden_dir, "closed_form_cases.json")))
+    pool = ELTPool(np.array(g["elts"]), np.array(g["elt_retention"]), np.array(g["elt_limit"]))
+    f = lambda v: INF if v == "inf" else float(v)  # noqa: E731
+    for case in g["cases"]:
+        if "event_nets" not in case:
+            continue
+        yet = make_tiny_yet(case["trials"], g["catalogue_size"])
+        t = case["terms"]
+        layer = Layer(np.array(case["elt_index"], dtype=np.int32), f(t["occ_retention"]),
+                      f(t["occ_limit"]), f(t["agg_retention"]), f(t["agg_limit"]), 0, yet.n_trials)
+        tables = ara.create_tables(yet.offsets, yet.ids, pool.losses)
+        assert ara.event_nets(tables, _spec(ara, layer, pool, yet)).tolist() == case["event_nets"]
+        tables.close()
+
+
+def test_event_nets_match_oracle(ara, cfg0):
+    """config0 (trials of about a thousand events, so the kernel carries its
+    running total over several 256-event steps), a sub-range written to a
+    device buffer, and the ragged/empty trials of the edge-case workload."""
+    import torch
+    w, tables, ref_ylt, _ = cfg0
+    yet, pool, layer = w.yet, w.pool, w.layers[0]
+    spec = _spec(ara, layer, pool, yet)
+    ref = oracle.event_nets(yet, pool, layer)
+    got = ara.event_nets(tables, spec)
+    ok, exact = _nets_close(got, ref, yet, layer, ref_ylt)
+    assert got.shape == ref.shape and ok
+    assert exact > 0.99, exact
+    sub_layer = Layer(layer.elt_index, layer.occ_retention, layer.occ_limit, layer.agg_retention,
+                      layer.agg_limit, 37, 501)
+    sub = _spec(ara, sub_layer, pool, yet)
+    n = int(yet.offsets[37 + 501] - yet.offsets[37])
+    out = torch.full((n + 5,), -1.0, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        ara.event_nets(tables, sub, out=out, stream=stream)
+    stream.synchronize()
+    dev = out.cpu().numpy()
+    first = int(yet.offsets[37])
+    assert np.array_equal(dev[:n], got[first:first + n])
+    assert np.all(dev[n:] == -1.0)
+    with pytest.raises(ara.AraError) as e:
+        ara.event_nets(tables, sub, out=np.empty(n - 1))
+    assert e.value.status == ara.ARA_ERR_BUFFER_TOO_SMALL
+
+    rng = np.random.default_rng(23)
+    C = 5000
+    pool2 = make_elt_pool(8, C, 900, seed=24)
+    lengths = rng.choice([0, 1, 2, 63, 64, 65, 255, 256, 257, 511, 512, 513, 3000], size=200)
+    trials = [rng.integers(0, C, size=k).tolist() for k in lengths]
+    yet2 = make_tiny_yet(trials, C)
+    t2 = ara.create_tables(yet2.offsets, yet2.ids, pool2.losses)
+    for lay in (Layer(np.array([1, 4, 7], dtype=np.int32), 1000.0, 4.0e5, 5.0e4, 2.0e6, 0, yet2.n_trials),
+                Layer(np.array([3], dtype=np.int32), 0.0, INF, 0.0, INF, 0, yet2.n_trials),
+                Layer(np.zeros(0, dtype=np.int32), 0.0, INF, 0.0, INF, 0, yet2.n_trials),
+                Layer(np.array([5, 2], dtype=np.int32), 10.0, INF, 1e300, INF, 7, 150),
+                Layer(np.array([2, 1], dtype=np.int32), 10.0, INF, 0.0, INF, 200, 0)):
+        ylt2, _ = oracle.run_layer(yet2, pool2, lay)
+        r2 = oracle.event_nets(yet2, pool2, lay)
+        g2 = ara.event_nets(t2, _spec(ara, lay, pool2, yet2))
+        assert g2.shape == r2.shape
+        ok, _ = _nets_close(g2, r2, yet2, lay, ylt2)
+        assert ok, lay
+    t2.close()
+
+
 def test_error_paths(ara):
     C = 100
     pool = make_elt_pool(2, C, 10, seed=3)

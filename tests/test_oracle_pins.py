@@ -320,6 +320,74 @@ def test_brute_force_tiny():
 
 
 # ---------------------------------------------------------------------------
+# per-event nets (aggregate terms on the running total)
+# ---------------------------------------------------------------------------
+
+def test_closed_form_event_nets(golden):
+    pool = _golden_pool(golden)
+    for case in golden["cases"]:
+        if "event_nets" not in case:
+            continue
+        yet = make_tiny_yet(case["trials"], golden["catalogue_size"])
+        layer = _golden_layer(case, yet.n_trials)
+        assert oracle.event_nets(yet, pool, layer).tolist() == case["event_nets"], case["name"]
+        py = oracle.event_nets_python(case["trials"], pool.losses, layer.elt_index,
+                                      pool.retention[layer.elt_index],
+                                      pool.limit[layer.elt_index], layer.occ_retention,
+                                      layer.occ_limit, layer.agg_retention, layer.agg_limit)
+        assert py == case["event_nets"]
+        # a sub-range starts its output at the range's first event
+        sub = Layer(layer.elt_index, layer.occ_retention, layer.occ_limit,
+                    layer.agg_retention, layer.agg_limit, 1, yet.n_trials - 2)
+        first = int(yet.offsets[1])
+        last = int(yet.offsets[yet.n_trials - 1])
+        assert oracle.event_nets(yet, pool, sub).tolist() == case["event_nets"][first:last]
+
+
+def test_event_nets_brute_force_tiny():
+    """Every trial of up to 3 events over a 6-event catalogue, against prefix
+    totals recomputed from scratch."""
+    rng = np.random.default_rng(5)
+    C = 6
+    losses = np.where(rng.random((3, C)) < 0.6, rng.integers(1, 50, (3, C)) * 8.0, 0.0)
+    pool = ELTPool(losses=losses, retention=np.array([16.0, 0.0, 40.0]),
+                   limit=np.array([200.0, 96.0, INF]))
+    trials = [list(t) for k in range(4) for t in itertools.product(range(C), repeat=k)]
+    yet = make_tiny_yet(trials, C)
+    for terms in ((0.0, INF, 0.0, INF), (24.0, 160.0, 40.0, 300.0), (0.0, INF, 100.0, 50.0)):
+        layer = Layer(np.array([2, 0, 1], dtype=np.int32), *terms, 0, yet.n_trials)
+        nets = oracle.event_nets(yet, pool, layer)
+        py = oracle.event_nets_python(trials, losses, layer.elt_index,
+                                      pool.retention[layer.elt_index],
+                                      pool.limit[layer.elt_index], *terms)
+        assert nets.tolist() == py
+
+
+def test_event_nets_invariants(small):
+    """nets >= 0; a net never exceeds its occurrence loss (clamp is
+    1-Lipschitz and non-decreasing); a trial's nets add up to its year loss
+    (A_0 = 0 for a non-negative retention); no aggregate limit gives back the
+    occurrence losses themselves."""
+    yet, pool, layer = small
+    nets = oracle.event_nets(yet, pool, layer)
+    ylt, _ = oracle.run_layer(yet, pool, layer)
+    _, o = oracle.occurrence_catalogue(pool, layer)
+    eps = np.finfo(np.float64).eps
+    assert nets.shape[0] == yet.offsets[-1]
+    assert np.all(nets >= 0.0)
+    o_ev = o[yet.ids.astype(np.int64)]
+    for t in range(yet.n_trials):
+        b, e = int(yet.offsets[t]), int(yet.offsets[t + 1])
+        scale = max(ylt[t], 1.0)
+        assert np.all(nets[b:e] <= o_ev[b:e] + 4 * eps * layer.agg_limit)
+        assert abs(math.fsum(nets[b:e].tolist()) - ylt[t]) <= (e - b + 1) * eps * scale
+    free = Layer(layer.elt_index, layer.occ_retention, layer.occ_limit, 0.0, INF, 0, yet.n_trials)
+    nets_free = oracle.event_nets(yet, pool, free)
+    # A_d - A_{d-1} = S_d - S_{d-1} with both rounded from exact prefixes
+    assert np.allclose(nets_free, o_ev, rtol=0.0, atol=1e-9 * float(o.max()))
+
+
+# ---------------------------------------------------------------------------
 # P5: metrics
 # ---------------------------------------------------------------------------
 
