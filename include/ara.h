@@ -84,9 +84,12 @@ typedef int32_t ara_status;
 #define ARA_KERNEL_BATCHED    2     /* persistent multi-layer trial pass */
 #define ARA_KERNEL_COMBINE    3     /* merge of the per-part partial sums into annual totals and
                                        aggregate terms (after the catalogue-partitioned pass) */
+#define ARA_KERNEL_AGGREGATE  4     /* per-trial program and portfolio sums of layer year losses */
 
 #define ARA_MAX_LAYER_ELTS 64       /* most ELTs one layer may cover (the paper's layers cover 3-30) */
 #define ARA_CHECKPOINT_EVERY 64     /* events between stored prefix sums of S */
+#define ARA_MAX_PROGRAMS 64         /* most programs one ara_run_portfolio call takes (the
+                                       paper's portfolios hold 1-10) */
 
 typedef struct ara_tables ara_tables;
 
@@ -107,6 +110,32 @@ typedef struct ara_layer {
     double agg_retention, agg_limit;
     int64_t trial_begin, trial_count;
 } ara_layer;
+
+/*
+ * A program (Section III-A): the layers it covers, in order.  `layers` is
+ * host memory holding n_layers entries.
+ */
+typedef struct ara_program {
+    int32_t n_layers;
+    const ara_layer* layers;
+} ara_program;
+
+/*
+ * Outputs of ara_run_portfolio.  Each pointer may be NULL to skip that
+ * output; the capacities count doubles.  With n = the portfolio's trial
+ * count and the layers numbered across programs in order:
+ *   layer_ylt      [n_layers_total][n]: the layers' year losses;
+ *   program_ylt    [n_programs][n]: per trial, the sum of the program's layers;
+ *   portfolio_ylt  [n]: per trial, the sum of every layer of the portfolio.
+ */
+typedef struct ara_portfolio_out {
+    double* layer_ylt;
+    int64_t layer_capacity;
+    double* program_ylt;
+    int64_t program_capacity;
+    double* portfolio_ylt;
+    int64_t portfolio_capacity;
+} ara_portfolio_out;
 
 /*
  * Launch-shape knobs picked by the autotuner; zero fields mean "default".
@@ -267,6 +296,33 @@ ara_status ara_debug_lookups(ara_tables* tables, const ara_layer* layer, int64_t
                              int64_t* n_out, void* stream);
 
 /*
+ * ara_run_portfolio -- Algorithm 1: for each program of the portfolio PF
+ * (Section III-A), for each of its layers, the YET split into n_splits
+ * contiguous trial ranges YET_i, each analysed as its own launch sequence,
+ * and the layer's YLT populated from the parts.  The paper gives no rule for
+ * combining layers; a program's year loss is read as the per-trial sum of
+ * its layers' year losses, the portfolio's as the sum over all its layers
+ * (no terms above the layer).  Both sums are accumulated in double-double
+ * in layer order and rounded once.
+ *
+ *   programs   n_programs entries (1..ARA_MAX_PROGRAMS), each with >= 1 layer.
+ *              Every layer must cover the same trials (same trial_begin and,
+ *              after resolving -1, the same count): the portfolio's range.
+ *   n_splits   >= 1.  Split i covers trials [b_i, b_{i+1}) with
+ *              b_i = begin + floor(i * n / n_splits); empty splits are skipped.
+ *              Results do not depend on n_splits (trials are independent).
+ *   out        see ara_portfolio_out; capacities too small give
+ *              ARA_ERR_BUFFER_TOO_SMALL (nothing written).
+ *   flags      ARA_DEVICE_PTR (all output pointers are device memory; the
+ *              call returns without waiting), ARA_LITERAL, ARA_PROFILE
+ *              (ARA_KERNEL_AGGREGATE times the sums).
+ * ARA_ERR_INVALID_ARG for layers over different trials, n_splits < 1 or no
+ * output; ARA_ERR_UNSUPPORTED beyond ARA_MAX_PROGRAMS.
+ */
+ara_status ara_run_portfolio(ara_tables* tables, const ara_program* programs, int32_t n_programs,
+                             int32_t n_splits, const ara_portfolio_out* out, uint32_t flags, void* stream);
+
+/*
  * ara_event_nets -- per-event net losses of one layer, the cumulative form of
  * the aggregate terms (Section III-B: the aggregate terms act on the
  * cumulative loss of the trial).  For each trial t of the layer and its
@@ -300,8 +356,9 @@ ara_status ara_read_checkpoints(ara_tables* tables, int32_t what, double* out,
 
 /*
  * ara_kernel_stats -- launches and summed device time (ms, from HIP events)
- * of one kernel class (ARA_KERNEL_*, 0..3; ARA_ERR_INVALID_ARG otherwise)
- * over the ara_run_layers calls made with ARA_PROFILE since the last reset.
+ * of one kernel class (ARA_KERNEL_*, 0..4; ARA_ERR_INVALID_ARG otherwise)
+ * over the ara_run_layers and ara_run_portfolio calls made with ARA_PROFILE
+ * since the last reset.
  * With the catalogue-partitioned pass, ARA_KERNEL_TRIAL_PASS times the pass
  * kernel alone and ARA_KERNEL_COMBINE the merge after it.  Waits for the
  * recorded events.  reset != 0 clears the totals after reading them.

@@ -16,6 +16,7 @@ from .reference import (  # noqa: F401
     run_layer_numpy,
     occurrence_catalogue,
     event_nets,
+    portfolio,
     event_nets_python,
     lookups,
     tail_count,

@@ -123,6 +123,37 @@ def run_layer(yet, pool, layer, sum_mode: str = "exact", threads: int = 0):
     return ylt, S
 
 
+def portfolio(yet, pool, programs, threads: int = 0):
+    """Year losses of a portfolio (Algorithm 1's loops over programs and their
+    layers, Section III-A), computed without any split of the YET.
+
+    ``programs`` is a list of programs, each a list of layers over the same
+    trials.  Returns (layer_ylt [n_layers][n], program_ylt [n_programs][n],
+    portfolio_ylt [n]).  The paper gives no rule for combining layers; a
+    program's year loss is taken as the per-trial sum of its layers' year
+    losses and the portfolio's as the sum over all of its layers, each sum
+    exact and rounded once (math.fsum).  Pinned by: the hand-worked portfolio
+    of tests/golden/closed_form_cases.json, a case where only a once-rounded
+    sum is right, and the one-layer reduction to run_layer.
+    """
+    layers = [layer for prog in programs for layer in prog]
+    if not programs or any(len(prog) == 0 for prog in programs):
+        raise ValueError("every program needs at least one layer")
+    ranges = {_range(yet, layer) for layer in layers}
+    if len(ranges) != 1:
+        raise ValueError("the layers of a portfolio must cover the same trials")
+    rows = np.stack([run_layer(yet, pool, layer, threads=threads)[0] for layer in layers])
+    n = rows.shape[1]
+    program_rows = np.empty((len(programs), n))
+    first = 0
+    for p, prog in enumerate(programs):
+        block = rows[first:first + len(prog)]
+        program_rows[p] = [math.fsum(block[:, k].tolist()) for k in range(n)]
+        first += len(prog)
+    portfolio_row = np.array([math.fsum(rows[:, k].tolist()) for k in range(n)])
+    return rows, program_rows, portfolio_row
+
+
 def event_nets(yet, pool, layer, threads: int = 0) -> np.ndarray:
     """Per-event net losses of ``layer`` (Section III-B: the aggregate terms act
     on the trial's cumulative loss), via the C oracle.

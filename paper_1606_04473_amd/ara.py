@@ -41,6 +41,7 @@ KERNEL_FOLD = 0
 KERNEL_TRIAL_PASS = 1
 KERNEL_BATCHED = 2
 KERNEL_COMBINE = 3
+KERNEL_AGGREGATE = 4
 
 MAX_LAYER_ELTS = 64
 CHECKPOINT_EVERY = 64
@@ -48,7 +49,7 @@ CHECKPOINT_EVERY = 64
 EXPORTED = (
     "ara_create_tables", "ara_destroy_tables", "ara_run_layers", "ara_risk_metrics", "ara_backward",
     "ara_last_error", "ara_status_string", "ara_table_bytes", "ara_footprint", "ara_debug_lookups",
-    "ara_event_nets",
+    "ara_event_nets", "ara_run_portfolio",
     "ara_read_checkpoints", "ara_set_tuning", "ara_get_tuning", "ara_device_info",
     "ara_kernel_stats", "ara_create_yet",
 )
@@ -78,6 +79,18 @@ class CLayer(ctypes.Structure):
         ("agg_limit", ctypes.c_double),
         ("trial_begin", ctypes.c_int64),
         ("trial_count", ctypes.c_int64),
+    ]
+
+
+class CProgram(ctypes.Structure):
+    _fields_ = [("n_layers", ctypes.c_int32), ("layers", ctypes.POINTER(CLayer))]
+
+
+class CPortfolioOut(ctypes.Structure):
+    _fields_ = [
+        ("layer_ylt", ctypes.c_void_p), ("layer_capacity", ctypes.c_int64),
+        ("program_ylt", ctypes.c_void_p), ("program_capacity", ctypes.c_int64),
+        ("portfolio_ylt", ctypes.c_void_p), ("portfolio_capacity", ctypes.c_int64),
     ]
 
 
@@ -130,6 +143,9 @@ def lib():
     L.ara_footprint.restype = i32
     L.ara_debug_lookups.argtypes = [P, ctypes.POINTER(CLayer), i64, P, P, i64, ctypes.POINTER(i64), P]
     L.ara_debug_lookups.restype = i32
+    L.ara_run_portfolio.argtypes = [P, ctypes.POINTER(CProgram), i32, i32, ctypes.POINTER(CPortfolioOut),
+                                    u32, P]
+    L.ara_run_portfolio.restype = i32
     L.ara_event_nets.argtypes = [P, ctypes.POINTER(CLayer), P, i64, ctypes.POINTER(i64), u32, P]
     L.ara_event_nets.restype = i32
     L.ara_read_checkpoints.argtypes = [P, i32, P, i64, ctypes.POINTER(i64)]
@@ -402,6 +418,50 @@ def debug_lookups(tables: Tables, layer: LayerSpec, trial: int, capacity: int = 
                                    _stream(stream)))
     K = int(n.value)
     return ids[:K].copy(), losses[:K * J].reshape(K, J).copy()
+
+
+PORTFOLIO_OUTPUTS = ("layer", "program", "portfolio")
+
+
+def run_portfolio(tables: Tables, programs: Sequence[Sequence[LayerSpec]], n_splits: int = 1,
+                  outs=None, flags: int = 0, stream=None):
+    """ara_run_portfolio: a portfolio given as a list of programs, each a list
+    of layers over the same trials.  With `outs` None, returns host arrays
+    {"layer": [n_layers, n], "program": [n_programs, n], "portfolio": [n]}.
+    Otherwise `outs` maps some of those names to NumPy arrays or CUDA float64
+    tensors (all host or all device) and only those are written."""
+    progs = (CProgram * len(programs))()
+    keep = []
+    for i, layers in enumerate(programs):
+        arr, k = _c_layers(layers) if len(layers) else ((CLayer * 1)(), [])
+        keep += [arr, k]
+        progs[i] = CProgram(len(layers), ctypes.cast(arr, ctypes.POINTER(CLayer)))
+    if outs is None:
+        n = int(programs[0][0].trial_count) if programs and programs[0] else 0
+        n_layers = sum(len(p) for p in programs)
+        outs = {"layer": np.empty((n_layers, n)), "program": np.empty((len(programs), n)),
+                "portfolio": np.empty(n)}
+    unknown = set(outs) - set(PORTFOLIO_OUTPUTS)
+    if unknown:
+        raise KeyError(f"unknown outputs {sorted(unknown)}")
+    c = CPortfolioOut()
+    devs = set()
+    for name in PORTFOLIO_OUTPUTS:
+        if outs.get(name) is None:
+            continue
+        po, ko, dev = _ptr(outs[name], np.float64)
+        if not dev and ko is not outs[name]:
+            raise ValueError(f"output {name!r} must be a contiguous float64 array")
+        devs.add(dev)
+        keep.append(ko)
+        setattr(c, f"{name}_ylt", po)
+        setattr(c, f"{name}_capacity", int(ko.numel() if dev else ko.size))
+    if len(devs) > 1:
+        raise ValueError("outputs must be all host or all device")
+    f = flags | (ARA_DEVICE_PTR if devs == {True} else 0)
+    _check(lib().ara_run_portfolio(tables.handle, progs, len(programs), int(n_splits), ctypes.byref(c), f,
+                                   _stream(stream)))
+    return outs
 
 
 def event_nets(tables: Tables, layer: LayerSpec, out=None, stream=None):

@@ -535,7 +535,7 @@ ara_status ara_table_bytes(const ara_tables* t, int64_t* bytes) {
 }
 
 ara_status ara_kernel_stats(ara_tables* t, int32_t kernel, int64_t* launches, double* total_ms, int32_t reset) {
-    if (!t || kernel < 0 || kernel > 3) return fail(ARA_ERR_INVALID_ARG, "bad argument");
+    if (!t || kernel < 0 || kernel > ARA_KERNEL_AGGREGATE) return fail(ARA_ERR_INVALID_ARG, "bad argument");
     DeviceScope ds(t->device);
     std::lock_guard<std::mutex> g(t->prof_mu);
     auto& ps = t->prof;
@@ -880,6 +880,159 @@ ara_status ara_run_layers(ara_tables* t, const ara_layer* layers, int32_t n_laye
     }
     if (!dev_out) {
         HIP_TRY(hipMemcpyAsync(ylt, out, sizeof(double) * total, hipMemcpyDeviceToHost, s), "copy YLT");
+        HIP_TRY(hipStreamSynchronize(s), "synchronize");
+    }
+    return ARA_OK;
+}
+
+ara_status ara_run_portfolio(ara_tables* t, const ara_program* programs, int32_t n_programs, int32_t n_splits,
+                             const ara_portfolio_out* out, uint32_t flags, void* stream) {
+    if (!t || !programs || !out) return fail(ARA_ERR_INVALID_ARG, "NULL argument");
+    if (n_programs < 1) return fail(ARA_ERR_INVALID_ARG, "a portfolio needs at least one program");
+    if (n_programs > ARA_MAX_PROGRAMS)
+        return fail(ARA_ERR_UNSUPPORTED, "%d programs, at most %d", n_programs, ARA_MAX_PROGRAMS);
+    if (n_splits < 1) return fail(ARA_ERR_INVALID_ARG, "n_splits must be >= 1");
+    if (!out->layer_ylt && !out->program_ylt && !out->portfolio_ylt) return fail(ARA_ERR_INVALID_ARG, "no output");
+    if (flags & (ARA_CHECKPOINT_S | ARA_CHECKPOINT_STRIDE | ARA_GRAPH))
+        return fail(ARA_ERR_INVALID_ARG, "ara_run_portfolio takes ARA_DEVICE_PTR, ARA_LITERAL and ARA_PROFILE");
+    std::vector<ara::LayerArgs> L;
+    ara::PortfolioSumArgs agg{};
+    agg.n_programs = n_programs;
+    agg.first[0] = 0;
+    for (int p = 0; p < n_programs; ++p) {
+        if (programs[p].n_layers < 1 || !programs[p].layers)
+            return fail(ARA_ERR_INVALID_ARG, "program %d has no layers", p);
+        for (int i = 0; i < programs[p].n_layers; ++i) {
+            ara::LayerArgs a;
+            ara_status st = build_layer_args(t, programs[p].layers[i], a);
+            if (st != ARA_OK) return st;
+            if (!L.empty() && (a.trial_begin != L[0].trial_begin || a.trial_count != L[0].trial_count))
+                return fail(ARA_ERR_INVALID_ARG, "program %d layer %d covers other trials than the first layer", p, i);
+            L.push_back(a);
+        }
+        agg.first[p + 1] = static_cast<int32_t>(L.size());
+    }
+    const int64_t n_layers = static_cast<int64_t>(L.size());
+    const int64_t begin = L[0].trial_begin, n = L[0].trial_count;
+    if (out->layer_ylt && out->layer_capacity < n_layers * n)
+        return fail(ARA_ERR_BUFFER_TOO_SMALL, "layer_ylt holds %lld values, %lld needed",
+                    (long long)out->layer_capacity, (long long)(n_layers * n));
+    if (out->program_ylt && out->program_capacity < n_programs * n)
+        return fail(ARA_ERR_BUFFER_TOO_SMALL, "program_ylt holds %lld values, %lld needed",
+                    (long long)out->program_capacity, (long long)(n_programs * n));
+    if (out->portfolio_ylt && out->portfolio_capacity < n)
+        return fail(ARA_ERR_BUFFER_TOO_SMALL, "portfolio_ylt holds %lld values, %lld needed",
+                    (long long)out->portfolio_capacity, (long long)n);
+    if (n == 0) return ARA_OK;
+    DeviceScope ds(t->device);
+    if (!ds.ok) return fail(ARA_ERR_DEVICE, "cannot select the tables' device");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const bool dev_out = (flags & ARA_DEVICE_PTR) != 0;
+    const bool literal = (flags & ARA_LITERAL) != 0;
+    const bool prof = (flags & ARA_PROFILE) != 0;
+    ara_tuning tu;
+    {
+        std::lock_guard<std::mutex> g(t->mu);
+        tu = t->tuning;
+    }
+    const bool use_parts = !literal && t->parts.P > 0;
+    const bool use_xcd = use_parts && tu.pass_variant == 0;
+    // split i covers [b(i), b(i + 1)): Algorithm 1's YET_i
+    auto split_at = [&](int64_t i) { return begin + (n * i) / n_splits; };
+    int64_t most = 0;
+    for (int64_t i = 0; i < n_splits; ++i) most = std::max(most, split_at(i + 1) - split_at(i));
+    // one kept scratch buffer: occurrence losses, part images, partial sums of
+    // the largest split, and whatever output the caller keeps on the host
+    auto up = [](size_t v) { return (v + 255) & ~size_t(255); };
+    const size_t o_bytes = literal ? 0 : up(sizeof(double) * t->C);
+    const size_t p_bytes = use_parts ? up(static_cast<size_t>(ara::part_scratch_bytes(t->C, t->parts.P))) : 0;
+    const size_t x_bytes = use_xcd ? up(sizeof(double) * 2 * t->parts.P * most) : 0;
+    const bool stage_layers = !dev_out || !out->layer_ylt;
+    const size_t l_bytes = stage_layers ? up(sizeof(double) * n_layers * n) : 0;
+    const size_t g_bytes = !dev_out && out->program_ylt ? up(sizeof(double) * n_programs * n) : 0;
+    const size_t f_bytes = !dev_out && out->portfolio_ylt ? up(sizeof(double) * n) : 0;
+    ScratchLease lease(t->scratch_mu);
+    lease.s = s;
+    HIP_TRY(scratch_acquire(t->scratch_mu, t->scratch, o_bytes + p_bytes + x_bytes + l_bytes + g_bytes + f_bytes + 256,
+                            s, &lease.b),
+            "portfolio scratch");
+    char* base = static_cast<char*>(lease.b->p);
+    double* o_buf = reinterpret_cast<double*>(base);
+    void* p_buf = base + o_bytes;
+    double* x_buf = reinterpret_cast<double*>(base + o_bytes + p_bytes);
+    double* layer_rows = stage_layers ? reinterpret_cast<double*>(base + o_bytes + p_bytes + x_bytes) : out->layer_ylt;
+    double* program_rows = nullptr;
+    double* portfolio_row = nullptr;
+    if (out->program_ylt)
+        program_rows = dev_out ? out->program_ylt
+                               : reinterpret_cast<double*>(base + o_bytes + p_bytes + x_bytes + l_bytes);
+    if (out->portfolio_ylt)
+        portfolio_row = dev_out ? out->portfolio_ylt
+                                : reinterpret_cast<double*>(base + o_bytes + p_bytes + x_bytes + l_bytes + g_bytes);
+    for (int64_t l = 0; l < n_layers; ++l) {
+        if (!literal) {
+            KernelTimer kt(t, s, prof, ARA_KERNEL_FOLD);
+            if (use_parts)
+                HIP_TRY(ara::launch_fold_parts(t->elts, t->C, L[l], nullptr, o_buf, t->parts.P, p_buf, s),
+                        "fold and part images");
+            else
+                HIP_TRY(ara::launch_fold(t->elts, t->C, L[l], o_buf, tu, s), "fold");
+            kt.done();
+        }
+        for (int64_t i = 0; i < n_splits; ++i) {
+            ara::LayerArgs Li = L[l];
+            Li.trial_begin = split_at(i);
+            Li.trial_count = split_at(i + 1) - Li.trial_begin;
+            if (Li.trial_count == 0) continue;
+            double* ylt_i = layer_rows + l * n + (Li.trial_begin - begin);
+            if (use_xcd) {
+                KernelTimer kp(t, s, prof, ARA_KERNEL_TRIAL_PASS);
+                HIP_TRY(ara::launch_xcd_pass(t->parts, t->n_trials, t->C, Li, p_buf, x_buf, t->n_cu, s),
+                        "XCD-affine trial pass");
+                kp.done();
+                KernelTimer kc(t, s, prof, ARA_KERNEL_COMBINE);
+                HIP_TRY(ara::launch_xcd_combine(t->parts, Li, nullptr, x_buf, ylt_i, nullptr, s), "partial sums merge");
+                kc.done();
+            } else if (use_parts) {
+                KernelTimer kp(t, s, prof, ARA_KERNEL_TRIAL_PASS);
+                HIP_TRY(ara::launch_part_pass(t->parts, t->n_trials, Li, p_buf, ylt_i, nullptr, t->n_cu, s,
+                                              tu.part_lanes_per_trial),
+                        "partitioned trial pass");
+                kp.done();
+            } else {
+                ara::TrialPassArgs a{};
+                a.offsets = t->offsets;
+                a.ids = t->ids;
+                a.elts = t->elts;
+                a.C = t->C;
+                a.o = o_buf;
+                a.ylt = ylt_i;
+                KernelTimer kp(t, s, prof, ARA_KERNEL_TRIAL_PASS);
+                HIP_TRY(ara::launch_trial_pass(a, Li, literal, tu, t->n_cu, s), "trial pass");
+                kp.done();
+            }
+        }
+    }
+    if (program_rows || portfolio_row) {
+        agg.layer_ylt = layer_rows;
+        agg.count = n;
+        agg.program_ylt = program_rows;
+        agg.portfolio_ylt = portfolio_row;
+        KernelTimer ka(t, s, prof, ARA_KERNEL_AGGREGATE);
+        HIP_TRY(ara::launch_portfolio_sum(agg, t->n_cu, s), "program and portfolio sums");
+        ka.done();
+    }
+    if (!dev_out) {
+        if (out->layer_ylt)
+            HIP_TRY(hipMemcpyAsync(out->layer_ylt, layer_rows, sizeof(double) * n_layers * n, hipMemcpyDeviceToHost, s),
+                    "copy layer YLTs");
+        if (out->program_ylt)
+            HIP_TRY(hipMemcpyAsync(out->program_ylt, program_rows, sizeof(double) * n_programs * n,
+                                   hipMemcpyDeviceToHost, s),
+                    "copy program YLTs");
+        if (out->portfolio_ylt)
+            HIP_TRY(hipMemcpyAsync(out->portfolio_ylt, portfolio_row, sizeof(double) * n, hipMemcpyDeviceToHost, s),
+                    "copy portfolio YLT");
         HIP_TRY(hipStreamSynchronize(s), "synchronize");
     }
     return ARA_OK;

@@ -230,8 +230,8 @@ struct ProfileState {
     };
     std::vector<Pending> pending;
     std::vector<hipEvent_t> free_events;
-    int64_t launches[4] = {0, 0, 0, 0};
-    double total_ms[4] = {0.0, 0.0, 0.0, 0.0};
+    int64_t launches[5] = {0, 0, 0, 0, 0};
+    double total_ms[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
 };
 
 // Pinned host staging for small per-call uploads; the event marks when the
@@ -319,6 +319,16 @@ hipError_t launch_fold(const double* elts, int64_t C, const LayerArgs& L, double
                        const ara_tuning& tu, hipStream_t s);
 hipError_t launch_trial_pass(const TrialPassArgs& a, const LayerArgs& L, bool literal,
                              const ara_tuning& tu, int n_cu, hipStream_t s);
+// per-trial sums of layer year losses into program and portfolio year losses
+struct PortfolioSumArgs {
+    const double* layer_ylt;              // [n_layers][count]
+    int64_t count;
+    int32_t n_programs;
+    int32_t first[ARA_MAX_PROGRAMS + 1];  // program p sums layers [first[p], first[p + 1])
+    double* program_ylt;                  // [n_programs][count] or null
+    double* portfolio_ylt;                // [count] or null
+};
+hipError_t launch_portfolio_sum(const PortfolioSumArgs& a, int n_cu, hipStream_t s);
 // per-event net losses of a layer's trials, in time order, from the folded o
 hipError_t launch_event_nets(const int64_t* offsets, const uint32_t* ids, const double* o, const LayerArgs& L,
                              double* nets, int n_cu, hipStream_t s);

@@ -360,6 +360,117 @@ def test_event_nets_match_oracle(ara, cfg0):
     t2.close()
 
 
+# ---------------------------------------------------------------------------
+# portfolio: programs of layers, the YET split N ways
+# ---------------------------------------------------------------------------
+
+def _portfolio_close(got, ref):
+    for name, r in zip(("layer", "program", "portfolio"), ref):
+        ok, worst = _close(np.asarray(got[name]).ravel(), np.asarray(r).ravel())
+        assert ok, (name, worst)
+
+
+def test_portfolio_closed_form(ara, golden_dir):
+    g = json.load(open(os.path.join(golden_dir, "closed_form_cases.json")))
+    pool = ELTPool(np.array(g["elts"]), np.array(g["elt_retention"]), np.array(g["elt_limit"]))
+    pc = g["portfolio_case"]
+    yet = make_tiny_yet(pc["trials"], g["catalogue_size"])
+    f = lambda v: INF if v == "inf" else float(v)  # noqa: E731
+    by_name = {}
+    for case in g["cases"]:
+        t = case["terms"]
+        lay = Layer(np.array(case["elt_index"], dtype=np.int32), f(t["occ_retention"]),
+                    f(t["occ_limit"]), f(t["agg_retention"]), f(t["agg_limit"]), 0, yet.n_trials)
+        by_name[case["name"][0]] = _spec(ara, lay, pool, yet)
+    programs = [[by_name[n] for n in prog] for prog in pc["programs"]]
+    tables = ara.create_tables(yet.offsets, yet.ids, pool.losses)
+    for n_splits in (1, 2, 4, 6, 9):          # 9 > 6 trials: some splits are empty
+        res = ara.run_portfolio(tables, programs, n_splits=n_splits)
+        assert res["layer"].tolist() == pc["layer_ylt"], n_splits
+        assert res["program"].tolist() == pc["program_ylt"], n_splits
+        assert res["portfolio"].tolist() == pc["portfolio_ylt"], n_splits
+    tables.close()
+
+
+def _portfolio_programs(pool, begin, count):
+    mk = lambda ix, *terms: Layer(np.array(ix, dtype=np.int32), *terms, begin, count)  # noqa: E731
+    return [
+        [mk([0, 1, 2, 3], 3000.0, 5.0e5, 2.0e5, 1.5e6)],
+        [mk([3, 1], 1000.0, 4.0e5, 5.0e4, 2.0e6), mk([0, 2, 3], 0.0, INF, 1.0e5, INF)],
+        [mk([2], 0.0, INF, 0.0, INF), mk([1, 0], 500.0, 2.0e5, 0.0, 8.0e5), mk([3], 0.0, 1.0e5, 3.0e5, INF)],
+    ]
+
+
+def test_portfolio_config0_splits(ara, cfg0):
+    """Three programs of 1-3 layers over config0: every output against the
+    oracle, bit-identical for every split count, device outputs on a side
+    stream, a sub-range, the literal pass, profiling and the error paths."""
+    import torch
+    w, tables, _, _ = cfg0
+    yet, pool = w.yet, w.pool
+    programs = _portfolio_programs(pool, 0, yet.n_trials)
+    ref = oracle.portfolio(yet, pool, programs)
+    specs = [[_spec(ara, l, pool, yet) for l in prog] for prog in programs]
+    base = ara.run_portfolio(tables, specs, n_splits=1)
+    _portfolio_close(base, ref)
+    for n_splits in (2, 3, 8, 64):
+        res = ara.run_portfolio(tables, specs, n_splits=n_splits)
+        for name in ("layer", "program", "portfolio"):
+            assert np.array_equal(res[name], base[name]), (name, n_splits)
+    n = yet.n_trials
+    outs = {"program": torch.empty((3, n), dtype=torch.float64, device="cuda"),
+            "portfolio": torch.empty(n, dtype=torch.float64, device="cuda")}
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        ara.run_portfolio(tables, specs, n_splits=4, outs=outs, stream=stream)
+    stream.synchronize()
+    assert np.array_equal(outs["program"].cpu().numpy(), base["program"])
+    assert np.array_equal(outs["portfolio"].cpu().numpy(), base["portfolio"])
+    sub = [[_spec(ara, l, pool, yet) for l in prog] for prog in _portfolio_programs(pool, 37, 5001)]
+    res = ara.run_portfolio(tables, sub, n_splits=5)
+    assert np.array_equal(res["portfolio"], base["portfolio"][37:37 + 5001])
+    assert np.array_equal(res["layer"], base["layer"][:, 37:37 + 5001])
+    lit = ara.run_portfolio(tables, specs, n_splits=3, flags=ara.ARA_LITERAL)
+    _portfolio_close(lit, ref)
+    ara.kernel_stats(tables, ara.KERNEL_AGGREGATE, reset=True)
+    ara.run_portfolio(tables, specs, n_splits=2, flags=ara.ARA_PROFILE)
+    launches, ms = ara.kernel_stats(tables, ara.KERNEL_AGGREGATE, reset=True)
+    assert launches == 1 and ms > 0.0
+    errors = [
+        ([[specs[0][0], sub[1][0]]], 1, ara.ARA_ERR_INVALID_ARG),    # layers over other trials
+        (specs, 0, ara.ARA_ERR_INVALID_ARG),                         # no split
+        ([specs[0], []], 1, ara.ARA_ERR_INVALID_ARG),                # empty program
+        ([specs[0]] * 65, 1, ara.ARA_ERR_UNSUPPORTED),               # too many programs
+    ]
+    for progs, n_splits, status in errors:
+        with pytest.raises(ara.AraError) as e:
+            ara.run_portfolio(tables, progs, n_splits=n_splits)
+        assert e.value.status == status
+    with pytest.raises(ara.AraError) as e:
+        ara.run_portfolio(tables, specs, outs={"portfolio": np.empty(n - 1)})
+    assert e.value.status == ara.ARA_ERR_BUFFER_TOO_SMALL
+
+
+def test_portfolio_multi_part_catalogue(ara):
+    """A catalogue of 11 parts: the portfolio through the XCD-affine pass and
+    the rank-based variant, split 1, 3 and 7 ways."""
+    C = 2_700_000
+    yet = make_yet(700, 120.0, C, seed=53)
+    pool = make_elt_pool(4, C, 120_000, seed=54)
+    tables = ara.create_tables(yet.offsets, yet.ids, pool.losses)
+    programs = _portfolio_programs(pool, 0, yet.n_trials)
+    ref = oracle.portfolio(yet, pool, programs)
+    specs = [[_spec(ara, l, pool, yet) for l in prog] for prog in programs]
+    for knobs in (dict(pass_variant=0), dict(pass_variant=1, part_lanes_per_trial=16)):
+        ara.set_tuning(tables, **knobs)
+        base = ara.run_portfolio(tables, specs, n_splits=1)
+        _portfolio_close(base, ref)
+        for n_splits in (3, 7):
+            res = ara.run_portfolio(tables, specs, n_splits=n_splits)
+            assert np.array_equal(res["portfolio"], base["portfolio"]), (knobs, n_splits)
+    tables.close()
+
+
 def test_error_paths(ara):
     C = 100
     pool = make_elt_pool(2, C, 10, seed=3)

@@ -388,6 +388,63 @@ def test_event_nets_invariants(small):
 
 
 # ---------------------------------------------------------------------------
+# portfolio: programs of layers over one YET
+# ---------------------------------------------------------------------------
+
+def _golden_portfolio(golden):
+    pool = _golden_pool(golden)
+    pc = golden["portfolio_case"]
+    yet = make_tiny_yet(pc["trials"], golden["catalogue_size"])
+    by_name = {c["name"][0]: _golden_layer(c, yet.n_trials) for c in golden["cases"]}
+    programs = [[by_name[name] for name in prog] for prog in pc["programs"]]
+    return yet, pool, programs, pc
+
+
+def test_closed_form_portfolio(golden):
+    yet, pool, programs, pc = _golden_portfolio(golden)
+    rows, prog_rows, pf = oracle.portfolio(yet, pool, programs)
+    assert rows.tolist() == pc["layer_ylt"]
+    assert prog_rows.tolist() == pc["program_ylt"]
+    assert pf.tolist() == pc["portfolio_ylt"]
+
+
+def test_portfolio_sums_round_once():
+    """Layer year losses 2^53, 1, 1: the sum rounded once is 2^53 + 2; adding
+    in turn in FP64 would give 2^53 twice over (ties to even)."""
+    big = 2.0 ** 53
+    pool = ELTPool(losses=np.array([[big], [1.0], [1.0]]), retention=np.zeros(3),
+                   limit=np.full(3, INF))
+    yet = make_tiny_yet([[0], []], 1)
+    layers = [Layer(np.array([j], dtype=np.int32), 0.0, INF, 0.0, INF, 0, 2) for j in range(3)]
+    rows, prog_rows, pf = oracle.portfolio(yet, pool, [layers])
+    assert rows[:, 0].tolist() == [big, 1.0, 1.0]
+    assert prog_rows.tolist() == [[big + 2.0, 0.0]]
+    assert pf.tolist() == [big + 2.0, 0.0]
+    assert (big + 1.0) + 1.0 == big      # the sequential order really does lose both
+
+
+def test_portfolio_reductions(small):
+    """One program of one layer is that layer; programs of integer-valued
+    layers add up exactly to the portfolio; layers over other trials are
+    rejected."""
+    yet, pool, layer = small
+    ylt, _ = oracle.run_layer(yet, pool, layer)
+    rows, prog_rows, pf = oracle.portfolio(yet, pool, [[layer]])
+    assert np.array_equal(rows[0], ylt) and np.array_equal(prog_rows[0], ylt)
+    assert np.array_equal(pf, ylt)
+    ints = ELTPool(losses=np.floor(pool.losses / 64.0), retention=np.zeros(pool.losses.shape[0]),
+                   limit=np.full(pool.losses.shape[0], INF))
+    lay = [Layer(np.array(ix, dtype=np.int32), 0.0, INF, 0.0, INF, 0, yet.n_trials)
+           for ix in ([0, 1], [2], [3, 4, 5], [1, 3])]
+    rows, prog_rows, pf = oracle.portfolio(yet, ints, [lay[:2], lay[2:]])
+    assert np.array_equal(prog_rows[0], rows[0] + rows[1])
+    assert np.array_equal(pf, prog_rows[0] + prog_rows[1])
+    other = Layer(lay[0].elt_index, 0.0, INF, 0.0, INF, 1, yet.n_trials - 1)
+    with pytest.raises(ValueError):
+        oracle.portfolio(yet, ints, [[lay[0], other]])
+
+
+# ---------------------------------------------------------------------------
 # P5: metrics
 # ---------------------------------------------------------------------------
 
