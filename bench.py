@@ -51,6 +51,11 @@ def parse():
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the 64-layer batched run (config 2)")
     ap.add_argument("--batched-steps", type=int, default=5)
+    ap.add_argument("--no-portfolio", action="store_true",
+                    help="skip the portfolio run (10 programs of the 64 library layers, YET split 1-8 ways)")
+    ap.add_argument("--portfolio-steps", type=int, default=3)
+    ap.add_argument("--no-event-nets", action="store_true",
+                    help="skip the per-event net-loss run on the main workload")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (reference for counter scaling)")
     return ap.parse_args()
@@ -116,6 +121,55 @@ def batched_study(ara, tables, w, library, steps, stream):
                      "pct_hbm_fused_bytes": round(res["fused_bytes"] / (ms / 1e3) / (HBM_PEAK_GBS * 1e9), 4)}
         log(f"batched 64 layers ({name}): {ms:.3f} ms, {lookups / (ms / 1e3):.3e} lookups/s")
     del out
+    return res
+
+
+def portfolio_study(ara, tables, w, steps):
+    """Algorithm 1 over a portfolio: the 64 library layers grouped in order
+    into 10 programs, every layer over all trials, the YET split 1, 2, 4 and
+    8 ways.  Per split count: time per portfolio (HIP events), whether the
+    program and portfolio YLTs are bit-identical to the unsplit run, and the
+    program/portfolio sum kernel's duration and HBM rate."""
+    import torch
+    from workloads import portfolio_programs
+    N = w.yet.n_trials
+    progs = portfolio_programs(w.layers, 10, 0, N, seed=w.meta["seed"] + 100)
+    specs = [[ara.LayerSpec.from_layer(l, w.pool, N) for l in p] for p in progs]
+    n_layers = sum(len(p) for p in progs)
+    lookups = float(w.yet.n_events) * sum(l.n_elts for p in progs for l in p)
+    sum_bytes = 8.0 * N * (n_layers + len(progs) + 1)
+    outs = {"program": torch.empty((len(progs), N), dtype=torch.float64, device="cuda"),
+            "portfolio": torch.empty(N, dtype=torch.float64, device="cuda")}
+    stream = torch.cuda.Stream()
+    res = {"programs": len(progs), "layers": n_layers, "layers_per_program": [len(p) for p in progs],
+           "trials": N, "lookups": lookups, "sum_kernel_bytes": sum_bytes, "by_splits": {}}
+    ref = None
+    for n_splits in (1, 2, 4, 8):
+        ara.run_portfolio(tables, specs, n_splits, outs=outs, stream=stream)
+        stream.synchronize()
+        if ref is None:
+            ref = {k: v.clone() for k, v in outs.items()}
+            identical = True
+        else:
+            identical = all(bool(torch.equal(outs[k], ref[k])) for k in outs)
+        ara.kernel_stats(tables, ara.KERNEL_AGGREGATE, reset=True)
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(steps):
+            ara.run_portfolio(tables, specs, n_splits, outs=outs, stream=stream, flags=ara.ARA_PROFILE)
+        b.record(stream)
+        stream.synchronize()
+        ms = a.elapsed_time(b) / steps
+        n_sum, ms_sum = ara.kernel_stats(tables, ara.KERNEL_AGGREGATE, reset=True)
+        sum_ms = ms_sum / max(n_sum, 1)
+        res["by_splits"][str(n_splits)] = {
+            "ms": round(ms, 3), "lookups_per_s": lookups / (ms / 1e3), "bit_identical_to_1": identical,
+            "sum_kernel_ms": round(sum_ms, 4),
+            "sum_kernel_gbs": round(sum_bytes / (sum_ms / 1e3) / 1e9, 1)}
+        log(f"portfolio {len(progs)} programs / {n_layers} layers, {n_splits} splits: {ms:.3f} ms, "
+            f"{lookups / (ms / 1e3):.3e} lookups/s, sums {sum_ms:.4f} ms, identical={identical}")
+    del outs, ref
     return res
 
 
@@ -239,6 +293,33 @@ def main() -> None:
         extra["grad_fwd_ratio_vs_plain_step"] = round((bwd / reps) / ms_step, 4)
         log(f"forward+ckpt {fwd / reps:.4f} ms, backward {bwd / reps:.4f} ms")
 
+    if not args.no_event_nets:
+        # per-event net losses of every event of the workload, to a device buffer
+        nets = torch.empty(n_ev, dtype=torch.float64, device="cuda")
+        ara.event_nets(tables, spec, out=nets, stream=stream)
+        torch.cuda.synchronize()
+        reps = 3
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            ara.event_nets(tables, spec, out=nets, stream=stream)
+        b.record(stream)
+        torch.cuda.synchronize()
+        nets_ms = a.elapsed_time(b) / reps
+        # the nets of a trial add up to its year loss (A_0 = 0): first 200 trials
+        head = nets[:int(yet.offsets[200])].cpu().numpy()
+        ylt_h = out[:200].cpu().numpy()
+        worst = max(abs(math.fsum(head[yet.offsets[t]:yet.offsets[t + 1]].tolist()) - ylt_h[t])
+                    / max(ylt_h[t], 1.0) for t in range(200))
+        nets_bytes = 4.0 * n_ev + 8.0 * (N + 1) + 8.0 * n_ev + 8.0 * J * C + 16.0 * C
+        extra["event_nets"] = {"ms": round(nets_ms, 4), "events_per_s": n_ev / (nets_ms / 1e3),
+                               "algorithmic_bytes": nets_bytes,
+                               "pct_hbm": round(nets_bytes / (nets_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                               "telescoping_rel_err_200_trials": worst}
+        log(f"event nets: {nets_ms:.4f} ms for {n_ev} events, telescoping error {worst:.2e}")
+        del nets
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -260,7 +341,8 @@ def main() -> None:
     del out, res
     serving = None
     batched = None
-    if not (args.no_serving and args.no_batched):
+    portfolio = None
+    if not (args.no_serving and args.no_batched and args.no_portfolio):
         t1 = time.time()
         w4 = make_config("config4")
         base = ara.create_tables(w4.yet.offsets, w4.yet.ids, w4.pool.losses)
@@ -268,6 +350,8 @@ def main() -> None:
         log(f"config2/4 tables resident ({base.bytes() / 1e9:.2f} GB) in {time.time() - t1:.1f}s")
         if not args.no_batched:
             batched = batched_study(ara, base, w4, library, args.batched_steps, stream)
+        if not args.no_portfolio:
+            portfolio = portfolio_study(ara, base, w4, args.portfolio_steps)
         if not args.no_serving:
             from paper_1606_04473_amd import serving as srv
             serving = srv.run_tenant_study(base, w4.yet.offsets, w4.yet.ids, library, n_tenants=8,
@@ -303,6 +387,8 @@ def main() -> None:
     line.update(extra)
     if batched is not None:
         line["batched_config2"] = batched
+    if portfolio is not None:
+        line["portfolio_config2_layers"] = portfolio
     if serving is not None:
         line["serving"] = serving
     print(json.dumps(line), flush=True)

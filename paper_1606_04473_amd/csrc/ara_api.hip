@@ -1208,20 +1208,24 @@ ara_status ara_event_nets(ara_tables* t, const ara_layer* layer, double* nets, i
     if (n == 0) return ARA_OK;
     if (!nets) return fail(ARA_ERR_INVALID_ARG, "NULL output");
     const bool dev = (flags & ARA_DEVICE_PTR) != 0;
-    PoolBuffer obuf, staged;
-    HIP_TRY(obuf.alloc(sizeof(double) * t->C, s), "scratch for occurrence losses");
-    double* out = nets;
-    if (!dev) {
-        HIP_TRY(staged.alloc(sizeof(double) * n, s), "scratch for net losses");
-        out = static_cast<double*>(staged.p);
-    }
-    ara_tuning tu;
-    {
-        std::lock_guard<std::mutex> g(t->mu);
-        tu = t->tuning;
-    }
-    HIP_TRY(ara::launch_fold(t->elts, t->C, L, static_cast<double*>(obuf.p), tu, s), "fold");
-    HIP_TRY(ara::launch_event_nets(t->offsets, t->ids, static_cast<const double*>(obuf.p), L, out, t->n_cu, s),
+    // kept scratch: o, the part images with the compact values, the probe
+    // words, staged output
+    auto up = [](size_t v) { return (v + 255) & ~size_t(255); };
+    const int P = ara::part_count(t->C);
+    const size_t o_bytes = up(sizeof(double) * t->C);
+    const size_t p_bytes = up(static_cast<size_t>(ara::part_scratch_bytes(t->C, P)));
+    const size_t w_bytes = up(static_cast<size_t>(ara::probe_table_bytes(t->C)));
+    const size_t n_bytes = dev ? 0 : up(sizeof(double) * n);
+    ScratchLease lease(t->scratch_mu);
+    lease.s = s;
+    HIP_TRY(scratch_acquire(t->scratch_mu, t->scratch, o_bytes + p_bytes + w_bytes + n_bytes + 256, s, &lease.b),
+            "scratch for occurrence losses, part images, probe words and net losses");
+    char* base = static_cast<char*>(lease.b->p);
+    uint64_t* probe = reinterpret_cast<uint64_t*>(base + o_bytes + p_bytes);
+    double* out = dev ? nets : reinterpret_cast<double*>(base + o_bytes + p_bytes + w_bytes);
+    HIP_TRY(ara::launch_fold_parts(t->elts, t->C, L, nullptr, reinterpret_cast<double*>(base), P, base + o_bytes, s),
+            "fold and part images");
+    HIP_TRY(ara::launch_event_nets(t->offsets, t->ids, base + o_bytes, P, t->C, probe, L, out, t->n_cu, s),
             "net-loss kernel");
     if (!dev) {
         HIP_TRY(hipMemcpyAsync(nets, out, sizeof(double) * n, hipMemcpyDeviceToHost, s), "copy nets");

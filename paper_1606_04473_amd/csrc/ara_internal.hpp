@@ -329,9 +329,12 @@ struct PortfolioSumArgs {
     double* portfolio_ylt;                // [count] or null
 };
 hipError_t launch_portfolio_sum(const PortfolioSumArgs& a, int n_cu, hipStream_t s);
-// per-event net losses of a layer's trials, in time order, from the folded o
-hipError_t launch_event_nets(const int64_t* offsets, const uint32_t* ids, const double* o, const LayerArgs& L,
-                             double* nets, int n_cu, hipStream_t s);
+// per-event net losses of a layer's trials, in time order, reading o(E)
+// through the part images and compact values that launch_fold_parts wrote to
+// part_scratch (P = catalogue parts)
+hipError_t launch_event_nets(const int64_t* offsets, const uint32_t* ids, const void* part_scratch, int P,
+                             int64_t C, uint64_t* probe, const LayerArgs& L, double* nets, int n_cu, hipStream_t s);
+int64_t probe_table_bytes(int64_t C);   // scratch for launch_event_nets' probe words
 hipError_t launch_debug_lookups(const int64_t* offsets, const uint32_t* ids, const double* elts,
                                 int64_t C, const LayerArgs& L, int64_t trial, uint32_t* ids_out,
                                 double* losses_out, hipStream_t s);
@@ -341,6 +344,7 @@ hipError_t build_part_layout(const int64_t* offsets, const uint32_t* ids, int64_
                              int n_cu, hipStream_t s, PartLayout* out);
 void free_part_layout(PartLayout* L);
 int64_t part_scratch_bytes(int64_t C, int P);
+int part_count(int64_t C);   // catalogue parts of the part images
 hipError_t launch_part_fold(const double* o, int64_t C, int P, void* scratch, hipStream_t s, bool with_ranks);
 // the fold fused with the part images, then ranks and the compact array; with
 // L_dev the terms are read from device memory (for graph replays), else from L

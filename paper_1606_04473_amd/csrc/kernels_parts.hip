@@ -22,6 +22,8 @@
 //    result does not depend on scheduling.
 #include <vector>
 
+#include <type_traits>
+
 #include "ara_internal.hpp"
 
 namespace ara {
@@ -1087,6 +1089,278 @@ PartScratch carve_parts(void* scratch, int P) {
     return r;
 }
 }  // namespace
+
+// ---------------------------------------------------------------------------
+// per-event net losses (the cumulative form of the aggregate terms)
+// ---------------------------------------------------------------------------
+
+namespace {
+
+constexpr int kProbeShift = 5;                  // 32 catalogue events per probe word
+constexpr int kNetsThreads = 256;
+
+// value moved across lanes by a DPP control; lanes without a source get 0
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t v) {
+    return static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), kCtrl, kRowMask, 0xF, false));
+}
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const uint64_t b = __double_as_longlong(v);
+    const uint32_t lo = dpp_u32<kCtrl, kRowMask>(static_cast<uint32_t>(b));
+    const uint32_t hi = dpp_u32<kCtrl, kRowMask>(static_cast<uint32_t>(b >> 32));
+    return __longlong_as_double(static_cast<int64_t>((static_cast<uint64_t>(hi) << 32) | lo));
+}
+__device__ __forceinline__ uint64_t readlane_u64(uint64_t v, int lane) {
+    const uint32_t lo = __builtin_amdgcn_readlane(static_cast<int>(static_cast<uint32_t>(v)), lane);
+    const uint32_t hi = __builtin_amdgcn_readlane(static_cast<int>(static_cast<uint32_t>(v >> 32)), lane);
+    return (static_cast<uint64_t>(hi) << 32) | lo;
+}
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+    return __longlong_as_double(static_cast<int64_t>(readlane_u64(static_cast<uint64_t>(__double_as_longlong(v)), lane)));
+}
+
+// One stage of a segmented double-double scan: (f, h, l) becomes
+// left (+) self, where a lane that starts a segment (f set) keeps its sum.
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ void seg_stage(uint32_t& f, double& h, double& l) {
+    const uint32_t uf = dpp_u32<kCtrl, kRowMask>(f);
+    const double uh = dpp_f64<kCtrl, kRowMask>(h), ul = dpp_f64<kCtrl, kRowMask>(l);
+    double mh = h, ml = l;
+    dd_merge(mh, ml, uh, ul);
+    if (!f) {
+        h = mh;
+        l = ml;
+        f = uf;
+    }
+}
+// inclusive over the wave: row shifts 1, 2, 4, 8, then row broadcasts 15, 31
+__device__ __forceinline__ void wave_seg_scan_dd(uint32_t& f, double& h, double& l) {
+    seg_stage<0x111, 0xF>(f, h, l);
+    seg_stage<0x112, 0xF>(f, h, l);
+    seg_stage<0x114, 0xF>(f, h, l);
+    seg_stage<0x118, 0xF>(f, h, l);
+    seg_stage<0x142, 0xA>(f, h, l);
+    seg_stage<0x143, 0xC>(f, h, l);
+}
+
+// smallest t in [lo, hi] with offsets[t] >= target, given offsets[hi] >=
+// target; a 64-way search, all arguments uniform over the wave
+__device__ int64_t first_trial_at(const int64_t* __restrict__ offsets, int64_t lo, int64_t hi, int64_t target,
+                                  int lane) {
+    while (hi - lo >= 64) {
+        const int64_t step = (hi - lo) / 64;
+        const uint64_t m = __ballot(offsets[lo + lane * step] >= target);   // index <= hi - step
+        if (m == 0) {
+            lo = lo + 63 * step + 1;
+        } else {
+            const int f = __builtin_ctzll(m);
+            const int64_t nlo = f > 0 ? lo + (f - 1) * step + 1 : lo;
+            hi = lo + f * step;
+            lo = nlo;
+        }
+    }
+    const int64_t idx = lo + lane;
+    const uint64_t m = __ballot(idx <= hi && offsets[idx] >= target);
+    return lo + __builtin_ctzll(m);
+}
+
+// probe word per 32 catalogue events: the bitmap bits (low half) and the
+// rank of the word's first event among the nonzero ones (high half), built
+// from the part images
+__global__ __launch_bounds__(256) void probe_table_kernel(const uint8_t* __restrict__ img, int64_t n_words,
+                                                          uint64_t* __restrict__ probe) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n_words) return;
+    constexpr int kShift = kPartShift - kProbeShift;                    // probe words per part
+    const uint8_t* base = img + (i >> kShift) * kImgBytes;
+    const uint32_t j = static_cast<uint32_t>(i & ((int64_t(1) << kShift) - 1));
+    const uint32_t* bm32 = reinterpret_cast<const uint32_t*>(base);
+    const uint16_t* r16 = reinterpret_cast<const uint16_t*>(base + int64_t(kWords) * 8);
+    const uint32_t* b32 = reinterpret_cast<const uint32_t*>(base + int64_t(kWords) * 8 + int64_t(kRank16) * 2);
+    uint32_t rank = b32[j >> 7] + r16[j >> 2];       // superblock base, 128-event offset
+    for (uint32_t k = j & ~3u; k < j; ++k) rank += __builtin_popcount(bm32[k]);
+    probe[i] = (static_cast<uint64_t>(rank) << 32) | bm32[j];
+}
+
+// The layer's trials are split into one contiguous run per wave (event
+// shares rounded to trial starts), and each wave streams its run's IDs in
+// steps of 64 kE positions in time order, kE consecutive positions per lane
+// (16-byte loads, the next step's issued before this step's work).  o(E) is
+// 0 unless E's bit is set in its probe word, else compact[rank + bits below]
+// -- one 8-byte probe per event and one more load per nonzero loss, both from
+// tables that stay in L2.  Trial starts (held one per lane and marked in a
+// per-wave LDS flag row) reset a segmented double-double scan: each event's
+// running total S_d (the lane's own prefix, the scan of the lanes before it,
+// the carry of earlier steps) is rounded once; A_d = clamp(S_d; AggR, AggL)
+// and the net is A_d - A_{d-1}, with A_{d-1} = A_0 = clamp(0; AggR, AggL)
+// for a trial's first event, so a trial's nets telescope to its year loss
+// minus A_0.  Nets are staged in LDS and written with non-temporal stores of
+// 64 consecutive values.
+template <int kE>
+__global__ __launch_bounds__(kNetsThreads) void event_nets_kernel(const int64_t* __restrict__ offsets,
+                                                                  const uint32_t* __restrict__ ids,
+                                                                  const uint64_t* __restrict__ probe,
+                                                                  const double* __restrict__ compact, LayerArgs L,
+                                                                  double* __restrict__ nets) {
+    static_assert(kE == 4 || kE == 8, "four or eight events per lane");
+    constexpr int kW = 64 * kE;                                        // positions per step
+    static_assert(kW <= kIdPad, "a step may read up to kW - 1 IDs past the table's end");
+    __shared__ double stage[kNetsThreads / 64][kW];
+    __shared__ __attribute__((aligned(8))) uint8_t flag_rows[kNetsThreads / 64][kW];
+    const int lane = threadIdx.x & 63;
+    double* st = stage[threadIdx.x >> 6];
+    uint8_t* fl = flag_rows[threadIdx.x >> 6];
+    const int64_t w = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+    const int64_t n_w = (static_cast<int64_t>(gridDim.x) * blockDim.x) >> 6;
+    const int64_t t0 = L.trial_begin, t1 = L.trial_begin + L.trial_count;
+    const int64_t ev0 = offsets[t0];
+    const int64_t tot = offsets[t1] - ev0;
+    const int64_t k0 = first_trial_at(offsets, t0, t1, ev0 + tot * w / n_w, lane);
+    const int64_t k1 = first_trial_at(offsets, t0, t1, ev0 + tot * (w + 1) / n_w, lane);
+    if (k0 >= k1) return;
+    const int64_t P0 = offsets[k0], P1 = offsets[k1];
+    if (P0 >= P1) return;
+    const double A0 = apply_terms(0.0, L.aggR, L.aggL);
+    using flag_word = typename std::conditional<kE == 8, uint64_t, uint32_t>::type;
+    *reinterpret_cast<flag_word*>(fl + lane * kE) = 0;
+    int64_t kb = k0;                                                   // trial starts held: kb .. kb + 63
+    int64_t bnd = kb + lane < k1 ? offsets[kb + lane] : INT64_MAX;
+    const int64_t c0 = P0 & ~int64_t(3);
+    u32x4 nxt[kE / 4];
+#pragma unroll
+    for (int u = 0; u < kE / 4; ++u)
+        nxt[u] = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(ids + c0 + lane * kE + 4 * u));
+    double ch = 0.0, cl = 0.0;       // running total of the segment open at the step's start
+    double a_prev = A0;              // A of the position before the step
+    for (int64_t c = c0; c < P1; c += kW) {
+        u32x4 cur[kE / 4];
+#pragma unroll
+        for (int u = 0; u < kE / 4; ++u) cur[u] = nxt[u];
+        if (c + kW < P1) {
+#pragma unroll
+            for (int u = 0; u < kE / 4; ++u)
+                nxt[u] = __builtin_nontemporal_load(
+                    reinterpret_cast<const u32x4*>(ids + c + kW + lane * kE + 4 * u));
+        }
+        // mark the trial starts inside [c, c + kW)
+        for (;;) {
+            if (bnd >= c && bnd < c + kW) fl[bnd - c] = 1;
+            if (static_cast<int64_t>(readlane_u64(static_cast<uint64_t>(bnd), 63)) >= c + kW) break;
+            kb += 64;
+            bnd = kb + lane < k1 ? offsets[kb + lane] : INT64_MAX;
+        }
+        __builtin_amdgcn_wave_barrier();
+        uint32_t fq[kE];
+        {
+            const flag_word fw = *reinterpret_cast<const flag_word*>(fl + lane * kE);
+#pragma unroll
+            for (int q = 0; q < kE; ++q) fq[q] = static_cast<uint32_t>(fw >> (8 * q)) & 1u;
+        }
+        const int64_t pos = c + lane * kE;
+        uint32_t E[kE];
+        bool ok[kE];
+#pragma unroll
+        for (int q = 0; q < kE; ++q) {
+            ok[q] = pos + q >= P0 && pos + q < P1;
+            E[q] = ok[q] ? cur[q >> 2][q & 3] : 0u;
+        }
+        uint64_t pw[kE];
+#pragma unroll
+        for (int q = 0; q < kE; ++q) pw[q] = probe[E[q] >> kProbeShift];
+        double oq[kE];
+#pragma unroll
+        for (int q = 0; q < kE; ++q) {
+            const uint32_t bits = static_cast<uint32_t>(pw[q]);
+            const uint32_t bi = E[q] & 31u;
+            oq[q] = 0.0;
+            if (ok[q] && ((bits >> bi) & 1u)) {
+                const uint32_t below = bi ? (~0u >> (32u - bi)) : 0u;
+                oq[q] = compact[static_cast<uint32_t>(pw[q] >> 32) + __builtin_popcount(bits & below)];
+            }
+        }
+        // the lane's total since its last trial start (all of it if none)
+        uint32_t sf = 0;
+        double h = 0.0, l = 0.0;
+#pragma unroll
+        for (int q = 0; q < kE; ++q) {
+            if (fq[q]) {
+                h = 0.0;
+                l = 0.0;
+            }
+            dd_add(h, l, oq[q]);
+            sf |= fq[q];
+        }
+        if (lane == 0 && !sf) dd_merge(h, l, ch, cl);              // the open segment's carry
+        double sh = h, sl = l;
+        wave_seg_scan_dd(sf, sh, sl);
+        // the open segment's total before this lane's first event, then the
+        // running totals again, event by event: A of every position to LDS
+        double rh = __shfl_up(sh, 1, 64), rl = __shfl_up(sl, 1, 64);
+        if (lane == 0) {
+            rh = ch;
+            rl = cl;
+        }
+#pragma unroll
+        for (int q = 0; q < kE; ++q) {
+            if (fq[q]) {
+                rh = 0.0;
+                rl = 0.0;
+            }
+            dd_add(rh, rl, oq[q]);
+            st[lane * kE + q] = apply_terms(rh + rl, L.aggR, L.aggL);
+        }
+        __builtin_amdgcn_wave_barrier();
+        // nets of 64 consecutive positions per store; A of the position before
+        // a trial's first event is A_0, before the step's first one a_prev
+#pragma unroll
+        for (int q = 0; q < kE; ++q) {
+            const int i = q * 64 + lane;
+            const int64_t p = c + i;
+            const double before = fl[i] ? A0 : (i == 0 ? a_prev : st[i - 1]);
+            if (p >= P0 && p < P1) __builtin_nontemporal_store(st[i] - before, nets + (p - ev0));
+        }
+        a_prev = st[kW - 1];
+        ch = readlane_f64(sh, 63);
+        cl = readlane_f64(sl, 63);
+        __builtin_amdgcn_wave_barrier();
+        *reinterpret_cast<flag_word*>(fl + lane * kE) = 0;
+    }
+}
+
+}  // namespace
+
+int part_count(int64_t C) { return static_cast<int>((C + kPartSize - 1) / kPartSize); }
+
+int64_t probe_table_bytes(int64_t C) {
+    return static_cast<int64_t>(sizeof(uint64_t)) * ((C + (1 << kProbeShift) - 1) >> kProbeShift);
+}
+
+hipError_t launch_event_nets(const int64_t* offsets, const uint32_t* ids, const void* part_scratch, int P,
+                             int64_t C, uint64_t* probe, const LayerArgs& L, double* nets, int n_cu, hipStream_t s) {
+    if (L.trial_count <= 0) return hipSuccess;
+    PartScratch ps = carve_parts(const_cast<void*>(part_scratch), P);
+    const int64_t n_words = probe_table_bytes(C) / static_cast<int64_t>(sizeof(uint64_t));
+    hipLaunchKernelGGL(probe_table_kernel, dim3(static_cast<uint32_t>((n_words + 255) / 256)), dim3(256), 0, s,
+                       ps.img, n_words, probe);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // as many workgroups as the device holds at once
+    static const int per_cu = [] {
+        int v = 0;
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, event_nets_kernel<8>, kNetsThreads, 0) ==
+                           hipSuccess &&
+                       v > 0
+                   ? v
+                   : 4;
+    }();
+    int64_t blocks = (L.trial_count + kNetsThreads / 64 - 1) / (kNetsThreads / 64);
+    const int64_t cap = static_cast<int64_t>(n_cu) * per_cu;
+    if (blocks > cap) blocks = cap;
+    hipLaunchKernelGGL(event_nets_kernel<8>, dim3(static_cast<uint32_t>(blocks)), dim3(kNetsThreads), 0, s, offsets,
+                       ids, probe, ps.compact, L, nets);
+    return hipGetLastError();
+}
 
 hipError_t launch_part_fold(const double* o, int64_t C, int P, void* scratch, hipStream_t s, bool with_ranks) {
     PartScratch ps = carve_parts(scratch, P);

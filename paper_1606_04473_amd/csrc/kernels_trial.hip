@@ -157,79 +157,6 @@ __global__ __launch_bounds__(256) void trial_pass_kernel(TrialPassArgs a, LayerA
 }
 
 // ---------------------------------------------------------------------------
-// per-event net losses (the cumulative form of the aggregate terms)
-// ---------------------------------------------------------------------------
-
-// One wave per trial, 256 events per step in time order.  Each event's
-// running total S_d is a double-double prefix sum (the lane's four events in
-// sequence, an exclusive scan over the wave, the carry of earlier steps),
-// rounded once; A_d = clamp(S_d; AggR, AggL) and the event's net loss is
-// A_d - A_{d-1}, with A_0 = clamp(0; AggR, AggL).  The nets of a trial add up
-// to its year loss (the sum telescopes).
-__global__ __launch_bounds__(256) void event_nets_kernel(const int64_t* __restrict__ offsets,
-                                                         const uint32_t* __restrict__ ids,
-                                                         const double* __restrict__ o, LayerArgs L,
-                                                         double* __restrict__ nets) {
-    const int lane = threadIdx.x & 63;
-    int64_t w = uniform_i64((static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6);
-    const int64_t n_w = (static_cast<int64_t>(gridDim.x) * blockDim.x) >> 6;
-    const int64_t ev0 = offsets[L.trial_begin];
-    const double A0 = apply_terms(0.0, L.aggR, L.aggL);
-    for (int64_t k = w; k < L.trial_count; k += n_w) {
-        const int64_t t = L.trial_begin + k;
-        const int64_t b = offsets[t], e = offsets[t + 1];
-        double ch = 0.0, cl = 0.0;            // running total before this step
-        double a_prev = A0;                   // A of the last event before this step
-        for (int64_t c = b; c < e; c += 256) {
-            const int64_t base = c + lane * 4;
-            double oq[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) oq[q] = base + q < e ? o[ids[base + q]] : 0.0;
-            // the lane's own prefix sums, then its total
-            double ph[4], pl[4];
-            double h = 0.0, l = 0.0;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                dd_add(h, l, oq[q]);
-                ph[q] = h;
-                pl[q] = l;
-            }
-            // inclusive scan of the lane totals over the wave, then shifted by one lane
-            double sh = h, sl = l;
-#pragma unroll
-            for (int off = 1; off < 64; off <<= 1) {
-                const double uh = __shfl_up(sh, off, 64), ul = __shfl_up(sl, off, 64);
-                if (lane >= off) dd_merge(sh, sl, uh, ul);
-            }
-            double xh = __shfl_up(sh, 1, 64), xl = __shfl_up(sl, 1, 64);
-            if (lane == 0) {
-                xh = 0.0;
-                xl = 0.0;
-            }
-            dd_merge(xh, xl, ch, cl);             // everything before this lane's first event
-            double a[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                double th = xh, tl = xl;
-                dd_merge(th, tl, ph[q], pl[q]);
-                a[q] = apply_terms(th + tl, L.aggR, L.aggL);
-            }
-            // A of the event before each of this lane's: the previous lane's last
-            double left = __shfl_up(a[3], 1, 64);
-            if (lane == 0) left = a_prev;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                if (base + q < e) nets[base + q - ev0] = a[q] - (q == 0 ? left : a[q - 1]);
-            }
-            // carry: the wave's total, and the A of the step's last event
-            dd_merge(ch, cl, __shfl(sh, 63, 64), __shfl(sl, 63, 64));
-            const int64_t last = (e - c < 256 ? e - c : 256) - 1;     // index of the step's last event
-            a_prev = __shfl(a[last & 3], static_cast<int>(last >> 2), 64);
-        }
-    }
-}
-
-// ---------------------------------------------------------------------------
 // debug lookups, validation, fill
 // ---------------------------------------------------------------------------
 
@@ -296,16 +223,6 @@ hipError_t launch_fold(const double* elts, int64_t C, const LayerArgs& L, double
     if (C <= 0) return hipSuccess;
     const int64_t blocks = (C + 255) / 256;
     hipLaunchKernelGGL(fold_kernel, dim3(static_cast<uint32_t>(blocks)), dim3(256), 0, s, elts, C, L, o);
-    return hipGetLastError();
-}
-
-hipError_t launch_event_nets(const int64_t* offsets, const uint32_t* ids, const double* o, const LayerArgs& L,
-                             double* nets, int n_cu, hipStream_t s) {
-    if (L.trial_count <= 0) return hipSuccess;
-    int64_t blocks = (L.trial_count + 3) / 4;
-    if (blocks > int64_t(n_cu) * 8) blocks = int64_t(n_cu) * 8;
-    hipLaunchKernelGGL(event_nets_kernel, dim3(static_cast<uint32_t>(blocks)), dim3(256), 0, s, offsets, ids, o, L,
-                       nets);
     return hipGetLastError();
 }
 

@@ -471,6 +471,48 @@ def test_portfolio_multi_part_catalogue(ara):
     tables.close()
 
 
+def test_event_nets_multi_part_catalogue(ara):
+    """A catalogue of 11 parts: the net-loss kernel reads o(E) through every
+    part's bitmap, ranks and compact values, with trials that start at every
+    alignment."""
+    C = 2_700_000
+    yet = make_yet(700, 1300.0, C, seed=55)
+    pool = make_elt_pool(4, C, 300_000, seed=56)
+    tables = ara.create_tables(yet.offsets, yet.ids, pool.losses)
+    for lay in (Layer(np.array([3, 1, 0], dtype=np.int32), 1500.0, 4.0e5, 5.0e4, 6.0e6, 0, yet.n_trials),
+                Layer(np.array([2], dtype=np.int32), 0.0, INF, 0.0, INF, 301, 257)):
+        ylt, _ = oracle.run_layer(yet, pool, lay)
+        ref = oracle.event_nets(yet, pool, lay)
+        got = ara.event_nets(tables, _spec(ara, lay, pool, yet))
+        assert got.shape == ref.shape
+        ok, exact = _nets_close(got, ref, yet, lay, ylt)
+        assert ok and exact > 0.99, exact
+    tables.close()
+
+
+def test_event_nets_short_and_empty_trials(ara):
+    """Runs of trials of 0-3 events (more trial starts per 512-position step
+    than a wave holds at once), empty trials at the ends of the range, long
+    trials between them, and ranges that begin and end inside such runs."""
+    rng = np.random.default_rng(57)
+    C = 40_000
+    pool = make_elt_pool(3, C, 9_000, seed=58)
+    lengths = np.concatenate([np.zeros(5, np.int64), rng.integers(0, 4, 3000), [2500, 0, 1],
+                              rng.integers(0, 4, 2000), rng.integers(300, 900, 40), np.zeros(7, np.int64)])
+    trials = [rng.integers(0, C, size=int(k)).tolist() for k in lengths]
+    yet = make_tiny_yet(trials, C)
+    tables = ara.create_tables(yet.offsets, yet.ids, pool.losses)
+    for begin, count in ((0, yet.n_trials), (3, 2000), (1777, 3200), (yet.n_trials - 9, 9)):
+        lay = Layer(np.array([0, 2, 1], dtype=np.int32), 500.0, 3.0e5, 4.0e4, 9.0e5, begin, count)
+        ylt, _ = oracle.run_layer(yet, pool, lay)
+        ref = oracle.event_nets(yet, pool, lay)
+        got = ara.event_nets(tables, _spec(ara, lay, pool, yet))
+        assert got.shape == ref.shape, (begin, count)
+        ok, exact = _nets_close(got, ref, yet, lay, ylt)
+        assert ok and (exact > 0.99 or len(ref) == 0), (begin, count, exact)
+    tables.close()
+
+
 def test_error_paths(ara):
     C = 100
     pool = make_elt_pool(2, C, 10, seed=3)

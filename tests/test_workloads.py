@@ -69,3 +69,17 @@ def test_config0_matches_recipe():
     assert 0 < layer.occ_retention < layer.occ_limit
     assert 0 < layer.agg_retention and 0 < layer.agg_limit
     assert tuple(w.probs) == (0.99,)
+
+
+def test_portfolio_programs_partition_the_layers():
+    from workloads import Layer, portfolio_programs
+    layers = [Layer(np.array([i % 7], dtype=np.int32), 0.0, 1.0, 0.0, 2.0, 5 * i, 10 + i)
+              for i in range(64)]
+    a = portfolio_programs(layers, 10, 0, 1000, seed=7)
+    b = portfolio_programs(layers, 10, 0, 1000, seed=7)
+    assert len(a) == 10 and all(len(p) >= 1 for p in a)
+    flat = [l for p in a for l in p]
+    assert [int(l.elt_index[0]) for l in flat] == [i % 7 for i in range(64)]   # order kept
+    assert all(l.trial_begin == 0 and l.trial_count == 1000 for l in flat)
+    assert [len(p) for p in a] == [len(p) for p in b]
+    assert [len(p) for p in portfolio_programs(layers, 1, 0, 9, seed=1)] == [64]

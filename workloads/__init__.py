@@ -19,5 +19,6 @@ from .generators import (  # noqa: F401
     make_config,
     make_tiny_yet,
     layer_library,
+    portfolio_programs,
     CONFIG_NAMES,
 )

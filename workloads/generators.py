@@ -337,6 +337,23 @@ def make_config(name: str, n_prefix: Optional[int] = None, calibrated: bool = Tr
     return Workload(name=name, yet=yet, pool=pool, layers=layers, probs=cfg["probs"], meta=meta)
 
 
+def portfolio_programs(layers: Sequence[Layer], n_programs: int, trial_begin: int,
+                       trial_count: int, seed: int) -> List[List[Layer]]:
+    """Group ``layers`` in order into ``n_programs`` programs of at least one
+    layer each (sizes from a seeded uniform split), every layer re-ranged to
+    the portfolio's trials [trial_begin, trial_begin + trial_count)."""
+    n = len(layers)
+    if not 1 <= n_programs <= n:
+        raise ValueError("need 1 <= n_programs <= number of layers")
+    rng = _rng(np.random.SeedSequence(seed))
+    cuts = np.sort(rng.choice(np.arange(1, n), size=n_programs - 1, replace=False)) if n_programs > 1 \
+        else np.zeros(0, dtype=np.int64)
+    bounds = [0, *[int(c) for c in cuts], n]
+    ranged = [Layer(l.elt_index, l.occ_retention, l.occ_limit, l.agg_retention, l.agg_limit,
+                    trial_begin, trial_count) for l in layers]
+    return [ranged[bounds[p]:bounds[p + 1]] for p in range(n_programs)]
+
+
 def _clip_layer(layer: Layer, n_trials: int) -> Layer:
     begin = min(layer.trial_begin, n_trials)
     count = max(0, min(layer.trial_begin + layer.trial_count, n_trials) - begin)
