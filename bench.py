@@ -27,6 +27,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "trial_pass_config1_traffic.json")
+NETS_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "event_nets_config1_traffic.json")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1606_04473_amd", "csrc", "kernels_parts.hip")
 
 
@@ -74,12 +75,12 @@ def copy_probe() -> None:
     print(json.dumps({"copy_probe_bytes": n * 8, "launches": 3}), flush=True)
 
 
-def measured_traffic():
-    """HBM bytes per trial-pass launch from the committed rocprofv3 counter
+def measured_traffic(path=TRAFFIC_FILE):
+    """HBM bytes per launch of a kernel from a committed rocprofv3 counter
     summary, if it was taken on the current kernel source."""
-    if not os.path.exists(TRAFFIC_FILE):
+    if not os.path.exists(path):
         return None
-    with open(TRAFFIC_FILE) as f:
+    with open(path) as f:
         rec = json.load(f)
     src = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
     if rec.get("kernel_source_sha256") != src:
@@ -316,7 +317,8 @@ def main() -> None:
         extra["event_nets"] = {"ms": round(nets_ms, 4), "events_per_s": n_ev / (nets_ms / 1e3),
                                "algorithmic_bytes": nets_bytes,
                                "pct_hbm": round(nets_bytes / (nets_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
-                               "telescoping_rel_err_200_trials": worst}
+                               "telescoping_rel_err_200_trials": worst,
+                               "traffic": measured_traffic(NETS_TRAFFIC_FILE)}
         log(f"event nets: {nets_ms:.4f} ms for {n_ev} events, telescoping error {worst:.2e}")
         del nets
 
