@@ -643,16 +643,22 @@ __global__ __launch_bounds__(1024) void xcd_pass_kernel(XcdPassArgs a) {
     // zero word after it, the hit queues, and the first kCache nonzero losses
     constexpr uint32_t kBmBytes = kWords * 8;       // 32 KB bitmap
     constexpr uint32_t kZeroWord = static_cast<uint32_t>(kImgBytes);   // byte offset of the zero word
-    __shared__ __attribute__((aligned(16))) uint32_t img[kImgBytes / 4 + 4];
-    __shared__ uint32_t queue[16][kQ];              // per-wave hit queues: event index within the part
-    __shared__ double cache[kCache];
+    // one LDS block with the image first, so a bitmap byte offset is its LDS
+    // address
+    constexpr uint32_t kImgWords = kImgBytes / 4 + 4;
+    constexpr uint32_t kQueueOff = kImgWords * 4;                       // 16 per-wave hit queues (event IDs)
+    constexpr uint32_t kCacheOff = kQueueOff + 16 * kQ * 4;             // the loss cache (8-byte aligned)
+    static_assert(kCacheOff % 16 == 0, "aligned loss cache");
+    __shared__ __attribute__((aligned(16))) uint8_t lds[kCacheOff + kCache * 8];
+    uint32_t* img = reinterpret_cast<uint32_t*>(lds);
+    double* cache = reinterpret_cast<double*>(lds + kCacheOff);
     const uint32_t* bm = img;
     const uint16_t* r16 = reinterpret_cast<const uint16_t*>(reinterpret_cast<const char*>(img) + kBmBytes);
     const uint32_t* b32 = reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(img) + kBmBytes +
                                                             kRank16 * 2);
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
-    uint32_t* q = queue[wv];
+    uint32_t* q = reinterpret_cast<uint32_t*>(lds + kQueueOff) + wv * kQ;
     // parts served by this workgroup (its XCD's), and its rank among the servers
     // of each; the two halves of the workgroup (8 waves each) serve separately
     const int n_xcd = a.n_xcd;
@@ -798,7 +804,7 @@ __global__ __launch_bounds__(1024) void xcd_pass_kernel(XcdPassArgs a) {
                     if (jj < hi) {
                         // rank of the event among the nonzero ones: superblock base,
                         // 128-event offset, and the set bits below it in its 128 bits
-                        const uint32_t e = q[jj];
+                        const uint32_t e = q[jj] - pbase;
                         const u32x4 w4 = *reinterpret_cast<const u32x4*>(bm + ((e >> 7) << 2));
                         const uint32_t b = e & 127u, wi = b >> 5;
                         const uint32_t below = (b & 31u) ? (~0u >> (32u - (b & 31u))) : 0u;
@@ -811,9 +817,9 @@ __global__ __launch_bounds__(1024) void xcd_pass_kernel(XcdPassArgs a) {
                         v[r2] = lr < static_cast<uint32_t>(kCache) ? cache[lr] : a.compact[rk];
                     }
                 }
+                // entries past the trial's last are 0.0, whose sum is exact
 #pragma unroll
-                for (int r2 = 0; r2 < 4; ++r2)
-                    if (j + 2 * r2 < hi) dd_add(acc_hi, acc_lo, v[r2]);
+                for (int r2 = 0; r2 < 4; ++r2) dd_add(acc_hi, acc_lo, v[r2]);
             }
             qs = qs == kInf ? kInf : qs - qn;
             qn = 0;
@@ -835,9 +841,9 @@ __global__ __launch_bounds__(1024) void xcd_pass_kernel(XcdPassArgs a) {
 #pragma unroll
                 for (int w = 0; w < 4; ++w) {
                     const uint32_t id = ids[u][w];
-                    uint32_t wa = ((id >> 5) << 2) - pw4;          // byte address of the bitmap word
-                    wa = wa < kBmBytes ? wa : kZeroWord;
-                    const uint32_t word = *reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(bm) + wa);
+                    // byte address of the bitmap word; the padding's lands on the zero word
+                    const uint32_t wa = min(__builtin_amdgcn_ubfe(id, 5u, 27u) * 4u - pw4, kZeroWord);
+                    const uint32_t word = *reinterpret_cast<const uint32_t*>(lds + wa);
                     hits |= __builtin_amdgcn_ubfe(word, id, 1u) << (u * 4 + w);
                 }
             }
@@ -877,7 +883,7 @@ __global__ __launch_bounds__(1024) void xcd_pass_kernel(XcdPassArgs a) {
 #pragma unroll
                 for (int w = 0; w < 4; ++w) {
                     const uint32_t hb = (hits >> (u * 4 + w)) & 1u;
-                    if (hb) q[at] = ids[u][w] - pbase;
+                    if (hb) q[at] = ids[u][w];
                     at += static_cast<int>(hb);
                 }
             }
