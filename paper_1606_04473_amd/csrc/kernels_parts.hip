@@ -773,7 +773,8 @@ __global__ __launch_bounds__(1024) void xcd_pass_kernel(XcdPassArgs a) {
         // rs are masked off
         uint32_t c = rs & ~uint32_t(kTileAlign - 1);
 
-        // one batch of 16-byte ID chunks; chunks outside [cb, end) read the padding
+        // one batch of 16-byte ID chunks; chunks at or past `end` read the
+        // padding instead (cached), so no HBM line past the range is fetched
         auto load_batch = [&](const uint32_t* ids, uint32_t cb, uint32_t end, u32x4* v) {
 #pragma unroll
             for (int u = 0; u < kU; ++u) {
@@ -832,29 +833,29 @@ __global__ __launch_bounds__(1024) void xcd_pass_kernel(XcdPassArgs a) {
             // are the sentinel padding: its word index runs past the bitmap and
             // is clamped to the zero word after it.  The bit offset only uses the
             // low 5 bits, which an event shares with its part-relative index.
-            uint32_t hits = 0;                      // bit 4u+w: word w of chunk u is a hit
-            uint32_t okmask = 0;
+            uint32_t hit[kU][4];                    // word w of chunk u is a hit (0 or 1)
+            uint32_t cnt[kU];
 #pragma unroll
             for (int u = 0; u < kU; ++u) {
-                const uint32_t pos = c + u * 256 + lane * 4;
-                okmask |= (pos >= rs && pos < re ? 0xFu : 0u) << (u * 4);
+                // a chunk lies wholly inside or outside [rs, re): both are multiples of 4
+                const uint32_t ok = c + u * 256 + lane * 4 - rs < re - rs ? 1u : 0u;
 #pragma unroll
                 for (int w = 0; w < 4; ++w) {
                     const uint32_t id = ids[u][w];
                     // byte address of the bitmap word; the padding's lands on the zero word
                     const uint32_t wa = min(__builtin_amdgcn_ubfe(id, 5u, 27u) * 4u - pw4, kZeroWord);
                     const uint32_t word = *reinterpret_cast<const uint32_t*>(lds + wa);
-                    hits |= __builtin_amdgcn_ubfe(word, id, 1u) << (u * 4 + w);
+                    hit[u][w] = __builtin_amdgcn_ubfe(word, id, 1u) & ok;
                 }
+                cnt[u] = hit[u][0] + hit[u][1] + hit[u][2] + hit[u][3];
             }
-            hits &= okmask;
             // per-chunk hit counts, prefix-summed over the wave two chunks at a time
             // (16-bit halves: at most 4 x 64 hits per chunk)
             uint32_t ex[kU], tot[kU];
 #pragma unroll
             for (int u = 0; u < kU; u += 2) {
-                const uint32_t ha = __builtin_popcount((hits >> (4 * u)) & 0xFu);
-                const uint32_t hb = u + 1 < kU ? __builtin_popcount((hits >> (4 * u + 4)) & 0xFu) : 0u;
+                const uint32_t ha = cnt[u];
+                const uint32_t hb = u + 1 < kU ? cnt[u + 1] : 0u;
                 const uint32_t sc = wave_scan_u32(ha | (hb << 16));
                 const uint32_t tt = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(sc), 63));
                 ex[u] = (sc & 0xFFFFu) - ha;
@@ -882,9 +883,8 @@ __global__ __launch_bounds__(1024) void xcd_pass_kernel(XcdPassArgs a) {
                 int at = pre[u];
 #pragma unroll
                 for (int w = 0; w < 4; ++w) {
-                    const uint32_t hb = (hits >> (u * 4 + w)) & 1u;
-                    if (hb) q[at] = ids[u][w];
-                    at += static_cast<int>(hb);
+                    if (hit[u][w]) q[at] = ids[u][w];
+                    at += static_cast<int>(hit[u][w]);
                 }
             }
             // trial boundaries inside this batch: the first hit at or after the
