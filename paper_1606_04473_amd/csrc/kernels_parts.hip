@@ -636,26 +636,22 @@ __global__ __launch_bounds__(1024) void xcd_pass_kernel(XcdPassArgs a) {
     constexpr int kTrialsPW = kTileMax / 8;         // 32 trials per wave
     constexpr uint32_t kBatch = 64 * 4 * kU;        // IDs per batch
     constexpr int kQ = 640;                         // queue entries per wave
-    constexpr int kCache = 10240;                   // nonzero losses of the part kept in LDS
     constexpr int kInf = 0x3FFFFFFF;
     static_assert(kQ >= static_cast<int>(kBatch), "a batch must fit the queue");
-    // LDS: the part image (bitmap, 128-event ranks, superblock bases) and a
-    // zero word after it, the hit queues, and the first kCache nonzero losses
-    constexpr uint32_t kBmBytes = kWords * 8;       // 32 KB bitmap
-    constexpr uint32_t kZeroWord = static_cast<uint32_t>(kImgBytes);   // byte offset of the zero word
-    // one LDS block with the image first, so a bitmap byte offset is its LDS
-    // address
-    constexpr uint32_t kImgWords = kImgBytes / 4 + 4;
-    constexpr uint32_t kQueueOff = kImgWords * 4;                       // 16 per-wave hit queues (event IDs)
+    // LDS, one block: the part's probe words (one per 32 events: the bitmap
+    // bits in the low half, the part-relative rank of the word's first event
+    // among the nonzero ones in the high half) with a zero word after them --
+    // first, so a probe word's byte offset is its LDS address -- then the hit
+    // queues, then as many of the part's first nonzero losses as fit
+    constexpr uint32_t kProbeWords = static_cast<uint32_t>(kPartSize >> 5);
+    constexpr uint32_t kZeroWord = kProbeWords * 8;                     // byte offset of the zero word
+    constexpr uint32_t kQueueOff = kZeroWord + 16;                      // 16 per-wave hit queues (event IDs)
     constexpr uint32_t kCacheOff = kQueueOff + 16 * kQ * 4;             // the loss cache (8-byte aligned)
-    static_assert(kCacheOff % 16 == 0, "aligned loss cache");
+    constexpr int kCache = static_cast<int>((160 * 1024 - kCacheOff) / 8);
+    static_assert(kCacheOff % 16 == 0 && kCache > 0, "LDS layout");
     __shared__ __attribute__((aligned(16))) uint8_t lds[kCacheOff + kCache * 8];
-    uint32_t* img = reinterpret_cast<uint32_t*>(lds);
+    uint64_t* pwords = reinterpret_cast<uint64_t*>(lds);
     double* cache = reinterpret_cast<double*>(lds + kCacheOff);
-    const uint32_t* bm = img;
-    const uint16_t* r16 = reinterpret_cast<const uint16_t*>(reinterpret_cast<const char*>(img) + kBmBytes);
-    const uint32_t* b32 = reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(img) + kBmBytes +
-                                                            kRank16 * 2);
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
     uint32_t* q = reinterpret_cast<uint32_t*>(lds + kQueueOff) + wv * kQ;
@@ -687,16 +683,22 @@ __global__ __launch_bounds__(1024) void xcd_pass_kernel(XcdPassArgs a) {
     const int half = lane & 1;
 
     for (int p = p0; p < P; p += pstep) {
+        // the part image (bitmap, 128-event ranks within superblocks, global
+        // superblock ranks) becomes the probe words
+        const uint8_t* gimg = a.img + static_cast<int64_t>(p) * kImgBytes;
+        const uint32_t* gbm = reinterpret_cast<const uint32_t*>(gimg);
+        const uint16_t* gr16 = reinterpret_cast<const uint16_t*>(gimg + int64_t(kWords) * 8);
+        const uint32_t* gb32 = reinterpret_cast<const uint32_t*>(gimg + int64_t(kWords) * 8 + int64_t(kRank16) * 2);
+        const uint32_t rank0 = gb32[0];             // global rank of the part's first nonzero loss
         __syncthreads();
-        {
-            const u32x4* src = reinterpret_cast<const u32x4*>(a.img + static_cast<int64_t>(p) * kImgBytes);
-            u32x4* dst = reinterpret_cast<u32x4*>(img);
-            for (int k = threadIdx.x; k < static_cast<int>(kImgBytes / 16); k += blockDim.x) dst[k] = src[k];
-            if (threadIdx.x == 0) dst[kImgBytes / 16] = u32x4{0u, 0u, 0u, 0u};
+        for (uint32_t j = threadIdx.x; j < kProbeWords; j += blockDim.x) {
+            uint32_t rank = gb32[j >> 7] - rank0 + gr16[j >> 2];
+            for (uint32_t k = j & ~3u; k < j; ++k) rank += __builtin_popcount(gbm[k]);
+            pwords[j] = (static_cast<uint64_t>(rank) << 32) | gbm[j];
         }
+        if (threadIdx.x == 0) pwords[kProbeWords] = 0;
         __syncthreads();
-        // the part's first nonzero losses, in rank order (global ranks from b32)
-        const uint32_t rank0 = b32[0];
+        // the part's first nonzero losses, in rank order
         for (int k = threadIdx.x; k < kCache; k += blockDim.x) {
             const int64_t g = static_cast<int64_t>(rank0) + k;
             cache[k] = g < a.C ? a.compact[g] : 0.0;
@@ -704,7 +706,7 @@ __global__ __launch_bounds__(1024) void xcd_pass_kernel(XcdPassArgs a) {
         __syncthreads();
         if (srank >= n_tiles) continue;
         const uint32_t pbase = static_cast<uint32_t>(static_cast<int64_t>(p) << kPartShift);
-        const uint32_t pw4 = pbase >> 3;            // byte offset of part p's first bitmap word, were it global
+        const uint32_t pw8 = pbase >> 2;            // byte offset of part p's first probe word, were it global
 
         // this server's m-th tile, clamped to a real tile past the end (never used there)
         auto tile_of = [&](int64_t m) -> int64_t {
@@ -803,19 +805,17 @@ __global__ __launch_bounds__(1024) void xcd_pass_kernel(XcdPassArgs a) {
                     const int jj = j + 2 * r2;
                     v[r2] = 0.0;
                     if (jj < hi) {
-                        // rank of the event among the nonzero ones: superblock base,
-                        // 128-event offset, and the set bits below it in its 128 bits
+                        // rank of the event among the part's nonzero ones: its probe
+                        // word's, plus the set bits below it in the word
                         const uint32_t e = q[jj] - pbase;
-                        const u32x4 w4 = *reinterpret_cast<const u32x4*>(bm + ((e >> 7) << 2));
-                        const uint32_t b = e & 127u, wi = b >> 5;
-                        const uint32_t below = (b & 31u) ? (~0u >> (32u - (b & 31u))) : 0u;
-                        uint32_t cnt = __builtin_popcount(wi == 0 ? (w4.x & below) : w4.x);
-                        cnt += wi >= 1 ? __builtin_popcount(wi == 1 ? (w4.y & below) : w4.y) : 0u;
-                        cnt += wi >= 2 ? __builtin_popcount(wi == 2 ? (w4.z & below) : w4.z) : 0u;
-                        cnt += wi == 3 ? __builtin_popcount(w4.w & below) : 0u;
-                        const uint32_t rk = b32[e >> 12] + r16[e >> 7] + cnt;
-                        const uint32_t lr = rk - rank0;
-                        v[r2] = lr < static_cast<uint32_t>(kCache) ? cache[lr] : a.compact[rk];
+                        const uint64_t pwd = *reinterpret_cast<const uint64_t*>(lds + (e >> 5) * 8u);
+                        const uint32_t below = (1u << (e & 31u)) - 1u;
+                        const uint32_t lr = static_cast<uint32_t>(pwd >> 32) +
+                                            __builtin_popcount(static_cast<uint32_t>(pwd) & below);
+                        // the LDS copy, read at a clamped rank, else the value from L2
+                        // (two loads of one address space each, no pointer select)
+                        v[r2] = cache[min(lr, static_cast<uint32_t>(kCache - 1))];
+                        if (lr >= static_cast<uint32_t>(kCache)) v[r2] = a.compact[rank0 + lr];
                     }
                 }
                 // entries past the trial's last are 0.0, whose sum is exact
@@ -843,7 +843,7 @@ __global__ __launch_bounds__(1024) void xcd_pass_kernel(XcdPassArgs a) {
                 for (int w = 0; w < 4; ++w) {
                     const uint32_t id = ids[u][w];
                     // byte address of the bitmap word; the padding's lands on the zero word
-                    const uint32_t wa = min(__builtin_amdgcn_ubfe(id, 5u, 27u) * 4u - pw4, kZeroWord);
+                    const uint32_t wa = min(__builtin_amdgcn_ubfe(id, 5u, 27u) * 8u - pw8, kZeroWord);
                     const uint32_t word = *reinterpret_cast<const uint32_t*>(lds + wa);
                     hit[u][w] = __builtin_amdgcn_ubfe(word, id, 1u) & ok;
                 }
