@@ -217,7 +217,9 @@ hipError_t take_event(ara::ProfileState& ps, hipEvent_t* ev) {
         ps.free_events.pop_back();
         return hipSuccess;
     }
-    return hipEventCreate(ev);
+    // timing only: no system-scope fence on record, which would write back and
+    // invalidate the caches between the kernels being timed
+    return hipEventCreateWithFlags(ev, hipEventDisableSystemFence);
 }
 
 // Records an event pair around a launch when profiling is on.
@@ -1071,7 +1073,7 @@ ara_status ara_risk_metrics(const double* ylt, int64_t n_trials, const double* p
     }
     ScratchLease scratch(metrics_mu);
     scratch.s = s;
-    HIP_TRY(scratch_acquire(metrics_mu, *sets, static_cast<size_t>(ara::metrics_scratch_bytes(n_probs)), s,
+    HIP_TRY(scratch_acquire(metrics_mu, *sets, static_cast<size_t>(ara::metrics_scratch_bytes(n_probs, n_trials)), s,
                             &scratch.b),
             "metrics scratch");
     if (!dev) HIP_TRY(results.alloc(sizeof(double) * (1 + 2 * n_probs), s), "metrics results");

@@ -371,7 +371,8 @@ struct MetricsOut {
     double* tvar;
     int stride;
 };
-int64_t metrics_scratch_bytes(int n_probs);
+// scratch of launch_metrics for n_probs probabilities over n year losses
+int64_t metrics_scratch_bytes(int n_probs, int64_t n);
 hipError_t launch_metrics(const double* ylt, int64_t n, const int64_t* m_host, int n_probs,
                           void* scratch, MetricsOut out, int n_cu, hipStream_t s);
 

@@ -2,13 +2,18 @@
 //
 // Year losses are >= 0, so their IEEE-754 bit patterns order like their
 // values when read as uint64.  PML_p (the m-th largest) is found by a radix
-// select over those patterns: six passes with 12/12/12/12/12/4-bit digits,
-// each a privatised LDS histogram of the values that match the prefix chosen
-// so far.  The digit of a pass is chosen at the start of the next pass by
-// every workgroup from the previous histogram (the same data, so the same
-// choice), which saves a launch per pass; three histograms rotate so that the
-// one being cleared is never read or written in the same pass.  All requested
-// probabilities advance together.  TVaR_p = (sum of the values above v +
+// select over those patterns with 12/12/12/12/12/4-bit digits, each pass a
+// privatised LDS histogram of the values that match the prefix chosen so
+// far.  The digit of a pass is chosen at the start of the next pass by every
+// workgroup from the previous histogram (the same data, so the same choice),
+// which saves a launch per pass; three histograms rotate so that the one
+// being cleared is never read or written in the same pass.  All requested
+// probabilities advance together.  For ara_risk_metrics the first two passes
+// run over all values; then one pass sums the values above each 24-bit
+// prefix and collects the keys inside it (a handful, unless many losses tie),
+// and a single workgroup chooses the last four digits over those
+// candidates.  Each launch costs about 9 us here, whatever its data, so
+// that cuts nine launches to five.  TVaR_p = (sum of the values above v +
 // (m - c_gt) v) / m, with v = PML_p and c_gt the count above it.  Sums are
 // double-double, reduced in a fixed order (deterministic), and the product
 // (m - c_gt) v is added exactly via fma.
@@ -39,13 +44,24 @@ struct Scratch {
     uint32_t* hist;       // [3][kMaxProbs][kBins]: pass k fills hist[k % 3]
     SelState* st;         // [2][kMaxProbs]: the state pass k uses is st[k & 1] (pass 0: st[0])
     uint32_t* flag;
+    uint32_t* ccount;     // [kMaxProbs] candidates collected per probability
+    uint64_t* cand;       // [n_probs][n] keys inside each probability's 24-bit prefix
 };
 
 constexpr int64_t kHistStride = int64_t(kMaxProbs) * kBins;   // one rotating histogram
 
+constexpr int64_t kCandAlign = 256;
+
+int64_t base_bytes() {
+    const int64_t np = static_cast<int64_t>(kMaxProbs + 1) * kSumBlocks;
+    return np * (2 * sizeof(double) + sizeof(int64_t)) + 3 * kHistStride * sizeof(uint32_t) +
+           2 * kMaxProbs * sizeof(SelState) + 64;
+}
+
 Scratch carve(void* base, int n_probs) {
     (void)n_probs;
     char* p = static_cast<char*>(base);
+    char* const start = p;
     Scratch s;
     const int64_t np = static_cast<int64_t>(kMaxProbs + 1) * kSumBlocks;
     s.part_hi = reinterpret_cast<double*>(p);
@@ -59,6 +75,8 @@ Scratch carve(void* base, int n_probs) {
     s.st = reinterpret_cast<SelState*>(p);
     p += 2 * kMaxProbs * sizeof(SelState);
     s.flag = reinterpret_cast<uint32_t*>(p);
+    s.ccount = reinterpret_cast<uint32_t*>(p + 16);
+    s.cand = reinterpret_cast<uint64_t*>(start + (base_bytes() + kCandAlign - 1) / kCandAlign * kCandAlign);
     return s;
 }
 
@@ -172,6 +190,7 @@ __global__ void select_init_kernel(Scratch s, MArgs ma, int n_probs) {
         s.st[tid].m = ma.m[tid];
     }
     if (tid == 0) *s.flag = 0;
+    if (tid < kMaxProbs) s.ccount[tid] = 0;
     for (int i = tid; i < n_probs * kBins; i += gridDim.x * blockDim.x) s.hist[i] = 0;
 }
 
@@ -292,6 +311,133 @@ __global__ __launch_bounds__(256) void tail_sums_kernel(const double* __restrict
     }
 }
 
+// After the two 12-bit passes: every workgroup chooses the second digit, so
+// each probability has a 24-bit prefix that holds its m-th largest value
+// (block 0 keeps the state in st[0]).  Values above the prefix's range are
+// summed and counted into the tail partials (slot 1 + q); the keys inside it
+// are appended to the probability's candidate list, one atomic per wave.
+__global__ __launch_bounds__(256) void collect_kernel(const double* __restrict__ x, int64_t n, Scratch s,
+                                                      int n_probs) {
+    __shared__ uint64_t pre_s[kMaxProbs], msk_s[kMaxProbs];
+    constexpr int done = 1;                         // the pass whose histogram is read
+    for (int q = 0; q < n_probs; ++q) {
+        SelState st = s.st[(done & 1) * kMaxProbs + q];
+        st = choose_digit(s.hist + (done % 3) * kHistStride + int64_t(q) * kBins, st, done);
+        if (threadIdx.x == 0) {
+            pre_s[q] = st.prefix;
+            msk_s[q] = st.mask;
+            if (blockIdx.x == 0) s.st[((done + 1) & 1) * kMaxProbs + q] = st;
+        }
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+    for (int q = 0; q < n_probs; ++q) {
+        const uint64_t pre = pre_s[q], msk = msk_s[q];
+        const uint64_t top = pre | ~msk;            // the largest key with the prefix
+        uint64_t* cand = s.cand + static_cast<int64_t>(q) * n;
+        double hi = 0.0, lo = 0.0;
+        int64_t cnt = 0;
+        // whole waves step together (the bound is per workgroup), so every
+        // lane takes part in the ballots
+        for (int64_t b = static_cast<int64_t>(blockIdx.x) * blockDim.x; b < n; b += 4 * stride) {
+            double v[4];
+            bool ok[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int64_t i = b + u * stride + threadIdx.x;
+                ok[u] = i < n;
+                v[u] = ok[u] ? x[i] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const uint64_t key = key_of(v[u]);
+                if (ok[u] && key > top) {
+                    dd_add(hi, lo, v[u]);
+                    cnt += 1;
+                }
+                const bool in = ok[u] && (key & msk) == pre;
+                const uint64_t bal = __ballot(in);
+                if (bal) {
+                    const int leader = __builtin_ctzll(bal);
+                    uint32_t at = 0;
+                    if (lane == leader) at = atomicAdd(&s.ccount[q], static_cast<uint32_t>(__popcll(bal)));
+                    at = static_cast<uint32_t>(__shfl(static_cast<int>(at), leader, kWave));
+                    if (in) cand[at + __popcll(bal & ((uint64_t(1) << lane) - 1))] = key;
+                }
+            }
+        }
+        block_reduce_dd(hi, lo, cnt);
+        if (threadIdx.x == 0) {
+            s.part_hi[(1 + q) * kSumBlocks + blockIdx.x] = hi;
+            s.part_lo[(1 + q) * kSumBlocks + blockIdx.x] = lo;
+            s.part_cnt[(1 + q) * kSumBlocks + blockIdx.x] = cnt;
+        }
+        __syncthreads();
+    }
+}
+
+// One workgroup: the mean from the pass-0 partials; per probability, the
+// remaining digits chosen over its candidates (histograms in LDS), then PML
+// and TVaR from the tail partials plus the candidates above the threshold
+// (fixed reduction order).
+__global__ __launch_bounds__(256) void finish_kernel(Scratch s, int n_probs, int n_mean_part, int n_tail_part,
+                                                     int64_t n, MetricsOut out) {
+    __shared__ __attribute__((aligned(16))) uint32_t hist[kBins];
+    const bool bad = *s.flag != 0;
+    const double nan = __longlong_as_double(0x7ff8000000000000LL);
+    {
+        double hi = 0.0, lo = 0.0;
+        int64_t cnt = 0;
+        for (int i = threadIdx.x; i < n_mean_part; i += blockDim.x) dd_merge(hi, lo, s.part_hi[i], s.part_lo[i]);
+        block_reduce_dd(hi, lo, cnt);
+        if (threadIdx.x == 0) *out.mean = bad ? nan : (hi + lo) / static_cast<double>(n);
+        __syncthreads();
+    }
+    for (int q = 0; q < n_probs; ++q) {
+        SelState st = s.st[q];                      // written by the collect pass (st[0])
+        const int64_t c = static_cast<int64_t>(s.ccount[q]);
+        const uint64_t* cand = s.cand + static_cast<int64_t>(q) * n;
+        for (int pass = 2; pass < kPasses; ++pass) {
+            for (int i = threadIdx.x; i < kBins; i += blockDim.x) hist[i] = 0;
+            __syncthreads();
+            const int shift = kShift[pass];
+            const uint64_t dmask = (uint64_t(1) << kBits[pass]) - 1;
+            for (int64_t j = threadIdx.x; j < c; j += blockDim.x) {
+                const uint64_t key = cand[j];
+                if ((key & st.mask) == st.prefix) atomicAdd(&hist[(key >> shift) & dmask], 1u);
+            }
+            __syncthreads();
+            st = choose_digit(hist, st, pass);
+        }
+        const uint64_t vk = st.prefix;              // all 64 bits chosen: the m-th largest key
+        double hi = 0.0, lo = 0.0;
+        int64_t cnt = 0;
+        for (int i = threadIdx.x; i < n_tail_part; i += blockDim.x) {
+            dd_merge(hi, lo, s.part_hi[(1 + q) * kSumBlocks + i], s.part_lo[(1 + q) * kSumBlocks + i]);
+            cnt += s.part_cnt[(1 + q) * kSumBlocks + i];
+        }
+        for (int64_t j = threadIdx.x; j < c; j += blockDim.x) {
+            const uint64_t key = cand[j];
+            if (key > vk) {
+                dd_add(hi, lo, __longlong_as_double(static_cast<long long>(key)));
+                cnt += 1;
+            }
+        }
+        block_reduce_dd(hi, lo, cnt);
+        if (threadIdx.x == 0) {
+            const double v = __longlong_as_double(static_cast<long long>(vk));
+            const double r = static_cast<double>(st.m - cnt);   // copies of v in the top m
+            const double p = r * v;
+            const double pe = fma(r, v, -p);                   // exact product p + pe
+            dd_merge(hi, lo, p, pe);
+            out.pml[q * out.stride] = bad ? nan : v;
+            out.tvar[q * out.stride] = bad ? nan : (hi + lo) / static_cast<double>(st.m);
+        }
+        __syncthreads();
+    }
+}
+
 // one workgroup: the mean from the pass-0 partials, then PML and TVaR per
 // probability from the tail partials (fixed reduction order)
 __global__ __launch_bounds__(256) void final_kernel(Scratch s, int n_probs, int n_mean_part, int n_tail_part,
@@ -361,11 +507,9 @@ __global__ __launch_bounds__(256) void tail_count_kernel(const double* __restric
 
 }  // namespace
 
-int64_t metrics_scratch_bytes(int n_probs) {
-    (void)n_probs;
-    const int64_t np = static_cast<int64_t>(kMaxProbs + 1) * kSumBlocks;
-    return np * (2 * sizeof(double) + sizeof(int64_t)) + 3 * kHistStride * sizeof(uint32_t) +
-           2 * kMaxProbs * sizeof(SelState) + 64;
+int64_t metrics_scratch_bytes(int n_probs, int64_t n) {
+    const int64_t base = (base_bytes() + kCandAlign - 1) / kCandAlign * kCandAlign;
+    return base + static_cast<int64_t>(n_probs) * n * static_cast<int64_t>(sizeof(uint64_t));
 }
 
 hipError_t launch_metrics(const double* ylt, int64_t n, const int64_t* m_host, int n_probs,
@@ -384,21 +528,25 @@ hipError_t launch_metrics(const double* ylt, int64_t n, const int64_t* m_host, i
     if (hblocks > kSumBlocks) hblocks = kSumBlocks;
     if (hblocks < 1) hblocks = 1;
     const size_t lds = sizeof(uint32_t) * kBins * (n_probs > 0 ? n_probs : 1);
-    const int passes = n_probs > 0 ? kPasses : 1;
+    // two 12-bit passes (the first also sums for the mean), then one pass that
+    // sums the tail above each 24-bit prefix and collects the keys inside it,
+    // and one workgroup that finishes the selection over those candidates
+    const int passes = n_probs > 0 ? 2 : 1;
     for (int pass = 0; pass < passes; ++pass) {
         hipLaunchKernelGGL(histogram_kernel, dim3(hblocks), dim3(256), lds, st, ylt, n, s, n_probs, pass,
                            pass == 0 ? 1 : 0);
         if ((err = hipGetLastError()) != hipSuccess) return err;
     }
-    int tblocks = 1;
-    if (n_probs > 0) {
-        tblocks = static_cast<int>((n + 1023) / 1024);
-        if (tblocks > kSumBlocks) tblocks = kSumBlocks;
-        if (tblocks < 1) tblocks = 1;
-        hipLaunchKernelGGL(tail_sums_kernel, dim3(tblocks), dim3(256), 0, st, ylt, n, s, n_probs);
-        if ((err = hipGetLastError()) != hipSuccess) return err;
+    if (n_probs == 0) {
+        hipLaunchKernelGGL(final_kernel, dim3(1), dim3(256), 0, st, s, 0, hblocks, 1, n, out);
+        return hipGetLastError();
     }
-    hipLaunchKernelGGL(final_kernel, dim3(1), dim3(256), 0, st, s, n_probs, hblocks, tblocks, n, out);
+    int tblocks = static_cast<int>((n + 1023) / 1024);
+    if (tblocks > kSumBlocks) tblocks = kSumBlocks;
+    if (tblocks < 1) tblocks = 1;
+    hipLaunchKernelGGL(collect_kernel, dim3(tblocks), dim3(256), 0, st, ylt, n, s, n_probs);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+    hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(256), 0, st, s, n_probs, hblocks, tblocks, n, out);
     return hipGetLastError();
 }
 
@@ -406,7 +554,7 @@ hipError_t launch_metrics(const double* ylt, int64_t n, const int64_t* m_host, i
 
 namespace ara {
 
-int64_t tail_stats_scratch_bytes() { return metrics_scratch_bytes(1); }
+int64_t tail_stats_scratch_bytes() { return metrics_scratch_bytes(1, 0); }
 
 hipError_t launch_tail_stats(const double* ylt, int64_t n, int64_t m, void* scratch, TailStats* out,
                              int n_cu, hipStream_t st) {

@@ -153,6 +153,34 @@ def test_config0_metrics(ara, cfg0):
     assert (dmean, dpml, dtvar) == (mean, pml, tvar)
 
 
+def test_metrics_ties_zeros_and_tiny_inputs(ara):
+    """The selection's candidate pass at its extremes, against the oracle: many
+    losses tied at the threshold, every loss equal (all are candidates), a
+    threshold of zero with half the losses zero, and one to three losses."""
+    import torch
+    rng = np.random.default_rng(61)
+    tied = rng.lognormal(12, 2, 100_000)
+    tied[rng.random(100_000) < 0.3] = 5.0e6
+    half_zero = np.where(rng.random(100_000) < 0.5, 0.0, rng.lognormal(10, 3, 100_000))
+    cases = [
+        (tied, [0.9, 0.99, 0.5]),
+        (np.full(200_000, 3.0), [0.99, 0.5]),
+        (half_zero, [0.25, 0.6, 0.999]),
+        (np.array([7.0]), [0.5]),
+        (np.array([2.0, 9.0]), [0.5, 0.75]),
+        (np.array([4.0, 4.0, 1.0]), [0.2, 0.9]),
+    ]
+    for y, probs in cases:
+        rmean, rpml, rtvar = oracle.risk_metrics(y, probs)
+        for inp in (y, torch.from_numpy(y).cuda()):
+            mean, pml, tvar = ara.risk_metrics(inp, probs)
+            assert abs(mean - rmean) <= REL * abs(rmean), (len(y), probs)
+            for a, b in zip(pml, rpml):
+                assert abs(a - b) <= REL * abs(b), (len(y), probs, pml, rpml)
+            for a, b in zip(tvar, rtvar):
+                assert abs(a - b) <= REL * abs(b), (len(y), probs, tvar, rtvar)
+
+
 def test_config0_checkpoints(ara, cfg0):
     w, tables, ref, S = cfg0
     yet, pool, layer = w.yet, w.pool, w.layers[0]
