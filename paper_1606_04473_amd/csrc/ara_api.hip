@@ -456,6 +456,7 @@ static ara_status create_impl(const int64_t* trial_offsets, int64_t n_trials, co
     if (base) {
         t->elts = const_cast<double*>(elt_losses);
         t->owns_elts = false;
+        t->sparse = base->sparse;
         std::lock_guard<std::mutex> g(const_cast<ara_tables*>(base)->mu);
         t->tuning = base->tuning;
     }
@@ -496,6 +497,13 @@ static ara_status create_impl(const int64_t* trial_offsets, int64_t n_trials, co
     if ((host_flag & 2u) || ends[0] != 0 || ends[1] != n_events)
         return cleanup(fail(ARA_ERR_INVALID_ARG, "trial offsets must start at 0, not decrease, end at n_events"));
     if (host_flag & 4u) return cleanup(fail(ARA_ERR_INVALID_ARG, "ELT losses must be finite and >= 0"));
+    if (!base) {
+        // the pool's nonzero entries, which the per-request fold reads
+        if ((e = ara::build_sparse_pool(t->elts, n_elts, catalogue_size, s, &t->sparse)) != hipSuccess ||
+            (e = hipStreamSynchronize(s)) != hipSuccess)
+            return cleanup(hip_fail(e, "sparse ELT pool"));
+        t->bytes += t->sparse.bytes;
+    }
     if (!(flags & ARA_PLAIN_LAYOUT) && n_trials > 0) {
         e = ara::build_part_layout(t->offsets, t->ids, n_trials, n_events, catalogue_size, t->n_cu, s, &t->parts);
         if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) {
@@ -516,6 +524,7 @@ void ara_destroy_tables(ara_tables* t) {
     if (t->offsets) (void)hipFree(t->offsets);
     if (t->ids) (void)hipFree(t->ids);
     if (t->elts && t->owns_elts) (void)hipFree(t->elts);
+    if (t->owns_elts) ara::free_sparse_pool(&t->sparse);
     free_checkpoints(t->ck);
     scratch_free_all(t->scratch);
     ara::free_part_layout(&t->parts);
@@ -746,7 +755,7 @@ ara_status ara_run_layers(ara_tables* t, const ara_layer* layers, int32_t n_laye
             }
             hipError_t le = hipSuccess;
             for (int i = 0; i < n_layers && le == hipSuccess; ++i) {
-                le = ara::launch_fold_parts(t->elts, t->C, L[i], dL + i, go, t->parts.P, gp, s);
+                le = ara::launch_fold_parts(t->sparse, t->C, L[i], dL + i, go, t->parts.P, gp, s);
                 if (le == hipSuccess) le = ara::launch_xcd_pass(t->parts, t->n_trials, t->C, L[i], gp, gx, t->n_cu, s);
                 if (le == hipSuccess)
                     le = ara::launch_xcd_combine(t->parts, L[i], dL + i, gx, out + L[i].out_offset, nullptr, s);
@@ -846,7 +855,7 @@ ara_status ara_run_layers(ara_tables* t, const ara_layer* layers, int32_t n_laye
         if (!literal) {
             KernelTimer kt(t, s, prof, ARA_KERNEL_FOLD);
             if (use_parts)
-                HIP_TRY(ara::launch_fold_parts(t->elts, t->C, L[i], nullptr, static_cast<double*>(obuf.p), t->parts.P,
+                HIP_TRY(ara::launch_fold_parts(t->sparse, t->C, L[i], nullptr, static_cast<double*>(obuf.p), t->parts.P,
                                                pbuf.p, s),
                         "fold and part images");
             else
@@ -975,7 +984,7 @@ ara_status ara_run_portfolio(ara_tables* t, const ara_program* programs, int32_t
         if (!literal) {
             KernelTimer kt(t, s, prof, ARA_KERNEL_FOLD);
             if (use_parts)
-                HIP_TRY(ara::launch_fold_parts(t->elts, t->C, L[l], nullptr, o_buf, t->parts.P, p_buf, s),
+                HIP_TRY(ara::launch_fold_parts(t->sparse, t->C, L[l], nullptr, o_buf, t->parts.P, p_buf, s),
                         "fold and part images");
             else
                 HIP_TRY(ara::launch_fold(t->elts, t->C, L[l], o_buf, tu, s), "fold");
@@ -1225,7 +1234,7 @@ ara_status ara_event_nets(ara_tables* t, const ara_layer* layer, double* nets, i
     char* base = static_cast<char*>(lease.b->p);
     uint64_t* probe = reinterpret_cast<uint64_t*>(base + o_bytes + p_bytes);
     double* out = dev ? nets : reinterpret_cast<double*>(base + o_bytes + p_bytes + w_bytes);
-    HIP_TRY(ara::launch_fold_parts(t->elts, t->C, L, nullptr, reinterpret_cast<double*>(base), P, base + o_bytes, s),
+    HIP_TRY(ara::launch_fold_parts(t->sparse, t->C, L, nullptr, reinterpret_cast<double*>(base), P, base + o_bytes, s),
             "fold and part images");
     HIP_TRY(ara::launch_event_nets(t->offsets, t->ids, base + o_bytes, P, t->C, probe, L, out, t->n_cu, s),
             "net-loss kernel");

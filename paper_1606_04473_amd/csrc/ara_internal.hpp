@@ -114,6 +114,21 @@ struct CheckpointState {
 // Part-major copy of the YET (see kernels_parts.hip): tiles of T trials,
 // inside a tile part by part, inside a part trial by trial.
 constexpr int kMaxParts = 64;
+
+// The nonzero entries of the ELT pool, row by row in 4096-event chunks (one
+// superblock of the part images each): entries of chunk c of row r are
+// [chunk_off[r * n_chunks + c], chunk_off[r * n_chunks + c + 1]), in event
+// order, with the event's index inside the chunk and its loss.
+struct SparsePool {
+    uint16_t* ev = nullptr;         // event index within its chunk
+    double* val = nullptr;          // loss (> 0)
+    int64_t* chunk_off = nullptr;   // [n_rows * n_chunks + 1]
+    int64_t n_chunks = 0;
+    int64_t nnz = 0;
+    int64_t bytes = 0;
+};
+hipError_t build_sparse_pool(const double* elts, int32_t n_rows, int64_t C, hipStream_t s, SparsePool* out);
+void free_sparse_pool(SparsePool* sp);
 struct PartLayout {
     int P = 0;                      // catalogue parts; 0 = layout absent
     int T = 0;                      // trials per tile
@@ -279,6 +294,7 @@ struct ara_tables {
     uint32_t* ids = nullptr;      // [n_events + kIdPad]
     double* elts = nullptr;       // [n_pool][C]
     bool owns_elts = true;        // false: the pool belongs to another tables object
+    ara::SparsePool sparse;       // the pool's nonzero entries (shared with the pool's owner)
     int64_t bytes = 0;
     ara_tuning tuning{};
     std::mutex mu;                // guards ck and tuning
@@ -348,7 +364,7 @@ int part_count(int64_t C);   // catalogue parts of the part images
 hipError_t launch_part_fold(const double* o, int64_t C, int P, void* scratch, hipStream_t s, bool with_ranks);
 // the fold fused with the part images, then ranks and the compact array; with
 // L_dev the terms are read from device memory (for graph replays), else from L
-hipError_t launch_fold_parts(const double* elts, int64_t C, const LayerArgs& L, const LayerArgs* L_dev, double* o,
+hipError_t launch_fold_parts(const SparsePool& sp, int64_t C, const LayerArgs& L, const LayerArgs* L_dev, double* o,
                              int P, void* scratch, hipStream_t s);
 // the XCD-affine pass writes per-part partial sums; the combine merges them
 hipError_t launch_xcd_pass(const PartLayout& lay, int64_t N, int64_t C, const LayerArgs& L, void* part_scratch,

@@ -196,15 +196,18 @@ __global__ __launch_bounds__(256) void part_image_kernel(const double* __restric
 }
 
 // The fold and the part images in one pass: one workgroup (256 threads) per
-// superblock of 4096 catalogue events.  Each lane folds 16 events (one per
-// 64-event word, so every ELT row is read in coalesced 512-byte rows with 16
-// loads in flight), summing the ELTs of each event in layer order exactly as
-// the fold does, then writes o, the bitmap words, the per-128 ranks and the
-// superblock count.
-__device__ __forceinline__ void fold_image_body(const double* __restrict__ elts, int64_t C, const LayerArgs& L,
+// superblock of 4096 catalogue events.  The superblock's ELT-combined losses
+// y are summed in LDS from the sparse pool: for each ELT of the layer, in
+// layer order, the chunk's nonzero entries (distinct events) each add their
+// per-ELT net loss, with a barrier between ELTs.  An absent loss adds +0.0
+// (retentions are >= 0), which leaves y unchanged, so y is bit-identical to
+// summing every ELT's dense row in layer order.  Then o, the bitmap words,
+// the per-128 ranks and the superblock count are written.
+__device__ __forceinline__ void fold_image_body(const SparsePool& sp, int64_t C, const LayerArgs& L,
                                                 double* __restrict__ o, uint8_t* __restrict__ img,
                                                 uint32_t* __restrict__ sb_count) {
     __shared__ uint32_t wc[64];
+    __shared__ double ys[kSuper];
     const int64_t sb = blockIdx.x;
     const int64_t e0 = sb * kSuper;
     const int64_t part = e0 >> kPartShift;
@@ -213,27 +216,26 @@ __device__ __forceinline__ void fold_image_body(const double* __restrict__ elts,
     uint16_t* r16 = reinterpret_cast<uint16_t*>(img + part * kImgBytes + int64_t(kWords) * 8);
     const int w = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
-    const int64_t eb = e0 + static_cast<int64_t>(w) * 16 * 64 + lane;   // event of word 0 of this wave
-    double y[16];
-#pragma unroll
-    for (int k = 0; k < 16; ++k) y[k] = 0.0;
-    for (int j = 0; j < L.J; ++j) {
-        const double* row = elts + static_cast<int64_t>(L.idx[j]) * C;
-        const double R = L.R[j], Lim = L.Lim[j];
-        double l[16];
-#pragma unroll
-        for (int k = 0; k < 16; ++k) {
-            const int64_t E = eb + k * 64;
-            l[k] = E < C ? __builtin_nontemporal_load(row + E) : 0.0;
+    for (int i = threadIdx.x; i < kSuper; i += blockDim.x) ys[i] = 0.0;
+    __syncthreads();
+    if (sb < sp.n_chunks) {
+        for (int j = 0; j < L.J; ++j) {
+            const int64_t key = static_cast<int64_t>(L.idx[j]) * sp.n_chunks + sb;
+            const int64_t b = sp.chunk_off[key], e = sp.chunk_off[key + 1];
+            const double R = L.R[j], Lim = L.Lim[j];
+            for (int64_t k = b + threadIdx.x; k < e; k += blockDim.x) {
+                const int ev = sp.ev[k];
+                ys[ev] = ys[ev] + apply_terms(sp.val[k], R, Lim);
+            }
+            __syncthreads();
         }
-#pragma unroll
-        for (int k = 0; k < 16; ++k) y[k] = y[k] + apply_terms(l[k], R, Lim);
     }
+    const int64_t eb = e0 + static_cast<int64_t>(w) * 16 * 64 + lane;   // event of word 0 of this wave
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
         const int word = w * 16 + k;
         const int64_t E = eb + k * 64;
-        const double v = apply_terms(y[k], L.occR, L.occL);
+        const double v = apply_terms(ys[word * 64 + lane], L.occR, L.occL);
         if (E < C) o[E] = v;
         const uint64_t bits = __ballot(E < C && v != 0.0);
         if (lane == 0) {
@@ -256,16 +258,91 @@ __device__ __forceinline__ void fold_image_body(const double* __restrict__ elts,
 
 // terms as kernel arguments (eager runs) or read from device memory (graph
 // replays, whose terms may change between replays)
-__global__ __launch_bounds__(256) void fold_image_kernel(const double* __restrict__ elts, int64_t C, LayerArgs L,
+__global__ __launch_bounds__(256) void fold_image_kernel(SparsePool sp, int64_t C, LayerArgs L,
                                                          double* __restrict__ o, uint8_t* __restrict__ img,
                                                          uint32_t* __restrict__ sb_count) {
-    fold_image_body(elts, C, L, o, img, sb_count);
+    fold_image_body(sp, C, L, o, img, sb_count);
 }
-__global__ __launch_bounds__(256) void fold_image_dev_kernel(const double* __restrict__ elts, int64_t C,
+__global__ __launch_bounds__(256) void fold_image_dev_kernel(SparsePool sp, int64_t C,
                                                              const LayerArgs* __restrict__ L, double* __restrict__ o,
                                                              uint8_t* __restrict__ img,
                                                              uint32_t* __restrict__ sb_count) {
-    fold_image_body(elts, C, *L, o, img, sb_count);
+    fold_image_body(sp, C, *L, o, img, sb_count);
+}
+
+// ---------------------------------------------------------------------------
+// the sparse pool (built once, when the tables are created)
+// ---------------------------------------------------------------------------
+
+// nonzero count of every (row, 4096-event chunk); grid (n_chunks, n_rows)
+__global__ __launch_bounds__(256) void sparse_count_kernel(const double* __restrict__ elts, int64_t C,
+                                                           int64_t n_chunks, int64_t* __restrict__ counts) {
+    __shared__ uint32_t wsum[4];
+    const int64_t row = blockIdx.y, chunk = blockIdx.x;
+    const double* r = elts + row * C;
+    const int64_t e0 = chunk * kSuper;
+    uint32_t cnt = 0;
+    for (int k = 0; k < kSuper / 256; ++k) {
+        const int64_t E = e0 + k * 256 + threadIdx.x;
+        cnt += (E < C && __builtin_nontemporal_load(r + E) != 0.0) ? 1u : 0u;
+    }
+    for (int off = 32; off >= 1; off >>= 1) cnt += __shfl_xor(cnt, off, kWave);
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) counts[row * n_chunks + chunk] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+}
+
+// exclusive scan of n counts in place (one workgroup), with the total at [n]
+__global__ __launch_bounds__(1024) void sparse_scan_kernel(int64_t* __restrict__ v, int64_t n) {
+    __shared__ int64_t sh[1024];
+    int64_t carry = 0;
+    for (int64_t c0 = 0; c0 < n; c0 += 1024) {
+        const int64_t i = c0 + threadIdx.x;
+        const int64_t x = i < n ? v[i] : 0;
+        sh[threadIdx.x] = x;
+        __syncthreads();
+        for (int off = 1; off < 1024; off <<= 1) {
+            const int64_t add = threadIdx.x >= off ? sh[threadIdx.x - off] : 0;
+            __syncthreads();
+            sh[threadIdx.x] += add;
+            __syncthreads();
+        }
+        if (i < n) v[i] = carry + sh[threadIdx.x] - x;
+        const int64_t total = sh[1023];
+        __syncthreads();
+        carry += total;
+    }
+    if (threadIdx.x == 0) v[n] = carry;
+}
+
+// each chunk's nonzero entries, in event order, at its offset; grid (n_chunks, n_rows)
+__global__ __launch_bounds__(256) void sparse_fill_kernel(const double* __restrict__ elts, int64_t C,
+                                                          int64_t n_chunks, const int64_t* __restrict__ off,
+                                                          uint16_t* __restrict__ ev, double* __restrict__ val) {
+    __shared__ uint32_t wsum[4];
+    const int64_t row = blockIdx.y, chunk = blockIdx.x;
+    const double* r = elts + row * C;
+    const int64_t e0 = chunk * kSuper;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int64_t at = off[row * n_chunks + chunk];
+    for (int k = 0; k < kSuper / 256; ++k) {
+        const int local = k * 256 + static_cast<int>(threadIdx.x);
+        const int64_t E = e0 + local;
+        const double x = E < C ? r[E] : 0.0;
+        const uint64_t bal = __ballot(x != 0.0);
+        if (lane == 0) wsum[w] = __popcll(bal);
+        __syncthreads();
+        uint32_t before = 0;
+        for (int i = 0; i < w; ++i) before += wsum[i];
+        const uint32_t total = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+        if (x != 0.0) {
+            const int64_t pos = at + before + __popcll(bal & lanemask_lt());
+            ev[pos] = static_cast<uint16_t>(local);
+            val[pos] = x;
+        }
+        at += total;
+        __syncthreads();
+    }
 }
 
 // exclusive scan of the superblock counts (one workgroup) into each part's
@@ -987,6 +1064,42 @@ hipError_t launch_batched_pass_lpt(int lpt, int grid, const BatchedPassArgs& a, 
 }  // namespace
 
 int64_t part_image_bytes(int P) { return static_cast<int64_t>(P) * kImgBytes; }
+
+hipError_t build_sparse_pool(const double* elts, int32_t n_rows, int64_t C, hipStream_t s, SparsePool* out) {
+    *out = SparsePool{};
+    if (n_rows > 65535) return hipErrorInvalidValue;            // rows are the grid's second dimension
+    const int64_t n_chunks = (C + kSuper - 1) / kSuper;
+    const int64_t n = static_cast<int64_t>(n_rows) * n_chunks;
+    out->n_chunks = n_chunks;
+    hipError_t e;
+    if ((e = hipMalloc(&out->chunk_off, sizeof(int64_t) * (n + 1))) != hipSuccess) return e;
+    out->bytes = static_cast<int64_t>(sizeof(int64_t)) * (n + 1);
+    if (n == 0) return hipMemsetAsync(out->chunk_off, 0, sizeof(int64_t), s);
+    const dim3 grid(static_cast<uint32_t>(n_chunks), static_cast<uint32_t>(n_rows));
+    hipLaunchKernelGGL(sparse_count_kernel, grid, dim3(256), 0, s, elts, C, n_chunks, out->chunk_off);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(sparse_scan_kernel, dim3(1), dim3(1024), 0, s, out->chunk_off, n);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    int64_t nnz = 0;
+    if ((e = hipMemcpyAsync(&nnz, out->chunk_off + n, sizeof(int64_t), hipMemcpyDeviceToHost, s)) != hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess)
+        return e;
+    out->nnz = nnz;
+    const int64_t cap = nnz > 0 ? nnz : 1;
+    if ((e = hipMalloc(&out->ev, sizeof(uint16_t) * cap)) != hipSuccess) return e;
+    if ((e = hipMalloc(&out->val, sizeof(double) * cap)) != hipSuccess) return e;
+    out->bytes += static_cast<int64_t>(sizeof(uint16_t) + sizeof(double)) * cap;
+    hipLaunchKernelGGL(sparse_fill_kernel, grid, dim3(256), 0, s, elts, C, n_chunks, out->chunk_off, out->ev,
+                       out->val);
+    return hipGetLastError();
+}
+
+void free_sparse_pool(SparsePool* sp) {
+    if (sp->ev) (void)hipFree(sp->ev);
+    if (sp->val) (void)hipFree(sp->val);
+    if (sp->chunk_off) (void)hipFree(sp->chunk_off);
+    *sp = SparsePool{};
+}
 int64_t part_size() { return kPartSize; }
 int part_tile_trials() { return kTileMax; }
 
@@ -1383,16 +1496,16 @@ hipError_t launch_part_fold(const double* o, int64_t C, int P, void* scratch, hi
     return hipGetLastError();
 }
 
-hipError_t launch_fold_parts(const double* elts, int64_t C, const LayerArgs& L, const LayerArgs* L_dev, double* o,
+hipError_t launch_fold_parts(const SparsePool& sp, int64_t C, const LayerArgs& L, const LayerArgs* L_dev, double* o,
                              int P, void* scratch, hipStream_t s) {
     PartScratch ps = carve_parts(scratch, P);
     const int64_t n_sb = static_cast<int64_t>(P) * kBase32;
     hipError_t e;
     if (L_dev)
-        hipLaunchKernelGGL(fold_image_dev_kernel, dim3(static_cast<uint32_t>(n_sb)), dim3(256), 0, s, elts, C, L_dev,
+        hipLaunchKernelGGL(fold_image_dev_kernel, dim3(static_cast<uint32_t>(n_sb)), dim3(256), 0, s, sp, C, L_dev,
                            o, ps.img, ps.sb_count);
     else
-        hipLaunchKernelGGL(fold_image_kernel, dim3(static_cast<uint32_t>(n_sb)), dim3(256), 0, s, elts, C, L, o,
+        hipLaunchKernelGGL(fold_image_kernel, dim3(static_cast<uint32_t>(n_sb)), dim3(256), 0, s, sp, C, L, o,
                            ps.img, ps.sb_count);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(superblock_scan_kernel, dim3(1), dim3(1024), 0, s, ps.sb_count, n_sb, ps.img, int64_t(0));
