@@ -1216,7 +1216,8 @@ PartScratch carve_parts(void* scratch, int P) {
 namespace {
 
 constexpr int kProbeShift = 5;                  // 32 catalogue events per probe word
-constexpr int kNetsThreads = 256;
+constexpr int kNetsThreads = 1024;              // one workgroup per CU: its waves share the coarse map
+constexpr int kCoarseBytes = 88 * 1024;         // LDS left for the coarse map beside the waves' rows
 
 // value moved across lanes by a DPP control; lanes without a source get 0
 template <int kCtrl, int kRowMask>
@@ -1302,6 +1303,30 @@ __global__ __launch_bounds__(256) void probe_table_kernel(const uint8_t* __restr
     probe[i] = (static_cast<uint64_t>(rank) << 32) | bm32[j];
 }
 
+// coarse map: bit i is set when any of events [i << cshift, (i + 1) << cshift)
+// has a nonzero loss; one thread per 32-bit word, from the probe words' bits
+__global__ __launch_bounds__(256) void coarse_map_kernel(const uint64_t* __restrict__ probe, int64_t n_words,
+                                                         int cshift, int64_t n_cw, uint32_t* __restrict__ coarse) {
+    const int64_t cw = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (cw >= n_cw) return;
+    uint32_t out = 0;
+    for (int k = 0; k < 32; ++k) {
+        const int64_t s0 = (cw * 32 + k) << cshift;                   // first event of the group
+        uint32_t any = 0;
+        if (cshift >= kProbeShift) {
+            const int64_t w0 = s0 >> kProbeShift, nw = int64_t(1) << (cshift - kProbeShift);
+            for (int64_t w = w0; w < w0 + nw && w < n_words; ++w) any |= static_cast<uint32_t>(probe[w]);
+        } else if ((s0 >> kProbeShift) < n_words) {
+            const uint32_t bits = static_cast<uint32_t>(probe[s0 >> kProbeShift]);
+            const uint32_t width = 1u << cshift;
+            const uint32_t mask = (width >= 32u ? ~0u : ((1u << width) - 1u)) << (s0 & 31);
+            any = bits & mask;
+        }
+        out |= (any != 0u ? 1u : 0u) << k;
+    }
+    coarse[cw] = out;
+}
+
 // The layer's trials are split into one contiguous run per wave (event
 // shares rounded to trial starts), and each wave streams its run's IDs in
 // steps of 64 kE positions in time order, kE consecutive positions per lane
@@ -1320,13 +1345,18 @@ template <int kE>
 __global__ __launch_bounds__(kNetsThreads) void event_nets_kernel(const int64_t* __restrict__ offsets,
                                                                   const uint32_t* __restrict__ ids,
                                                                   const uint64_t* __restrict__ probe,
-                                                                  const double* __restrict__ compact, LayerArgs L,
-                                                                  double* __restrict__ nets) {
+                                                                  const uint32_t* __restrict__ gcoarse, int cshift,
+                                                                  int64_t n_cw, const double* __restrict__ compact,
+                                                                  LayerArgs L, double* __restrict__ nets) {
     static_assert(kE == 4 || kE == 8, "four or eight events per lane");
     constexpr int kW = 64 * kE;                                        // positions per step
     static_assert(kW <= kIdPad, "a step may read up to kW - 1 IDs past the table's end");
     __shared__ double stage[kNetsThreads / 64][kW];
     __shared__ __attribute__((aligned(8))) uint8_t flag_rows[kNetsThreads / 64][kW];
+    extern __shared__ uint32_t coarse[];                               // [n_cw]
+    // the coarse map, before any wave can leave (the only workgroup barrier)
+    for (int64_t i = threadIdx.x; i < n_cw; i += blockDim.x) coarse[i] = gcoarse[i];
+    __syncthreads();
     const int lane = threadIdx.x & 63;
     double* st = stage[threadIdx.x >> 6];
     uint8_t* fl = flag_rows[threadIdx.x >> 6];
@@ -1384,9 +1414,14 @@ __global__ __launch_bounds__(kNetsThreads) void event_nets_kernel(const int64_t*
             ok[q] = pos + q >= P0 && pos + q < P1;
             E[q] = ok[q] ? cur[q >> 2][q & 3] : 0u;
         }
+        // the L2 probe only where the coarse map says the event's group has a loss
         uint64_t pw[kE];
 #pragma unroll
-        for (int q = 0; q < kE; ++q) pw[q] = probe[E[q] >> kProbeShift];
+        for (int q = 0; q < kE; ++q) {
+            const uint32_t cb = E[q] >> cshift;
+            pw[q] = 0;
+            if (ok[q] && ((coarse[cb >> 5] >> (cb & 31u)) & 1u)) pw[q] = probe[E[q] >> kProbeShift];
+        }
         double oq[kE];
 #pragma unroll
         for (int q = 0; q < kE; ++q) {
@@ -1452,32 +1487,38 @@ __global__ __launch_bounds__(kNetsThreads) void event_nets_kernel(const int64_t*
 int part_count(int64_t C) { return static_cast<int>((C + kPartSize - 1) / kPartSize); }
 
 int64_t probe_table_bytes(int64_t C) {
-    return static_cast<int64_t>(sizeof(uint64_t)) * ((C + (1 << kProbeShift) - 1) >> kProbeShift);
+    // probe words, then the coarse map (at most kCoarseBytes)
+    return static_cast<int64_t>(sizeof(uint64_t)) * ((C + (1 << kProbeShift) - 1) >> kProbeShift) + 256 +
+           kCoarseBytes;
 }
 
 hipError_t launch_event_nets(const int64_t* offsets, const uint32_t* ids, const void* part_scratch, int P,
                              int64_t C, uint64_t* probe, const LayerArgs& L, double* nets, int n_cu, hipStream_t s) {
     if (L.trial_count <= 0) return hipSuccess;
     PartScratch ps = carve_parts(const_cast<void*>(part_scratch), P);
-    const int64_t n_words = probe_table_bytes(C) / static_cast<int64_t>(sizeof(uint64_t));
+    const int64_t n_words = (C + (1 << kProbeShift) - 1) >> kProbeShift;
     hipLaunchKernelGGL(probe_table_kernel, dim3(static_cast<uint32_t>((n_words + 255) / 256)), dim3(256), 0, s,
                        ps.img, n_words, probe);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    // as many workgroups as the device holds at once
-    static const int per_cu = [] {
-        int v = 0;
-        return hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, event_nets_kernel<8>, kNetsThreads, 0) ==
-                           hipSuccess &&
-                       v > 0
-                   ? v
-                   : 4;
-    }();
+    // the finest coarse map that fits: 2^cshift events per bit
+    int cshift = 0;
+    while ((((C + (int64_t(1) << cshift) - 1) >> cshift) + 31) / 32 * 4 > kCoarseBytes) ++cshift;
+    const int64_t n_cw = (((C + (int64_t(1) << cshift) - 1) >> cshift) + 31) / 32;
+    uint32_t* coarse = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(probe) + sizeof(uint64_t) * n_words + 256);
+    hipLaunchKernelGGL(coarse_map_kernel, dim3(static_cast<uint32_t>((n_cw + 255) / 256)), dim3(256), 0, s, probe,
+                       n_words, cshift, n_cw, coarse);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const size_t lds = sizeof(uint32_t) * static_cast<size_t>(n_cw);
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, event_nets_kernel<8>, kNetsThreads, lds) != hipSuccess ||
+        per_cu < 1)
+        per_cu = 1;
     int64_t blocks = (L.trial_count + kNetsThreads / 64 - 1) / (kNetsThreads / 64);
     const int64_t cap = static_cast<int64_t>(n_cu) * per_cu;
     if (blocks > cap) blocks = cap;
-    hipLaunchKernelGGL(event_nets_kernel<8>, dim3(static_cast<uint32_t>(blocks)), dim3(kNetsThreads), 0, s, offsets,
-                       ids, probe, ps.compact, L, nets);
+    hipLaunchKernelGGL(event_nets_kernel<8>, dim3(static_cast<uint32_t>(blocks)), dim3(kNetsThreads), lds, s, offsets,
+                       ids, probe, coarse, cshift, n_cw, ps.compact, L, nets);
     return hipGetLastError();
 }
 
