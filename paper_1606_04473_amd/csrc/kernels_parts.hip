@@ -1217,7 +1217,7 @@ namespace {
 
 constexpr int kProbeShift = 5;                  // 32 catalogue events per probe word
 constexpr int kNetsThreads = 1024;              // one workgroup per CU: its waves share the coarse map
-constexpr int kCoarseBytes = 88 * 1024;         // LDS left for the coarse map beside the waves' rows
+constexpr int kCoarseBytes = 124 * 1024;        // LDS left for the coarse map beside the waves' rows
 
 // value moved across lanes by a DPP control; lanes without a source get 0
 template <int kCtrl, int kRowMask>
@@ -1332,8 +1332,11 @@ __global__ __launch_bounds__(256) void coarse_map_kernel(const uint64_t* __restr
 // steps of 64 kE positions in time order, kE consecutive positions per lane
 // (16-byte loads, the next step's issued before this step's work).  o(E) is
 // 0 unless E's bit is set in its probe word, else compact[rank + bits below]
-// -- one 8-byte probe per event and one more load per nonzero loss, both from
-// tables that stay in L2.  Trial starts (held one per lane and marked in a
+// -- an 8-byte probe and one more load per nonzero loss, both from tables
+// that stay in L2.  L2 serves these random requests at a bounded rate, so the
+// workgroup's 16 waves first test a coarse map in LDS (one bit per 2^cshift
+// events, set when any of them has a loss) and probe L2 only for events
+// whose bit is set.  Trial starts (held one per lane and marked in a
 // per-wave LDS flag row) reset a segmented double-double scan: each event's
 // running total S_d (the lane's own prefix, the scan of the lanes before it,
 // the carry of earlier steps) is rounded once; A_d = clamp(S_d; AggR, AggL)
@@ -1511,13 +1514,13 @@ hipError_t launch_event_nets(const int64_t* offsets, const uint32_t* ids, const 
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const size_t lds = sizeof(uint32_t) * static_cast<size_t>(n_cw);
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, event_nets_kernel<8>, kNetsThreads, lds) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, event_nets_kernel<4>, kNetsThreads, lds) != hipSuccess ||
         per_cu < 1)
         per_cu = 1;
     int64_t blocks = (L.trial_count + kNetsThreads / 64 - 1) / (kNetsThreads / 64);
     const int64_t cap = static_cast<int64_t>(n_cu) * per_cu;
     if (blocks > cap) blocks = cap;
-    hipLaunchKernelGGL(event_nets_kernel<8>, dim3(static_cast<uint32_t>(blocks)), dim3(kNetsThreads), lds, s, offsets,
+    hipLaunchKernelGGL(event_nets_kernel<4>, dim3(static_cast<uint32_t>(blocks)), dim3(kNetsThreads), lds, s, offsets,
                        ids, probe, coarse, cshift, n_cw, ps.compact, L, nets);
     return hipGetLastError();
 }
