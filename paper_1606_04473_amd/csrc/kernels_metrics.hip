@@ -27,6 +27,7 @@ constexpr int kSumBlocks = 512;
 constexpr int kBins = 4096;
 constexpr int kPasses = 6;
 constexpr int kMaxProbs = 4;   // 4 x 16 KB histograms fit the 64 KB dynamic-LDS default
+constexpr int kDirect = 256;   // candidates ranked directly (all pairs) instead of by radix digits
 __constant__ int kShift[kPasses] = {52, 40, 28, 16, 4, 0};
 __constant__ int kBits[kPasses] = {12, 12, 12, 12, 12, 4};
 
@@ -384,6 +385,8 @@ __global__ __launch_bounds__(256) void collect_kernel(const double* __restrict__
 __global__ __launch_bounds__(256) void finish_kernel(Scratch s, int n_probs, int n_mean_part, int n_tail_part,
                                                      int64_t n, MetricsOut out) {
     __shared__ __attribute__((aligned(16))) uint32_t hist[kBins];
+    __shared__ uint64_t keys[kDirect];
+    __shared__ uint64_t found;
     const bool bad = *s.flag != 0;
     const double nan = __longlong_as_double(0x7ff8000000000000LL);
     {
@@ -398,7 +401,26 @@ __global__ __launch_bounds__(256) void finish_kernel(Scratch s, int n_probs, int
         SelState st = s.st[q];                      // written by the collect pass (st[0])
         const int64_t c = static_cast<int64_t>(s.ccount[q]);
         const uint64_t* cand = s.cand + static_cast<int64_t>(q) * n;
-        for (int pass = 2; pass < kPasses; ++pass) {
+        if (c <= kDirect) {
+            // few candidates: the k-th largest is the key with fewer than k
+            // keys above it and at least k at or above it
+            for (int64_t j = threadIdx.x; j < c; j += blockDim.x) keys[j] = cand[j];
+            __syncthreads();
+            for (int64_t j = threadIdx.x; j < c; j += blockDim.x) {
+                const uint64_t kj = keys[j];
+                int64_t gt = 0, ge = 0;
+                for (int64_t i = 0; i < c; ++i) {
+                    gt += keys[i] > kj;
+                    ge += keys[i] >= kj;
+                }
+                if (gt < st.k && st.k <= ge) found = kj;      // every such thread writes the same key
+            }
+            __syncthreads();
+            st.prefix = found;
+            st.mask = ~uint64_t(0);
+            __syncthreads();
+        }
+        for (int pass = 2; pass < kPasses && c > kDirect; ++pass) {
             for (int i = threadIdx.x; i < kBins; i += blockDim.x) hist[i] = 0;
             __syncthreads();
             const int shift = kShift[pass];
