@@ -11,8 +11,9 @@
 // probabilities advance together.  For ara_risk_metrics the first two passes
 // run over all values; then one pass sums the values above each 24-bit
 // prefix and collects the keys inside it (a handful, unless many losses tie),
-// and a single workgroup chooses the last four digits over those
-// candidates.  Each launch costs about 9 us here, whatever its data, so
+// and a single workgroup finishes the selection over those candidates: up to
+// 256 of them are ranked directly against each other, more go through the
+// last four digit passes.  Each launch costs about 9 us here, whatever its data, so
 // that cuts nine launches to five.  TVaR_p = (sum of the values above v +
 // (m - c_gt) v) / m, with v = PML_p and c_gt the count above it.  Sums are
 // double-double, reduced in a fixed order (deterministic), and the product
@@ -262,53 +263,6 @@ __global__ __launch_bounds__(256) void histogram_kernel(const double* __restrict
     for (int k = threadIdx.x; k < n_probs * kBins; k += blockDim.x) {
         const uint32_t c = lds_hist[k];
         if (c) atomicAdd(&h[k], c);
-    }
-}
-
-// After the last pass: every workgroup chooses the last digit (block 0 keeps
-// the final state in st[0]), then sums and counts, for each probability, the
-// values strictly above its threshold (slot 1 + q).
-__global__ __launch_bounds__(256) void tail_sums_kernel(const double* __restrict__ x, int64_t n, Scratch s,
-                                                        int n_probs) {
-    __shared__ uint64_t thr_s[kMaxProbs];
-    constexpr int last = kPasses - 1;
-    for (int q = 0; q < n_probs; ++q) {
-        SelState st = s.st[(last & 1) * kMaxProbs + q];
-        st = choose_digit(s.hist + (last % 3) * kHistStride + int64_t(q) * kBins, st, last);
-        if (threadIdx.x == 0) {
-            thr_s[q] = st.prefix;
-            if (blockIdx.x == 0) s.st[((last + 1) & 1) * kMaxProbs + q] = st;
-        }
-    }
-    __syncthreads();
-    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
-    const int64_t tid = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    for (int q = 0; q < n_probs; ++q) {
-        double hi = 0.0, lo = 0.0;
-        int64_t cnt = 0;
-        const uint64_t thr = thr_s[q];
-        auto take = [&](double v) {
-            if (key_of(v) > thr) {
-                dd_add(hi, lo, v);
-                cnt += 1;
-            }
-        };
-        int64_t i = tid;
-        for (; i + 3 * stride < n; i += 4 * stride) {
-            const double v0 = x[i], v1 = x[i + stride], v2 = x[i + 2 * stride], v3 = x[i + 3 * stride];
-            take(v0);
-            take(v1);
-            take(v2);
-            take(v3);
-        }
-        for (; i < n; i += stride) take(x[i]);
-        block_reduce_dd(hi, lo, cnt);
-        if (threadIdx.x == 0) {
-            s.part_hi[(1 + q) * kSumBlocks + blockIdx.x] = hi;
-            s.part_lo[(1 + q) * kSumBlocks + blockIdx.x] = lo;
-            s.part_cnt[(1 + q) * kSumBlocks + blockIdx.x] = cnt;
-        }
-        __syncthreads();
     }
 }
 
