@@ -26,7 +26,13 @@
  *   - Calls with host outputs return after the results are in host memory.
  *     Calls with device outputs are asynchronous on `stream`.
  *   - Tables are read-only after creation: several threads may run layers on
- *     the same tables concurrently, on different streams.  Per-call scratch
+ *     the same tables concurrently, on different streams.  The scratch of
+ *     ara_run_layers (per-layer sequences), ara_run_portfolio, ara_event_nets
+ *     and ara_risk_metrics is device memory kept between calls (by the
+ *     tables, or by the library per device for the metrics): a call reuses a
+ *     buffer last used on its own stream at once, one last used on another
+ *     stream once that stream has passed its last use, and otherwise
+ *     allocates a new one.  Other scratch, and staging for host arguments,
  *     comes from the device's stream-ordered memory pool.
  */
 #ifndef ARA_H

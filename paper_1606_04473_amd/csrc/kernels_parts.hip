@@ -712,17 +712,17 @@ __global__ __launch_bounds__(1024) void xcd_pass_kernel(XcdPassArgs a) {
     constexpr int kU = 2;                           // 16-byte loads per lane per batch
     constexpr int kTrialsPW = kTileMax / 8;         // 32 trials per wave
     constexpr uint32_t kBatch = 64 * 4 * kU;        // IDs per batch
-    constexpr int kQ = 640;                         // queue entries per wave
+    constexpr int kQ = 512;                         // queue entries per wave (one batch)
     constexpr int kInf = 0x3FFFFFFF;
     static_assert(kQ >= static_cast<int>(kBatch), "a batch must fit the queue");
     // LDS, one block: the part's probe words (one per 32 events: the bitmap
     // bits in the low half, the part-relative rank of the word's first event
-    // among the nonzero ones in the high half) with a zero word after them --
-    // first, so a probe word's byte offset is its LDS address -- then the hit
-    // queues, then as many of the part's first nonzero losses as fit
+    // among the nonzero ones in the high half) -- first, so a probe word's
+    // byte offset is its LDS address -- then the hit queues, then as many of
+    // the part's first nonzero losses as fit
     constexpr uint32_t kProbeWords = static_cast<uint32_t>(kPartSize >> 5);
-    constexpr uint32_t kZeroWord = kProbeWords * 8;                     // byte offset of the zero word
-    constexpr uint32_t kQueueOff = kZeroWord + 16;                      // 16 per-wave hit queues (event IDs)
+    constexpr uint32_t kProbeMask = (kProbeWords - 1) * 8;              // byte offset bits of a probe word
+    constexpr uint32_t kQueueOff = kProbeWords * 8;                     // 16 per-wave hit queues (event IDs)
     constexpr uint32_t kCacheOff = kQueueOff + 16 * kQ * 4;             // the loss cache (8-byte aligned)
     constexpr int kCache = static_cast<int>((160 * 1024 - kCacheOff) / 8);
     static_assert(kCacheOff % 16 == 0 && kCache > 0, "LDS layout");
@@ -773,7 +773,6 @@ __global__ __launch_bounds__(1024) void xcd_pass_kernel(XcdPassArgs a) {
             for (uint32_t k = j & ~3u; k < j; ++k) rank += __builtin_popcount(gbm[k]);
             pwords[j] = (static_cast<uint64_t>(rank) << 32) | gbm[j];
         }
-        if (threadIdx.x == 0) pwords[kProbeWords] = 0;
         __syncthreads();
         // the part's first nonzero losses, in rank order
         for (int k = threadIdx.x; k < kCache; k += blockDim.x) {
@@ -782,8 +781,6 @@ __global__ __launch_bounds__(1024) void xcd_pass_kernel(XcdPassArgs a) {
         }
         __syncthreads();
         if (srank >= n_tiles) continue;
-        const uint32_t pbase = static_cast<uint32_t>(static_cast<int64_t>(p) << kPartShift);
-        const uint32_t pw8 = pbase >> 2;            // byte offset of part p's first probe word, were it global
 
         // this server's m-th tile, clamped to a real tile past the end (never used there)
         auto tile_of = [&](int64_t m) -> int64_t {
@@ -883,8 +880,11 @@ __global__ __launch_bounds__(1024) void xcd_pass_kernel(XcdPassArgs a) {
                     v[r2] = 0.0;
                     if (jj < hi) {
                         // rank of the event among the part's nonzero ones: its probe
-                        // word's, plus the set bits below it in the word
-                        const uint32_t e = q[jj] - pbase;
+                        // word's, plus the set bits below it in the word.  Parts are
+                        // aligned, so the low bits of an ID are its part-relative
+                        // index; a queued padding ID reads as the part's last event.
+                        const uint32_t id = q[jj];
+                        const uint32_t e = id & static_cast<uint32_t>(kPartSize - 1);
                         const uint64_t pwd = *reinterpret_cast<const uint64_t*>(lds + (e >> 5) * 8u);
                         const uint32_t below = (1u << (e & 31u)) - 1u;
                         const uint32_t lr = static_cast<uint32_t>(pwd >> 32) +
@@ -893,6 +893,7 @@ __global__ __launch_bounds__(1024) void xcd_pass_kernel(XcdPassArgs a) {
                         // (two loads of one address space each, no pointer select)
                         v[r2] = cache[min(lr, static_cast<uint32_t>(kCache - 1))];
                         if (lr >= static_cast<uint32_t>(kCache)) v[r2] = a.compact[rank0 + lr];
+                        if (id == kSentinel) v[r2] = 0.0;   // segment padding adds nothing
                     }
                 }
                 // entries past the trial's last are 0.0, whose sum is exact
@@ -906,10 +907,11 @@ __global__ __launch_bounds__(1024) void xcd_pass_kernel(XcdPassArgs a) {
         // test a batch against the bitmap and append its hits to the queue in
         // position order (chunk u, lane, word); note where each trial's hits start
         auto process = [&](const u32x4* ids) {
-            // every ID in [rs, re) belongs to part p, so the only other values
-            // are the sentinel padding: its word index runs past the bitmap and
-            // is clamped to the zero word after it.  The bit offset only uses the
-            // low 5 bits, which an event shares with its part-relative index.
+            // every ID in [rs, re) belongs to part p, and parts are aligned to
+            // their size, so an ID's bits 5..17 are its probe word and its low 5
+            // bits the bit in it.  The only other IDs are the segment padding,
+            // which reads the part's last event: if that event is nonzero the
+            // padding is queued like a hit, and the drain gives it 0.0.
             uint32_t hit[kU][4];                    // word w of chunk u is a hit (0 or 1)
             uint32_t cnt[kU];
 #pragma unroll
@@ -919,8 +921,7 @@ __global__ __launch_bounds__(1024) void xcd_pass_kernel(XcdPassArgs a) {
 #pragma unroll
                 for (int w = 0; w < 4; ++w) {
                     const uint32_t id = ids[u][w];
-                    // byte address of the bitmap word; the padding's lands on the zero word
-                    const uint32_t wa = min(__builtin_amdgcn_ubfe(id, 5u, 27u) * 8u - pw8, kZeroWord);
+                    const uint32_t wa = (id >> 2) & kProbeMask;   // byte address of its probe word
                     const uint32_t word = *reinterpret_cast<const uint32_t*>(lds + wa);
                     hit[u][w] = __builtin_amdgcn_ubfe(word, id, 1u) & ok;
                 }

@@ -636,6 +636,43 @@ def test_more_parts_than_xcds(ara):
     tables.close()
 
 
+def test_segment_padding_with_nonzero_last_events(ara):
+    """Segments of the partitioned layout are padded to a multiple of 4 IDs,
+    and the XCD-affine pass reads a padding ID as the last event of its part.
+    Here every part's last event has a nonzero occurrence loss and the trials
+    have ragged lengths (most segments carry padding), some of them holding
+    those last events once or twice: the padding must add nothing and the
+    real occurrences must count.  Both pass variants against the oracle."""
+    C = 3 * 2**18
+    last = np.array([2**18 - 1, 2 * 2**18 - 1, C - 1], dtype=np.int64)
+    pool = make_elt_pool(3, C, 30_000, seed=71)
+    pool.losses[:, last] = np.array([8.0e6, 9.5e6, 1.1e7])
+    rng = np.random.default_rng(72)
+    trials = []
+    for t in range(700):
+        ids = rng.integers(0, C, size=int(rng.integers(0, 41))).tolist()
+        for _ in range(int(rng.integers(0, 3))):
+            ids.insert(int(rng.integers(0, len(ids) + 1)), int(rng.choice(last)))
+        trials.append(ids)
+    yet = make_tiny_yet(trials, C)
+    layer = Layer(np.array([2, 0, 1], dtype=np.int32), 1500.0, 4.0e6, 1.0e4, 6.0e7, 0, -1)
+    _, o = oracle.occurrence_catalogue(pool, layer)
+    assert np.all(o[last] > 0.0)
+    assert sum(int(np.isin(tr, last).any()) for tr in trials) > 100
+    ref, _ = oracle.run_layer(yet, pool, layer)
+    tables = ara.create_tables(yet.offsets, yet.ids, pool.losses)
+    for begin, count in ((0, yet.n_trials), (255, 300), (699, 1)):
+        sub = Layer(layer.elt_index, layer.occ_retention, layer.occ_limit, layer.agg_retention,
+                    layer.agg_limit, begin, count)
+        spec = _spec(ara, sub, pool, yet)
+        for knobs in (dict(pass_variant=0), dict(pass_variant=1, part_lanes_per_trial=16)):
+            ara.set_tuning(tables, **knobs)
+            ylt = ara.run_layers(tables, [spec])
+            ok, worst = _close(ylt, ref[begin:begin + count])
+            assert ok, (begin, count, knobs, worst)
+    tables.close()
+
+
 # ---------------------------------------------------------------------------
 # paper-scale share (1M trials x Poisson(1000), 16 ELTs): sampled parity
 # ---------------------------------------------------------------------------
