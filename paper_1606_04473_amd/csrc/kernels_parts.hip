@@ -201,13 +201,19 @@ __global__ __launch_bounds__(256) void part_image_kernel(const double* __restric
 // layer order, the chunk's nonzero entries (distinct events) each add their
 // per-ELT net loss, with a barrier between ELTs.  An absent loss adds +0.0
 // (retentions are >= 0), which leaves y unchanged, so y is bit-identical to
-// summing every ELT's dense row in layer order.  Then o, the bitmap words,
-// the per-128 ranks and the superblock count are written.
+// summing every ELT's dense row in layer order.  The next ELT's entries are
+// loaded while one ELT is added, so the ELTs cost one load latency, not one
+// each.  Then o, the bitmap words, the per-128 ranks and the superblock count
+// are written, and the superblock's nonzero o, packed in event order, go to
+// its 4096-value slot of `stage` (compact_stage_kernel moves them to their
+// global ranks).
 __device__ __forceinline__ void fold_image_body(const SparsePool& sp, int64_t C, const LayerArgs& L,
                                                 double* __restrict__ o, uint8_t* __restrict__ img,
-                                                uint32_t* __restrict__ sb_count) {
+                                                uint32_t* __restrict__ sb_count, double* __restrict__ stage) {
+    constexpr int kAhead = 2;                       // entries per thread loaded one ELT ahead
     __shared__ uint32_t wc[64];
     __shared__ double ys[kSuper];
+    __shared__ int64_t range[2 * kMaxJ];            // ELT j's entries of this chunk: [range[2j], range[2j+1])
     const int64_t sb = blockIdx.x;
     const int64_t e0 = sb * kSuper;
     const int64_t part = e0 >> kPartShift;
@@ -217,20 +223,53 @@ __device__ __forceinline__ void fold_image_body(const SparsePool& sp, int64_t C,
     const int w = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     for (int i = threadIdx.x; i < kSuper; i += blockDim.x) ys[i] = 0.0;
+    const int J = sb < sp.n_chunks ? L.J : 0;       // J <= kMaxJ <= blockDim.x
+    if (static_cast<int>(threadIdx.x) < J) {
+        const int64_t key = static_cast<int64_t>(L.idx[threadIdx.x]) * sp.n_chunks + sb;
+        range[2 * threadIdx.x] = sp.chunk_off[key];
+        range[2 * threadIdx.x + 1] = sp.chunk_off[key + 1];
+    }
     __syncthreads();
-    if (sb < sp.n_chunks) {
-        for (int j = 0; j < L.J; ++j) {
-            const int64_t key = static_cast<int64_t>(L.idx[j]) * sp.n_chunks + sb;
-            const int64_t b = sp.chunk_off[key], e = sp.chunk_off[key + 1];
-            const double R = L.R[j], Lim = L.Lim[j];
-            for (int64_t k = b + threadIdx.x; k < e; k += blockDim.x) {
-                const int ev = sp.ev[k];
-                ys[ev] = ys[ev] + apply_terms(sp.val[k], R, Lim);
-            }
-            __syncthreads();
+    auto fetch = [&](int j, int* ev, double* val) {
+        const int64_t b = range[2 * j], e = range[2 * j + 1];
+#pragma unroll
+        for (int u = 0; u < kAhead; ++u) {
+            const int64_t k = b + threadIdx.x + static_cast<int64_t>(u) * blockDim.x;
+            ev[u] = k < e ? static_cast<int>(sp.ev[k]) : -1;
+            val[u] = k < e ? sp.val[k] : 0.0;
+        }
+    };
+    int cev[kAhead], nev[kAhead];
+    double cval[kAhead], nval[kAhead];
+#pragma unroll
+    for (int u = 0; u < kAhead; ++u) {
+        cev[u] = nev[u] = -1;
+        cval[u] = nval[u] = 0.0;
+    }
+    if (J > 0) fetch(0, cev, cval);
+    for (int j = 0; j < J; ++j) {
+        if (j + 1 < J) fetch(j + 1, nev, nval);
+        const double R = L.R[j], Lim = L.Lim[j];
+#pragma unroll
+        for (int u = 0; u < kAhead; ++u)
+            if (cev[u] >= 0) ys[cev[u]] = ys[cev[u]] + apply_terms(cval[u], R, Lim);
+        // the rest of a chunk with more entries than the look-ahead holds
+        const int64_t e = range[2 * j + 1];
+        for (int64_t k = range[2 * j] + threadIdx.x + static_cast<int64_t>(kAhead) * blockDim.x; k < e;
+             k += blockDim.x) {
+            const int ev = sp.ev[k];
+            ys[ev] = ys[ev] + apply_terms(sp.val[k], R, Lim);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < kAhead; ++u) {
+            cev[u] = nev[u];
+            cval[u] = nval[u];
         }
     }
     const int64_t eb = e0 + static_cast<int64_t>(w) * 16 * 64 + lane;   // event of word 0 of this wave
+    double vk[16];
+    uint64_t bk[16];
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
         const int word = w * 16 + k;
@@ -238,12 +277,25 @@ __device__ __forceinline__ void fold_image_body(const SparsePool& sp, int64_t C,
         const double v = apply_terms(ys[word * 64 + lane], L.occR, L.occL);
         if (E < C) o[E] = v;
         const uint64_t bits = __ballot(E < C && v != 0.0);
+        vk[k] = v;
+        bk[k] = bits;
         if (lane == 0) {
             bm[ls * 64 + word] = bits;
             wc[word] = __popcll(bits);
         }
     }
     __syncthreads();
+    {   // the nonzero o packed in event order: the wave's first word starts
+        // after the counts of the words before it
+        uint32_t at = 0;
+        for (int k = 0; k < w * 16; ++k) at += wc[k];
+        double* dst = stage + sb * kSuper;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            if ((bk[k] >> lane) & 1ull) dst[at + __popcll(bk[k] & lanemask_lt())] = vk[k];
+            at += __popcll(bk[k]);
+        }
+    }
     if (threadIdx.x < 32) {
         uint32_t before = 0;
         for (int b = 0; b < static_cast<int>(threadIdx.x); ++b) before += wc[2 * b] + wc[2 * b + 1];
@@ -260,14 +312,39 @@ __device__ __forceinline__ void fold_image_body(const SparsePool& sp, int64_t C,
 // replays, whose terms may change between replays)
 __global__ __launch_bounds__(256) void fold_image_kernel(SparsePool sp, int64_t C, LayerArgs L,
                                                          double* __restrict__ o, uint8_t* __restrict__ img,
-                                                         uint32_t* __restrict__ sb_count) {
-    fold_image_body(sp, C, L, o, img, sb_count);
+                                                         uint32_t* __restrict__ sb_count, double* __restrict__ stage) {
+    fold_image_body(sp, C, L, o, img, sb_count, stage);
 }
 __global__ __launch_bounds__(256) void fold_image_dev_kernel(SparsePool sp, int64_t C,
                                                              const LayerArgs* __restrict__ L, double* __restrict__ o,
-                                                             uint8_t* __restrict__ img,
-                                                             uint32_t* __restrict__ sb_count) {
-    fold_image_body(sp, C, *L, o, img, sb_count);
+                                                             uint8_t* __restrict__ img, uint32_t* __restrict__ sb_count,
+                                                             double* __restrict__ stage) {
+    fold_image_body(sp, C, *L, o, img, sb_count, stage);
+}
+
+// After the fold: each superblock's global rank (the nonzero count of the
+// superblocks before it, summed by its own workgroup) goes to its part's base
+// table, and its packed nonzero o to compact[rank], one workgroup per superblock
+__global__ __launch_bounds__(256) void compact_stage_kernel(const double* __restrict__ stage,
+                                                            const uint32_t* __restrict__ sb_count,
+                                                            uint8_t* __restrict__ img, double* __restrict__ compact) {
+    __shared__ uint32_t wsum[4];
+    const int64_t sb = blockIdx.x;
+    uint32_t before = 0;
+    for (int64_t i = threadIdx.x; i < sb; i += blockDim.x) before += sb_count[i];
+    for (int off = 32; off >= 1; off >>= 1) before += __shfl_xor(before, off, kWave);
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = before;
+    __syncthreads();
+    const uint32_t base = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    if (threadIdx.x == 0) {
+        const int64_t part = sb / kBase32;
+        uint32_t* b32 = reinterpret_cast<uint32_t*>(img + part * kImgBytes + int64_t(kWords) * 8 +
+                                                    int64_t(kRank16) * 2);
+        b32[sb % kBase32] = base;
+    }
+    const uint32_t n = sb_count[sb];
+    const double* src = stage + sb * kSuper;
+    for (uint32_t k = threadIdx.x; k < n; k += blockDim.x) compact[static_cast<int64_t>(base) + k] = src[k];
 }
 
 // ---------------------------------------------------------------------------
@@ -1185,7 +1262,7 @@ void free_part_layout(PartLayout* L) {
 
 int64_t part_scratch_bytes(int64_t C, int P) {
     const int64_t n_sb = static_cast<int64_t>(P) * kBase32;
-    return part_image_bytes(P) + sizeof(uint32_t) * n_sb + sizeof(double) * C + 256;
+    return part_image_bytes(P) + sizeof(uint32_t) * n_sb + sizeof(double) * C + sizeof(double) * n_sb * kSuper + 256;
 }
 
 namespace {
@@ -1193,7 +1270,8 @@ struct PartScratch {
     uint8_t* img;
     uint32_t* sb_count;
     uint32_t* counter;
-    double* compact;
+    double* stage;        // [n_sb][kSuper]: each superblock's nonzero o, packed, before compaction
+    double* compact;      // [C]: the nonzero o at their global ranks (last: sized by C)
 };
 PartScratch carve_parts(void* scratch, int P) {
     char* p = static_cast<char*>(scratch);
@@ -1205,6 +1283,8 @@ PartScratch carve_parts(void* scratch, int P) {
     p += sizeof(uint32_t) * n_sb;
     r.counter = reinterpret_cast<uint32_t*>(p);
     p += 256;
+    r.stage = reinterpret_cast<double*>(p);
+    p += sizeof(double) * n_sb * kSuper;
     r.compact = reinterpret_cast<double*>(p);
     return r;
 }
@@ -1548,15 +1628,13 @@ hipError_t launch_fold_parts(const SparsePool& sp, int64_t C, const LayerArgs& L
     hipError_t e;
     if (L_dev)
         hipLaunchKernelGGL(fold_image_dev_kernel, dim3(static_cast<uint32_t>(n_sb)), dim3(256), 0, s, sp, C, L_dev,
-                           o, ps.img, ps.sb_count);
+                           o, ps.img, ps.sb_count, ps.stage);
     else
         hipLaunchKernelGGL(fold_image_kernel, dim3(static_cast<uint32_t>(n_sb)), dim3(256), 0, s, sp, C, L, o,
-                           ps.img, ps.sb_count);
+                           ps.img, ps.sb_count, ps.stage);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(superblock_scan_kernel, dim3(1), dim3(1024), 0, s, ps.sb_count, n_sb, ps.img, int64_t(0));
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(compact_kernel, dim3(static_cast<uint32_t>(n_sb)), dim3(256), 0, s, o, C, ps.img, ps.compact,
-                       int64_t(0), int64_t(0));
+    hipLaunchKernelGGL(compact_stage_kernel, dim3(static_cast<uint32_t>(n_sb)), dim3(256), 0, s, ps.stage,
+                       ps.sb_count, ps.img, ps.compact);
     return hipGetLastError();
 }
 
