@@ -201,9 +201,11 @@ __global__ void select_init_kernel(Scratch s, MArgs ma, int n_probs) {
 // fills, and count this pass's digits of the values matching the prefix.
 __global__ __launch_bounds__(256) void histogram_kernel(const double* __restrict__ x, int64_t n, Scratch s,
                                                         int n_probs, int pass, int with_mean) {
-    extern __shared__ uint32_t lds_hist[];   // [n_probs][kBins]
+    extern __shared__ uint32_t lds_hist[];   // [nq][kBins]
     __shared__ SelState cur[kMaxProbs];
-    for (int i = threadIdx.x; i < n_probs * kBins; i += blockDim.x) lds_hist[i] = 0;
+    // pass 0 starts every probability from the empty prefix, so one histogram serves all
+    const int nq = pass == 0 ? (n_probs > 0 ? 1 : 0) : n_probs;
+    for (int i = threadIdx.x; i < nq * kBins; i += blockDim.x) lds_hist[i] = 0;
     for (int q = 0; q < n_probs; ++q) {
         SelState st = s.st[q];                          // pass 0: the initial state
         if (pass > 0) {
@@ -235,19 +237,19 @@ __global__ __launch_bounds__(256) void histogram_kernel(const double* __restrict
         if (with_mean) dd_add(mhi, mlo, v);
         const uint64_t key = key_of(v);
         const uint32_t d = static_cast<uint32_t>((key >> shift) & dmask);
-        for (int q = 0; q < n_probs; ++q)
+        for (int q = 0; q < nq; ++q)
             if ((key & msk[q]) == pre[q]) atomicAdd(&lds_hist[q * kBins + d], 1u);
     };
-    // four loads in flight per thread, then the tail
-    int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    for (; i + 3 * stride < n; i += 4 * stride) {
-        const double v0 = x[i], v1 = x[i + stride], v2 = x[i + 2 * stride], v3 = x[i + 3 * stride];
-        take(v0);
-        take(v1);
-        take(v2);
-        take(v3);
+    // eight loads in flight per thread (all of a thread's values at the
+    // launch's usual 2048 values per workgroup)
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += 8 * stride) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = i + u * stride < n ? x[i + u * stride] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (i + u * stride < n) take(v[u]);
     }
-    for (; i < n; i += stride) take(x[i]);
     if (bad) atomicOr(s.flag, 1u);
     if (with_mean) {
         int64_t zero = 0;
@@ -260,9 +262,11 @@ __global__ __launch_bounds__(256) void histogram_kernel(const double* __restrict
     }
     __syncthreads();
     uint32_t* h = s.hist + (pass % 3) * kHistStride;
-    for (int k = threadIdx.x; k < n_probs * kBins; k += blockDim.x) {
+    for (int k = threadIdx.x; k < nq * kBins; k += blockDim.x) {
         const uint32_t c = lds_hist[k];
-        if (c) atomicAdd(&h[k], c);
+        if (c)
+            for (int q = k / kBins; q < (pass == 0 ? n_probs : k / kBins + 1); ++q)
+                atomicAdd(&h[q * kBins + k % kBins], c);
     }
 }
 
@@ -509,7 +513,8 @@ hipError_t launch_metrics(const double* ylt, int64_t n, const int64_t* m_host, i
     // and one workgroup that finishes the selection over those candidates
     const int passes = n_probs > 0 ? 2 : 1;
     for (int pass = 0; pass < passes; ++pass) {
-        hipLaunchKernelGGL(histogram_kernel, dim3(hblocks), dim3(256), lds, st, ylt, n, s, n_probs, pass,
+        hipLaunchKernelGGL(histogram_kernel, dim3(hblocks), dim3(256), pass == 0 ? sizeof(uint32_t) * kBins : lds, st,
+                           ylt, n, s, n_probs, pass,
                            pass == 0 ? 1 : 0);
         if ((err = hipGetLastError()) != hipSuccess) return err;
     }
