@@ -201,19 +201,23 @@ __global__ __launch_bounds__(256) void part_image_kernel(const double* __restric
 // layer order, the chunk's nonzero entries (distinct events) each add their
 // per-ELT net loss, with a barrier between ELTs.  An absent loss adds +0.0
 // (retentions are >= 0), which leaves y unchanged, so y is bit-identical to
-// summing every ELT's dense row in layer order.  The next ELT's entries are
-// loaded while one ELT is added, so the ELTs cost one load latency, not one
-// each.  Then o, the bitmap words, the per-128 ranks and the superblock count
-// are written, and the superblock's nonzero o, packed in event order, go to
-// its 4096-value slot of `stage` (compact_stage_kernel moves them to their
-// global ranks).
+// summing every ELT's dense row in layer order.  The entries of all the
+// layer's ELTs are first copied to LDS with independent loads (up to kStage
+// of them; the rest are read in place), so the ELTs cost one load latency,
+// not one each.  Then o, the bitmap words, the per-128 ranks and the
+// superblock count are written, and the superblock's nonzero o, packed in
+// event order, go to its 4096-value slot of `stage` (compact_stage_kernel
+// moves them to their global ranks).
 __device__ __forceinline__ void fold_image_body(const SparsePool& sp, int64_t C, const LayerArgs& L,
                                                 double* __restrict__ o, uint8_t* __restrict__ img,
                                                 uint32_t* __restrict__ sb_count, double* __restrict__ stage) {
-    constexpr int kAhead = 2;                       // entries per thread loaded one ELT ahead
+    constexpr int kStage = 2048;                    // entries staged in LDS
     __shared__ uint32_t wc[64];
     __shared__ double ys[kSuper];
-    __shared__ int64_t range[2 * kMaxJ];            // ELT j's entries of this chunk: [range[2j], range[2j+1])
+    __shared__ double sval[kStage];
+    __shared__ uint16_t sev[kStage];
+    __shared__ int64_t gstart[kMaxJ];               // ELT j's first entry of this chunk in the pool
+    __shared__ int32_t fpre[kMaxJ + 1];             // ELT j's entries are [fpre[j], fpre[j+1]) of the chunk's list
     const int64_t sb = blockIdx.x;
     const int64_t e0 = sb * kSuper;
     const int64_t part = e0 >> kPartShift;
@@ -223,49 +227,76 @@ __device__ __forceinline__ void fold_image_body(const SparsePool& sp, int64_t C,
     const int w = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     for (int i = threadIdx.x; i < kSuper; i += blockDim.x) ys[i] = 0.0;
-    const int J = sb < sp.n_chunks ? L.J : 0;       // J <= kMaxJ <= blockDim.x
-    if (static_cast<int>(threadIdx.x) < J) {
-        const int64_t key = static_cast<int64_t>(L.idx[threadIdx.x]) * sp.n_chunks + sb;
-        range[2 * threadIdx.x] = sp.chunk_off[key];
-        range[2 * threadIdx.x + 1] = sp.chunk_off[key + 1];
+    const int J = sb < sp.n_chunks ? L.J : 0;       // J <= kMaxJ <= 64: one wave holds the ELTs
+    if (w == 0) {
+        int32_t cnt = 0;
+        if (lane < J) {
+            const int64_t key = static_cast<int64_t>(L.idx[lane]) * sp.n_chunks + sb;
+            const int64_t b = sp.chunk_off[key];
+            gstart[lane] = b;
+            cnt = static_cast<int32_t>(sp.chunk_off[key + 1] - b);    // <= 4096
+        }
+        int32_t inc = cnt;                          // inclusive scan over the wave
+        for (int off = 1; off < 64; off <<= 1) {
+            const int32_t v = __shfl_up(inc, off, kWave);
+            if (lane >= off) inc += v;
+        }
+        if (lane < J) fpre[lane + 1] = inc;
+        if (lane == 0) fpre[0] = 0;
     }
     __syncthreads();
-    auto fetch = [&](int j, int* ev, double* val) {
-        const int64_t b = range[2 * j], e = range[2 * j + 1];
-#pragma unroll
-        for (int u = 0; u < kAhead; ++u) {
-            const int64_t k = b + threadIdx.x + static_cast<int64_t>(u) * blockDim.x;
-            ev[u] = k < e ? static_cast<int>(sp.ev[k]) : -1;
-            val[u] = k < e ? sp.val[k] : 0.0;
+    const int n_list = fpre[J];
+    const int staged = n_list < kStage ? n_list : kStage;
+    // ELT of entry f of the list: the first j whose range ends past f
+    auto elt_of = [&](int f) {
+        int lo = 0, hi = J - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (fpre[mid + 1] > f) hi = mid;
+            else lo = mid + 1;
         }
+        return lo;
     };
-    int cev[kAhead], nev[kAhead];
-    double cval[kAhead], nval[kAhead];
+    for (int f0 = threadIdx.x; f0 < staged; f0 += 4 * blockDim.x) {
+        uint16_t ev[4];
+        double val[4];
 #pragma unroll
-    for (int u = 0; u < kAhead; ++u) {
-        cev[u] = nev[u] = -1;
-        cval[u] = nval[u] = 0.0;
+        for (int u = 0; u < 4; ++u) {
+            const int f = f0 + u * static_cast<int>(blockDim.x);
+            if (f < staged) {
+                const int j = elt_of(f);
+                const int64_t k = gstart[j] + (f - fpre[j]);
+                ev[u] = sp.ev[k];
+                val[u] = sp.val[k];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int f = f0 + u * static_cast<int>(blockDim.x);
+            if (f < staged) {
+                sev[f] = ev[u];
+                sval[f] = val[u];
+            }
+        }
     }
-    if (J > 0) fetch(0, cev, cval);
+    __syncthreads();
     for (int j = 0; j < J; ++j) {
-        if (j + 1 < J) fetch(j + 1, nev, nval);
         const double R = L.R[j], Lim = L.Lim[j];
-#pragma unroll
-        for (int u = 0; u < kAhead; ++u)
-            if (cev[u] >= 0) ys[cev[u]] = ys[cev[u]] + apply_terms(cval[u], R, Lim);
-        // the rest of a chunk with more entries than the look-ahead holds
-        const int64_t e = range[2 * j + 1];
-        for (int64_t k = range[2 * j] + threadIdx.x + static_cast<int64_t>(kAhead) * blockDim.x; k < e;
-             k += blockDim.x) {
-            const int ev = sp.ev[k];
-            ys[ev] = ys[ev] + apply_terms(sp.val[k], R, Lim);
+        const int fe = fpre[j + 1];
+        for (int f = fpre[j] + static_cast<int>(threadIdx.x); f < fe; f += blockDim.x) {
+            int ev;
+            double v;
+            if (f < kStage) {
+                ev = sev[f];
+                v = sval[f];
+            } else {
+                const int64_t k = gstart[j] + (f - fpre[j]);
+                ev = sp.ev[k];
+                v = sp.val[k];
+            }
+            ys[ev] = ys[ev] + apply_terms(v, R, Lim);
         }
         __syncthreads();
-#pragma unroll
-        for (int u = 0; u < kAhead; ++u) {
-            cev[u] = nev[u];
-            cval[u] = nval[u];
-        }
     }
     const int64_t eb = e0 + static_cast<int64_t>(w) * 16 * 64 + lane;   // event of word 0 of this wave
     double vk[16];
