@@ -673,6 +673,37 @@ def test_segment_padding_with_nonzero_last_events(ara):
     tables.close()
 
 
+def test_dense_elts_fold(ara):
+    """ELTs at 50% density: a 4096-event chunk holds ~20 000 sparse entries
+    over the layer's ten ELTs, far more than the fold stages in LDS, so most
+    are added straight from the pool.  The sums must still be taken in layer
+    order, per event; each part also holds many more nonzero losses than the
+    pass keeps in LDS.  Year losses (both pass variants) and per-event nets
+    against the oracle."""
+    C = 600_000
+    yet = make_yet(400, 300.0, C, seed=81)
+    pool = make_elt_pool(12, C, 300_000, seed=82)
+    idx = np.array([11, 3, 7, 0, 9, 1, 5, 10, 2, 6], dtype=np.int32)
+    tables = ara.create_tables(yet.offsets, yet.ids, pool.losses)
+    # annual totals run 1.1e8-1.5e8: about half the trials fall below AggR, a few reach AggL
+    for lay in (Layer(idx, 2500.0, 2.0e6, 1.2e8, 2.0e7, 0, yet.n_trials),
+                Layer(idx[::-1].copy(), 0.0, INF, 0.0, INF, 37, 300)):
+        ref, _ = oracle.run_layer(yet, pool, lay)
+        spec = _spec(ara, lay, pool, yet)
+        for knobs in (dict(pass_variant=0), dict(pass_variant=1, part_lanes_per_trial=16)):
+            ara.set_tuning(tables, **knobs)
+            ylt = ara.run_layers(tables, [spec])
+            ok, worst = _close(ylt, ref)
+            assert ok, (knobs, worst)
+        ara.set_tuning(tables, pass_variant=0)
+        nets_ref = oracle.event_nets(yet, pool, lay)
+        got = ara.event_nets(tables, spec)
+        assert got.shape == nets_ref.shape
+        ok, exact = _nets_close(got, nets_ref, yet, lay, ref)
+        assert ok and exact > 0.99, exact
+    tables.close()
+
+
 # ---------------------------------------------------------------------------
 # paper-scale share (1M trials x Poisson(1000), 16 ELTs): sampled parity
 # ---------------------------------------------------------------------------
