@@ -96,6 +96,7 @@ hipError_t scratch_acquire(std::mutex& mu, std::vector<ara::ScratchBuffer*>& set
         }
         pick->p = nullptr;
         pick->cap = 0;
+        pick->primed = false;
         if (e == hipSuccess) e = hipMalloc(&pick->p, bytes);
         if (e == hipSuccess) pick->cap = bytes;
     }
@@ -1097,7 +1098,11 @@ ara_status ara_risk_metrics(const double* ylt, int64_t n_trials, const double* p
     // through the results buffer [mean, PML_0, TVaR_0, PML_1, ...]
     const ara::MetricsOut out = dev ? ara::MetricsOut{mean_out, pml_out, tvar_out, 1}
                                     : ara::MetricsOut{r, r + 1, r + 2, 2};
-    HIP_TRY(ara::launch_metrics(x, n_trials, m.data(), n_probs, scratch.b->p, out, n_cu, s), "metrics kernels");
+    // the scratch counts as primed only once this whole sequence is enqueued
+    const bool primed = scratch.b->primed;
+    scratch.b->primed = false;
+    HIP_TRY(ara::launch_metrics(x, n_trials, m.data(), n_probs, scratch.b->p, primed, out, n_cu, s), "metrics kernels");
+    scratch.b->primed = true;
     if (dev) return ARA_OK;
     std::vector<double> h(1 + 2 * n_probs);
     HIP_TRY(hipMemcpyAsync(h.data(), r, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s), "copy metrics");

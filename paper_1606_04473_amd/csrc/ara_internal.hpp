@@ -269,6 +269,7 @@ struct ScratchBuffer {
     hipEvent_t done = nullptr;      // recorded on `stream` after the last use
     hipStream_t stream = nullptr;
     bool busy = false;
+    bool primed = false;            // metrics: left ready by a whole launch sequence (cleared on growth)
 };
 
 // A captured batched run: persistent scratch, a graph, and the shape it was
@@ -389,8 +390,10 @@ struct MetricsOut {
 };
 // scratch of launch_metrics for n_probs probabilities over n year losses
 int64_t metrics_scratch_bytes(int n_probs, int64_t n);
+// `primed`: the scratch was last used by a launch_metrics sequence that was
+// enqueued whole, which leaves it ready for the next one (no init kernel)
 hipError_t launch_metrics(const double* ylt, int64_t n, const int64_t* m_host, int n_probs,
-                          void* scratch, MetricsOut out, int n_cu, hipStream_t s);
+                          void* scratch, bool primed, MetricsOut out, int n_cu, hipStream_t s);
 
 // order statistics of a YLT for one tail count m
 struct TailStats {

@@ -14,7 +14,10 @@
 // and a single workgroup finishes the selection over those candidates: up to
 // 256 of them are ranked directly against each other, more go through the
 // last four digit passes.  Each launch costs about 9 us here, whatever its data, so
-// that cuts nine launches to five.  TVaR_p = (sum of the values above v +
+// that cuts nine launches to five.  The scratch is kept between calls and each
+// call leaves it ready for the next (its candidate pass clears the first
+// histogram, its last kernel the error flag), so a call on a reused scratch
+// skips the init kernel: four launches.  TVaR_p = (sum of the values above v +
 // (m - c_gt) v) / m, with v = PML_p and c_gt the count above it.  Sums are
 // double-double, reduced in a fixed order (deterministic), and the product
 // (m - c_gt) v is added exactly via fma.
@@ -182,7 +185,8 @@ __device__ SelState choose_digit(const uint32_t* __restrict__ h, SelState st, in
     return r;
 }
 
-// resets the selection state and clears the first histogram with plain stores
+// resets the selection state and clears the first histogram (every
+// probability's slot) with plain stores
 __global__ void select_init_kernel(Scratch s, MArgs ma, int n_probs) {
     const int tid = blockIdx.x * blockDim.x + threadIdx.x;
     if (tid < n_probs) {
@@ -193,21 +197,26 @@ __global__ void select_init_kernel(Scratch s, MArgs ma, int n_probs) {
     }
     if (tid == 0) *s.flag = 0;
     if (tid < kMaxProbs) s.ccount[tid] = 0;
-    for (int i = tid; i < n_probs * kBins; i += gridDim.x * blockDim.x) s.hist[i] = 0;
+    for (int64_t i = tid; i < kHistStride; i += gridDim.x * blockDim.x) s.hist[i] = 0;
 }
 
 // Pass `pass` of the radix select (and, in pass 0, the sum for the mean):
 // finish the previous pass's digit choice, clear the histogram the next pass
 // fills, and count this pass's digits of the values matching the prefix.
 __global__ __launch_bounds__(256) void histogram_kernel(const double* __restrict__ x, int64_t n, Scratch s,
-                                                        int n_probs, int pass, int with_mean) {
+                                                        MArgs ma, int n_probs, int pass, int with_mean) {
     extern __shared__ uint32_t lds_hist[];   // [nq][kBins]
     __shared__ SelState cur[kMaxProbs];
     // pass 0 starts every probability from the empty prefix, so one histogram serves all
     const int nq = pass == 0 ? (n_probs > 0 ? 1 : 0) : n_probs;
     for (int i = threadIdx.x; i < nq * kBins; i += blockDim.x) lds_hist[i] = 0;
     for (int q = 0; q < n_probs; ++q) {
-        SelState st = s.st[q];                          // pass 0: the initial state
+        // pass 0 starts from the empty prefix and records that state for pass 1
+        SelState st{0, 0, ma.m[q], ma.m[q]};
+        if (pass == 0 && blockIdx.x == 0 && threadIdx.x == 0) {
+            s.st[q] = st;
+            s.ccount[q] = 0;
+        }
         if (pass > 0) {
             st = s.st[((pass - 1) & 1) * kMaxProbs + q];
             st = choose_digit(s.hist + ((pass - 1) % 3) * kHistStride + int64_t(q) * kBins, st, pass - 1);
@@ -289,6 +298,13 @@ __global__ __launch_bounds__(256) void collect_kernel(const double* __restrict__
         }
     }
     __syncthreads();
+    {   // the first pass's histogram, read for the last time by the second
+        // pass, is cleared for the next call (with the error flag, cleared
+        // by the last kernel, the scratch is then ready without an init)
+        const int64_t per = (kHistStride + gridDim.x - 1) / gridDim.x;
+        const int64_t b0 = per * blockIdx.x;
+        for (int64_t i = b0 + threadIdx.x; i < b0 + per && i < kHistStride; i += blockDim.x) s.hist[i] = 0;
+    }
     const int lane = threadIdx.x & 63;
     const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
     for (int q = 0; q < n_probs; ++q) {
@@ -416,6 +432,7 @@ __global__ __launch_bounds__(256) void finish_kernel(Scratch s, int n_probs, int
         }
         __syncthreads();
     }
+    if (threadIdx.x == 0) *s.flag = 0;              // read by every thread before the barriers above
 }
 
 // one workgroup: the mean from the pass-0 partials, then PML and TVaR per
@@ -450,6 +467,7 @@ __global__ __launch_bounds__(256) void final_kernel(Scratch s, int n_probs, int 
         }
         __syncthreads();
     }
+    if (threadIdx.x == 0) *s.flag = 0;              // read by every thread before the barriers above
 }
 
 // one workgroup: the final digit for the single tail count, into `out`
@@ -493,15 +511,19 @@ int64_t metrics_scratch_bytes(int n_probs, int64_t n) {
 }
 
 hipError_t launch_metrics(const double* ylt, int64_t n, const int64_t* m_host, int n_probs,
-                          void* scratch, MetricsOut out, int n_cu, hipStream_t st) {
+                          void* scratch, bool primed, MetricsOut out, int n_cu, hipStream_t st) {
     if (n_probs > kMaxProbs) return hipErrorInvalidValue;
     (void)n_cu;
     Scratch s = carve(scratch, n_probs);
     MArgs ma{};
     for (int q = 0; q < n_probs; ++q) ma.m[q] = m_host[q];
     hipError_t err;
-    hipLaunchKernelGGL(select_init_kernel, dim3(16), dim3(256), 0, st, s, ma, n_probs);
-    if ((err = hipGetLastError()) != hipSuccess) return err;
+    // a scratch left by a completed call has a clear first histogram and a
+    // clear error flag; only a new one (or one after a failed launch) needs this
+    if (!primed) {
+        hipLaunchKernelGGL(select_init_kernel, dim3(16), dim3(256), 0, st, s, ma, n_probs);
+        if ((err = hipGetLastError()) != hipSuccess) return err;
+    }
     // enough workgroups to keep many loads in flight; each adds only its
     // non-zero bins to the global histogram (values crowd into few bins)
     int hblocks = static_cast<int>((n + 2047) / 2048);
@@ -514,8 +536,7 @@ hipError_t launch_metrics(const double* ylt, int64_t n, const int64_t* m_host, i
     const int passes = n_probs > 0 ? 2 : 1;
     for (int pass = 0; pass < passes; ++pass) {
         hipLaunchKernelGGL(histogram_kernel, dim3(hblocks), dim3(256), pass == 0 ? sizeof(uint32_t) * kBins : lds, st,
-                           ylt, n, s, n_probs, pass,
-                           pass == 0 ? 1 : 0);
+                           ylt, n, s, ma, n_probs, pass, pass == 0 ? 1 : 0);
         if ((err = hipGetLastError()) != hipSuccess) return err;
     }
     if (n_probs == 0) {
@@ -549,7 +570,7 @@ hipError_t launch_tail_stats(const double* ylt, int64_t n, int64_t m, void* scra
     if (hblocks > kSumBlocks) hblocks = kSumBlocks;
     if (hblocks < 1) hblocks = 1;
     for (int pass = 0; pass < kPasses; ++pass) {
-        hipLaunchKernelGGL(histogram_kernel, dim3(hblocks), dim3(256), sizeof(uint32_t) * kBins, st, ylt, n, s,
+        hipLaunchKernelGGL(histogram_kernel, dim3(hblocks), dim3(256), sizeof(uint32_t) * kBins, st, ylt, n, s, ma,
                            1, pass, 0);
         if ((err = hipGetLastError()) != hipSuccess) return err;
     }

@@ -181,6 +181,38 @@ def test_metrics_ties_zeros_and_tiny_inputs(ara):
                 assert abs(a - b) <= REL * abs(b), (len(y), probs, tvar, rtvar)
 
 
+def test_metrics_back_to_back_calls(ara):
+    """The metrics scratch is kept between calls and left ready by each one
+    (its first histogram and error flag cleared by the call's last kernels).
+    Calls of changing sizes and probability counts, one rejected for a NaN
+    loss and one for a negative loss, host and device inputs, each against
+    the oracle: a state left over from one call would show in the next."""
+    import torch
+    rng = np.random.default_rng(91)
+    seq = [(rng.lognormal(12, 2, 50_000), [0.99, 0.996, 0.9, 0.5]),
+           (rng.lognormal(8, 1, 3_000), [0.9]),
+           ("nan", [0.99]),
+           (rng.lognormal(10, 3, 120_000), [0.99, 0.5]),
+           ("neg", [0.9, 0.99]),
+           (np.where(rng.random(70_000) < 0.4, 0.0, rng.lognormal(9, 2, 70_000)), [0.999, 0.6, 0.3]),
+           (rng.lognormal(12, 2, 50_000), [0.99, 0.996, 0.9, 0.5])]
+    for i, (y, probs) in enumerate(seq):
+        if isinstance(y, str):
+            bad = rng.lognormal(10, 1, 10_000)
+            bad[1234] = math.nan if y == "nan" else -1.0
+            with pytest.raises(ara.AraError):
+                ara.risk_metrics(bad, probs)
+            continue
+        rmean, rpml, rtvar = oracle.risk_metrics(y, probs)
+        inp = y if i % 2 else torch.from_numpy(y).cuda()
+        mean, pml, tvar = ara.risk_metrics(inp, probs)
+        assert abs(mean - rmean) <= REL * abs(rmean), i
+        for a, b in zip(pml, rpml):
+            assert abs(a - b) <= REL * abs(b), (i, pml, rpml)
+        for a, b in zip(tvar, rtvar):
+            assert abs(a - b) <= REL * abs(b), (i, tvar, rtvar)
+
+
 def test_config0_checkpoints(ara, cfg0):
     w, tables, ref, S = cfg0
     yet, pool, layer = w.yet, w.pool, w.layers[0]
