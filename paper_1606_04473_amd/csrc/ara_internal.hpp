@@ -236,6 +236,7 @@ struct PartAdjArgs {
     uint64_t* w_mean;
     uint64_t* w_tvar;
     uint32_t* tile_counter;
+    const uint32_t* sb_count;       // nonzero count of each superblock (for part-relative ranks)
 };
 
 struct ProfileState {

@@ -32,11 +32,11 @@ namespace {
 
 constexpr int kPartShift = 18;
 constexpr int64_t kPartSize = int64_t(1) << kPartShift;       // catalogue events per part
-constexpr int kWords = kPartSize / 64;                        // 8192 u64 bitmap words
-constexpr int kRank16 = kPartSize / 128;                      // 4096 u16
+constexpr int kWords = kPartSize / 64;                        // 4096 u64 bitmap words
+constexpr int kRank16 = kPartSize / 128;                      // 2048 u16
 constexpr int kSuperShift = 12;
 constexpr int kSuper = 1 << kSuperShift;                      // 4096 events per superblock
-constexpr int kBase32 = kPartSize / kSuper;                   // 128 u32
+constexpr int kBase32 = kPartSize / kSuper;                   // 64 u32
 constexpr int64_t kImgBytes = int64_t(kWords) * 8 + int64_t(kRank16) * 2 + int64_t(kBase32) * 4;
 static_assert(kImgBytes == 37120, "part image layout");
 static_assert(kImgBytes % 16 == 0, "16-byte copies");
@@ -773,6 +773,130 @@ __global__ __launch_bounds__(512) void part_adjoint_kernel(PartAdjArgs a) {
             }
         }
         __syncthreads();
+    }
+}
+
+// Backward histogram, XCD-affine, for the same result as part_adjoint_kernel.
+// Workgroups on XCD x serve the parts p = x (mod 8) as in the forward pass,
+// each over a fixed share of the tiles, so a part's probe words (bitmap bits
+// and part-relative ranks, built from the part image and its superblock
+// counts) are loaded into LDS once.  An occurrence of a movable event in a
+// trial inside the aggregate band counts 1 for W_mean: in an LDS counter
+// when the event is among the part's first kCounts nonzero events (by rank),
+// else with a global atomic; the LDS counters are added to W_mean once per
+// part.  TVaR weights (tail trials only) use global atomics.  All counts are
+// integers, so the order of the additions does not matter.  The LDS counters
+// are 32-bit: the launcher uses this kernel only for layouts of fewer than
+// 2^32 IDs, which bounds every count.
+__global__ __launch_bounds__(1024) void xcd_adjoint_kernel(PartAdjArgs a, int n_xcd) {
+    constexpr uint32_t kProbeWords = static_cast<uint32_t>(kPartSize >> 5);
+    constexpr uint32_t kCounts = 24000;
+    __shared__ uint64_t pw[kProbeWords];
+    __shared__ uint32_t cnt[kCounts];
+    __shared__ uint32_t sbb[kBase32];               // part-relative rank of each superblock's first event
+    const int lane = threadIdx.x & 63;
+    const int lig = lane & 15;
+    const int slot = (threadIdx.x >> 6) * 4 + (lane >> 4);     // 64 groups of 16 lanes, one trial each
+    const int n_slots = static_cast<int>(blockDim.x >> 4);
+    const int P = a.P;
+    const TailStats ts = *a.tail;
+    const int x = static_cast<int>(blockIdx.x % n_xcd);
+    const int r = static_cast<int>(blockIdx.x / n_xcd);
+    const int nr = static_cast<int>(gridDim.x / n_xcd);
+    int p0, pstep, srank, nserv;
+    if (P >= n_xcd) {
+        p0 = x;
+        pstep = n_xcd;
+        srank = r;
+        nserv = nr;
+    } else {
+        p0 = x % P;
+        pstep = P;
+        srank = (x / P) * nr + r;
+        nserv = ((n_xcd - 1 - p0) / P + 1) * nr;
+    }
+    const int64_t n_tiles = a.last_tile - a.first_tile;
+    for (int p = p0; p < P; p += pstep) {
+        const uint8_t* gimg = a.img + static_cast<int64_t>(p) * kImgBytes;
+        const uint32_t* gbm = reinterpret_cast<const uint32_t*>(gimg);
+        const uint16_t* gr16 = reinterpret_cast<const uint16_t*>(gimg + int64_t(kWords) * 8);
+        __syncthreads();                            // the previous part's counters are flushed
+        if (threadIdx.x == 0) {
+            uint32_t run = 0;
+            for (int k = 0; k < kBase32; ++k) {
+                sbb[k] = run;
+                run += a.sb_count[static_cast<int64_t>(p) * kBase32 + k];
+            }
+        }
+        for (uint32_t k = threadIdx.x; k < kCounts; k += blockDim.x) cnt[k] = 0;
+        __syncthreads();
+        for (uint32_t j = threadIdx.x; j < kProbeWords; j += blockDim.x) {
+            uint32_t rank = sbb[j >> 7] + gr16[j >> 2];
+            for (uint32_t k = j & ~3u; k < j; ++k) rank += __builtin_popcount(gbm[k]);
+            pw[j] = (static_cast<uint64_t>(rank) << 32) | gbm[j];
+        }
+        __syncthreads();
+        const uint32_t pbase = static_cast<uint32_t>(static_cast<int64_t>(p) << kPartShift);
+        for (int64_t m = srank; m < n_tiles; m += nserv) {
+            const int64_t tile = a.first_tile + m;
+            const int64_t t0 = tile * a.T;
+            const int Tk = static_cast<int>(a.N - t0 < a.T ? a.N - t0 : a.T);
+            const int64_t sbase = tile * (static_cast<int64_t>(a.T) * P + 1);
+            const uint32_t* tids = a.pids + a.tile_start[tile];
+            for (int i = slot; i < Tk; i += n_slots) {
+                const int64_t t = t0 + i;
+                if (t < a.t_lo || t >= a.t_hi) continue;
+                const int64_t k = t - a.t_lo;
+                const double ta = a.S[k] - a.aggR;
+                if (!((ta > 0.0) && (ta < a.aggL))) continue;
+                const uint64_t key = __double_as_longlong(a.ylt[k] + 0.0);
+                const unsigned long long wt =
+                    key > ts.v_bits ? ts.c_eq : (key == ts.v_bits ? ts.m - ts.c_gt : 0);
+                const uint32_t sb = a.seg_rel[sbase + static_cast<int64_t>(p) * Tk + i];
+                const uint32_t se = a.seg_rel[sbase + static_cast<int64_t>(p) * Tk + i + 1];
+                constexpr int kU = 4;
+                for (uint32_t c = sb + lig * 4; c < se; c += 64 * kU) {
+                    u32x4 v[kU];
+#pragma unroll
+                    for (int u = 0; u < kU; ++u) {
+                        const uint32_t cu = c + u * 64;
+                        v[u] = cu < se ? __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(tids + cu))
+                                       : u32x4{kSentinel, kSentinel, kSentinel, kSentinel};
+                    }
+#pragma unroll
+                    for (int q = 0; q < kU * 4; ++q) {
+                        const uint32_t id = v[q >> 2][q & 3];
+                        const uint32_t el = id - pbase;
+                        if (el >= static_cast<uint32_t>(kPartSize)) continue;     // padding
+                        const uint64_t w = pw[el >> 5];
+                        const uint32_t bi = el & 31u;
+                        if (!((w >> bi) & 1ull)) continue;
+                        const uint32_t rank = static_cast<uint32_t>(w >> 32) +
+                                              __builtin_popcount(static_cast<uint32_t>(w) & ((1u << bi) - 1u));
+                        if (rank < kCounts)
+                            atomicAdd(&cnt[rank], 1u);
+                        else
+                            atomicAdd(reinterpret_cast<unsigned long long*>(&a.w_mean[id]), 1ull);
+                        if (wt) atomicAdd(reinterpret_cast<unsigned long long*>(&a.w_tvar[id]), wt);
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        // the LDS counters to W_mean: the events of each probe word, in rank order
+        for (uint32_t j = threadIdx.x; j < kProbeWords; j += blockDim.x) {
+            const uint64_t w = pw[j];
+            uint32_t bits = static_cast<uint32_t>(w);
+            uint32_t rank = static_cast<uint32_t>(w >> 32);
+            while (bits && rank < kCounts) {
+                const uint32_t b = static_cast<uint32_t>(__builtin_ctz(bits));
+                const uint32_t c = cnt[rank];
+                if (c) atomicAdd(reinterpret_cast<unsigned long long*>(&a.w_mean[pbase + j * 32 + b]),
+                                 static_cast<unsigned long long>(c));
+                bits &= bits - 1u;
+                ++rank;
+            }
+        }
     }
 }
 
@@ -1732,6 +1856,15 @@ hipError_t launch_part_adjoint(const PartLayout& lay, int64_t N, const LayerArgs
     a.w_mean = w_mean;
     a.w_tvar = w_tvar;
     a.tile_counter = ps.counter;
+    a.sb_count = ps.sb_count;
+    if (lay.length < (int64_t(1) << 32)) {
+        // one workgroup per CU, a multiple of the XCD count (see xcd_adjoint_kernel)
+        int64_t grid = int64_t(n_cu);
+        grid -= grid % kXcds;
+        if (grid < kXcds) grid = kXcds;
+        hipLaunchKernelGGL(xcd_adjoint_kernel, dim3(static_cast<uint32_t>(grid)), dim3(1024), 0, s, a, kXcds);
+        return hipGetLastError();
+    }
     int64_t grid = a.last_tile - a.first_tile;
     if (grid > int64_t(n_cu) * 2) grid = int64_t(n_cu) * 2;
     hipLaunchKernelGGL(part_adjoint_kernel, dim3(static_cast<uint32_t>(grid)), dim3(512), 0, s, a);
