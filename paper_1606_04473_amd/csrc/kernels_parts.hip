@@ -784,8 +784,10 @@ __global__ __launch_bounds__(512) void part_adjoint_kernel(PartAdjArgs a) {
 // trial inside the aggregate band counts 1 for W_mean: in an LDS counter
 // when the event is among the part's first kCounts nonzero events (by rank),
 // else with a global atomic; the LDS counters are added to W_mean once per
-// part.  TVaR weights (tail trials only) use global atomics.  All counts are
-// integers, so the order of the additions does not matter.  The LDS counters
+// part.  TVaR weights (tail trials only) use global atomics.  Each group of
+// 16 lanes takes four trials of a tile at once, so their segments' loads are
+// in flight together.  All counts are integers, so the order of the additions
+// does not matter.  The LDS counters
 // are 32-bit: the launcher uses this kernel only for layouts of fewer than
 // 2^32 IDs, which bounds every count.
 __global__ __launch_bounds__(1024) void xcd_adjoint_kernel(PartAdjArgs a, int n_xcd) {
@@ -843,42 +845,60 @@ __global__ __launch_bounds__(1024) void xcd_adjoint_kernel(PartAdjArgs a, int n_
             const int Tk = static_cast<int>(a.N - t0 < a.T ? a.N - t0 : a.T);
             const int64_t sbase = tile * (static_cast<int64_t>(a.T) * P + 1);
             const uint32_t* tids = a.pids + a.tile_start[tile];
-            for (int i = slot; i < Tk; i += n_slots) {
-                const int64_t t = t0 + i;
-                if (t < a.t_lo || t >= a.t_hi) continue;
-                const int64_t k = t - a.t_lo;
-                const double ta = a.S[k] - a.aggR;
-                if (!((ta > 0.0) && (ta < a.aggL))) continue;
-                const uint64_t key = __double_as_longlong(a.ylt[k] + 0.0);
-                const unsigned long long wt =
-                    key > ts.v_bits ? ts.c_eq : (key == ts.v_bits ? ts.m - ts.c_gt : 0);
-                const uint32_t sb = a.seg_rel[sbase + static_cast<int64_t>(p) * Tk + i];
-                const uint32_t se = a.seg_rel[sbase + static_cast<int64_t>(p) * Tk + i + 1];
+            // kTr trials per group of 16 lanes, whose segments' loads are in flight together
+            constexpr int kTr = 4;
+            for (int i0 = slot; i0 < Tk; i0 += kTr * n_slots) {
+                uint32_t sb2[kTr], len2[kTr];
+                unsigned long long wt2[kTr];
+#pragma unroll
+                for (int h = 0; h < kTr; ++h) {
+                    const int i = i0 + h * n_slots;
+                    sb2[h] = 0;
+                    len2[h] = 0;
+                    wt2[h] = 0;
+                    const int64_t t = t0 + i;
+                    if (i >= Tk || t < a.t_lo || t >= a.t_hi) continue;
+                    const int64_t k = t - a.t_lo;
+                    const double ta = a.S[k] - a.aggR;
+                    if (!((ta > 0.0) && (ta < a.aggL))) continue;        // outside the aggregate band
+                    const uint64_t key = __double_as_longlong(a.ylt[k] + 0.0);
+                    wt2[h] = key > ts.v_bits ? ts.c_eq : (key == ts.v_bits ? ts.m - ts.c_gt : 0);
+                    sb2[h] = a.seg_rel[sbase + static_cast<int64_t>(p) * Tk + i];
+                    len2[h] = a.seg_rel[sbase + static_cast<int64_t>(p) * Tk + i + 1] - sb2[h];
+                }
                 constexpr int kU = 4;
-                for (uint32_t c = sb + lig * 4; c < se; c += 64 * kU) {
-                    u32x4 v[kU];
+                uint32_t lmax = 0;
 #pragma unroll
-                    for (int u = 0; u < kU; ++u) {
-                        const uint32_t cu = c + u * 64;
-                        v[u] = cu < se ? __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(tids + cu))
-                                       : u32x4{kSentinel, kSentinel, kSentinel, kSentinel};
-                    }
+                for (int h = 0; h < kTr; ++h) lmax = len2[h] > lmax ? len2[h] : lmax;
+                for (uint32_t off = lig * 4; off < lmax; off += 64 * kU) {
+                    u32x4 v[kTr][kU];
 #pragma unroll
-                    for (int q = 0; q < kU * 4; ++q) {
-                        const uint32_t id = v[q >> 2][q & 3];
-                        const uint32_t el = id - pbase;
-                        if (el >= static_cast<uint32_t>(kPartSize)) continue;     // padding
-                        const uint64_t w = pw[el >> 5];
-                        const uint32_t bi = el & 31u;
-                        if (!((w >> bi) & 1ull)) continue;
-                        const uint32_t rank = static_cast<uint32_t>(w >> 32) +
-                                              __builtin_popcount(static_cast<uint32_t>(w) & ((1u << bi) - 1u));
-                        if (rank < kCounts)
-                            atomicAdd(&cnt[rank], 1u);
-                        else
-                            atomicAdd(reinterpret_cast<unsigned long long*>(&a.w_mean[id]), 1ull);
-                        if (wt) atomicAdd(reinterpret_cast<unsigned long long*>(&a.w_tvar[id]), wt);
-                    }
+                    for (int h = 0; h < kTr; ++h)
+#pragma unroll
+                        for (int u = 0; u < kU; ++u) {
+                            const uint32_t o = off + u * 64;
+                            v[h][u] = o < len2[h]
+                                          ? __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(tids + sb2[h] + o))
+                                          : u32x4{kSentinel, kSentinel, kSentinel, kSentinel};
+                        }
+#pragma unroll
+                    for (int h = 0; h < kTr; ++h)
+#pragma unroll
+                        for (int q = 0; q < kU * 4; ++q) {
+                            const uint32_t id = v[h][q >> 2][q & 3];
+                            const uint32_t el = id - pbase;
+                            if (el >= static_cast<uint32_t>(kPartSize)) continue;     // padding
+                            const uint64_t w = pw[el >> 5];
+                            const uint32_t bi = el & 31u;
+                            if (!((w >> bi) & 1ull)) continue;
+                            const uint32_t rank = static_cast<uint32_t>(w >> 32) +
+                                                  __builtin_popcount(static_cast<uint32_t>(w) & ((1u << bi) - 1u));
+                            if (rank < kCounts)
+                                atomicAdd(&cnt[rank], 1u);
+                            else
+                                atomicAdd(reinterpret_cast<unsigned long long*>(&a.w_mean[id]), 1ull);
+                            if (wt2[h]) atomicAdd(reinterpret_cast<unsigned long long*>(&a.w_tvar[id]), wt2[h]);
+                        }
                 }
             }
         }
