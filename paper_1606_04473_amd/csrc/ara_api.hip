@@ -1150,12 +1150,20 @@ ara_status ara_backward(ara_tables* t, const ara_layer* layer, double tvar_p, do
         const ara_tuning tu = t->tuning;   // t->mu is held
         HIP_TRY(obuf.alloc(sizeof(double) * t->C, s), "scratch for occurrence losses");
         HIP_TRY(pbuf.alloc(ara::part_scratch_bytes(t->C, t->parts.P), s), "scratch for part images");
-        HIP_TRY(ara::launch_fold(t->elts, t->C, L, static_cast<double*>(obuf.p), tu, s), "fold");
-        HIP_TRY(ara::launch_part_fold(static_cast<const double*>(obuf.p), t->C, t->parts.P, pbuf.p, s, false),
-                "images");
+        if (t->sparse.chunk_off) {
+            // the forward's fold from the sparse pool (o, images and superblock counts)
+            HIP_TRY(ara::launch_fold_parts(t->sparse, t->C, L, nullptr, static_cast<double*>(obuf.p), t->parts.P,
+                                           pbuf.p, s),
+                    "fold");
+        } else {
+            HIP_TRY(ara::launch_fold(t->elts, t->C, L, static_cast<double*>(obuf.p), tu, s), "fold");
+            HIP_TRY(ara::launch_part_fold(static_cast<const double*>(obuf.p), t->C, t->parts.P, pbuf.p, s, false),
+                    "images");
+        }
     }
     HIP_TRY(ara::launch_adjoint(t->offsets, t->ids, t->elts, t->C, L, t->ck.S, t->ck.ylt, m, scratch.p, gm, gt,
-                                t->n_cu, s, use_parts ? &t->parts : nullptr, pbuf.p, t->n_trials),
+                                t->n_cu, s, use_parts ? &t->parts : nullptr, pbuf.p, t->n_trials,
+                                t->sparse.chunk_off ? &t->sparse : nullptr),
             "adjoint kernels");
     if (!dev) {
         std::vector<double> h(2 * P);

@@ -418,6 +418,6 @@ hipError_t launch_adjoint(const int64_t* offsets, const uint32_t* ids, const dou
                           int64_t C, const LayerArgs& L, const double* S, const double* ylt,
                           int64_t m, void* scratch, double* d_grad_mean, double* d_grad_tvar,
                           int n_cu, hipStream_t s, const PartLayout* parts, void* part_scratch,
-                          int64_t n_trials_total);
+                          int64_t n_trials_total, const SparsePool* sp);
 
 }  // namespace ara

@@ -36,6 +36,90 @@ struct AdjScratch {
     void* tail_scratch;
 };
 
+// The same numerators from the sparse ELT pool: one workgroup per chunk of
+// kSparseChunk events.  y(E) is rebuilt in LDS as the forward fold does it
+// (each ELT's entries added in layer order; an absent loss would add +0.0),
+// so it is bit-identical to the dense sum.  Each event with a weight then adds
+// its occurrence-term slopes, and each nonzero loss (E, l) of ELT j its
+// per-ELT slopes; an absent loss has l - R_j <= 0 and no slope, so the sparse
+// entries give the dense kernel's integer sums.
+constexpr int kSparseChunk = 4096;                  // events per chunk of the sparse pool
+__global__ __launch_bounds__(256) void catalogue_sparse_kernel(SparsePool sp, int64_t C, LayerArgs L,
+                                                               const uint64_t* __restrict__ w_mean,
+                                                               const uint64_t* __restrict__ w_tvar,
+                                                               long long* __restrict__ acc) {
+    __shared__ double ys[kSparseChunk];
+    __shared__ uint8_t act[kSparseChunk];           // inside the occurrence band, with a weight
+    __shared__ long long lacc[2 * kMaxP];
+    __shared__ int64_t rb[kMaxJ], re[kMaxJ];
+    const int t = threadIdx.x;
+    const int64_t chunk = blockIdx.x;
+    const int64_t e0 = chunk * kSparseChunk;
+    const int J = L.J;
+    const int P = 2 * J + 4;
+    for (int i = t; i < kSparseChunk; i += blockDim.x) ys[i] = 0.0;
+    for (int i = t; i < 2 * kMaxP; i += blockDim.x) lacc[i] = 0;
+    if (t < J) {
+        const int64_t key = static_cast<int64_t>(L.idx[t]) * sp.n_chunks + chunk;
+        rb[t] = sp.chunk_off[key];
+        re[t] = sp.chunk_off[key + 1];
+    }
+    __syncthreads();
+    for (int j = 0; j < J; ++j) {
+        const double R = L.R[j], Lim = L.Lim[j];
+        for (int64_t k = rb[j] + t; k < re[j]; k += blockDim.x) {
+            const int ev = sp.ev[k];
+            ys[ev] = ys[ev] + apply_terms(sp.val[k], R, Lim);
+        }
+        __syncthreads();
+    }
+    for (int i = t; i < kSparseChunk; i += blockDim.x) {
+        const int64_t e = e0 + i;
+        uint8_t a = 0;
+        if (e < C) {
+            const long long wm = static_cast<long long>(w_mean[e]);
+            const long long wv = static_cast<long long>(w_tvar[e]);
+            if (wm != 0 || wv != 0) {
+                const double to = ys[i] - L.occR;
+                if (to > L.occL) {
+                    add_i64(&lacc[2 * J + 1], wm);
+                    if (wv) add_i64(&lacc[kMaxP + 2 * J + 1], wv);
+                }
+                if ((to > 0.0) && (to < L.occL)) {
+                    add_i64(&lacc[2 * J], -wm);
+                    if (wv) add_i64(&lacc[kMaxP + 2 * J], -wv);
+                    a = 1;
+                }
+            }
+        }
+        act[i] = a;
+    }
+    __syncthreads();
+    for (int j = 0; j < J; ++j) {
+        const double R = L.R[j], Lim = L.Lim[j];
+        for (int64_t k = rb[j] + t; k < re[j]; k += blockDim.x) {
+            const int ev = sp.ev[k];
+            if (!act[ev]) continue;
+            const long long wm = static_cast<long long>(w_mean[e0 + ev]);
+            const long long wv = static_cast<long long>(w_tvar[e0 + ev]);
+            const double tj = sp.val[k] - R;
+            if (tj > 0.0 && tj < Lim) {
+                add_i64(&lacc[j], -wm);
+                if (wv) add_i64(&lacc[kMaxP + j], -wv);
+            }
+            if (tj > Lim) {
+                add_i64(&lacc[J + j], wm);
+                if (wv) add_i64(&lacc[kMaxP + J + j], wv);
+            }
+        }
+    }
+    __syncthreads();
+    for (int i = t; i < 2 * kMaxP; i += blockDim.x) {
+        const int q = i % kMaxP;
+        if (q < P - 2 && lacc[i] != 0) add_i64(&acc[i], lacc[i]);
+    }
+}
+
 __global__ __launch_bounds__(256) void mark_kernel(const double* __restrict__ elts, int64_t C, LayerArgs L,
                                                    uint8_t* __restrict__ mark, uint64_t* __restrict__ w_mean,
                                                    uint64_t* __restrict__ w_tvar, int with_mark) {
@@ -225,7 +309,8 @@ int64_t adjoint_scratch_bytes(int64_t C, int J) {
 hipError_t launch_adjoint(const int64_t* offsets, const uint32_t* ids, const double* elts, int64_t C,
                           const LayerArgs& L, const double* S, const double* ylt, int64_t m, void* scratch,
                           double* d_grad_mean, double* d_grad_tvar, int n_cu, hipStream_t s,
-                          const PartLayout* parts, void* part_scratch, int64_t n_trials_total) {
+                          const PartLayout* parts, void* part_scratch, int64_t n_trials_total,
+                          const SparsePool* sp) {
     AdjScratch a = carve(scratch, C);
     hipError_t err;
     const int64_t n = L.trial_count;
@@ -255,10 +340,15 @@ hipError_t launch_adjoint(const int64_t* offsets, const uint32_t* ids, const dou
                            ids, L, S, ylt, a.tail, a.mark, a.w_mean, a.w_tvar, a.acc);
         if ((err = hipGetLastError()) != hipSuccess) return err;
     }
-    int64_t gblocks = (C + 255) / 256;
-    if (gblocks > int64_t(n_cu) * 4) gblocks = int64_t(n_cu) * 4;
-    hipLaunchKernelGGL(catalogue_kernel, dim3(static_cast<uint32_t>(gblocks)), dim3(256), 0, s, elts, C, L,
-                       a.w_mean, a.w_tvar, a.acc);
+    if (sp && sp->chunk_off && sp->n_chunks == (C + kSparseChunk - 1) / kSparseChunk) {
+        hipLaunchKernelGGL(catalogue_sparse_kernel, dim3(static_cast<uint32_t>(sp->n_chunks)), dim3(256), 0, s, *sp,
+                           C, L, a.w_mean, a.w_tvar, a.acc);
+    } else {
+        int64_t gblocks = (C + 255) / 256;
+        if (gblocks > int64_t(n_cu) * 4) gblocks = int64_t(n_cu) * 4;
+        hipLaunchKernelGGL(catalogue_kernel, dim3(static_cast<uint32_t>(gblocks)), dim3(256), 0, s, elts, C, L,
+                           a.w_mean, a.w_tvar, a.acc);
+    }
     if ((err = hipGetLastError()) != hipSuccess) return err;
     hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(256), 0, s, a.acc, a.tail, 2 * L.J + 4, n, d_grad_mean,
                        d_grad_tvar);

@@ -673,26 +673,29 @@ def test_gradients_more_parts_than_xcds(ara):
     parts in turn (probe words and LDS counters rebuilt per part), the last
     part is ragged, each part has more nonzero events than the LDS counters
     hold (the rest are counted with global atomics), and a trial sub-range
-    cuts tiles.  Gradients are integer counts, so they must equal the
-    oracle's."""
+    cuts tiles; the plain layout's histogram pass is checked on the same
+    inputs.  Gradients are integer counts, so they must equal the oracle's."""
     C = 2_700_000
     yet = make_yet(900, 400.0, C, seed=101)
     pool = make_elt_pool(4, C, 300_000, seed=102)
-    tables = ara.create_tables(yet.offsets, yet.ids, pool.losses)
+    part = ara.create_tables(yet.offsets, yet.ids, pool.losses)
+    plain = ara.create_tables(yet.offsets, yet.ids, pool.losses, flags=ara.ARA_PLAIN_LAYOUT)
     # annual totals run 8.0e6-1.65e7: about 85% of the trials fall inside the
     # aggregate band, and the occurrence limit leaves the ELT limits active
     for begin, count in ((0, yet.n_trials), (300, 457)):
         layer = Layer(np.array([3, 1, 0], dtype=np.int32), 1500.0, 3.0e6, 8.6e6, 6.2e6, begin, count)
         spec = _spec(ara, layer, pool, yet)
         ref, S = oracle.run_layer(yet, pool, layer)
-        ara.run_layers(tables, [spec], flags=ara.ARA_CHECKPOINT_S)
-        for p in (0.99, 0.9):
-            gm, gt = ara.backward(tables, spec, p)
-            g = oracle.gradients(yet, pool, layer, p, ylt=ref, S=S)
-            assert np.array_equal(gm, g["grad_mean"]), (begin, p, gm, g["grad_mean"])
-            assert np.array_equal(gt, g["grad_tvar"]), (begin, p, gt, g["grad_tvar"])
-        assert np.count_nonzero(gm) >= gm.shape[0] - 1
-    tables.close()
+        for tables in (part, plain):
+            ara.run_layers(tables, [spec], flags=ara.ARA_CHECKPOINT_S)
+            for p in (0.99, 0.9):
+                gm, gt = ara.backward(tables, spec, p)
+                g = oracle.gradients(yet, pool, layer, p, ylt=ref, S=S)
+                assert np.array_equal(gm, g["grad_mean"]), (begin, p, gm, g["grad_mean"])
+                assert np.array_equal(gt, g["grad_tvar"]), (begin, p, gt, g["grad_tvar"])
+            assert np.count_nonzero(gm) >= gm.shape[0] - 1
+    part.close()
+    plain.close()
 
 
 def test_segment_padding_with_nonzero_last_events(ara):
