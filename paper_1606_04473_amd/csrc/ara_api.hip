@@ -1133,7 +1133,7 @@ ara_status ara_backward(ara_tables* t, const ara_layer* layer, double tvar_p, do
     const int P = 2 * L.J + 4;
     const bool dev = (flags & ARA_DEVICE_PTR) != 0;
     PoolBuffer scratch, staged;
-    HIP_TRY(scratch.alloc(ara::adjoint_scratch_bytes(t->C, L.J), s), "adjoint scratch");
+    HIP_TRY(scratch.alloc(ara::adjoint_scratch_bytes(t->C, L.J, L.trial_count), s), "adjoint scratch");
     double* gm = grad_mean;
     double* gt = grad_tvar;
     if (!dev) {

@@ -403,7 +403,7 @@ struct TailStats {
     int64_t c_eq;      // year losses equal to it
     int64_t m;
 };
-int64_t tail_stats_scratch_bytes();
+int64_t tail_stats_scratch_bytes(int64_t n);
 hipError_t launch_tail_stats(const double* ylt, int64_t n, int64_t m, void* scratch, TailStats* out,
                              int n_cu, hipStream_t s);
 
@@ -413,7 +413,7 @@ hipError_t launch_part_adjoint(const PartLayout& lay, int64_t N, const LayerArgs
 
 // adjoint; with `parts` (and `part_scratch` holding the forward's part images)
 // the histogram pass runs over the partitioned layout
-int64_t adjoint_scratch_bytes(int64_t C, int J);
+int64_t adjoint_scratch_bytes(int64_t C, int J, int64_t n);
 hipError_t launch_adjoint(const int64_t* offsets, const uint32_t* ids, const double* elts,
                           int64_t C, const LayerArgs& L, const double* S, const double* ylt,
                           int64_t m, void* scratch, double* d_grad_mean, double* d_grad_tvar,

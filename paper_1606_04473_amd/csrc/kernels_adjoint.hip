@@ -300,10 +300,10 @@ AdjScratch carve(void* base, int64_t C) {
 
 }  // namespace
 
-int64_t adjoint_scratch_bytes(int64_t C, int J) {
+int64_t adjoint_scratch_bytes(int64_t C, int J, int64_t n) {
     (void)J;
     const int64_t Ca = (C + 255) & ~int64_t(255);
-    return Ca * (2 * sizeof(uint64_t) + 1) + 2 * kMaxP * sizeof(long long) + 256 + tail_stats_scratch_bytes();
+    return Ca * (2 * sizeof(uint64_t) + 1) + 2 * kMaxP * sizeof(long long) + 256 + tail_stats_scratch_bytes(n);
 }
 
 hipError_t launch_adjoint(const int64_t* offsets, const uint32_t* ids, const double* elts, int64_t C,

@@ -8,8 +8,8 @@
 // workgroup from the previous histogram (the same data, so the same choice),
 // which saves a launch per pass; three histograms rotate so that the one
 // being cleared is never read or written in the same pass.  All requested
-// probabilities advance together.  For ara_risk_metrics the first two passes
-// run over all values; then one pass sums the values above each 24-bit
+// probabilities advance together.  For ara_risk_metrics (and the adjoint's
+// tail statistics) the first two passes run over all values; then one pass sums the values above each 24-bit
 // prefix and collects the keys inside it (a handful, unless many losses tie),
 // and a single workgroup finishes the selection over those candidates: up to
 // 256 of them are ranked directly against each other, more go through the
@@ -471,37 +471,7 @@ __global__ __launch_bounds__(256) void final_kernel(Scratch s, int n_probs, int 
 }
 
 // one workgroup: the final digit for the single tail count, into `out`
-__global__ __launch_bounds__(256) void tail_finish_kernel(Scratch s, TailStats* out) {
-    constexpr int last = kPasses - 1;
-    SelState st = s.st[(last & 1) * kMaxProbs];
-    st = choose_digit(s.hist + (last % 3) * kHistStride, st, last);
-    if (threadIdx.x == 0) {
-        out->v_bits = st.prefix;
-        out->m = st.m;
-        out->c_gt = 0;
-        out->c_eq = 0;
-    }
-}
 
-__global__ __launch_bounds__(256) void tail_count_kernel(const double* __restrict__ x, int64_t n,
-                                                         TailStats* out) {
-    const uint64_t v = out->v_bits;
-    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
-    unsigned long long gt = 0, eq = 0;
-    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) {
-        const uint64_t k = key_of(x[i]);
-        gt += k > v;
-        eq += k == v;
-    }
-    for (int off = 32; off >= 1; off >>= 1) {
-        gt += __shfl_xor(gt, off, kWave);
-        eq += __shfl_xor(eq, off, kWave);
-    }
-    if ((threadIdx.x & 63) == 0) {
-        if (gt) atomicAdd(reinterpret_cast<unsigned long long*>(&out->c_gt), gt);
-        if (eq) atomicAdd(reinterpret_cast<unsigned long long*>(&out->c_eq), eq);
-    }
-}
 
 }  // namespace
 
@@ -556,10 +526,86 @@ hipError_t launch_metrics(const double* ylt, int64_t n, const int64_t* m_host, i
 
 namespace ara {
 
-int64_t tail_stats_scratch_bytes() { return metrics_scratch_bytes(1, 0); }
+int64_t tail_stats_scratch_bytes(int64_t n) { return metrics_scratch_bytes(1, n); }
 
+namespace {
+
+// After collect_kernel for one tail count m: the m-th largest key, chosen
+// among the candidates inside its 24-bit prefix as finish_kernel does, the
+// count of year losses above it (those above the prefix, counted by
+// collect_kernel, plus the candidates above it) and the count equal to it
+// (all of them are candidates).  One workgroup.
+__global__ __launch_bounds__(256) void tail_select_kernel(Scratch s, int n_tail_part, TailStats* out) {
+    __shared__ __attribute__((aligned(16))) uint32_t hist[kBins];
+    __shared__ uint64_t keys[kDirect];
+    __shared__ uint64_t found;
+    __shared__ unsigned long long red[2][4];
+    SelState st = s.st[0];                          // written by the collect pass
+    const int64_t c = static_cast<int64_t>(s.ccount[0]);
+    const uint64_t* cand = s.cand;
+    if (c <= kDirect) {
+        for (int64_t j = threadIdx.x; j < c; j += blockDim.x) keys[j] = cand[j];
+        __syncthreads();
+        for (int64_t j = threadIdx.x; j < c; j += blockDim.x) {
+            const uint64_t kj = keys[j];
+            int64_t gt = 0, ge = 0;
+            for (int64_t i = 0; i < c; ++i) {
+                gt += keys[i] > kj;
+                ge += keys[i] >= kj;
+            }
+            if (gt < st.k && st.k <= ge) found = kj;          // every such thread writes the same key
+        }
+        __syncthreads();
+        st.prefix = found;
+        st.mask = ~uint64_t(0);
+        __syncthreads();
+    }
+    for (int pass = 2; pass < kPasses && c > kDirect; ++pass) {
+        for (int i = threadIdx.x; i < kBins; i += blockDim.x) hist[i] = 0;
+        __syncthreads();
+        const int shift = kShift[pass];
+        const uint64_t dmask = (uint64_t(1) << kBits[pass]) - 1;
+        for (int64_t j = threadIdx.x; j < c; j += blockDim.x) {
+            const uint64_t key = cand[j];
+            if ((key & st.mask) == st.prefix) atomicAdd(&hist[(key >> shift) & dmask], 1u);
+        }
+        __syncthreads();
+        st = choose_digit(hist, st, pass);
+    }
+    const uint64_t vk = st.prefix;
+    unsigned long long gt = 0, eq = 0;
+    for (int i = threadIdx.x; i < n_tail_part; i += blockDim.x)
+        gt += static_cast<unsigned long long>(s.part_cnt[kSumBlocks + i]);
+    for (int64_t j = threadIdx.x; j < c; j += blockDim.x) {
+        const uint64_t key = cand[j];
+        gt += key > vk;
+        eq += key == vk;
+    }
+    for (int off = 32; off >= 1; off >>= 1) {
+        gt += __shfl_xor(gt, off, kWave);
+        eq += __shfl_xor(eq, off, kWave);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        red[0][threadIdx.x >> 6] = gt;
+        red[1][threadIdx.x >> 6] = eq;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        out->v_bits = vk;
+        out->m = st.m;
+        out->c_gt = static_cast<int64_t>(red[0][0] + red[0][1] + red[0][2] + red[0][3]);
+        out->c_eq = static_cast<int64_t>(red[1][0] + red[1][1] + red[1][2] + red[1][3]);
+    }
+}
+
+}  // namespace
+
+// the m-th largest year loss with the counts above and at it: the selection of
+// launch_metrics (two 12-bit passes, the candidates inside the 24-bit prefix,
+// one workgroup over them), five launches
 hipError_t launch_tail_stats(const double* ylt, int64_t n, int64_t m, void* scratch, TailStats* out,
                              int n_cu, hipStream_t st) {
+    (void)n_cu;
     Scratch s = carve(scratch, 1);
     MArgs ma{};
     ma.m[0] = m;
@@ -569,17 +615,17 @@ hipError_t launch_tail_stats(const double* ylt, int64_t n, int64_t m, void* scra
     int hblocks = static_cast<int>((n + 2047) / 2048);
     if (hblocks > kSumBlocks) hblocks = kSumBlocks;
     if (hblocks < 1) hblocks = 1;
-    for (int pass = 0; pass < kPasses; ++pass) {
+    for (int pass = 0; pass < 2; ++pass) {
         hipLaunchKernelGGL(histogram_kernel, dim3(hblocks), dim3(256), sizeof(uint32_t) * kBins, st, ylt, n, s, ma,
                            1, pass, 0);
         if ((err = hipGetLastError()) != hipSuccess) return err;
     }
-    hipLaunchKernelGGL(tail_finish_kernel, dim3(1), dim3(256), 0, st, s, out);
+    int tblocks = static_cast<int>((n + 1023) / 1024);
+    if (tblocks > kSumBlocks) tblocks = kSumBlocks;
+    if (tblocks < 1) tblocks = 1;
+    hipLaunchKernelGGL(collect_kernel, dim3(tblocks), dim3(256), 0, st, ylt, n, s, 1);
     if ((err = hipGetLastError()) != hipSuccess) return err;
-    int cblocks = static_cast<int>((n + 1023) / 1024);
-    if (cblocks > 2 * n_cu) cblocks = 2 * n_cu;
-    if (cblocks < 1) cblocks = 1;
-    hipLaunchKernelGGL(tail_count_kernel, dim3(cblocks), dim3(256), 0, st, ylt, n, out);
+    hipLaunchKernelGGL(tail_select_kernel, dim3(1), dim3(256), 0, st, s, tblocks, out);
     return hipGetLastError();
 }
 
