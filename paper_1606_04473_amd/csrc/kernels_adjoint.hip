@@ -217,11 +217,25 @@ __global__ __launch_bounds__(256) void agg_counts_kernel(LayerArgs L, const doub
         r_tvar += __shfl_xor(r_tvar, off, kWave);
         l_tvar += __shfl_xor(l_tvar, off, kWave);
     }
+    // one set of device atomics per workgroup: every workgroup adds to the
+    // same four counters, so per-wave atomics would queue on them
+    __shared__ long long red[4][4];
+    const int w = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) {
-        if (r_mean) add_i64(&acc[P - 2], r_mean);
-        if (l_mean) add_i64(&acc[P - 1], l_mean);
-        if (r_tvar) add_i64(&acc[kMaxP + P - 2], r_tvar);
-        if (l_tvar) add_i64(&acc[kMaxP + P - 1], l_tvar);
+        red[w][0] = r_mean;
+        red[w][1] = l_mean;
+        red[w][2] = r_tvar;
+        red[w][3] = l_tvar;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        long long v[4] = {0, 0, 0, 0};
+        for (int i = 0; i < static_cast<int>(blockDim.x >> 6); ++i)
+            for (int q = 0; q < 4; ++q) v[q] += red[i][q];
+        if (v[0]) add_i64(&acc[P - 2], v[0]);
+        if (v[1]) add_i64(&acc[P - 1], v[1]);
+        if (v[2]) add_i64(&acc[kMaxP + P - 2], v[2]);
+        if (v[3]) add_i64(&acc[kMaxP + P - 1], v[3]);
     }
 }
 
@@ -324,7 +338,7 @@ hipError_t launch_adjoint(const int64_t* offsets, const uint32_t* ids, const dou
     if ((err = hipGetLastError()) != hipSuccess) return err;
     if (parts && parts->P > 0 && part_scratch) {
         int64_t ab = (n + 255) / 256;
-        if (ab > int64_t(n_cu) * 4) ab = int64_t(n_cu) * 4;
+        if (ab > int64_t(n_cu)) ab = int64_t(n_cu);
         if (ab < 1) ab = 1;
         hipLaunchKernelGGL(agg_counts_kernel, dim3(static_cast<uint32_t>(ab)), dim3(256), 0, s, L, S, ylt, a.tail,
                            a.acc);
