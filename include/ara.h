@@ -2,10 +2,10 @@
  * ara.h -- C ABI of the MI355X (gfx950) Aggregate Risk Analysis library.
  *
  * The analysis (Prades, Varghese, Reano, Silla, "Multi-Tenant Virtual GPUs
- * for Optimising Performance of a Financial Risk Application", Section III)
+ * for Optimising Performance of a Financial Risk Application", Section IV)
  * maps a Year Event Table (YET, Eq. 1) and a set of Event Loss Tables (ELT,
  * Eq. 2) grouped into layers (Eq. 3) to a Year Loss Table (YLT): one loss per
- * trial, from which PML and TVaR are derived (Section III-A, end).
+ * trial, from which PML and TVaR are derived (Section IV-A, end).
  *
  * Per trial t, event occurrence d and layer ELT j (Algorithm 3):
  *     x_j  = clamp(ELT_j[E_{t,d}]; R_j, Lim_j)          per-ELT terms
@@ -50,7 +50,7 @@ typedef int32_t ara_status;
 #define ARA_ERR_INVALID_ARG      1  /* malformed argument: NULL, negative size, NaN term, p outside (0,1), bad CSR */
 #define ARA_ERR_OUT_OF_RANGE     2  /* an event ID >= catalogue size, or an ELT index outside the pool */
 #define ARA_ERR_BUFFER_TOO_SMALL 3  /* an output capacity is below what the call writes */
-#define ARA_ERR_NO_MEMORY        4  /* device allocation failed, or the footprint exceeds the set budget */
+#define ARA_ERR_NO_MEMORY        4  /* a device or pinned-host allocation failed */
 #define ARA_ERR_DEVICE           5  /* a HIP runtime error; the HIP message is in ara_last_error() */
 #define ARA_ERR_NOT_READY        6  /* ara_backward without a matching checkpointed forward */
 #define ARA_ERR_UNSUPPORTED      7  /* a valid request this build does not handle (e.g. J > ARA_MAX_LAYER_ELTS) */
@@ -118,7 +118,7 @@ typedef struct ara_layer {
 } ara_layer;
 
 /*
- * A program (Section III-A): the layers it covers, in order.  `layers` is
+ * A program (Section IV-A): the layers it covers, in order.  `layers` is
  * host memory holding n_layers entries.
  */
 typedef struct ara_program {
@@ -169,7 +169,7 @@ typedef struct ara_tuning {
  *                  non-decreasing, offsets[n_trials] == n_events.
  *   event_ids      uint32[n_events], catalogue indices < catalogue_size.
  *   elt_losses     float64[n_elts][catalogue_size], row-major dense
- *                  direct-access tables (Section III-B); 0.0 = no loss.
+ *                  direct-access tables (Section IV-B); 0.0 = no loss.
  *                  Finite and >= 0.
  *   flags          ARA_DEVICE_PTR: the three arrays are device memory.
  *                  ARA_PLAIN_LAYOUT: skip the catalogue-partitioned copy.
@@ -232,7 +232,7 @@ ara_status ara_run_layers(ara_tables* tables, const ara_layer* layers, int32_t n
                           double* ylt, int64_t ylt_capacity, uint32_t flags, void* stream);
 
 /*
- * ara_risk_metrics -- the portfolio risk metrics named in Section III-A
+ * ara_risk_metrics -- the portfolio risk metrics named in Section IV-A
  * (PML, TVaR), plus the mean annual loss, from one layer's YLT.
  *
  *   ylt        float64[n_trials], values >= 0 (as produced by ara_run_layers);
@@ -242,10 +242,8 @@ ara_status ara_run_layers(ara_tables* tables, const ara_layer* layers, int32_t n
  *   mean_out   1 double; pml_out, tvar_out n_probs doubles each; host
  *              memory, or device memory with ARA_DEVICE_PTR.
  *
- * With m = ceil(n_trials * (1 - p)) -- p read as the short decimal it
- * approximates, so a product within 1e-9 relative of an integer is that
- * integer -- clamped to [1, n_trials]: PML_p is the m-th largest year loss
- * and TVaR_p the mean of the m largest.  Sums are accumulated in
+ * With m = ara_tail_count(n_trials, p) (below): PML_p is the m-th largest
+ * year loss and TVaR_p the mean of the m largest.  Sums are accumulated in
  * double-double and rounded once.  Errors: ARA_ERR_INVALID_ARG for
  * n_trials < 1 or p outside (0, 1).
  */
@@ -303,7 +301,7 @@ ara_status ara_debug_lookups(ara_tables* tables, const ara_layer* layer, int64_t
 
 /*
  * ara_run_portfolio -- Algorithm 1: for each program of the portfolio PF
- * (Section III-A), for each of its layers, the YET split into n_splits
+ * (Section IV-A), for each of its layers, the YET split into n_splits
  * contiguous trial ranges YET_i, each analysed as its own launch sequence,
  * and the layer's YLT populated from the parts.  The paper gives no rule for
  * combining layers; a program's year loss is read as the per-trial sum of
@@ -330,7 +328,7 @@ ara_status ara_run_portfolio(ara_tables* tables, const ara_program* programs, in
 
 /*
  * ara_event_nets -- per-event net losses of one layer, the cumulative form of
- * the aggregate terms (Section III-B: the aggregate terms act on the
+ * the aggregate terms (Section IV-B: the aggregate terms act on the
  * cumulative loss of the trial).  For each trial t of the layer and its
  * events d = 1..K_t in storage (time) order, with S_d the running total of
  * the occurrence losses o and A_d = clamp(S_d; AggR, AggL), A_0 =
@@ -375,6 +373,18 @@ ara_status ara_kernel_stats(ara_tables* tables, int32_t kernel, int64_t* launche
 /* Launch-shape knobs used by later calls on these tables (NULL resets). */
 ara_status ara_set_tuning(ara_tables* tables, const ara_tuning* tuning);
 ara_status ara_get_tuning(const ara_tables* tables, ara_tuning* tuning);
+
+/*
+ * ara_tail_count -- the number m of largest year losses that PML_p and
+ * TVaR_p are taken over (Section IV-A names both metrics without defining
+ * them).  m = ceil(n_trials * (1 - p)) with p read as the decimal it was
+ * written as: the shortest decimal string that converts back to the same
+ * double, taken exactly (so p = 0.99 gives m = 10000 for 10^6 trials, and
+ * p = 0.989999999999 gives 10001), then clamped to [1, n_trials].  Host
+ * only; needs no device.  ARA_ERR_INVALID_ARG for n_trials < 1, p outside
+ * (0, 1) or m NULL.  ara_risk_metrics and ara_backward use this m.
+ */
+ara_status ara_tail_count(int64_t n_trials, double p, int64_t* m);
 
 /* Number of compute units and the device index of the tables' device. */
 ara_status ara_device_info(int32_t* n_cu, int32_t* device);

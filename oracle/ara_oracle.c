@@ -4,7 +4,7 @@
  * baseline call it; the GPU library never does.
  *
  * Plain FP64 C, written from the paper's description of the analysis
- * (Section III-B, Algorithm 3 and the term definitions that follow it):
+ * (Section IV-B, Algorithm 3 and the term definitions that follow it):
  *
  *   for every trial T of the Year Event Table (Eq. 1), in storage order
  *     for every event E of T, in ascending time-stamp order
@@ -204,7 +204,7 @@ int ara_oracle_run_layer(const int64_t* offsets, int64_t n_trials,
 
 /*
  * Per-event net losses: the aggregate terms act on the trial's cumulative
- * loss (Section III-B), so after the d-th event of a trial (time order) the
+ * loss (Section IV-B), so after the d-th event of a trial (time order) the
  * recovered amount is A_d = clamp(S_d; AggR, AggL) with S_d the sum of the
  * first d occurrence losses, and the d-th event adds A_d - A_{d-1}, with
  * A_0 = clamp(0; AggR, AggL).  Each S_d is the exact running sum rounded once.

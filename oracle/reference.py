@@ -1,14 +1,14 @@
 """Python face of the CPU oracle -- TEST INFRASTRUCTURE ONLY.
 
 Three independent renderings of the same definition (Algorithm 3 with the
-term definitions of Section III-B) live here:
+term definitions of Section IV-B) live here:
 
 * ``run_layer``        -- the C oracle (ara_oracle.c), literal loop nest;
 * ``run_layer_python`` -- pure-Python loops with math.fsum, for tiny cases;
 * ``run_layer_numpy``  -- NumPy elementwise ops over the catalogue, then a
   per-trial sum; a second formulation written independently of the C code.
 
-The risk metrics (Section III-A names PML and TVaR without defining them)
+The risk metrics (Section IV-A names PML and TVaR without defining them)
 follow the return-period reading: m = ceil(N (1 - p)) with p read as the
 decimal it was written as; PML_p is the m-th largest year loss; TVaR_p is the
 mean of the m largest.
@@ -19,7 +19,7 @@ from __future__ import annotations
 import ctypes
 import math
 import os
-from decimal import Decimal, localcontext
+from fractions import Fraction
 from typing import List, Sequence, Tuple
 
 import numpy as np
@@ -125,7 +125,7 @@ def run_layer(yet, pool, layer, sum_mode: str = "exact", threads: int = 0):
 
 def portfolio(yet, pool, programs, threads: int = 0):
     """Year losses of a portfolio (Algorithm 1's loops over programs and their
-    layers, Section III-A), computed without any split of the YET.
+    layers, Section IV-A), computed without any split of the YET.
 
     ``programs`` is a list of programs, each a list of layers over the same
     trials.  Returns (layer_ylt [n_layers][n], program_ylt [n_programs][n],
@@ -155,7 +155,7 @@ def portfolio(yet, pool, programs, threads: int = 0):
 
 
 def event_nets(yet, pool, layer, threads: int = 0) -> np.ndarray:
-    """Per-event net losses of ``layer`` (Section III-B: the aggregate terms act
+    """Per-event net losses of ``layer`` (Section IV-B: the aggregate terms act
     on the trial's cumulative loss), via the C oracle.
 
     For the d-th event of a trial, A_d = clamp(S_d; AggR, AggL) with S_d the
@@ -280,8 +280,10 @@ def occurrence_catalogue(pool, layer):
 
 
 def lookups(yet, pool, layer, trial: int):
-    """Event IDs of a trial and the raw ELT losses looked up for them, [K][J]
-    (direct access, Section III-B).  Pinned by construction of the tables."""
+    """Event IDs of a trial in storage (time) order and the raw ELT losses
+    looked up for them: losses[k][j] = ELT_{elt_index[j]}[ids[k]] (direct
+    access, Section IV-B), shape [K][J].  Pinned by the golden tables (ids
+    and losses of hand-built trials, written out by hand)."""
     ids = np.asarray(yet.trial(trial), dtype=np.uint32)
     idx = np.asarray(layer.elt_index, dtype=np.int64)
     losses = pool.losses[idx][:, ids.astype(np.int64)].T.copy()
@@ -294,18 +296,20 @@ def lookups(yet, pool, layer, trial: int):
 
 def tail_count(n: int, p: float) -> int:
     """m = ceil(n (1 - p)) with p taken as the decimal it was written as
-    (its shortest round-trip representation), clamped to [1, n].
+    (its shortest round-trip representation, repr), in exact rational
+    arithmetic, clamped to [1, n].
 
-    Pinned by: hand values (N=1e6: m=10000 at 0.99, 4000 at 0.996)."""
+    Pinned by hand values: N=1e6 gives m=10000 at 0.99 and 4000 at 0.996
+    (where the FP64 product would give 10001), 10001 at 0.989999999999 (where
+    snapping to the nearest integer would give 10000), 3 for N=3 at 1/3 and
+    2 at 2/3 (their repr digits leave a remainder above the integer)."""
     if not (0.0 < p < 1.0):
         raise ValueError("p must lie in (0, 1)")
     if n < 1:
         raise ValueError("need at least one trial")
-    with localcontext() as ctx:
-        ctx.prec = 60
-        q = Decimal(repr(float(p)))
-        m = (Decimal(n) * (Decimal(1) - q)).to_integral_value(rounding="ROUND_CEILING")
-    return int(min(max(int(m), 1), n))
+    q = Fraction(repr(float(p)))
+    m = math.ceil(n * (1 - q))
+    return int(min(max(m, 1), n))
 
 
 def risk_metrics(ylt: np.ndarray, probs: Sequence[float]):

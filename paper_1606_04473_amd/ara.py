@@ -51,7 +51,7 @@ EXPORTED = (
     "ara_last_error", "ara_status_string", "ara_table_bytes", "ara_footprint", "ara_debug_lookups",
     "ara_event_nets", "ara_run_portfolio",
     "ara_read_checkpoints", "ara_set_tuning", "ara_get_tuning", "ara_device_info",
-    "ara_kernel_stats", "ara_create_yet",
+    "ara_kernel_stats", "ara_create_yet", "ara_tail_count",
 )
 
 
@@ -158,6 +158,8 @@ def lib():
     L.ara_kernel_stats.restype = i32
     L.ara_device_info.argtypes = [ctypes.POINTER(i32), ctypes.POINTER(i32)]
     L.ara_device_info.restype = i32
+    L.ara_tail_count.argtypes = [i64, f64, ctypes.POINTER(i64)]
+    L.ara_tail_count.restype = i32
     _LIB = L
     return L
 
@@ -533,6 +535,13 @@ def device_info():
     d = ctypes.c_int32()
     _check(lib().ara_device_info(ctypes.byref(n), ctypes.byref(d)))
     return int(n.value), int(d.value)
+
+
+def tail_count(n_trials: int, p: float) -> int:
+    """The m that PML_p and TVaR_p are taken over (host only, no device)."""
+    m = ctypes.c_int64()
+    _check(lib().ara_tail_count(int(n_trials), float(p), ctypes.byref(m)))
+    return int(m.value)
 
 
 def status_string(status: int) -> str:

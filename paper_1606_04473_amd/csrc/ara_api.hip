@@ -5,6 +5,8 @@
 #include <cstdio>
 #include <cstring>
 #include <algorithm>
+#include <charconv>
+#include <cstdlib>
 #include <list>
 #include <new>
 #include <string>
@@ -192,14 +194,34 @@ bool same_layer(const ara::LayerArgs& a, const ara::LayerArgs& b) {
     return true;
 }
 
-// m = ceil(n (1 - p)), p read as the short decimal it approximates: a
-// product within 1e-9 relative of an integer is taken as that integer.
+// m = ceil(n (1 - p)) with p read as the decimal it was written as: the
+// shortest decimal string that converts back to the same double (what
+// std::to_chars produces), taken exactly.  With that string's digits D and
+// k decimal places, p = D / 10^k and m = n - floor(n D / 10^k), clamped to
+// [1, n].  n D < 2^63 * 10^17 < 2^120 fits in 128 bits; for k > 38 the
+// quotient is 0.  Requires 1 <= n and 0 < p < 1.
 int64_t tail_count(int64_t n, double p) {
-    const double q = (1.0 - p) * static_cast<double>(n);
-    const double r = std::nearbyint(q);
-    int64_t m;
-    if (std::fabs(q - r) <= 1e-9 * std::fmax(1.0, q)) m = static_cast<int64_t>(r);
-    else m = static_cast<int64_t>(std::ceil(q));
+    char buf[64];
+    const auto r = std::to_chars(buf, buf + sizeof(buf), p, std::chars_format::scientific);
+    *r.ptr = '\0';
+    // "d.ddde-XX" or "de-XX": mantissa digits, then the exponent
+    unsigned __int128 D = 0;
+    int nd = 0;
+    const char* c = buf;
+    for (; *c && *c != 'e'; ++c) {
+        if (*c == '.') continue;
+        D = D * 10u + static_cast<unsigned>(*c - '0');
+        ++nd;
+    }
+    const int e10 = (*c == 'e') ? std::atoi(c + 1) : 0;
+    const int k = (nd - 1) - e10;                   // p = D * 10^-k, k >= 1 since p < 1
+    unsigned __int128 q = 0;
+    if (k <= 38) {
+        unsigned __int128 pow10 = 1;
+        for (int i = 0; i < k; ++i) pow10 *= 10u;
+        q = (static_cast<unsigned __int128>(static_cast<uint64_t>(n)) * D) / pow10;
+    }
+    int64_t m = n - static_cast<int64_t>(q);
     if (m < 1) m = 1;
     if (m > n) m = n;
     return m;
@@ -385,6 +407,14 @@ const char* ara_status_string(ara_status s) {
         case ARA_ERR_UNSUPPORTED: return "ARA_ERR_UNSUPPORTED";
         default: return "ARA_ERR_UNKNOWN";
     }
+}
+
+ara_status ara_tail_count(int64_t n_trials, double p, int64_t* m) {
+    if (!m) return fail(ARA_ERR_INVALID_ARG, "m is NULL");
+    if (n_trials < 1) return fail(ARA_ERR_INVALID_ARG, "n_trials < 1");
+    if (!(p > 0.0 && p < 1.0)) return fail(ARA_ERR_INVALID_ARG, "p must lie in (0, 1)");
+    *m = tail_count(n_trials, p);
+    return ARA_OK;
 }
 
 ara_status ara_device_info(int32_t* n_cu, int32_t* device) {

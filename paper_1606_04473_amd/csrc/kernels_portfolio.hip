@@ -1,5 +1,5 @@
 // Program and portfolio year losses (Algorithm 1's outer loops, Section
-// III-A): per trial, the sum of the year losses of a program's layers, and
+// IV-A): per trial, the sum of the year losses of a program's layers, and
 // of every layer of the portfolio.
 //
 // The layers' YLTs lie row by row ([layer][trial]), so a thread per trial

@@ -53,8 +53,9 @@ __device__ __forceinline__ void occurrence_losses(const TrialPassArgs& a, const 
     if constexpr (LITERAL) {
         double y[4] = {0.0, 0.0, 0.0, 0.0};
         // ELT-outer over the lane's events: every lane of the wave reads the
-        // same ELT at the same time (the paper's "all threads within a block
-        // access the same ELT"); each event still sums its ELTs in layer order.
+        // same ELT at the same time, as the paper's kernel has a whole thread
+        // block work on one ELT at once (Section IV-B); each event still sums
+        // its ELTs in layer order.
         for (int j = 0; j < L.J; ++j) {
             const double* row = a.elts + static_cast<int64_t>(L.idx[j]) * a.C;
             const double R = L.R[j];

@@ -1,4 +1,4 @@
-"""Performance and energy model for multi-tenant deployments (Section V-E).
+"""Performance and energy model for multi-tenant deployments (Section V-F).
 
 Eq. 4:  total = T_transfer(g) + T_computation(g)
 Eq. 5:  T_computation(g) = ComputationTime_1pGPU / g        (perfect scaling)

@@ -338,7 +338,7 @@ def run_tenant_study(base, offsets, ids, library, n_tenants: int = 8, per_tenant
 
 # ---------------------------------------------------------------------------
 # one analysis split over v tenants: measured time and energy beside the
-# deployment model of Section V-E (Eqs. 4-10), fitted on one tenant
+# deployment model of Section V-F (Eqs. 4-10), fitted on one tenant
 # ---------------------------------------------------------------------------
 
 class PowerSampler:

@@ -102,3 +102,29 @@ def test_product_path_has_no_oracle_dependency():
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "from oracle" not in text, f
                 assert "ara_oracle" not in text, f
+
+
+def test_tail_count_matches_oracle(ara):
+    """The library's m (shortest decimal digits of p, exact integer arithmetic)
+    equals the oracle's (Python repr of p as an exact fraction) on hand-picked
+    and random probabilities over a range of trial counts."""
+    import oracle
+    rng = np.random.default_rng(20250)
+    probs = [0.99, 0.996, 0.989999999999, 0.9899999999999999, 0.5, 0.25, 0.75, 1.0 / 3.0, 2.0 / 3.0,
+             0.1, 0.2, 0.3, 0.7, 0.9, 0.95, 0.999, 0.9999, 0.99999999, 1e-300, 5e-324,
+             math.nextafter(1.0, 0.0), math.nextafter(0.99, 1.0), math.nextafter(0.99, 0.0),
+             0.1 + 0.2, 1e-17, 0.123456789012345678]
+    probs += [float(x) for x in rng.random(300)]
+    probs += [float(x) for x in 1.0 - 10.0 ** -rng.uniform(1, 16, 100)]
+    probs += [round(float(x), int(d)) for x, d in zip(rng.random(200), rng.integers(1, 13, 200))]
+    probs = [p for p in probs if 0.0 < p < 1.0]
+    sizes = [1, 2, 3, 4, 7, 10, 100, 997, 10_000, 1_000_000, 123_456_789, 10 ** 12, 2 ** 62,
+             2 ** 63 - 1]
+    for n in sizes:
+        for p in probs:
+            assert ara.tail_count(n, p) == oracle.tail_count(n, p), (n, p)
+    with pytest.raises(ara.AraError):
+        ara.tail_count(0, 0.5)
+    for bad in (0.0, 1.0, math.nan, -0.5, math.inf):
+        with pytest.raises(ara.AraError):
+            ara.tail_count(10, bad)

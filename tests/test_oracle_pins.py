@@ -449,14 +449,50 @@ def test_portfolio_reductions(small):
 # ---------------------------------------------------------------------------
 
 def test_tail_count_values():
-    assert oracle.tail_count(1_000_000, 0.99) == 10_000
+    """Hand-worked values of m = ceil(N (1 - p)) with p read as its decimal."""
+    assert oracle.tail_count(1_000_000, 0.99) == 10_000      # FP64 (1-p)*N is 10000.000000000009
     assert oracle.tail_count(1_000_000, 0.996) == 4_000
     assert oracle.tail_count(10_000, 0.99) == 100
     assert oracle.tail_count(4, 0.5) == 2
-    assert oracle.tail_count(3, 0.99) == 1
-    assert oracle.tail_count(7, 0.5) == 4
+    assert oracle.tail_count(3, 0.99) == 1                   # 0.03 -> 1
+    assert oracle.tail_count(7, 0.5) == 4                    # 3.5 -> 4
+    # 10^6 x 0.010000000001 = 10000.000001 -> 10001 (a 1e-9 snap would say 10000)
+    assert oracle.tail_count(1_000_000, 0.989999999999) == 10_001
+    # repr(1/3) = 0.3333333333333333: 3 x 0.6666666666666667 = 2.0000000000000001 -> 3
+    assert oracle.tail_count(3, 1.0 / 3.0) == 3
+    # repr(2/3) = 0.6666666666666666: 3 x 0.3333333333333334 = 1.0000000000000002 -> 2
+    assert oracle.tail_count(3, 2.0 / 3.0) == 2
+    assert oracle.tail_count(1, 0.999) == 1                  # clamped up to 1
+    assert oracle.tail_count(10, 1e-300) == 10               # 10 - 1e-299 -> 10
+    assert oracle.tail_count(2 ** 62, 0.75) == 2 ** 60       # exact at large N
     with pytest.raises(ValueError):
         oracle.tail_count(10, 1.0)
+    with pytest.raises(ValueError):
+        oracle.tail_count(0, 0.5)
+
+
+def test_lookups_golden_tables(golden_dir):
+    """oracle.lookups returns the trial's IDs in storage order and the raw
+    losses [event][ELT] in the layer's ELT order (values written out by hand
+    from the golden ELT rows)."""
+    g = json.load(open(os.path.join(golden_dir, "closed_form_cases.json")))
+    losses = np.array(g["elts"], dtype=np.float64)
+    pool = ELTPool(losses, np.array(g["elt_retention"]), np.array(g["elt_limit"]))
+    yet = make_tiny_yet([[1, 2, 6], [3], [], [6, 6, 2]], g["catalogue_size"])
+    both = Layer(np.array([0, 1], dtype=np.int32), 0.0, INF, 0.0, INF, 0, yet.n_trials)
+    rev = Layer(np.array([1, 0], dtype=np.int32), 0.0, INF, 0.0, INF, 0, yet.n_trials)
+    ids, got = oracle.lookups(yet, pool, both, 0)
+    assert ids.tolist() == [1, 2, 6]
+    assert got.tolist() == [[100.0, 0.0], [250.0, 100.0], [500.0, 1000.0]]
+    ids, got = oracle.lookups(yet, pool, rev, 0)
+    assert got.tolist() == [[0.0, 100.0], [100.0, 250.0], [1000.0, 500.0]]
+    ids, got = oracle.lookups(yet, pool, both, 1)
+    assert ids.tolist() == [3] and got.tolist() == [[40.0, 0.0]]
+    ids, got = oracle.lookups(yet, pool, both, 2)
+    assert ids.tolist() == [] and got.shape == (0, 2)
+    ids, got = oracle.lookups(yet, pool, both, 3)
+    assert ids.tolist() == [6, 6, 2]
+    assert got.tolist() == [[500.0, 1000.0], [500.0, 1000.0], [250.0, 100.0]]
 
 
 def test_metrics_on_permutations():

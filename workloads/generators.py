@@ -1,6 +1,6 @@
 """Seeded generators for Year Event Tables, Event Loss Tables and terms.
 
-Shapes follow the paper's description of its inputs (Section III-A): trials of
+Shapes follow the paper's description of its inputs (Section IV-A): trials of
 roughly 800-1500 time-ordered (event, timestamp) pairs (Eq. 1), direct-access
 ELTs holding 10k-30k event losses each (Eq. 2), layers covering 3-30 ELTs
 (Eq. 3).  The industrial data is not public; these draws stand in for it:
