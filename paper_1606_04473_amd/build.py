@@ -15,7 +15,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libara.so")
-SOURCES = ["ara_api.hip", "kernels_trial.hip", "kernels_parts.hip", "kernels_metrics.hip",
+SOURCES = ["ara_api.hip", "kernels_trial.hip", "kernels_parts.hip", "kernels_stream.hip", "kernels_metrics.hip",
            "kernels_adjoint.hip", "kernels_portfolio.hip"]
 ARCH = os.environ.get("ARA_OFFLOAD_ARCH", "gfx950")
 

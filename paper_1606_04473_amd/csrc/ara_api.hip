@@ -383,6 +383,31 @@ hipError_t upload_plan(ara::HostStage& st, const BatchPlan& b, const ara::Batche
     return hipEventRecord(st.done, s);
 }
 
+// The passes that write per-(part, trial) partial sums for a merge: the
+// streaming pass over the 16-bit part-major copy (default), or the XCD-affine
+// pass over the 32-bit partitioned copy (pass_variant 2, or tables without
+// the 16-bit copy).
+struct SplitPass {
+    const ara_tables* t;
+    bool stream;
+    SplitPass(const ara_tables* tt, const ara_tuning& tu) : t(tt), stream(tu.pass_variant == 0 && tt->stream.P > 0) {}
+    size_t partial_bytes(int64_t trials) const {
+        const int64_t n = trials > 0 ? trials : 1;
+        return stream ? static_cast<size_t>(ara::stream_partials_bytes(t->stream, n))
+                      : sizeof(double) * 2 * static_cast<size_t>(t->parts.P) * n;
+    }
+    hipError_t pass(const ara::LayerArgs& L, void* part_scratch, void* partials, hipStream_t s) const {
+        if (stream) return ara::launch_stream_pass(t->stream, t->C, L, part_scratch, t->parts.P, partials, t->n_cu, s);
+        return ara::launch_xcd_pass(t->parts, t->n_trials, t->C, L, part_scratch, static_cast<double*>(partials),
+                                    t->n_cu, s);
+    }
+    hipError_t combine(const ara::LayerArgs& L, const ara::LayerArgs* L_dev, const void* partials, double* ylt,
+                       double* S, hipStream_t s) const {
+        if (stream) return ara::launch_stream_combine(t->stream, L, L_dev, partials, ylt, S, s);
+        return ara::launch_xcd_combine(t->parts, L, L_dev, static_cast<const double*>(partials), ylt, S, s);
+    }
+};
+
 int query_cu_count(int device) {
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) != hipSuccess || prop.multiProcessorCount <= 0) return 256;
@@ -544,6 +569,14 @@ static ara_status create_impl(const int64_t* trial_offsets, int64_t n_trials, co
             return cleanup(hip_fail(e, "partitioned layout"));
         }
         t->bytes += t->parts.bytes;
+        e = ara::build_stream_layout(t->offsets, t->ids, n_trials, n_events, catalogue_size, t->n_cu, s, &t->stream);
+        if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) {
+            (void)hipGetLastError();
+            t->stream = ara::StreamLayout{};   // not enough memory for the 16-bit copy: 32-bit passes only
+        } else if (e != hipSuccess) {
+            return cleanup(hip_fail(e, "16-bit stream layout"));
+        }
+        t->bytes += t->stream.bytes;
     }
     *out = t;
     return ARA_OK;
@@ -559,6 +592,7 @@ void ara_destroy_tables(ara_tables* t) {
     free_checkpoints(t->ck);
     scratch_free_all(t->scratch);
     ara::free_part_layout(&t->parts);
+    ara::free_stream_layout(&t->stream);
     for (auto* g : t->graphs) free_graph(g);
     t->graphs.clear();
     stage_free(t->stage);
@@ -612,7 +646,7 @@ ara_status ara_set_tuning(ara_tables* t, const ara_tuning* tu) {
         v.part_lanes_per_trial != 32 && v.part_lanes_per_trial != 64)
         return fail(ARA_ERR_INVALID_ARG, "part_lanes_per_trial must be 8, 16, 32 or 64");
     if (v.schedule < 0 || v.schedule > 1) return fail(ARA_ERR_INVALID_ARG, "schedule must be 0 or 1");
-    if (v.pass_variant < 0 || v.pass_variant > 1) return fail(ARA_ERR_INVALID_ARG, "pass_variant must be 0 or 1");
+    if (v.pass_variant < 0 || v.pass_variant > 2) return fail(ARA_ERR_INVALID_ARG, "pass_variant must be 0, 1 or 2");
     std::lock_guard<std::mutex> g(t->mu);
     t->tuning = v;
     return ARA_OK;
@@ -636,7 +670,12 @@ ara_status ara_footprint(const ara_tables* t, const ara_layer* layers, int32_t n
     if (!(flags & ARA_LITERAL) && t->parts.P > 0) {
         int64_t most = 0;
         for (int i = 0; i < n_layers; ++i) most = std::max(most, layers[i].trial_count);
-        b += ara::part_scratch_bytes(t->C, t->parts.P) + 16 * int64_t(t->parts.P) * most;
+        ara_tuning tu;
+        {
+            std::lock_guard<std::mutex> g(const_cast<ara_tables*>(t)->mu);
+            tu = t->tuning;
+        }
+        b += ara::part_scratch_bytes(t->C, t->parts.P) + static_cast<int64_t>(SplitPass(t, tu).partial_bytes(most));
     }
     if (!(flags & ARA_DEVICE_PTR)) b += sizeof(double) * total;       // staged output
     if (flags & (ARA_CHECKPOINT_S | ARA_CHECKPOINT_STRIDE)) b += 2 * sizeof(double) * total;
@@ -682,12 +721,14 @@ ara_status ara_run_layers(ara_tables* t, const ara_layer* layers, int32_t n_laye
     }
     // the partitioned pass serves plain runs; stride checkpoints need time order
     const bool use_parts = !literal && t->parts.P > 0 && !(flags & ARA_CHECKPOINT_STRIDE);
-    // the XCD-affine pass (default) writes per-part partial sums; pass_variant 1
-    // selects the rank-based pass with the compact value array
-    const bool use_xcd = use_parts && tu.pass_variant == 0;
+    // the streaming pass (default) and the XCD-affine pass (pass_variant 2)
+    // write per-part partial sums; pass_variant 1 selects the rank-based pass
+    // with the compact value array
+    const bool use_xcd = use_parts && tu.pass_variant != 1;
+    const SplitPass split(t, tu);
     // several layers run as one persistent rank-based launch with pass_variant
-    // 1; with the XCD-affine pass (the default) they run one launch sequence
-    // per layer, which ARA_GRAPH captures and replays as a whole
+    // 1; with the streaming (default) or XCD-affine pass they run one launch
+    // sequence per layer, which ARA_GRAPH captures and replays as a whole
     const bool batched = n_layers > 1 && !(flags & ARA_PER_LAYER) && !literal && !ckpt && t->parts.P > 0 &&
                          tu.pass_variant == 1;
     const bool xgraph = (flags & ARA_GRAPH) && use_xcd && !ckpt;
@@ -700,7 +741,7 @@ ara_status ara_run_layers(ara_tables* t, const ara_layer* layers, int32_t n_laye
     if (use_xcd) {
         int64_t most = 0;
         for (int i = 0; i < n_layers; ++i) most = std::max(most, L[i].trial_count);
-        x_bytes = up(sizeof(double) * 2 * t->parts.P * (most > 0 ? most : 1));
+        x_bytes = up(split.partial_bytes(most));
     }
     ScratchLease lease(t->scratch_mu);
     lease.s = s;
@@ -751,7 +792,7 @@ ara_status ara_run_layers(ara_tables* t, const ara_layer* layers, int32_t n_laye
             most = std::max(most, L[i].trial_count);
         }
         const size_t la_bytes = up(sizeof(ara::LayerArgs) * n_layers);
-        const size_t xg_bytes = up(sizeof(double) * 2 * t->parts.P * (most > 0 ? most : 1));
+        const size_t xg_bytes = up(split.partial_bytes(most));
         const bool prof = (flags & ARA_PROFILE) != 0;
         std::lock_guard<std::mutex> g(t->stage_mu);
         ara::GraphEntry* ge = nullptr;
@@ -778,7 +819,7 @@ ara_status ara_run_layers(ara_tables* t, const ara_layer* layers, int32_t n_laye
             const ara::LayerArgs* dL = reinterpret_cast<const ara::LayerArgs*>(gb);
             double* go = reinterpret_cast<double*>(gb + la_bytes);
             void* gp = gb + la_bytes + o_bytes;
-            double* gx = reinterpret_cast<double*>(gb + la_bytes + o_bytes + p_bytes);
+            void* gx = gb + la_bytes + o_bytes + p_bytes;
             if ((e = upload(ge)) != hipSuccess || (e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal)) !=
                                                       hipSuccess) {
                 free_graph(ge);
@@ -787,9 +828,8 @@ ara_status ara_run_layers(ara_tables* t, const ara_layer* layers, int32_t n_laye
             hipError_t le = hipSuccess;
             for (int i = 0; i < n_layers && le == hipSuccess; ++i) {
                 le = ara::launch_fold_parts(t->sparse, t->C, L[i], dL + i, go, t->parts.P, gp, s);
-                if (le == hipSuccess) le = ara::launch_xcd_pass(t->parts, t->n_trials, t->C, L[i], gp, gx, t->n_cu, s);
-                if (le == hipSuccess)
-                    le = ara::launch_xcd_combine(t->parts, L[i], dL + i, gx, out + L[i].out_offset, nullptr, s);
+                if (le == hipSuccess) le = split.pass(L[i], gp, gx, s);
+                if (le == hipSuccess) le = split.combine(L[i], dL + i, gx, out + L[i].out_offset, nullptr, s);
             }
             e = hipStreamEndCapture(s, &ge->graph);
             if (le != hipSuccess || e != hipSuccess ||
@@ -895,13 +935,10 @@ ara_status ara_run_layers(ara_tables* t, const ara_layer* layers, int32_t n_laye
         }
         if (use_xcd) {
             KernelTimer kp(t, s, prof, ARA_KERNEL_TRIAL_PASS);
-            HIP_TRY(ara::launch_xcd_pass(t->parts, t->n_trials, t->C, L[i], pbuf.p, static_cast<double*>(xbuf.p),
-                                         t->n_cu, s),
-                    "XCD-affine trial pass");
+            HIP_TRY(split.pass(L[i], pbuf.p, xbuf.p, s), "trial pass");
             kp.done();
             KernelTimer kc(t, s, prof, ARA_KERNEL_COMBINE);
-            HIP_TRY(ara::launch_xcd_combine(t->parts, L[i], nullptr, static_cast<const double*>(xbuf.p), a.ylt, a.S, s),
-                    "partial sums merge");
+            HIP_TRY(split.combine(L[i], nullptr, xbuf.p, a.ylt, a.S, s), "partial sums merge");
             kc.done();
             continue;
         }
@@ -978,7 +1015,8 @@ ara_status ara_run_portfolio(ara_tables* t, const ara_program* programs, int32_t
         tu = t->tuning;
     }
     const bool use_parts = !literal && t->parts.P > 0;
-    const bool use_xcd = use_parts && tu.pass_variant == 0;
+    const bool use_xcd = use_parts && tu.pass_variant != 1;
+    const SplitPass split(t, tu);
     // split i covers [b(i), b(i + 1)): Algorithm 1's YET_i
     auto split_at = [&](int64_t i) { return begin + (n * i) / n_splits; };
     int64_t most = 0;
@@ -988,7 +1026,7 @@ ara_status ara_run_portfolio(ara_tables* t, const ara_program* programs, int32_t
     auto up = [](size_t v) { return (v + 255) & ~size_t(255); };
     const size_t o_bytes = literal ? 0 : up(sizeof(double) * t->C);
     const size_t p_bytes = use_parts ? up(static_cast<size_t>(ara::part_scratch_bytes(t->C, t->parts.P))) : 0;
-    const size_t x_bytes = use_xcd ? up(sizeof(double) * 2 * t->parts.P * most) : 0;
+    const size_t x_bytes = use_xcd ? up(split.partial_bytes(most)) : 0;
     const bool stage_layers = !dev_out || !out->layer_ylt;
     const size_t l_bytes = stage_layers ? up(sizeof(double) * n_layers * n) : 0;
     const size_t g_bytes = !dev_out && out->program_ylt ? up(sizeof(double) * n_programs * n) : 0;
@@ -1001,7 +1039,7 @@ ara_status ara_run_portfolio(ara_tables* t, const ara_program* programs, int32_t
     char* base = static_cast<char*>(lease.b->p);
     double* o_buf = reinterpret_cast<double*>(base);
     void* p_buf = base + o_bytes;
-    double* x_buf = reinterpret_cast<double*>(base + o_bytes + p_bytes);
+    void* x_buf = base + o_bytes + p_bytes;
     double* layer_rows = stage_layers ? reinterpret_cast<double*>(base + o_bytes + p_bytes + x_bytes) : out->layer_ylt;
     double* program_rows = nullptr;
     double* portfolio_row = nullptr;
@@ -1029,11 +1067,10 @@ ara_status ara_run_portfolio(ara_tables* t, const ara_program* programs, int32_t
             double* ylt_i = layer_rows + l * n + (Li.trial_begin - begin);
             if (use_xcd) {
                 KernelTimer kp(t, s, prof, ARA_KERNEL_TRIAL_PASS);
-                HIP_TRY(ara::launch_xcd_pass(t->parts, t->n_trials, t->C, Li, p_buf, x_buf, t->n_cu, s),
-                        "XCD-affine trial pass");
+                HIP_TRY(split.pass(Li, p_buf, x_buf, s), "trial pass");
                 kp.done();
                 KernelTimer kc(t, s, prof, ARA_KERNEL_COMBINE);
-                HIP_TRY(ara::launch_xcd_combine(t->parts, Li, nullptr, x_buf, ylt_i, nullptr, s), "partial sums merge");
+                HIP_TRY(split.combine(Li, nullptr, x_buf, ylt_i, nullptr, s), "partial sums merge");
                 kc.done();
             } else if (use_parts) {
                 KernelTimer kp(t, s, prof, ARA_KERNEL_TRIAL_PASS);

@@ -140,6 +140,50 @@ struct PartLayout {
     int64_t* tile_start = nullptr;  // [n_tiles + 1]
 };
 
+// Per-request part images, one per 2^18-event part of the catalogue, written
+// by launch_fold_parts at the start of the part scratch: u64 bitmap words of
+// o(E) != 0, a u16 rank per 128 events relative to its 4096-event
+// superblock, and the u32 global rank of each superblock.  The nonzero o(E)
+// themselves follow, in rank order (part_compact_values).
+constexpr int kImgShift = 18;
+constexpr int kImgWords = (1 << kImgShift) / 64;
+constexpr int kImgRank16 = (1 << kImgShift) / 128;
+constexpr int kImgBase32 = (1 << kImgShift) / 4096;
+constexpr int64_t kImgPartBytes = int64_t(kImgWords) * 8 + int64_t(kImgRank16) * 2 + int64_t(kImgBase32) * 4;
+double* part_compact_values(void* part_scratch, int P);
+
+// Second copy of the YET for the streaming pass (kernels_stream.hip): the
+// catalogue cut into parts of 2^16 events; per part, one contiguous stream of
+// 16-bit part-relative IDs holding, group of G consecutive trials after
+// group, each trial's events of that part in time order.  Groups start on
+// 16-byte boundaries (the gap holds 0xFFFF).
+constexpr int kStreamShift = 16;
+constexpr int kMaxStreamParts = 64;
+constexpr int kStreamGroupMax = 32;
+struct StreamLayout {
+    int P = 0;                      // stream parts; 0 = layout absent
+    int G = 0;                      // trials per group (<= kStreamGroupMax)
+    int64_t NG = 0;                 // groups: ceil(N / G)
+    int64_t length = 0;             // IDs, padding included
+    int64_t bytes = 0;
+    uint16_t* ids = nullptr;        // [length + 8 * 64]
+    int64_t* part_base = nullptr;   // [P + 1] first ID of each part's stream
+    uint32_t* gstart = nullptr;     // [P][NG + 1] group starts relative to the part's stream
+    uint16_t* gend = nullptr;       // [P][NG][32] end of trial i of the group, relative to the group start
+};
+hipError_t build_stream_layout(const int64_t* offsets, const uint32_t* ids, int64_t N, int64_t n_events, int64_t C,
+                               int n_cu, hipStream_t s, StreamLayout* out);
+void free_stream_layout(StreamLayout* L);
+// bytes of the per-(part, trial) partial sums of the streaming pass
+int64_t stream_partials_bytes(const StreamLayout& lay, int64_t trials);
+// the streaming pass: reads the part images and compact values that
+// launch_fold_parts wrote to part_scratch (n_img_parts 2^18-event parts), writes
+// per-(stream part, trial) partial sums; the combine merges them in part order
+hipError_t launch_stream_pass(const StreamLayout& lay, int64_t C, const LayerArgs& L, void* part_scratch,
+                              int n_img_parts, void* partials, int n_cu, hipStream_t s);
+hipError_t launch_stream_combine(const StreamLayout& lay, const LayerArgs& L, const LayerArgs* L_dev,
+                                 const void* partials, double* ylt, double* S, hipStream_t s);
+
 constexpr int kXcds = 8;           // gfx950 (MI355X): 8 XCDs, workgroups dispatched round-robin
 
 struct XcdPassArgs {
@@ -302,6 +346,7 @@ struct ara_tables {
     std::mutex mu;                // guards ck and tuning
     ara::CheckpointState ck;
     ara::PartLayout parts;
+    ara::StreamLayout stream;     // 16-bit part-major copy for the streaming pass
     std::mutex stage_mu;          // guards stage and graphs
     ara::HostStage stage;
     std::vector<ara::GraphEntry*> graphs;

@@ -38,7 +38,7 @@ constexpr int kSuperShift = 12;
 constexpr int kSuper = 1 << kSuperShift;                      // 4096 events per superblock
 constexpr int kBase32 = kPartSize / kSuper;                   // 64 u32
 constexpr int64_t kImgBytes = int64_t(kWords) * 8 + int64_t(kRank16) * 2 + int64_t(kBase32) * 4;
-static_assert(kImgBytes == 37120, "part image layout");
+static_assert(kImgBytes == 37120 && kImgBytes == kImgPartBytes && kPartShift == kImgShift, "part image layout");
 static_assert(kImgBytes % 16 == 0, "16-byte copies");
 constexpr int kTileMax = 256;                                 // trials per tile (LDS accumulators)
 constexpr int kTileAlign = 32;                                // tiles start on 128-byte boundaries
@@ -1464,6 +1464,8 @@ PartScratch carve_parts(void* scratch, int P) {
     return r;
 }
 }  // namespace
+
+double* part_compact_values(void* part_scratch, int P) { return carve_parts(part_scratch, P).compact; }
 
 // ---------------------------------------------------------------------------
 // per-event net losses (the cumulative form of the aggregate terms)

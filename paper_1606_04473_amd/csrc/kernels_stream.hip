@@ -1,0 +1,663 @@
+// Streaming trial pass over a 16-bit, part-major copy of the YET.
+//
+// Algorithm 3 reduces, after the per-request fold (o(E) for every catalogue
+// event: the per-ELT terms, the combination over ELTs and the occurrence
+// terms, which depend on the event alone), to S_t = sum of o(E) over the
+// events of trial t, then the aggregate terms.  Most o(E) are zero, so the
+// work per streamed event is one question -- is o(E) nonzero, and what is it
+// -- answered here entirely from LDS:
+//
+//  * the catalogue is cut into parts of 2^16 events.  At table creation the
+//    YET is copied part-major: for each part one contiguous stream holding,
+//    group of G consecutive trials after group, each trial's events of that
+//    part in time order, as 16-bit part-relative IDs.  Each group starts on
+//    a 16-byte boundary (the gap holds 0xFFFF), and the end of every trial
+//    inside its group is kept as a 16-bit offset.  The stream is half the
+//    bytes of the 32-bit IDs.
+//  * a workgroup (16 waves, one per CU) takes a contiguous run of (part,
+//    group) work items.  For its part it builds in LDS a byte per catalogue
+//    event -- 0 for o(E) = 0, else 1 + the event's rank among the nonzero
+//    events of its 128-event block -- plus the rank of each block's first
+//    nonzero event, and copies the part's first nonzero o(E) (in rank order)
+//    into the rest of its LDS.  One ID costs one address operation and one
+//    LDS byte read.
+//  * each wave streams one group per batch (two 16-byte loads per lane), the
+//    next batch in flight while this one is tested, and appends the hits in
+//    stream order to its LDS queue.  Lane i holds where trial i starts; the
+//    queue index of its first hit comes from the per-chunk hit masks.  At
+//    the end of the group, lanes 2t and 2t+1 sum trial t's queued losses in
+//    double-double, in queue order, so the result does not depend on timing.
+//  * each (part, trial) partial sum is written once (high part FP64, low part
+//    FP32); the combine adds a trial's partials in part order, rounds once and
+//    applies the aggregate terms.
+#include <cmath>
+#include <vector>
+
+#include "ara_internal.hpp"
+
+namespace ara {
+
+namespace {
+
+constexpr int kQSize = 1 << kStreamShift;       // catalogue events per stream part
+constexpr int kChunkIds = 8;                    // 16-bit IDs per 16-byte load
+constexpr int64_t kStreamPad = 512;             // readable 0xFFFF IDs after the stream
+
+__device__ __forceinline__ uint64_t stream_lanemask_lt() {
+    const int lane = threadIdx.x & 63;
+    return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+// ---------------------------------------------------------------------------
+// create-time layout
+// ---------------------------------------------------------------------------
+
+// cnt[t * P + q] = events of trial t in stream part q; one wave per trial
+__global__ __launch_bounds__(256) void stream_count_kernel(const int64_t* __restrict__ offsets,
+                                                           const uint32_t* __restrict__ ids, int64_t N, int P,
+                                                           int32_t* __restrict__ cnt) {
+    __shared__ int32_t c[4][kMaxStreamParts];
+    const int w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int64_t n_waves = (static_cast<int64_t>(gridDim.x) * blockDim.x) >> 6;
+    for (int64_t t = uniform_i64((static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6); t < N;
+         t += n_waves) {
+        for (int p = lane; p < P; p += 64) c[w][p] = 0;
+        __builtin_amdgcn_wave_barrier();
+        for (int64_t i = offsets[t] + lane; i < offsets[t + 1]; i += 64) atomicAdd(&c[w][ids[i] >> kStreamShift], 1);
+        __builtin_amdgcn_wave_barrier();
+        for (int p = lane; p < P; p += 64) cnt[t * P + p] = c[w][p];
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+// per (part, group) k = q * NG + g: the end of each of the group's trials
+// relative to the group start (slots past the group's trials repeat the
+// group's end), and the group's size padded to whole 16-byte chunks.  Flags
+// bit 0 when a group holds more than 65535 IDs of one part.
+__global__ __launch_bounds__(256) void stream_group_kernel(const int32_t* __restrict__ cnt, int64_t N, int P, int G,
+                                                           int64_t NG, uint16_t* __restrict__ gend,
+                                                           uint32_t* __restrict__ gsize, uint32_t* __restrict__ flag) {
+    const int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k >= static_cast<int64_t>(P) * NG) return;
+    const int q = static_cast<int>(k / NG);
+    const int64_t g = k - static_cast<int64_t>(q) * NG;
+    uint32_t run = 0;
+    for (int i = 0; i < kStreamGroupMax; ++i) {
+        const int64_t t = g * G + i;
+        if (i < G && t < N) run += static_cast<uint32_t>(cnt[t * P + q]);
+        gend[k * kStreamGroupMax + i] = static_cast<uint16_t>(run < 65535u ? run : 65535u);
+    }
+    if (run > 65535u) atomicOr(flag, 1u);
+    gsize[k] = (run + kChunkIds - 1) & ~static_cast<uint32_t>(kChunkIds - 1);
+}
+
+// per part (one workgroup each): exclusive scan of the padded group sizes;
+// flags bit 1 when a part's stream reaches 2^32 IDs
+__global__ __launch_bounds__(1024) void stream_scan_kernel(const uint32_t* __restrict__ gsize, int64_t NG,
+                                                           uint32_t* __restrict__ gstart,
+                                                           uint64_t* __restrict__ part_len,
+                                                           uint32_t* __restrict__ flag) {
+    __shared__ uint64_t tsum[1024];
+    const int q = blockIdx.x;
+    const uint32_t* src = gsize + static_cast<int64_t>(q) * NG;
+    uint32_t* dst = gstart + static_cast<int64_t>(q) * (NG + 1);
+    const int64_t per = (NG + 1023) / 1024;
+    const int64_t j0 = static_cast<int64_t>(threadIdx.x) * per;
+    uint64_t local = 0;
+    for (int64_t j = j0; j < j0 + per && j < NG; ++j) local += src[j];
+    tsum[threadIdx.x] = local;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const uint64_t add = static_cast<int>(threadIdx.x) >= off ? tsum[threadIdx.x - off] : 0ull;
+        __syncthreads();
+        tsum[threadIdx.x] += add;
+        __syncthreads();
+    }
+    uint64_t run = tsum[threadIdx.x] - local;
+    for (int64_t j = j0; j < j0 + per && j < NG; ++j) {
+        dst[j] = static_cast<uint32_t>(run);
+        run += src[j];
+    }
+    if (threadIdx.x == 1023) {
+        const uint64_t total = tsum[1023];
+        dst[NG] = static_cast<uint32_t>(total);
+        part_len[q] = total;
+        if (total >= (uint64_t(1) << 32) - 4096) atomicOr(flag, 2u);
+    }
+}
+
+__global__ void stream_fill_kernel(uint32_t* p, int64_t n, uint32_t v) {
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
+}
+
+// stable scatter of each trial's events into its segments of the part
+// streams, one wave per trial: for each 64 events, one ballot per distinct part
+__global__ __launch_bounds__(256) void stream_scatter_kernel(const int64_t* __restrict__ offsets,
+                                                             const uint32_t* __restrict__ ids, int64_t N, int P, int G,
+                                                             int64_t NG, const int64_t* __restrict__ part_base,
+                                                             const uint32_t* __restrict__ gstart,
+                                                             const uint16_t* __restrict__ gend,
+                                                             uint16_t* __restrict__ out) {
+    __shared__ int64_t cur[4][kMaxStreamParts];
+    const int w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int64_t n_waves = (static_cast<int64_t>(gridDim.x) * blockDim.x) >> 6;
+    for (int64_t t = uniform_i64((static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6); t < N;
+         t += n_waves) {
+        const int64_t g = t / G;
+        const int i = static_cast<int>(t - g * G);
+        for (int q = lane; q < P; q += 64) {
+            const int64_t k = static_cast<int64_t>(q) * NG + g;
+            cur[w][q] = part_base[q] + gstart[static_cast<int64_t>(q) * (NG + 1) + g] +
+                        (i ? gend[k * kStreamGroupMax + i - 1] : 0);
+        }
+        __builtin_amdgcn_wave_barrier();
+        const int64_t b = offsets[t], e = offsets[t + 1];
+        for (int64_t c = b; c < e; c += 64) {
+            const bool valid = c + lane < e;
+            const uint32_t id = valid ? ids[c + lane] : 0u;
+            const int pid = static_cast<int>(id >> kStreamShift);
+            uint64_t todo = __ballot(valid);
+            while (todo) {
+                const int leader = __builtin_ctzll(todo);
+                const int qq = __builtin_amdgcn_readlane(pid, leader);
+                const uint64_t m = __ballot(valid && pid == qq);
+                const int64_t at = cur[w][qq];
+                if (valid && pid == qq) out[at + __popcll(m & stream_lanemask_lt())] = static_cast<uint16_t>(id);
+                __builtin_amdgcn_wave_barrier();
+                if (lane == 0) cur[w][qq] = at + __popcll(m);
+                __builtin_amdgcn_wave_barrier();
+                todo &= ~m;
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// the pass
+// ---------------------------------------------------------------------------
+
+struct StreamPassArgs {
+    const uint16_t* ids;
+    const int64_t* part_base;
+    const uint32_t* gstart;
+    const uint16_t* gend;
+    const uint8_t* img;             // part images of the 2^18-event parts
+    const double* compact;          // nonzero o(E) in rank order
+    int64_t C;
+    int P;
+    int G;
+    int64_t NG;
+    int64_t g_lo, g_hi;             // groups holding the layer's trials
+    int64_t t_lo, t_hi;
+    double* part_hi;                // [P][t_hi - t_lo]
+    float* part_lo;
+    const uint16_t* pad;            // 16 readable bytes of 0xFFFF
+    int n_xcd;
+};
+
+// Inclusive prefix sum over the 64 lanes of a wave: four DPP row shifts, then
+// two row broadcasts carry the row totals.
+__device__ __forceinline__ uint32_t stream_wave_scan(uint32_t x) {
+    x += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(x), 0x111, 0xF, 0xF, false));
+    x += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(x), 0x112, 0xF, 0xF, false));
+    x += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(x), 0x114, 0xF, 0xF, false));
+    x += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(x), 0x118, 0xF, 0xF, false));
+    x += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(x), 0x142, 0xA, 0xF, false));
+    x += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(x), 0x143, 0xC, 0xF, false));
+    return x;
+}
+
+// the value held by the partner lane (lane ^ 1)
+__device__ __forceinline__ double stream_swap_pair(double v) {
+    const uint64_t b = __double_as_longlong(v);
+    const uint32_t lo = static_cast<uint32_t>(
+        __builtin_amdgcn_mov_dpp(static_cast<int>(static_cast<uint32_t>(b)), 0xB1, 0xF, 0xF, false));
+    const uint32_t hi = static_cast<uint32_t>(
+        __builtin_amdgcn_mov_dpp(static_cast<int>(static_cast<uint32_t>(b >> 32)), 0xB1, 0xF, 0xF, false));
+    return __longlong_as_double(static_cast<int64_t>((static_cast<uint64_t>(hi) << 32) | lo));
+}
+
+__global__ __launch_bounds__(1024) void stream_pass_kernel(StreamPassArgs a) {
+    constexpr int kU = 2;                                     // 16-byte loads per lane per batch
+    constexpr uint32_t kBatch = 64 * kChunkIds * kU;          // IDs per batch
+    constexpr int kQ = 1024;                                  // 16-bit queue entries per wave
+    constexpr int kInf = 0x3FFFFFFF;
+    static_assert(kQ >= static_cast<int>(kBatch), "a batch must fit an empty queue");
+    // LDS, one block: the byte map first (a byte's address is its event's
+    // part-relative ID), then the rank of each 128-event block's first nonzero
+    // event, the 16 hit queues, and as many of the part's nonzero o(E) as fit
+    constexpr uint32_t kBaseOff = kQSize;
+    constexpr uint32_t kQueueOff = kBaseOff + (kQSize / 128) * 2;
+    constexpr uint32_t kValOff = kQueueOff + 16 * kQ * 2;
+    constexpr int kCap = static_cast<int>((160 * 1024 - kValOff) / 8);
+    static_assert(kValOff % 16 == 0 && kCap > 0, "LDS layout");
+    __shared__ __attribute__((aligned(16))) uint8_t lds[kValOff + kCap * 8];
+    uint16_t* bases = reinterpret_cast<uint16_t*>(lds + kBaseOff);
+    double* vals = reinterpret_cast<double*>(lds + kValOff);
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+    uint16_t* q = reinterpret_cast<uint16_t*>(lds + kQueueOff) + wv * kQ;
+    const int pt = lane >> 1;                       // the trial of a group this lane sums (with its partner)
+    const int half = lane & 1;
+    const int G = a.G;
+    const int64_t count = a.t_hi - a.t_lo;
+
+    // the (part, group) work list, part-major; workgroup b runs on XCD b % n_xcd,
+    // and each XCD takes a contiguous share of the list
+    const int64_t NGr = a.g_hi - a.g_lo;
+    const int64_t n_items = static_cast<int64_t>(a.P) * NGr;
+    const int64_t n_wg = gridDim.x;
+    const int64_t per_x = n_wg / a.n_xcd;
+    const int64_t l = static_cast<int64_t>(blockIdx.x % a.n_xcd) * per_x + blockIdx.x / a.n_xcd;
+    int64_t it = l * n_items / n_wg;
+    const int64_t it_end = (l + 1) * n_items / n_wg;
+
+    while (it < it_end) {
+        const int pq = static_cast<int>(it / NGr);
+        const int64_t seg_end = min(it_end, static_cast<int64_t>(pq + 1) * NGr);
+        const int64_t ga = a.g_lo + (it - static_cast<int64_t>(pq) * NGr);
+        const int64_t gb = a.g_lo + (seg_end - static_cast<int64_t>(pq) * NGr);
+        it = seg_end;
+        // ---- the LDS image of stream part pq, from the part image of the
+        // 2^18-event part that holds it
+        const int ip = pq >> 2, is = pq & 3;
+        const uint8_t* gimg = a.img + static_cast<int64_t>(ip) * kImgPartBytes;
+        const uint64_t* gbm = reinterpret_cast<const uint64_t*>(gimg) + is * (kImgWords / 4);
+        const uint16_t* gr16 = reinterpret_cast<const uint16_t*>(gimg + int64_t(kImgWords) * 8) + is * (kImgRank16 / 4);
+        const uint32_t* gb32 = reinterpret_cast<const uint32_t*>(gimg + int64_t(kImgWords) * 8 + int64_t(kImgRank16) * 2) +
+                               is * (kImgBase32 / 4);
+        const uint32_t g0 = gb32[0];                // global rank of the part's first nonzero event
+        __syncthreads();
+        {
+            // byte map: thread i covers events 64i .. 64i+63 (one bitmap word)
+            const int i = threadIdx.x;
+            const uint64_t w = gbm[i];
+            uint32_t run = (i & 1) ? static_cast<uint32_t>(__popcll(gbm[i - 1])) : 0u;
+            uint32_t* dst = reinterpret_cast<uint32_t*>(lds + i * 64);
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                uint32_t pk = 0;
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const uint32_t bit = static_cast<uint32_t>(w >> (4 * k + b)) & 1u;
+                    run += bit;
+                    pk |= (bit ? run : 0u) << (8 * b);
+                }
+                dst[k] = pk;
+            }
+        }
+        if (threadIdx.x < kQSize / 128) {
+            const int k = threadIdx.x;
+            bases[k] = static_cast<uint16_t>(gb32[k >> 5] + gr16[k] - g0);
+        }
+        for (int k = threadIdx.x; k < kCap; k += blockDim.x) {
+            const int64_t gk = static_cast<int64_t>(g0) + k;
+            vals[k] = gk < a.C ? a.compact[gk] : 0.0;
+        }
+        __syncthreads();
+
+        // ---- this wave's groups [wa, wb) of the part
+        const int64_t n = gb - ga;
+        const int64_t wa = ga + wv * n / 16, wb = ga + (wv + 1) * n / 16;
+        if (wa >= wb) continue;
+        const uint16_t* ids = a.ids + a.part_base[pq];
+        const uint32_t* gs = a.gstart + static_cast<int64_t>(pq) * (a.NG + 1);
+        const uint16_t* ge = a.gend + static_cast<int64_t>(pq) * a.NG * kStreamGroupMax;
+        const double* gcompact = a.compact + g0;
+        double* out_hi = a.part_hi + static_cast<int64_t>(pq) * count;
+        float* out_lo = a.part_lo + static_cast<int64_t>(pq) * count;
+        // lane i: where trial i of group g starts; lanes >= G: the group's end
+        auto bounds = [&](int64_t g) -> uint32_t {
+            const int64_t gg = g < wb ? g : wb - 1;
+            const uint32_t s0 = gs[gg];
+            const int i = lane < kStreamGroupMax ? lane : kStreamGroupMax;
+            return i == 0 ? s0 : s0 + ge[gg * kStreamGroupMax + i - 1];
+        };
+        int64_t g = wa;
+        uint32_t B = bounds(g), B1 = bounds(g + 1), B2 = bounds(g + 2);
+        uint32_t rs = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(B), 0));
+        uint32_t re = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(B), kStreamGroupMax));
+        uint32_t c = rs;                            // first ID of the batch (a multiple of 8)
+        int qs = kInf;                              // lane i: queue index of trial i's first hit
+        int qn = 0;                                 // queue entries
+        double acc_hi = 0.0, acc_lo = 0.0;
+
+        auto load_batch = [&](uint32_t cb, uint32_t end, u32x4* v) {
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const uint32_t cu = cb + u * 64 * kChunkIds + lane * kChunkIds;
+                const uint16_t* src = cu < end ? ids + cu : a.pad;
+                v[u] = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(src));
+            }
+        };
+        // the batch after the one at c: the rest of this group, else the next group's first
+        auto load_next = [&](u32x4* v) {
+            if (c + kBatch < re) {
+                load_batch(c + kBatch, re, v);
+            } else {
+                const uint32_t n_rs = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(B1), 0));
+                const uint32_t n_re =
+                    static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(B1), kStreamGroupMax));
+                load_batch(n_rs, g + 1 < wb ? n_re : 0u, v);
+            }
+        };
+        // sum the queued hits: lanes 2t and 2t+1 take trial t's entries
+        // alternately, four in flight per lane
+        auto drain = [&]() {
+            int lo = __shfl(qs, pt), hi = __shfl(qs, pt + 1);
+            lo = lo < 0 ? 0 : (lo > qn ? qn : lo);
+            hi = hi < 0 ? 0 : (hi > qn ? qn : hi);
+            for (int j = lo + half; j < hi; j += 8) {
+                // four entries at once (slots past the trial's last reread entry j
+                // and add 0.0, whose sum is exact), each step's loads issued together
+                uint32_t e[4], rk[4];
+                double v[4];
+#pragma unroll
+                for (int r2 = 0; r2 < 4; ++r2) {
+                    const int jj = j + 2 * r2;
+                    e[r2] = q[jj < hi ? jj : j];
+                }
+                // rank among the part's nonzero events: the block's base plus the
+                // byte, which is 1 + the rank inside the block
+#pragma unroll
+                for (int r2 = 0; r2 < 4; ++r2) rk[r2] = static_cast<uint32_t>(bases[e[r2] >> 7]) + lds[e[r2]] - 1u;
+                // the LDS copy at a clamped rank, else the value from L2 (two
+                // loads of one address space each, no pointer select)
+#pragma unroll
+                for (int r2 = 0; r2 < 4; ++r2) v[r2] = vals[min(rk[r2], static_cast<uint32_t>(kCap - 1))];
+#pragma unroll
+                for (int r2 = 0; r2 < 4; ++r2)
+                    if (rk[r2] >= static_cast<uint32_t>(kCap)) v[r2] = gcompact[rk[r2]];
+#pragma unroll
+                for (int r2 = 0; r2 < 4; ++r2) dd_add(acc_hi, acc_lo, j + 2 * r2 < hi ? v[r2] : 0.0);
+            }
+            qs = qs == kInf ? kInf : qs - qn;
+            qn = 0;
+            __builtin_amdgcn_wave_barrier();
+        };
+        // test a batch against the byte map, append its hits to the queue in
+        // stream order, and note where each trial's hits start
+        auto process = [&](const u32x4* v) {
+            // Chunks past the group's end read padding or the next group's IDs;
+            // their hits are queued after the group's end boundary (lanes >= G
+            // note where it falls), so no trial sums them.
+            uint32_t m[kU];                         // bit w: ID w of the lane's chunk is a hit
+            uint32_t h[kU][8];                      // the same bits, one per register
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                uint32_t mm = 0;
+#pragma unroll
+                for (int d = 0; d < 4; ++d) {
+                    const uint32_t D = v[u][d];
+                    h[u][2 * d] = min(static_cast<uint32_t>(lds[D & 0xFFFFu]), 1u);
+                    h[u][2 * d + 1] = min(static_cast<uint32_t>(lds[D >> 16]), 1u);
+                    mm |= h[u][2 * d] << (2 * d);
+                    mm |= h[u][2 * d + 1] << (2 * d + 1);
+                }
+                m[u] = mm;
+            }
+            // hit counts per chunk, prefix-summed over the wave two chunks at a time
+            // (16-bit halves: at most 8 x 64 hits per load)
+            uint32_t pre[kU], tot = 0;
+            {
+                const uint32_t ca = static_cast<uint32_t>(__popc(m[0]));
+                const uint32_t cb = static_cast<uint32_t>(__popc(m[1]));
+                const uint32_t sc = stream_wave_scan(ca | (cb << 16));
+                const uint32_t tt = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(sc), 63));
+                pre[0] = (sc & 0xFFFFu) - ca;
+                pre[1] = (tt & 0xFFFFu) + (sc >> 16) - cb;
+                tot = (tt & 0xFFFFu) + (tt >> 16);
+            }
+            if (qn + static_cast<int>(tot) > kQ) drain();    // exact: a batch always fits an empty queue
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                uint8_t* at = reinterpret_cast<uint8_t*>(q + qn + pre[u]);   // LDS byte address of the next entry
+#pragma unroll
+                for (int w = 0; w < 8; ++w) {
+                    if (h[u][w]) *reinterpret_cast<uint16_t*>(at) = static_cast<uint16_t>(v[u][w >> 1] >> (16 * (w & 1)));
+                    at += h[u][w] << 1;
+                }
+            }
+            // trial starts inside this batch: the hits of the chunk before the
+            // start's position, plus the chunk's queue offset
+            const uint32_t rel = B - c;
+            const uint32_t k = rel >> 3;
+            const int src = static_cast<int>(k & 63u);
+            const uint32_t p0 = static_cast<uint32_t>(__shfl(static_cast<int>((pre[0] << 8) | m[0]), src));
+            const uint32_t p1 = static_cast<uint32_t>(__shfl(static_cast<int>((pre[1] << 8) | m[1]), src));
+            const uint32_t pk = (k >> 6) == 0 ? p0 : p1;
+            const uint32_t below = (pk & 0xFFu) & ((1u << (rel & 7u)) - 1u);
+            if (B >= c && rel < kBatch) qs = qn + static_cast<int>(pk >> 8) + __popc(below);
+            qn += static_cast<int>(tot);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        };
+        // after a batch: advance; at the end of the group drain the queue, write
+        // the partial sums and move to the next group (its first batch is in
+        // flight).  Returns false after the wave's last group.
+        auto step = [&]() -> bool {
+            c += kBatch;
+            if (c < re) return true;
+            drain();
+            dd_merge(acc_hi, acc_lo, stream_swap_pair(acc_hi), stream_swap_pair(acc_lo));
+            {
+                const double s_hi = acc_hi + acc_lo;          // renormalised: |lo| <= ulp(hi) / 2
+                const double s_lo = acc_lo - (s_hi - acc_hi);
+                const int64_t t = g * G + pt;
+                if (half == 0 && pt < G && t >= a.t_lo && t < a.t_hi) {
+                    out_hi[t - a.t_lo] = s_hi;
+                    out_lo[t - a.t_lo] = static_cast<float>(s_lo);
+                }
+            }
+            acc_hi = 0.0;
+            acc_lo = 0.0;
+            qs = kInf;
+            if (g + 1 >= wb) return false;
+            ++g;
+            B = B1;
+            B1 = B2;
+            B2 = bounds(g + 2);
+            rs = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(B), 0));
+            re = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(B), kStreamGroupMax));
+            c = rs;
+            return true;
+        };
+
+        // two register buffers in turn, so the next batch's loads stay in
+        // flight while this one is tested
+        u32x4 bufA[kU], bufB[kU];
+        load_batch(c, re, bufA);
+        for (;;) {
+            load_next(bufB);
+            process(bufA);
+            if (!step()) break;
+            load_next(bufA);
+            process(bufB);
+            if (!step()) break;
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void stream_combine_kernel(const double* __restrict__ part_hi,
+                                                             const float* __restrict__ part_lo, int P, int64_t count,
+                                                             double aggR, double aggL,
+                                                             const LayerArgs* __restrict__ L_dev,
+                                                             double* __restrict__ ylt, double* __restrict__ S_out) {
+    const int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k >= count) return;
+    if (L_dev) {                                    // terms from device memory (graph replays)
+        aggR = L_dev->aggR;
+        aggL = L_dev->aggL;
+    }
+    double hi = 0.0, lo = 0.0;
+    for (int p = 0; p < P; ++p)
+        dd_merge(hi, lo, part_hi[p * count + k], static_cast<double>(part_lo[p * count + k]));
+    const double S = hi + lo;
+    ylt[k] = apply_terms(S, aggR, aggL);
+    if (S_out) S_out[k] = S;
+}
+
+// trials per group: enough that the group's IDs fill whole batches of
+// 512-ID loads with little left over, given the mean IDs per (trial, part)
+int choose_group_trials(double lam) {
+    int best_g = kStreamGroupMax;
+    double best = 1e300;
+    for (int g = kStreamGroupMax; g >= 8; --g) {
+        const double mean = g * lam, sd = std::sqrt(mean > 0.0 ? mean : 0.0);
+        const double chunks = (mean + 2.5 * sd) / kChunkIds + 1.0;
+        const double loads = std::ceil(chunks / 64.0);
+        const double cost = (loads * 512.0 * 5.0 + 200.0) / g;
+        if (cost < best - 1e-9) {
+            best = cost;
+            best_g = g;
+        }
+    }
+    return best_g;
+}
+
+}  // namespace
+
+hipError_t build_stream_layout(const int64_t* offsets, const uint32_t* ids, int64_t N, int64_t n_events, int64_t C,
+                               int n_cu, hipStream_t s, StreamLayout* out) {
+    *out = StreamLayout{};
+    const int P = static_cast<int>((C + kQSize - 1) / kQSize);
+    if (N < 1 || P < 1 || P > kMaxStreamParts) return hipSuccess;      // layout not used
+    const int G = choose_group_trials(static_cast<double>(n_events) / (static_cast<double>(N) * P));
+    const int64_t NG = (N + G - 1) / G;
+    const int64_t n_grp = static_cast<int64_t>(P) * NG;
+    hipError_t e;
+    int32_t* cnt = nullptr;
+    uint32_t* gsize = nullptr;
+    uint64_t* plen = nullptr;
+    uint32_t* flag = nullptr;
+    std::vector<uint64_t> h_len(P);
+    std::vector<int64_t> h_base(P + 1);
+    uint32_t h_flag = 0;
+    int64_t blocks = (N + 3) / 4;
+    if (blocks > int64_t(n_cu) * 16) blocks = int64_t(n_cu) * 16;
+    if ((e = hipMalloc(&cnt, sizeof(int32_t) * N * P)) != hipSuccess) goto fail;
+    if ((e = hipMalloc(&gsize, sizeof(uint32_t) * n_grp)) != hipSuccess) goto fail;
+    if ((e = hipMalloc(&plen, sizeof(uint64_t) * P)) != hipSuccess) goto fail;
+    if ((e = hipMalloc(&flag, sizeof(uint32_t))) != hipSuccess) goto fail;
+    if ((e = hipMalloc(&out->gend, sizeof(uint16_t) * n_grp * kStreamGroupMax)) != hipSuccess) goto fail;
+    if ((e = hipMalloc(&out->gstart, sizeof(uint32_t) * P * (NG + 1))) != hipSuccess) goto fail;
+    if ((e = hipMalloc(&out->part_base, sizeof(int64_t) * (P + 1))) != hipSuccess) goto fail;
+    if ((e = hipMemsetAsync(flag, 0, sizeof(uint32_t), s)) != hipSuccess) goto fail;
+    hipLaunchKernelGGL(stream_count_kernel, dim3(static_cast<uint32_t>(blocks)), dim3(256), 0, s, offsets, ids, N, P,
+                       cnt);
+    if ((e = hipGetLastError()) != hipSuccess) goto fail;
+    hipLaunchKernelGGL(stream_group_kernel, dim3(static_cast<uint32_t>((n_grp + 255) / 256)), dim3(256), 0, s, cnt, N,
+                       P, G, NG, out->gend, gsize, flag);
+    if ((e = hipGetLastError()) != hipSuccess) goto fail;
+    hipLaunchKernelGGL(stream_scan_kernel, dim3(static_cast<uint32_t>(P)), dim3(1024), 0, s, gsize, NG, out->gstart,
+                       plen, flag);
+    if ((e = hipGetLastError()) != hipSuccess) goto fail;
+    if ((e = hipMemcpyAsync(h_len.data(), plen, sizeof(uint64_t) * P, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(&h_flag, flag, sizeof(uint32_t), hipMemcpyDeviceToHost, s)) != hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess)
+        goto fail;
+    if (h_flag) {                       // a group or a part too large for 16/32-bit offsets: not used
+        e = hipSuccess;
+        goto fail;
+    }
+    h_base[0] = 0;
+    for (int q = 0; q < P; ++q) h_base[q + 1] = h_base[q] + static_cast<int64_t>(h_len[q]);
+    out->length = h_base[P];
+    if ((e = hipMemcpyAsync(out->part_base, h_base.data(), sizeof(int64_t) * (P + 1), hipMemcpyHostToDevice, s)) !=
+        hipSuccess)
+        goto fail;
+    if ((e = hipMalloc(&out->ids, sizeof(uint16_t) * (out->length + kStreamPad))) != hipSuccess) goto fail;
+    {
+        const int64_t n32 = (out->length + kStreamPad) / 2;
+        int64_t fb = (n32 + 255) / 256;
+        if (fb > 8192) fb = 8192;
+        hipLaunchKernelGGL(stream_fill_kernel, dim3(static_cast<uint32_t>(fb)), dim3(256), 0, s,
+                           reinterpret_cast<uint32_t*>(out->ids), n32, 0xFFFFFFFFu);
+        if ((e = hipGetLastError()) != hipSuccess) goto fail;
+    }
+    hipLaunchKernelGGL(stream_scatter_kernel, dim3(static_cast<uint32_t>(blocks)), dim3(256), 0, s, offsets, ids, N, P,
+                       G, NG, out->part_base, out->gstart, out->gend, out->ids);
+    if ((e = hipGetLastError()) != hipSuccess) goto fail;
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) goto fail;
+    (void)hipFree(cnt);
+    (void)hipFree(gsize);
+    (void)hipFree(plen);
+    (void)hipFree(flag);
+    out->P = P;
+    out->G = G;
+    out->NG = NG;
+    out->bytes = static_cast<int64_t>(sizeof(uint16_t)) * (out->length + kStreamPad) +
+                 static_cast<int64_t>(sizeof(uint16_t)) * n_grp * kStreamGroupMax +
+                 static_cast<int64_t>(sizeof(uint32_t)) * P * (NG + 1) + static_cast<int64_t>(sizeof(int64_t)) * (P + 1);
+    return hipSuccess;
+fail:
+    if (cnt) (void)hipFree(cnt);
+    if (gsize) (void)hipFree(gsize);
+    if (plen) (void)hipFree(plen);
+    if (flag) (void)hipFree(flag);
+    free_stream_layout(out);
+    return e;
+}
+
+void free_stream_layout(StreamLayout* L) {
+    if (L->ids) (void)hipFree(L->ids);
+    if (L->part_base) (void)hipFree(L->part_base);
+    if (L->gstart) (void)hipFree(L->gstart);
+    if (L->gend) (void)hipFree(L->gend);
+    *L = StreamLayout{};
+}
+
+int64_t stream_partials_bytes(const StreamLayout& lay, int64_t trials) {
+    const int64_t n = static_cast<int64_t>(lay.P) * (trials > 0 ? trials : 1);
+    return static_cast<int64_t>(sizeof(double) + sizeof(float)) * n + 256;
+}
+
+hipError_t launch_stream_pass(const StreamLayout& lay, int64_t C, const LayerArgs& L, void* part_scratch,
+                              int n_img_parts, void* partials, int n_cu, hipStream_t s) {
+    if (L.trial_count <= 0) return hipSuccess;
+    if (lay.P <= 0 || (lay.P - 1) / 4 >= n_img_parts) return hipErrorInvalidValue;
+    StreamPassArgs a{};
+    a.ids = lay.ids;
+    a.part_base = lay.part_base;
+    a.gstart = lay.gstart;
+    a.gend = lay.gend;
+    a.img = static_cast<const uint8_t*>(part_scratch);
+    a.compact = part_compact_values(part_scratch, n_img_parts);
+    a.C = C;
+    a.P = lay.P;
+    a.G = lay.G;
+    a.NG = lay.NG;
+    a.t_lo = L.trial_begin;
+    a.t_hi = L.trial_begin + L.trial_count;
+    a.g_lo = a.t_lo / lay.G;
+    a.g_hi = (a.t_hi + lay.G - 1) / lay.G;
+    a.part_hi = static_cast<double*>(partials);
+    a.part_lo = reinterpret_cast<float*>(a.part_hi + static_cast<int64_t>(lay.P) * L.trial_count);
+    a.pad = lay.ids + lay.length;
+    a.n_xcd = kXcds;
+    // one 1024-thread workgroup per CU (its LDS holds the part's byte map and
+    // values), a multiple of the XCD count
+    int64_t grid = int64_t(n_cu);
+    grid -= grid % kXcds;
+    if (grid < kXcds) grid = kXcds;
+    hipLaunchKernelGGL(stream_pass_kernel, dim3(static_cast<uint32_t>(grid)), dim3(1024), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_stream_combine(const StreamLayout& lay, const LayerArgs& L, const LayerArgs* L_dev,
+                                 const void* partials, double* ylt, double* S, hipStream_t s) {
+    if (L.trial_count <= 0) return hipSuccess;
+    const double* hi = static_cast<const double*>(partials);
+    const float* lo = reinterpret_cast<const float*>(hi + static_cast<int64_t>(lay.P) * L.trial_count);
+    const int64_t blocks = (L.trial_count + 255) / 256;
+    hipLaunchKernelGGL(stream_combine_kernel, dim3(static_cast<uint32_t>(blocks)), dim3(256), 0, s, hi, lo, lay.P,
+                       L.trial_count, L.aggR, L.aggL, L_dev, ylt, S);
+    return hipGetLastError();
+}
+
+}  // namespace ara

@@ -521,7 +521,7 @@ def test_portfolio_multi_part_catalogue(ara):
     programs = _portfolio_programs(pool, 0, yet.n_trials)
     ref = oracle.portfolio(yet, pool, programs)
     specs = [[_spec(ara, l, pool, yet) for l in prog] for prog in programs]
-    for knobs in (dict(pass_variant=0), dict(pass_variant=1, part_lanes_per_trial=16)):
+    for knobs in (dict(pass_variant=0), dict(pass_variant=1, part_lanes_per_trial=16), dict(pass_variant=2)):
         ara.set_tuning(tables, **knobs)
         base = ara.run_portfolio(tables, specs, n_splits=1)
         _portfolio_close(base, ref)
@@ -660,7 +660,7 @@ def test_more_parts_than_xcds(ara):
         layer = Layer(np.array([3, 1, 0], dtype=np.int32), 1500.0, 4.0e5, 5.0e4, 6.0e5, begin, count)
         spec = _spec(ara, layer, pool, yet)
         ref, _ = oracle.run_layer(yet, pool, layer)
-        for knobs in (dict(pass_variant=0), dict(pass_variant=1, part_lanes_per_trial=16)):
+        for knobs in (dict(pass_variant=0), dict(pass_variant=1, part_lanes_per_trial=16), dict(pass_variant=2)):
             ara.set_tuning(tables, **knobs)
             ylt = ara.run_layers(tables, [spec])
             ok, worst = _close(ylt, ref)
@@ -727,7 +727,7 @@ def test_segment_padding_with_nonzero_last_events(ara):
         sub = Layer(layer.elt_index, layer.occ_retention, layer.occ_limit, layer.agg_retention,
                     layer.agg_limit, begin, count)
         spec = _spec(ara, sub, pool, yet)
-        for knobs in (dict(pass_variant=0), dict(pass_variant=1, part_lanes_per_trial=16)):
+        for knobs in (dict(pass_variant=0), dict(pass_variant=1, part_lanes_per_trial=16), dict(pass_variant=2)):
             ara.set_tuning(tables, **knobs)
             ylt = ara.run_layers(tables, [spec])
             ok, worst = _close(ylt, ref[begin:begin + count])
@@ -752,7 +752,7 @@ def test_dense_elts_fold(ara):
                 Layer(idx[::-1].copy(), 0.0, INF, 0.0, INF, 37, 300)):
         ref, _ = oracle.run_layer(yet, pool, lay)
         spec = _spec(ara, lay, pool, yet)
-        for knobs in (dict(pass_variant=0), dict(pass_variant=1, part_lanes_per_trial=16)):
+        for knobs in (dict(pass_variant=0), dict(pass_variant=1, part_lanes_per_trial=16), dict(pass_variant=2)):
             ara.set_tuning(tables, **knobs)
             ylt = ara.run_layers(tables, [spec])
             ok, worst = _close(ylt, ref)
@@ -764,6 +764,38 @@ def test_dense_elts_fold(ara):
         ok, exact = _nets_close(got, nets_ref, yet, lay, ref)
         assert ok and exact > 0.99, exact
     tables.close()
+
+
+def test_stream_pass_group_shapes(ara):
+    """The 16-bit streaming pass on the shapes its layout takes: trials of 0-4
+    events (32-trial groups of a few IDs per part, many empty segments and
+    empty groups), and trials of ~6000 events (8-trial groups of ~12 000 IDs
+    per part: a dozen batches per group, queues drained part-way through a
+    group, more nonzero losses per part than the LDS copy holds).  Sub-ranges
+    start and end inside groups.  Every pass variant against the oracle."""
+    C = 200_000
+    pool = make_elt_pool(6, C, 50_000, seed=91)
+    cases = (make_yet(2000, 1.5, C, seed=92), make_yet(300, 6000.0, C, seed=93))
+    for yet in cases:
+        tables = ara.create_tables(yet.offsets, yet.ids, pool.losses)
+        n = yet.n_trials
+        for begin, count in ((0, n), (5, n - 17), (n - 1, 1), (3, 29)):
+            layer = Layer(np.array([5, 0, 3, 1], dtype=np.int32), 500.0, 3.0e6, 1.0e4, 5.0e8, begin, count)
+            spec = _spec(ara, layer, pool, yet)
+            ref, S = oracle.run_layer(yet, pool, layer)
+            for knobs in (dict(pass_variant=0), dict(pass_variant=1, part_lanes_per_trial=16),
+                          dict(pass_variant=2)):
+                ara.set_tuning(tables, **knobs)
+                ylt = ara.run_layers(tables, [spec], flags=ara.ARA_CHECKPOINT_S)
+                ok, worst = _close(ylt, ref)
+                assert ok, (n, begin, count, knobs, worst)
+                got_S = ara.read_checkpoints(tables, 0)
+                ok, worst = _close(got_S, S)
+                assert ok, (n, begin, count, knobs, worst)
+                if knobs["pass_variant"] != 1:
+                    assert np.mean(got_S == S) > 0.999, (n, begin, count, knobs)
+        ara.set_tuning(tables)
+        tables.close()
 
 
 # ---------------------------------------------------------------------------
@@ -908,7 +940,7 @@ def test_batched_layers_persistent_and_graph(ara):
     ref = np.concatenate(refs)
     out = torch.empty(ref.shape[0], dtype=torch.float64, device="cuda")
     stream = torch.cuda.Stream()
-    for variant in (0, 1):
+    for variant in (0, 1, 2):
         ara.set_tuning(tables, pass_variant=variant, part_lanes_per_trial=16)
         eager = ara.run_layers(tables, specs)
         per = ara.run_layers(tables, specs, flags=ara.ARA_PER_LAYER)
