@@ -27,9 +27,9 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "trial_pass_config1_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stream_pass_kernel_config1_traffic.json")
 NETS_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "event_nets_config1_traffic.json")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_1606_04473_amd", "csrc", "kernels_parts.hip")
+CSRC = os.path.join(ROOT, "paper_1606_04473_amd", "csrc")
 
 
 def log(msg: str) -> None:
@@ -78,12 +78,15 @@ def copy_probe() -> None:
 
 def measured_traffic(path=TRAFFIC_FILE):
     """HBM bytes per launch of a kernel from a committed rocprofv3 counter
-    summary, if it was taken on the current kernel source."""
+    summary, if it was taken on the current source of the kernel's file."""
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
-    src = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    src_file = os.path.join(CSRC, rec.get("kernel_source", "kernels_parts.hip"))
+    if not os.path.exists(src_file):
+        return None
+    src = hashlib.sha256(open(src_file, "rb").read()).hexdigest()
     if rec.get("kernel_source_sha256") != src:
         return None
     return rec.get("traffic_bytes_per_launch")
@@ -254,16 +257,33 @@ def main() -> None:
     lookups = float(n_ev) * J
     value = lookups / (ms_step / 1e3)
     step_bytes = 4.0 * n_ev + 8.0 * (N + 1) + 8.0 * J * C + 8.0 * N
+    # the pass's algorithmic bytes per launch: 4 B per event (its ID), 16 B per
+    # trial (offsets in, year loss out), 8 B per catalogue event (o)
     tp_bytes = 4.0 * n_ev + 8.0 * (N + 1) + 8.0 * N + 8.0 * C
     achieved = tp_bytes / (tp_avg / 1e3) / 1e9
+    lay = tables.layout()
+    streaming = lay["stream_parts"] > 0
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
-                "kernel": "xcd_pass_kernel",
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": measured_traffic() if streaming else None,
+                "kernel": "stream_pass_kernel" if streaming else "xcd_pass_kernel",
                 "algorithmic_bytes_per_launch": tp_bytes, "avg_launch_ms": round(tp_avg, 5)}
+    if streaming:
+        # the 16-bit layout's own bytes: its IDs (2 B each, padding included),
+        # each group's 32 trial ends (2 B) and start (4 B) per part, and the
+        # per-(part, trial) partial sums written (8 + 4 B)
+        P16, NG = lay["stream_parts"], lay["stream_groups"]
+        lay_bytes = 2.0 * lay["stream_ids"] + P16 * NG * (64.0 + 4.0) + 12.0 * P16 * N
+        roofline["layout_bytes_per_launch"] = lay_bytes
+        roofline["layout_achieved"] = round(lay_bytes / (tp_avg / 1e3) / 1e9, 1)
+        roofline["layout_frac"] = round(lay_bytes / (tp_avg / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
+        roofline["layout"] = {"stream_parts": P16, "group_trials": lay["stream_group_trials"],
+                              "groups_per_part": NG, "stream_ids": lay["stream_ids"]}
 
     extra = {"pct_hbm_step": round(step_bytes / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
              "step_algorithmic_bytes": step_bytes, "fold_ms": round(fold_avg, 5),
              "combine_ms": round(comb_avg, 5),
+             "combine_bytes": 12.0 * lay["stream_parts"] * N + 16.0 * N if streaming else 16.0 * lay["image_parts"] * N + 16.0 * N,
              "ms_per_step_with_kernel_events": round(ms_step_profiled, 5),
              "trial_pass_ms": round(tp_avg, 5)}
 

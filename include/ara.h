@@ -66,7 +66,7 @@ typedef int32_t ara_status;
                                        launch sequence per layer instead of the batched launch (a
                                        fold per layer, then one persistent pass over a (layer, tile)
                                        work list sorted by decreasing cost).  With pass_variant 0
-                                       (the default) layers always run one sequence each. */
+                                       (the default) or 2 layers always run one sequence each. */
 #define ARA_GRAPH        (1u << 4)  /* ara_run_layers: replay a HIP graph of the whole call, captured
                                        on first use for this shape (layer count, trial ranges,
                                        output pointer; with pass_variant 1 also the ELT counts) --
@@ -154,8 +154,12 @@ typedef struct ara_tuning {
     int32_t blocks_per_cu;          /* time-ordered pass: resident workgroups per CU (0 = 8) */
     int32_t fold_events_per_thread; /* reserved (0) */
     int32_t schedule;               /* batched pass work order: 0 = decreasing cost, 1 = layer-major */
-    int32_t pass_variant;           /* single-layer pass: 0 = XCD-affine dense gathers (each XCD
-                                       serves its own catalogue parts), 1 = LDS ranks + compact values */
+    int32_t pass_variant;           /* pass over the YET: 0 = the 16-bit part-major copy streamed
+                                       against per-part LDS byte maps and loss copies (falls back
+                                       to 2 when the tables hold no such copy), 1 = the 32-bit
+                                       partitioned copy with LDS ranks + compact values, one
+                                       persistent launch for several layers, 2 = the 32-bit
+                                       partitioned copy, each XCD serving its own catalogue parts */
     int32_t reserved;
 } ara_tuning;
 
@@ -172,13 +176,18 @@ typedef struct ara_tuning {
  *                  direct-access tables (Section IV-B); 0.0 = no loss.
  *                  Finite and >= 0.
  *   flags          ARA_DEVICE_PTR: the three arrays are device memory.
- *                  ARA_PLAIN_LAYOUT: skip the catalogue-partitioned copy.
+ *                  ARA_PLAIN_LAYOUT: skip the catalogue-partitioned copies.
  *
- * Besides the time-ordered CSR the library keeps, by default, a second copy
- * of the event IDs laid out for its trial pass: tiles of 256 consecutive
- * trials, inside a tile the catalogue's parts of 2^18 events one after the
- * other, inside a part each trial's events of that part in time order.  It
- * depends on the YET alone, so every layer run on the tables uses it.
+ * Besides the time-ordered CSR the library keeps, by default, two more
+ * copies of the event IDs laid out for its trial passes.  The 32-bit
+ * partitioned copy: tiles of 256 consecutive trials, inside a tile the
+ * catalogue's parts of 2^18 events one after the other, inside a part each
+ * trial's events of that part in time order.  The 16-bit copy, which the
+ * default pass streams: the catalogue cut into parts of 2^16 events, and per
+ * part one stream of part-relative IDs holding, group of consecutive trials
+ * after group, each trial's events of that part in time order (about 2 bytes
+ * per event).  Both depend on the YET alone, so every layer run on the
+ * tables uses them (ara_layout_info_get reports their sizes).
  *   out            receives the handle; freed by ara_destroy_tables.
  *
  * The arrays are caller-owned and only read during the call: the library
@@ -385,6 +394,33 @@ ara_status ara_get_tuning(const ara_tables* tables, ara_tuning* tuning);
  * (0, 1) or m NULL.  ara_risk_metrics and ara_backward use this m.
  */
 ara_status ara_tail_count(int64_t n_trials, double p, int64_t* m);
+
+/*
+ * The device copies of the YET the tables keep for their passes, for
+ * measurement (the bytes a pass streams) and admission control.
+ *   image_parts          catalogue parts of 2^18 events (the per-request part
+ *                        images and the 32-bit partitioned copy); 0 if the
+ *                        partitioned copy is absent
+ *   partitioned_ids      32-bit IDs in the partitioned copy, padding included
+ *   stream_parts         catalogue parts of 2^16 events of the 16-bit copy
+ *                        that the default pass streams; 0 if absent
+ *   stream_group_trials  trials per group of that copy
+ *   stream_groups        groups per part (ceil(n_trials / stream_group_trials))
+ *   stream_ids           16-bit IDs in that copy, padding included
+ *   *_bytes              device bytes of each copy with its offsets
+ */
+typedef struct ara_layout_info {
+    int32_t image_parts;
+    int32_t stream_parts;
+    int32_t stream_group_trials;
+    int32_t reserved;
+    int64_t partitioned_ids;
+    int64_t partitioned_bytes;
+    int64_t stream_groups;
+    int64_t stream_ids;
+    int64_t stream_bytes;
+} ara_layout_info;
+ara_status ara_layout_info_get(const ara_tables* tables, ara_layout_info* info);
 
 /* Number of compute units and the device index of the tables' device. */
 ara_status ara_device_info(int32_t* n_cu, int32_t* device);

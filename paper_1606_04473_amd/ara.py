@@ -51,7 +51,7 @@ EXPORTED = (
     "ara_last_error", "ara_status_string", "ara_table_bytes", "ara_footprint", "ara_debug_lookups",
     "ara_event_nets", "ara_run_portfolio",
     "ara_read_checkpoints", "ara_set_tuning", "ara_get_tuning", "ara_device_info",
-    "ara_kernel_stats", "ara_create_yet", "ara_tail_count",
+    "ara_kernel_stats", "ara_create_yet", "ara_tail_count", "ara_layout_info_get",
 )
 
 
@@ -107,6 +107,20 @@ class CTuning(ctypes.Structure):
     ]
 
 
+
+class CLayoutInfo(ctypes.Structure):
+    _fields_ = [
+        ("image_parts", ctypes.c_int32),
+        ("stream_parts", ctypes.c_int32),
+        ("stream_group_trials", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("partitioned_ids", ctypes.c_int64),
+        ("partitioned_bytes", ctypes.c_int64),
+        ("stream_groups", ctypes.c_int64),
+        ("stream_ids", ctypes.c_int64),
+        ("stream_bytes", ctypes.c_int64),
+    ]
+
 _LIB = None
 
 
@@ -156,6 +170,8 @@ def lib():
     L.ara_get_tuning.restype = i32
     L.ara_kernel_stats.argtypes = [P, i32, ctypes.POINTER(i64), ctypes.POINTER(f64), i32]
     L.ara_kernel_stats.restype = i32
+    L.ara_layout_info_get.argtypes = [P, ctypes.POINTER(CLayoutInfo)]
+    L.ara_layout_info_get.restype = i32
     L.ara_device_info.argtypes = [ctypes.POINTER(i32), ctypes.POINTER(i32)]
     L.ara_device_info.restype = i32
     L.ara_tail_count.argtypes = [i64, f64, ctypes.POINTER(i64)]
@@ -302,6 +318,12 @@ class Tables:
         v = ctypes.c_int64()
         _check(lib().ara_table_bytes(self.handle, ctypes.byref(v)))
         return int(v.value)
+
+    def layout(self) -> dict:
+        """ara_layout_info_get: the sizes of the YET copies the passes stream."""
+        v = CLayoutInfo()
+        _check(lib().ara_layout_info_get(self.handle, ctypes.byref(v)))
+        return {name: int(getattr(v, name)) for name, _ in CLayoutInfo._fields_ if name != "reserved"}
 
 
 def create_tables(offsets, ids, elt_losses, catalogue_size: Optional[int] = None,

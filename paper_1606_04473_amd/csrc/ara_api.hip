@@ -610,6 +610,21 @@ ara_status ara_table_bytes(const ara_tables* t, int64_t* bytes) {
     return ARA_OK;
 }
 
+ara_status ara_layout_info_get(const ara_tables* t, ara_layout_info* info) {
+    if (!t || !info) return fail(ARA_ERR_INVALID_ARG, "NULL argument");
+    ara_layout_info v{};
+    v.image_parts = t->parts.P;
+    v.partitioned_ids = t->parts.length;
+    v.partitioned_bytes = t->parts.bytes;
+    v.stream_parts = t->stream.P;
+    v.stream_group_trials = t->stream.G;
+    v.stream_groups = t->stream.NG;
+    v.stream_ids = t->stream.length;
+    v.stream_bytes = t->stream.bytes;
+    *info = v;
+    return ARA_OK;
+}
+
 ara_status ara_kernel_stats(ara_tables* t, int32_t kernel, int64_t* launches, double* total_ms, int32_t reset) {
     if (!t || kernel < 0 || kernel > ARA_KERNEL_AGGREGATE) return fail(ARA_ERR_INVALID_ARG, "bad argument");
     DeviceScope ds(t->device);

@@ -224,19 +224,20 @@ __device__ __forceinline__ double stream_swap_pair(double v) {
 __global__ __launch_bounds__(1024) void stream_pass_kernel(StreamPassArgs a) {
     constexpr int kU = 2;                                     // 16-byte loads per lane per batch
     constexpr uint32_t kBatch = 64 * kChunkIds * kU;          // IDs per batch
-    constexpr int kQ = 1024;                                  // 16-bit queue entries per wave
+    constexpr int kQ = 64 * kChunkIds;                        // 16-bit queue entries per wave: one load's IDs
     constexpr int kInf = 0x3FFFFFFF;
-    static_assert(kQ >= static_cast<int>(kBatch), "a batch must fit an empty queue");
+    static_assert(kU == 2, "a batch is two loads per lane, each fitting an empty queue");
     // LDS, one block: the byte map first (a byte's address is its event's
     // part-relative ID), then the rank of each 128-event block's first nonzero
-    // event, the 16 hit queues, and as many of the part's nonzero o(E) as fit
+    // event minus one, the 16 hit queues, and as many of the part's nonzero
+    // o(E) as fit, followed by one 0.0 that the drain's idle slots read
     constexpr uint32_t kBaseOff = kQSize;
-    constexpr uint32_t kQueueOff = kBaseOff + (kQSize / 128) * 2;
+    constexpr uint32_t kQueueOff = kBaseOff + (kQSize / 128) * 4;
     constexpr uint32_t kValOff = kQueueOff + 16 * kQ * 2;
-    constexpr int kCap = static_cast<int>((160 * 1024 - kValOff) / 8);
+    constexpr int kCap = static_cast<int>((160 * 1024 - kValOff) / 8) - 1;
     static_assert(kValOff % 16 == 0 && kCap > 0, "LDS layout");
-    __shared__ __attribute__((aligned(16))) uint8_t lds[kValOff + kCap * 8];
-    uint16_t* bases = reinterpret_cast<uint16_t*>(lds + kBaseOff);
+    __shared__ __attribute__((aligned(16))) uint8_t lds[kValOff + (kCap + 1) * 8];
+    uint32_t* bases = reinterpret_cast<uint32_t*>(lds + kBaseOff);
     double* vals = reinterpret_cast<double*>(lds + kValOff);
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
@@ -292,11 +293,11 @@ __global__ __launch_bounds__(1024) void stream_pass_kernel(StreamPassArgs a) {
         }
         if (threadIdx.x < kQSize / 128) {
             const int k = threadIdx.x;
-            bases[k] = static_cast<uint16_t>(gb32[k >> 5] + gr16[k] - g0);
+            bases[k] = gb32[k >> 5] + gr16[k] - g0 - 1u;
         }
-        for (int k = threadIdx.x; k < kCap; k += blockDim.x) {
+        for (int k = threadIdx.x; k <= kCap; k += blockDim.x) {
             const int64_t gk = static_cast<int64_t>(g0) + k;
-            vals[k] = gk < a.C ? a.compact[gk] : 0.0;
+            vals[k] = k < kCap && gk < a.C ? a.compact[gk] : 0.0;
         }
         __syncthreads();
 
@@ -346,34 +347,43 @@ __global__ __launch_bounds__(1024) void stream_pass_kernel(StreamPassArgs a) {
             }
         };
         // sum the queued hits: lanes 2t and 2t+1 take trial t's entries
-        // alternately, four in flight per lane
+        // alternately, four at a time per lane
         auto drain = [&]() {
+            constexpr int kR = 4;
             int lo = __shfl(qs, pt), hi = __shfl(qs, pt + 1);
             lo = lo < 0 ? 0 : (lo > qn ? qn : lo);
             hi = hi < 0 ? 0 : (hi > qn ? qn : hi);
-            for (int j = lo + half; j < hi; j += 8) {
-                // four entries at once (slots past the trial's last reread entry j
-                // and add 0.0, whose sum is exact), each step's loads issued together
-                uint32_t e[4], rk[4];
-                double v[4];
+            for (int j = lo + half; j < hi; j += 2 * kR) {
+                // each step's loads issued together.  Slots past the trial's last
+                // entry read whatever LDS follows (still inside the allocation),
+                // then the 0.0 after the copied losses, whose sum is exact.
+                uint32_t e[kR], rk[kR];
+                bool valid[kR];
+                double v[kR];
 #pragma unroll
-                for (int r2 = 0; r2 < 4; ++r2) {
-                    const int jj = j + 2 * r2;
-                    e[r2] = q[jj < hi ? jj : j];
+                for (int r2 = 0; r2 < kR; ++r2) {
+                    valid[r2] = j + 2 * r2 < hi;
+                    e[r2] = q[j + 2 * r2];
                 }
-                // rank among the part's nonzero events: the block's base plus the
-                // byte, which is 1 + the rank inside the block
+                // rank among the part's nonzero events: the block's base (minus
+                // one) plus the byte, which is 1 + the rank inside the block
 #pragma unroll
-                for (int r2 = 0; r2 < 4; ++r2) rk[r2] = static_cast<uint32_t>(bases[e[r2] >> 7]) + lds[e[r2]] - 1u;
-                // the LDS copy at a clamped rank, else the value from L2 (two
-                // loads of one address space each, no pointer select)
+                for (int r2 = 0; r2 < kR; ++r2) rk[r2] = bases[e[r2] >> 7] + lds[e[r2]];
+                // the LDS copy; ranks past it (parts with more nonzero losses than
+                // LDS holds) then read the value from L2
+                bool spill = false;
 #pragma unroll
-                for (int r2 = 0; r2 < 4; ++r2) v[r2] = vals[min(rk[r2], static_cast<uint32_t>(kCap - 1))];
+                for (int r2 = 0; r2 < kR; ++r2) {
+                    v[r2] = vals[valid[r2] ? min(rk[r2], static_cast<uint32_t>(kCap - 1)) : kCap];
+                    spill |= valid[r2] && rk[r2] >= static_cast<uint32_t>(kCap);
+                }
+                if (__ballot(spill)) {
 #pragma unroll
-                for (int r2 = 0; r2 < 4; ++r2)
-                    if (rk[r2] >= static_cast<uint32_t>(kCap)) v[r2] = gcompact[rk[r2]];
+                    for (int r2 = 0; r2 < kR; ++r2)
+                        if (valid[r2] && rk[r2] >= static_cast<uint32_t>(kCap)) v[r2] = gcompact[rk[r2]];
+                }
 #pragma unroll
-                for (int r2 = 0; r2 < 4; ++r2) dd_add(acc_hi, acc_lo, j + 2 * r2 < hi ? v[r2] : 0.0);
+                for (int r2 = 0; r2 < kR; ++r2) dd_add(acc_hi, acc_lo, v[r2]);
             }
             qs = qs == kInf ? kInf : qs - qn;
             qn = 0;
@@ -386,23 +396,24 @@ __global__ __launch_bounds__(1024) void stream_pass_kernel(StreamPassArgs a) {
             // their hits are queued after the group's end boundary (lanes >= G
             // note where it falls), so no trial sums them.
             uint32_t m[kU];                         // bit w: ID w of the lane's chunk is a hit
-            uint32_t h[kU][8];                      // the same bits, one per register
+            uint32_t h[kU][8];                      // each ID's byte (nonzero: a hit)
 #pragma unroll
             for (int u = 0; u < kU; ++u) {
                 uint32_t mm = 0;
 #pragma unroll
                 for (int d = 0; d < 4; ++d) {
                     const uint32_t D = v[u][d];
-                    h[u][2 * d] = min(static_cast<uint32_t>(lds[D & 0xFFFFu]), 1u);
-                    h[u][2 * d + 1] = min(static_cast<uint32_t>(lds[D >> 16]), 1u);
-                    mm |= h[u][2 * d] << (2 * d);
-                    mm |= h[u][2 * d + 1] << (2 * d + 1);
+                    const uint32_t b0 = lds[D & 0xFFFFu], b1 = lds[D >> 16];
+                    h[u][2 * d] = b0;
+                    h[u][2 * d + 1] = b1;
+                    mm |= min(b0, 1u) << (2 * d);
+                    mm |= min(b1, 1u) << (2 * d + 1);
                 }
                 m[u] = mm;
             }
             // hit counts per chunk, prefix-summed over the wave two chunks at a time
             // (16-bit halves: at most 8 x 64 hits per load)
-            uint32_t pre[kU], tot = 0;
+            uint32_t pre[kU], tot = 0, tot0 = 0;
             {
                 const uint32_t ca = static_cast<uint32_t>(__popc(m[0]));
                 const uint32_t cb = static_cast<uint32_t>(__popc(m[1]));
@@ -410,29 +421,49 @@ __global__ __launch_bounds__(1024) void stream_pass_kernel(StreamPassArgs a) {
                 const uint32_t tt = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(sc), 63));
                 pre[0] = (sc & 0xFFFFu) - ca;
                 pre[1] = (tt & 0xFFFFu) + (sc >> 16) - cb;
-                tot = (tt & 0xFFFFu) + (tt >> 16);
+                tot0 = tt & 0xFFFFu;
+                tot = tot0 + (tt >> 16);
             }
-            if (qn + static_cast<int>(tot) > kQ) drain();    // exact: a batch always fits an empty queue
-#pragma unroll
-            for (int u = 0; u < kU; ++u) {
-                uint8_t* at = reinterpret_cast<uint8_t*>(q + qn + pre[u]);   // LDS byte address of the next entry
+            // append the hits of load u; `skip` hits of the batch precede the queue's end
+            auto append = [&](int u, uint32_t skip) {
+                uint8_t* at = reinterpret_cast<uint8_t*>(q + qn + (pre[u] - skip));   // LDS byte address
 #pragma unroll
                 for (int w = 0; w < 8; ++w) {
-                    if (h[u][w]) *reinterpret_cast<uint16_t*>(at) = static_cast<uint16_t>(v[u][w >> 1] >> (16 * (w & 1)));
-                    at += h[u][w] << 1;
+                    const bool hit = h[u][w] != 0u;
+                    if (hit) *reinterpret_cast<uint16_t*>(at) = static_cast<uint16_t>(v[u][w >> 1] >> (16 * (w & 1)));
+                    at += hit ? 2 : 0;
                 }
-            }
-            // trial starts inside this batch: the hits of the chunk before the
-            // start's position, plus the chunk's queue offset
+            };
+            // trial starts at batch positions [from, to): the hits of the chunk
+            // before the start's position, plus the chunk's queue offset
             const uint32_t rel = B - c;
             const uint32_t k = rel >> 3;
             const int src = static_cast<int>(k & 63u);
             const uint32_t p0 = static_cast<uint32_t>(__shfl(static_cast<int>((pre[0] << 8) | m[0]), src));
             const uint32_t p1 = static_cast<uint32_t>(__shfl(static_cast<int>((pre[1] << 8) | m[1]), src));
             const uint32_t pk = (k >> 6) == 0 ? p0 : p1;
-            const uint32_t below = (pk & 0xFFu) & ((1u << (rel & 7u)) - 1u);
-            if (B >= c && rel < kBatch) qs = qn + static_cast<int>(pk >> 8) + __popc(below);
-            qn += static_cast<int>(tot);
+            const int before = static_cast<int>(pk >> 8) + __popc((pk & 0xFFu) & ((1u << (rel & 7u)) - 1u));
+            auto record = [&](uint32_t from, uint32_t to, int skip) {
+                if (B >= c && rel >= from && rel < to) qs = qn + before - skip;
+            };
+            if (qn + static_cast<int>(tot) > kQ) drain();
+            if (tot <= static_cast<uint32_t>(kQ)) {
+                append(0, 0u);
+                append(1, 0u);
+                record(0u, kBatch, 0);
+                qn += static_cast<int>(tot);
+            } else {
+                // more hits than the queue holds (dense layers): the first load's
+                // hits, a drain, then the second load's (each fits an empty queue)
+                const uint32_t t0 = tot0;
+                append(0, 0u);
+                record(0u, kBatch / 2, 0);
+                qn += static_cast<int>(t0);
+                drain();
+                append(1, t0);
+                record(kBatch / 2, kBatch, static_cast<int>(t0));
+                qn += static_cast<int>(tot - t0);
+            }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
