@@ -261,6 +261,30 @@ ara_status ara_risk_metrics(const double* ylt, int64_t n_trials, const double* p
                             double* tvar_out, uint32_t flags, void* stream);
 
 /*
+ * ara_risk_metrics_noalloc -- for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  The same results as ara_risk_metrics with ARA_DEVICE_PTR, from
+ * the same kernels, but the scratch they need lives in a static device array
+ * of the library (one per device, held until the process ends) instead of
+ * memory the call allocates.  The call allocates nothing, host or device.
+ *
+ *   ylt        device float64[n_trials], values >= 0.
+ *   probs      host float64[n_probs], each in (0, 1); n_probs <= 4.
+ *   mean_out, pml_out, tvar_out   device memory (1, n_probs and n_probs
+ *              doubles), written on `stream` without waiting.
+ *
+ * Limit: n_probs * n_trials <= ARA_METRICS_NOALLOC_KEYS (any n_trials for
+ * n_probs = 0), else ARA_ERR_UNSUPPORTED before any device work.  Every call
+ * on one device uses that device's one array, so calls that overlap in time
+ * on one device race and give wrong results: order them (one stream, or
+ * events).  Other errors as ara_risk_metrics.
+ */
+#define ARA_METRICS_NOALLOC_KEYS (4ll << 20)
+ara_status ara_risk_metrics_noalloc(const double* ylt, int64_t n_trials, const double* probs,
+                                    int32_t n_probs, double* mean_out, double* pml_out,
+                                    double* tvar_out, void* stream);
+
+/*
  * ara_backward -- gradients of the mean annual loss and of TVaR_p with
  * respect to theta = [R_1..R_J, Lim_1..Lim_J, OccR, OccL, AggR, AggL] of one
  * layer (2J + 4 values each, in that order).  The paper defines no

@@ -145,6 +145,8 @@ def lib():
     L.ara_run_layers.restype = i32
     L.ara_risk_metrics.argtypes = [P, i64, P, i32, P, P, P, u32, P]
     L.ara_risk_metrics.restype = i32
+    L.ara_risk_metrics_noalloc.argtypes = [P, i64, P, i32, P, P, P, P]
+    L.ara_risk_metrics_noalloc.restype = i32
     L.ara_backward.argtypes = [P, ctypes.POINTER(CLayer), f64, P, P, u32, P]
     L.ara_backward.restype = i32
     L.ara_last_error.argtypes = []
@@ -407,6 +409,25 @@ def risk_metrics(ylt, probs: Sequence[float], stream=None, outputs=None):
                                   pml.ctypes.data_as(ctypes.c_void_p),
                                   tvar.ctypes.data_as(ctypes.c_void_p), 0, _stream(stream)))
     return float(mean.value), pml[:k].tolist(), tvar[:k].tolist()
+
+
+def risk_metrics_noalloc(ylt, probs: Sequence[float], outputs, stream=None):
+    """ara_risk_metrics_noalloc: `ylt` a float64 CUDA tensor, `outputs` a
+    float64 CUDA tensor of size 1 + 2 n_probs that receives [mean, pml...,
+    tvar...]; asynchronous on `stream`.  The library allocates nothing."""
+    py, ky, dev = _ptr(ylt, np.float64)
+    po, ko, dev_o = _ptr(outputs, np.float64)
+    if not (dev and dev_o):
+        raise ValueError("ara_risk_metrics_noalloc takes device tensors")
+    p = np.ascontiguousarray(probs, dtype=np.float64)
+    k = p.shape[0]
+    if ko.numel() < 1 + 2 * k:
+        raise ValueError("outputs must hold 1 + 2 n_probs doubles")
+    base = outputs.data_ptr()
+    _check(lib().ara_risk_metrics_noalloc(py, int(ky.numel()), p.ctypes.data_as(ctypes.c_void_p), k,
+                                          ctypes.c_void_p(base), ctypes.c_void_p(base + 8),
+                                          ctypes.c_void_p(base + 8 * (1 + k)), _stream(stream)))
+    return outputs
 
 
 def backward(tables: Tables, layer: LayerSpec, tvar_p: float, grad_mean=None, grad_tvar=None,

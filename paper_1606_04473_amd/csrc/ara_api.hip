@@ -1198,6 +1198,38 @@ ara_status ara_risk_metrics(const double* ylt, int64_t n_trials, const double* p
     return ARA_OK;
 }
 
+ara_status ara_risk_metrics_noalloc(const double* ylt, int64_t n_trials, const double* probs, int32_t n_probs,
+                                    double* mean_out, double* pml_out, double* tvar_out, void* stream) {
+    if (!ylt || !mean_out || n_probs < 0 || (n_probs > 0 && (!probs || !pml_out || !tvar_out)))
+        return fail(ARA_ERR_INVALID_ARG, "NULL argument");
+    if (n_trials < 1) return fail(ARA_ERR_INVALID_ARG, "need at least one trial");
+    if (n_probs > 4) return fail(ARA_ERR_UNSUPPORTED, "at most 4 probabilities per call");
+    int64_t m[4] = {0, 0, 0, 0};
+    for (int q = 0; q < n_probs; ++q) {
+        if (!(probs[q] > 0.0 && probs[q] < 1.0)) return fail(ARA_ERR_INVALID_ARG, "p must lie in (0, 1)");
+        m[q] = tail_count(n_trials, probs[q]);
+    }
+    void* scratch = nullptr;
+    int64_t capacity = 0;
+    HIP_TRY(ara::metrics_noalloc_scratch(&scratch, &capacity), "static metrics scratch");
+    const int64_t need = ara::metrics_scratch_bytes(n_probs, n_trials);
+    if (need > capacity)
+        return fail(ARA_ERR_UNSUPPORTED,
+                    "%lld trials x %d probabilities need %lld bytes of scratch; the static scratch holds %lld "
+                    "(n_probs * n_trials <= %lld); use ara_risk_metrics",
+                    (long long)n_trials, n_probs, (long long)need, (long long)capacity,
+                    (long long)ARA_METRICS_NOALLOC_KEYS);
+    int device = 0;
+    HIP_TRY(hipGetDevice(&device), "hipGetDevice");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    // not primed: the first kernel clears the histograms, counters and flag
+    // that earlier calls on this device left in the shared array
+    HIP_TRY(ara::launch_metrics(ylt, n_trials, m, n_probs, scratch, false,
+                                ara::MetricsOut{mean_out, pml_out, tvar_out, 1}, query_cu_count(device), s),
+            "metrics kernels");
+    return ARA_OK;
+}
+
 ara_status ara_backward(ara_tables* t, const ara_layer* layer, double tvar_p, double* grad_mean,
                         double* grad_tvar, uint32_t flags, void* stream) {
     if (!t || !layer) return fail(ARA_ERR_INVALID_ARG, "NULL argument");

@@ -441,6 +441,10 @@ int64_t metrics_scratch_bytes(int n_probs, int64_t n);
 hipError_t launch_metrics(const double* ylt, int64_t n, const int64_t* m_host, int n_probs,
                           void* scratch, bool primed, MetricsOut out, int n_cu, hipStream_t s);
 
+// the static scratch of ara_risk_metrics_noalloc on the current device and
+// its size in bytes (launch_metrics needs metrics_scratch_bytes of it)
+hipError_t metrics_noalloc_scratch(void** ptr, int64_t* capacity);
+
 // order statistics of a YLT for one tail count m
 struct TailStats {
     uint64_t v_bits;   // bit pattern of the m-th largest year loss

@@ -57,11 +57,20 @@ constexpr int64_t kHistStride = int64_t(kMaxProbs) * kBins;   // one rotating hi
 
 constexpr int64_t kCandAlign = 256;
 
-int64_t base_bytes() {
-    const int64_t np = static_cast<int64_t>(kMaxProbs + 1) * kSumBlocks;
-    return np * (2 * sizeof(double) + sizeof(int64_t)) + 3 * kHistStride * sizeof(uint32_t) +
-           2 * kMaxProbs * sizeof(SelState) + 64;
+constexpr int64_t base_bytes() {
+    return static_cast<int64_t>(kMaxProbs + 1) * kSumBlocks * (2 * sizeof(double) + sizeof(int64_t)) +
+           3 * kHistStride * sizeof(uint32_t) + 2 * kMaxProbs * sizeof(SelState) + 64;
 }
+
+// Scratch of the allocation-free entry point: the fixed block plus candidate
+// keys for up to kMaxProbs x kStaticTrials year losses (32.2 MiB).  A static
+// device array, so each device the library runs on holds its own copy until
+// the process ends; host code reaches it only through the address that
+// hipGetSymbolAddress returns on that device (metrics_noalloc_scratch).
+constexpr int64_t kStaticTrials = int64_t(1) << 20;
+constexpr int64_t kStaticBytes =
+    (base_bytes() + kCandAlign - 1) / kCandAlign * kCandAlign + kMaxProbs * kStaticTrials * int64_t(sizeof(uint64_t));
+static __device__ __align__(256) uint8_t scratch[kStaticBytes];
 
 Scratch carve(void* base, int n_probs) {
     (void)n_probs;
@@ -527,6 +536,28 @@ hipError_t launch_metrics(const double* ylt, int64_t n, const int64_t* m_host, i
 namespace ara {
 
 int64_t tail_stats_scratch_bytes(int64_t n) { return metrics_scratch_bytes(1, n); }
+
+// The device address of `scratch` on the current device, looked up once per
+// device (with that device current) and kept; later calls reuse it.  No
+// allocation of any kind.
+hipError_t metrics_noalloc_scratch(void** ptr, int64_t* capacity) {
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static void* addr[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> g(mu);
+    if (!addr[dev]) {
+        void* p = nullptr;
+        if ((e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch))) != hipSuccess) return e;
+        addr[dev] = p;
+    }
+    *ptr = addr[dev];
+    *capacity = kStaticBytes;
+    return hipSuccess;
+}
 
 namespace {
 
