@@ -333,6 +333,45 @@ ara_status ara_debug_lookups(ara_tables* tables, const ara_layer* layer, int64_t
                              int64_t* n_out, void* stream);
 
 /*
+ * ara_debug_read -- the data the default pass works from, copied to host for
+ * bit-exact checks of its lookups and indexing (Algorithm 3's lookup step;
+ * Section IV-B: direct-access tables).  `what`:
+ *   ARA_DEBUG_OCCURRENCE     float64[C]: o(E) for every catalogue event E (the
+ *                            per-ELT terms, the sum over the layer's ELTs in
+ *                            layer order, the occurrence terms), as the fold
+ *                            of `layer` writes it for the pass
+ *   ARA_DEBUG_COMPACT        float64[nnz]: the nonzero o(E) in catalogue order,
+ *                            the array the pass reads them from by rank
+ *   ARA_DEBUG_IMAGES         uint8[image_parts * 37120]: per 2^18-event part,
+ *                            4096 u64 bitmap words of o(E) != 0 (bit E % 64
+ *                            of word E / 64), 2048 u16 counts of nonzero events
+ *                            before each 128-event block inside its
+ *                            4096-event superblock, 64 u32 global ranks of
+ *                            each superblock's first nonzero event
+ *   ARA_DEBUG_STREAM_IDS     uint16[stream_ids]: the 16-bit copy of the YET
+ *                            (see ara_create_tables and ara_layout_info_get)
+ *   ARA_DEBUG_STREAM_BASE    int64[stream_parts + 1]: where each part's stream starts
+ *   ARA_DEBUG_STREAM_GSTART  uint32[stream_parts][stream_groups + 1]: group
+ *                            starts relative to the part's stream
+ *   ARA_DEBUG_STREAM_GEND    uint16[stream_parts][stream_groups][32]: end of
+ *                            each trial of the group relative to the group's
+ *                            start (slots past the group's trials repeat its end)
+ * `layer` (its trial range is ignored) is needed for the first three only.
+ * `out` is host memory of `capacity` bytes; *n_out receives the bytes of the
+ * result (ARA_ERR_BUFFER_TOO_SMALL, nothing copied, if above capacity).
+ * ARA_ERR_UNSUPPORTED when the tables hold no such copy.  Synchronous.
+ */
+#define ARA_DEBUG_OCCURRENCE    0
+#define ARA_DEBUG_COMPACT       1
+#define ARA_DEBUG_IMAGES        2
+#define ARA_DEBUG_STREAM_IDS    3
+#define ARA_DEBUG_STREAM_BASE   4
+#define ARA_DEBUG_STREAM_GSTART 5
+#define ARA_DEBUG_STREAM_GEND   6
+ara_status ara_debug_read(ara_tables* tables, const ara_layer* layer, int32_t what, void* out,
+                          int64_t capacity, int64_t* n_out, void* stream);
+
+/*
  * ara_run_portfolio -- Algorithm 1: for each program of the portfolio PF
  * (Section IV-A), for each of its layers, the YET split into n_splits
  * contiguous trial ranges YET_i, each analysed as its own launch sequence,

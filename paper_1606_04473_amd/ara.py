@@ -145,6 +145,8 @@ def lib():
     L.ara_run_layers.restype = i32
     L.ara_risk_metrics.argtypes = [P, i64, P, i32, P, P, P, u32, P]
     L.ara_risk_metrics.restype = i32
+    L.ara_debug_read.argtypes = [P, P, i32, P, i64, ctypes.POINTER(i64), P]
+    L.ara_debug_read.restype = i32
     L.ara_risk_metrics_noalloc.argtypes = [P, i64, P, i32, P, P, P, P]
     L.ara_risk_metrics_noalloc.restype = i32
     L.ara_backward.argtypes = [P, ctypes.POINTER(CLayer), f64, P, P, u32, P]
@@ -463,6 +465,34 @@ def debug_lookups(tables: Tables, layer: LayerSpec, trial: int, capacity: int = 
                                    _stream(stream)))
     K = int(n.value)
     return ids[:K].copy(), losses[:K * J].reshape(K, J).copy()
+
+
+DEBUG_OCCURRENCE = 0
+DEBUG_COMPACT = 1
+DEBUG_IMAGES = 2
+DEBUG_STREAM_IDS = 3
+DEBUG_STREAM_BASE = 4
+DEBUG_STREAM_GSTART = 5
+DEBUG_STREAM_GEND = 6
+_DEBUG_DTYPES = {DEBUG_OCCURRENCE: np.float64, DEBUG_COMPACT: np.float64, DEBUG_IMAGES: np.uint8,
+                 DEBUG_STREAM_IDS: np.uint16, DEBUG_STREAM_BASE: np.int64, DEBUG_STREAM_GSTART: np.uint32,
+                 DEBUG_STREAM_GEND: np.uint16}
+
+
+def debug_read(tables: Tables, what: int, layer: Optional[LayerSpec] = None, stream=None) -> np.ndarray:
+    """ara_debug_read: the fold's o(E), compact values or part images for
+    `layer`, or the arrays of the 16-bit stream copy, as a NumPy array."""
+    arr = None
+    if layer is not None:
+        arr, keep = _c_layers([layer])
+    n = ctypes.c_int64()
+    st = lib().ara_debug_read(tables.handle, arr, int(what), None, 0, ctypes.byref(n), _stream(stream))
+    if st not in (ARA_OK, ARA_ERR_BUFFER_TOO_SMALL):
+        _check(st)
+    out = np.empty(int(n.value) // np.dtype(_DEBUG_DTYPES[what]).itemsize, dtype=_DEBUG_DTYPES[what])
+    _check(lib().ara_debug_read(tables.handle, arr, int(what), out.ctypes.data_as(ctypes.c_void_p), out.nbytes,
+                                ctypes.byref(n), _stream(stream)))
+    return out
 
 
 PORTFOLIO_OUTPUTS = ("layer", "program", "portfolio")

@@ -1324,6 +1324,72 @@ ara_status ara_debug_lookups(ara_tables* t, const ara_layer* layer, int64_t tria
     return ARA_OK;
 }
 
+ara_status ara_debug_read(ara_tables* t, const ara_layer* layer, int32_t what, void* out, int64_t capacity,
+                          int64_t* n_out, void* stream) {
+    if (!t || !n_out || capacity < 0) return fail(ARA_ERR_INVALID_ARG, "NULL argument");
+    if (what < ARA_DEBUG_OCCURRENCE || what > ARA_DEBUG_STREAM_GEND) return fail(ARA_ERR_INVALID_ARG, "bad `what`");
+    DeviceScope ds(t->device);
+    if (!ds.ok) return fail(ARA_ERR_DEVICE, "cannot select the tables' device");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const void* src = nullptr;
+    int64_t bytes = 0;
+    PoolBuffer buf;
+    if (what >= ARA_DEBUG_STREAM_IDS) {
+        const ara::StreamLayout& st = t->stream;
+        if (st.P == 0) return fail(ARA_ERR_UNSUPPORTED, "the tables hold no 16-bit stream copy");
+        switch (what) {
+            case ARA_DEBUG_STREAM_IDS: src = st.ids; bytes = sizeof(uint16_t) * st.length; break;
+            case ARA_DEBUG_STREAM_BASE: src = st.part_base; bytes = sizeof(int64_t) * (st.P + 1); break;
+            case ARA_DEBUG_STREAM_GSTART: src = st.gstart; bytes = sizeof(uint32_t) * st.P * (st.NG + 1); break;
+            default: src = st.gend; bytes = sizeof(uint16_t) * st.P * st.NG * ara::kStreamGroupMax; break;
+        }
+    } else {
+        if (!layer) return fail(ARA_ERR_INVALID_ARG, "the fold's outputs need a layer");
+        if (t->parts.P == 0) return fail(ARA_ERR_UNSUPPORTED, "the tables hold no partitioned copy (plain layout)");
+        ara_layer probe = *layer;
+        probe.trial_begin = 0;
+        probe.trial_count = 0;
+        ara::LayerArgs L;
+        ara_status st = build_layer_args(t, probe, L);
+        if (st != ARA_OK) return st;
+        const size_t o_bytes = (sizeof(double) * t->C + 255) & ~size_t(255);
+        const size_t p_bytes = static_cast<size_t>(ara::part_scratch_bytes(t->C, t->parts.P));
+        HIP_TRY(buf.alloc(o_bytes + p_bytes, s), "scratch for the fold");
+        double* o = static_cast<double*>(buf.p);
+        void* pbuf = static_cast<char*>(buf.p) + o_bytes;
+        HIP_TRY(ara::launch_fold_parts(t->sparse, t->C, L, nullptr, o, t->parts.P, pbuf, s), "fold and part images");
+        if (what == ARA_DEBUG_OCCURRENCE) {
+            src = o;
+            bytes = sizeof(double) * t->C;
+        } else if (what == ARA_DEBUG_IMAGES) {
+            src = pbuf;
+            bytes = ara::kImgPartBytes * t->parts.P;
+        } else {
+            const int64_t n_sb = static_cast<int64_t>(t->parts.P) * ara::kImgBase32;
+            std::vector<uint32_t> cnt(n_sb);
+            HIP_TRY(hipMemcpyAsync(cnt.data(), ara::part_superblock_counts(pbuf, t->parts.P), sizeof(uint32_t) * n_sb,
+                                   hipMemcpyDeviceToHost, s),
+                    "copy superblock counts");
+            HIP_TRY(hipStreamSynchronize(s), "synchronize");
+            int64_t nnz = 0;
+            for (uint32_t c : cnt) nnz += c;
+            src = ara::part_compact_values(pbuf, t->parts.P);
+            bytes = sizeof(double) * nnz;
+        }
+    }
+    *n_out = bytes;
+    if (bytes > capacity) {
+        HIP_TRY(hipStreamSynchronize(s), "synchronize");
+        return fail(ARA_ERR_BUFFER_TOO_SMALL, "%lld bytes, capacity %lld", (long long)bytes, (long long)capacity);
+    }
+    if (bytes > 0) {
+        if (!out) return fail(ARA_ERR_INVALID_ARG, "out is NULL");
+        HIP_TRY(hipMemcpyAsync(out, src, bytes, hipMemcpyDeviceToHost, s), "copy");
+    }
+    HIP_TRY(hipStreamSynchronize(s), "synchronize");
+    return ARA_OK;
+}
+
 ara_status ara_event_nets(ara_tables* t, const ara_layer* layer, double* nets, int64_t capacity, int64_t* n_out,
                           uint32_t flags, void* stream) {
     if (!t || !layer || !n_out || capacity < 0) return fail(ARA_ERR_INVALID_ARG, "NULL argument");

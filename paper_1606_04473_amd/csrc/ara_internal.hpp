@@ -151,6 +151,8 @@ constexpr int kImgRank16 = (1 << kImgShift) / 128;
 constexpr int kImgBase32 = (1 << kImgShift) / 4096;
 constexpr int64_t kImgPartBytes = int64_t(kImgWords) * 8 + int64_t(kImgRank16) * 2 + int64_t(kImgBase32) * 4;
 double* part_compact_values(void* part_scratch, int P);
+// nonzero o(E) per 4096-event superblock, P * 64 of them, after launch_fold_parts
+uint32_t* part_superblock_counts(void* part_scratch, int P);
 
 // Second copy of the YET for the streaming pass (kernels_stream.hip): the
 // catalogue cut into parts of 2^16 events; per part, one contiguous stream of

@@ -1466,6 +1466,7 @@ PartScratch carve_parts(void* scratch, int P) {
 }  // namespace
 
 double* part_compact_values(void* part_scratch, int P) { return carve_parts(part_scratch, P).compact; }
+uint32_t* part_superblock_counts(void* part_scratch, int P) { return carve_parts(part_scratch, P).sb_count; }
 
 // ---------------------------------------------------------------------------
 // per-event net losses (the cumulative form of the aggregate terms)
