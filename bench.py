@@ -93,10 +93,15 @@ def measured_traffic(path=TRAFFIC_FILE):
 
 
 def batched_study(ara, tables, w, library, steps, stream):
-    """All 64 layers of the shared-YET library in one call: the batched
-    persistent pass replayed from a HIP graph, and one launch sequence per
-    layer, each timed with HIP events over `steps` runs."""
+    """All 64 layers of the shared-YET library in one ara_run_layers call.
+    The autotuner picks the pass variant and launch shape for this shape
+    (timing every candidate on it); then, each timed with HIP events over
+    `steps` calls: the tuned choice replayed from a HIP graph and eagerly,
+    the per-layer streaming sequences, and the persistent batched launch
+    (pass_variant 1), eagerly and from a graph."""
+    import tempfile
     import torch
+    from paper_1606_04473_amd import autotune
     off = w.yet.offsets
     lookups = sum(float(off[l.trial_begin + l.trial_count] - off[l.trial_begin]) * l.n_elts for l in library)
     events = sum(float(off[l.trial_begin + l.trial_count] - off[l.trial_begin]) for l in library)
@@ -104,12 +109,23 @@ def batched_study(ara, tables, w, library, steps, stream):
     C = w.yet.catalogue_size
     out = torch.empty(total, dtype=torch.float64, device="cuda")
     stream = torch.cuda.Stream()            # graph capture needs a stream of its own
-    res = {"layers": len(library), "lookups": lookups, "ylt_values": total}
+    res = {"layers": len(library), "lookups": lookups, "ylt_values": total, "event_layer_pairs": events}
     # Alg. 1 order (a YET pass per layer) and a fused single pass, as algorithmic bytes
     res["alg1_bytes"] = 4.0 * events + sum(8.0 * l.n_elts * C + 16.0 * l.trial_count for l in library)
     res["fused_bytes"] = 4.0 * w.yet.n_events + 8.0 * len({int(j) for l in library for j in l.elt_index}) * C \
         + 8.0 * total
-    for name, flags in (("graph", ara.ARA_GRAPH), ("per_layer", ara.ARA_PER_LAYER)):
+    report = {}
+    with torch.cuda.stream(stream):
+        best = autotune.tuned(tables, library, out, path=os.path.join(tempfile.mkdtemp(), "tune.json"), repeats=2,
+                              report=report)
+    res["autotune"] = {"chosen": best, "candidates": report.get("detail")}
+    log(f"batched 64 layers: autotuner chose {best}")
+    legs = (("tuned_graph", best, ara.ARA_GRAPH), ("tuned", best, 0),
+            ("stream_per_layer", dict(pass_variant=0), 0),
+            ("persistent", dict(pass_variant=1, part_lanes_per_trial=16), 0),
+            ("persistent_graph", dict(pass_variant=1, part_lanes_per_trial=16), ara.ARA_GRAPH))
+    for name, knobs, flags in legs:
+        ara.set_tuning(tables, **knobs)
         torch.cuda.synchronize()
         for _ in range(2):
             ara.run_layers(tables, library, out=out, flags=flags, stream=stream)
@@ -122,9 +138,14 @@ def batched_study(ara, tables, w, library, steps, stream):
         b.record(stream)
         stream.synchronize()
         ms = a.elapsed_time(b) / steps
-        res[name] = {"ms": round(ms, 3), "lookups_per_s": lookups / (ms / 1e3),
-                     "pct_hbm_fused_bytes": round(res["fused_bytes"] / (ms / 1e3) / (HBM_PEAK_GBS * 1e9), 4)}
-        log(f"batched 64 layers ({name}): {ms:.3f} ms, {lookups / (ms / 1e3):.3e} lookups/s")
+        res[name] = {"knobs": knobs, "graph": bool(flags & ara.ARA_GRAPH), "ms": round(ms, 3),
+                     "lookups_per_s": lookups / (ms / 1e3),
+                     "event_layer_pairs_per_s": events / (ms / 1e3),
+                     "pct_hbm_fused_bytes": round(res["fused_bytes"] / (ms / 1e3) / (HBM_PEAK_GBS * 1e9), 4),
+                     "pct_hbm_alg1_bytes": round(res["alg1_bytes"] / (ms / 1e3) / (HBM_PEAK_GBS * 1e9), 4)}
+        log(f"batched 64 layers ({name}): {ms:.3f} ms, {lookups / (ms / 1e3):.3e} lookups/s, "
+            f"{events / (ms / 1e3):.3e} event-layer pairs/s")
+    ara.set_tuning(tables)
     del out
     return res
 

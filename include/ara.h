@@ -321,6 +321,22 @@ ara_status ara_footprint(const ara_tables* tables, const ara_layer* layers, int3
                          uint32_t flags, int64_t* bytes);
 
 /*
+ * Device bytes, for admission control (upper bounds, computed on the host):
+ * ara_yet_footprint     -- the peak that ara_create_tables (without its ELT
+ *                          pool) or ara_create_yet holds for a YET of these
+ *                          sizes with `flags` (ARA_PLAIN_LAYOUT: no
+ *                          partitioned copies), its build temporaries included;
+ * ara_metrics_footprint -- the scratch of one ara_risk_metrics call over
+ *                          n_trials year losses and n_probs probabilities
+ *                          (with ARA_DEVICE_PTR: device inputs and outputs).
+ * Together with ara_footprint (an ara_run_layers call's scratch) they give
+ * what one analysis adds to the device on top of the resident tables.
+ */
+ara_status ara_yet_footprint(int64_t n_trials, int64_t n_events, int64_t catalogue_size, uint32_t flags,
+                             int64_t* bytes);
+ara_status ara_metrics_footprint(int64_t n_trials, int32_t n_probs, uint32_t flags, int64_t* bytes);
+
+/*
  * ara_debug_lookups -- the raw lookups of Algorithm 3 for one trial, as the
  * device performs them: ids_out[k] = k-th event ID of the trial and
  * losses_out[k * n_elts + j] = ELT_{elt_index[j]}[ids_out[k]].  Host outputs;
@@ -353,7 +369,7 @@ ara_status ara_debug_lookups(ara_tables* tables, const ara_layer* layer, int64_t
  *   ARA_DEBUG_STREAM_BASE    int64[stream_parts + 1]: where each part's stream starts
  *   ARA_DEBUG_STREAM_GSTART  uint32[stream_parts][stream_groups + 1]: group
  *                            starts relative to the part's stream
- *   ARA_DEBUG_STREAM_GEND    uint16[stream_parts][stream_groups][32]: end of
+ *   ARA_DEBUG_STREAM_GEND    uint16[stream_parts][stream_groups][64]: end of
  *                            each trial of the group relative to the group's
  *                            start (slots past the group's trials repeat its end)
  * `layer` (its trial range is ignored) is needed for the first three only.

@@ -145,6 +145,10 @@ def lib():
     L.ara_run_layers.restype = i32
     L.ara_risk_metrics.argtypes = [P, i64, P, i32, P, P, P, u32, P]
     L.ara_risk_metrics.restype = i32
+    L.ara_yet_footprint.argtypes = [i64, i64, i64, u32, ctypes.POINTER(i64)]
+    L.ara_yet_footprint.restype = i32
+    L.ara_metrics_footprint.argtypes = [i64, i32, u32, ctypes.POINTER(i64)]
+    L.ara_metrics_footprint.restype = i32
     L.ara_debug_read.argtypes = [P, P, i32, P, i64, ctypes.POINTER(i64), P]
     L.ara_debug_read.restype = i32
     L.ara_risk_metrics_noalloc.argtypes = [P, i64, P, i32, P, P, P, P]
@@ -575,6 +579,20 @@ def footprint(tables: Tables, layers: Sequence[LayerSpec], flags: int = 0) -> in
     arr, keep = _c_layers(layers)
     v = ctypes.c_int64()
     _check(lib().ara_footprint(tables.handle, arr, len(layers), flags, ctypes.byref(v)))
+    return int(v.value)
+
+
+def yet_footprint(n_trials: int, n_events: int, catalogue_size: int, flags: int = 0) -> int:
+    """ara_yet_footprint: device bytes of tables built for a YET of these sizes."""
+    v = ctypes.c_int64()
+    _check(lib().ara_yet_footprint(int(n_trials), int(n_events), int(catalogue_size), int(flags), ctypes.byref(v)))
+    return int(v.value)
+
+
+def metrics_footprint(n_trials: int, n_probs: int, flags: int = ARA_DEVICE_PTR) -> int:
+    """ara_metrics_footprint: scratch bytes of one ara_risk_metrics call."""
+    v = ctypes.c_int64()
+    _check(lib().ara_metrics_footprint(int(n_trials), int(n_probs), int(flags), ctypes.byref(v)))
     return int(v.value)
 
 

@@ -699,6 +699,43 @@ ara_status ara_footprint(const ara_tables* t, const ara_layer* layers, int32_t n
     return ARA_OK;
 }
 
+ara_status ara_yet_footprint(int64_t n_trials, int64_t n_events, int64_t catalogue_size, uint32_t flags,
+                             int64_t* bytes) {
+    if (!bytes || n_trials < 0 || n_events < 0 || catalogue_size < 1)
+        return fail(ARA_ERR_INVALID_ARG, "NULL output or negative size");
+    const int64_t N = n_trials, E = n_events;
+    int64_t b = 8 * (N + 1) + 4 * (E + ara::kIdPad) + 64;          // offsets, IDs, validation flag
+    int64_t temp = 0;
+    if (!(flags & ARA_PLAIN_LAYOUT) && N > 0) {
+        // 32-bit partitioned copy: IDs, segment padding (< 4 per segment,
+        // < 32 per tile), segment starts, tile starts; counts while building
+        const int64_t P = (catalogue_size + (int64_t(1) << ara::kImgShift) - 1) >> ara::kImgShift;
+        if (P <= ara::kMaxParts) {
+            const int64_t T = 256, tiles = (N + T - 1) / T;
+            b += 4 * (E + 3 * N * P + 32 * tiles + ara::kIdPad) + 4 * tiles * (T * P + 1) + 8 * (tiles + 1);
+            temp = std::max(temp, 4 * N * P + 8 * tiles);
+        }
+        // 16-bit copy: IDs (groups of at least 16 trials padded to 8 IDs per
+        // part), trial ends and group starts, part bases; counts while building
+        const int64_t Q = (catalogue_size + (int64_t(1) << ara::kStreamShift) - 1) >> ara::kStreamShift;
+        if (Q <= ara::kMaxStreamParts) {
+            const int64_t NG = (N + 15) / 16;
+            b += 2 * (E + 7 * Q * NG + 512) + 2 * ara::kStreamGroupSlots * Q * NG + 4 * Q * (NG + 1) + 8 * (Q + 1);
+            temp = std::max(temp, 4 * N * Q + 4 * Q * NG + 8 * Q + 4);
+        }
+    }
+    *bytes = b + temp;
+    return ARA_OK;
+}
+
+ara_status ara_metrics_footprint(int64_t n_trials, int32_t n_probs, uint32_t flags, int64_t* bytes) {
+    if (!bytes || n_trials < 0 || n_probs < 0 || n_probs > 4) return fail(ARA_ERR_INVALID_ARG, "bad argument");
+    int64_t b = ara::metrics_scratch_bytes(n_probs, n_trials);
+    if (!(flags & ARA_DEVICE_PTR)) b += 8 * n_trials + 8 * (1 + 2 * static_cast<int64_t>(n_probs));
+    *bytes = b;
+    return ARA_OK;
+}
+
 ara_status ara_run_layers(ara_tables* t, const ara_layer* layers, int32_t n_layers, double* ylt,
                           int64_t ylt_capacity, uint32_t flags, void* stream) {
     if (!t || !layers || n_layers < 1) return fail(ARA_ERR_INVALID_ARG, "NULL argument or no layer");
@@ -1341,7 +1378,7 @@ ara_status ara_debug_read(ara_tables* t, const ara_layer* layer, int32_t what, v
             case ARA_DEBUG_STREAM_IDS: src = st.ids; bytes = sizeof(uint16_t) * st.length; break;
             case ARA_DEBUG_STREAM_BASE: src = st.part_base; bytes = sizeof(int64_t) * (st.P + 1); break;
             case ARA_DEBUG_STREAM_GSTART: src = st.gstart; bytes = sizeof(uint32_t) * st.P * (st.NG + 1); break;
-            default: src = st.gend; bytes = sizeof(uint16_t) * st.P * st.NG * ara::kStreamGroupMax; break;
+            default: src = st.gend; bytes = sizeof(uint16_t) * st.P * st.NG * ara::kStreamGroupSlots; break;
         }
     } else {
         if (!layer) return fail(ARA_ERR_INVALID_ARG, "the fold's outputs need a layer");

@@ -161,7 +161,8 @@ uint32_t* part_superblock_counts(void* part_scratch, int P);
 // 16-byte boundaries (the gap holds 0xFFFF).
 constexpr int kStreamShift = 16;
 constexpr int kMaxStreamParts = 64;
-constexpr int kStreamGroupMax = 32;
+constexpr int kStreamGroupMax = 63;       // trials per group at most (one lane each, plus the group's end)
+constexpr int kStreamGroupSlots = 64;     // trial ends kept per group (slots past the group's trials repeat its end)
 struct StreamLayout {
     int P = 0;                      // stream parts; 0 = layout absent
     int G = 0;                      // trials per group (<= kStreamGroupMax)
@@ -171,7 +172,7 @@ struct StreamLayout {
     uint16_t* ids = nullptr;        // [length + 8 * 64]
     int64_t* part_base = nullptr;   // [P + 1] first ID of each part's stream
     uint32_t* gstart = nullptr;     // [P][NG + 1] group starts relative to the part's stream
-    uint16_t* gend = nullptr;       // [P][NG][32] end of trial i of the group, relative to the group start
+    uint16_t* gend = nullptr;       // [P][NG][64] end of trial i of the group, relative to the group start
 };
 hipError_t build_stream_layout(const int64_t* offsets, const uint32_t* ids, int64_t N, int64_t n_events, int64_t C,
                                int n_cu, hipStream_t s, StreamLayout* out);

@@ -21,12 +21,13 @@
 //    nonzero event, and copies the part's first nonzero o(E) (in rank order)
 //    into the rest of its LDS.  One ID costs one address operation and one
 //    LDS byte read.
-//  * each wave streams one group per batch (two 16-byte loads per lane), the
-//    next batch in flight while this one is tested, and appends the hits in
-//    stream order to its LDS queue.  Lane i holds where trial i starts; the
-//    queue index of its first hit comes from the per-chunk hit masks.  At
-//    the end of the group, lanes 2t and 2t+1 sum trial t's queued losses in
-//    double-double, in queue order, so the result does not depend on timing.
+//  * each wave streams one group (up to 63 trials) in batches of two 16-byte
+//    loads per lane, the next batch in flight while this one is tested, and
+//    appends the hits in stream order to its LDS queue.  Lane i holds where
+//    trial i starts; the queue index of its first hit comes from the
+//    per-chunk hit masks.  At the end of the group lane t sums trial t's
+//    queued losses in double-double, in queue order, so the result does not
+//    depend on timing.
 //  * each (part, trial) partial sum is written once (high part FP64, low part
 //    FP32); the combine adds a trial's partials in part order, rounds once and
 //    applies the aggregate terms.
@@ -83,10 +84,10 @@ __global__ __launch_bounds__(256) void stream_group_kernel(const int32_t* __rest
     const int q = static_cast<int>(k / NG);
     const int64_t g = k - static_cast<int64_t>(q) * NG;
     uint32_t run = 0;
-    for (int i = 0; i < kStreamGroupMax; ++i) {
+    for (int i = 0; i < kStreamGroupSlots; ++i) {
         const int64_t t = g * G + i;
         if (i < G && t < N) run += static_cast<uint32_t>(cnt[t * P + q]);
-        gend[k * kStreamGroupMax + i] = static_cast<uint16_t>(run < 65535u ? run : 65535u);
+        gend[k * kStreamGroupSlots + i] = static_cast<uint16_t>(run < 65535u ? run : 65535u);
     }
     if (run > 65535u) atomicOr(flag, 1u);
     gsize[k] = (run + kChunkIds - 1) & ~static_cast<uint32_t>(kChunkIds - 1);
@@ -151,7 +152,7 @@ __global__ __launch_bounds__(256) void stream_scatter_kernel(const int64_t* __re
         for (int q = lane; q < P; q += 64) {
             const int64_t k = static_cast<int64_t>(q) * NG + g;
             cur[w][q] = part_base[q] + gstart[static_cast<int64_t>(q) * (NG + 1) + g] +
-                        (i ? gend[k * kStreamGroupMax + i - 1] : 0);
+                        (i ? gend[k * kStreamGroupSlots + i - 1] : 0);
         }
         __builtin_amdgcn_wave_barrier();
         const int64_t b = offsets[t], e = offsets[t + 1];
@@ -211,16 +212,6 @@ __device__ __forceinline__ uint32_t stream_wave_scan(uint32_t x) {
     return x;
 }
 
-// the value held by the partner lane (lane ^ 1)
-__device__ __forceinline__ double stream_swap_pair(double v) {
-    const uint64_t b = __double_as_longlong(v);
-    const uint32_t lo = static_cast<uint32_t>(
-        __builtin_amdgcn_mov_dpp(static_cast<int>(static_cast<uint32_t>(b)), 0xB1, 0xF, 0xF, false));
-    const uint32_t hi = static_cast<uint32_t>(
-        __builtin_amdgcn_mov_dpp(static_cast<int>(static_cast<uint32_t>(b >> 32)), 0xB1, 0xF, 0xF, false));
-    return __longlong_as_double(static_cast<int64_t>((static_cast<uint64_t>(hi) << 32) | lo));
-}
-
 __global__ __launch_bounds__(1024) void stream_pass_kernel(StreamPassArgs a) {
     constexpr int kU = 2;                                     // 16-byte loads per lane per batch
     constexpr uint32_t kBatch = 64 * kChunkIds * kU;          // IDs per batch
@@ -242,8 +233,6 @@ __global__ __launch_bounds__(1024) void stream_pass_kernel(StreamPassArgs a) {
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
     uint16_t* q = reinterpret_cast<uint16_t*>(lds + kQueueOff) + wv * kQ;
-    const int pt = lane >> 1;                       // the trial of a group this lane sums (with its partner)
-    const int half = lane & 1;
     const int G = a.G;
     const int64_t count = a.t_hi - a.t_lo;
 
@@ -307,7 +296,7 @@ __global__ __launch_bounds__(1024) void stream_pass_kernel(StreamPassArgs a) {
         if (wa >= wb) continue;
         const uint16_t* ids = a.ids + a.part_base[pq];
         const uint32_t* gs = a.gstart + static_cast<int64_t>(pq) * (a.NG + 1);
-        const uint16_t* ge = a.gend + static_cast<int64_t>(pq) * a.NG * kStreamGroupMax;
+        const uint16_t* ge = a.gend + static_cast<int64_t>(pq) * a.NG * kStreamGroupSlots;
         const double* gcompact = a.compact + g0;
         double* out_hi = a.part_hi + static_cast<int64_t>(pq) * count;
         float* out_lo = a.part_lo + static_cast<int64_t>(pq) * count;
@@ -315,13 +304,12 @@ __global__ __launch_bounds__(1024) void stream_pass_kernel(StreamPassArgs a) {
         auto bounds = [&](int64_t g) -> uint32_t {
             const int64_t gg = g < wb ? g : wb - 1;
             const uint32_t s0 = gs[gg];
-            const int i = lane < kStreamGroupMax ? lane : kStreamGroupMax;
-            return i == 0 ? s0 : s0 + ge[gg * kStreamGroupMax + i - 1];
+            return lane == 0 ? s0 : s0 + ge[gg * kStreamGroupSlots + lane - 1];
         };
         int64_t g = wa;
         uint32_t B = bounds(g), B1 = bounds(g + 1), B2 = bounds(g + 2);
         uint32_t rs = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(B), 0));
-        uint32_t re = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(B), kStreamGroupMax));
+        uint32_t re = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(B), 63));
         uint32_t c = rs;                            // first ID of the batch (a multiple of 8)
         int qs = kInf;                              // lane i: queue index of trial i's first hit
         int qn = 0;                                 // queue entries
@@ -342,18 +330,18 @@ __global__ __launch_bounds__(1024) void stream_pass_kernel(StreamPassArgs a) {
             } else {
                 const uint32_t n_rs = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(B1), 0));
                 const uint32_t n_re =
-                    static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(B1), kStreamGroupMax));
+                    static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(B1), 63));
                 load_batch(n_rs, g + 1 < wb ? n_re : 0u, v);
             }
         };
-        // sum the queued hits: lanes 2t and 2t+1 take trial t's entries
-        // alternately, four at a time per lane
+        // sum the queued hits: lane t takes trial t's entries, four at a time
         auto drain = [&]() {
             constexpr int kR = 4;
-            int lo = __shfl(qs, pt), hi = __shfl(qs, pt + 1);
+            int lo = __shfl(qs, lane), hi = __shfl(qs, (lane + 1) & 63);
             lo = lo < 0 ? 0 : (lo > qn ? qn : lo);
             hi = hi < 0 ? 0 : (hi > qn ? qn : hi);
-            for (int j = lo + half; j < hi; j += 2 * kR) {
+            if (lane >= G) hi = lo;                 // lanes past the group's trials
+            for (int j = lo; j < hi; j += kR) {
                 // each step's loads issued together.  Slots past the trial's last
                 // entry read whatever LDS follows (still inside the allocation),
                 // then the 0.0 after the copied losses, whose sum is exact.
@@ -362,8 +350,8 @@ __global__ __launch_bounds__(1024) void stream_pass_kernel(StreamPassArgs a) {
                 double v[kR];
 #pragma unroll
                 for (int r2 = 0; r2 < kR; ++r2) {
-                    valid[r2] = j + 2 * r2 < hi;
-                    e[r2] = q[j + 2 * r2];
+                    valid[r2] = j + r2 < hi;
+                    e[r2] = q[j + r2];
                 }
                 // rank among the part's nonzero events: the block's base (minus
                 // one) plus the byte, which is 1 + the rank inside the block
@@ -475,12 +463,11 @@ __global__ __launch_bounds__(1024) void stream_pass_kernel(StreamPassArgs a) {
             c += kBatch;
             if (c < re) return true;
             drain();
-            dd_merge(acc_hi, acc_lo, stream_swap_pair(acc_hi), stream_swap_pair(acc_lo));
             {
                 const double s_hi = acc_hi + acc_lo;          // renormalised: |lo| <= ulp(hi) / 2
                 const double s_lo = acc_lo - (s_hi - acc_hi);
-                const int64_t t = g * G + pt;
-                if (half == 0 && pt < G && t >= a.t_lo && t < a.t_hi) {
+                const int64_t t = g * G + lane;
+                if (lane < G && t >= a.t_lo && t < a.t_hi) {
                     out_hi[t - a.t_lo] = s_hi;
                     out_lo[t - a.t_lo] = static_cast<float>(s_lo);
                 }
@@ -494,7 +481,7 @@ __global__ __launch_bounds__(1024) void stream_pass_kernel(StreamPassArgs a) {
             B1 = B2;
             B2 = bounds(g + 2);
             rs = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(B), 0));
-            re = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(B), kStreamGroupMax));
+            re = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(B), 63));
             c = rs;
             return true;
         };
@@ -538,7 +525,7 @@ __global__ __launch_bounds__(256) void stream_combine_kernel(const double* __res
 int choose_group_trials(double lam) {
     int best_g = kStreamGroupMax;
     double best = 1e300;
-    for (int g = kStreamGroupMax; g >= 8; --g) {
+    for (int g = kStreamGroupMax; g >= 16; --g) {
         const double mean = g * lam, sd = std::sqrt(mean > 0.0 ? mean : 0.0);
         const double chunks = (mean + 2.5 * sd) / kChunkIds + 1.0;
         const double loads = std::ceil(chunks / 64.0);
@@ -575,7 +562,7 @@ hipError_t build_stream_layout(const int64_t* offsets, const uint32_t* ids, int6
     if ((e = hipMalloc(&gsize, sizeof(uint32_t) * n_grp)) != hipSuccess) goto fail;
     if ((e = hipMalloc(&plen, sizeof(uint64_t) * P)) != hipSuccess) goto fail;
     if ((e = hipMalloc(&flag, sizeof(uint32_t))) != hipSuccess) goto fail;
-    if ((e = hipMalloc(&out->gend, sizeof(uint16_t) * n_grp * kStreamGroupMax)) != hipSuccess) goto fail;
+    if ((e = hipMalloc(&out->gend, sizeof(uint16_t) * n_grp * kStreamGroupSlots)) != hipSuccess) goto fail;
     if ((e = hipMalloc(&out->gstart, sizeof(uint32_t) * P * (NG + 1))) != hipSuccess) goto fail;
     if ((e = hipMalloc(&out->part_base, sizeof(int64_t) * (P + 1))) != hipSuccess) goto fail;
     if ((e = hipMemsetAsync(flag, 0, sizeof(uint32_t), s)) != hipSuccess) goto fail;
@@ -623,7 +610,7 @@ hipError_t build_stream_layout(const int64_t* offsets, const uint32_t* ids, int6
     out->G = G;
     out->NG = NG;
     out->bytes = static_cast<int64_t>(sizeof(uint16_t)) * (out->length + kStreamPad) +
-                 static_cast<int64_t>(sizeof(uint16_t)) * n_grp * kStreamGroupMax +
+                 static_cast<int64_t>(sizeof(uint16_t)) * n_grp * kStreamGroupSlots +
                  static_cast<int64_t>(sizeof(uint32_t)) * P * (NG + 1) + static_cast<int64_t>(sizeof(int64_t)) * (P + 1);
     return hipSuccess;
 fail:

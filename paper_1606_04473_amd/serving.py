@@ -4,20 +4,21 @@ The paper runs several clients ("tenants") on virtual GPUs mapped onto one
 physical GPU, so that one tenant's host-to-device transfer overlaps another's
 kernel, and compares two transfer modes (Section V-D): *concurrent* (every
 device receives its data at once, sharing the link) and *sequential* (one
-transfer at a time at full link bandwidth while others compute).  Here a
-tenant is a worker thread with its own HIP stream; tenants share one GPU, the
-resident ELT pool and, in "resident" mode, the resident YET.
+transfer at a time at full link bandwidth while others compute).  Here the
+tenants' requests share a pool of slots, each a worker thread with its own
+HIP stream; slots share one GPU, the resident ELT pool and, in "resident"
+mode, the resident YET.
 
 Each request is an analysis: a slice of trials of the YET and 1-16 layers.
 Shipped modes copy the slice to the device (Algorithm 2) -- concurrently or
 under a FIFO transfer token -- and build tables for it that share the
 resident ELT pool (ara_create_yet); resident mode runs the layers on trial
 ranges of the resident YET.  Admission is by device memory: a request waits
-(FIFO) until its footprint fits the budget, then runs as soon as its tenant is
-free, overlapping with the other tenants' work (continuous batching: requests
-are admitted as slots and memory free up, not in fixed batches).  Results
-carry arrival, admission, start and finish times; latency is finish minus
-arrival.
+(FIFO) until its footprint -- the library's own count of what it will hold --
+fits the budget, then runs in the slot that took it, overlapping with the
+other slots' work (continuous batching: requests are admitted as slots and
+memory free up, not in fixed batches).  Results carry arrival, admission,
+start and finish times; latency is finish minus arrival.
 """
 
 from __future__ import annotations
@@ -109,6 +110,8 @@ class Result:
     footprint: int = 0
     metrics: List[List[float]] = field(default_factory=list)   # per layer [mean, pml.., tvar..]
     error: Optional[str] = None
+    phases: Dict[str, float] = field(default_factory=dict)     # seconds: ship, build, compute
+    stream_layout: bool = False           # the request's tables hold the 16-bit copy
 
     @property
     def latency(self) -> float:
@@ -152,7 +155,11 @@ def percentile(x: Sequence[float], q: float) -> float:
 def summarize(results: Sequence[Result], wall: float) -> Dict[str, float]:
     ok = [r for r in results if r.error is None]
     lat = [r.latency for r in ok]
+    phases = {f"{k}_ms_mean": float(np.mean([r.phases[k] for r in ok if k in r.phases])) * 1e3
+              for k in ("ship", "build", "compute") if any(k in r.phases for r in ok)}
     return {
+        **phases,
+        "fast_layout_requests": sum(1 for r in ok if r.stream_layout),
         "requests": len(results),
         "completed": len(ok),
         "rejected": len(results) - len(ok),
@@ -176,16 +183,27 @@ def pin_ids(ids: np.ndarray):
 
 
 class Server:
-    """Runs requests for n_tenants tenants on one GPU.
+    """Serves requests on one GPU from a shared pool of `n_slots` slots.
 
     base:     resident tables (ELT pool and, for resident mode, the YET);
     offsets, ids: the host YET the requests slice (ids pinned by the server);
     library:  LayerSpec list (trial ranges are replaced per request);
-    probs:    risk-metric probabilities reported per layer.
+    probs:    risk-metric probabilities reported per layer;
+    budget_bytes: the device bytes requests may hold at once; None = the
+              device's free memory when the server starts, less `reserve`.
+
+    Requests wait in one arrival-ordered queue whatever their tenant; a free
+    slot (a worker thread with its own HIP stream) takes the oldest arrived
+    one, waits for admission by device memory (FIFO, the request's footprint
+    from the library's own counts), then ships its YET slice (or uses the
+    resident YET), runs its layers and metrics, and frees its memory.
+    Requests that arrive while others run are admitted as slots and memory
+    free up, and their work overlaps on the device.
     """
 
-    def __init__(self, base, offsets: np.ndarray, ids: np.ndarray, library, n_tenants: int,
-                 mode: str, budget_bytes: int, probs=(0.99,), pinned_ids=None):
+    def __init__(self, base, offsets: np.ndarray, ids: np.ndarray, library, n_slots: int,
+                 mode: str, budget_bytes: Optional[int] = None, probs=(0.99,), pinned_ids=None,
+                 reserve: int = 2 << 30):
         import torch
         from . import ara
         if mode not in MODES:
@@ -195,26 +213,37 @@ class Server:
         self.base = base
         self.offsets = np.ascontiguousarray(offsets, dtype=np.int64)
         self.library = list(library)
-        self.n_tenants = n_tenants
+        self.n_slots = n_slots
         self.mode = mode
         self.probs = list(probs)
+        self.free_bytes_at_start = int(torch.cuda.mem_get_info()[0])
+        if budget_bytes is None:
+            budget_bytes = max(self.free_bytes_at_start - reserve, 0)
         self.admission = AdmissionController(budget_bytes)
         self.transfer_token = threading.Lock()
         self.device = torch.device("cuda", torch.cuda.current_device())
-        self.streams = [torch.cuda.Stream() for _ in range(n_tenants)]
+        self.streams = [torch.cuda.Stream() for _ in range(n_slots)]
         self.host_ids = pinned_ids
         if mode != "resident" and self.host_ids is None:
             self.host_ids = pin_ids(ids)
 
     def footprint(self, req: Request) -> int:
-        n_ev = int(self.offsets[req.trial_begin + req.n_trials] - self.offsets[req.trial_begin])
-        out = 8 * req.n_trials * len(req.layer_ids) + 8 * (1 + 2 * len(self.probs)) * len(req.layer_ids)
-        scratch = 8 * self.base.catalogue_size * 2 + 8 * 1024 * 1024   # occurrence losses, images, compact
-        if self.mode == "resident":
-            return out + scratch
-        yet = 4 * n_ev + 8 * (req.n_trials + 1)
-        # staging copy + owned copy + partitioned copy (~ the IDs again, padded)
-        return 2 * yet + 5 * n_ev + 16 * req.n_trials + out + scratch
+        """Device bytes the request holds at its peak, from the library's counts:
+        its shipped YET (the device copy it is shipped into, then the tables
+        built from it, with their build temporaries), the scratch of its
+        largest ara_run_layers call, the metrics scratch and its outputs."""
+        ara = self.ara
+        n = req.n_trials
+        n_ev = int(self.offsets[req.trial_begin + n] - self.offsets[req.trial_begin])
+        k = len(self.probs)
+        b = 8 * n + 8 * (1 + 2 * k) * len(req.layer_ids)                 # YLT and metrics outputs
+        b += ara.metrics_footprint(n, k, ara.ARA_DEVICE_PTR)
+        specs = self._layers_for(req, 0 if self.mode != "resident" else req.trial_begin)
+        b += max(ara.footprint(self.base, [s], ara.ARA_DEVICE_PTR) for s in specs)
+        if self.mode != "resident":
+            b += 4 * n_ev + 8 * (n + 1)                                    # the shipped slice
+            b += ara.yet_footprint(n, n_ev, self.base.catalogue_size)
+        return b
 
     def _layers_for(self, req: Request, begin: int):
         specs = []
@@ -224,10 +253,15 @@ class Server:
                                             s.occ_limit, s.agg_retention, s.agg_limit, begin, req.n_trials))
         return specs
 
-    def _serve_one(self, req: Request, res: Result, t0: float) -> None:
+    def _serve_one(self, req: Request, res: Result, slot: int, t0: float) -> None:
         torch, ara = self.torch, self.ara
-        stream = self.streams[req.tenant]
-        nb = self.footprint(req)
+        stream = self.streams[slot]
+        try:
+            nb = self.footprint(req)
+        except Exception as exc:              # e.g. a layer the library rejects
+            res.error = f"{type(exc).__name__}: {exc}"
+            res.finished = time.perf_counter() - t0
+            return
         res.footprint = nb
         if not self.admission.acquire(nb):
             res.error = "footprint exceeds the device-memory budget"
@@ -240,6 +274,7 @@ class Server:
                 res.started = time.perf_counter() - t0
                 if self.mode == "resident":
                     tables, begin = self.base, req.trial_begin
+                    res.stream_layout = tables.layout()["stream_parts"] > 0
                 else:
                     lo = int(self.offsets[req.trial_begin])
                     hi = int(self.offsets[req.trial_begin + req.n_trials])
@@ -247,6 +282,7 @@ class Server:
                     off = off.pin_memory()
                     d_ids = torch.empty(hi - lo, dtype=torch.int32, device=self.device)
                     d_off = torch.empty(req.n_trials + 1, dtype=torch.int64, device=self.device)
+                    tp = time.perf_counter()
                     if self.mode == "sequential":
                         with self.transfer_token:
                             d_ids.copy_(self.host_ids[lo:hi], non_blocking=True)
@@ -255,17 +291,23 @@ class Server:
                     else:
                         d_ids.copy_(self.host_ids[lo:hi], non_blocking=True)
                         d_off.copy_(off, non_blocking=True)
+                    tb = time.perf_counter()
                     tables = ara.create_yet(self.base, d_off, d_ids, stream=stream)
+                    res.phases["ship"] = tb - tp
+                    res.phases["build"] = time.perf_counter() - tb
+                    res.stream_layout = tables.layout()["stream_parts"] > 0
                     del d_ids, d_off
                     begin = 0
                 specs = self._layers_for(req, begin)
                 k = len(self.probs)
+                tc = time.perf_counter()
                 ylt = torch.empty(req.n_trials, dtype=torch.float64, device=self.device)
                 out = torch.empty((len(specs), 1 + 2 * k), dtype=torch.float64, device=self.device)
                 for i, s in enumerate(specs):
                     ara.run_layers(tables, [s], out=ylt, stream=stream)
                     ara.risk_metrics(ylt, self.probs, outputs=out[i], stream=stream)
-                host = out.cpu()              # waits for this tenant's stream only
+                host = out.cpu()              # waits for this slot's stream only
+                res.phases["compute"] = time.perf_counter() - tc
                 res.metrics = host.numpy().tolist()
         except Exception as exc:              # a poisoned request fails alone
             res.error = f"{type(exc).__name__}: {exc}"
@@ -276,23 +318,25 @@ class Server:
             self.admission.release(nb)
 
     def run(self, requests: Sequence[Request], time_scale: float = 1.0) -> List[Result]:
-        """Serve `requests` (arrival times scaled by time_scale).  One worker
-        per tenant takes that tenant's requests in arrival order."""
-        per_tenant: Dict[int, List[Request]] = {k: [] for k in range(self.n_tenants)}
-        for r in requests:
-            per_tenant[r.tenant % self.n_tenants].append(r)
+        """Serve `requests`, each arriving at arrival * time_scale seconds
+        (time_scale 0: all at once, a closed loop at saturation)."""
+        queue = deque(sorted(requests, key=lambda r: (r.arrival, r.rid)))
         results = {r.rid: Result(r.rid, r.tenant, r.arrival * time_scale) for r in requests}
+        lock = threading.Lock()
         t0 = time.perf_counter()
 
-        def worker(k: int) -> None:
-            for r in per_tenant[k]:
+        def slot(k: int) -> None:
+            while True:
+                with lock:
+                    if not queue:
+                        return
+                    r = queue.popleft()
                 wait = r.arrival * time_scale - (time.perf_counter() - t0)
                 if wait > 0:
                     time.sleep(wait)
-                rr = Request(r.rid, k, r.arrival, r.trial_begin, r.n_trials, r.layer_ids)
-                self._serve_one(rr, results[r.rid], t0)
+                self._serve_one(r, results[r.rid], k, t0)
 
-        threads = [threading.Thread(target=worker, args=(k,)) for k in range(self.n_tenants)]
+        threads = [threading.Thread(target=slot, args=(k,)) for k in range(self.n_slots)]
         for th in threads:
             th.start()
         for th in threads:
@@ -302,37 +346,60 @@ class Server:
         return [results[r.rid] for r in requests]
 
 
+def admission_summary(results: Sequence[Result], controller: AdmissionController) -> Dict[str, float]:
+    """Admission by device memory: how many requests waited for memory and how
+    long (from taking a slot to admission), the budget and the peak held, and
+    the p99 of arrival to admission (waits for a slot and for memory)."""
+    waits = [w for w in controller.waits]
+    queued = [r.admitted - r.arrival for r in results if r.error is None and not math.isnan(r.admitted)]
+    return {"budget_bytes": controller.budget, "peak_bytes": controller.peak,
+            "admission_waits_over_1ms": int(sum(1 for w in waits if w > 1e-3)),
+            "admission_wait_p50_ms": percentile(waits, 50) * 1e3,
+            "admission_wait_p99_ms": percentile(waits, 99) * 1e3,
+            "queue_to_admission_p99_ms": percentile(queued, 99) * 1e3}
+
+
 def run_tenant_study(base, offsets, ids, library, n_tenants: int = 8, per_tenant: int = 6,
-                     seed: int = 160604478, budget_bytes: int = 160 << 30, probs=(0.99,),
+                     seed: int = 160604478, budget_bytes: Optional[int] = 16 << 30, probs=(0.99,),
                      load: float = 0.7, modes: Sequence[str] = ("concurrent", "sequential", "resident"),
                      log=None) -> Dict[str, object]:
-    """Config-4 study: requests with Poisson arrivals at `load` times the
-    single-tenant capacity, served by n_tenants tenants in each transfer mode
-    and by one tenant; p50/p99 latency and throughput for each."""
+    """Config-4 study.  Requests of n_tenants tenants (Poisson arrivals at
+    `load` times the one-slot capacity) served from one slot and from
+    n_tenants slots in each transfer mode: p50/p99 latency, throughput and
+    admission waits under a device-memory budget (16 GiB by default, standing
+    in for a GPU shared with other work, so that admission binds; None = the
+    free memory).  Then the same requests all at once (closed loop): the
+    capacity in requests per second of each mode and slot count."""
     n_yet = int(offsets.shape[0] - 1)
     pinned = pin_ids(ids)
-    # capacity: one tenant, requests back to back, shipped concurrently
+    # one-slot capacity, requests back to back, shipped concurrently
     probe = make_requests(1, 6, 0.0, n_yet, len(library), seed=seed + 77)
-    for r in probe:
-        r.arrival = 0.0
     srv = Server(base, offsets, ids, library, 1, "concurrent", budget_bytes, probs, pinned)
     srv.run(probe[:1], 0.0)                                   # warm-up
     res = srv.run(probe, 0.0)
     service = srv.wall / max(len(res), 1)
     rate_total = load / service
     reqs = make_requests(n_tenants, per_tenant, rate_total / n_tenants, n_yet, len(library), seed=seed)
-    out: Dict[str, object] = {"service_ms_one_tenant": service * 1e3, "arrival_rate_req_s": rate_total,
-                              "load": load, "tenants": n_tenants, "requests": len(reqs)}
+    out: Dict[str, object] = {"service_ms_one_slot": service * 1e3, "arrival_rate_req_s": rate_total,
+                              "load": load, "tenants": n_tenants, "requests": len(reqs),
+                              "budget_bytes": srv.admission.budget,
+                              "free_device_bytes": srv.free_bytes_at_start}
     for mode in modes:
         for k in (1, n_tenants):
             s = Server(base, offsets, ids, library, k, mode, budget_bytes, probs, pinned)
             r = s.run(reqs, 1.0)
             summ = summarize(r, s.wall)
-            summ["admission_peak_bytes"] = s.admission.peak
+            summ.update(admission_summary(r, s.admission))
+            closed = Server(base, offsets, ids, library, k, mode, budget_bytes, probs, pinned)
+            rc = closed.run(reqs, 0.0)
+            summ["capacity_req_s"] = summarize(rc, closed.wall)["throughput_req_s"]
+            summ["capacity_admission_waits_over_1ms"] = admission_summary(rc, closed.admission)[
+                "admission_waits_over_1ms"]
             out[f"{mode}_{k}t"] = summ
             if log:
-                log(f"serving {mode} tenants={k}: p50 {summ['p50_ms']:.1f} ms p99 {summ['p99_ms']:.1f} ms "
-                    f"{summ['throughput_req_s']:.2f} req/s")
+                log(f"serving {mode} slots={k}: p50 {summ['p50_ms']:.1f} ms p99 {summ['p99_ms']:.1f} ms, "
+                    f"{summ['throughput_req_s']:.2f} req/s offered, capacity {summ['capacity_req_s']:.2f} req/s, "
+                    f"{summ['admission_waits_over_1ms']} admission waits (p99 {summ['admission_wait_p99_ms']:.1f} ms)")
     return out
 
 
@@ -432,11 +499,15 @@ def fit_split_model(transfer_s: float, compute_s: float, fixed_s: float, w_idle:
 
 
 def split_study(base, offsets, pinned_ids, library, layer_ids: Sequence[int], tenants=(1, 2, 4, 8),
-                modes=("concurrent", "sequential"), probs=(0.99,), repeats: int = 2, log=None) -> Dict[str, object]:
+                modes=("concurrent", "sequential"), probs=(0.99,), repeats: int = 3, window_s: float = 1.5,
+                log=None) -> Dict[str, object]:
     """The whole YET analysed with `layer_ids`, split over v tenants on one
     GPU (each ships its slice, builds its tables, runs the layers and the
     metrics), for each transfer mode; wall time, energy and activity per
-    (mode, v), and the model's prediction from single-tenant components."""
+    (mode, v), and the model's prediction from single-tenant components.
+    Energy per analysis comes from `repeats` rounds (every (mode, v) once per
+    round, in rotated order) of a fixed window of back-to-back analyses:
+    median and range over the rounds, gross and above the idle power."""
     import torch
     from . import ara
     from .perf_model import Platform   # noqa: F401  (documents the dependency)
@@ -517,77 +588,100 @@ def split_study(base, offsets, pinned_ids, library, layer_ids: Sequence[int], te
         "transfer_s": t_ship, "compute_s": t_comp, "build_s": t_build, "fixed_per_tenant_s": t_fixed,
         "power_idle_w": w_idle, "power_busy_w": w_busy}, "runs": {}}
 
-    for mode in modes:
-        for v in tenants:
-            streams = [torch.cuda.Stream() for _ in range(v)]
-            token = threading.Lock()
-            errors: List[str] = []
+    def make_runner(mode: str, v: int):
+        streams = [torch.cuda.Stream() for _ in range(v)]
+        token = threading.Lock()
+        errors: List[str] = []
+        built: List[object] = []
 
-            built: List[object] = []
-
-            def tenant(k: int, b: int, c: int) -> None:
-                try:
-                    s = streams[k]
-                    with torch.cuda.stream(s):
-                        if mode == "sequential":
-                            with token:
-                                d_off, d_ids = ship(b, c, s)
-                                s.synchronize()
-                        else:
+        def tenant(k: int, b: int, c: int) -> None:
+            try:
+                s = streams[k]
+                with torch.cuda.stream(s):
+                    if mode == "sequential":
+                        with token:
                             d_off, d_ids = ship(b, c, s)
-                        tab = ara.create_yet(base, d_off, d_ids, stream=s)
-                        del d_off, d_ids
-                        compute(tab, 0, c, s)
-                        s.synchronize()
-                        built.append(tab)     # freed after the run: a free waits for the whole device
-                except Exception as exc:  # reported, not raised inside the thread
-                    errors.append(f"{type(exc).__name__}: {exc}")
+                            s.synchronize()
+                    else:
+                        d_off, d_ids = ship(b, c, s)
+                    tab = ara.create_yet(base, d_off, d_ids, stream=s)
+                    del d_off, d_ids
+                    compute(tab, 0, c, s)
+                    s.synchronize()
+                    built.append(tab)     # freed after the run: a free waits for the whole device
+            except Exception as exc:  # reported, not raised inside the thread
+                errors.append(f"{type(exc).__name__}: {exc}")
 
-            def once() -> float:
-                torch.cuda.synchronize()
-                ths = [threading.Thread(target=tenant, args=(k, b, c))
-                       for k, (b, c) in enumerate(split_ranges(n, v))]
-                t0 = time.perf_counter()
-                for th in ths:
-                    th.start()
-                for th in ths:
-                    th.join()
-                torch.cuda.synchronize()
-                wall = time.perf_counter() - t0
-                for tab in built:
-                    tab.close()
-                built.clear()
-                return wall
+        def once() -> float:
+            torch.cuda.synchronize()
+            ths = [threading.Thread(target=tenant, args=(k, b, c)) for k, (b, c) in enumerate(split_ranges(n, v))]
+            t0 = time.perf_counter()
+            for th in ths:
+                th.start()
+            for th in ths:
+                th.join()
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            for tab in built:
+                tab.close()
+            built.clear()
+            return wall
 
-            best = once()
-            # energy: the analysis back to back for >= 2 s inside one sampling
-            # window (the power readings are too coarse for a single run); the
-            # tables' frees between runs fall inside the window too
-            k_runs = max(repeats, int(math.ceil(2.0 / max(best, 1e-3))))
-            energy = None
+        return once, errors
+
+    combos = [(mode, v) for mode in modes for v in tenants]
+    runners = {c: make_runner(*c) for c in combos}
+    times = {c: [] for c in combos}
+    energy = {c: [] for c in combos}
+    for c in combos:
+        times[c].append(runners[c][0]())                     # warm-up, timed
+    # energy: every (mode, v) in turn, `repeats` rounds in rotated order, each a
+    # fixed window of back-to-back analyses sampled as one: energy per analysis
+    # = mean power x window / analyses, gross and above idle power
+    for rnd in range(repeats):
+        order = combos[rnd % len(combos):] + combos[:rnd % len(combos)]
+        for c in order:
+            once = runners[c][0]
             with sampler:
-                for _ in range(k_runs):
-                    best = min(best, once())
+                t_start = time.perf_counter()
+                k_runs = 0
+                while time.perf_counter() - t_start < window_s:
+                    times[c].append(once())
+                    k_runs += 1
+                span = time.perf_counter() - t_start
             summ = sampler.summary()
             if summ:
-                # the window also holds the frees and thread starts between runs:
-                # energy per analysis = the window's mean power x the analysis time
-                energy = {"mean_power_w": summ["mean_power_w"],
-                          "mean_gfx_activity_pct": summ["mean_gfx_activity_pct"],
-                          "energy_j": summ["mean_power_w"] * best, "window_energy_j": summ["energy_j"],
-                          "runs_in_window": k_runs, "samples": summ["samples"]}
-            rec = {"time_s": best, "model_time_s": model.exec_time(1, v),
-                   "model_fully_overlapped_s": model.time_fully_overlapped(1, v),
-                   "model_not_overlapped_s": model.time_not_overlapped(1, v)}
-            if energy:
-                rec.update(energy)
-                rec["model_energy_j"] = model.energy(1, v)
-            if errors:
-                rec["errors"] = errors[:3]
-            out["runs"][f"{mode}_{v}"] = rec
-            if log:
-                en = f", {energy['energy_j']:.1f} J" if energy else ""
-                log(f"split {mode} v={v}: {best * 1e3:.1f} ms (model {rec['model_time_s'] * 1e3:.1f} ms){en}")
+                e = {"gross_j": summ["mean_power_w"] * span / k_runs, "mean_power_w": summ["mean_power_w"],
+                     "activity_pct": summ["mean_gfx_activity_pct"], "analyses": k_runs}
+                if w_idle is not None:
+                    e["net_j"] = (summ["mean_power_w"] - w_idle) * span / k_runs
+                energy[c].append(e)
+    for c in combos:
+        mode, v = c
+        t = times[c]
+        rec = {"time_s": min(t), "time_median_s": float(np.median(t)), "runs": len(t),
+               "model_time_s": model.exec_time(1, v), "model_fully_overlapped_s": model.time_fully_overlapped(1, v),
+               "model_not_overlapped_s": model.time_not_overlapped(1, v)}
+        es = energy[c]
+        if es:
+            g = [e["gross_j"] for e in es]
+            rec.update({"energy_j": float(np.median(g)), "energy_j_min": min(g), "energy_j_max": max(g),
+                        "mean_power_w": float(np.median([e["mean_power_w"] for e in es])),
+                        "rounds": len(es), "analyses_per_window": [e["analyses"] for e in es],
+                        "model_energy_j": model.energy(1, v)})
+            acts = [e["activity_pct"] for e in es if e["activity_pct"] is not None]
+            rec["mean_gfx_activity_pct"] = float(np.median(acts)) if acts else None
+            if "net_j" in es[0]:
+                nj = [e["net_j"] for e in es]
+                rec.update({"energy_above_idle_j": float(np.median(nj)), "energy_above_idle_j_min": min(nj),
+                            "energy_above_idle_j_max": max(nj)})
+        if runners[c][1]:
+            rec["errors"] = runners[c][1][:3]
+        out["runs"][f"{mode}_{v}"] = rec
+        if log:
+            en = (f", {rec['energy_j']:.1f} J [{rec['energy_j_min']:.1f}, {rec['energy_j_max']:.1f}]"
+                  if "energy_j" in rec else "")
+            log(f"split {mode} v={v}: {rec['time_s'] * 1e3:.1f} ms (model {rec['model_time_s'] * 1e3:.1f} ms){en}")
     best_key = min(out["runs"], key=lambda k: out["runs"][k]["time_s"])
     model_v = min(tenants, key=lambda v: model.exec_time(1, v))
     out["best_measured"] = best_key

@@ -127,7 +127,7 @@ def _expected_stream(yet, G):
     tq_pad = np.zeros((NG * G, P), dtype=np.int64)
     tq_pad[:N] = tq
     ends = np.cumsum(tq_pad.reshape(NG, G, P), axis=1)             # [NG][G][P]
-    gend = np.zeros((P, NG, 32), dtype=np.int64)
+    gend = np.zeros((P, NG, 64), dtype=np.int64)
     gend[:, :, :G] = ends.transpose(2, 0, 1)
     gend[:, :, G:] = gend[:, :, G - 1:G]
     return stream, base, gstart, gend
@@ -136,7 +136,7 @@ def _expected_stream(yet, G):
 def _check_stream(ara, tables, yet):
     lay = tables.layout()
     G = lay["stream_group_trials"]
-    assert 8 <= G <= 32 and lay["stream_parts"] == (yet.catalogue_size + 65535) >> 16
+    assert 16 <= G <= 63 and lay["stream_parts"] == (yet.catalogue_size + 65535) >> 16
     stream, base, gstart, gend = _expected_stream(yet, G)
     assert lay["stream_ids"] == stream.shape[0]
     assert np.array_equal(ara.debug_read(tables, ara.DEBUG_STREAM_IDS), stream)
@@ -147,7 +147,7 @@ def _check_stream(ara, tables, yet):
 
 def test_stream_copy_is_the_yet(ara):
     """config0 (two parts), a 20-part catalogue with ragged trials, and trials
-    of 0-3 events (groups of 32, mostly empty segments)."""
+    of 0-3 events (groups of 63, mostly empty segments)."""
     w = make_config("config0")
     for yet in (w.yet, make_yet(3000, 150.0, 1_300_000, seed=183), make_yet(5000, 1.5, 300_000, seed=184)):
         pool = make_elt_pool(1, yet.catalogue_size, 10, seed=185)

@@ -795,9 +795,9 @@ def test_dense_elts_fold(ara):
 
 def test_stream_pass_group_shapes(ara):
     """The 16-bit streaming pass on the shapes its layout takes: trials of 0-4
-    events (32-trial groups of a few IDs per part, many empty segments and
-    empty groups), and trials of ~6000 events (8-trial groups of ~12 000 IDs
-    per part: a dozen batches per group, queues drained part-way through a
+    events (63-trial groups of a few IDs per part, many empty segments and
+    empty groups), and trials of ~6000 events (16-trial groups of ~24 000 IDs
+    per part: two dozen batches per group, queues drained part-way through a
     group, more nonzero losses per part than the LDS copy holds).  Sub-ranges
     start and end inside groups.  Every pass variant against the oracle."""
     C = 200_000
@@ -1010,4 +1010,49 @@ def test_autotuner_choices_keep_parity(ara, tmp_path):
     best = autotune.tuned(tables, [spec], out, path=str(tmp_path / "c.json"), repeats=1)
     got = ara.get_tuning(tables)
     assert all(got[k] == v for k, v in best.items()), (got, best)
+    tables.close()
+
+
+def test_autotuner_many_layers(ara, tmp_path):
+    """The tuner on five layers of uneven ELT counts and trial ranges: every
+    candidate (per-layer streaming and XCD-affine sequences, the persistent
+    launch with four lane counts and two schedules) records a nonzero device
+    time, the timings differ, the choice is the fastest, it keeps parity, and
+    the cached choice is reused."""
+    import torch
+    from paper_1606_04473_amd import autotune
+    C = 1_100_000
+    yet = make_yet(20_000, 120.0, C, seed=301)
+    pool = make_elt_pool(24, C, 30_000, seed=302)
+    rng = np.random.default_rng(303)
+    layers = []
+    for k in range(5):
+        J = int(rng.integers(1, 25))
+        idx = rng.choice(24, size=J, replace=False).astype(np.int32)
+        n = int(rng.integers(2000, yet.n_trials + 1))
+        b = int(rng.integers(0, yet.n_trials - n + 1))
+        layers.append(Layer(idx, 1500.0 + 100 * k, 5.0e5, 2.0e4 * (k + 1), 6.0e5, b, n))
+    specs = [_spec(ara, l, pool, yet) for l in layers]
+    tables = ara.create_tables(yet.offsets, yet.ids, pool.losses)
+    ref = np.concatenate([oracle.run_layer(yet, pool, l)[0] for l in layers])
+    out = torch.empty(ref.shape[0], dtype=torch.float64, device="cuda")
+    res = autotune.tune(tables, specs, out, repeats=2)
+    ms = [t for t, _ in res["timings"]]
+    assert len(ms) == len(autotune.candidates(len(specs))) and all(t > 0.0 for t in ms)
+    assert len(set(ms)) > 1 and res["best_ms"] == min(ms)
+    assert any("batched_ms" in d for d in res["detail"]) and any("trial_pass_ms" in d for d in res["detail"])
+    ok, worst = _close(ara.run_layers(tables, specs), ref)       # with the chosen knobs
+    assert ok, (res["best"], worst)
+    for _, knobs in res["timings"]:
+        ara.set_tuning(tables, **knobs)
+        ok, worst = _close(ara.run_layers(tables, specs), ref)
+        assert ok, (knobs, worst)
+    report = {}
+    best = autotune.tuned(tables, specs, out, path=str(tmp_path / "c.json"), repeats=1, report=report)
+    assert report["cached"] is False
+    again = {}
+    assert autotune.tuned(tables, specs, out, path=str(tmp_path / "c.json"), report=again) == best
+    assert again["cached"] is True
+    got = ara.get_tuning(tables)
+    assert all(got[k] == v for k, v in best.items())
     tables.close()

@@ -65,6 +65,33 @@ def test_percentile_and_summary():
     assert s["completed"] == 2 and s["rejected"] == 1 and s["p99_ms"] == 1000.0
 
 
+def test_power_sampler_summary_on_synthetic_samples():
+    """Energy is the trapezoid integral of the power samples over time; mean
+    power is that energy over the sampled span; activity is the mean of the
+    samples that report one."""
+    from paper_1606_04473_amd.serving import PowerSampler
+    s = PowerSampler.__new__(PowerSampler)
+    s.samples = [(10.0, 100.0, 50.0), (11.0, 200.0, 60.0), (13.0, 200.0, None)]
+    r = s.summary()
+    assert r["energy_j"] == 0.5 * (100.0 + 200.0) * 1.0 + 0.5 * (200.0 + 200.0) * 2.0
+    assert r["mean_power_w"] == r["energy_j"] / 3.0
+    assert r["mean_gfx_activity_pct"] == 55.0 and r["samples"] == 3
+    s.samples = [(0.0, 300.0, None), (0.5, 300.0, None), (2.0, 300.0, None)]
+    r = s.summary()
+    assert r["energy_j"] == 600.0 and r["mean_power_w"] == 300.0 and r["mean_gfx_activity_pct"] is None
+    s.samples = [(0.0, 5.0, 1.0)]
+    assert s.summary() is None
+
+
+def test_split_ranges_cover_the_trials():
+    from paper_1606_04473_amd.serving import split_ranges
+    for n, v in ((10, 3), (7, 8), (1_000_000, 8)):
+        r = split_ranges(n, v)
+        assert len(r) == v and sum(c for _, c in r) == n
+        assert all(r[i][0] + r[i][1] == r[i + 1][0] for i in range(v - 1))
+        assert max(c for _, c in r) - min(c for _, c in r) <= 1
+
+
 @pytest.mark.gpu
 def test_alone_equals_mix_all_modes():
     import torch
@@ -126,8 +153,9 @@ def test_autotune_cache_and_shape_class(tmp_path):
 
     one = autotune.shape_class(T, [L(16, 1_000_000)])
     many = autotune.shape_class(T, [L(16, 500_000)] * 64)
-    assert one.startswith("P8-ev10-") and one.endswith("-one-J4") and "-many-" in many
-    assert len(autotune.candidates(1)) == 3 and len(autotune.candidates(64)) == 6
+    assert one.startswith("P31-ev10-") and one.endswith("-one-J4") and "-many-" in many
+    assert len(autotune.candidates(1)) == 4 and len(autotune.candidates(64)) == 8
+    assert {c["pass_variant"] for c in autotune.candidates(64)} == {0, 1, 2}
     path = str(tmp_path / "cache.json")
     assert autotune.load_cache(path) == {}
     autotune.save_cache({"k": {"part_lanes_per_trial": 32}}, path)
