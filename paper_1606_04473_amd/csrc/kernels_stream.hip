@@ -200,6 +200,20 @@ struct StreamPassArgs {
     int n_xcd;
 };
 
+// bit if the lane's condition holds, else 0: one select on the compare's lane
+// mask, so the compare that also guards the lane's queue append is not redone
+// in inverted form
+template <uint32_t kBit>
+__device__ __forceinline__ uint32_t lane_select(bool cond) {
+    const uint64_t lanes = __builtin_amdgcn_ballot_w64(cond);
+    uint32_t r;
+    if constexpr (kBit <= 64)                   // an inline constant
+        __asm__("v_cndmask_b32_e64 %0, 0, %1, %2" : "=v"(r) : "i"(kBit), "s"(lanes));
+    else
+        __asm__("v_cndmask_b32_e64 %0, 0, %1, %2" : "=v"(r) : "v"(kBit), "s"(lanes));
+    return r;
+}
+
 // Inclusive prefix sum over the 64 lanes of a wave: four DPP row shifts, then
 // two row broadcasts carry the row totals.
 __device__ __forceinline__ uint32_t stream_wave_scan(uint32_t x) {
@@ -212,23 +226,32 @@ __device__ __forceinline__ uint32_t stream_wave_scan(uint32_t x) {
     return x;
 }
 
-__global__ __launch_bounds__(1024) void stream_pass_kernel(StreamPassArgs a) {
+// gstart_all is a.gstart again, as a restrict-qualified parameter: its loads at
+// wave-uniform addresses then go through the scalar unit, so a group's range
+// never waits on the vector loads in flight
+__global__ __launch_bounds__(1024) void stream_pass_kernel(StreamPassArgs a, const uint32_t* __restrict__ gstart_all) {
     constexpr int kU = 2;                                     // 16-byte loads per lane per batch
     constexpr uint32_t kBatch = 64 * kChunkIds * kU;          // IDs per batch
     constexpr int kQ = 64 * kChunkIds;                        // 16-bit queue entries per wave: one load's IDs
     constexpr int kInf = 0x3FFFFFFF;
+    constexpr int kHeld = 4;                                  // groups' sums held before a store
+    // s_waitcnt operand: vector memory count 0, the other counters at their maximum
+    constexpr int kWaitVm0 = (0xF << 8) | (0x7 << 4);
     static_assert(kU == 2, "a batch is two loads per lane, each fitting an empty queue");
-    // LDS, one block: the byte map first (a byte's address is its event's
-    // part-relative ID), then the rank of each 128-event block's first nonzero
-    // event minus one, the 16 hit queues, and as many of the part's nonzero
-    // o(E) as fit, followed by one 0.0 that the drain's idle slots read
-    constexpr uint32_t kBaseOff = kQSize;
-    constexpr uint32_t kQueueOff = kBaseOff + (kQSize / 128) * 4;
+    // LDS, one block: the rank of each 128-event block's first nonzero event
+    // minus one, then the byte map (a byte's offset from the map's start is its
+    // event's part-relative ID; that offset fits the LDS instructions' constant
+    // field, so a lookup costs no address arithmetic), the 16 hit queues, and as
+    // many of the part's nonzero o(E) as fit, followed by one 0.0 that the
+    // drain's idle slots read
+    constexpr uint32_t kMapOff = (kQSize / 128) * 4;
+    constexpr uint32_t kQueueOff = kMapOff + kQSize;
     constexpr uint32_t kValOff = kQueueOff + 16 * kQ * 2;
     constexpr int kCap = static_cast<int>((160 * 1024 - kValOff) / 8) - 1;
-    static_assert(kValOff % 16 == 0 && kCap > 0, "LDS layout");
+    static_assert(kValOff % 16 == 0 && kCap > 0 && kMapOff < 65536, "LDS layout");
     __shared__ __attribute__((aligned(16))) uint8_t lds[kValOff + (kCap + 1) * 8];
-    uint32_t* bases = reinterpret_cast<uint32_t*>(lds + kBaseOff);
+    uint32_t* bases = reinterpret_cast<uint32_t*>(lds);
+    uint8_t* map = lds + kMapOff;
     double* vals = reinterpret_cast<double*>(lds + kValOff);
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
@@ -261,13 +284,25 @@ __global__ __launch_bounds__(1024) void stream_pass_kernel(StreamPassArgs a) {
         const uint32_t* gb32 = reinterpret_cast<const uint32_t*>(gimg + int64_t(kImgWords) * 8 + int64_t(kImgRank16) * 2) +
                                is * (kImgBase32 / 4);
         const uint32_t g0 = gb32[0];                // global rank of the part's first nonzero event
+        // the part's nonzero count, from the rank of the next quarter's first
+        // superblock (the next image part's, after the last quarter; unknown
+        // after the catalogue's last image part): when every rank fits the LDS
+        // copy of the values the drain skips the L2 fallback
+        const int64_t n_img = (a.C + (int64_t(1) << kImgShift) - 1) >> kImgShift;
+        bool fits = false;
+        if (is < 3 || ip + 1 < n_img) {
+            const uint32_t g_next = is < 3 ? gb32[kImgBase32 / 4]
+                                           : *reinterpret_cast<const uint32_t*>(
+                                                 gimg + kImgPartBytes + int64_t(kImgWords) * 8 + int64_t(kImgRank16) * 2);
+            fits = g_next - g0 <= static_cast<uint32_t>(kCap);
+        }
         __syncthreads();
         {
             // byte map: thread i covers events 64i .. 64i+63 (one bitmap word)
             const int i = threadIdx.x;
             const uint64_t w = gbm[i];
             uint32_t run = (i & 1) ? static_cast<uint32_t>(__popcll(gbm[i - 1])) : 0u;
-            uint32_t* dst = reinterpret_cast<uint32_t*>(lds + i * 64);
+            uint32_t* dst = reinterpret_cast<uint32_t*>(map + i * 64);
 #pragma unroll
             for (int k = 0; k < 16; ++k) {
                 uint32_t pk = 0;
@@ -295,25 +330,33 @@ __global__ __launch_bounds__(1024) void stream_pass_kernel(StreamPassArgs a) {
         const int64_t wa = ga + wv * n / 16, wb = ga + (wv + 1) * n / 16;
         if (wa >= wb) continue;
         const uint16_t* ids = a.ids + a.part_base[pq];
-        const uint32_t* gs = a.gstart + static_cast<int64_t>(pq) * (a.NG + 1);
+        const uint32_t* gs = gstart_all + static_cast<int64_t>(pq) * (a.NG + 1);
         const uint16_t* ge = a.gend + static_cast<int64_t>(pq) * a.NG * kStreamGroupSlots;
         const double* gcompact = a.compact + g0;
         double* out_hi = a.part_hi + static_cast<int64_t>(pq) * count;
         float* out_lo = a.part_lo + static_cast<int64_t>(pq) * count;
-        // lane i: where trial i of group g starts; lanes >= G: the group's end
-        auto bounds = [&](int64_t g) -> uint32_t {
-            const int64_t gg = g < wb ? g : wb - 1;
-            const uint32_t s0 = gs[gg];
-            return lane == 0 ? s0 : s0 + ge[gg * kStreamGroupSlots + lane - 1];
+        // B, lane i: where trial i of group g starts; lanes >= G: the group's
+        // end.  The next group's trial ends are loaded with every batch (every
+        // lane loads, lane 0 then drops its value; no value is carried over, so
+        // no copy waits on the load) and added to its start when it begins.
+        auto group_ends = [&](int64_t gg) -> uint32_t {
+            return ge[gg * kStreamGroupSlots + (lane == 0 ? 0 : lane - 1)];
         };
+        auto starts = [&](uint32_t s0, uint32_t ends) -> uint32_t { return lane == 0 ? s0 : s0 + ends; };
+        // a group's IDs run from its start to the next group's start (its end
+        // rounded up to the 8-ID chunk: the same chunks)
         int64_t g = wa;
-        uint32_t B = bounds(g), B1 = bounds(g + 1), B2 = bounds(g + 2);
-        uint32_t rs = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(B), 0));
-        uint32_t re = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(B), 63));
+        uint32_t rs = gs[g];
+        uint32_t re = gs[g + 1];
+        uint32_t B = starts(rs, group_ends(g));
+        uint32_t next_ends = 0;
         uint32_t c = rs;                            // first ID of the batch (a multiple of 8)
         int qs = kInf;                              // lane i: queue index of trial i's first hit
         int qn = 0;                                 // queue entries
         double acc_hi = 0.0, acc_lo = 0.0;
+        double held_hi[kHeld];
+        float held_lo[kHeld];
+        int n_held = 0;
 
         auto load_batch = [&](uint32_t cb, uint32_t end, u32x4* v) {
 #pragma unroll
@@ -325,53 +368,86 @@ __global__ __launch_bounds__(1024) void stream_pass_kernel(StreamPassArgs a) {
         };
         // the batch after the one at c: the rest of this group, else the next group's first
         auto load_next = [&](u32x4* v) {
+            next_ends = group_ends(g + 1 < wb ? g + 1 : g);
             if (c + kBatch < re) {
                 load_batch(c + kBatch, re, v);
             } else {
-                const uint32_t n_rs = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(B1), 0));
-                const uint32_t n_re =
-                    static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(B1), 63));
-                load_batch(n_rs, g + 1 < wb ? n_re : 0u, v);
+                const bool more = g + 1 < wb;
+                const uint32_t n_rs = more ? gs[g + 1] : 0u;
+                const uint32_t n_re = more ? gs[g + 2] : 0u;
+                load_batch(n_rs, n_re, v);
             }
         };
-        // sum the queued hits: lane t takes trial t's entries, four at a time
+        // sum the queued hits: lane t takes trial t's entries, four at a time.
+        // The loads of a step are issued together.
+        auto rank = [&](uint32_t e) -> uint32_t {
+            // rank among the part's nonzero events: the block's base (minus one)
+            // plus the byte, which is 1 + the rank inside the block
+            return bases[e >> 7] + map[e];
+        };
         auto drain = [&]() {
             constexpr int kR = 4;
             int lo = __shfl(qs, lane), hi = __shfl(qs, (lane + 1) & 63);
             lo = lo < 0 ? 0 : (lo > qn ? qn : lo);
             hi = hi < 0 ? 0 : (hi > qn ? qn : hi);
             if (lane >= G) hi = lo;                 // lanes past the group's trials
-            for (int j = lo; j < hi; j += kR) {
-                // each step's loads issued together.  Slots past the trial's last
-                // entry read whatever LDS follows (still inside the allocation),
-                // then the 0.0 after the copied losses, whose sum is exact.
-                uint32_t e[kR], rk[kR];
-                bool valid[kR];
-                double v[kR];
+            if (fits) {
+                // every rank has its value in LDS: whole steps unchecked, then
+                // the last one to three entries, whose idle slots read the 0.0
+                // after the copied losses (their queue reads, at most two entries
+                // past a full queue, stay inside the allocation)
+                int j = lo;
+                for (; j + kR <= hi; j += kR) {
+                    uint32_t e[kR];
+                    double v[kR];
 #pragma unroll
-                for (int r2 = 0; r2 < kR; ++r2) {
-                    valid[r2] = j + r2 < hi;
-                    e[r2] = q[j + r2];
+                    for (int r2 = 0; r2 < kR; ++r2) e[r2] = q[j + r2];
+#pragma unroll
+                    for (int r2 = 0; r2 < kR; ++r2) v[r2] = vals[rank(e[r2])];
+#pragma unroll
+                    for (int r2 = 0; r2 < kR; ++r2) dd_add(acc_hi, acc_lo, v[r2]);
                 }
-                // rank among the part's nonzero events: the block's base (minus
-                // one) plus the byte, which is 1 + the rank inside the block
+                if (j < hi) {
+                    uint32_t e[kR - 1];
+                    double v[kR - 1];
 #pragma unroll
-                for (int r2 = 0; r2 < kR; ++r2) rk[r2] = bases[e[r2] >> 7] + lds[e[r2]];
-                // the LDS copy; ranks past it (parts with more nonzero losses than
-                // LDS holds) then read the value from L2
-                bool spill = false;
+                    for (int r2 = 0; r2 < kR - 1; ++r2) e[r2] = q[j + r2];
 #pragma unroll
-                for (int r2 = 0; r2 < kR; ++r2) {
-                    v[r2] = vals[valid[r2] ? min(rk[r2], static_cast<uint32_t>(kCap - 1)) : kCap];
-                    spill |= valid[r2] && rk[r2] >= static_cast<uint32_t>(kCap);
+                    for (int r2 = 0; r2 < kR - 1; ++r2) v[r2] = vals[j + r2 < hi ? rank(e[r2]) : kCap];
+#pragma unroll
+                    for (int r2 = 0; r2 < kR - 1; ++r2) dd_add(acc_hi, acc_lo, v[r2]);
                 }
-                if (__ballot(spill)) {
+            } else {
+                for (int j = lo; j < hi; j += kR) {
+                    // slots past the trial's last entry read whatever LDS follows
+                    // (still inside the allocation), then the 0.0 after the copied
+                    // losses, whose sum is exact
+                    uint32_t e[kR], rk[kR];
+                    bool valid[kR];
+                    double v[kR];
 #pragma unroll
-                    for (int r2 = 0; r2 < kR; ++r2)
-                        if (valid[r2] && rk[r2] >= static_cast<uint32_t>(kCap)) v[r2] = gcompact[rk[r2]];
+                    for (int r2 = 0; r2 < kR; ++r2) {
+                        valid[r2] = j + r2 < hi;
+                        e[r2] = q[j + r2];
+                    }
+#pragma unroll
+                    for (int r2 = 0; r2 < kR; ++r2) rk[r2] = rank(e[r2]);
+                    // the LDS copy; ranks past it (parts with more nonzero losses
+                    // than LDS holds) then read the value from L2
+                    bool spill = false;
+#pragma unroll
+                    for (int r2 = 0; r2 < kR; ++r2) {
+                        v[r2] = vals[valid[r2] ? min(rk[r2], static_cast<uint32_t>(kCap - 1)) : kCap];
+                        spill |= valid[r2] && rk[r2] >= static_cast<uint32_t>(kCap);
+                    }
+                    if (__ballot(spill)) {
+#pragma unroll
+                        for (int r2 = 0; r2 < kR; ++r2)
+                            if (valid[r2] && rk[r2] >= static_cast<uint32_t>(kCap)) v[r2] = gcompact[rk[r2]];
+                    }
+#pragma unroll
+                    for (int r2 = 0; r2 < kR; ++r2) dd_add(acc_hi, acc_lo, v[r2]);
                 }
-#pragma unroll
-                for (int r2 = 0; r2 < kR; ++r2) dd_add(acc_hi, acc_lo, v[r2]);
             }
             qs = qs == kInf ? kInf : qs - qn;
             qn = 0;
@@ -384,20 +460,20 @@ __global__ __launch_bounds__(1024) void stream_pass_kernel(StreamPassArgs a) {
             // their hits are queued after the group's end boundary (lanes >= G
             // note where it falls), so no trial sums them.
             uint32_t m[kU];                         // bit w: ID w of the lane's chunk is a hit
-            uint32_t h[kU][8];                      // each ID's byte (nonzero: a hit)
+            bool hit[kU][8];
 #pragma unroll
             for (int u = 0; u < kU; ++u) {
-                uint32_t mm = 0;
+                uint32_t b[8];
 #pragma unroll
                 for (int d = 0; d < 4; ++d) {
-                    const uint32_t D = v[u][d];
-                    const uint32_t b0 = lds[D & 0xFFFFu], b1 = lds[D >> 16];
-                    h[u][2 * d] = b0;
-                    h[u][2 * d + 1] = b1;
-                    mm |= min(b0, 1u) << (2 * d);
-                    mm |= min(b1, 1u) << (2 * d + 1);
+                    b[2 * d] = map[v[u][d] & 0xFFFFu];
+                    b[2 * d + 1] = map[v[u][d] >> 16];
                 }
-                m[u] = mm;
+#pragma unroll
+                for (int w = 0; w < 8; ++w) hit[u][w] = b[w] != 0;
+                m[u] = lane_select<1>(hit[u][0]) | lane_select<2>(hit[u][1]) | lane_select<4>(hit[u][2]) |
+                       lane_select<8>(hit[u][3]) | lane_select<16>(hit[u][4]) | lane_select<32>(hit[u][5]) |
+                       lane_select<64>(hit[u][6]) | lane_select<128>(hit[u][7]);
             }
             // hit counts per chunk, prefix-summed over the wave two chunks at a time
             // (16-bit halves: at most 8 x 64 hits per load)
@@ -417,9 +493,8 @@ __global__ __launch_bounds__(1024) void stream_pass_kernel(StreamPassArgs a) {
                 uint8_t* at = reinterpret_cast<uint8_t*>(q + qn + (pre[u] - skip));   // LDS byte address
 #pragma unroll
                 for (int w = 0; w < 8; ++w) {
-                    const bool hit = h[u][w] != 0u;
-                    if (hit) *reinterpret_cast<uint16_t*>(at) = static_cast<uint16_t>(v[u][w >> 1] >> (16 * (w & 1)));
-                    at += hit ? 2 : 0;
+                    if (hit[u][w]) *reinterpret_cast<uint16_t*>(at) = static_cast<uint16_t>(v[u][w >> 1] >> (16 * (w & 1)));
+                    at += hit[u][w] ? 2 : 0;
                 }
             };
             // trial starts at batch positions [from, to): the hits of the chunk
@@ -456,7 +531,24 @@ __global__ __launch_bounds__(1024) void stream_pass_kernel(StreamPassArgs a) {
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         };
-        // after a batch: advance; at the end of the group drain the queue, write
+        // Partial sums of the last kHeld groups wait in registers and are stored
+        // together, then waited for at once: a store pending at the next wait
+        // for a batch would make that wait cover every load in flight (stores
+        // and loads share one counter and complete in either order), which at
+        // every group's end would stall the stream
+        auto flush = [&]() {
+#pragma unroll
+            for (int k = 0; k < kHeld; ++k) {
+                const int64_t t = (g - k) * G + lane;
+                if (k < n_held && lane < G && t >= a.t_lo && t < a.t_hi) {
+                    out_hi[t - a.t_lo] = held_hi[k];
+                    out_lo[t - a.t_lo] = held_lo[k];
+                }
+            }
+            n_held = 0;
+            __builtin_amdgcn_s_waitcnt(kWaitVm0);
+        };
+        // after a batch: advance; at the end of the group drain the queue, hold
         // the partial sums and move to the next group (its first batch is in
         // flight).  Returns false after the wave's last group.
         auto step = [&]() -> bool {
@@ -464,24 +556,25 @@ __global__ __launch_bounds__(1024) void stream_pass_kernel(StreamPassArgs a) {
             if (c < re) return true;
             drain();
             {
-                const double s_hi = acc_hi + acc_lo;          // renormalised: |lo| <= ulp(hi) / 2
-                const double s_lo = acc_lo - (s_hi - acc_hi);
-                const int64_t t = g * G + lane;
-                if (lane < G && t >= a.t_lo && t < a.t_hi) {
-                    out_hi[t - a.t_lo] = s_hi;
-                    out_lo[t - a.t_lo] = static_cast<float>(s_lo);
+                // the group's sums join the held results (newest first)
+#pragma unroll
+                for (int k = kHeld - 1; k > 0; --k) {
+                    held_hi[k] = held_hi[k - 1];
+                    held_lo[k] = held_lo[k - 1];
                 }
+                held_hi[0] = acc_hi + acc_lo;          // renormalised: |lo| <= ulp(hi) / 2
+                held_lo[0] = static_cast<float>(acc_lo - (held_hi[0] - acc_hi));
+                ++n_held;
+                if (n_held == kHeld || g + 1 >= wb) flush();
             }
             acc_hi = 0.0;
             acc_lo = 0.0;
             qs = kInf;
             if (g + 1 >= wb) return false;
             ++g;
-            B = B1;
-            B1 = B2;
-            B2 = bounds(g + 2);
-            rs = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(B), 0));
-            re = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(B), 63));
+            rs = gs[g];
+            re = gs[g + 1];
+            B = starts(rs, next_ends);
             c = rs;
             return true;
         };
@@ -663,7 +756,7 @@ hipError_t launch_stream_pass(const StreamLayout& lay, int64_t C, const LayerArg
     int64_t grid = int64_t(n_cu);
     grid -= grid % kXcds;
     if (grid < kXcds) grid = kXcds;
-    hipLaunchKernelGGL(stream_pass_kernel, dim3(static_cast<uint32_t>(grid)), dim3(1024), 0, s, a);
+    hipLaunchKernelGGL(stream_pass_kernel, dim3(static_cast<uint32_t>(grid)), dim3(1024), 0, s, a, a.gstart);
     return hipGetLastError();
 }
 
