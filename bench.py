@@ -76,6 +76,29 @@ def copy_probe() -> None:
     print(json.dumps({"copy_probe_bytes": n * 8, "launches": 3}), flush=True)
 
 
+def cpu_model() -> str:
+    """The host CPU's model name."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def time_oracle(oracle, yet, pool, layer, threads: int, min_s: float = 1.0) -> float:
+    """Seconds per oracle run of one layer, repeated until min_s has passed."""
+    reps, t0 = 0, time.time()
+    while True:
+        oracle.run_layer(yet, pool, layer, threads=threads)
+        reps += 1
+        if time.time() - t0 >= min_s:
+            return (time.time() - t0) / reps
+
+
 def measured_traffic(path=TRAFFIC_FILE):
     """HBM bytes per launch of a kernel from a committed rocprofv3 counter
     summary, if it was taken on the current source of the kernel's file."""
@@ -346,6 +369,17 @@ def main() -> None:
         extra["grad_fwd_ratio"] = round(bwd / fwd, 4)
         extra["grad_fwd_ratio_vs_plain_step"] = round((bwd / reps) / ms_step, 4)
         log(f"forward+ckpt {fwd / reps:.4f} ms, backward {bwd / reps:.4f} ms")
+        # the forward that also keeps prefix sums of S every 64 events in time
+        # order (the time-ordered pass over the 32-bit YET)
+        step(ara.ARA_CHECKPOINT_STRIDE)
+        torch.cuda.synchronize()
+        e[0].record(stream)
+        for _ in range(reps):
+            step(ara.ARA_CHECKPOINT_STRIDE)
+        e[1].record(stream)
+        torch.cuda.synchronize()
+        extra["fwd_stride_checkpointed_ms"] = round(e[0].elapsed_time(e[1]) / reps, 4)
+        log(f"forward+stride checkpoints {extra['fwd_stride_checkpointed_ms']:.4f} ms")
 
     if not args.no_event_nets:
         # per-event net losses of every event of the workload, to a device buffer
@@ -389,8 +423,30 @@ def main() -> None:
         cpu = {"value": ev_s * J / dt, "unit": "event-ELT lookups/s", "cores": oracle.max_threads(),
                "kind": "oracle",
                "sample": f"first {n_s} trials ({ev_s} events x {J} ELTs) of the same workload, "
-                         f"{dt:.1f} s, exact-sum FP64 C oracle"}
+                         f"{dt:.1f} s, exact-sum FP64 C oracle",
+               "cpu_model": cpu_model()}
         log(f"cpu oracle: {cpu['value']:.3e} lookups/s on {cpu['cores']} threads ({dt:.1f}s)")
+        # one core on a smaller sample of the same workload, and the small
+        # 10,000-trial workload on all cores and on one
+        n1 = min(20_000, N)
+        sub1 = Layer(layer.elt_index, layer.occ_retention, layer.occ_limit, layer.agg_retention,
+                     layer.agg_limit, 0, n1)
+        ev1 = int(yet.offsets[n1])
+        dt1 = time_oracle(oracle, yet, pool, sub1, threads=1)
+        cpu["single_core"] = {"value": ev1 * J / dt1, "cores": 1,
+                              "sample": f"first {n1} trials ({ev1} events x {J} ELTs), {dt1:.2f} s per run"}
+        w0 = make_config("config0")
+        l0 = w0.layers[0]
+        lk0 = float(w0.yet.offsets[-1]) * l0.n_elts
+        small = {}
+        for name, th in (("all_cores", 0), ("single_core", 1)):
+            d0 = time_oracle(oracle, w0.yet, w0.pool, l0, threads=th)
+            small[name] = {"value": lk0 / d0, "cores": oracle.max_threads() if th == 0 else 1,
+                           "seconds_per_run": round(d0, 5)}
+        cpu["small_workload"] = dict(small, workload=f"{w0.yet.n_trials} trials x Poisson(100) events, "
+                                                     f"{w0.yet.catalogue_size}-event catalogue, {l0.n_elts} ELTs")
+        log(f"cpu oracle: one core {cpu['single_core']['value']:.3e} lookups/s; small workload "
+            f"{small['all_cores']['value']:.3e} (all cores) / {small['single_core']['value']:.3e} (one core)")
 
     tables.close()
     del out, res

@@ -65,7 +65,21 @@ __global__ __launch_bounds__(256) void part_count_kernel(const int64_t* __restri
          t += n_waves) {
         for (int p = lane; p < P; p += 64) c[w][p] = 0;
         __builtin_amdgcn_wave_barrier();
-        for (int64_t i = offsets[t] + lane; i < offsets[t + 1]; i += 64) atomicAdd(&c[w][ids[i] >> kPartShift], 1);
+        {
+            // four 64-ID chunks loaded together
+            const int64_t b = offsets[t], e = offsets[t + 1];
+            for (int64_t c0 = b; c0 < e; c0 += 256) {
+                uint32_t idk[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int64_t at = c0 + k * 64 + lane;
+                    idk[k] = at < e ? ids[at] : 0u;
+                }
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    if (c0 + k * 64 + lane < e) atomicAdd(&c[w][idk[k] >> kPartShift], 1);
+            }
+        }
         __builtin_amdgcn_wave_barrier();
         for (int p = lane; p < P; p += 64) cnt[t * P + p] = c[w][p];
         __builtin_amdgcn_wave_barrier();
@@ -122,6 +136,8 @@ __global__ __launch_bounds__(256) void part_scatter_kernel(const int64_t* __rest
     __shared__ int64_t cur[4][kMaxParts];
     const int w = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
+    const int n_bits = P > 1 ? 32 - __builtin_clz(static_cast<uint32_t>(P - 1)) : 0;
+    const uint64_t above = lane == 63 ? 0ull : (~0ull << (lane + 1));
     const int64_t n_waves = (static_cast<int64_t>(gridDim.x) * blockDim.x) >> 6;
     for (int64_t t = uniform_i64((static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6); t < N;
          t += n_waves) {
@@ -132,18 +148,36 @@ __global__ __launch_bounds__(256) void part_scatter_kernel(const int64_t* __rest
         const int64_t base = tile * (static_cast<int64_t>(T) * P + 1);
         for (int p = lane; p < P; p += 64) cur[w][p] = tile_start[tile] + seg_rel[base + static_cast<int64_t>(p) * Tk + i];
         __builtin_amdgcn_wave_barrier();
+        // per 64 IDs: the lanes holding an ID of this lane's part are the AND,
+        // over the part number's bits, of that bit's ballot or its complement;
+        // a lane's rank among the earlier ones places it, all 64 write in one
+        // store, and the last lane of each part moves its cursor on
         const int64_t b = offsets[t], e = offsets[t + 1];
-        for (int64_t c = b; c < e; c += 64) {
-            const bool valid = c + lane < e;
-            const uint32_t id = valid ? ids[c + lane] : 0u;
-            const int pid = static_cast<int>(id >> kPartShift);
-            for (int q = 0; q < P; ++q) {
-                const uint64_t m = __ballot(valid && pid == q);
-                if (m == 0) continue;
-                const int64_t at = cur[w][q];
-                if (valid && pid == q) pids[at + __popcll(m & lanemask_lt())] = id;
+        constexpr int kAhead = 4;                   // chunks of 64 IDs loaded together
+        for (int64_t c0 = b; c0 < e; c0 += 64 * kAhead) {
+            uint32_t idk[kAhead];
+#pragma unroll
+            for (int k = 0; k < kAhead; ++k) {
+                const int64_t at = c0 + k * 64 + lane;
+                idk[k] = at < e ? ids[at] : 0u;
+            }
+#pragma unroll
+            for (int k = 0; k < kAhead; ++k) {
+                const int64_t c = c0 + k * 64;
+                if (c >= e) break;
+                const bool valid = c + lane < e;
+                const uint32_t id = idk[k];
+                const int pid = static_cast<int>(id >> kPartShift);
+                uint64_t same = __ballot(valid);
+                for (int bit = 0; bit < n_bits; ++bit) {
+                    const bool set = ((pid >> bit) & 1) != 0;
+                    const uint64_t lanes = __ballot(set);
+                    same &= set ? lanes : ~lanes;
+                }
+                const int64_t at = cur[w][pid];
+                if (valid) pids[at + __popcll(same & lanemask_lt())] = id;
                 __builtin_amdgcn_wave_barrier();
-                if (lane == 0) cur[w][q] = at + __popcll(m);
+                if (valid && (same & above) == 0) cur[w][pid] = at + __popcll(same);
                 __builtin_amdgcn_wave_barrier();
             }
         }
@@ -1366,10 +1400,10 @@ hipError_t build_part_layout(const int64_t* offsets, const uint32_t* ids, int64_
     hipError_t e;
     int32_t* cnt = nullptr;
     int64_t* tsize = nullptr;
-    if ((e = hipMalloc(&cnt, sizeof(int32_t) * N * P)) != hipSuccess) return e;
+    if ((e = hipMallocAsync(reinterpret_cast<void**>(&cnt), sizeof(int32_t) * N * P, s)) != hipSuccess) return e;
     if ((e = hipMalloc(&out->seg_rel, sizeof(uint32_t) * (n_tiles * (static_cast<int64_t>(T) * P + 1)))) != hipSuccess)
         goto fail;
-    if ((e = hipMalloc(&tsize, sizeof(int64_t) * n_tiles)) != hipSuccess) goto fail;
+    if ((e = hipMallocAsync(reinterpret_cast<void**>(&tsize), sizeof(int64_t) * n_tiles, s)) != hipSuccess) goto fail;
     if ((e = hipMalloc(&out->tile_start, sizeof(int64_t) * (n_tiles + 1))) != hipSuccess) goto fail;
     {
         int64_t blocks = (N + 3) / 4;
@@ -1387,8 +1421,9 @@ hipError_t build_part_layout(const int64_t* offsets, const uint32_t* ids, int64_
         st[0] = 0;
         for (int64_t k = 0; k < n_tiles; ++k) {
             if (h[k] >= (int64_t(1) << 31)) {   // too large for 32-bit positions: keep the plain layout
-                (void)hipFree(cnt);
-                (void)hipFree(tsize);
+                (void)hipFreeAsync(cnt, s);
+                (void)hipFreeAsync(tsize, s);
+                (void)hipStreamSynchronize(s);
                 (void)hipFree(out->seg_rel);
                 (void)hipFree(out->tile_start);
                 *out = PartLayout{};
@@ -1418,12 +1453,14 @@ hipError_t build_part_layout(const int64_t* offsets, const uint32_t* ids, int64_
         out->bytes = sizeof(uint32_t) * (total + kIdPad) + sizeof(uint32_t) * (n_tiles * (int64_t(T) * P + 1)) +
                      sizeof(int64_t) * (n_tiles + 1);
     }
-    (void)hipFree(cnt);
-    (void)hipFree(tsize);
+    // temporaries go back to the stream-ordered pool: no free waits for the device
+    (void)hipFreeAsync(cnt, s);
+    (void)hipFreeAsync(tsize, s);
     return hipSuccess;
 fail:
-    if (cnt) (void)hipFree(cnt);
-    if (tsize) (void)hipFree(tsize);
+    if (cnt) (void)hipFreeAsync(cnt, s);
+    if (tsize) (void)hipFreeAsync(tsize, s);
+    (void)hipStreamSynchronize(s);
     free_part_layout(out);
     return e;
 }

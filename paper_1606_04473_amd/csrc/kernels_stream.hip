@@ -65,7 +65,21 @@ __global__ __launch_bounds__(256) void stream_count_kernel(const int64_t* __rest
          t += n_waves) {
         for (int p = lane; p < P; p += 64) c[w][p] = 0;
         __builtin_amdgcn_wave_barrier();
-        for (int64_t i = offsets[t] + lane; i < offsets[t + 1]; i += 64) atomicAdd(&c[w][ids[i] >> kStreamShift], 1);
+        {
+            // four 64-ID chunks loaded together
+            const int64_t b = offsets[t], e = offsets[t + 1];
+            for (int64_t c0 = b; c0 < e; c0 += 256) {
+                uint32_t idk[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int64_t at = c0 + k * 64 + lane;
+                    idk[k] = at < e ? ids[at] : 0u;
+                }
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    if (c0 + k * 64 + lane < e) atomicAdd(&c[w][idk[k] >> kStreamShift], 1);
+            }
+        }
         __builtin_amdgcn_wave_barrier();
         for (int p = lane; p < P; p += 64) cnt[t * P + p] = c[w][p];
         __builtin_amdgcn_wave_barrier();
@@ -134,7 +148,11 @@ __global__ void stream_fill_kernel(uint32_t* p, int64_t n, uint32_t v) {
 }
 
 // stable scatter of each trial's events into its segments of the part
-// streams, one wave per trial: for each 64 events, one ballot per distinct part
+// streams, one wave per trial.  For each 64 events every lane finds the lanes
+// holding an event of its own part -- the AND over the part number's bits of
+// that bit's ballot or its complement -- takes its rank among the earlier
+// ones, and all 64 write in one store; the last lane of each part moves that
+// part's cursor on.
 __global__ __launch_bounds__(256) void stream_scatter_kernel(const int64_t* __restrict__ offsets,
                                                              const uint32_t* __restrict__ ids, int64_t N, int P, int G,
                                                              int64_t NG, const int64_t* __restrict__ part_base,
@@ -144,6 +162,9 @@ __global__ __launch_bounds__(256) void stream_scatter_kernel(const int64_t* __re
     __shared__ int64_t cur[4][kMaxStreamParts];
     const int w = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
+    const int n_bits = P > 1 ? 32 - __builtin_clz(static_cast<uint32_t>(P - 1)) : 0;
+    const uint64_t below = stream_lanemask_lt();
+    const uint64_t above = lane == 63 ? 0ull : (~0ull << (lane + 1));
     const int64_t n_waves = (static_cast<int64_t>(gridDim.x) * blockDim.x) >> 6;
     for (int64_t t = uniform_i64((static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6); t < N;
          t += n_waves) {
@@ -156,21 +177,32 @@ __global__ __launch_bounds__(256) void stream_scatter_kernel(const int64_t* __re
         }
         __builtin_amdgcn_wave_barrier();
         const int64_t b = offsets[t], e = offsets[t + 1];
-        for (int64_t c = b; c < e; c += 64) {
-            const bool valid = c + lane < e;
-            const uint32_t id = valid ? ids[c + lane] : 0u;
-            const int pid = static_cast<int>(id >> kStreamShift);
-            uint64_t todo = __ballot(valid);
-            while (todo) {
-                const int leader = __builtin_ctzll(todo);
-                const int qq = __builtin_amdgcn_readlane(pid, leader);
-                const uint64_t m = __ballot(valid && pid == qq);
-                const int64_t at = cur[w][qq];
-                if (valid && pid == qq) out[at + __popcll(m & stream_lanemask_lt())] = static_cast<uint16_t>(id);
+        constexpr int kAhead = 4;                   // chunks of 64 IDs loaded together
+        for (int64_t c0 = b; c0 < e; c0 += 64 * kAhead) {
+            uint32_t idk[kAhead];
+#pragma unroll
+            for (int k = 0; k < kAhead; ++k) {
+                const int64_t at = c0 + k * 64 + lane;
+                idk[k] = at < e ? ids[at] : 0u;
+            }
+#pragma unroll
+            for (int k = 0; k < kAhead; ++k) {
+                const int64_t c = c0 + k * 64;
+                if (c >= e) break;
+                const bool valid = c + lane < e;
+                const uint32_t id = idk[k];
+                const int pid = static_cast<int>(id >> kStreamShift);
+                uint64_t same = __ballot(valid);
+                for (int bit = 0; bit < n_bits; ++bit) {
+                    const bool set = ((pid >> bit) & 1) != 0;
+                    const uint64_t lanes = __ballot(set);
+                    same &= set ? lanes : ~lanes;
+                }
+                const int64_t at = cur[w][pid];
+                if (valid) out[at + __popcll(same & below)] = static_cast<uint16_t>(id);
                 __builtin_amdgcn_wave_barrier();
-                if (lane == 0) cur[w][qq] = at + __popcll(m);
+                if (valid && (same & above) == 0) cur[w][pid] = at + __popcll(same);
                 __builtin_amdgcn_wave_barrier();
-                todo &= ~m;
             }
         }
         __builtin_amdgcn_wave_barrier();
@@ -651,10 +683,10 @@ hipError_t build_stream_layout(const int64_t* offsets, const uint32_t* ids, int6
     uint32_t h_flag = 0;
     int64_t blocks = (N + 3) / 4;
     if (blocks > int64_t(n_cu) * 16) blocks = int64_t(n_cu) * 16;
-    if ((e = hipMalloc(&cnt, sizeof(int32_t) * N * P)) != hipSuccess) goto fail;
-    if ((e = hipMalloc(&gsize, sizeof(uint32_t) * n_grp)) != hipSuccess) goto fail;
-    if ((e = hipMalloc(&plen, sizeof(uint64_t) * P)) != hipSuccess) goto fail;
-    if ((e = hipMalloc(&flag, sizeof(uint32_t))) != hipSuccess) goto fail;
+    if ((e = hipMallocAsync(reinterpret_cast<void**>(&cnt), sizeof(int32_t) * N * P, s)) != hipSuccess) goto fail;
+    if ((e = hipMallocAsync(reinterpret_cast<void**>(&gsize), sizeof(uint32_t) * n_grp, s)) != hipSuccess) goto fail;
+    if ((e = hipMallocAsync(reinterpret_cast<void**>(&plen), sizeof(uint64_t) * P, s)) != hipSuccess) goto fail;
+    if ((e = hipMallocAsync(reinterpret_cast<void**>(&flag), sizeof(uint32_t), s)) != hipSuccess) goto fail;
     if ((e = hipMalloc(&out->gend, sizeof(uint16_t) * n_grp * kStreamGroupSlots)) != hipSuccess) goto fail;
     if ((e = hipMalloc(&out->gstart, sizeof(uint32_t) * P * (NG + 1))) != hipSuccess) goto fail;
     if ((e = hipMalloc(&out->part_base, sizeof(int64_t) * (P + 1))) != hipSuccess) goto fail;
@@ -694,11 +726,15 @@ hipError_t build_stream_layout(const int64_t* offsets, const uint32_t* ids, int6
     hipLaunchKernelGGL(stream_scatter_kernel, dim3(static_cast<uint32_t>(blocks)), dim3(256), 0, s, offsets, ids, N, P,
                        G, NG, out->part_base, out->gstart, out->gend, out->ids);
     if ((e = hipGetLastError()) != hipSuccess) goto fail;
-    if ((e = hipStreamSynchronize(s)) != hipSuccess) goto fail;
-    (void)hipFree(cnt);
-    (void)hipFree(gsize);
-    (void)hipFree(plen);
-    (void)hipFree(flag);
+    // temporaries go back to the stream-ordered pool: no free waits for the device
+    (void)hipFreeAsync(cnt, s);
+    (void)hipFreeAsync(gsize, s);
+    (void)hipFreeAsync(plen, s);
+    (void)hipFreeAsync(flag, s);
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) {
+        free_stream_layout(out);
+        return e;
+    }
     out->P = P;
     out->G = G;
     out->NG = NG;
@@ -707,10 +743,11 @@ hipError_t build_stream_layout(const int64_t* offsets, const uint32_t* ids, int6
                  static_cast<int64_t>(sizeof(uint32_t)) * P * (NG + 1) + static_cast<int64_t>(sizeof(int64_t)) * (P + 1);
     return hipSuccess;
 fail:
-    if (cnt) (void)hipFree(cnt);
-    if (gsize) (void)hipFree(gsize);
-    if (plen) (void)hipFree(plen);
-    if (flag) (void)hipFree(flag);
+    if (cnt) (void)hipFreeAsync(cnt, s);
+    if (gsize) (void)hipFreeAsync(gsize, s);
+    if (plen) (void)hipFreeAsync(plen, s);
+    if (flag) (void)hipFreeAsync(flag, s);
+    (void)hipStreamSynchronize(s);
     free_stream_layout(out);
     return e;
 }

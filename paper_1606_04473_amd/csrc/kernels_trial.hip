@@ -181,7 +181,16 @@ __global__ void validate_kernel(const int64_t* offsets, int64_t n_trials, const 
     const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
     const int64_t tid = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     uint32_t f = 0;
-    for (int64_t i = tid; i < n_events; i += stride)
+    // the IDs 16 bytes at a time (the allocation is 256-byte aligned), then the tail
+    const int64_t n4 = n_events / 4;
+    const u32x4* ids4 = reinterpret_cast<const u32x4*>(ids);
+    const uint32_t c32 = C > 0xFFFFFFFFll ? 0xFFFFFFFFu : static_cast<uint32_t>(C);
+    const bool wide = C > 0xFFFFFFFFll;              // every 32-bit ID is below C
+    for (int64_t i = tid; i < n4; i += stride) {
+        const u32x4 v = __builtin_nontemporal_load(ids4 + i);
+        if (!wide && (v.x >= c32 || v.y >= c32 || v.z >= c32 || v.w >= c32)) f |= 1u;
+    }
+    for (int64_t i = 4 * n4 + tid; i < n_events; i += stride)
         if (static_cast<int64_t>(ids[i]) >= C) f |= 1u;
     for (int64_t i = tid; i < n_trials; i += stride)
         if (offsets[i + 1] < offsets[i]) f |= 2u;
@@ -254,7 +263,7 @@ hipError_t launch_debug_lookups(const int64_t* offsets, const uint32_t* ids, con
 hipError_t launch_validate(const int64_t* offsets, int64_t n_trials, const uint32_t* ids,
                            int64_t n_events, const double* elts, int64_t n_elt_values, int64_t C,
                            uint32_t* d_flags, int n_cu, hipStream_t s) {
-    const int blocks = n_cu * 4;
+    const int blocks = n_cu * 8;                 // 32 waves per CU
     hipLaunchKernelGGL(validate_kernel, dim3(blocks), dim3(256), 0, s, offsets, n_trials, ids, n_events,
                        elts, n_elt_values, C, d_flags);
     return hipGetLastError();
