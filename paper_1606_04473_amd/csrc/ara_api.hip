@@ -91,15 +91,14 @@ hipError_t scratch_acquire(std::mutex& mu, std::vector<ara::ScratchBuffer*>& set
     hipError_t e = hipSuccess;
     if (!pick->done) e = hipEventCreateWithFlags(&pick->done, hipEventDisableTiming);
     if (e == hipSuccess && pick->cap < bytes) {
-        // growing: the old memory may still be read by work on its stream
-        if (pick->p) {
-            if (pick->stream) e = hipStreamSynchronize(pick->stream);
-            if (e == hipSuccess) e = hipFree(pick->p);
-        }
+        // growing: the old memory may still be read by work on its last
+        // stream, so it goes back to the stream-ordered pool in that stream's
+        // order; the new memory is taken in this call's stream order
+        if (pick->p) e = hipFreeAsync(pick->p, pick->stream);
         pick->p = nullptr;
         pick->cap = 0;
         pick->primed = false;
-        if (e == hipSuccess) e = hipMalloc(&pick->p, bytes);
+        if (e == hipSuccess) e = hipMallocAsync(&pick->p, bytes, s);
         if (e == hipSuccess) pick->cap = bytes;
     }
     if (e != hipSuccess) {
@@ -119,14 +118,58 @@ void scratch_release(std::mutex& mu, ara::ScratchBuffer* b, hipStream_t s) {
     b->busy = false;
 }
 
-void scratch_free_all(std::vector<ara::ScratchBuffer*>& sets) {
+// frees on stream fs after each buffer's last use (its event)
+void scratch_free_all(std::vector<ara::ScratchBuffer*>& sets, hipStream_t fs) {
     for (auto* b : sets) {
-        if (b->p) (void)hipFree(b->p);
+        if (b->done) (void)hipStreamWaitEvent(fs, b->done, 0);
+        if (b->p) (void)hipFreeAsync(b->p, fs);
         if (b->done) (void)hipEventDestroy(b->done);
         delete b;
     }
     sets.clear();
 }
+
+// the stream on which destroyed tables return their memory to the pool (one
+// per device, default priority, never destroyed)
+hipStream_t free_stream(int device) {
+    static std::mutex mu;
+    static std::vector<std::pair<int, hipStream_t>> streams;
+    std::lock_guard<std::mutex> g(mu);
+    for (auto& d : streams)
+        if (d.first == device) return d.second;
+    hipStream_t st = nullptr;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) st = nullptr;
+    streams.emplace_back(device, st);
+    return st;
+}
+
+// Records, on stream s, an event after the work enqueued there so far on t's
+// behalf (one event per stream, re-recorded by later calls).
+void note_use(ara_tables* t, hipStream_t s) {
+    std::lock_guard<std::mutex> g(t->fence_mu);
+    for (auto& f : t->fences)
+        if (f.first == s) {
+            (void)hipEventRecord(f.second, s);
+            return;
+        }
+    hipEvent_t ev = nullptr;
+    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return;
+    if (hipEventRecord(ev, s) != hipSuccess) {
+        (void)hipEventDestroy(ev);
+        return;
+    }
+    t->fences.emplace_back(s, ev);
+}
+
+// note_use on scope exit, so a call's error returns are covered too
+struct UseFence {
+    ara_tables* t;
+    hipStream_t s;
+    UseFence(ara_tables* tt, hipStream_t ss) : t(tt), s(ss) {}
+    ~UseFence() {
+        if (t) note_use(t, s);
+    }
+};
 
 // releases on scope exit, so early error returns give the buffer back
 struct ScratchLease {
@@ -503,6 +546,7 @@ static ara_status create_impl(const int64_t* trial_offsets, int64_t n_trials, co
     t->C = catalogue_size;
     t->n_pool = n_elts;
     auto cleanup = [&](ara_status st) {
+        note_use(t, s);                 // the memory goes back after the create's own work
         ara_destroy_tables(t);
         return st;
     };
@@ -517,8 +561,10 @@ static ara_status create_impl(const int64_t* trial_offsets, int64_t n_trials, co
         t->tuning = base->tuning;
     }
     hipError_t e;
-    if ((e = hipMalloc(&t->offsets, off_bytes)) != hipSuccess) return cleanup(hip_fail(e, "hipMalloc offsets"));
-    if ((e = hipMalloc(&t->ids, id_bytes)) != hipSuccess) return cleanup(hip_fail(e, "hipMalloc event ids"));
+    if ((e = hipMallocAsync(reinterpret_cast<void**>(&t->offsets), off_bytes, s)) != hipSuccess)
+        return cleanup(hip_fail(e, "allocate offsets"));
+    if ((e = hipMallocAsync(reinterpret_cast<void**>(&t->ids), id_bytes, s)) != hipSuccess)
+        return cleanup(hip_fail(e, "allocate event ids"));
     if (elt_bytes && (e = hipMalloc(&t->elts, elt_bytes)) != hipSuccess)
         return cleanup(hip_fail(e, "hipMalloc ELT pool"));
     t->bytes = static_cast<int64_t>(off_bytes + id_bytes + elt_bytes);
@@ -578,6 +624,7 @@ static ara_status create_impl(const int64_t* trial_offsets, int64_t n_trials, co
         }
         t->bytes += t->stream.bytes;
     }
+    note_use(t, s);
     *out = t;
     return ARA_OK;
 }
@@ -585,14 +632,27 @@ static ara_status create_impl(const int64_t* trial_offsets, int64_t n_trials, co
 void ara_destroy_tables(ara_tables* t) {
     if (!t) return;
     DeviceScope ds(t->device);
-    if (t->offsets) (void)hipFree(t->offsets);
-    if (t->ids) (void)hipFree(t->ids);
+    // The YET, its layouts and the kept scratch come from the stream-ordered
+    // pool: they go back on an internal stream once every stream the tables
+    // were used on has reached the end of its last call's work, and the host
+    // does not wait (a hipFree would wait for the whole device)
+    hipStream_t fs = free_stream(t->device);
+    {
+        std::lock_guard<std::mutex> g(t->fence_mu);
+        for (auto& f : t->fences) {
+            (void)hipStreamWaitEvent(fs, f.second, 0);
+            (void)hipEventDestroy(f.second);
+        }
+        t->fences.clear();
+    }
+    if (t->offsets) (void)hipFreeAsync(t->offsets, fs);
+    if (t->ids) (void)hipFreeAsync(t->ids, fs);
+    scratch_free_all(t->scratch, fs);
+    ara::free_part_layout(&t->parts, fs);
+    ara::free_stream_layout(&t->stream, fs);
     if (t->elts && t->owns_elts) (void)hipFree(t->elts);
     if (t->owns_elts) ara::free_sparse_pool(&t->sparse);
     free_checkpoints(t->ck);
-    scratch_free_all(t->scratch);
-    ara::free_part_layout(&t->parts);
-    ara::free_stream_layout(&t->stream);
     for (auto* g : t->graphs) free_graph(g);
     t->graphs.clear();
     stage_free(t->stage);
@@ -758,6 +818,7 @@ ara_status ara_run_layers(ara_tables* t, const ara_layer* layers, int32_t n_laye
     DeviceScope ds(t->device);
     if (!ds.ok) return fail(ARA_ERR_DEVICE, "cannot select the tables' device");
     hipStream_t s = static_cast<hipStream_t>(stream);
+    UseFence use_fence(t, s);           // the tables' memory outlives this call's work
     const bool dev_out = (flags & ARA_DEVICE_PTR) != 0;
     const bool literal = (flags & ARA_LITERAL) != 0;
     ara_tuning tu;
@@ -1058,6 +1119,7 @@ ara_status ara_run_portfolio(ara_tables* t, const ara_program* programs, int32_t
     DeviceScope ds(t->device);
     if (!ds.ok) return fail(ARA_ERR_DEVICE, "cannot select the tables' device");
     hipStream_t s = static_cast<hipStream_t>(stream);
+    UseFence use_fence(t, s);           // the tables' memory outlives this call's work
     const bool dev_out = (flags & ARA_DEVICE_PTR) != 0;
     const bool literal = (flags & ARA_LITERAL) != 0;
     const bool prof = (flags & ARA_PROFILE) != 0;
@@ -1281,6 +1343,7 @@ ara_status ara_backward(ara_tables* t, const ara_layer* layer, double tvar_p, do
     DeviceScope ds(t->device);
     if (!ds.ok) return fail(ARA_ERR_DEVICE, "cannot select the tables' device");
     hipStream_t s = static_cast<hipStream_t>(stream);
+    UseFence use_fence(t, s);           // the tables' memory outlives this call's work
     const int P = 2 * L.J + 4;
     const bool dev = (flags & ARA_DEVICE_PTR) != 0;
     PoolBuffer scratch, staged;
@@ -1339,6 +1402,7 @@ ara_status ara_debug_lookups(ara_tables* t, const ara_layer* layer, int64_t tria
     DeviceScope ds(t->device);
     if (!ds.ok) return fail(ARA_ERR_DEVICE, "cannot select the tables' device");
     hipStream_t s = static_cast<hipStream_t>(stream);
+    UseFence use_fence(t, s);           // the tables' memory outlives this call's work
     int64_t be[2];
     HIP_TRY(hipMemcpyAsync(be, t->offsets + trial, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, s), "offsets");
     HIP_TRY(hipStreamSynchronize(s), "synchronize");
@@ -1368,6 +1432,7 @@ ara_status ara_debug_read(ara_tables* t, const ara_layer* layer, int32_t what, v
     DeviceScope ds(t->device);
     if (!ds.ok) return fail(ARA_ERR_DEVICE, "cannot select the tables' device");
     hipStream_t s = static_cast<hipStream_t>(stream);
+    UseFence use_fence(t, s);           // the tables' memory outlives this call's work
     const void* src = nullptr;
     int64_t bytes = 0;
     PoolBuffer buf;
@@ -1436,6 +1501,7 @@ ara_status ara_event_nets(ara_tables* t, const ara_layer* layer, double* nets, i
     DeviceScope ds(t->device);
     if (!ds.ok) return fail(ARA_ERR_DEVICE, "cannot select the tables' device");
     hipStream_t s = static_cast<hipStream_t>(stream);
+    UseFence use_fence(t, s);           // the tables' memory outlives this call's work
     int64_t be[2] = {0, 0};
     HIP_TRY(hipMemcpyAsync(&be[0], t->offsets + L.trial_begin, sizeof(int64_t), hipMemcpyDeviceToHost, s), "offsets");
     HIP_TRY(hipMemcpyAsync(&be[1], t->offsets + L.trial_begin + L.trial_count, sizeof(int64_t), hipMemcpyDeviceToHost,

@@ -176,7 +176,8 @@ struct StreamLayout {
 };
 hipError_t build_stream_layout(const int64_t* offsets, const uint32_t* ids, int64_t N, int64_t n_events, int64_t C,
                                int n_cu, hipStream_t s, StreamLayout* out);
-void free_stream_layout(StreamLayout* L);
+// frees in stream order on s (the layout's memory comes from the stream-ordered pool)
+void free_stream_layout(StreamLayout* L, hipStream_t s);
 // bytes of the per-(part, trial) partial sums of the streaming pass
 int64_t stream_partials_bytes(const StreamLayout& lay, int64_t trials);
 // the streaming pass: reads the part images and compact values that
@@ -357,6 +358,11 @@ struct ara_tables {
     ara::ProfileState prof;
     std::mutex scratch_mu;        // guards scratch
     std::vector<ara::ScratchBuffer*> scratch;
+    // one event per stream the tables were used on, recorded after each call's
+    // work: destroying the tables frees their stream-ordered memory after all of
+    // them, without waiting on the host
+    std::mutex fence_mu;
+    std::vector<std::pair<hipStream_t, hipEvent_t>> fences;
 };
 
 namespace ara {
@@ -408,7 +414,8 @@ hipError_t launch_debug_lookups(const int64_t* offsets, const uint32_t* ids, con
 // catalogue-partitioned path
 hipError_t build_part_layout(const int64_t* offsets, const uint32_t* ids, int64_t N, int64_t n_events, int64_t C,
                              int n_cu, hipStream_t s, PartLayout* out);
-void free_part_layout(PartLayout* L);
+// frees in stream order on s (the layout's memory comes from the stream-ordered pool)
+void free_part_layout(PartLayout* L, hipStream_t s);
 int64_t part_scratch_bytes(int64_t C, int P);
 int part_count(int64_t C);   // catalogue parts of the part images
 hipError_t launch_part_fold(const double* o, int64_t C, int P, void* scratch, hipStream_t s, bool with_ranks);

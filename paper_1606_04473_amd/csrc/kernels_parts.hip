@@ -1401,10 +1401,13 @@ hipError_t build_part_layout(const int64_t* offsets, const uint32_t* ids, int64_
     int32_t* cnt = nullptr;
     int64_t* tsize = nullptr;
     if ((e = hipMallocAsync(reinterpret_cast<void**>(&cnt), sizeof(int32_t) * N * P, s)) != hipSuccess) return e;
-    if ((e = hipMalloc(&out->seg_rel, sizeof(uint32_t) * (n_tiles * (static_cast<int64_t>(T) * P + 1)))) != hipSuccess)
+    if ((e = hipMallocAsync(reinterpret_cast<void**>(&out->seg_rel),
+                            sizeof(uint32_t) * (n_tiles * (static_cast<int64_t>(T) * P + 1)), s)) != hipSuccess)
         goto fail;
     if ((e = hipMallocAsync(reinterpret_cast<void**>(&tsize), sizeof(int64_t) * n_tiles, s)) != hipSuccess) goto fail;
-    if ((e = hipMalloc(&out->tile_start, sizeof(int64_t) * (n_tiles + 1))) != hipSuccess) goto fail;
+    if ((e = hipMallocAsync(reinterpret_cast<void**>(&out->tile_start), sizeof(int64_t) * (n_tiles + 1), s)) !=
+        hipSuccess)
+        goto fail;
     {
         int64_t blocks = (N + 3) / 4;
         if (blocks > int64_t(n_cu) * 16) blocks = int64_t(n_cu) * 16;
@@ -1423,9 +1426,9 @@ hipError_t build_part_layout(const int64_t* offsets, const uint32_t* ids, int64_
             if (h[k] >= (int64_t(1) << 31)) {   // too large for 32-bit positions: keep the plain layout
                 (void)hipFreeAsync(cnt, s);
                 (void)hipFreeAsync(tsize, s);
+                (void)hipFreeAsync(out->seg_rel, s);
+                (void)hipFreeAsync(out->tile_start, s);
                 (void)hipStreamSynchronize(s);
-                (void)hipFree(out->seg_rel);
-                (void)hipFree(out->tile_start);
                 *out = PartLayout{};
                 return hipSuccess;
             }
@@ -1435,7 +1438,9 @@ hipError_t build_part_layout(const int64_t* offsets, const uint32_t* ids, int64_
         if ((e = hipMemcpyAsync(out->tile_start, st.data(), sizeof(int64_t) * (n_tiles + 1), hipMemcpyHostToDevice,
                                 s)) != hipSuccess)
             goto fail;
-        if ((e = hipMalloc(&out->pids, sizeof(uint32_t) * (total + kIdPad))) != hipSuccess) goto fail;
+        if ((e = hipMallocAsync(reinterpret_cast<void**>(&out->pids), sizeof(uint32_t) * (total + kIdPad), s)) !=
+            hipSuccess)
+            goto fail;
         int64_t fb = (total + kIdPad + 255) / 256;
         if (fb > 8192) fb = 8192;
         hipLaunchKernelGGL(fill_u32_kernel, dim3(static_cast<uint32_t>(fb)), dim3(256), 0, s, out->pids, total + kIdPad,
@@ -1460,15 +1465,15 @@ hipError_t build_part_layout(const int64_t* offsets, const uint32_t* ids, int64_
 fail:
     if (cnt) (void)hipFreeAsync(cnt, s);
     if (tsize) (void)hipFreeAsync(tsize, s);
+    free_part_layout(out, s);
     (void)hipStreamSynchronize(s);
-    free_part_layout(out);
     return e;
 }
 
-void free_part_layout(PartLayout* L) {
-    if (L->pids) (void)hipFree(L->pids);
-    if (L->seg_rel) (void)hipFree(L->seg_rel);
-    if (L->tile_start) (void)hipFree(L->tile_start);
+void free_part_layout(PartLayout* L, hipStream_t s) {
+    if (L->pids) (void)hipFreeAsync(L->pids, s);
+    if (L->seg_rel) (void)hipFreeAsync(L->seg_rel, s);
+    if (L->tile_start) (void)hipFreeAsync(L->tile_start, s);
     *L = PartLayout{};
 }
 

@@ -687,9 +687,13 @@ hipError_t build_stream_layout(const int64_t* offsets, const uint32_t* ids, int6
     if ((e = hipMallocAsync(reinterpret_cast<void**>(&gsize), sizeof(uint32_t) * n_grp, s)) != hipSuccess) goto fail;
     if ((e = hipMallocAsync(reinterpret_cast<void**>(&plen), sizeof(uint64_t) * P, s)) != hipSuccess) goto fail;
     if ((e = hipMallocAsync(reinterpret_cast<void**>(&flag), sizeof(uint32_t), s)) != hipSuccess) goto fail;
-    if ((e = hipMalloc(&out->gend, sizeof(uint16_t) * n_grp * kStreamGroupSlots)) != hipSuccess) goto fail;
-    if ((e = hipMalloc(&out->gstart, sizeof(uint32_t) * P * (NG + 1))) != hipSuccess) goto fail;
-    if ((e = hipMalloc(&out->part_base, sizeof(int64_t) * (P + 1))) != hipSuccess) goto fail;
+    if ((e = hipMallocAsync(reinterpret_cast<void**>(&out->gend), sizeof(uint16_t) * n_grp * kStreamGroupSlots, s)) !=
+        hipSuccess)
+        goto fail;
+    if ((e = hipMallocAsync(reinterpret_cast<void**>(&out->gstart), sizeof(uint32_t) * P * (NG + 1), s)) != hipSuccess)
+        goto fail;
+    if ((e = hipMallocAsync(reinterpret_cast<void**>(&out->part_base), sizeof(int64_t) * (P + 1), s)) != hipSuccess)
+        goto fail;
     if ((e = hipMemsetAsync(flag, 0, sizeof(uint32_t), s)) != hipSuccess) goto fail;
     hipLaunchKernelGGL(stream_count_kernel, dim3(static_cast<uint32_t>(blocks)), dim3(256), 0, s, offsets, ids, N, P,
                        cnt);
@@ -714,7 +718,9 @@ hipError_t build_stream_layout(const int64_t* offsets, const uint32_t* ids, int6
     if ((e = hipMemcpyAsync(out->part_base, h_base.data(), sizeof(int64_t) * (P + 1), hipMemcpyHostToDevice, s)) !=
         hipSuccess)
         goto fail;
-    if ((e = hipMalloc(&out->ids, sizeof(uint16_t) * (out->length + kStreamPad))) != hipSuccess) goto fail;
+    if ((e = hipMallocAsync(reinterpret_cast<void**>(&out->ids), sizeof(uint16_t) * (out->length + kStreamPad), s)) !=
+        hipSuccess)
+        goto fail;
     {
         const int64_t n32 = (out->length + kStreamPad) / 2;
         int64_t fb = (n32 + 255) / 256;
@@ -732,7 +738,7 @@ hipError_t build_stream_layout(const int64_t* offsets, const uint32_t* ids, int6
     (void)hipFreeAsync(plen, s);
     (void)hipFreeAsync(flag, s);
     if ((e = hipStreamSynchronize(s)) != hipSuccess) {
-        free_stream_layout(out);
+        free_stream_layout(out, s);
         return e;
     }
     out->P = P;
@@ -747,16 +753,16 @@ fail:
     if (gsize) (void)hipFreeAsync(gsize, s);
     if (plen) (void)hipFreeAsync(plen, s);
     if (flag) (void)hipFreeAsync(flag, s);
+    free_stream_layout(out, s);
     (void)hipStreamSynchronize(s);
-    free_stream_layout(out);
     return e;
 }
 
-void free_stream_layout(StreamLayout* L) {
-    if (L->ids) (void)hipFree(L->ids);
-    if (L->part_base) (void)hipFree(L->part_base);
-    if (L->gstart) (void)hipFree(L->gstart);
-    if (L->gend) (void)hipFree(L->gend);
+void free_stream_layout(StreamLayout* L, hipStream_t s) {
+    if (L->ids) (void)hipFreeAsync(L->ids, s);
+    if (L->part_base) (void)hipFreeAsync(L->part_base, s);
+    if (L->gstart) (void)hipFreeAsync(L->gstart, s);
+    if (L->gend) (void)hipFreeAsync(L->gend, s);
     *L = StreamLayout{};
 }
 
