@@ -336,6 +336,39 @@ def test_concurrent_streams_same_results(ara, cfg0):
         assert np.array_equal(o.cpu().numpy(), base)
 
 
+def test_destroy_with_work_in_flight(ara):
+    """Tables destroyed right after calls on two side streams, with no
+    synchronisation, then new tables of the same size built and run on a third
+    stream (the pool hands the freed memory out again): the first calls' year
+    losses must still match the oracle, because destroy returns the memory only
+    after each stream's last call has finished."""
+    import torch
+    w = make_config("config1", n_prefix=100_000)
+    yet, pool, layer = w.yet, w.pool, w.layers[0]
+    ref, S = oracle.run_layer(yet, pool, layer)
+    other = make_yet(yet.n_trials, 1000.0, yet.catalogue_size, seed=313)
+    spec = _spec(ara, layer, pool, yet)
+    sa, sb, sc = torch.cuda.Stream(), torch.cuda.Stream(), torch.cuda.Stream()
+    outs = [torch.empty(yet.n_trials, dtype=torch.float64, device="cuda") for _ in range(2)]
+    junk = torch.empty(other.n_trials, dtype=torch.float64, device="cuda")
+    for rep in range(3):
+        for o in outs:
+            o.fill_(-1.0)
+        torch.cuda.synchronize()
+        t1 = ara.create_tables(yet.offsets, yet.ids, pool.losses)
+        ara.run_layers(t1, [spec], out=outs[0], stream=sa)
+        ara.run_layers(t1, [spec], out=outs[1], stream=sb)
+        t1.close()
+        t2 = ara.create_tables(other.offsets, other.ids, pool.losses)
+        ara.run_layers(t2, [_spec(ara, layer, pool, other)], out=junk, stream=sc)
+        t2.close()
+        torch.cuda.synchronize()
+        for o in outs:
+            got = o.cpu().numpy()
+            err = np.abs(got - ref) / np.maximum(np.maximum(np.abs(ref), np.abs(S)), 1e-300)
+            assert float(err.max()) <= REL, (rep, float(err.max()))
+
+
 # ---------------------------------------------------------------------------
 # ragged, empty and degenerate inputs
 # ---------------------------------------------------------------------------
