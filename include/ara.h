@@ -79,7 +79,9 @@ typedef int32_t ara_status;
 
 #define ARA_CHECKPOINT_STRIDE (1u << 7) /* ara_run_layers: ARA_CHECKPOINT_S plus the prefix sums
                                        of S every 64 events in time order (read them with
-                                       ara_read_checkpoints); uses the time-ordered pass */
+                                       ara_read_checkpoints); the default pass and pass_variant
+                                       2 add one time-ordered pass over the 32-bit YET for them,
+                                       pass_variant 1 runs the time-ordered trial pass instead */
 #define ARA_PLAIN_LAYOUT (1u << 6)  /* ara_create_tables: keep only the time-ordered YET (no
                                        catalogue-partitioned copy; saves ~4 B per event of device
                                        memory, slower ara_run_layers) */

@@ -832,8 +832,11 @@ ara_status ara_run_layers(ara_tables* t, const ara_layer* layers, int32_t n_laye
         HIP_TRY(staged.alloc(sizeof(double) * (total > 0 ? total : 1), s), "scratch for YLT");
         out = static_cast<double*>(staged.p);
     }
-    // the partitioned pass serves plain runs; stride checkpoints need time order
-    const bool use_parts = !literal && t->parts.P > 0 && !(flags & ARA_CHECKPOINT_STRIDE);
+    // the partitioned passes serve plain runs.  Stride checkpoints need time
+    // order: after the streaming or XCD-affine pass a time-ordered pass of their
+    // own writes them; with pass_variant 1 the time-ordered trial pass does all
+    const bool stride = (flags & ARA_CHECKPOINT_STRIDE) != 0;
+    const bool use_parts = !literal && t->parts.P > 0 && !(stride && tu.pass_variant == 1);
     // the streaming pass (default) and the XCD-affine pass (pass_variant 2)
     // write per-part partial sums; pass_variant 1 selects the rank-based pass
     // with the compact value array
@@ -1053,6 +1056,13 @@ ara_status ara_run_layers(ara_tables* t, const ara_layer* layers, int32_t n_laye
             KernelTimer kc(t, s, prof, ARA_KERNEL_COMBINE);
             HIP_TRY(split.combine(L[i], nullptr, xbuf.p, a.ylt, a.S, s), "partial sums merge");
             kc.done();
+            if (stride_buf) {
+                PoolBuffer probe;
+                HIP_TRY(probe.alloc(static_cast<size_t>(ara::probe_table_bytes(t->C)), s), "scratch for probe words");
+                HIP_TRY(ara::launch_stride_checkpoints(t->offsets, t->ids, pbuf.p, t->parts.P, t->C,
+                                                       static_cast<uint64_t*>(probe.p), L[i], stride_buf, t->n_cu, s),
+                        "stride checkpoints");
+            }
             continue;
         }
         KernelTimer kt(t, s, prof, ARA_KERNEL_TRIAL_PASS);

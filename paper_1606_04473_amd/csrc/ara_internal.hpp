@@ -406,6 +406,12 @@ hipError_t launch_portfolio_sum(const PortfolioSumArgs& a, int n_cu, hipStream_t
 // part_scratch (P = catalogue parts)
 hipError_t launch_event_nets(const int64_t* offsets, const uint32_t* ids, const void* part_scratch, int P,
                              int64_t C, uint64_t* probe, const LayerArgs& L, double* nets, int n_cu, hipStream_t s);
+// the forward's stride checkpoints in the same time-ordered pass: slot b of
+// `stride` receives the running total S of the trial that owns global event
+// 64b + 63, after that event (slots outside the layer's trials untouched)
+hipError_t launch_stride_checkpoints(const int64_t* offsets, const uint32_t* ids, const void* part_scratch, int P,
+                                     int64_t C, uint64_t* probe, const LayerArgs& L, double* stride, int n_cu,
+                                     hipStream_t s);
 int64_t probe_table_bytes(int64_t C);   // scratch for launch_event_nets' probe words
 hipError_t launch_debug_lookups(const int64_t* offsets, const uint32_t* ids, const double* elts,
                                 int64_t C, const LayerArgs& L, int64_t trial, uint32_t* ids_out,

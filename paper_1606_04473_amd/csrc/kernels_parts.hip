@@ -1644,8 +1644,10 @@ __global__ __launch_bounds__(256) void coarse_map_kernel(const uint64_t* __restr
 // and the net is A_d - A_{d-1}, with A_{d-1} = A_0 = clamp(0; AggR, AggL)
 // for a trial's first event, so a trial's nets telescope to its year loss
 // minus A_0.  Nets are staged in LDS and written with non-temporal stores of
-// 64 consecutive values.
-template <int kE>
+// 64 consecutive values.  With kStride the kernel writes, instead of nets,
+// the running total S_d of every position d = 64b + 63 to slot b of `nets`
+// (the stride checkpoints of the forward pass).
+template <int kE, bool kStride = false>
 __global__ __launch_bounds__(kNetsThreads) void event_nets_kernel(const int64_t* __restrict__ offsets,
                                                                   const uint32_t* __restrict__ ids,
                                                                   const uint64_t* __restrict__ probe,
@@ -1766,19 +1768,25 @@ __global__ __launch_bounds__(kNetsThreads) void event_nets_kernel(const int64_t*
                 rl = 0.0;
             }
             dd_add(rh, rl, oq[q]);
-            st[lane * kE + q] = apply_terms(rh + rl, L.aggR, L.aggL);
+            if constexpr (kStride) {
+                if (ok[q] && ((pos + q) & 63) == 63) nets[(pos + q) >> 6] = rh + rl;
+            } else {
+                st[lane * kE + q] = apply_terms(rh + rl, L.aggR, L.aggL);
+            }
         }
         __builtin_amdgcn_wave_barrier();
         // nets of 64 consecutive positions per store; A of the position before
         // a trial's first event is A_0, before the step's first one a_prev
+        if constexpr (!kStride) {
 #pragma unroll
-        for (int q = 0; q < kE; ++q) {
-            const int i = q * 64 + lane;
-            const int64_t p = c + i;
-            const double before = fl[i] ? A0 : (i == 0 ? a_prev : st[i - 1]);
-            if (p >= P0 && p < P1) __builtin_nontemporal_store(st[i] - before, nets + (p - ev0));
+            for (int q = 0; q < kE; ++q) {
+                const int i = q * 64 + lane;
+                const int64_t p = c + i;
+                const double before = fl[i] ? A0 : (i == 0 ? a_prev : st[i - 1]);
+                if (p >= P0 && p < P1) __builtin_nontemporal_store(st[i] - before, nets + (p - ev0));
+            }
+            a_prev = st[kW - 1];
         }
-        a_prev = st[kW - 1];
         ch = readlane_f64(sh, 63);
         cl = readlane_f64(sl, 63);
         __builtin_amdgcn_wave_barrier();
@@ -1796,8 +1804,11 @@ int64_t probe_table_bytes(int64_t C) {
            kCoarseBytes;
 }
 
-hipError_t launch_event_nets(const int64_t* offsets, const uint32_t* ids, const void* part_scratch, int P,
-                             int64_t C, uint64_t* probe, const LayerArgs& L, double* nets, int n_cu, hipStream_t s) {
+namespace {
+
+hipError_t launch_nets_or_stride(const int64_t* offsets, const uint32_t* ids, const void* part_scratch, int P,
+                                 int64_t C, uint64_t* probe, const LayerArgs& L, double* out, bool stride, int n_cu,
+                                 hipStream_t s) {
     if (L.trial_count <= 0) return hipSuccess;
     PartScratch ps = carve_parts(const_cast<void*>(part_scratch), P);
     const int64_t n_words = (C + (1 << kProbeShift) - 1) >> kProbeShift;
@@ -1821,9 +1832,26 @@ hipError_t launch_event_nets(const int64_t* offsets, const uint32_t* ids, const 
     int64_t blocks = (L.trial_count + kNetsThreads / 64 - 1) / (kNetsThreads / 64);
     const int64_t cap = static_cast<int64_t>(n_cu) * per_cu;
     if (blocks > cap) blocks = cap;
-    hipLaunchKernelGGL(event_nets_kernel<4>, dim3(static_cast<uint32_t>(blocks)), dim3(kNetsThreads), lds, s, offsets,
-                       ids, probe, coarse, cshift, n_cw, ps.compact, L, nets);
+    if (stride)
+        hipLaunchKernelGGL((event_nets_kernel<4, true>), dim3(static_cast<uint32_t>(blocks)), dim3(kNetsThreads), lds,
+                           s, offsets, ids, probe, coarse, cshift, n_cw, ps.compact, L, out);
+    else
+        hipLaunchKernelGGL((event_nets_kernel<4, false>), dim3(static_cast<uint32_t>(blocks)), dim3(kNetsThreads), lds,
+                           s, offsets, ids, probe, coarse, cshift, n_cw, ps.compact, L, out);
     return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_event_nets(const int64_t* offsets, const uint32_t* ids, const void* part_scratch, int P,
+                             int64_t C, uint64_t* probe, const LayerArgs& L, double* nets, int n_cu, hipStream_t s) {
+    return launch_nets_or_stride(offsets, ids, part_scratch, P, C, probe, L, nets, false, n_cu, s);
+}
+
+hipError_t launch_stride_checkpoints(const int64_t* offsets, const uint32_t* ids, const void* part_scratch, int P,
+                                     int64_t C, uint64_t* probe, const LayerArgs& L, double* stride, int n_cu,
+                                     hipStream_t s) {
+    return launch_nets_or_stride(offsets, ids, part_scratch, P, C, probe, L, stride, true, n_cu, s);
 }
 
 hipError_t launch_part_fold(const double* o, int64_t C, int P, void* scratch, hipStream_t s, bool with_ranks) {

@@ -249,22 +249,27 @@ def test_config0_checkpoints(ara, cfg0):
         ara.read_checkpoints(tables, 1)                   # no stride checkpoints were asked for
     ok, worst = _close(ara.read_checkpoints(tables, 0), S)
     assert ok, worst
-    ara.run_layers(tables, [spec], flags=ara.ARA_CHECKPOINT_STRIDE)
-    S_gpu = ara.read_checkpoints(tables, 0)
-    ok, worst = _close(S_gpu, S)
-    assert ok, worst
-    slots = ara.read_checkpoints(tables, 1)
     _, o = oracle.occurrence_catalogue(pool, layer)
     trial_of = np.repeat(np.arange(yet.n_trials), np.diff(yet.offsets))
-    checked = 0
-    for b in range(slots.shape[0]):
-        last = 64 * b + 63
-        t = trial_of[last]
-        start = yet.offsets[t]
-        pref = math.fsum(o[yet.ids[start:last + 1]].tolist())
-        assert abs(slots[b] - pref) <= REL * pref, b
-        checked += 1
-    assert checked == yet.n_events // 64
+    # the stride slots after the streaming pass (0), the rank-based pass (1:
+    # the time-ordered trial pass writes them) and the XCD-affine pass (2)
+    for pv in (0, 1, 2):
+        ara.set_tuning(tables, pass_variant=pv)
+        ara.run_layers(tables, [spec], flags=ara.ARA_CHECKPOINT_STRIDE)
+        S_gpu = ara.read_checkpoints(tables, 0)
+        ok, worst = _close(S_gpu, S)
+        assert ok, (pv, worst)
+        slots = ara.read_checkpoints(tables, 1)
+        checked = 0
+        for b in range(slots.shape[0]):
+            last = 64 * b + 63
+            t = trial_of[last]
+            start = yet.offsets[t]
+            pref = math.fsum(o[yet.ids[start:last + 1]].tolist())
+            assert abs(slots[b] - pref) <= REL * pref, (pv, b)
+            checked += 1
+        assert checked == yet.n_events // 64
+    ara.set_tuning(tables)
 
 
 def test_config0_gradients_match_oracle_exactly(ara, cfg0):
