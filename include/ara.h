@@ -161,7 +161,9 @@ typedef struct ara_tuning {
                                        to 2 when the tables hold no such copy), 1 = the 32-bit
                                        partitioned copy with LDS ranks + compact values, one
                                        persistent launch for several layers, 2 = the 32-bit
-                                       partitioned copy, each XCD serving its own catalogue parts */
+                                       partitioned copy, each XCD serving its own catalogue parts.
+                                       ara_backward's histogram follows it: 0 over the 16-bit copy,
+                                       1 and 2 over the 32-bit copy */
     int32_t reserved;
 } ara_tuning;
 
@@ -299,7 +301,10 @@ ara_status ara_risk_metrics_noalloc(const double* ylt, int64_t n_trials, const d
  * Requires a preceding ara_run_layers(tables, layer, 1, ..., ARA_CHECKPOINT_S)
  * with identical layer terms, else ARA_ERR_NOT_READY.  grad_mean/grad_tvar
  * are host memory (2J + 4 doubles each), or device memory with
- * ARA_DEVICE_PTR.  Either may be NULL to skip it.
+ * ARA_DEVICE_PTR.  Either may be NULL to skip it.  The per-event occurrence
+ * counts come from one pass over the YET: with pass_variant 0 (the default)
+ * over the 16-bit part-major copy, else over the 32-bit partitioned copy
+ * (the plain layout's own pass without either); all give the same integers.
  */
 ara_status ara_backward(ara_tables* tables, const ara_layer* layer, double tvar_p,
                         double* grad_mean, double* grad_tvar, uint32_t flags, void* stream);

@@ -1370,6 +1370,9 @@ ara_status ara_backward(ara_tables* t, const ara_layer* layer, double tvar_p, do
     // of the part images, rebuilt here from a fold of the layer
     PoolBuffer obuf, pbuf;
     const bool use_parts = t->parts.P > 0;
+    // pass_variant 0: the histogram streams the 16-bit copy when the tables
+    // hold one; else the XCD-affine pass over the 32-bit partitioned copy
+    const bool use_stream = use_parts && t->tuning.pass_variant == 0 && t->stream.P > 0;
     if (use_parts) {
         const ara_tuning tu = t->tuning;   // t->mu is held
         HIP_TRY(obuf.alloc(sizeof(double) * t->C, s), "scratch for occurrence losses");
@@ -1387,7 +1390,7 @@ ara_status ara_backward(ara_tables* t, const ara_layer* layer, double tvar_p, do
     }
     HIP_TRY(ara::launch_adjoint(t->offsets, t->ids, t->elts, t->C, L, t->ck.S, t->ck.ylt, m, scratch.p, gm, gt,
                                 t->n_cu, s, use_parts ? &t->parts : nullptr, pbuf.p, t->n_trials,
-                                t->sparse.chunk_off ? &t->sparse : nullptr),
+                                t->sparse.chunk_off ? &t->sparse : nullptr, use_stream ? &t->stream : nullptr),
             "adjoint kernels");
     if (!dev) {
         std::vector<double> h(2 * P);

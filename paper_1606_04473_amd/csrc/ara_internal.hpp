@@ -187,6 +187,17 @@ hipError_t launch_stream_pass(const StreamLayout& lay, int64_t C, const LayerArg
                               int n_img_parts, void* partials, int n_cu, hipStream_t s);
 hipError_t launch_stream_combine(const StreamLayout& lay, const LayerArgs& L, const LayerArgs* L_dev,
                                  const void* partials, double* ylt, double* S, hipStream_t s);
+struct TailStats;
+// the backward histogram over the same stream: for the trials inside the
+// aggregate band, occurrences of each nonzero-o(E) event added to w_mean and
+// TVaR weights to w_tvar (both [C], zeroed by the caller); S and ylt are the
+// checkpointed forward's, tail its order statistics on the device.  scratch
+// holds stream_adjoint_scratch_bytes(L.trial_count) bytes.
+int64_t stream_adjoint_scratch_bytes(int64_t trials);
+hipError_t launch_stream_adjoint(const StreamLayout& lay, int64_t C, const LayerArgs& L, void* part_scratch,
+                                 int n_img_parts, const double* S, const double* ylt, const TailStats* tail,
+                                 void* scratch, int64_t scratch_bytes, uint64_t* w_mean, uint64_t* w_tvar, int n_cu,
+                                 hipStream_t s);
 
 constexpr int kXcds = 8;           // gfx950 (MI355X): 8 XCDs, workgroups dispatched round-robin
 
@@ -477,12 +488,13 @@ hipError_t launch_part_adjoint(const PartLayout& lay, int64_t N, const LayerArgs
                                uint64_t* w_tvar, int n_cu, hipStream_t s);
 
 // adjoint; with `parts` (and `part_scratch` holding the forward's part images)
-// the histogram pass runs over the partitioned layout
+// the histogram pass runs over the partitioned layout, or over the 16-bit
+// stream when `stream` is given and holds one
 int64_t adjoint_scratch_bytes(int64_t C, int J, int64_t n);
 hipError_t launch_adjoint(const int64_t* offsets, const uint32_t* ids, const double* elts,
                           int64_t C, const LayerArgs& L, const double* S, const double* ylt,
                           int64_t m, void* scratch, double* d_grad_mean, double* d_grad_tvar,
                           int n_cu, hipStream_t s, const PartLayout* parts, void* part_scratch,
-                          int64_t n_trials_total, const SparsePool* sp);
+                          int64_t n_trials_total, const SparsePool* sp, const StreamLayout* stream);
 
 }  // namespace ara

@@ -33,6 +33,8 @@ struct AdjScratch {
     uint64_t* w_tvar;      // [C]
     long long* acc;        // [2][kMaxP] integer numerators
     TailStats* tail;
+    void* cls;             // trial classes of the stream histogram
+    int64_t cls_bytes;
     void* tail_scratch;
 };
 
@@ -294,7 +296,7 @@ __global__ void finalize_kernel(const long long* acc, const TailStats* tail, int
     if (grad_tvar) grad_tvar[i] = static_cast<double>(acc[kMaxP + i]) / static_cast<double>(ts.m * ts.c_eq);
 }
 
-AdjScratch carve(void* base, int64_t C) {
+AdjScratch carve(void* base, int64_t C, int64_t n) {
     char* p = static_cast<char*>(base);
     AdjScratch s;
     const int64_t Ca = (C + 255) & ~int64_t(255);
@@ -308,6 +310,9 @@ AdjScratch carve(void* base, int64_t C) {
     p += 256;
     s.mark = reinterpret_cast<uint8_t*>(p);
     p += Ca;
+    s.cls = p;
+    s.cls_bytes = (stream_adjoint_scratch_bytes(n) + 255) & ~int64_t(255);
+    p += s.cls_bytes;
     s.tail_scratch = p;
     return s;
 }
@@ -317,15 +322,16 @@ AdjScratch carve(void* base, int64_t C) {
 int64_t adjoint_scratch_bytes(int64_t C, int J, int64_t n) {
     (void)J;
     const int64_t Ca = (C + 255) & ~int64_t(255);
-    return Ca * (2 * sizeof(uint64_t) + 1) + 2 * kMaxP * sizeof(long long) + 256 + tail_stats_scratch_bytes(n);
+    return Ca * (2 * sizeof(uint64_t) + 1) + 2 * kMaxP * sizeof(long long) + 256 +
+           ((stream_adjoint_scratch_bytes(n) + 255) & ~int64_t(255)) + tail_stats_scratch_bytes(n);
 }
 
 hipError_t launch_adjoint(const int64_t* offsets, const uint32_t* ids, const double* elts, int64_t C,
                           const LayerArgs& L, const double* S, const double* ylt, int64_t m, void* scratch,
                           double* d_grad_mean, double* d_grad_tvar, int n_cu, hipStream_t s,
                           const PartLayout* parts, void* part_scratch, int64_t n_trials_total,
-                          const SparsePool* sp) {
-    AdjScratch a = carve(scratch, C);
+                          const SparsePool* sp, const StreamLayout* stream) {
+    AdjScratch a = carve(scratch, C, L.trial_count);
     hipError_t err;
     const int64_t n = L.trial_count;
     if ((err = launch_tail_stats(ylt, n, m, a.tail_scratch, a.tail, n_cu, s)) != hipSuccess) return err;
@@ -343,9 +349,14 @@ hipError_t launch_adjoint(const int64_t* offsets, const uint32_t* ids, const dou
         hipLaunchKernelGGL(agg_counts_kernel, dim3(static_cast<uint32_t>(ab)), dim3(256), 0, s, L, S, ylt, a.tail,
                            a.acc);
         if ((err = hipGetLastError()) != hipSuccess) return err;
-        if ((err = launch_part_adjoint(*parts, n_trials_total, L, part_scratch, S, ylt, a.tail, a.w_mean,
-                                       a.w_tvar, n_cu, s)) != hipSuccess)
+        if (stream && stream->P > 0 && (stream->P - 1) / 4 < parts->P) {
+            if ((err = launch_stream_adjoint(*stream, C, L, part_scratch, parts->P, S, ylt, a.tail, a.cls,
+                                             a.cls_bytes, a.w_mean, a.w_tvar, n_cu, s)) != hipSuccess)
+                return err;
+        } else if ((err = launch_part_adjoint(*parts, n_trials_total, L, part_scratch, S, ylt, a.tail, a.w_mean,
+                                              a.w_tvar, n_cu, s)) != hipSuccess) {
             return err;
+        }
     } else {
         int64_t tblocks = (n + 3) / 4;
         if (tblocks > int64_t(n_cu) * 8) tblocks = int64_t(n_cu) * 8;

@@ -31,6 +31,10 @@
 //  * each (part, trial) partial sum is written once (high part FP64, low part
 //    FP32); the combine adds a trial's partials in part order, rounds once and
 //    applies the aggregate terms.
+//  * the backward's histogram (how often each event with o(E) != 0 occurs in
+//    the trials inside the aggregate band, and the TVaR weights of the tail
+//    trials) is the same kernel instantiated with kAdj: the same test and
+//    queue, a drain that counts occurrences in LDS instead of summing losses.
 #include <cmath>
 #include <vector>
 
@@ -258,10 +262,31 @@ __device__ __forceinline__ uint32_t stream_wave_scan(uint32_t x) {
     return x;
 }
 
+// Extra arguments of the backward histogram over the stream.  Lane i of group
+// g holds trial g*G + i's class: 0 outside the layer's trials or outside the
+// aggregate band, else bit 0, plus bit 1 when its year loss lies above the
+// m-th largest (TVaR weight c_eq) or bit 2 when it equals it (weight m - c_gt)
+struct StreamAdjArgs {
+    const uint8_t* cls;             // [g_hi - g_lo][64]
+    uint64_t* w_mean;               // [C] occurrences in trials inside the band
+    uint64_t* w_tvar;               // [C] TVaR weights
+    const TailStats* tail;
+};
+
+// The pass over the stream.  The forward (kAdj false) sums each trial's
+// nonzero o(E), part by part.  The backward histogram (kAdj true) runs the
+// same test and queue; its drain counts each queued occurrence of a trial
+// inside the aggregate band per event, in 32-bit LDS counters indexed by rank
+// that go to W_mean when the workgroup leaves the part (ranks past the
+// counters, and the TVaR weights of the few tail trials, use global atomics).
+// All weights are integers, so the order of the additions does not matter.
+//
 // gstart_all is a.gstart again, as a restrict-qualified parameter: its loads at
 // wave-uniform addresses then go through the scalar unit, so a group's range
 // never waits on the vector loads in flight
-__global__ __launch_bounds__(1024) void stream_pass_kernel(StreamPassArgs a, const uint32_t* __restrict__ gstart_all) {
+template <bool kAdj>
+__global__ __launch_bounds__(1024) void stream_pass_kernel(StreamPassArgs a, StreamAdjArgs adj,
+                                                           const uint32_t* __restrict__ gstart_all) {
     constexpr int kU = 2;                                     // 16-byte loads per lane per batch
     constexpr uint32_t kBatch = 64 * kChunkIds * kU;          // IDs per batch
     constexpr int kQ = 64 * kChunkIds;                        // 16-bit queue entries per wave: one load's IDs
@@ -273,23 +298,29 @@ __global__ __launch_bounds__(1024) void stream_pass_kernel(StreamPassArgs a, con
     // LDS, one block: the rank of each 128-event block's first nonzero event
     // minus one, then the byte map (a byte's offset from the map's start is its
     // event's part-relative ID; that offset fits the LDS instructions' constant
-    // field, so a lookup costs no address arithmetic), the 16 hit queues, and as
-    // many of the part's nonzero o(E) as fit, followed by one 0.0 that the
-    // drain's idle slots read
+    // field, so a lookup costs no address arithmetic), the 16 hit queues, and
+    // then the forward's copy of as many of the part's nonzero o(E) as fit,
+    // followed by one 0.0 that the drain's idle slots read, or the backward's
+    // counters
     constexpr uint32_t kMapOff = (kQSize / 128) * 4;
     constexpr uint32_t kQueueOff = kMapOff + kQSize;
     constexpr uint32_t kValOff = kQueueOff + 16 * kQ * 2;
     constexpr int kCap = static_cast<int>((160 * 1024 - kValOff) / 8) - 1;
+    constexpr int kCnt = static_cast<int>((160 * 1024 - kValOff) / 4);
     static_assert(kValOff % 16 == 0 && kCap > 0 && kMapOff < 65536, "LDS layout");
-    __shared__ __attribute__((aligned(16))) uint8_t lds[kValOff + (kCap + 1) * 8];
+    constexpr uint32_t kLdsBytes = kAdj ? kValOff + kCnt * 4 : kValOff + (kCap + 1) * 8;
+    __shared__ __attribute__((aligned(16))) uint8_t lds[kLdsBytes];
     uint32_t* bases = reinterpret_cast<uint32_t*>(lds);
     uint8_t* map = lds + kMapOff;
     double* vals = reinterpret_cast<double*>(lds + kValOff);
+    uint32_t* cnt = reinterpret_cast<uint32_t*>(lds + kValOff);
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
     uint16_t* q = reinterpret_cast<uint16_t*>(lds + kQueueOff) + wv * kQ;
     const int G = a.G;
     const int64_t count = a.t_hi - a.t_lo;
+    TailStats ts{};
+    if constexpr (kAdj) ts = *adj.tail;
 
     // the (part, group) work list, part-major; workgroup b runs on XCD b % n_xcd,
     // and each XCD takes a contiguous share of the list
@@ -301,7 +332,27 @@ __global__ __launch_bounds__(1024) void stream_pass_kernel(StreamPassArgs a, con
     int64_t it = l * n_items / n_wg;
     const int64_t it_end = (l + 1) * n_items / n_wg;
 
+    // the backward's counters to W_mean once every wave is done with the part,
+    // in the byte map's event order; the part before the first has none
+    int prev_pq = -1;
+    auto flush_counts = [&]() {
+        __syncthreads();
+        const int64_t ebase = static_cast<int64_t>(prev_pq) << kStreamShift;
+        for (int e = threadIdx.x; e < kQSize; e += blockDim.x) {
+            const uint32_t b = map[e];
+            if (!b) continue;
+            const uint32_t r = bases[e >> 7] + b;
+            if (r >= static_cast<uint32_t>(kCnt)) continue;
+            const uint32_t cv = cnt[r];
+            if (cv) atomicAdd(reinterpret_cast<unsigned long long*>(&adj.w_mean[ebase + e]),
+                              static_cast<unsigned long long>(cv));
+        }
+    };
+
     while (it < it_end) {
+        if constexpr (kAdj) {
+            if (prev_pq >= 0) flush_counts();
+        }
         const int pq = static_cast<int>(it / NGr);
         const int64_t seg_end = min(it_end, static_cast<int64_t>(pq + 1) * NGr);
         const int64_t ga = a.g_lo + (it - static_cast<int64_t>(pq) * NGr);
@@ -319,14 +370,15 @@ __global__ __launch_bounds__(1024) void stream_pass_kernel(StreamPassArgs a, con
         // the part's nonzero count, from the rank of the next quarter's first
         // superblock (the next image part's, after the last quarter; unknown
         // after the catalogue's last image part): when every rank fits the LDS
-        // copy of the values the drain skips the L2 fallback
+        // copy of the values (the counters) the drain skips the L2 fallback
+        // (the global atomics)
         const int64_t n_img = (a.C + (int64_t(1) << kImgShift) - 1) >> kImgShift;
         bool fits = false;
         if (is < 3 || ip + 1 < n_img) {
             const uint32_t g_next = is < 3 ? gb32[kImgBase32 / 4]
                                            : *reinterpret_cast<const uint32_t*>(
                                                  gimg + kImgPartBytes + int64_t(kImgWords) * 8 + int64_t(kImgRank16) * 2);
-            fits = g_next - g0 <= static_cast<uint32_t>(kCap);
+            fits = g_next - g0 <= static_cast<uint32_t>(kAdj ? kCnt : kCap);
         }
         __syncthreads();
         {
@@ -351,15 +403,20 @@ __global__ __launch_bounds__(1024) void stream_pass_kernel(StreamPassArgs a, con
             const int k = threadIdx.x;
             bases[k] = gb32[k >> 5] + gr16[k] - g0 - 1u;
         }
-        for (int k = threadIdx.x; k <= kCap; k += blockDim.x) {
-            const int64_t gk = static_cast<int64_t>(g0) + k;
-            vals[k] = k < kCap && gk < a.C ? a.compact[gk] : 0.0;
+        if constexpr (kAdj) {
+            for (int k = threadIdx.x; k < kCnt; k += blockDim.x) cnt[k] = 0u;
+        } else {
+            for (int k = threadIdx.x; k <= kCap; k += blockDim.x) {
+                const int64_t gk = static_cast<int64_t>(g0) + k;
+                vals[k] = k < kCap && gk < a.C ? a.compact[gk] : 0.0;
+            }
         }
         __syncthreads();
 
         // ---- this wave's groups [wa, wb) of the part
         const int64_t n = gb - ga;
         const int64_t wa = ga + wv * n / 16, wb = ga + (wv + 1) * n / 16;
+        if constexpr (kAdj) prev_pq = pq;
         if (wa >= wb) continue;
         const uint16_t* ids = a.ids + a.part_base[pq];
         const uint32_t* gs = gstart_all + static_cast<int64_t>(pq) * (a.NG + 1);
@@ -367,14 +424,17 @@ __global__ __launch_bounds__(1024) void stream_pass_kernel(StreamPassArgs a, con
         const double* gcompact = a.compact + g0;
         double* out_hi = a.part_hi + static_cast<int64_t>(pq) * count;
         float* out_lo = a.part_lo + static_cast<int64_t>(pq) * count;
+        const int64_t ebase = static_cast<int64_t>(pq) << kStreamShift;   // catalogue ID of the part's event 0
         // B, lane i: where trial i of group g starts; lanes >= G: the group's
         // end.  The next group's trial ends are loaded with every batch (every
         // lane loads, lane 0 then drops its value; no value is carried over, so
         // no copy waits on the load) and added to its start when it begins.
+        // The backward loads the next group's trial classes alongside.
         auto group_ends = [&](int64_t gg) -> uint32_t {
             return ge[gg * kStreamGroupSlots + (lane == 0 ? 0 : lane - 1)];
         };
         auto starts = [&](uint32_t s0, uint32_t ends) -> uint32_t { return lane == 0 ? s0 : s0 + ends; };
+        auto group_class = [&](int64_t gg) -> uint32_t { return adj.cls[(gg - a.g_lo) * 64 + lane]; };
         // a group's IDs run from its start to the next group's start (its end
         // rounded up to the 8-ID chunk: the same chunks)
         int64_t g = wa;
@@ -382,6 +442,8 @@ __global__ __launch_bounds__(1024) void stream_pass_kernel(StreamPassArgs a, con
         uint32_t re = gs[g + 1];
         uint32_t B = starts(rs, group_ends(g));
         uint32_t next_ends = 0;
+        uint32_t cls = 0, next_cls = 0;
+        if constexpr (kAdj) cls = group_class(g);
         uint32_t c = rs;                            // first ID of the batch (a multiple of 8)
         int qs = kInf;                              // lane i: queue index of trial i's first hit
         int qn = 0;                                 // queue entries
@@ -401,6 +463,7 @@ __global__ __launch_bounds__(1024) void stream_pass_kernel(StreamPassArgs a, con
         // the batch after the one at c: the rest of this group, else the next group's first
         auto load_next = [&](u32x4* v) {
             next_ends = group_ends(g + 1 < wb ? g + 1 : g);
+            if constexpr (kAdj) next_cls = group_class(g + 1 < wb ? g + 1 : g);
             if (c + kBatch < re) {
                 load_batch(c + kBatch, re, v);
             } else {
@@ -410,7 +473,7 @@ __global__ __launch_bounds__(1024) void stream_pass_kernel(StreamPassArgs a, con
                 load_batch(n_rs, n_re, v);
             }
         };
-        // sum the queued hits: lane t takes trial t's entries, four at a time.
+        // the queued hits: lane t takes trial t's entries, four at a time.
         // The loads of a step are issued together.
         auto rank = [&](uint32_t e) -> uint32_t {
             // rank among the part's nonzero events: the block's base (minus one)
@@ -423,7 +486,57 @@ __global__ __launch_bounds__(1024) void stream_pass_kernel(StreamPassArgs a, con
             lo = lo < 0 ? 0 : (lo > qn ? qn : lo);
             hi = hi < 0 ? 0 : (hi > qn ? qn : hi);
             if (lane >= G) hi = lo;                 // lanes past the group's trials
-            if (fits) {
+            if constexpr (kAdj) {
+                if (!(cls & 1u)) hi = lo;           // outside the aggregate band: no weight
+                if (fits) {
+                    // every rank has its LDS counter: whole steps unchecked,
+                    // then the last one to three entries (their queue reads,
+                    // at most two entries past a full queue, stay inside the
+                    // allocation)
+                    int j = lo;
+                    for (; j + kR <= hi; j += kR) {
+                        uint32_t e[kR], rk[kR];
+#pragma unroll
+                        for (int r2 = 0; r2 < kR; ++r2) e[r2] = q[j + r2];
+#pragma unroll
+                        for (int r2 = 0; r2 < kR; ++r2) rk[r2] = rank(e[r2]);
+#pragma unroll
+                        for (int r2 = 0; r2 < kR; ++r2) atomicAdd(&cnt[rk[r2]], 1u);
+                    }
+                    if (j < hi) {
+                        uint32_t e[kR - 1], rk[kR - 1];
+#pragma unroll
+                        for (int r2 = 0; r2 < kR - 1; ++r2) e[r2] = q[j + r2];
+#pragma unroll
+                        for (int r2 = 0; r2 < kR - 1; ++r2) rk[r2] = rank(e[r2]);
+#pragma unroll
+                        for (int r2 = 0; r2 < kR - 1; ++r2)
+                            if (j + r2 < hi) atomicAdd(&cnt[rk[r2]], 1u);
+                    }
+                } else {
+                    for (int j = lo; j < hi; j += kR) {
+                        uint32_t e[kR], rk[kR];
+#pragma unroll
+                        for (int r2 = 0; r2 < kR; ++r2) e[r2] = q[j + r2];
+#pragma unroll
+                        for (int r2 = 0; r2 < kR; ++r2) rk[r2] = rank(e[r2]);
+#pragma unroll
+                        for (int r2 = 0; r2 < kR; ++r2) {
+                            if (j + r2 >= hi) continue;
+                            if (rk[r2] < static_cast<uint32_t>(kCnt))
+                                atomicAdd(&cnt[rk[r2]], 1u);
+                            else
+                                atomicAdd(reinterpret_cast<unsigned long long*>(&adj.w_mean[ebase + e[r2]]), 1ull);
+                        }
+                    }
+                }
+                if (cls & 6u) {
+                    // a tail trial: its TVaR weight on each of its occurrences
+                    const unsigned long long wt = static_cast<unsigned long long>((cls & 2u) ? ts.c_eq : ts.m - ts.c_gt);
+                    for (int j = lo; j < hi; ++j)
+                        atomicAdd(reinterpret_cast<unsigned long long*>(&adj.w_tvar[ebase + q[j]]), wt);
+                }
+            } else if (fits) {
                 // every rank has its value in LDS: whole steps unchecked, then
                 // the last one to three entries, whose idle slots read the 0.0
                 // after the copied losses (their queue reads, at most two entries
@@ -490,7 +603,7 @@ __global__ __launch_bounds__(1024) void stream_pass_kernel(StreamPassArgs a, con
         auto process = [&](const u32x4* v) {
             // Chunks past the group's end read padding or the next group's IDs;
             // their hits are queued after the group's end boundary (lanes >= G
-            // note where it falls), so no trial sums them.
+            // note where it falls), so no trial takes them.
             uint32_t m[kU];                         // bit w: ID w of the lane's chunk is a hit
             bool hit[kU][8];
 #pragma unroll
@@ -581,13 +694,13 @@ __global__ __launch_bounds__(1024) void stream_pass_kernel(StreamPassArgs a, con
             __builtin_amdgcn_s_waitcnt(kWaitVm0);
         };
         // after a batch: advance; at the end of the group drain the queue, hold
-        // the partial sums and move to the next group (its first batch is in
-        // flight).  Returns false after the wave's last group.
+        // the partial sums (the forward) and move to the next group (its first
+        // batch is in flight).  Returns false after the wave's last group.
         auto step = [&]() -> bool {
             c += kBatch;
             if (c < re) return true;
             drain();
-            {
+            if constexpr (!kAdj) {
                 // the group's sums join the held results (newest first)
 #pragma unroll
                 for (int k = kHeld - 1; k > 0; --k) {
@@ -598,15 +711,16 @@ __global__ __launch_bounds__(1024) void stream_pass_kernel(StreamPassArgs a, con
                 held_lo[0] = static_cast<float>(acc_lo - (held_hi[0] - acc_hi));
                 ++n_held;
                 if (n_held == kHeld || g + 1 >= wb) flush();
+                acc_hi = 0.0;
+                acc_lo = 0.0;
             }
-            acc_hi = 0.0;
-            acc_lo = 0.0;
             qs = kInf;
             if (g + 1 >= wb) return false;
             ++g;
             rs = gs[g];
             re = gs[g + 1];
             B = starts(rs, next_ends);
+            if constexpr (kAdj) cls = next_cls;
             c = rs;
             return true;
         };
@@ -623,6 +737,33 @@ __global__ __launch_bounds__(1024) void stream_pass_kernel(StreamPassArgs a, con
             process(bufB);
             if (!step()) break;
         }
+    }
+    if constexpr (kAdj) {
+        if (prev_pq >= 0) flush_counts();
+    }
+}
+
+// the trial classes of StreamAdjArgs, one byte per (group, lane) slot
+__global__ __launch_bounds__(256) void stream_class_kernel(const double* __restrict__ S, const double* __restrict__ ylt,
+                                                           const TailStats* __restrict__ tail, double aggR, double aggL,
+                                                           int64_t t_lo, int64_t t_hi, int G, int64_t g_lo,
+                                                           int64_t n_slots, uint8_t* __restrict__ cls) {
+    const TailStats ts = *tail;
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n_slots; i += stride) {
+        const int lane = static_cast<int>(i & 63);
+        const int64_t t = (g_lo + (i >> 6)) * G + lane;
+        uint32_t c = 0;
+        if (lane < G && t >= t_lo && t < t_hi) {
+            const int64_t k = t - t_lo;
+            const double ta = S[k] - aggR;
+            if ((ta > 0.0) && (ta < aggL)) {
+                // year losses are >= 0, so their bit patterns order like their values
+                const uint64_t key = __double_as_longlong(ylt[k] + 0.0);
+                c = 1u | (key > ts.v_bits ? 2u : (key == ts.v_bits ? 4u : 0u));
+            }
+        }
+        cls[i] = static_cast<uint8_t>(c);
     }
 }
 
@@ -771,10 +912,9 @@ int64_t stream_partials_bytes(const StreamLayout& lay, int64_t trials) {
     return static_cast<int64_t>(sizeof(double) + sizeof(float)) * n + 256;
 }
 
-hipError_t launch_stream_pass(const StreamLayout& lay, int64_t C, const LayerArgs& L, void* part_scratch,
-                              int n_img_parts, void* partials, int n_cu, hipStream_t s) {
-    if (L.trial_count <= 0) return hipSuccess;
-    if (lay.P <= 0 || (lay.P - 1) / 4 >= n_img_parts) return hipErrorInvalidValue;
+namespace {
+
+StreamPassArgs pass_args(const StreamLayout& lay, int64_t C, const LayerArgs& L, void* part_scratch, int n_img_parts) {
     StreamPassArgs a{};
     a.ids = lay.ids;
     a.part_base = lay.part_base;
@@ -790,16 +930,60 @@ hipError_t launch_stream_pass(const StreamLayout& lay, int64_t C, const LayerArg
     a.t_hi = L.trial_begin + L.trial_count;
     a.g_lo = a.t_lo / lay.G;
     a.g_hi = (a.t_hi + lay.G - 1) / lay.G;
-    a.part_hi = static_cast<double*>(partials);
-    a.part_lo = reinterpret_cast<float*>(a.part_hi + static_cast<int64_t>(lay.P) * L.trial_count);
     a.pad = lay.ids + lay.length;
     a.n_xcd = kXcds;
-    // one 1024-thread workgroup per CU (its LDS holds the part's byte map and
-    // values), a multiple of the XCD count
+    return a;
+}
+
+// one 1024-thread workgroup per CU (its LDS holds the part's byte map and
+// values or counters), a multiple of the XCD count
+uint32_t pass_grid(int n_cu) {
     int64_t grid = int64_t(n_cu);
     grid -= grid % kXcds;
     if (grid < kXcds) grid = kXcds;
-    hipLaunchKernelGGL(stream_pass_kernel, dim3(static_cast<uint32_t>(grid)), dim3(1024), 0, s, a, a.gstart);
+    return static_cast<uint32_t>(grid);
+}
+
+}  // namespace
+
+hipError_t launch_stream_pass(const StreamLayout& lay, int64_t C, const LayerArgs& L, void* part_scratch,
+                              int n_img_parts, void* partials, int n_cu, hipStream_t s) {
+    if (L.trial_count <= 0) return hipSuccess;
+    if (lay.P <= 0 || (lay.P - 1) / 4 >= n_img_parts) return hipErrorInvalidValue;
+    StreamPassArgs a = pass_args(lay, C, L, part_scratch, n_img_parts);
+    a.part_hi = static_cast<double*>(partials);
+    a.part_lo = reinterpret_cast<float*>(a.part_hi + static_cast<int64_t>(lay.P) * L.trial_count);
+    hipLaunchKernelGGL(stream_pass_kernel<false>, dim3(pass_grid(n_cu)), dim3(1024), 0, s, a, StreamAdjArgs{},
+                       a.gstart);
+    return hipGetLastError();
+}
+
+int64_t stream_adjoint_scratch_bytes(int64_t trials) {
+    // (group, lane) class slots: at most trials / 16 + 2 groups of 64
+    return 4 * (trials > 0 ? trials : 0) + 256;
+}
+
+hipError_t launch_stream_adjoint(const StreamLayout& lay, int64_t C, const LayerArgs& L, void* part_scratch,
+                                 int n_img_parts, const double* S, const double* ylt, const TailStats* tail,
+                                 void* scratch, int64_t scratch_bytes, uint64_t* w_mean, uint64_t* w_tvar, int n_cu,
+                                 hipStream_t s) {
+    if (L.trial_count <= 0) return hipSuccess;
+    if (lay.P <= 0 || (lay.P - 1) / 4 >= n_img_parts) return hipErrorInvalidValue;
+    const StreamPassArgs a = pass_args(lay, C, L, part_scratch, n_img_parts);
+    const int64_t n_slots = (a.g_hi - a.g_lo) * 64;
+    if (n_slots > scratch_bytes) return hipErrorInvalidValue;
+    StreamAdjArgs adj{};
+    adj.cls = static_cast<const uint8_t*>(scratch);
+    adj.w_mean = w_mean;
+    adj.w_tvar = w_tvar;
+    adj.tail = tail;
+    int64_t cb = (n_slots + 255) / 256;
+    if (cb > int64_t(n_cu) * 8) cb = int64_t(n_cu) * 8;
+    hipLaunchKernelGGL(stream_class_kernel, dim3(static_cast<uint32_t>(cb)), dim3(256), 0, s, S, ylt, tail, L.aggR,
+                       L.aggL, a.t_lo, a.t_hi, a.G, a.g_lo, n_slots, static_cast<uint8_t*>(scratch));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(stream_pass_kernel<true>, dim3(pass_grid(n_cu)), dim3(1024), 0, s, a, adj, a.gstart);
     return hipGetLastError();
 }
 

@@ -277,12 +277,16 @@ def test_config0_gradients_match_oracle_exactly(ara, cfg0):
     yet, pool, layer = w.yet, w.pool, w.layers[0]
     spec = _spec(ara, layer, pool, yet)
     ara.run_layers(tables, [spec], flags=ara.ARA_CHECKPOINT_S)
-    for p in (0.99, 0.9):
-        gm, gt = ara.backward(tables, spec, p)
-        g = oracle.gradients(yet, pool, layer, p, ylt=ref, S=S)
-        assert np.array_equal(gm, g["grad_mean"]), (gm, g["grad_mean"])
-        assert np.array_equal(gt, g["grad_tvar"]), (gt, g["grad_tvar"])
-    assert np.count_nonzero(gm) == gm.shape[0]
+    # the histogram over the 16-bit stream (0) and over the 32-bit partitioned copy (2)
+    for pv in (0, 2):
+        ara.set_tuning(tables, pass_variant=pv)
+        for p in (0.99, 0.9):
+            gm, gt = ara.backward(tables, spec, p)
+            g = oracle.gradients(yet, pool, layer, p, ylt=ref, S=S)
+            assert np.array_equal(gm, g["grad_mean"]), (pv, gm, g["grad_mean"])
+            assert np.array_equal(gt, g["grad_tvar"]), (pv, gt, g["grad_tvar"])
+        assert np.count_nonzero(gm) == gm.shape[0]
+    ara.set_tuning(tables)
 
 
 def test_backward_requires_checkpointed_forward(ara, cfg0):
@@ -751,16 +755,58 @@ def test_gradients_more_parts_than_xcds(ara):
         layer = Layer(np.array([3, 1, 0], dtype=np.int32), 1500.0, 3.0e6, 8.6e6, 6.2e6, begin, count)
         spec = _spec(ara, layer, pool, yet)
         ref, S = oracle.run_layer(yet, pool, layer)
-        for tables in (part, plain):
+        # the stream histogram (42 parts of 2^16 events), the XCD-affine one and
+        # the plain layout's
+        for tables, pv in ((part, 0), (part, 2), (plain, 0)):
+            ara.set_tuning(tables, pass_variant=pv)
             ara.run_layers(tables, [spec], flags=ara.ARA_CHECKPOINT_S)
             for p in (0.99, 0.9):
                 gm, gt = ara.backward(tables, spec, p)
                 g = oracle.gradients(yet, pool, layer, p, ylt=ref, S=S)
-                assert np.array_equal(gm, g["grad_mean"]), (begin, p, gm, g["grad_mean"])
-                assert np.array_equal(gt, g["grad_tvar"]), (begin, p, gt, g["grad_tvar"])
+                assert np.array_equal(gm, g["grad_mean"]), (begin, pv, p, gm, g["grad_mean"])
+                assert np.array_equal(gt, g["grad_tvar"]), (begin, pv, p, gt, g["grad_tvar"])
             assert np.count_nonzero(gm) >= gm.shape[0] - 1
+    assert part.layout()["stream_parts"] == 42
     part.close()
     plain.close()
+
+
+def test_stream_histogram_dense_parts_and_tail_ties(ara):
+    """The backward histogram over the 16-bit stream where most of each part's
+    events have o(E) != 0, so ranks run past the LDS counters (global atomics),
+    and whose last part is the last quarter of the last part image (its nonzero
+    count unknown: every rank checked).  Each trial appears three times in a
+    row, so year losses tie in threes and the TVaR threshold falls inside a
+    tie: trials above it weigh c_eq, trials at it m - c_gt.  Full range and a
+    sub-range that cuts groups; gradients must equal the oracle's."""
+    C = (1 << 18) + 3 * (1 << 16) + 1000
+    base = make_yet(700, 250.0, C, seed=131)
+    trips = [base.trial(t).tolist() for t in range(base.n_trials) for _ in range(3)]
+    yet = make_tiny_yet(trips, C)
+    pool = make_elt_pool(3, C, 380_000, seed=132)
+    tables = ara.create_tables(yet.offsets, yet.ids, pool.losses)
+    assert tables.layout()["stream_parts"] == 8
+    checked = 0
+    # AggR near the 30th percentile of S: about a third of the trials lie
+    # outside the aggregate band and carry no weight
+    for begin, count, p in ((0, yet.n_trials, 0.995), (0, yet.n_trials, 0.985), (301, 1201, 0.99)):
+        layer = Layer(np.array([2, 0, 1], dtype=np.int32), 100.0, INF, 5.0e7, INF, begin, count)
+        spec = _spec(ara, layer, pool, yet)
+        ref, S = oracle.run_layer(yet, pool, layer)
+        _, o = oracle.occurrence_catalogue(pool, layer)
+        assert np.count_nonzero(o[:1 << 16]) > 40_000          # far past the LDS counters
+        g = oracle.gradients(yet, pool, layer, p, ylt=ref, S=S)
+        assert g["c_eq"] == 3 and g["m"] - g["c_gt"] != 3     # the threshold inside a tie
+        assert 0.2 < np.mean(S <= 5.0e7) < 0.5
+        for pv in (0, 2):
+            ara.set_tuning(tables, pass_variant=pv)
+            ara.run_layers(tables, [spec], flags=ara.ARA_CHECKPOINT_S)
+            gm, gt = ara.backward(tables, spec, p)
+            assert np.array_equal(gm, g["grad_mean"]), (begin, pv, p)
+            assert np.array_equal(gt, g["grad_tvar"]), (begin, pv, p)
+            checked += 1
+    assert checked == 6
+    tables.close()
 
 
 def test_segment_padding_with_nonzero_last_events(ara):
@@ -926,10 +972,13 @@ def test_config1_prefix_full_parity_and_gradients(ara, cfg1):
     ref, S = oracle.run_layer(yet, pool, layer)
     ok, worst = _close(ylt, ref)
     assert ok, worst
-    gm, gt = ara.backward(tables, spec, 0.99)
     g = oracle.gradients(yet, pool, layer, 0.99, ylt=ref, S=S)
-    assert np.array_equal(gm, g["grad_mean"])
-    assert np.array_equal(gt, g["grad_tvar"])
+    for pv in (0, 2):
+        ara.set_tuning(tables, pass_variant=pv)
+        gm, gt = ara.backward(tables, spec, 0.99)
+        assert np.array_equal(gm, g["grad_mean"]), pv
+        assert np.array_equal(gt, g["grad_tvar"]), pv
+    ara.set_tuning(tables)
 
 
 def test_config1_gradient_vs_finite_differences(ara, cfg1):
