@@ -45,66 +45,148 @@ struct AdjScratch {
 // its occurrence-term slopes, and each nonzero loss (E, l) of ELT j its
 // per-ELT slopes; an absent loss has l - R_j <= 0 and no slope, so the sparse
 // entries give the dense kernel's integer sums.
+//
+// The chunk's entries of the layer's ELTs (in layer order) are first copied to
+// LDS, kStage at a time, with all their loads in flight together; the fold
+// and the per-ELT slopes then read LDS only, so the ordered fold costs one
+// barrier per ELT and no memory latency.  The weights of the chunk's events
+// are kept in LDS for the slopes.
 constexpr int kSparseChunk = 4096;                  // events per chunk of the sparse pool
-__global__ __launch_bounds__(256) void catalogue_sparse_kernel(SparsePool sp, int64_t C, LayerArgs L,
-                                                               const uint64_t* __restrict__ w_mean,
-                                                               const uint64_t* __restrict__ w_tvar,
-                                                               long long* __restrict__ acc) {
+constexpr int kStage = 4096;                        // pool entries staged in LDS at a time
+
+// sum over the wave's lanes
+__device__ __forceinline__ long long wave_sum_i64(long long v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+__global__ __launch_bounds__(1024) void catalogue_sparse_kernel(SparsePool sp, int64_t C, LayerArgs L,
+                                                                const uint64_t* __restrict__ w_mean,
+                                                                const uint64_t* __restrict__ w_tvar,
+                                                                long long* __restrict__ acc) {
     __shared__ double ys[kSparseChunk];
+    __shared__ long long wms[kSparseChunk], wvs[kSparseChunk];
     __shared__ uint8_t act[kSparseChunk];           // inside the occurrence band, with a weight
+    __shared__ double s_val[kStage];
+    __shared__ uint16_t s_ev[kStage];
+    __shared__ uint8_t s_j[kStage];
     __shared__ long long lacc[2 * kMaxP];
-    __shared__ int64_t rb[kMaxJ], re[kMaxJ];
+    __shared__ int64_t rb[kMaxJ], pre[kMaxJ + 1];
+    __shared__ double sR[kMaxJ], sLim[kMaxJ];
     const int t = threadIdx.x;
+    const int nt = blockDim.x;
     const int64_t chunk = blockIdx.x;
     const int64_t e0 = chunk * kSparseChunk;
     const int J = L.J;
     const int P = 2 * J + 4;
-    for (int i = t; i < kSparseChunk; i += blockDim.x) ys[i] = 0.0;
-    for (int i = t; i < 2 * kMaxP; i += blockDim.x) lacc[i] = 0;
+    for (int i = t; i < kSparseChunk; i += nt) ys[i] = 0.0;
+    for (int i = t; i < 2 * kMaxP; i += nt) lacc[i] = 0;
     if (t < J) {
-        const int64_t key = static_cast<int64_t>(L.idx[t]) * sp.n_chunks + chunk;
-        rb[t] = sp.chunk_off[key];
-        re[t] = sp.chunk_off[key + 1];
+        sR[t] = L.R[t];
+        sLim[t] = L.Lim[t];
+    }
+    if (t == 0) {
+        int64_t run = 0;
+        for (int j = 0; j < J; ++j) {
+            const int64_t key = static_cast<int64_t>(L.idx[j]) * sp.n_chunks + chunk;
+            const int64_t b = sp.chunk_off[key];
+            rb[j] = b;
+            pre[j] = run;
+            run += sp.chunk_off[key + 1] - b;
+        }
+        pre[J] = run;
     }
     __syncthreads();
-    for (int j = 0; j < J; ++j) {
-        const double R = L.R[j], Lim = L.Lim[j];
-        for (int64_t k = rb[j] + t; k < re[j]; k += blockDim.x) {
-            const int ev = sp.ev[k];
-            ys[ev] = ys[ev] + apply_terms(sp.val[k], R, Lim);
+    const int64_t n_ent = pre[J];
+    // entries [r0, r0 + nr) of the chunk's list (ELT by ELT) to LDS
+    auto stage = [&](int64_t r0, int nr) {
+        for (int i = t; i < nr; i += nt) {
+            const int64_t f = r0 + i;
+            int lo = 0, hi = J;                     // the ELT whose range holds f: pre[lo] <= f < pre[lo + 1]
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (pre[mid] <= f) lo = mid; else hi = mid;
+            }
+            const int64_t k = rb[lo] + (f - pre[lo]);
+            s_ev[i] = sp.ev[k];
+            s_val[i] = sp.val[k];
+            s_j[i] = static_cast<uint8_t>(lo);
         }
+    };
+    // the fold, ELT by ELT in layer order
+    for (int64_t r0 = 0; r0 < n_ent; r0 += kStage) {
+        const int nr = static_cast<int>(n_ent - r0 < kStage ? n_ent - r0 : kStage);
+        __syncthreads();                            // the previous round's entries are used
+        stage(r0, nr);
         __syncthreads();
+        for (int j = 0; j < J; ++j) {
+            const int64_t a = pre[j] > r0 ? pre[j] : r0;
+            const int64_t b = pre[j + 1] < r0 + nr ? pre[j + 1] : r0 + nr;
+            if (a >= b) continue;                   // uniform: no ELT j entries in this round
+            const double R = L.R[j], Lim = L.Lim[j];
+            for (int64_t f = a + t; f < b; f += nt) {
+                const int i = static_cast<int>(f - r0);
+                const int ev = s_ev[i];
+                ys[ev] = ys[ev] + apply_terms(s_val[i], R, Lim);
+            }
+            __syncthreads();
+        }
     }
-    for (int i = t; i < kSparseChunk; i += blockDim.x) {
-        const int64_t e = e0 + i;
-        uint8_t a = 0;
-        if (e < C) {
-            const long long wm = static_cast<long long>(w_mean[e]);
-            const long long wv = static_cast<long long>(w_tvar[e]);
-            if (wm != 0 || wv != 0) {
-                const double to = ys[i] - L.occR;
-                if (to > L.occL) {
-                    add_i64(&lacc[2 * J + 1], wm);
-                    if (wv) add_i64(&lacc[kMaxP + 2 * J + 1], wv);
-                }
-                if ((to > 0.0) && (to < L.occL)) {
-                    add_i64(&lacc[2 * J], -wm);
-                    if (wv) add_i64(&lacc[kMaxP + 2 * J], -wv);
-                    a = 1;
+    // occurrence-term slopes; the events' weights and band flags to LDS
+    {
+        long long over_m = 0, over_v = 0, in_m = 0, in_v = 0;
+        for (int i = t; i < kSparseChunk; i += nt) {
+            const int64_t e = e0 + i;
+            long long wm = 0, wv = 0;
+            uint8_t a = 0;
+            if (e < C) {
+                wm = static_cast<long long>(w_mean[e]);
+                wv = static_cast<long long>(w_tvar[e]);
+                if (wm != 0 || wv != 0) {
+                    const double to = ys[i] - L.occR;
+                    if (to > L.occL) {
+                        over_m += wm;
+                        over_v += wv;
+                    }
+                    if ((to > 0.0) && (to < L.occL)) {
+                        in_m += wm;
+                        in_v += wv;
+                        a = 1;
+                    }
                 }
             }
+            wms[i] = wm;
+            wvs[i] = wv;
+            act[i] = a;
         }
-        act[i] = a;
+        over_m = wave_sum_i64(over_m);
+        over_v = wave_sum_i64(over_v);
+        in_m = wave_sum_i64(in_m);
+        in_v = wave_sum_i64(in_v);
+        if ((t & 63) == 0) {
+            if (over_m) add_i64(&lacc[2 * J + 1], over_m);
+            if (over_v) add_i64(&lacc[kMaxP + 2 * J + 1], over_v);
+            if (in_m) add_i64(&lacc[2 * J], -in_m);
+            if (in_v) add_i64(&lacc[kMaxP + 2 * J], -in_v);
+        }
     }
-    __syncthreads();
-    for (int j = 0; j < J; ++j) {
-        const double R = L.R[j], Lim = L.Lim[j];
-        for (int64_t k = rb[j] + t; k < re[j]; k += blockDim.x) {
-            const int ev = sp.ev[k];
+    // per-ELT slopes of the events inside the occurrence band (the staged
+    // entries are still in LDS when the list fit in one round)
+    for (int64_t r0 = 0; r0 < n_ent; r0 += kStage) {
+        const int nr = static_cast<int>(n_ent - r0 < kStage ? n_ent - r0 : kStage);
+        __syncthreads();
+        if (n_ent > kStage) {
+            stage(r0, nr);
+            __syncthreads();
+        }
+        for (int i = t; i < nr; i += nt) {
+            const int ev = s_ev[i];
             if (!act[ev]) continue;
-            const long long wm = static_cast<long long>(w_mean[e0 + ev]);
-            const long long wv = static_cast<long long>(w_tvar[e0 + ev]);
-            const double tj = sp.val[k] - R;
+            const int j = s_j[i];
+            const long long wm = wms[ev], wv = wvs[ev];
+            const double tj = s_val[i] - sR[j];
+            const double Lim = sLim[j];
             if (tj > 0.0 && tj < Lim) {
                 add_i64(&lacc[j], -wm);
                 if (wv) add_i64(&lacc[kMaxP + j], -wv);
@@ -116,7 +198,7 @@ __global__ __launch_bounds__(256) void catalogue_sparse_kernel(SparsePool sp, in
         }
     }
     __syncthreads();
-    for (int i = t; i < 2 * kMaxP; i += blockDim.x) {
+    for (int i = t; i < 2 * kMaxP; i += nt) {
         const int q = i % kMaxP;
         if (q < P - 2 && lacc[i] != 0) add_i64(&acc[i], lacc[i]);
     }
@@ -366,7 +448,7 @@ hipError_t launch_adjoint(const int64_t* offsets, const uint32_t* ids, const dou
         if ((err = hipGetLastError()) != hipSuccess) return err;
     }
     if (sp && sp->chunk_off && sp->n_chunks == (C + kSparseChunk - 1) / kSparseChunk) {
-        hipLaunchKernelGGL(catalogue_sparse_kernel, dim3(static_cast<uint32_t>(sp->n_chunks)), dim3(256), 0, s, *sp,
+        hipLaunchKernelGGL(catalogue_sparse_kernel, dim3(static_cast<uint32_t>(sp->n_chunks)), dim3(1024), 0, s, *sp,
                            C, L, a.w_mean, a.w_tvar, a.acc);
     } else {
         int64_t gblocks = (C + 255) / 256;
