@@ -282,17 +282,30 @@ __global__ __launch_bounds__(256) void agg_counts_kernel(LayerArgs L, const doub
     const int P = 2 * L.J + 4;
     long long r_mean = 0, l_mean = 0, r_tvar = 0, l_tvar = 0;
     const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
-    for (int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; k < L.trial_count; k += stride) {
-        const double ta = S[k] - L.aggR;
-        const uint64_t key = __double_as_longlong(ylt[k] + 0.0);
-        const long long wt = key > ts.v_bits ? ts.c_eq : (key == ts.v_bits ? ts.m - ts.c_gt : 0);
-        if ((ta > 0.0) && (ta < L.aggL)) {
-            r_mean -= 1;
-            r_tvar -= wt;
+    const int64_t n = L.trial_count;
+    // four trials per thread per round, their loads in flight together
+    constexpr int kU = 4;
+    for (int64_t k0 = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; k0 < n; k0 += kU * stride) {
+        double sv[kU], yv[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int64_t k = k0 + u * stride;
+            sv[u] = k < n ? S[k] : L.aggR;          // a trial past the end: ta = 0, no count
+            yv[u] = k < n ? ylt[k] : 0.0;
         }
-        if (ta > L.aggL) {
-            l_mean += 1;
-            l_tvar += wt;
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const double ta = sv[u] - L.aggR;
+            const uint64_t key = __double_as_longlong(yv[u] + 0.0);
+            const long long wt = key > ts.v_bits ? ts.c_eq : (key == ts.v_bits ? ts.m - ts.c_gt : 0);
+            if ((ta > 0.0) && (ta < L.aggL)) {
+                r_mean -= 1;
+                r_tvar -= wt;
+            }
+            if (ta > L.aggL) {
+                l_mean += 1;
+                l_tvar += wt;
+            }
         }
     }
     for (int off = 32; off >= 1; off >>= 1) {
