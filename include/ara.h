@@ -32,8 +32,12 @@
  *     tables, or by the library per device for the metrics): a call reuses a
  *     buffer last used on its own stream at once, one last used on another
  *     stream once that stream has passed its last use, and otherwise
- *     allocates a new one.  Other scratch, and staging for host arguments,
- *     comes from the device's stream-ordered memory pool.
+ *     allocates a new one.  Other scratch, staging for host arguments and
+ *     the tables' own copies come from the library's device memory cache
+ *     (memory from hipMalloc, kept when freed and handed out again under the
+ *     same stream rule), so steady-state calls neither allocate from nor
+ *     return memory to the runtime.  Destroying tables returns their memory to
+ *     the cache after the last work enqueued on them, without waiting.
  */
 #ifndef ARA_H
 #define ARA_H

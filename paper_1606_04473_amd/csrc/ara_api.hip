@@ -1,5 +1,5 @@
-// C ABI of libara: argument checks, table residency, per-call scratch from
-// the stream-ordered pool, kernel dispatch.  No exception crosses the ABI.
+// C ABI of libara: argument checks, table residency, the library's device
+// memory cache, kernel dispatch.  No exception crosses the ABI.
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -10,9 +10,126 @@
 #include <list>
 #include <new>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "ara_internal.hpp"
+
+// ---------------------------------------------------------------------------
+// Device memory of the library.  Blocks come from hipMalloc in size classes
+// (four per octave, so a block exceeds its request by under 25%) and are kept
+// when freed: a freed block is handed out again at once for work on the
+// stream that freed it (stream order covers the earlier use), and for work on
+// any other stream once an event recorded at the free has completed, which
+// is checked without waiting.  In steady state no call allocates from or
+// returns memory to the runtime, so independent streams never wait on each
+// other inside an allocation.  Idle blocks are released (hipFree) only when
+// hipMalloc runs out of memory.
+namespace ara {
+namespace {
+
+struct CacheBlock {
+    size_t size = 0;
+    hipStream_t stream = nullptr;   // stream of the last free
+    hipEvent_t ready = nullptr;     // recorded on it at that free
+    bool in_use = true;
+};
+
+struct DeviceCache {
+    std::mutex mu;
+    std::unordered_map<void*, CacheBlock> blocks;
+};
+
+DeviceCache& device_cache(int device) {
+    static std::mutex mu;
+    static std::vector<std::pair<int, DeviceCache*>> caches;     // kept until the process ends
+    std::lock_guard<std::mutex> g(mu);
+    for (auto& c : caches)
+        if (c.first == device) return *c.second;
+    caches.emplace_back(device, new DeviceCache());
+    return *caches.back().second;
+}
+
+size_t size_class(size_t bytes) {
+    if (bytes <= 512) return 512;
+    const int k = 63 - __builtin_clzll(static_cast<unsigned long long>(bytes));
+    const size_t base = size_t(1) << k;             // base <= bytes < 2 base
+    const size_t step = base >> 2;
+    return base + (bytes - base + step - 1) / step * step;
+}
+
+// hipFree of the idle blocks whose last free has completed (waits for the device)
+void release_idle(DeviceCache& c) {
+    std::lock_guard<std::mutex> g(c.mu);
+    for (auto it = c.blocks.begin(); it != c.blocks.end();) {
+        CacheBlock& b = it->second;
+        if (!b.in_use && (!b.ready || hipEventQuery(b.ready) == hipSuccess)) {
+            if (b.ready) (void)hipEventDestroy(b.ready);
+            (void)hipFree(it->first);
+            it = c.blocks.erase(it);
+        } else {
+            ++it;
+        }
+    }
+}
+
+}  // namespace
+
+hipError_t dev_alloc(void** p, size_t bytes, hipStream_t s) {
+    *p = nullptr;
+    int device = 0;
+    hipError_t e = hipGetDevice(&device);
+    if (e != hipSuccess) return e;
+    DeviceCache& c = device_cache(device);
+    const size_t cls = size_class(bytes);
+    {
+        std::lock_guard<std::mutex> g(c.mu);
+        for (auto& kv : c.blocks) {
+            CacheBlock& b = kv.second;
+            if (b.in_use || b.size != cls) continue;
+            if (b.stream != s && b.ready && hipEventQuery(b.ready) != hipSuccess) continue;
+            b.in_use = true;
+            *p = kv.first;
+            return hipSuccess;
+        }
+    }
+    void* q = nullptr;
+    e = hipMalloc(&q, cls);
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) {
+        (void)hipGetLastError();
+        release_idle(c);
+        e = hipMalloc(&q, cls);
+    }
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> g(c.mu);
+    CacheBlock b;
+    b.size = cls;
+    b.stream = s;
+    c.blocks.emplace(q, b);
+    *p = q;
+    return hipSuccess;
+}
+
+void dev_free(void* p, hipStream_t s) {
+    if (!p) return;
+    int device = 0;
+    if (hipGetDevice(&device) != hipSuccess) return;
+    DeviceCache& c = device_cache(device);
+    std::lock_guard<std::mutex> g(c.mu);
+    auto it = c.blocks.find(p);
+    if (it == c.blocks.end()) return;
+    CacheBlock& b = it->second;
+    if (!b.ready && hipEventCreateWithFlags(&b.ready, hipEventDisableTiming) != hipSuccess) b.ready = nullptr;
+    if (b.ready && hipEventRecord(b.ready, s) != hipSuccess) {
+        // without an event the block can only go back to work on s
+        (void)hipEventDestroy(b.ready);
+        b.ready = nullptr;
+    }
+    b.stream = s;
+    b.in_use = false;
+}
+
+}  // namespace ara
 
 namespace {
 
@@ -59,12 +176,12 @@ struct PoolBuffer {
     void* p = nullptr;
     hipStream_t s = nullptr;
     ~PoolBuffer() {
-        if (p) (void)hipFreeAsync(p, s);
+        if (p) ara::dev_free(p, s);
     }
     hipError_t alloc(size_t bytes, hipStream_t stream) {
         s = stream;
         if (bytes == 0) bytes = 256;
-        return hipMallocAsync(&p, bytes, stream);
+        return ara::dev_alloc(&p, bytes, stream);
     }
 };
 
@@ -92,13 +209,13 @@ hipError_t scratch_acquire(std::mutex& mu, std::vector<ara::ScratchBuffer*>& set
     if (!pick->done) e = hipEventCreateWithFlags(&pick->done, hipEventDisableTiming);
     if (e == hipSuccess && pick->cap < bytes) {
         // growing: the old memory may still be read by work on its last
-        // stream, so it goes back to the stream-ordered pool in that stream's
-        // order; the new memory is taken in this call's stream order
-        if (pick->p) e = hipFreeAsync(pick->p, pick->stream);
+        // stream, so it goes back to the cache in that stream's order; the new
+        // memory is taken in this call's stream order
+        if (pick->p) ara::dev_free(pick->p, pick->stream);
         pick->p = nullptr;
         pick->cap = 0;
         pick->primed = false;
-        if (e == hipSuccess) e = hipMallocAsync(&pick->p, bytes, s);
+        if (e == hipSuccess) e = ara::dev_alloc(&pick->p, bytes, s);
         if (e == hipSuccess) pick->cap = bytes;
     }
     if (e != hipSuccess) {
@@ -122,7 +239,7 @@ void scratch_release(std::mutex& mu, ara::ScratchBuffer* b, hipStream_t s) {
 void scratch_free_all(std::vector<ara::ScratchBuffer*>& sets, hipStream_t fs) {
     for (auto* b : sets) {
         if (b->done) (void)hipStreamWaitEvent(fs, b->done, 0);
-        if (b->p) (void)hipFreeAsync(b->p, fs);
+        if (b->p) ara::dev_free(b->p, fs);
         if (b->done) (void)hipEventDestroy(b->done);
         delete b;
     }
@@ -179,20 +296,6 @@ struct ScratchLease {
     ScratchLease(std::mutex& m) : mu(m) {}
     ~ScratchLease() { scratch_release(mu, b, s); }
 };
-
-void keep_pool_memory(int device) {
-    static std::mutex mu;
-    static std::vector<int> done;
-    std::lock_guard<std::mutex> g(mu);
-    for (int d : done)
-        if (d == device) return;
-    hipMemPool_t pool;
-    if (hipDeviceGetDefaultMemPool(&pool, device) == hipSuccess) {
-        uint64_t thr = UINT64_MAX;
-        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
-    }
-    done.push_back(device);
-}
 
 bool bad_term(double v) { return std::isnan(v) || v < 0.0; }
 
@@ -536,7 +639,6 @@ static ara_status create_impl(const int64_t* trial_offsets, int64_t n_trials, co
     } else {
         HIP_TRY(hipGetDevice(&device), "hipGetDevice");
     }
-    keep_pool_memory(device);
     ara_tables* t = new (std::nothrow) ara_tables();
     if (!t) return fail(ARA_ERR_NO_MEMORY, "host allocation failed");
     t->device = device;
@@ -561,9 +663,9 @@ static ara_status create_impl(const int64_t* trial_offsets, int64_t n_trials, co
         t->tuning = base->tuning;
     }
     hipError_t e;
-    if ((e = hipMallocAsync(reinterpret_cast<void**>(&t->offsets), off_bytes, s)) != hipSuccess)
+    if ((e = ara::dev_alloc(reinterpret_cast<void**>(&t->offsets), off_bytes, s)) != hipSuccess)
         return cleanup(hip_fail(e, "allocate offsets"));
-    if ((e = hipMallocAsync(reinterpret_cast<void**>(&t->ids), id_bytes, s)) != hipSuccess)
+    if ((e = ara::dev_alloc(reinterpret_cast<void**>(&t->ids), id_bytes, s)) != hipSuccess)
         return cleanup(hip_fail(e, "allocate event ids"));
     if (elt_bytes && (e = hipMalloc(&t->elts, elt_bytes)) != hipSuccess)
         return cleanup(hip_fail(e, "hipMalloc ELT pool"));
@@ -632,10 +734,11 @@ static ara_status create_impl(const int64_t* trial_offsets, int64_t n_trials, co
 void ara_destroy_tables(ara_tables* t) {
     if (!t) return;
     DeviceScope ds(t->device);
-    // The YET, its layouts and the kept scratch come from the stream-ordered
-    // pool: they go back on an internal stream once every stream the tables
-    // were used on has reached the end of its last call's work, and the host
-    // does not wait (a hipFree would wait for the whole device)
+    // The YET, its layouts and the kept scratch come from the library's
+    // device memory cache: they go back to it on an internal stream once every
+    // stream the tables were used on has reached the end of its last call's
+    // work, and the host does not wait (a hipFree would wait for the whole
+    // device)
     hipStream_t fs = free_stream(t->device);
     {
         std::lock_guard<std::mutex> g(t->fence_mu);
@@ -645,8 +748,8 @@ void ara_destroy_tables(ara_tables* t) {
         }
         t->fences.clear();
     }
-    if (t->offsets) (void)hipFreeAsync(t->offsets, fs);
-    if (t->ids) (void)hipFreeAsync(t->ids, fs);
+    if (t->offsets) ara::dev_free(t->offsets, fs);
+    if (t->ids) ara::dev_free(t->ids, fs);
     scratch_free_all(t->scratch, fs);
     ara::free_part_layout(&t->parts, fs);
     ara::free_stream_layout(&t->stream, fs);
@@ -1255,7 +1358,6 @@ ara_status ara_risk_metrics(const double* ylt, int64_t n_trials, const double* p
     hipStream_t s = static_cast<hipStream_t>(stream);
     int device = 0;
     HIP_TRY(hipGetDevice(&device), "hipGetDevice");
-    keep_pool_memory(device);
     const int n_cu = query_cu_count(device);
     const bool dev = (flags & ARA_DEVICE_PTR) != 0;
     PoolBuffer staged_in, results;

@@ -15,6 +15,13 @@
 namespace ara {
 
 constexpr int kWave = 64;
+
+// The library's device memory (ara_api.hip): dev_alloc takes a block for work
+// on stream s; dev_free gives it back after the work enqueued on s so far.  A
+// block freed on s serves later work on s at once and work on other streams
+// once s has reached the free.  Blocks are kept, not returned to the runtime.
+hipError_t dev_alloc(void** p, size_t bytes, hipStream_t s);
+void dev_free(void* p, hipStream_t s);
 constexpr int kMaxJ = ARA_MAX_LAYER_ELTS;
 constexpr int kStride = ARA_CHECKPOINT_EVERY;
 // The event-ID array is padded with zero IDs so that aligned 16-byte loads
@@ -176,7 +183,7 @@ struct StreamLayout {
 };
 hipError_t build_stream_layout(const int64_t* offsets, const uint32_t* ids, int64_t N, int64_t n_events, int64_t C,
                                int n_cu, hipStream_t s, StreamLayout* out);
-// frees in stream order on s (the layout's memory comes from the stream-ordered pool)
+// frees in stream order on s (the layout's memory comes from dev_alloc)
 void free_stream_layout(StreamLayout* L, hipStream_t s);
 // bytes of the per-(part, trial) partial sums of the streaming pass
 int64_t stream_partials_bytes(const StreamLayout& lay, int64_t trials);
@@ -370,8 +377,8 @@ struct ara_tables {
     std::mutex scratch_mu;        // guards scratch
     std::vector<ara::ScratchBuffer*> scratch;
     // one event per stream the tables were used on, recorded after each call's
-    // work: destroying the tables frees their stream-ordered memory after all of
-    // them, without waiting on the host
+    // work: destroying the tables returns their memory to the cache after all
+    // of them, without waiting on the host
     std::mutex fence_mu;
     std::vector<std::pair<hipStream_t, hipEvent_t>> fences;
 };
@@ -431,7 +438,7 @@ hipError_t launch_debug_lookups(const int64_t* offsets, const uint32_t* ids, con
 // catalogue-partitioned path
 hipError_t build_part_layout(const int64_t* offsets, const uint32_t* ids, int64_t N, int64_t n_events, int64_t C,
                              int n_cu, hipStream_t s, PartLayout* out);
-// frees in stream order on s (the layout's memory comes from the stream-ordered pool)
+// frees in stream order on s (the layout's memory comes from dev_alloc)
 void free_part_layout(PartLayout* L, hipStream_t s);
 int64_t part_scratch_bytes(int64_t C, int P);
 int part_count(int64_t C);   // catalogue parts of the part images

@@ -1400,12 +1400,12 @@ hipError_t build_part_layout(const int64_t* offsets, const uint32_t* ids, int64_
     hipError_t e;
     int32_t* cnt = nullptr;
     int64_t* tsize = nullptr;
-    if ((e = hipMallocAsync(reinterpret_cast<void**>(&cnt), sizeof(int32_t) * N * P, s)) != hipSuccess) return e;
-    if ((e = hipMallocAsync(reinterpret_cast<void**>(&out->seg_rel),
+    if ((e = dev_alloc(reinterpret_cast<void**>(&cnt), sizeof(int32_t) * N * P, s)) != hipSuccess) return e;
+    if ((e = dev_alloc(reinterpret_cast<void**>(&out->seg_rel),
                             sizeof(uint32_t) * (n_tiles * (static_cast<int64_t>(T) * P + 1)), s)) != hipSuccess)
         goto fail;
-    if ((e = hipMallocAsync(reinterpret_cast<void**>(&tsize), sizeof(int64_t) * n_tiles, s)) != hipSuccess) goto fail;
-    if ((e = hipMallocAsync(reinterpret_cast<void**>(&out->tile_start), sizeof(int64_t) * (n_tiles + 1), s)) !=
+    if ((e = dev_alloc(reinterpret_cast<void**>(&tsize), sizeof(int64_t) * n_tiles, s)) != hipSuccess) goto fail;
+    if ((e = dev_alloc(reinterpret_cast<void**>(&out->tile_start), sizeof(int64_t) * (n_tiles + 1), s)) !=
         hipSuccess)
         goto fail;
     {
@@ -1424,10 +1424,10 @@ hipError_t build_part_layout(const int64_t* offsets, const uint32_t* ids, int64_
         st[0] = 0;
         for (int64_t k = 0; k < n_tiles; ++k) {
             if (h[k] >= (int64_t(1) << 31)) {   // too large for 32-bit positions: keep the plain layout
-                (void)hipFreeAsync(cnt, s);
-                (void)hipFreeAsync(tsize, s);
-                (void)hipFreeAsync(out->seg_rel, s);
-                (void)hipFreeAsync(out->tile_start, s);
+                dev_free(cnt, s);
+                dev_free(tsize, s);
+                dev_free(out->seg_rel, s);
+                dev_free(out->tile_start, s);
                 (void)hipStreamSynchronize(s);
                 *out = PartLayout{};
                 return hipSuccess;
@@ -1438,7 +1438,7 @@ hipError_t build_part_layout(const int64_t* offsets, const uint32_t* ids, int64_
         if ((e = hipMemcpyAsync(out->tile_start, st.data(), sizeof(int64_t) * (n_tiles + 1), hipMemcpyHostToDevice,
                                 s)) != hipSuccess)
             goto fail;
-        if ((e = hipMallocAsync(reinterpret_cast<void**>(&out->pids), sizeof(uint32_t) * (total + kIdPad), s)) !=
+        if ((e = dev_alloc(reinterpret_cast<void**>(&out->pids), sizeof(uint32_t) * (total + kIdPad), s)) !=
             hipSuccess)
             goto fail;
         int64_t fb = (total + kIdPad + 255) / 256;
@@ -1458,22 +1458,22 @@ hipError_t build_part_layout(const int64_t* offsets, const uint32_t* ids, int64_
         out->bytes = sizeof(uint32_t) * (total + kIdPad) + sizeof(uint32_t) * (n_tiles * (int64_t(T) * P + 1)) +
                      sizeof(int64_t) * (n_tiles + 1);
     }
-    // temporaries go back to the stream-ordered pool: no free waits for the device
-    (void)hipFreeAsync(cnt, s);
-    (void)hipFreeAsync(tsize, s);
+    // temporaries go back to the library's device memory cache: no free waits for the device
+    dev_free(cnt, s);
+    dev_free(tsize, s);
     return hipSuccess;
 fail:
-    if (cnt) (void)hipFreeAsync(cnt, s);
-    if (tsize) (void)hipFreeAsync(tsize, s);
+    if (cnt) dev_free(cnt, s);
+    if (tsize) dev_free(tsize, s);
     free_part_layout(out, s);
     (void)hipStreamSynchronize(s);
     return e;
 }
 
 void free_part_layout(PartLayout* L, hipStream_t s) {
-    if (L->pids) (void)hipFreeAsync(L->pids, s);
-    if (L->seg_rel) (void)hipFreeAsync(L->seg_rel, s);
-    if (L->tile_start) (void)hipFreeAsync(L->tile_start, s);
+    if (L->pids) dev_free(L->pids, s);
+    if (L->seg_rel) dev_free(L->seg_rel, s);
+    if (L->tile_start) dev_free(L->tile_start, s);
     *L = PartLayout{};
 }
 

@@ -824,16 +824,16 @@ hipError_t build_stream_layout(const int64_t* offsets, const uint32_t* ids, int6
     uint32_t h_flag = 0;
     int64_t blocks = (N + 3) / 4;
     if (blocks > int64_t(n_cu) * 16) blocks = int64_t(n_cu) * 16;
-    if ((e = hipMallocAsync(reinterpret_cast<void**>(&cnt), sizeof(int32_t) * N * P, s)) != hipSuccess) goto fail;
-    if ((e = hipMallocAsync(reinterpret_cast<void**>(&gsize), sizeof(uint32_t) * n_grp, s)) != hipSuccess) goto fail;
-    if ((e = hipMallocAsync(reinterpret_cast<void**>(&plen), sizeof(uint64_t) * P, s)) != hipSuccess) goto fail;
-    if ((e = hipMallocAsync(reinterpret_cast<void**>(&flag), sizeof(uint32_t), s)) != hipSuccess) goto fail;
-    if ((e = hipMallocAsync(reinterpret_cast<void**>(&out->gend), sizeof(uint16_t) * n_grp * kStreamGroupSlots, s)) !=
+    if ((e = dev_alloc(reinterpret_cast<void**>(&cnt), sizeof(int32_t) * N * P, s)) != hipSuccess) goto fail;
+    if ((e = dev_alloc(reinterpret_cast<void**>(&gsize), sizeof(uint32_t) * n_grp, s)) != hipSuccess) goto fail;
+    if ((e = dev_alloc(reinterpret_cast<void**>(&plen), sizeof(uint64_t) * P, s)) != hipSuccess) goto fail;
+    if ((e = dev_alloc(reinterpret_cast<void**>(&flag), sizeof(uint32_t), s)) != hipSuccess) goto fail;
+    if ((e = dev_alloc(reinterpret_cast<void**>(&out->gend), sizeof(uint16_t) * n_grp * kStreamGroupSlots, s)) !=
         hipSuccess)
         goto fail;
-    if ((e = hipMallocAsync(reinterpret_cast<void**>(&out->gstart), sizeof(uint32_t) * P * (NG + 1), s)) != hipSuccess)
+    if ((e = dev_alloc(reinterpret_cast<void**>(&out->gstart), sizeof(uint32_t) * P * (NG + 1), s)) != hipSuccess)
         goto fail;
-    if ((e = hipMallocAsync(reinterpret_cast<void**>(&out->part_base), sizeof(int64_t) * (P + 1), s)) != hipSuccess)
+    if ((e = dev_alloc(reinterpret_cast<void**>(&out->part_base), sizeof(int64_t) * (P + 1), s)) != hipSuccess)
         goto fail;
     if ((e = hipMemsetAsync(flag, 0, sizeof(uint32_t), s)) != hipSuccess) goto fail;
     hipLaunchKernelGGL(stream_count_kernel, dim3(static_cast<uint32_t>(blocks)), dim3(256), 0, s, offsets, ids, N, P,
@@ -859,7 +859,7 @@ hipError_t build_stream_layout(const int64_t* offsets, const uint32_t* ids, int6
     if ((e = hipMemcpyAsync(out->part_base, h_base.data(), sizeof(int64_t) * (P + 1), hipMemcpyHostToDevice, s)) !=
         hipSuccess)
         goto fail;
-    if ((e = hipMallocAsync(reinterpret_cast<void**>(&out->ids), sizeof(uint16_t) * (out->length + kStreamPad), s)) !=
+    if ((e = dev_alloc(reinterpret_cast<void**>(&out->ids), sizeof(uint16_t) * (out->length + kStreamPad), s)) !=
         hipSuccess)
         goto fail;
     {
@@ -873,11 +873,11 @@ hipError_t build_stream_layout(const int64_t* offsets, const uint32_t* ids, int6
     hipLaunchKernelGGL(stream_scatter_kernel, dim3(static_cast<uint32_t>(blocks)), dim3(256), 0, s, offsets, ids, N, P,
                        G, NG, out->part_base, out->gstart, out->gend, out->ids);
     if ((e = hipGetLastError()) != hipSuccess) goto fail;
-    // temporaries go back to the stream-ordered pool: no free waits for the device
-    (void)hipFreeAsync(cnt, s);
-    (void)hipFreeAsync(gsize, s);
-    (void)hipFreeAsync(plen, s);
-    (void)hipFreeAsync(flag, s);
+    // temporaries go back to the library's device memory cache: no free waits for the device
+    dev_free(cnt, s);
+    dev_free(gsize, s);
+    dev_free(plen, s);
+    dev_free(flag, s);
     if ((e = hipStreamSynchronize(s)) != hipSuccess) {
         free_stream_layout(out, s);
         return e;
@@ -890,20 +890,20 @@ hipError_t build_stream_layout(const int64_t* offsets, const uint32_t* ids, int6
                  static_cast<int64_t>(sizeof(uint32_t)) * P * (NG + 1) + static_cast<int64_t>(sizeof(int64_t)) * (P + 1);
     return hipSuccess;
 fail:
-    if (cnt) (void)hipFreeAsync(cnt, s);
-    if (gsize) (void)hipFreeAsync(gsize, s);
-    if (plen) (void)hipFreeAsync(plen, s);
-    if (flag) (void)hipFreeAsync(flag, s);
+    if (cnt) dev_free(cnt, s);
+    if (gsize) dev_free(gsize, s);
+    if (plen) dev_free(plen, s);
+    if (flag) dev_free(flag, s);
     free_stream_layout(out, s);
     (void)hipStreamSynchronize(s);
     return e;
 }
 
 void free_stream_layout(StreamLayout* L, hipStream_t s) {
-    if (L->ids) (void)hipFreeAsync(L->ids, s);
-    if (L->part_base) (void)hipFreeAsync(L->part_base, s);
-    if (L->gstart) (void)hipFreeAsync(L->gstart, s);
-    if (L->gend) (void)hipFreeAsync(L->gend, s);
+    if (L->ids) dev_free(L->ids, s);
+    if (L->part_base) dev_free(L->part_base, s);
+    if (L->gstart) dev_free(L->gstart, s);
+    if (L->gend) dev_free(L->gend, s);
     *L = StreamLayout{};
 }
 

@@ -34,6 +34,30 @@ import numpy as np
 
 MODES = ("concurrent", "sequential", "resident")
 
+# Device staging for shipped slices, one (IDs, offsets) pair per (device, slot),
+# sized for the whole YET and kept for the process: servers made one after the
+# other reuse them.  Allocating a slice buffer per request would leave blocks
+# of every size cached under each slot's stream by torch's allocator; once
+# those caches fill the device, an allocation makes the allocator free them,
+# and each free waits for the whole device (other slots' copies included).
+_SLICE_BUFFERS: Dict[tuple, tuple] = {}
+
+
+def slice_buffers(device, slot: int, n_ids: int, n_off: int):
+    """Slot `slot`'s device staging on `device`: an int32 tensor of at least
+    n_ids IDs and an int64 tensor of at least n_off offsets, allocated on first
+    use (or when too small) and then reused."""
+    import torch
+    key = (device.index, slot)
+    bufs = _SLICE_BUFFERS.get(key)
+    if bufs is None or bufs[0].numel() < n_ids or bufs[1].numel() < n_off:
+        _SLICE_BUFFERS.pop(key, None)
+        torch.cuda.synchronize(device)
+        bufs = (torch.empty(max(n_ids, 1), dtype=torch.int32, device=device),
+                torch.empty(max(n_off, 1), dtype=torch.int64, device=device))
+        _SLICE_BUFFERS[key] = bufs
+    return bufs
+
 
 # ---------------------------------------------------------------------------
 # admission by device memory (no GPU needed)
@@ -198,7 +222,10 @@ class Server:
     from the library's own counts), then ships its YET slice (or uses the
     resident YET), runs its layers and metrics, and frees its memory.
     Requests that arrive while others run are admitted as slots and memory
-    free up, and their work overlaps on the device.
+    free up, and their work overlaps on the device.  A shipped slice lands in
+    the slot's device staging (kept for the process and reused, see
+    _SLICE_BUFFERS), from which the library copies it into the request's
+    tables; the footprint still counts the slice.
     """
 
     def __init__(self, base, offsets: np.ndarray, ids: np.ndarray, library, n_slots: int,
@@ -226,6 +253,14 @@ class Server:
         self.host_ids = pinned_ids
         if mode != "resident" and self.host_ids is None:
             self.host_ids = pin_ids(ids)
+        if mode != "resident":
+            for k in range(n_slots):
+                self._slice_buffers(k)
+
+    def _slice_buffers(self, slot: int):
+        """The slot's device staging for a shipped slice, sized for the whole
+        YET (see _SLICE_BUFFERS)."""
+        return slice_buffers(self.device, slot, int(self.offsets[-1]), int(self.offsets.shape[0]))
 
     def footprint(self, req: Request) -> int:
         """Device bytes the request holds at its peak, from the library's counts:
@@ -280,8 +315,9 @@ class Server:
                     hi = int(self.offsets[req.trial_begin + req.n_trials])
                     off = torch.from_numpy(self.offsets[req.trial_begin:req.trial_begin + req.n_trials + 1] - lo)
                     off = off.pin_memory()
-                    d_ids = torch.empty(hi - lo, dtype=torch.int32, device=self.device)
-                    d_off = torch.empty(req.n_trials + 1, dtype=torch.int64, device=self.device)
+                    ids_buf, off_buf = self._slice_buffers(slot)
+                    d_ids = ids_buf[:hi - lo]
+                    d_off = off_buf[:req.n_trials + 1]
                     tp = time.perf_counter()
                     if self.mode == "sequential":
                         with self.transfer_token:
@@ -531,11 +567,12 @@ def split_study(base, offsets, pinned_ids, library, layer_ids: Sequence[int], te
                                      s.agg_retention, s.agg_limit, begin, count))
         return out
 
-    def ship(lo_t: int, cnt: int, stream):
+    def ship(lo_t: int, cnt: int, stream, slot: int = 0):
         lo, hi = int(offsets[lo_t]), int(offsets[lo_t + cnt])
         off = torch.from_numpy(offsets[lo_t:lo_t + cnt + 1] - lo).pin_memory()
-        d_ids = torch.empty(hi - lo, dtype=torch.int32, device=dev)
-        d_off = torch.empty(cnt + 1, dtype=torch.int64, device=dev)
+        ids_buf, off_buf = slice_buffers(dev, slot, int(offsets[-1]), n + 1)
+        d_ids = ids_buf[:hi - lo]
+        d_off = off_buf[:cnt + 1]
         d_ids.copy_(pinned_ids[lo:hi], non_blocking=True)
         d_off.copy_(off, non_blocking=True)
         return d_off, d_ids
@@ -607,10 +644,10 @@ def split_study(base, offsets, pinned_ids, library, layer_ids: Sequence[int], te
                 with torch.cuda.stream(s):
                     if mode == "sequential":
                         with token:
-                            d_off, d_ids = ship(b, c, s)
+                            d_off, d_ids = ship(b, c, s, k)
                             s.synchronize()
                     else:
-                        d_off, d_ids = ship(b, c, s)
+                        d_off, d_ids = ship(b, c, s, k)
                     tab = ara.create_yet(base, d_off, d_ids, stream=s)
                     del d_off, d_ids
                     compute(tab, 0, c, s)
