@@ -326,6 +326,22 @@ const char* ara_status_string(ara_status status);
 /* Device bytes held by the tables (YET, offsets, ELT pool). */
 ara_status ara_table_bytes(const ara_tables* tables, int64_t* bytes);
 
+/*
+ * The library's device memory cache on the current device (see the
+ * threading notes at the top): memory freed by tables and calls stays cached
+ * for reuse instead of going back to the runtime.
+ *
+ * ara_cached_memory -- bytes the cache holds in total, and of those the
+ *   bytes no tables or call is using (idle).  Either pointer may be NULL.
+ * ara_release_cached_memory -- returns to the runtime (hipFree, which waits
+ *   for the device) every idle block whose last use has completed, for
+ *   callers that need the memory elsewhere; reports the bytes released
+ *   (NULL: not reported).  Blocks in use, or whose last use is still running,
+ *   stay cached.  Later calls allocate again as needed.
+ */
+ara_status ara_cached_memory(int64_t* held_bytes, int64_t* idle_bytes);
+ara_status ara_release_cached_memory(int64_t* bytes_released);
+
 /* Peak device scratch bytes ara_run_layers(tables, layers, n_layers, ..,
    flags) allocates beyond the tables and the output; for admission control. */
 ara_status ara_footprint(const ara_tables* tables, const ara_layer* layers, int32_t n_layers,

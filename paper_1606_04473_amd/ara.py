@@ -161,6 +161,10 @@ def lib():
     L.ara_status_string.restype = ctypes.c_char_p
     L.ara_table_bytes.argtypes = [P, ctypes.POINTER(i64)]
     L.ara_table_bytes.restype = i32
+    L.ara_cached_memory.argtypes = [ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    L.ara_cached_memory.restype = i32
+    L.ara_release_cached_memory.argtypes = [ctypes.POINTER(i64)]
+    L.ara_release_cached_memory.restype = i32
     L.ara_footprint.argtypes = [P, ctypes.POINTER(CLayer), i32, u32, ctypes.POINTER(i64)]
     L.ara_footprint.restype = i32
     L.ara_debug_lookups.argtypes = [P, ctypes.POINTER(CLayer), i64, P, P, i64, ctypes.POINTER(i64), P]
@@ -633,6 +637,20 @@ def tail_count(n_trials: int, p: float) -> int:
     m = ctypes.c_int64()
     _check(lib().ara_tail_count(int(n_trials), float(p), ctypes.byref(m)))
     return int(m.value)
+
+
+def cached_memory():
+    """ara_cached_memory on the current device: (held_bytes, idle_bytes)."""
+    held, idle = ctypes.c_int64(), ctypes.c_int64()
+    _check(lib().ara_cached_memory(ctypes.byref(held), ctypes.byref(idle)))
+    return held.value, idle.value
+
+
+def release_cached_memory() -> int:
+    """ara_release_cached_memory on the current device: bytes released."""
+    freed = ctypes.c_int64()
+    _check(lib().ara_release_cached_memory(ctypes.byref(freed)))
+    return freed.value
 
 
 def status_string(status: int) -> str:

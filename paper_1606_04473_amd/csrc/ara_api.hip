@@ -58,22 +58,40 @@ size_t size_class(size_t bytes) {
     return base + (bytes - base + step - 1) / step * step;
 }
 
-// hipFree of the idle blocks whose last free has completed (waits for the device)
-void release_idle(DeviceCache& c) {
+// hipFree of the idle blocks whose last free has completed (waits for the
+// device); returns the bytes released
+int64_t release_idle(DeviceCache& c) {
     std::lock_guard<std::mutex> g(c.mu);
+    int64_t freed = 0;
     for (auto it = c.blocks.begin(); it != c.blocks.end();) {
         CacheBlock& b = it->second;
         if (!b.in_use && (!b.ready || hipEventQuery(b.ready) == hipSuccess)) {
             if (b.ready) (void)hipEventDestroy(b.ready);
             (void)hipFree(it->first);
+            freed += static_cast<int64_t>(b.size);
             it = c.blocks.erase(it);
         } else {
             ++it;
         }
     }
+    return freed;
 }
 
 }  // namespace
+
+void cache_stats(int device, int64_t* held, int64_t* idle) {
+    DeviceCache& c = device_cache(device);
+    std::lock_guard<std::mutex> g(c.mu);
+    int64_t h = 0, i = 0;
+    for (auto& kv : c.blocks) {
+        h += static_cast<int64_t>(kv.second.size);
+        if (!kv.second.in_use) i += static_cast<int64_t>(kv.second.size);
+    }
+    *held = h;
+    *idle = i;
+}
+
+int64_t cache_release(int device) { return release_idle(device_cache(device)); }
 
 hipError_t dev_alloc(void** p, size_t bytes, hipStream_t s) {
     *p = nullptr;
@@ -770,6 +788,24 @@ void ara_destroy_tables(ara_tables* t) {
 ara_status ara_table_bytes(const ara_tables* t, int64_t* bytes) {
     if (!t || !bytes) return fail(ARA_ERR_INVALID_ARG, "NULL argument");
     *bytes = t->bytes;
+    return ARA_OK;
+}
+
+ara_status ara_cached_memory(int64_t* held_bytes, int64_t* idle_bytes) {
+    int device = 0;
+    HIP_TRY(hipGetDevice(&device), "hipGetDevice");
+    int64_t held = 0, idle = 0;
+    ara::cache_stats(device, &held, &idle);
+    if (held_bytes) *held_bytes = held;
+    if (idle_bytes) *idle_bytes = idle;
+    return ARA_OK;
+}
+
+ara_status ara_release_cached_memory(int64_t* bytes_released) {
+    int device = 0;
+    HIP_TRY(hipGetDevice(&device), "hipGetDevice");
+    const int64_t freed = ara::cache_release(device);
+    if (bytes_released) *bytes_released = freed;
     return ARA_OK;
 }
 

@@ -22,6 +22,10 @@ constexpr int kWave = 64;
 // once s has reached the free.  Blocks are kept, not returned to the runtime.
 hipError_t dev_alloc(void** p, size_t bytes, hipStream_t s);
 void dev_free(void* p, hipStream_t s);
+// bytes the cache of `device` holds, and of those not in use
+void cache_stats(int device, int64_t* held, int64_t* idle);
+// hipFree of the idle blocks of `device` whose last use has completed
+int64_t cache_release(int device);
 constexpr int kMaxJ = ARA_MAX_LAYER_ELTS;
 constexpr int kStride = ARA_CHECKPOINT_EVERY;
 // The event-ID array is padded with zero IDs so that aligned 16-byte loads

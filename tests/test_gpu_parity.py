@@ -345,6 +345,31 @@ def test_concurrent_streams_same_results(ara, cfg0):
         assert np.array_equal(o.cpu().numpy(), base)
 
 
+def test_device_memory_cache_release(ara):
+    """Freed device memory stays in the library's cache for reuse; releasing
+    hands every idle block back to the runtime, the counts add up, and tables
+    built afterwards (allocating afresh) give the same year losses."""
+    import torch
+    w = make_config("config0")
+    spec = _spec(ara, w.layers[0], w.pool, w.yet)
+
+    def run():
+        t = ara.create_tables(w.yet.offsets, w.yet.ids, w.pool.losses)
+        y = ara.run_layers(t, [spec])
+        t.close()
+        return y
+
+    y0 = run()
+    torch.cuda.synchronize()
+    held, idle = ara.cached_memory()
+    assert held >= idle > 0
+    freed = ara.release_cached_memory()
+    held2, idle2 = ara.cached_memory()
+    assert freed == idle and idle2 == 0 and held2 == held - freed
+    y1 = run()
+    assert np.array_equal(y0, y1)
+
+
 def test_destroy_with_work_in_flight(ara):
     """Tables destroyed right after calls on two side streams, with no
     synchronisation, then new tables of the same size built and run on a third
