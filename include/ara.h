@@ -269,6 +269,29 @@ ara_status ara_risk_metrics(const double* ylt, int64_t n_trials, const double* p
                             double* tvar_out, uint32_t flags, void* stream);
 
 /*
+ * ara_analyze -- one layer's year losses and its risk metrics in one call:
+ * the results of ara_run_layers(tables, layer, 1, ylt, ...) followed by
+ * ara_risk_metrics over those year losses, bit for bit (the same kernels).
+ *
+ *   layer       as ara_run_layers (one layer, trial_count >= 1).
+ *   probs       host float64[n_probs], each in (0, 1); n_probs <= 4.
+ *   ylt         float64[trial_count] (ylt_capacity values at least).
+ *   metrics     float64[1 + 2 * n_probs]: the mean, then PML_p for each p,
+ *               then TVaR_p for each p.
+ *   flags       ARA_DEVICE_PTR (ylt and metrics are device memory),
+ *               ARA_GRAPH (with ARA_DEVICE_PTR and a non-null stream: the
+ *               fold, the pass, the combine and the metrics kernels are
+ *               captured as one HIP graph per output addresses, trial range
+ *               and tail counts, with scratch of its own, and replayed; new
+ *               terms and ELT choices reuse it), ARA_PROFILE.
+ *
+ * Errors as ara_run_layers and ara_risk_metrics; ARA_ERR_INVALID_ARG for
+ * other flags.  Asynchronous on `stream` with device outputs.
+ */
+ara_status ara_analyze(ara_tables* tables, const ara_layer* layer, const double* probs, int32_t n_probs,
+                       double* ylt, int64_t ylt_capacity, double* metrics, uint32_t flags, void* stream);
+
+/*
  * ara_risk_metrics_noalloc -- for callers that cannot allocate device memory
  * (code under HIP graph capture, tight serving loops, harnesses that forbid
  * hipMalloc).  The same results as ara_risk_metrics with ARA_DEVICE_PTR, from

@@ -161,6 +161,8 @@ def lib():
     L.ara_status_string.restype = ctypes.c_char_p
     L.ara_table_bytes.argtypes = [P, ctypes.POINTER(i64)]
     L.ara_table_bytes.restype = i32
+    L.ara_analyze.argtypes = [P, ctypes.POINTER(CLayer), P, i32, P, i64, P, u32, P]
+    L.ara_analyze.restype = i32
     L.ara_cached_memory.argtypes = [ctypes.POINTER(i64), ctypes.POINTER(i64)]
     L.ara_cached_memory.restype = i32
     L.ara_release_cached_memory.argtypes = [ctypes.POINTER(i64)]
@@ -545,6 +547,31 @@ def run_portfolio(tables: Tables, programs: Sequence[Sequence[LayerSpec]], n_spl
     _check(lib().ara_run_portfolio(tables.handle, progs, len(programs), int(n_splits), ctypes.byref(c), f,
                                    _stream(stream)))
     return outs
+
+
+def analyze(tables: Tables, layer: LayerSpec, probs, ylt=None, metrics=None, flags: int = 0, stream=None):
+    """ara_analyze: the layer's year losses and [mean, PML_p..., TVaR_p...].
+    With CUDA tensors for `ylt` and `metrics` the call is asynchronous on
+    `stream` (ARA_GRAPH replays one graph); otherwise NumPy arrays are
+    returned.  Returns (ylt, metrics)."""
+    arr, keep = _c_layers([layer])
+    p = np.ascontiguousarray(probs, dtype=np.float64)
+    k = int(p.shape[0])
+    if ylt is None:
+        ylt = np.empty(layer.trial_count, dtype=np.float64)
+    if metrics is None:
+        metrics = np.empty(1 + 2 * k, dtype=np.float64)
+    py, ky, dy = _ptr(ylt, np.float64)
+    pm, km, dm = _ptr(metrics, np.float64)
+    if dy != dm:
+        raise ValueError("ylt and metrics must both be host arrays or both device tensors")
+    cap = int(ky.numel() if dy else ky.size)
+    mcap = int(km.numel() if dm else km.size)
+    if mcap < 1 + 2 * k:
+        raise ValueError("metrics holds fewer than 1 + 2 * len(probs) values")
+    _check(lib().ara_analyze(tables.handle, arr, p.ctypes.data_as(ctypes.c_void_p), k, py, cap, pm,
+                             flags | (ARA_DEVICE_PTR if dy else 0), _stream(stream)))
+    return ylt, metrics
 
 
 def event_nets(tables: Tables, layer: LayerSpec, out=None, stream=None):

@@ -1445,6 +1445,118 @@ ara_status ara_risk_metrics(const double* ylt, int64_t n_trials, const double* p
     return ARA_OK;
 }
 
+ara_status ara_analyze(ara_tables* t, const ara_layer* layer, const double* probs, int32_t n_probs, double* ylt,
+                       int64_t ylt_capacity, double* metrics, uint32_t flags, void* stream) {
+    if (!t || !layer || !ylt || !metrics || n_probs < 0 || (n_probs > 0 && !probs))
+        return fail(ARA_ERR_INVALID_ARG, "NULL argument");
+    if (n_probs > 4) return fail(ARA_ERR_UNSUPPORTED, "at most 4 probabilities per call");
+    if (flags & ~static_cast<uint32_t>(ARA_DEVICE_PTR | ARA_GRAPH | ARA_PROFILE))
+        return fail(ARA_ERR_INVALID_ARG, "flags: ARA_DEVICE_PTR, ARA_GRAPH and ARA_PROFILE only");
+    ara::LayerArgs L;
+    ara_status st = build_layer_args(t, *layer, L);
+    if (st != ARA_OK) return st;
+    if (L.trial_count < 1) return fail(ARA_ERR_INVALID_ARG, "layer has no trials");
+    if (ylt_capacity < L.trial_count)
+        return fail(ARA_ERR_BUFFER_TOO_SMALL, "ylt holds %lld values, %lld needed", (long long)ylt_capacity,
+                    (long long)L.trial_count);
+    std::vector<int64_t> m(n_probs);
+    for (int q = 0; q < n_probs; ++q) {
+        if (!(probs[q] > 0.0 && probs[q] < 1.0)) return fail(ARA_ERR_INVALID_ARG, "p must lie in (0, 1)");
+        m[q] = tail_count(L.trial_count, probs[q]);
+    }
+    const bool dev = (flags & ARA_DEVICE_PTR) != 0;
+    if ((flags & ARA_GRAPH) && (!dev || !stream))
+        return fail(ARA_ERR_INVALID_ARG, "ARA_GRAPH needs device outputs and a non-null stream");
+    ara_tuning tu;
+    {
+        std::lock_guard<std::mutex> g(t->mu);
+        tu = t->tuning;
+    }
+    if (!(flags & ARA_GRAPH) || t->parts.P <= 0) {
+        // the two calls one after the other (the plain layout has no graph)
+        st = ara_run_layers(t, layer, 1, ylt, ylt_capacity, flags & (ARA_DEVICE_PTR | ARA_PROFILE), stream);
+        if (st != ARA_OK) return st;
+        return ara_risk_metrics(ylt, L.trial_count, probs, n_probs, metrics, metrics + 1, metrics + 1 + n_probs,
+                                flags & ARA_DEVICE_PTR, stream);
+    }
+    // one graph: fold, pass, combine and the metrics kernels, on scratch the
+    // graph owns (the metrics part primed once; each replay leaves it ready
+    // for the next).  Terms and ELT choices are read from device memory, so
+    // new terms reuse the graph.
+    DeviceScope ds(t->device);
+    if (!ds.ok) return fail(ARA_ERR_DEVICE, "cannot select the tables' device");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    UseFence use_fence(t, s);           // the tables' memory outlives this call's work
+    const SplitPass split(t, tu);
+    auto up = [](size_t n) { return (n + 255) & ~size_t(255); };
+    const size_t la_bytes = up(sizeof(ara::LayerArgs));
+    const size_t o_bytes = up(sizeof(double) * t->C);
+    const size_t p_bytes = up(static_cast<size_t>(ara::part_scratch_bytes(t->C, t->parts.P)));
+    const size_t xg_bytes = up(split.partial_bytes(L.trial_count));
+    const size_t m_bytes = up(static_cast<size_t>(ara::metrics_scratch_bytes(n_probs, L.trial_count)));
+    // what the graph bakes in: the outputs, the trial range, the pass and the tail counts
+    std::vector<int64_t> key{-2, reinterpret_cast<int64_t>(ylt), reinterpret_cast<int64_t>(metrics), L.trial_begin,
+                             L.trial_count, split.stream ? 1 : 0, n_probs};
+    for (int q = 0; q < n_probs; ++q) key.push_back(m[q]);
+    const bool prof = (flags & ARA_PROFILE) != 0;
+    std::lock_guard<std::mutex> g(t->stage_mu);
+    ara::GraphEntry* ge = nullptr;
+    for (auto* c : t->graphs)
+        if (c->key == key) ge = c;
+    auto upload = [&](ara::GraphEntry* e) -> hipError_t {
+        hipError_t r = stage_acquire(e->stage, sizeof(ara::LayerArgs));
+        if (r != hipSuccess) return r;
+        std::memcpy(e->stage.p, &L, sizeof(ara::LayerArgs));
+        if ((r = hipMemcpyAsync(e->scratch, e->stage.p, sizeof(ara::LayerArgs), hipMemcpyHostToDevice, s)) !=
+            hipSuccess)
+            return r;
+        return hipEventRecord(e->stage.done, s);
+    };
+    if (!ge) {
+        ge = new ara::GraphEntry();
+        ge->key = key;
+        hipError_t e = hipMalloc(&ge->scratch, la_bytes + o_bytes + p_bytes + xg_bytes + m_bytes);
+        if (e != hipSuccess) {
+            free_graph(ge);
+            return hip_fail(e, "graph scratch");
+        }
+        char* gb = static_cast<char*>(ge->scratch);
+        const ara::LayerArgs* dL = reinterpret_cast<const ara::LayerArgs*>(gb);
+        double* go = reinterpret_cast<double*>(gb + la_bytes);
+        void* gp = gb + la_bytes + o_bytes;
+        void* gx = gb + la_bytes + o_bytes + p_bytes;
+        void* gm = gb + la_bytes + o_bytes + p_bytes + xg_bytes;
+        if ((e = upload(ge)) != hipSuccess || (e = ara::launch_metrics_prime(gm, m.data(), n_probs, s)) != hipSuccess ||
+            (e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal)) != hipSuccess) {
+            free_graph(ge);
+            return hip_fail(e, "graph capture");
+        }
+        hipError_t le = ara::launch_fold_parts(t->sparse, t->C, L, dL, go, t->parts.P, gp, s);
+        if (le == hipSuccess) le = split.pass(L, gp, gx, s);
+        if (le == hipSuccess) le = split.combine(L, dL, gx, ylt, nullptr, s);
+        if (le == hipSuccess)
+            le = ara::launch_metrics(ylt, L.trial_count, m.data(), n_probs, gm, true,
+                                     ara::MetricsOut{metrics, metrics + 1, metrics + 1 + n_probs, 1}, t->n_cu, s);
+        e = hipStreamEndCapture(s, &ge->graph);
+        if (le != hipSuccess || e != hipSuccess ||
+            (e = hipGraphInstantiate(&ge->exec, ge->graph, nullptr, nullptr, 0)) != hipSuccess) {
+            free_graph(ge);
+            return hip_fail(le != hipSuccess ? le : e, "graph instantiate");
+        }
+        if (t->graphs.size() >= 8) {
+            free_graph(t->graphs.front());
+            t->graphs.erase(t->graphs.begin());
+        }
+        t->graphs.push_back(ge);
+    } else {
+        HIP_TRY(upload(ge), "upload layer terms");
+    }
+    KernelTimer kt(t, s, prof, ARA_KERNEL_BATCHED);
+    HIP_TRY(hipGraphLaunch(ge->exec, s), "graph launch");
+    kt.done();
+    return ARA_OK;
+}
+
 ara_status ara_risk_metrics_noalloc(const double* ylt, int64_t n_trials, const double* probs, int32_t n_probs,
                                     double* mean_out, double* pml_out, double* tvar_out, void* stream) {
     if (!ylt || !mean_out || n_probs < 0 || (n_probs > 0 && (!probs || !pml_out || !tvar_out)))

@@ -476,6 +476,9 @@ struct MetricsOut {
 int64_t metrics_scratch_bytes(int n_probs, int64_t n);
 // `primed`: the scratch was last used by a launch_metrics sequence that was
 // enqueued whole, which leaves it ready for the next one (no init kernel)
+// readies a new scratch for launch_metrics(..., primed = true): the state the
+// previous sequence of a reused scratch leaves behind
+hipError_t launch_metrics_prime(void* scratch, const int64_t* m_host, int n_probs, hipStream_t s);
 hipError_t launch_metrics(const double* ylt, int64_t n, const int64_t* m_host, int n_probs,
                           void* scratch, bool primed, MetricsOut out, int n_cu, hipStream_t s);
 

@@ -489,6 +489,15 @@ int64_t metrics_scratch_bytes(int n_probs, int64_t n) {
     return base + static_cast<int64_t>(n_probs) * n * static_cast<int64_t>(sizeof(uint64_t));
 }
 
+hipError_t launch_metrics_prime(void* scratch, const int64_t* m_host, int n_probs, hipStream_t st) {
+    if (n_probs > kMaxProbs) return hipErrorInvalidValue;
+    Scratch s = carve(scratch, n_probs);
+    MArgs ma{};
+    for (int q = 0; q < n_probs; ++q) ma.m[q] = m_host[q];
+    hipLaunchKernelGGL(select_init_kernel, dim3(16), dim3(256), 0, st, s, ma, n_probs);
+    return hipGetLastError();
+}
+
 hipError_t launch_metrics(const double* ylt, int64_t n, const int64_t* m_host, int n_probs,
                           void* scratch, bool primed, MetricsOut out, int n_cu, hipStream_t st) {
     if (n_probs > kMaxProbs) return hipErrorInvalidValue;

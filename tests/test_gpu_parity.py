@@ -345,6 +345,55 @@ def test_concurrent_streams_same_results(ara, cfg0):
         assert np.array_equal(o.cpu().numpy(), base)
 
 
+def _analyze_check(ara, tables, spec, n, probs):
+    """ara_analyze eager, as a replayed graph (three replays with eager work
+    between them, then new terms through the same graph) and with host
+    outputs, against ara_run_layers followed by ara_risk_metrics, bit for bit."""
+    import torch
+    k = len(probs)
+
+    def separate(sp):
+        y = torch.empty(n, dtype=torch.float64, device="cuda")
+        ara.run_layers(tables, [sp], out=y)
+        r = torch.empty(1 + 2 * k, dtype=torch.float64, device="cuda")
+        ara.risk_metrics(y, probs, outputs=r)
+        torch.cuda.synchronize()
+        return y.cpu().numpy(), r.cpu().numpy()
+
+    y0, r0 = separate(spec)
+    yh, rh = ara.analyze(tables, spec, probs)
+    assert np.array_equal(yh, y0) and np.array_equal(rh, r0)
+    stream = torch.cuda.Stream()
+    y = torch.empty(n, dtype=torch.float64, device="cuda")
+    r = torch.empty(1 + 2 * k, dtype=torch.float64, device="cuda")
+    with torch.cuda.stream(stream):
+        for flags in (0, ara.ARA_GRAPH, ara.ARA_GRAPH, ara.ARA_GRAPH):
+            y.fill_(-1.0)
+            r.fill_(-1.0)
+            ara.analyze(tables, spec, probs, ylt=y, metrics=r, flags=flags, stream=stream)
+            stream.synchronize()
+            assert np.array_equal(y.cpu().numpy(), y0), flags
+            assert np.array_equal(r.cpu().numpy(), r0), flags
+        spec2 = spec.with_theta(spec.theta() * 1.01)
+        y2, r2 = separate(spec2)
+        assert not np.array_equal(r2, r0)
+        ara.analyze(tables, spec2, probs, ylt=y, metrics=r, flags=ara.ARA_GRAPH, stream=stream)
+        stream.synchronize()
+        assert np.array_equal(y.cpu().numpy(), y2) and np.array_equal(r.cpu().numpy(), r2)
+
+
+def test_analyze_matches_layer_call_and_metrics(ara, cfg0):
+    w, tables, _, _ = cfg0
+    spec = _spec(ara, w.layers[0], w.pool, w.yet)
+    _analyze_check(ara, tables, spec, w.yet.n_trials, [0.99, 0.9])
+    with pytest.raises(ara.AraError) as e:
+        ara.analyze(tables, spec, [0.99] * 5)
+    assert e.value.status == ara.ARA_ERR_UNSUPPORTED
+    with pytest.raises(ara.AraError) as e:
+        ara.analyze(tables, spec, [1.5])
+    assert e.value.status == ara.ARA_ERR_INVALID_ARG
+
+
 def test_device_memory_cache_release(ara):
     """Freed device memory stays in the library's cache for reuse; releasing
     hands every idle block back to the runtime, the counts add up, and tables
@@ -1004,6 +1053,13 @@ def test_config1_prefix_full_parity_and_gradients(ara, cfg1):
         assert np.array_equal(gm, g["grad_mean"]), pv
         assert np.array_equal(gt, g["grad_tvar"]), pv
     ara.set_tuning(tables)
+
+
+def test_config1_analyze_graph(ara, cfg1):
+    """The one-graph analysis on the 1M-trial workload (the benchmark's step)."""
+    w, tables = cfg1
+    spec = _spec(ara, w.layers[0], w.pool, w.yet)
+    _analyze_check(ara, tables, spec, w.yet.n_trials, list(w.probs))
 
 
 def test_config1_gradient_vs_finite_differences(ara, cfg1):
