@@ -392,6 +392,10 @@ def test_analyze_matches_layer_call_and_metrics(ara, cfg0):
     with pytest.raises(ara.AraError) as e:
         ara.analyze(tables, spec, [1.5])
     assert e.value.status == ara.ARA_ERR_INVALID_ARG
+    # the plain layout has no graph: ARA_GRAPH runs the two calls
+    plain = ara.create_tables(w.yet.offsets, w.yet.ids, w.pool.losses, flags=ara.ARA_PLAIN_LAYOUT)
+    _analyze_check(ara, plain, spec, w.yet.n_trials, [0.99])
+    plain.close()
 
 
 def test_device_memory_cache_release(ara):
