@@ -385,7 +385,11 @@ def _analyze_check(ara, tables, spec, n, probs):
 def test_analyze_matches_layer_call_and_metrics(ara, cfg0):
     w, tables, _, _ = cfg0
     spec = _spec(ara, w.layers[0], w.pool, w.yet)
-    _analyze_check(ara, tables, spec, w.yet.n_trials, [0.99, 0.9])
+    # the streaming pass (0) and the XCD-affine pass (2) inside the graph
+    for pv in (0, 2):
+        ara.set_tuning(tables, pass_variant=pv)
+        _analyze_check(ara, tables, spec, w.yet.n_trials, [0.99, 0.9])
+    ara.set_tuning(tables)
     with pytest.raises(ara.AraError) as e:
         ara.analyze(tables, spec, [0.99] * 5)
     assert e.value.status == ara.ARA_ERR_UNSUPPORTED
