@@ -1472,8 +1472,9 @@ ara_status ara_analyze(ara_tables* t, const ara_layer* layer, const double* prob
         std::lock_guard<std::mutex> g(t->mu);
         tu = t->tuning;
     }
-    if (!(flags & ARA_GRAPH) || t->parts.P <= 0) {
-        // the two calls one after the other (the plain layout has no graph)
+    if (!(flags & ARA_GRAPH) || t->parts.P <= 0 || tu.pass_variant == 1) {
+        // the two calls one after the other (as ara_run_layers, no graph for
+        // the plain layout or the rank-based pass of pass_variant 1)
         st = ara_run_layers(t, layer, 1, ylt, ylt_capacity, flags & (ARA_DEVICE_PTR | ARA_PROFILE), stream);
         if (st != ARA_OK) return st;
         return ara_risk_metrics(ylt, L.trial_count, probs, n_probs, metrics, metrics + 1, metrics + 1 + n_probs,

@@ -385,8 +385,9 @@ def _analyze_check(ara, tables, spec, n, probs):
 def test_analyze_matches_layer_call_and_metrics(ara, cfg0):
     w, tables, _, _ = cfg0
     spec = _spec(ara, w.layers[0], w.pool, w.yet)
-    # the streaming pass (0) and the XCD-affine pass (2) inside the graph
-    for pv in (0, 2):
+    # the streaming pass (0) and the XCD-affine pass (2) inside the graph; the
+    # rank-based pass (1) runs the two calls
+    for pv in (0, 2, 1):
         ara.set_tuning(tables, pass_variant=pv)
         _analyze_check(ara, tables, spec, w.yet.n_trials, [0.99, 0.9])
     ara.set_tuning(tables)
