@@ -58,8 +58,8 @@ size_t size_class(size_t bytes) {
     return base + (bytes - base + step - 1) / step * step;
 }
 
-// hipFree of the idle blocks whose last free has completed (waits for the
-// device); returns the bytes released
+// hipFree of the idle blocks whose last free has completed, or that have no
+// event (hipFree waits for the device); returns the bytes released
 int64_t release_idle(DeviceCache& c) {
     std::lock_guard<std::mutex> g(c.mu);
     int64_t freed = 0;
@@ -105,7 +105,9 @@ hipError_t dev_alloc(void** p, size_t bytes, hipStream_t s) {
         for (auto& kv : c.blocks) {
             CacheBlock& b = kv.second;
             if (b.in_use || b.size != cls) continue;
-            if (b.stream != s && b.ready && hipEventQuery(b.ready) != hipSuccess) continue;
+            // another stream only once the free is known to be complete (a
+            // block without an event serves its own stream only)
+            if (b.stream != s && (!b.ready || hipEventQuery(b.ready) != hipSuccess)) continue;
             b.in_use = true;
             *p = kv.first;
             return hipSuccess;
