@@ -391,6 +391,7 @@ def test_analyze_matches_layer_call_and_metrics(ara, cfg0):
         ara.set_tuning(tables, pass_variant=pv)
         _analyze_check(ara, tables, spec, w.yet.n_trials, [0.99, 0.9])
     ara.set_tuning(tables)
+    _analyze_check(ara, tables, spec, w.yet.n_trials, [])          # the mean alone
     with pytest.raises(ara.AraError) as e:
         ara.analyze(tables, spec, [0.99] * 5)
     assert e.value.status == ara.ARA_ERR_UNSUPPORTED
