@@ -1655,6 +1655,7 @@ __global__ __launch_bounds__(kNetsThreads) void event_nets_kernel(const int64_t*
                                                                   int64_t n_cw, const double* __restrict__ compact,
                                                                   LayerArgs L, double* __restrict__ nets) {
     static_assert(kE == 4 || kE == 8, "four or eight events per lane");
+    static_assert(!kStride || kE == 4, "stride slots are lanes' last events only with four events per lane");
     constexpr int kW = 64 * kE;                                        // positions per step
     static_assert(kW <= kIdPad, "a step may read up to kW - 1 IDs past the table's end");
     __shared__ double stage[kNetsThreads / 64][kW];
@@ -1756,21 +1757,23 @@ __global__ __launch_bounds__(kNetsThreads) void event_nets_kernel(const int64_t*
         wave_seg_scan_dd(sf, sh, sl);
         // the open segment's total before this lane's first event, then the
         // running totals again, event by event: A of every position to LDS
-        double rh = __shfl_up(sh, 1, 64), rl = __shfl_up(sl, 1, 64);
-        if (lane == 0) {
-            rh = ch;
-            rl = cl;
-        }
-#pragma unroll
-        for (int q = 0; q < kE; ++q) {
-            if (fq[q]) {
-                rh = 0.0;
-                rl = 0.0;
+        if constexpr (kStride) {
+            // positions are 4-aligned per lane, so each 64b + 63 is some lane's
+            // last event, where the running total is that lane's inclusive scan
+            if (ok[kE - 1] && ((pos + kE - 1) & 63) == 63) nets[(pos + kE - 1) >> 6] = sh + sl;
+        } else {
+            double rh = __shfl_up(sh, 1, 64), rl = __shfl_up(sl, 1, 64);
+            if (lane == 0) {
+                rh = ch;
+                rl = cl;
             }
-            dd_add(rh, rl, oq[q]);
-            if constexpr (kStride) {
-                if (ok[q] && ((pos + q) & 63) == 63) nets[(pos + q) >> 6] = rh + rl;
-            } else {
+#pragma unroll
+            for (int q = 0; q < kE; ++q) {
+                if (fq[q]) {
+                    rh = 0.0;
+                    rl = 0.0;
+                }
+                dd_add(rh, rl, oq[q]);
                 st[lane * kE + q] = apply_terms(rh + rl, L.aggR, L.aggL);
             }
         }
