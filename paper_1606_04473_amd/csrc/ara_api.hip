@@ -1040,8 +1040,10 @@ ara_status ara_run_layers(ara_tables* t, const ara_layer* layers, int32_t n_laye
     if ((flags & ARA_GRAPH) && (batched || xgraph) && (!dev_out || s == nullptr))
         return fail(ARA_ERR_INVALID_ARG, "ARA_GRAPH needs a device output and a non-null stream");
     if (xgraph) {
-        // key: layer count, output, trial ranges (terms and ELT choices may change)
-        std::vector<int64_t> key{-1, static_cast<int64_t>(n_layers), reinterpret_cast<int64_t>(out)};   // -1: not a batched plan
+        // key: the pass captured, layer count, output, trial ranges (terms and
+        // ELT choices may change); -1: not a batched plan
+        std::vector<int64_t> key{-1, split.stream ? 1 : 0, static_cast<int64_t>(n_layers),
+                                 reinterpret_cast<int64_t>(out)};
         int64_t most = 0;
         for (int i = 0; i < n_layers; ++i) {
             key.push_back(L[i].trial_begin);
