@@ -229,8 +229,8 @@ def main() -> None:
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build measures one GPU; the analysis shards by trials "
-                                   "across GPUs (see DESIGN.md) but multi-GPU runs are not part of it",
+        print(json.dumps({"error": "bench.py measures one GPU: the analysis shards by trials "
+                                   "across GPUs, but runs on several GPUs are not measured",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 

@@ -57,7 +57,7 @@ typedef int32_t ara_status;
 #define ARA_ERR_NO_MEMORY        4  /* a device or pinned-host allocation failed */
 #define ARA_ERR_DEVICE           5  /* a HIP runtime error; the HIP message is in ara_last_error() */
 #define ARA_ERR_NOT_READY        6  /* ara_backward without a matching checkpointed forward */
-#define ARA_ERR_UNSUPPORTED      7  /* a valid request this build does not handle (e.g. J > ARA_MAX_LAYER_ELTS) */
+#define ARA_ERR_UNSUPPORTED      7  /* a valid request the library does not handle (e.g. J > ARA_MAX_LAYER_ELTS) */
 
 /* flags */
 #define ARA_DEVICE_PTR   (1u << 0)  /* pointer arguments of the call are device memory */
