@@ -1646,7 +1646,10 @@ __global__ __launch_bounds__(256) void coarse_map_kernel(const uint64_t* __restr
 // minus A_0.  Nets are staged in LDS and written with non-temporal stores of
 // 64 consecutive values.  With kStride the kernel writes, instead of nets,
 // the running total S_d of every position d = 64b + 63 to slot b of `nets`
-// (the stride checkpoints of the forward pass).
+// (the stride checkpoints of the forward pass); it needs no LDS stage and is
+// launched with eight events per lane, which spreads the wave scan over twice
+// the events (the nets keep four: eight would double the stage and leave the
+// coarse map half the LDS).
 template <int kE, bool kStride = false>
 __global__ __launch_bounds__(kNetsThreads) void event_nets_kernel(const int64_t* __restrict__ offsets,
                                                                   const uint32_t* __restrict__ ids,
@@ -1655,10 +1658,10 @@ __global__ __launch_bounds__(kNetsThreads) void event_nets_kernel(const int64_t*
                                                                   int64_t n_cw, const double* __restrict__ compact,
                                                                   LayerArgs L, double* __restrict__ nets) {
     static_assert(kE == 4 || kE == 8, "four or eight events per lane");
-    static_assert(!kStride || kE == 4, "stride slots are lanes' last events only with four events per lane");
+    static_assert(64 % kE == 0, "stride slots are lanes' last events when kE divides 64");
     constexpr int kW = 64 * kE;                                        // positions per step
     static_assert(kW <= kIdPad, "a step may read up to kW - 1 IDs past the table's end");
-    __shared__ double stage[kNetsThreads / 64][kW];
+    __shared__ double stage[kNetsThreads / 64][kStride ? 1 : kW];   // A per position
     __shared__ __attribute__((aligned(8))) uint8_t flag_rows[kNetsThreads / 64][kW];
     extern __shared__ uint32_t coarse[];                               // [n_cw]
     // the coarse map, before any wave can leave (the only workgroup barrier)
@@ -1682,7 +1685,7 @@ __global__ __launch_bounds__(kNetsThreads) void event_nets_kernel(const int64_t*
     *reinterpret_cast<flag_word*>(fl + lane * kE) = 0;
     int64_t kb = k0;                                                   // trial starts held: kb .. kb + 63
     int64_t bnd = kb + lane < k1 ? offsets[kb + lane] : INT64_MAX;
-    const int64_t c0 = P0 & ~int64_t(3);
+    const int64_t c0 = P0 & ~int64_t(kE - 1);                      // 16-byte and lane aligned
     u32x4 nxt[kE / 4];
 #pragma unroll
     for (int u = 0; u < kE / 4; ++u)
@@ -1758,8 +1761,9 @@ __global__ __launch_bounds__(kNetsThreads) void event_nets_kernel(const int64_t*
         // the open segment's total before this lane's first event, then the
         // running totals again, event by event: A of every position to LDS
         if constexpr (kStride) {
-            // positions are 4-aligned per lane, so each 64b + 63 is some lane's
-            // last event, where the running total is that lane's inclusive scan
+            // a lane's first position is a multiple of kE, and kE divides 64, so
+            // each 64b + 63 is some lane's last event, where the running total is
+            // that lane's inclusive scan
             if (ok[kE - 1] && ((pos + kE - 1) & 63) == 63) nets[(pos + kE - 1) >> 6] = sh + sl;
         } else {
             double rh = __shfl_up(sh, 1, 64), rl = __shfl_up(sl, 1, 64);
@@ -1829,14 +1833,16 @@ hipError_t launch_nets_or_stride(const int64_t* offsets, const uint32_t* ids, co
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const size_t lds = sizeof(uint32_t) * static_cast<size_t>(n_cw);
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, event_nets_kernel<4>, kNetsThreads, lds) != hipSuccess ||
+    if ((stride ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, event_nets_kernel<8, true>, kNetsThreads, lds)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, event_nets_kernel<4, false>, kNetsThreads,
+                                                                lds)) != hipSuccess ||
         per_cu < 1)
         per_cu = 1;
     int64_t blocks = (L.trial_count + kNetsThreads / 64 - 1) / (kNetsThreads / 64);
     const int64_t cap = static_cast<int64_t>(n_cu) * per_cu;
     if (blocks > cap) blocks = cap;
     if (stride)
-        hipLaunchKernelGGL((event_nets_kernel<4, true>), dim3(static_cast<uint32_t>(blocks)), dim3(kNetsThreads), lds,
+        hipLaunchKernelGGL((event_nets_kernel<8, true>), dim3(static_cast<uint32_t>(blocks)), dim3(kNetsThreads), lds,
                            s, offsets, ids, probe, coarse, cshift, n_cw, ps.compact, L, out);
     else
         hipLaunchKernelGGL((event_nets_kernel<4, false>), dim3(static_cast<uint32_t>(blocks)), dim3(kNetsThreads), lds,

@@ -726,6 +726,41 @@ def test_event_nets_short_and_empty_trials(ara):
     tables.close()
 
 
+
+def test_stride_checkpoints_short_trials_and_ranges(ara):
+    """Stride slots (the running total at every event 64b + 63) on runs of
+    trials of 0-3 events, a long trial, empty trials at the ends, and ranges
+    that begin and end inside such runs, after each pass variant: slots inside
+    the range match the exact prefix sums, those outside hold NaN."""
+    rng = np.random.default_rng(61)
+    C = 40_000
+    pool = make_elt_pool(3, C, 9_000, seed=62)
+    lengths = np.concatenate([np.zeros(3, np.int64), rng.integers(0, 4, 2500), [3000, 0, 5],
+                              rng.integers(0, 4, 1500), rng.integers(100, 700, 30), np.zeros(4, np.int64)])
+    trials = [rng.integers(0, C, size=int(k)).tolist() for k in lengths]
+    yet = make_tiny_yet(trials, C)
+    tables = ara.create_tables(yet.offsets, yet.ids, pool.losses)
+    trial_of = np.repeat(np.arange(yet.n_trials), np.diff(yet.offsets))
+    for begin, count in ((0, yet.n_trials), (5, 2600), (1901, 1700), (yet.n_trials - 37, 37)):
+        lay = Layer(np.array([2, 0], dtype=np.int32), 400.0, 2.0e5, 3.0e4, 8.0e5, begin, count)
+        _, o = oracle.occurrence_catalogue(pool, lay)
+        spec = _spec(ara, lay, pool, yet)
+        for pv in (0, 1, 2):
+            ara.set_tuning(tables, pass_variant=pv)
+            ara.run_layers(tables, [spec], flags=ara.ARA_CHECKPOINT_STRIDE)
+            slots = ara.read_checkpoints(tables, 1)
+            assert slots.shape[0] == yet.n_events // 64
+            for b in range(slots.shape[0]):
+                last = 64 * b + 63
+                t = trial_of[last]
+                if not begin <= t < begin + count:
+                    assert np.isnan(slots[b]), (begin, count, pv, b)
+                    continue
+                pref = math.fsum(o[yet.ids[yet.offsets[t]:last + 1]].tolist())
+                assert abs(slots[b] - pref) <= REL * pref, (begin, count, pv, b, slots[b], pref)
+    ara.set_tuning(tables)
+    tables.close()
+
 def test_error_paths(ara):
     C = 100
     pool = make_elt_pool(2, C, 10, seed=3)
