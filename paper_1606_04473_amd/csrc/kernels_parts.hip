@@ -1518,7 +1518,8 @@ namespace {
 
 constexpr int kProbeShift = 5;                  // 32 catalogue events per probe word
 constexpr int kNetsThreads = 1024;              // one workgroup per CU: its waves share the coarse map
-constexpr int kCoarseBytes = 124 * 1024;        // LDS left for the coarse map beside the waves' rows
+constexpr int kNetsStageBytes = 37 * 1024;     // the waves' stage and flag rows
+constexpr int kCoarseBytes = 160 * 1024 - kNetsStageBytes;   // LDS left for the coarse map
 
 // value moved across lanes by a DPP control; lanes without a source get 0
 template <int kCtrl, int kRowMask>
@@ -1638,18 +1639,18 @@ __global__ __launch_bounds__(256) void coarse_map_kernel(const uint64_t* __restr
 // workgroup's 16 waves first test a coarse map in LDS (one bit per 2^cshift
 // events, set when any of them has a loss) and probe L2 only for events
 // whose bit is set.  Trial starts (held one per lane and marked in a
-// per-wave LDS flag row) reset a segmented double-double scan: each event's
+// per-wave LDS bit row) reset a segmented double-double scan: each event's
 // running total S_d (the lane's own prefix, the scan of the lanes before it,
 // the carry of earlier steps) is rounded once; A_d = clamp(S_d; AggR, AggL)
 // and the net is A_d - A_{d-1}, with A_{d-1} = A_0 = clamp(0; AggR, AggL)
 // for a trial's first event, so a trial's nets telescope to its year loss
-// minus A_0.  Nets are staged in LDS and written with non-temporal stores of
-// 64 consecutive values.  With kStride the kernel writes, instead of nets,
-// the running total S_d of every position d = 64b + 63 to slot b of `nets`
-// (the stride checkpoints of the forward pass); it needs no LDS stage and is
-// launched with eight events per lane, which spreads the wave scan over twice
-// the events (the nets keep four: eight would double the stage and leave the
-// coarse map half the LDS).
+// minus A_0.  A lane forms its kE nets in registers (A of the position before
+// its first one comes from the lane below); the nets go through a per-wave
+// LDS stage, half a step at a time, and out in non-temporal stores of 64
+// consecutive values.  With kStride the kernel writes, instead of nets, the
+// running total S_d of every position d = 64b + 63 to slot b of `nets` (the
+// stride checkpoints of the forward pass) and needs no stage.  Eight events
+// per lane spread the wave scan over twice the events of four.
 template <int kE, bool kStride = false>
 __global__ __launch_bounds__(kNetsThreads) void event_nets_kernel(const int64_t* __restrict__ offsets,
                                                                   const uint32_t* __restrict__ ids,
@@ -1661,15 +1662,17 @@ __global__ __launch_bounds__(kNetsThreads) void event_nets_kernel(const int64_t*
     static_assert(64 % kE == 0, "stride slots are lanes' last events when kE divides 64");
     constexpr int kW = 64 * kE;                                        // positions per step
     static_assert(kW <= kIdPad, "a step may read up to kW - 1 IDs past the table's end");
-    __shared__ double stage[kNetsThreads / 64][kStride ? 1 : kW];   // A per position
-    __shared__ __attribute__((aligned(8))) uint8_t flag_rows[kNetsThreads / 64][kW];
+    constexpr int kRow = 32 * (kE + 1);        // half a step's nets, one pad slot per lane
+    static_assert(kNetsStageBytes >= (kNetsThreads / 64) * (kRow * 8 + kW / 8), "stage rows fit their LDS share");
+    __shared__ double stage[kNetsThreads / 64][kStride ? 1 : kRow];
+    __shared__ uint32_t flag_rows[kNetsThreads / 64][kW / 32];          // bit i: a trial starts at c + i
     extern __shared__ uint32_t coarse[];                               // [n_cw]
     // the coarse map, before any wave can leave (the only workgroup barrier)
     for (int64_t i = threadIdx.x; i < n_cw; i += blockDim.x) coarse[i] = gcoarse[i];
     __syncthreads();
     const int lane = threadIdx.x & 63;
     double* st = stage[threadIdx.x >> 6];
-    uint8_t* fl = flag_rows[threadIdx.x >> 6];
+    uint32_t* fl = flag_rows[threadIdx.x >> 6];
     const int64_t w = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
     const int64_t n_w = (static_cast<int64_t>(gridDim.x) * blockDim.x) >> 6;
     const int64_t t0 = L.trial_begin, t1 = L.trial_begin + L.trial_count;
@@ -1681,11 +1684,10 @@ __global__ __launch_bounds__(kNetsThreads) void event_nets_kernel(const int64_t*
     const int64_t P0 = offsets[k0], P1 = offsets[k1];
     if (P0 >= P1) return;
     const double A0 = apply_terms(0.0, L.aggR, L.aggL);
-    using flag_word = typename std::conditional<kE == 8, uint64_t, uint32_t>::type;
-    *reinterpret_cast<flag_word*>(fl + lane * kE) = 0;
+    if (lane < kW / 32) fl[lane] = 0;
     int64_t kb = k0;                                                   // trial starts held: kb .. kb + 63
     int64_t bnd = kb + lane < k1 ? offsets[kb + lane] : INT64_MAX;
-    const int64_t c0 = P0 & ~int64_t(kE - 1);                      // 16-byte and lane aligned
+    const int64_t c0 = P0 & ~int64_t(kE - 1);                          // 16-byte and lane aligned
     u32x4 nxt[kE / 4];
 #pragma unroll
     for (int u = 0; u < kE / 4; ++u)
@@ -1704,7 +1706,10 @@ __global__ __launch_bounds__(kNetsThreads) void event_nets_kernel(const int64_t*
         }
         // mark the trial starts inside [c, c + kW)
         for (;;) {
-            if (bnd >= c && bnd < c + kW) fl[bnd - c] = 1;
+            if (bnd >= c && bnd < c + kW) {
+                const uint32_t i = static_cast<uint32_t>(bnd - c);
+                atomicOr(&fl[i >> 5], 1u << (i & 31u));
+            }
             if (static_cast<int64_t>(readlane_u64(static_cast<uint64_t>(bnd), 63)) >= c + kW) break;
             kb += 64;
             bnd = kb + lane < k1 ? offsets[kb + lane] : INT64_MAX;
@@ -1712,9 +1717,9 @@ __global__ __launch_bounds__(kNetsThreads) void event_nets_kernel(const int64_t*
         __builtin_amdgcn_wave_barrier();
         uint32_t fq[kE];
         {
-            const flag_word fw = *reinterpret_cast<const flag_word*>(fl + lane * kE);
+            const uint32_t fb = fl[(lane * kE) >> 5] >> ((lane * kE) & 31);
 #pragma unroll
-            for (int q = 0; q < kE; ++q) fq[q] = static_cast<uint32_t>(fw >> (8 * q)) & 1u;
+            for (int q = 0; q < kE; ++q) fq[q] = (fb >> q) & 1u;
         }
         const int64_t pos = c + lane * kE;
         uint32_t E[kE];
@@ -1758,19 +1763,20 @@ __global__ __launch_bounds__(kNetsThreads) void event_nets_kernel(const int64_t*
         if (lane == 0 && !sf) dd_merge(h, l, ch, cl);              // the open segment's carry
         double sh = h, sl = l;
         wave_seg_scan_dd(sf, sh, sl);
-        // the open segment's total before this lane's first event, then the
-        // running totals again, event by event: A of every position to LDS
         if constexpr (kStride) {
             // a lane's first position is a multiple of kE, and kE divides 64, so
             // each 64b + 63 is some lane's last event, where the running total is
             // that lane's inclusive scan
             if (ok[kE - 1] && ((pos + kE - 1) & 63) == 63) nets[(pos + kE - 1) >> 6] = sh + sl;
         } else {
+            // the open segment's total before this lane's first event, then the
+            // running totals again, event by event, and A of each position
             double rh = __shfl_up(sh, 1, 64), rl = __shfl_up(sl, 1, 64);
             if (lane == 0) {
                 rh = ch;
                 rl = cl;
             }
+            double A[kE];
 #pragma unroll
             for (int q = 0; q < kE; ++q) {
                 if (fq[q]) {
@@ -1778,26 +1784,39 @@ __global__ __launch_bounds__(kNetsThreads) void event_nets_kernel(const int64_t*
                     rl = 0.0;
                 }
                 dd_add(rh, rl, oq[q]);
-                st[lane * kE + q] = apply_terms(rh + rl, L.aggR, L.aggL);
+                A[q] = apply_terms(rh + rl, L.aggR, L.aggL);
             }
-        }
-        __builtin_amdgcn_wave_barrier();
-        // nets of 64 consecutive positions per store; A of the position before
-        // a trial's first event is A_0, before the step's first one a_prev
-        if constexpr (!kStride) {
+            // A of the position before each: A_0 before a trial's first event,
+            // the lane below's last A before this lane's first, a_prev before the step's
+            double before = __shfl_up(A[kE - 1], 1, 64);
+            if (lane == 0) before = a_prev;
+            double net[kE];
 #pragma unroll
-            for (int q = 0; q < kE; ++q) {
-                const int i = q * 64 + lane;
-                const int64_t p = c + i;
-                const double before = fl[i] ? A0 : (i == 0 ? a_prev : st[i - 1]);
-                if (p >= P0 && p < P1) __builtin_nontemporal_store(st[i] - before, nets + (p - ev0));
+            for (int q = 0; q < kE; ++q) net[q] = A[q] - (fq[q] ? A0 : (q == 0 ? before : A[q - 1]));
+            a_prev = readlane_f64(A[kE - 1], 63);
+            // half a step at a time: lanes [32 hf, 32 hf + 32) hold positions
+            // [kW/2 hf, kW/2 (hf + 1)); position i of the half sits at i + i / kE
+#pragma unroll
+            for (int hf = 0; hf < 2; ++hf) {
+                if ((lane >> 5) == hf) {
+#pragma unroll
+                    for (int q = 0; q < kE; ++q) st[(lane & 31) * (kE + 1) + q] = net[q];
+                }
+                __builtin_amdgcn_wave_barrier();
+#pragma unroll
+                for (int r = 0; r < kE / 2; ++r) {
+                    const int i = r * 64 + lane;
+                    const int64_t p = c + hf * (kW / 2) + i;
+                    const double v = st[i + i / kE];
+                    if (p >= P0 && p < P1) __builtin_nontemporal_store(v, nets + (p - ev0));
+                }
+                __builtin_amdgcn_wave_barrier();
             }
-            a_prev = st[kW - 1];
         }
         ch = readlane_f64(sh, 63);
         cl = readlane_f64(sl, 63);
         __builtin_amdgcn_wave_barrier();
-        *reinterpret_cast<flag_word*>(fl + lane * kE) = 0;
+        if (lane < kW / 32) fl[lane] = 0;
     }
 }
 
@@ -1834,7 +1853,7 @@ hipError_t launch_nets_or_stride(const int64_t* offsets, const uint32_t* ids, co
     const size_t lds = sizeof(uint32_t) * static_cast<size_t>(n_cw);
     int per_cu = 0;
     if ((stride ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, event_nets_kernel<8, true>, kNetsThreads, lds)
-                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, event_nets_kernel<4, false>, kNetsThreads,
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, event_nets_kernel<8, false>, kNetsThreads,
                                                                 lds)) != hipSuccess ||
         per_cu < 1)
         per_cu = 1;
@@ -1845,7 +1864,7 @@ hipError_t launch_nets_or_stride(const int64_t* offsets, const uint32_t* ids, co
         hipLaunchKernelGGL((event_nets_kernel<8, true>), dim3(static_cast<uint32_t>(blocks)), dim3(kNetsThreads), lds,
                            s, offsets, ids, probe, coarse, cshift, n_cw, ps.compact, L, out);
     else
-        hipLaunchKernelGGL((event_nets_kernel<4, false>), dim3(static_cast<uint32_t>(blocks)), dim3(kNetsThreads), lds,
+        hipLaunchKernelGGL((event_nets_kernel<8, false>), dim3(static_cast<uint32_t>(blocks)), dim3(kNetsThreads), lds,
                            s, offsets, ids, probe, coarse, cshift, n_cw, ps.compact, L, out);
     return hipGetLastError();
 }
