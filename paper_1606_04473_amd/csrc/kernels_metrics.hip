@@ -28,6 +28,7 @@ namespace ara {
 namespace {
 
 constexpr int kSumBlocks = 512;
+static_assert(kSumBlocks % 256 == 0, "the finishing workgroup holds kSumBlocks / 256 partials per thread");
 constexpr int kBins = 4096;
 constexpr int kPasses = 6;
 constexpr int kMaxProbs = 4;   // 4 x 16 KB histograms fit the 64 KB dynamic-LDS default
@@ -316,46 +317,60 @@ __global__ __launch_bounds__(256) void collect_kernel(const double* __restrict__
     }
     const int lane = threadIdx.x & 63;
     const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
-    for (int q = 0; q < n_probs; ++q) {
-        const uint64_t pre = pre_s[q], msk = msk_s[q];
-        const uint64_t top = pre | ~msk;            // the largest key with the prefix
-        uint64_t* cand = s.cand + static_cast<int64_t>(q) * n;
-        double hi = 0.0, lo = 0.0;
-        int64_t cnt = 0;
-        // whole waves step together (the bound is per workgroup), so every
-        // lane takes part in the ballots
-        for (int64_t b = static_cast<int64_t>(blockIdx.x) * blockDim.x; b < n; b += 4 * stride) {
-            double v[4];
-            bool ok[4];
+    uint64_t pre[kMaxProbs], msk[kMaxProbs];
+    double hi[kMaxProbs], lo[kMaxProbs];
+    int64_t cnt[kMaxProbs];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int64_t i = b + u * stride + threadIdx.x;
-                ok[u] = i < n;
-                v[u] = ok[u] ? x[i] : 0.0;
-            }
+    for (int q = 0; q < kMaxProbs; ++q) {
+        pre[q] = q < n_probs ? pre_s[q] : 0;
+        msk[q] = q < n_probs ? msk_s[q] : 0;
+        hi[q] = 0.0;
+        lo[q] = 0.0;
+        cnt[q] = 0;
+    }
+    // each value is loaded once for every probability, eight loads in
+    // flight per thread; whole waves step together (the bound is per
+    // workgroup), so every lane takes part in the ballots
+    for (int64_t b = static_cast<int64_t>(blockIdx.x) * blockDim.x; b < n; b += 8 * stride) {
+        double v[8];
+        bool ok[8];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const uint64_t key = key_of(v[u]);
+        for (int u = 0; u < 8; ++u) {
+            const int64_t i = b + u * stride + threadIdx.x;
+            ok[u] = i < n;
+            v[u] = ok[u] ? x[i] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const uint64_t key = key_of(v[u]);
+#pragma unroll
+            for (int q = 0; q < kMaxProbs; ++q) {
+                if (q >= n_probs) break;
+                const uint64_t top = pre[q] | ~msk[q];      // the largest key with the prefix
                 if (ok[u] && key > top) {
-                    dd_add(hi, lo, v[u]);
-                    cnt += 1;
+                    dd_add(hi[q], lo[q], v[u]);
+                    cnt[q] += 1;
                 }
-                const bool in = ok[u] && (key & msk) == pre;
+                const bool in = ok[u] && (key & msk[q]) == pre[q];
                 const uint64_t bal = __ballot(in);
                 if (bal) {
                     const int leader = __builtin_ctzll(bal);
                     uint32_t at = 0;
                     if (lane == leader) at = atomicAdd(&s.ccount[q], static_cast<uint32_t>(__popcll(bal)));
                     at = static_cast<uint32_t>(__shfl(static_cast<int>(at), leader, kWave));
-                    if (in) cand[at + __popcll(bal & ((uint64_t(1) << lane) - 1))] = key;
+                    if (in) s.cand[static_cast<int64_t>(q) * n + at + __popcll(bal & ((uint64_t(1) << lane) - 1))] = key;
                 }
             }
         }
-        block_reduce_dd(hi, lo, cnt);
+    }
+#pragma unroll
+    for (int q = 0; q < kMaxProbs; ++q) {
+        if (q >= n_probs) break;
+        block_reduce_dd(hi[q], lo[q], cnt[q]);
         if (threadIdx.x == 0) {
-            s.part_hi[(1 + q) * kSumBlocks + blockIdx.x] = hi;
-            s.part_lo[(1 + q) * kSumBlocks + blockIdx.x] = lo;
-            s.part_cnt[(1 + q) * kSumBlocks + blockIdx.x] = cnt;
+            s.part_hi[(1 + q) * kSumBlocks + blockIdx.x] = hi[q];
+            s.part_lo[(1 + q) * kSumBlocks + blockIdx.x] = lo[q];
+            s.part_cnt[(1 + q) * kSumBlocks + blockIdx.x] = cnt[q];
         }
         __syncthreads();
     }
@@ -364,37 +379,78 @@ __global__ __launch_bounds__(256) void collect_kernel(const double* __restrict__
 // One workgroup: the mean from the pass-0 partials; per probability, the
 // remaining digits chosen over its candidates (histograms in LDS), then PML
 // and TVaR from the tail partials plus the candidates above the threshold
-// (fixed reduction order).
+// (fixed reduction order).  Every load that depends on no other is issued
+// first (partials, states, candidate counts), then the candidates of each
+// probability with few of them go to LDS, so the work waits for two round
+// trips to memory instead of one or more per step.
 __global__ __launch_bounds__(256) void finish_kernel(Scratch s, int n_probs, int n_mean_part, int n_tail_part,
                                                      int64_t n, MetricsOut out) {
     __shared__ __attribute__((aligned(16))) uint32_t hist[kBins];
-    __shared__ uint64_t keys[kDirect];
+    __shared__ uint64_t keys[kMaxProbs][kDirect];
     __shared__ uint64_t found;
+    constexpr int kPer = kSumBlocks / 256;                  // partials per thread
     const bool bad = *s.flag != 0;
     const double nan = __longlong_as_double(0x7ff8000000000000LL);
+    double mh[kPer], ml[kPer];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        const int i = threadIdx.x + u * 256;
+        mh[u] = i < n_mean_part ? s.part_hi[i] : 0.0;
+        ml[u] = i < n_mean_part ? s.part_lo[i] : 0.0;
+    }
+    SelState sq[kMaxProbs];
+    int64_t cq[kMaxProbs];
+    double th[kMaxProbs][kPer], tl[kMaxProbs][kPer];
+    int64_t tc[kMaxProbs][kPer];
+#pragma unroll
+    for (int q = 0; q < kMaxProbs; ++q) {
+        if (q >= n_probs) break;
+        sq[q] = s.st[q];                            // written by the collect pass (st[0])
+        cq[q] = static_cast<int64_t>(s.ccount[q]);
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int i = threadIdx.x + u * 256;
+            const bool in = i < n_tail_part;
+            th[q][u] = in ? s.part_hi[(1 + q) * kSumBlocks + i] : 0.0;
+            tl[q][u] = in ? s.part_lo[(1 + q) * kSumBlocks + i] : 0.0;
+            tc[q][u] = in ? s.part_cnt[(1 + q) * kSumBlocks + i] : 0;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < kMaxProbs; ++q) {
+        if (q >= n_probs) break;
+        if (cq[q] <= kDirect) {
+            const uint64_t* cand = s.cand + static_cast<int64_t>(q) * n;
+            for (int64_t j = threadIdx.x; j < cq[q]; j += blockDim.x) keys[q][j] = cand[j];
+        }
+    }
+    __syncthreads();
     {
         double hi = 0.0, lo = 0.0;
         int64_t cnt = 0;
-        for (int i = threadIdx.x; i < n_mean_part; i += blockDim.x) dd_merge(hi, lo, s.part_hi[i], s.part_lo[i]);
+#pragma unroll
+        for (int u = 0; u < kPer; ++u)
+            if (threadIdx.x + u * 256 < n_mean_part) dd_merge(hi, lo, mh[u], ml[u]);
         block_reduce_dd(hi, lo, cnt);
         if (threadIdx.x == 0) *out.mean = bad ? nan : (hi + lo) / static_cast<double>(n);
         __syncthreads();
     }
-    for (int q = 0; q < n_probs; ++q) {
-        SelState st = s.st[q];                      // written by the collect pass (st[0])
-        const int64_t c = static_cast<int64_t>(s.ccount[q]);
+#pragma unroll
+    for (int q = 0; q < kMaxProbs; ++q) {
+        if (q >= n_probs) break;
+        SelState st = sq[q];
+        const int64_t c = cq[q];
         const uint64_t* cand = s.cand + static_cast<int64_t>(q) * n;
+        const uint64_t* kq = keys[q];
         if (c <= kDirect) {
             // few candidates: the k-th largest is the key with fewer than k
             // keys above it and at least k at or above it
-            for (int64_t j = threadIdx.x; j < c; j += blockDim.x) keys[j] = cand[j];
-            __syncthreads();
             for (int64_t j = threadIdx.x; j < c; j += blockDim.x) {
-                const uint64_t kj = keys[j];
+                const uint64_t kj = kq[j];
                 int64_t gt = 0, ge = 0;
                 for (int64_t i = 0; i < c; ++i) {
-                    gt += keys[i] > kj;
-                    ge += keys[i] >= kj;
+                    gt += kq[i] > kj;
+                    ge += kq[i] >= kj;
                 }
                 if (gt < st.k && st.k <= ge) found = kj;      // every such thread writes the same key
             }
@@ -418,12 +474,15 @@ __global__ __launch_bounds__(256) void finish_kernel(Scratch s, int n_probs, int
         const uint64_t vk = st.prefix;              // all 64 bits chosen: the m-th largest key
         double hi = 0.0, lo = 0.0;
         int64_t cnt = 0;
-        for (int i = threadIdx.x; i < n_tail_part; i += blockDim.x) {
-            dd_merge(hi, lo, s.part_hi[(1 + q) * kSumBlocks + i], s.part_lo[(1 + q) * kSumBlocks + i]);
-            cnt += s.part_cnt[(1 + q) * kSumBlocks + i];
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            if (threadIdx.x + u * 256 < n_tail_part) {
+                dd_merge(hi, lo, th[q][u], tl[q][u]);
+                cnt += tc[q][u];
+            }
         }
         for (int64_t j = threadIdx.x; j < c; j += blockDim.x) {
-            const uint64_t key = cand[j];
+            const uint64_t key = c <= kDirect ? kq[j] : cand[j];
             if (key > vk) {
                 dd_add(hi, lo, __longlong_as_double(static_cast<long long>(key)));
                 cnt += 1;
