@@ -33,6 +33,13 @@ constexpr int kBins = 4096;
 constexpr int kPasses = 6;
 constexpr int kMaxProbs = 4;   // 4 x 16 KB histograms fit the 64 KB dynamic-LDS default
 constexpr int kDirect = 256;   // candidates ranked directly (all pairs) instead of by radix digits
+// Workgroup sizes of the two histogram passes.  Each workgroup adds its
+// nonzero bins to the global histogram with device atomics, and those on one
+// bin serialise (in the first pass the values crowd into the few bins of
+// their exponents), so fewer, larger workgroups wait less: 45.7 against
+// 51.5 us for 1M losses and two probabilities with 256 threads in both.
+constexpr int kHist0Threads = 1024;
+constexpr int kHist1Threads = 1024;
 __constant__ int kShift[kPasses] = {52, 40, 28, 16, 4, 0};
 __constant__ int kBits[kPasses] = {12, 12, 12, 12, 12, 4};
 
@@ -102,8 +109,8 @@ __device__ __forceinline__ uint64_t key_of(double x) {
 
 // block-wide double-double reduction; result valid in thread 0
 __device__ __forceinline__ void block_reduce_dd(double& hi, double& lo, int64_t& cnt) {
-    __shared__ double sh[4], sl[4];
-    __shared__ int64_t sc[4];
+    __shared__ double sh[16], sl[16];              // up to 1024 threads
+    __shared__ int64_t sc[16];
     group_reduce_dd(hi, lo, kWave);
     for (int off = 32; off >= 1; off >>= 1) cnt += __shfl_xor(cnt, off, kWave);
     const int w = threadIdx.x >> 6;
@@ -139,10 +146,15 @@ __device__ SelState choose_digit(const uint32_t* __restrict__ h, SelState st, in
     const int nb = 1 << kBits[pass];
     const int per = (nb + 255) / 256;                    // 16 (12-bit digits) or 1 (the last, 4-bit)
     // thread i owns bins [nb - per (i+1), nb - per i): thread 0 the largest digits
-    const int hiBin = nb - per * threadIdx.x;
+    const int t = threadIdx.x;
+    const bool owner = t < 256;                           // larger workgroups: the rest wait at the barriers
+    const int hiBin = nb - per * (owner ? t : 0);
     const int loBin = hiBin - per;
     uint32_t cnt[16];
-    if (per == 16) {                                      // 16 aligned bins: four 16-byte loads
+    if (!owner) {
+#pragma unroll
+        for (int k = 0; k < 16; ++k) cnt[k] = 0;
+    } else if (per == 16) {                               // 16 aligned bins: four 16-byte loads
         const u32x4* v = reinterpret_cast<const u32x4*>(h + loBin);
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
@@ -159,19 +171,19 @@ __device__ SelState choose_digit(const uint32_t* __restrict__ h, SelState st, in
     uint64_t local = 0;
 #pragma unroll
     for (int k = 0; k < 16; ++k) local += cnt[k];
-    if (threadIdx.x == 0) out = st;       // unchanged unless a bin is chosen (k beyond the count)
-    scan[threadIdx.x] = local;
+    if (t == 0) out = st;                 // unchanged unless a bin is chosen (k beyond the count)
+    if (owner) scan[t] = local;
     __syncthreads();
     for (int off = 1; off < 256; off <<= 1) {
-        uint64_t add = threadIdx.x >= off ? scan[threadIdx.x - off] : 0;
+        const uint64_t add = owner && t >= off ? scan[t - off] : 0;
         __syncthreads();
-        scan[threadIdx.x] += add;
+        if (owner) scan[t] += add;
         __syncthreads();
     }
-    const uint64_t incl = scan[threadIdx.x];
+    const uint64_t incl = owner ? scan[t] : 0;
     const uint64_t excl = incl - local;
     const uint64_t k = static_cast<uint64_t>(st.k);
-    if (excl < k && k <= incl) {
+    if (owner && excl < k && k <= incl) {
         uint64_t cum = excl;
         for (int i = per - 1; i >= 0; --i) {              // from this thread's largest digit down
             const uint64_t c = cnt[i];
@@ -213,8 +225,9 @@ __global__ void select_init_kernel(Scratch s, MArgs ma, int n_probs) {
 // Pass `pass` of the radix select (and, in pass 0, the sum for the mean):
 // finish the previous pass's digit choice, clear the histogram the next pass
 // fills, and count this pass's digits of the values matching the prefix.
-__global__ __launch_bounds__(256) void histogram_kernel(const double* __restrict__ x, int64_t n, Scratch s,
-                                                        MArgs ma, int n_probs, int pass, int with_mean) {
+template <int kT>
+__global__ __launch_bounds__(kT) void histogram_kernel(const double* __restrict__ x, int64_t n, Scratch s,
+                                                       MArgs ma, int n_probs, int pass, int with_mean) {
     extern __shared__ uint32_t lds_hist[];   // [nq][kBins]
     __shared__ SelState cur[kMaxProbs];
     // pass 0 starts every probability from the empty prefix, so one histogram serves all
@@ -229,7 +242,9 @@ __global__ __launch_bounds__(256) void histogram_kernel(const double* __restrict
         }
         if (pass > 0) {
             st = s.st[((pass - 1) & 1) * kMaxProbs + q];
-            st = choose_digit(s.hist + ((pass - 1) % 3) * kHistStride + int64_t(q) * kBins, st, pass - 1);
+            // pass 0 fills the first probability's slot only: its histogram serves all
+            st = choose_digit(s.hist + ((pass - 1) % 3) * kHistStride + int64_t(pass == 1 ? 0 : q) * kBins, st,
+                              pass - 1);
             if (blockIdx.x == 0 && threadIdx.x == 0) s.st[(pass & 1) * kMaxProbs + q] = st;
         }
         if (threadIdx.x == 0) cur[q] = st;
@@ -283,9 +298,7 @@ __global__ __launch_bounds__(256) void histogram_kernel(const double* __restrict
     uint32_t* h = s.hist + (pass % 3) * kHistStride;
     for (int k = threadIdx.x; k < nq * kBins; k += blockDim.x) {
         const uint32_t c = lds_hist[k];
-        if (c)
-            for (int q = k / kBins; q < (pass == 0 ? n_probs : k / kBins + 1); ++q)
-                atomicAdd(&h[q * kBins + k % kBins], c);
+        if (c) atomicAdd(&h[k], c);
     }
 }
 
@@ -548,6 +561,17 @@ int64_t metrics_scratch_bytes(int n_probs, int64_t n) {
     return base + static_cast<int64_t>(n_probs) * n * static_cast<int64_t>(sizeof(uint64_t));
 }
 
+namespace {
+// workgroups of `threads` threads for eight values per thread, at most kSumBlocks
+int hist_blocks(int64_t n, int threads) {
+    const int64_t per = static_cast<int64_t>(threads) * 8;
+    int64_t b = (n + per - 1) / per;
+    if (b > kSumBlocks) b = kSumBlocks;
+    if (b < 1) b = 1;
+    return static_cast<int>(b);
+}
+}  // namespace
+
 hipError_t launch_metrics_prime(void* scratch, const int64_t* m_host, int n_probs, hipStream_t st) {
     if (n_probs > kMaxProbs) return hipErrorInvalidValue;
     Scratch s = carve(scratch, n_probs);
@@ -571,31 +595,26 @@ hipError_t launch_metrics(const double* ylt, int64_t n, const int64_t* m_host, i
         hipLaunchKernelGGL(select_init_kernel, dim3(16), dim3(256), 0, st, s, ma, n_probs);
         if ((err = hipGetLastError()) != hipSuccess) return err;
     }
-    // enough workgroups to keep many loads in flight; each adds only its
-    // non-zero bins to the global histogram (values crowd into few bins)
-    int hblocks = static_cast<int>((n + 2047) / 2048);
-    if (hblocks > kSumBlocks) hblocks = kSumBlocks;
-    if (hblocks < 1) hblocks = 1;
-    const size_t lds = sizeof(uint32_t) * kBins * (n_probs > 0 ? n_probs : 1);
     // two 12-bit passes (the first also sums for the mean), then one pass that
     // sums the tail above each 24-bit prefix and collects the keys inside it,
     // and one workgroup that finishes the selection over those candidates
-    const int passes = n_probs > 0 ? 2 : 1;
-    for (int pass = 0; pass < passes; ++pass) {
-        hipLaunchKernelGGL(histogram_kernel, dim3(hblocks), dim3(256), pass == 0 ? sizeof(uint32_t) * kBins : lds, st,
-                           ylt, n, s, ma, n_probs, pass, pass == 0 ? 1 : 0);
-        if ((err = hipGetLastError()) != hipSuccess) return err;
-    }
+    const int h0 = hist_blocks(n, kHist0Threads), h1 = hist_blocks(n, kHist1Threads);
+    hipLaunchKernelGGL(histogram_kernel<kHist0Threads>, dim3(h0), dim3(kHist0Threads), sizeof(uint32_t) * kBins, st,
+                       ylt, n, s, ma, n_probs, 0, 1);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
     if (n_probs == 0) {
-        hipLaunchKernelGGL(final_kernel, dim3(1), dim3(256), 0, st, s, 0, hblocks, 1, n, out);
+        hipLaunchKernelGGL(final_kernel, dim3(1), dim3(256), 0, st, s, 0, h0, 1, n, out);
         return hipGetLastError();
     }
+    hipLaunchKernelGGL(histogram_kernel<kHist1Threads>, dim3(h1), dim3(kHist1Threads),
+                       sizeof(uint32_t) * kBins * n_probs, st, ylt, n, s, ma, n_probs, 1, 0);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
     int tblocks = static_cast<int>((n + 1023) / 1024);
     if (tblocks > kSumBlocks) tblocks = kSumBlocks;
     if (tblocks < 1) tblocks = 1;
     hipLaunchKernelGGL(collect_kernel, dim3(tblocks), dim3(256), 0, st, ylt, n, s, n_probs);
     if ((err = hipGetLastError()) != hipSuccess) return err;
-    hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(256), 0, st, s, n_probs, hblocks, tblocks, n, out);
+    hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(256), 0, st, s, n_probs, h0, tblocks, n, out);
     return hipGetLastError();
 }
 
@@ -711,14 +730,12 @@ hipError_t launch_tail_stats(const double* ylt, int64_t n, int64_t m, void* scra
     hipError_t err;
     hipLaunchKernelGGL(select_init_kernel, dim3(16), dim3(256), 0, st, s, ma, 1);
     if ((err = hipGetLastError()) != hipSuccess) return err;
-    int hblocks = static_cast<int>((n + 2047) / 2048);
-    if (hblocks > kSumBlocks) hblocks = kSumBlocks;
-    if (hblocks < 1) hblocks = 1;
-    for (int pass = 0; pass < 2; ++pass) {
-        hipLaunchKernelGGL(histogram_kernel, dim3(hblocks), dim3(256), sizeof(uint32_t) * kBins, st, ylt, n, s, ma,
-                           1, pass, 0);
-        if ((err = hipGetLastError()) != hipSuccess) return err;
-    }
+    hipLaunchKernelGGL(histogram_kernel<kHist0Threads>, dim3(hist_blocks(n, kHist0Threads)), dim3(kHist0Threads),
+                       sizeof(uint32_t) * kBins, st, ylt, n, s, ma, 1, 0, 0);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+    hipLaunchKernelGGL(histogram_kernel<kHist1Threads>, dim3(hist_blocks(n, kHist1Threads)), dim3(kHist1Threads),
+                       sizeof(uint32_t) * kBins, st, ylt, n, s, ma, 1, 1, 0);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
     int tblocks = static_cast<int>((n + 1023) / 1024);
     if (tblocks > kSumBlocks) tblocks = kSumBlocks;
     if (tblocks < 1) tblocks = 1;
