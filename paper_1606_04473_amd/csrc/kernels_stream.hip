@@ -151,65 +151,108 @@ __global__ void stream_fill_kernel(uint32_t* p, int64_t n, uint32_t v) {
     for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
 }
 
-// stable scatter of each trial's events into its segments of the part
-// streams, one wave per trial.  For each 64 events every lane finds the lanes
-// holding an event of its own part -- the AND over the part number's bits of
-// that bit's ballot or its complement -- takes its rank among the earlier
-// ones, and all 64 write in one store; the last lane of each part moves that
-// part's cursor on.
-__global__ __launch_bounds__(256) void stream_scatter_kernel(const int64_t* __restrict__ offsets,
-                                                             const uint32_t* __restrict__ ids, int64_t N, int P, int G,
-                                                             int64_t NG, const int64_t* __restrict__ part_base,
-                                                             const uint32_t* __restrict__ gstart,
-                                                             const uint16_t* __restrict__ gend,
-                                                             uint16_t* __restrict__ out) {
-    __shared__ int64_t cur[4][kMaxStreamParts];
+// Stable scatter of each trial's events into its segments of the part
+// streams, one workgroup per group of G trials.  The group's segments of
+// every part are staged in LDS (each padded with 0xFFFF as in the stream) and
+// its trials are scattered there, one wave per trial, sixteen at a time: for
+// each 64 events every lane finds the lanes holding an event of its own part
+// -- the AND over the part number's bits of that bit's ballot or its
+// complement -- takes its rank among the earlier ones, and all 64 write in
+// one store; the last lane of each part moves that part's cursor on.  Each
+// part's segment then leaves in 16-byte stores to its place in the stream:
+// whole lines instead of 2-byte writes spread over up to P lines per 64
+// events.  A group whose padded segments exceed the stage is scattered
+// straight to the stream.
+constexpr int kGroupStageIds = 72 * 1024;     // 144 KB of LDS
+__global__ __launch_bounds__(1024) void stream_group_scatter_kernel(
+    const int64_t* __restrict__ offsets, const uint32_t* __restrict__ ids, int64_t N, int P, int G, int64_t NG,
+    const int64_t* __restrict__ part_base, const uint32_t* __restrict__ gstart, const uint16_t* __restrict__ gend,
+    uint16_t* __restrict__ out) {
+    __shared__ __attribute__((aligned(16))) uint16_t stage[kGroupStageIds];
+    __shared__ uint32_t seg[kMaxStreamParts + 1];     // staged start of each part's segment
+    __shared__ int64_t cur[16][kMaxStreamParts];       // per wave: where each part's next event goes
     const int w = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     const int n_bits = P > 1 ? 32 - __builtin_clz(static_cast<uint32_t>(P - 1)) : 0;
     const uint64_t below = stream_lanemask_lt();
     const uint64_t above = lane == 63 ? 0ull : (~0ull << (lane + 1));
-    const int64_t n_waves = (static_cast<int64_t>(gridDim.x) * blockDim.x) >> 6;
-    for (int64_t t = uniform_i64((static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6); t < N;
-         t += n_waves) {
-        const int64_t g = t / G;
-        const int i = static_cast<int>(t - g * G);
-        for (int q = lane; q < P; q += 64) {
-            const int64_t k = static_cast<int64_t>(q) * NG + g;
-            cur[w][q] = part_base[q] + gstart[static_cast<int64_t>(q) * (NG + 1) + g] +
-                        (i ? gend[k * kStreamGroupSlots + i - 1] : 0);
-        }
-        __builtin_amdgcn_wave_barrier();
-        const int64_t b = offsets[t], e = offsets[t + 1];
-        constexpr int kAhead = 4;                   // chunks of 64 IDs loaded together
-        for (int64_t c0 = b; c0 < e; c0 += 64 * kAhead) {
-            uint32_t idk[kAhead];
-#pragma unroll
-            for (int k = 0; k < kAhead; ++k) {
-                const int64_t at = c0 + k * 64 + lane;
-                idk[k] = at < e ? ids[at] : 0u;
+    for (int64_t g = blockIdx.x; g < NG; g += gridDim.x) {
+        if (threadIdx.x == 0) {
+            uint32_t run = 0;
+            for (int q = 0; q < P; ++q) {
+                seg[q] = run;
+                const int64_t k = static_cast<int64_t>(q) * (NG + 1) + g;
+                run += gstart[k + 1] - gstart[k];
             }
+            seg[P] = run;
+        }
+        __syncthreads();
+        const uint32_t total = seg[P];
+        const bool staged = total <= static_cast<uint32_t>(kGroupStageIds);
+        if (staged) {
+            for (uint32_t u = threadIdx.x; u < total / 8; u += blockDim.x)
+                reinterpret_cast<u32x4*>(stage)[u] = u32x4{0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu};
+        }
+        __syncthreads();
+        const int64_t t0 = g * G;
+        const int64_t t1 = t0 + G < N ? t0 + G : N;
+        for (int64_t t = t0 + w; t < t1; t += 16) {
+            const int i = static_cast<int>(t - t0);
+            for (int q = lane; q < P; q += 64) {
+                const int64_t k = static_cast<int64_t>(q) * NG + g;
+                const int64_t rel = i ? gend[k * kStreamGroupSlots + i - 1] : 0;
+                cur[w][q] = staged ? seg[q] + rel
+                                   : part_base[q] + gstart[static_cast<int64_t>(q) * (NG + 1) + g] + rel;
+            }
+            __builtin_amdgcn_wave_barrier();
+            const int64_t b = offsets[t], e = offsets[t + 1];
+            constexpr int kAhead = 8;                   // chunks of 64 IDs loaded together
+            for (int64_t c0 = b; c0 < e; c0 += 64 * kAhead) {
+                uint32_t idk[kAhead];
 #pragma unroll
-            for (int k = 0; k < kAhead; ++k) {
-                const int64_t c = c0 + k * 64;
-                if (c >= e) break;
-                const bool valid = c + lane < e;
-                const uint32_t id = idk[k];
-                const int pid = static_cast<int>(id >> kStreamShift);
-                uint64_t same = __ballot(valid);
-                for (int bit = 0; bit < n_bits; ++bit) {
-                    const bool set = ((pid >> bit) & 1) != 0;
-                    const uint64_t lanes = __ballot(set);
-                    same &= set ? lanes : ~lanes;
+                for (int k = 0; k < kAhead; ++k) {
+                    const int64_t at = c0 + k * 64 + lane;
+                    idk[k] = at < e ? ids[at] : 0u;
                 }
-                const int64_t at = cur[w][pid];
-                if (valid) out[at + __popcll(same & below)] = static_cast<uint16_t>(id);
-                __builtin_amdgcn_wave_barrier();
-                if (valid && (same & above) == 0) cur[w][pid] = at + __popcll(same);
-                __builtin_amdgcn_wave_barrier();
+#pragma unroll
+                for (int k = 0; k < kAhead; ++k) {
+                    const int64_t c = c0 + k * 64;
+                    if (c >= e) break;
+                    const bool valid = c + lane < e;
+                    const uint32_t id = idk[k];
+                    const int pid = static_cast<int>(id >> kStreamShift);
+                    uint64_t same = __ballot(valid);
+                    for (int bit = 0; bit < n_bits; ++bit) {
+                        const bool set = ((pid >> bit) & 1) != 0;
+                        const uint64_t lanes = __ballot(set);
+                        same &= set ? lanes : ~lanes;
+                    }
+                    const int64_t at = cur[w][pid];
+                    if (valid) {
+                        const int64_t to = at + __popcll(same & below);
+                        if (staged)
+                            stage[to] = static_cast<uint16_t>(id);
+                        else
+                            out[to] = static_cast<uint16_t>(id);
+                    }
+                    __builtin_amdgcn_wave_barrier();
+                    if (valid && (same & above) == 0) cur[w][pid] = at + __popcll(same);
+                    __builtin_amdgcn_wave_barrier();
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+        __syncthreads();
+        if (staged) {
+            // segments are whole 8-ID chunks, here and in the stream
+            for (int q = w; q < P; q += 16) {
+                const uint32_t s0 = seg[q] / 8, s1 = seg[q + 1] / 8;
+                u32x4* dst = reinterpret_cast<u32x4*>(out + part_base[q] +
+                                                      gstart[static_cast<int64_t>(q) * (NG + 1) + g]);
+                for (uint32_t u = s0 + lane; u < s1; u += 64) dst[u - s0] = reinterpret_cast<const u32x4*>(stage)[u];
             }
         }
-        __builtin_amdgcn_wave_barrier();
+        __syncthreads();
     }
 }
 
@@ -870,8 +913,12 @@ hipError_t build_stream_layout(const int64_t* offsets, const uint32_t* ids, int6
                            reinterpret_cast<uint32_t*>(out->ids), n32, 0xFFFFFFFFu);
         if ((e = hipGetLastError()) != hipSuccess) goto fail;
     }
-    hipLaunchKernelGGL(stream_scatter_kernel, dim3(static_cast<uint32_t>(blocks)), dim3(256), 0, s, offsets, ids, N, P,
-                       G, NG, out->part_base, out->gstart, out->gend, out->ids);
+    {
+        int64_t gb = NG;
+        if (gb > int64_t(n_cu)) gb = n_cu;                 // one 16-wave workgroup per CU (the stage fills LDS)
+        hipLaunchKernelGGL(stream_group_scatter_kernel, dim3(static_cast<uint32_t>(gb)), dim3(1024), 0, s, offsets,
+                           ids, N, P, G, NG, out->part_base, out->gstart, out->gend, out->ids);
+    }
     if ((e = hipGetLastError()) != hipSuccess) goto fail;
     // temporaries go back to the library's device memory cache: no free waits for the device
     dev_free(cnt, s);

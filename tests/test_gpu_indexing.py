@@ -20,7 +20,7 @@ import numpy as np
 import pytest
 
 import oracle
-from workloads import Layer, make_config, make_elt_pool, make_yet
+from workloads import Layer, make_config, make_elt_pool, make_tiny_yet, make_yet
 
 pytestmark = pytest.mark.gpu
 
@@ -151,6 +151,21 @@ def test_stream_copy_is_the_yet(ara):
     w = make_config("config0")
     for yet in (w.yet, make_yet(3000, 150.0, 1_300_000, seed=183), make_yet(5000, 1.5, 300_000, seed=184)):
         pool = make_elt_pool(1, yet.catalogue_size, 10, seed=185)
+        tables = ara.create_tables(yet.offsets, yet.ids, pool.losses)
+        _check_stream(ara, tables, yet)
+        tables.close()
+
+
+def test_stream_copy_groups_past_the_stage(ara):
+    """Groups whose padded segments exceed the scatter's LDS stage are written
+    to the stream directly: trials of ~5000 events (every group too large),
+    and long trials followed by short ones (both kinds in one layout)."""
+    rng = np.random.default_rng(187)
+    C = 2_000_000
+    lengths = np.concatenate([rng.integers(4000, 7000, 100), rng.integers(0, 50, 3000)])
+    trials = [rng.integers(0, C, size=int(k)).tolist() for k in lengths]
+    for yet in (make_yet(600, 5000.0, 300_000, seed=186), make_tiny_yet(trials, C)):
+        pool = make_elt_pool(1, yet.catalogue_size, 10, seed=188)
         tables = ara.create_tables(yet.offsets, yet.ids, pool.losses)
         _check_stream(ara, tables, yet)
         tables.close()
