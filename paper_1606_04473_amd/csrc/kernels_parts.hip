@@ -127,61 +127,115 @@ __global__ void fill_u32_kernel(uint32_t* p, int64_t n, uint32_t v) {
     for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
 }
 
-// stable scatter of each trial's events into its part segments, one wave per trial
-__global__ __launch_bounds__(256) void part_scatter_kernel(const int64_t* __restrict__ offsets,
-                                                           const uint32_t* __restrict__ ids, int64_t N, int P, int T,
-                                                           const uint32_t* __restrict__ seg_rel,
-                                                           const int64_t* __restrict__ tile_start,
-                                                           uint32_t* __restrict__ pids) {
-    __shared__ int64_t cur[4][kMaxParts];
+// Scatter of each trial's IDs into its per-part segments of the tiled copy,
+// one workgroup per run of kChunkTrials trials of a tile.  Inside a tile each
+// part's segments of consecutive trials are consecutive, so the run's
+// segments of every part form one contiguous range per part: they are staged
+// in LDS (part after part, the padding that ends each trial's segment filled
+// with the sentinel), the trials scattered there one wave per trial,
+// and each part's range then leaves in coalesced 4-byte stores instead of
+// writes spread over up to P lines per 64 IDs.  Per 64 IDs the lanes holding
+// an ID of this lane's part are the AND, over the part number's bits, of that
+// bit's ballot or its complement; a lane's rank among the earlier ones places
+// it, all 64 write in one store, and the last lane of each part moves its
+// cursor on.  A run whose IDs exceed the stage is scattered straight to the
+// copy.
+constexpr int kChunkTrials = 32;
+constexpr int kPartStageIds = 36 * 1024;        // 144 KB of LDS
+__global__ __launch_bounds__(1024) void part_scatter_kernel(const int64_t* __restrict__ offsets,
+                                                            const uint32_t* __restrict__ ids, int64_t N, int P, int T,
+                                                            const uint32_t* __restrict__ seg_rel,
+                                                            const int64_t* __restrict__ tile_start,
+                                                            uint32_t* __restrict__ pids) {
+    __shared__ uint32_t stage[kPartStageIds];
+    __shared__ uint32_t sseg[kMaxParts + 1];          // staged start of each part's range
+    __shared__ int64_t cur[16][kMaxParts];
     const int w = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     const int n_bits = P > 1 ? 32 - __builtin_clz(static_cast<uint32_t>(P - 1)) : 0;
     const uint64_t above = lane == 63 ? 0ull : (~0ull << (lane + 1));
-    const int64_t n_waves = (static_cast<int64_t>(gridDim.x) * blockDim.x) >> 6;
-    for (int64_t t = uniform_i64((static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6); t < N;
-         t += n_waves) {
-        const int64_t tile = t / T;
-        const int i = static_cast<int>(t - tile * T);
+    const int64_t n_tiles = (N + T - 1) / T;
+    const int64_t per_tile = (T + kChunkTrials - 1) / kChunkTrials;
+    for (int64_t r = blockIdx.x; r < n_tiles * per_tile; r += gridDim.x) {
+        const int64_t tile = r / per_tile;
         const int64_t t0 = tile * T;
         const int Tk = static_cast<int>(N - t0 < T ? N - t0 : T);
+        const int i0 = static_cast<int>(r - tile * per_tile) * kChunkTrials;
+        if (i0 >= Tk) continue;                                   // uniform over the workgroup
+        const int i1 = i0 + kChunkTrials < Tk ? i0 + kChunkTrials : Tk;
         const int64_t base = tile * (static_cast<int64_t>(T) * P + 1);
-        for (int p = lane; p < P; p += 64) cur[w][p] = tile_start[tile] + seg_rel[base + static_cast<int64_t>(p) * Tk + i];
-        __builtin_amdgcn_wave_barrier();
-        // per 64 IDs: the lanes holding an ID of this lane's part are the AND,
-        // over the part number's bits, of that bit's ballot or its complement;
-        // a lane's rank among the earlier ones places it, all 64 write in one
-        // store, and the last lane of each part moves its cursor on
-        const int64_t b = offsets[t], e = offsets[t + 1];
-        constexpr int kAhead = 4;                   // chunks of 64 IDs loaded together
-        for (int64_t c0 = b; c0 < e; c0 += 64 * kAhead) {
-            uint32_t idk[kAhead];
-#pragma unroll
-            for (int k = 0; k < kAhead; ++k) {
-                const int64_t at = c0 + k * 64 + lane;
-                idk[k] = at < e ? ids[at] : 0u;
+        if (w == 0) {                                  // each part's range size, scanned over the wave
+            uint32_t n = 0;
+            if (lane < P)
+                n = seg_rel[base + static_cast<int64_t>(lane) * Tk + i1] - seg_rel[base + static_cast<int64_t>(lane) * Tk + i0];
+            uint32_t inc = n;
+            for (int off = 1; off < 64; off <<= 1) {
+                const uint32_t v = __shfl_up(inc, off, 64);
+                if (lane >= off) inc += v;
             }
+            if (lane < P) sseg[lane] = inc - n;
+            if (lane == P - 1) sseg[P] = inc;
+        }
+        __syncthreads();
+        const bool staged = sseg[P] <= static_cast<uint32_t>(kPartStageIds);
+        if (staged) {                                  // segments end in sentinel padding, as in the copy
+            for (uint32_t u = threadIdx.x; u < sseg[P]; u += blockDim.x) stage[u] = kSentinel;
+        }
+        __syncthreads();
+        for (int i = i0 + w; i < i1; i += 16) {
+            const int64_t t = t0 + i;
+            for (int p = lane; p < P; p += 64) {
+                const int64_t k = base + static_cast<int64_t>(p) * Tk;
+                cur[w][p] = staged ? sseg[p] + (seg_rel[k + i] - seg_rel[k + i0]) : tile_start[tile] + seg_rel[k + i];
+            }
+            __builtin_amdgcn_wave_barrier();
+            const int64_t b = offsets[t], e = offsets[t + 1];
+            constexpr int kAhead = 8;                   // chunks of 64 IDs loaded together
+            for (int64_t c0 = b; c0 < e; c0 += 64 * kAhead) {
+                uint32_t idk[kAhead];
 #pragma unroll
-            for (int k = 0; k < kAhead; ++k) {
-                const int64_t c = c0 + k * 64;
-                if (c >= e) break;
-                const bool valid = c + lane < e;
-                const uint32_t id = idk[k];
-                const int pid = static_cast<int>(id >> kPartShift);
-                uint64_t same = __ballot(valid);
-                for (int bit = 0; bit < n_bits; ++bit) {
-                    const bool set = ((pid >> bit) & 1) != 0;
-                    const uint64_t lanes = __ballot(set);
-                    same &= set ? lanes : ~lanes;
+                for (int k = 0; k < kAhead; ++k) {
+                    const int64_t at = c0 + k * 64 + lane;
+                    idk[k] = at < e ? ids[at] : 0u;
                 }
-                const int64_t at = cur[w][pid];
-                if (valid) pids[at + __popcll(same & lanemask_lt())] = id;
-                __builtin_amdgcn_wave_barrier();
-                if (valid && (same & above) == 0) cur[w][pid] = at + __popcll(same);
-                __builtin_amdgcn_wave_barrier();
+#pragma unroll
+                for (int k = 0; k < kAhead; ++k) {
+                    const int64_t c = c0 + k * 64;
+                    if (c >= e) break;
+                    const bool valid = c + lane < e;
+                    const uint32_t id = idk[k];
+                    const int pid = static_cast<int>(id >> kPartShift);
+                    uint64_t same = __ballot(valid);
+                    for (int bit = 0; bit < n_bits; ++bit) {
+                        const bool set = ((pid >> bit) & 1) != 0;
+                        const uint64_t lanes = __ballot(set);
+                        same &= set ? lanes : ~lanes;
+                    }
+                    const int64_t at = cur[w][pid];
+                    if (valid) {
+                        const int64_t to = at + __popcll(same & lanemask_lt());
+                        if (staged)
+                            stage[to] = id;
+                        else
+                            pids[to] = id;
+                    }
+                    __builtin_amdgcn_wave_barrier();
+                    if (valid && (same & above) == 0) cur[w][pid] = at + __popcll(same);
+                    __builtin_amdgcn_wave_barrier();
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+        __syncthreads();
+        if (staged) {
+            for (int p = w; p < P; p += 16) {
+                const int64_t k = base + static_cast<int64_t>(p) * Tk;
+                uint32_t* dst = pids + tile_start[tile] + seg_rel[k + i0];
+                const uint32_t s0 = sseg[p], n = sseg[p + 1] - s0;
+                for (uint32_t u = lane; u < n; u += 64) dst[u] = stage[s0 + u];
             }
         }
-        __builtin_amdgcn_wave_barrier();
+        __syncthreads();
     }
 }
 
@@ -1446,8 +1500,13 @@ hipError_t build_part_layout(const int64_t* offsets, const uint32_t* ids, int64_
         hipLaunchKernelGGL(fill_u32_kernel, dim3(static_cast<uint32_t>(fb)), dim3(256), 0, s, out->pids, total + kIdPad,
                            kSentinel);
         if ((e = hipGetLastError()) != hipSuccess) goto fail;
-        hipLaunchKernelGGL(part_scatter_kernel, dim3(static_cast<uint32_t>(blocks)), dim3(256), 0, s, offsets, ids, N,
-                           P, T, out->seg_rel, out->tile_start, out->pids);
+        {
+            // one 16-wave workgroup per CU (the stage fills LDS), over runs of kChunkTrials trials
+            int64_t sb = n_tiles * ((T + kChunkTrials - 1) / kChunkTrials);
+            if (sb > int64_t(n_cu)) sb = n_cu;
+            hipLaunchKernelGGL(part_scatter_kernel, dim3(static_cast<uint32_t>(sb)), dim3(1024), 0, s, offsets, ids, N,
+                               P, T, out->seg_rel, out->tile_start, out->pids);
+        }
         if ((e = hipGetLastError()) != hipSuccess) goto fail;
         if ((e = hipStreamSynchronize(s)) != hipSuccess) goto fail;
         (void)n_events;

@@ -177,14 +177,19 @@ __global__ __launch_bounds__(1024) void stream_group_scatter_kernel(
     const uint64_t below = stream_lanemask_lt();
     const uint64_t above = lane == 63 ? 0ull : (~0ull << (lane + 1));
     for (int64_t g = blockIdx.x; g < NG; g += gridDim.x) {
-        if (threadIdx.x == 0) {
-            uint32_t run = 0;
-            for (int q = 0; q < P; ++q) {
-                seg[q] = run;
-                const int64_t k = static_cast<int64_t>(q) * (NG + 1) + g;
-                run += gstart[k + 1] - gstart[k];
+        if (w == 0) {                                  // each part's padded segment, scanned over the wave
+            uint32_t n = 0;
+            if (lane < P) {
+                const int64_t k = static_cast<int64_t>(lane) * (NG + 1) + g;
+                n = gstart[k + 1] - gstart[k];
             }
-            seg[P] = run;
+            uint32_t inc = n;
+            for (int off = 1; off < 64; off <<= 1) {
+                const uint32_t v = __shfl_up(inc, off, 64);
+                if (lane >= off) inc += v;
+            }
+            if (lane < P) seg[lane] = inc - n;
+            if (lane == P - 1) seg[P] = inc;
         }
         __syncthreads();
         const uint32_t total = seg[P];
