@@ -351,6 +351,8 @@ struct GraphEntry {
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph = nullptr;
     HostStage stage;
+    std::vector<uint8_t> last;          // the layer arguments last copied to `scratch`,
+    hipStream_t last_stream = nullptr;  // on this stream: the same again need no copy
 };
 
 }  // namespace ara
