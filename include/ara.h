@@ -77,8 +77,8 @@ typedef int32_t ara_status;
                                        the per-layer sequences, or with pass_variant 1 and several
                                        layers the batched launch.  Terms and ELT choices may change
                                        between replays (they are copied to the device only when
-                                       they differ from the last replay's on the same stream, so
-                                       repeated replays queue without host waits).  Requires a
+                                       they differ from the last replay's, so repeated replays
+                                       queue without host waits).  Requires a
                                        device output and a non-null stream (ARA_ERR_INVALID_ARG
                                        otherwise). */
 #define ARA_PROFILE      (1u << 5)  /* ara_run_layers: bracket each kernel with HIP events on the

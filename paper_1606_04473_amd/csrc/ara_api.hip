@@ -453,12 +453,14 @@ hipError_t stage_acquire(ara::HostStage& st, size_t bytes) {
 }
 
 // Copy a graph's layer arguments to the head of its scratch through its pinned
-// stage.  Arguments equal to the last ones copied on the same stream are
-// already there in stream order, so nothing is copied and the host does not
-// wait for the stage: a caller that replays a graph with the same terms can
-// queue many replays ahead of the device.
+// stage.  Arguments equal to the last ones copied are already there -- in
+// stream order on the stream that copied them, on any stream once that copy
+// has completed -- so nothing is copied and the host does not wait for the
+// stage: a caller that replays a graph with the same terms can queue many
+// replays ahead of the device.
 hipError_t upload_layer_args(ara::GraphEntry* e, const void* args, size_t bytes, hipStream_t s) {
-    if (e->last_stream == s && e->last.size() == bytes && std::memcmp(e->last.data(), args, bytes) == 0)
+    if (e->last.size() == bytes && std::memcmp(e->last.data(), args, bytes) == 0 &&
+        (e->last_stream == s || hipEventQuery(e->stage.done) == hipSuccess))
         return hipSuccess;
     e->last.clear();
     hipError_t r = stage_acquire(e->stage, bytes);

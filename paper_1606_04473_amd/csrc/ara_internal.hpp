@@ -352,7 +352,7 @@ struct GraphEntry {
     hipGraph_t graph = nullptr;
     HostStage stage;
     std::vector<uint8_t> last;          // the layer arguments last copied to `scratch`,
-    hipStream_t last_stream = nullptr;  // on this stream: the same again need no copy
+    hipStream_t last_stream = nullptr;  // on this stream (stage.done marks the copy)
 };
 
 }  // namespace ara
